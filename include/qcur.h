@@ -1,0 +1,220 @@
+/*
+ * libqcur -- quaternion CUR (QMCUR) low-rank approximation on AMD MI355X (gfx950).
+ *
+ * Method: Wu, Kou, Cai, Yu, "Efficient quaternion CUR method for low-rank
+ * approximation to quaternion matrix" (arXiv 2402.19147), Algorithm 1 and
+ * Section 3.1.  Given a quaternion matrix A (m x n), column and row index sets
+ * J and I are drawn from length (squared-norm) or uniform probabilities,
+ * C = A(:,J), R = A(I,:) and W = A(I,J) are gathered, the core U is formed as
+ * W^+ or C^+ A R^+, and C U R together with ||A - CUR||_F is evaluated.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Quaternion matrices are four real planes (qcur_qmat).  Plane c (0 = real,
+ * 1 = i, 2 = j, 3 = k) starts at p + c * pstride elements; element (i, j) of a
+ * plane sits at i * ld + j (row-major).  Planes must not overlap:
+ * ld >= cols and pstride >= rows * ld (pstride may be anything when rows == 0).
+ *
+ * All matrix, vector and index pointers are DEVICE pointers unless a name
+ * ends in _host.  The caller owns every buffer; the library never allocates
+ * or frees caller memory and keeps no pointer after a call returns.  Work is
+ * enqueued on the handle's stream (qcur_set_stream) and calls return without
+ * waiting for it, except where a call says it synchronises.
+ *
+ * Indices are 0-based (the paper's [n] is 1-based).  The core U is
+ * |J| x |I| = c x r.
+ *
+ * Errors: every call returns a qcur_status and never throws or aborts.
+ * Argument, shape and dtype errors are detected on the host before anything
+ * is enqueued (and before the handle is used, so they can be checked without
+ * a GPU).  Conditions that depend on data (zero norm, non-finite values,
+ * invalid probabilities, too few positive weights, out-of-range or repeated
+ * indices) are detected by the kernels, which OR a bit into the handle's
+ * device status word; qcur_sync_status synchronises the stream and returns
+ * and clears that word.  HIP runtime failures map to QCUR_ERR_DEVICE.
+ * qcur_last_error gives a thread-local text for the last host-side error.
+ */
+#ifndef QCUR_H
+#define QCUR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QCUR_OK = 0,
+  QCUR_ERR_ARG = 1,          /* null pointer, negative size, bad enum, bad index */
+  QCUR_ERR_SHAPE = 2,        /* operand shapes or strides disagree */
+  QCUR_ERR_DTYPE = 3,        /* unsupported dtype combination */
+  QCUR_ERR_WORKSPACE = 4,    /* workspace missing or too small */
+  QCUR_ERR_SAMPLE = 5,       /* invalid probabilities or fewer positive weights than draws */
+  QCUR_ERR_NUMERIC = 6,      /* non-finite values or ||A||_F = 0 */
+  QCUR_ERR_DEVICE = 7,       /* HIP runtime error */
+  QCUR_ERR_UNSUPPORTED = 8   /* valid request outside the implemented limits */
+} qcur_status;
+
+typedef enum { QCUR_F64 = 0, QCUR_F32 = 1, QCUR_BF16 = 2 } qcur_dtype;
+typedef enum { QCUR_OP_N = 0, QCUR_OP_H = 1 } qcur_op;           /* H: conjugate transpose */
+typedef enum { QCUR_LENGTH = 0, QCUR_UNIFORM = 1 } qcur_sampling;
+typedef enum { QCUR_CORE_WPINV = 0, QCUR_CORE_CAR = 1 } qcur_core;
+
+typedef struct {
+  void* p;          /* device pointer to element (0,0) of plane 0 */
+  int64_t rows;
+  int64_t cols;
+  int64_t ld;       /* row stride in elements */
+  int64_t pstride;  /* plane stride in elements */
+  int32_t dtype;    /* qcur_dtype */
+} qcur_qmat;
+
+typedef struct qcur_ctx* qcur_handle;
+
+/* ---- handle, stream, status ------------------------------------------- */
+
+/* Creates a handle bound to HIP device `device`.  Allocates the handle's own
+ * device status word (4 bytes).  Errors: QCUR_ERR_ARG, QCUR_ERR_DEVICE. */
+qcur_status qcur_create(qcur_handle* handle, int device);
+qcur_status qcur_destroy(qcur_handle handle);
+/* Binds a hipStream_t (passed as void*; NULL = default stream). */
+qcur_status qcur_set_stream(qcur_handle handle, void* hip_stream);
+/* Synchronises the stream, returns the status bits raised by kernels since
+ * the last call (mapped to the most severe qcur_status) and clears them. */
+qcur_status qcur_sync_status(qcur_handle handle);
+const char* qcur_status_string(qcur_status status);
+const char* qcur_last_error(void);
+/* Library version as major*10000 + minor*100 + patch. */
+int qcur_version(void);
+
+/* ---- workspace queries (host only, no GPU needed) --------------------- */
+size_t qcur_probs_workspace(int64_t m, int64_t n);
+size_t qcur_pinv_workspace(int64_t p, int64_t q);
+size_t qcur_approx_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int core, int compute);
+size_t qcur_residual_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int compute);
+size_t qcur_backward_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int compute);
+/* Optional split-K workspace of qcur_gemm for D (M x N) with inner size K. */
+size_t qcur_gemm_workspace(int64_t M, int64_t N, int64_t K, int compute);
+
+/* ---- the eight calls of the hot path ----------------------------------- */
+
+/* Sampling probabilities (Section 3.1).  QCUR_LENGTH: p_col[j] =
+ * ||A(:,j)||^2 / ||A||_F^2 and q_row[i] = ||A(i,:)||^2 / ||A||_F^2, where
+ * |a|^2 sums the squares of the four components (Section 2.2); sums are
+ * accumulated in FP64 in a fixed order, so results are run-to-run identical.
+ * QCUR_UNIFORM: p_col[j] = 1/n, q_row[i] = 1/m.
+ * A: any dtype, m x n.  p_col: double[n], q_row: double[m], fro2: double[1]
+ * (optional, may be NULL; always ||A||_F^2).  ws: qcur_probs_workspace(m, n)
+ * bytes.  ||A||_F = 0 or a non-finite norm raises QCUR_ERR_NUMERIC in the
+ * status word (length mode). */
+qcur_status qcur_probs(qcur_handle handle, const qcur_qmat* A, int sampling, double* p_col,
+                       double* q_row, double* fro2, void* ws, size_t ws_bytes);
+
+/* Draws `count` indices from the probabilities probs[0..n) (Algorithm 1,
+ * steps 1-2) and writes them sorted ascending to idx[count] (int64).
+ * Integer-CDF sampler: weights w_j = floor(p_j * 2^60); draw t takes
+ * u = output number set_id * 2^32 + t of SplitMix64 seeded with `seed`,
+ * tau = floor(u * T / 2^64) for the current weight total T, and picks the
+ * smallest j whose inclusive prefix sum exceeds tau; without replacement the
+ * picked weight is then removed.  Bit-exact for identical probs.
+ * Limits: 1 <= n <= 16384 without replacement, n <= 8192 with replacement
+ * (weights are held in LDS); count <= n without replacement, count < 2^31.
+ * Data errors (QCUR_ERR_SAMPLE in the status word): p_j outside [0, 1] or
+ * non-finite, total weight zero or >= 2^64, fewer positive weights than
+ * draws without replacement.  On such an error idx is filled with -1. */
+qcur_status qcur_draw(qcur_handle handle, const double* probs, int64_t n, int64_t count,
+                      uint64_t seed, uint64_t set_id, int with_replacement, int64_t* idx);
+
+/* Gathers C = A(:,J) (m x c), R = A(I,:) (r x n) and W = A(I,J) (r x c)
+ * (Section 2.1 notation; Algorithm 1 steps 1-2).  Any of C, R, W may be NULL.
+ * Each output may have its own dtype (values are converted, BF16 with
+ * round-to-nearest-even).  Out-of-range indices write zeros and raise
+ * QCUR_ERR_ARG in the status word. */
+qcur_status qcur_gather(qcur_handle handle, const qcur_qmat* A, const int64_t* I, int64_t r,
+                        const int64_t* J, int64_t c, qcur_qmat* C, qcur_qmat* R, qcur_qmat* W);
+
+/* Moore-Penrose inverse Xp = X^+ (q x p) of X (p x q), both FP64
+ * (Section 2.1).  Singular values <= rtol * sigma_max count as zero
+ * (rtol < 0 selects max(p, q) * 2^-52); max_rank > 0 keeps at most that many.
+ * rank_out (device int64[1], may be NULL) receives the kept rank.
+ * Computed by one-sided (Hestenes) Jacobi on quaternion columns.
+ * Synchronises the stream once per Jacobi sweep to test convergence.
+ * ws: qcur_pinv_workspace(p, q) bytes.  Non-finite input raises
+ * QCUR_ERR_NUMERIC in the status word. */
+qcur_status qcur_pinv(qcur_handle handle, const qcur_qmat* X, double rtol, int64_t max_rank,
+                      qcur_qmat* Xp, int64_t* rank_out, void* ws, size_t ws_bytes);
+
+/* Quaternion product D = alpha * op(A) op(B) + beta * D (Section 2.2
+ * multiplication laws) with real alpha, beta; op(X) is X or X^H.
+ * Mapped onto MFMA as the real-block (4m x 4k) times component-stacked
+ * (4k x n) contraction: exactly 16 real multiply-accumulates per quaternion
+ * multiply-accumulate.  compute = QCUR_F64: A, B, D FP64.  QCUR_F32: A, B, D
+ * FP32.  QCUR_BF16: A, B BF16, D FP32 (FP32 accumulation).  D must not
+ * alias A or B.  beta == 0 ignores the old contents of D.  ws (may be NULL)
+ * enables a deterministic split of K for thin outputs when ws_bytes >=
+ * qcur_gemm_workspace(M, N, K, compute); results do not depend on it beyond
+ * summation order. */
+qcur_status qcur_gemm(qcur_handle handle, int opA, int opB, double alpha, const qcur_qmat* A,
+                      const qcur_qmat* B, double beta, qcur_qmat* D, int compute, void* ws,
+                      size_t ws_bytes);
+
+/* Core and optional product (Algorithm 1 step 3; Section 3.1).
+ * core QCUR_CORE_WPINV: U = W^+ (W r x c, any dtype; A, C, R may be NULL).
+ * core QCUR_CORE_CAR: U = C^+ (A R^+) with C (m x c), R (r x n), A (m x n).
+ * Pseudoinverses are FP64.  compute selects the dtype of the products:
+ * QCUR_F64 (U, B FP64), QCUR_F32 (FP32 products; U, B FP32) or QCUR_BF16
+ * (BF16 operands with FP32 accumulation; U, B FP32).  A, C, R and W may be
+ * given in any dtype: operands are converted to the product dtype in the
+ * workspace, while the refinement residual A - C U R subtracts A in the
+ * precision it was given.  refine_steps >= 0 applies U <- U + C^+ ((A - C U R) R^+)
+ * that many times (CAR only).  B (m x n, may be NULL) receives C U R.
+ * rank_out (device int64[2], may be NULL): kept ranks of the pseudoinverses
+ * (W: [rank, rank]; CAR: [rank C, rank R]).
+ * ws: qcur_approx_workspace(m, n, c, r, core, compute) bytes. */
+qcur_status qcur_approx(qcur_handle handle, const qcur_qmat* A, const qcur_qmat* C,
+                        const qcur_qmat* R, const qcur_qmat* W, int core, int compute,
+                        int refine_steps, double rtol, int64_t max_rank, qcur_qmat* U,
+                        qcur_qmat* B, int64_t* rank_out, void* ws, size_t ws_bytes);
+
+/* Residual ||P_Omega(A - C U R)||_F (the numerator of the relative error of
+ * Example 4.2; with a mask, the data-fit term of the completion problem in
+ * Example 4.4).  B1 = C U is formed first, then B1 R is produced tile by tile
+ * and never stored: each tile subtracts A, applies the mask, squares and
+ * reduces; tile partials are summed in FP64 in a fixed order.
+ * mask: uint8 m x n with row stride mask_ld (NULL = all ones).
+ * compute as in qcur_gemm; C, U, R are converted to its operand dtype when
+ * needed, A is read in its own dtype.
+ * fro: device double[1].  E (optional, m x n, FP64 for QCUR_F64 else FP32)
+ * receives e_scale * P_Omega(A - CUR).
+ * ws: qcur_residual_workspace(m, n, c, r, compute) bytes. */
+qcur_status qcur_residual(qcur_handle handle, const qcur_qmat* A, const qcur_qmat* C,
+                          const qcur_qmat* U, const qcur_qmat* R, const uint8_t* mask,
+                          int64_t mask_ld, int compute, double* fro, qcur_qmat* E,
+                          double e_scale, void* ws, size_t ws_bytes);
+
+/* Adjoint of B = C U R with U = W^+ (intersection core), through the gathers
+ * C = A(:,J), R = A(I,:), W = A(I,J) and the pseudoinverse (constant-rank
+ * derivative of Golub and Pereyra).  U is recomputed from W, not stored.
+ * gB != NULL: dA = d<gB, CUR(A)>/dA (vector-Jacobian product).
+ * gB == NULL: masked loss L = ||P_Omega(A - CUR(A))||_F^2 (mask as in
+ * qcur_residual); dA = dL/dA and loss (device double[1], may be NULL)
+ * receives L.  I and J must hold distinct in-range indices (else
+ * QCUR_ERR_ARG in the status word).  compute QCUR_F64 or QCUR_F32 (A, gB
+ * and dA in that dtype).  ws: qcur_backward_workspace(m, n, c, r, compute). */
+qcur_status qcur_backward(qcur_handle handle, const qcur_qmat* A, const int64_t* I, int64_t r,
+                          const int64_t* J, int64_t c, const qcur_qmat* gB, const uint8_t* mask,
+                          int64_t mask_ld, double rtol, int64_t max_rank, int compute,
+                          qcur_qmat* dA, double* loss, void* ws, size_t ws_bytes);
+
+/* ---- helpers ----------------------------------------------------------- */
+
+/* Elementwise dtype conversion Y = X (same shape; BF16 with
+ * round-to-nearest-even, FP64 -> FP32 correctly rounded). */
+qcur_status qcur_cast(qcur_handle handle, const qcur_qmat* X, qcur_qmat* Y);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QCUR_H */

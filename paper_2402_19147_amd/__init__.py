@@ -1,0 +1,15 @@
+"""libqcur: quaternion CUR (QMCUR) low-rank approximation on AMD MI355X.
+
+The compute path is the HIP library libqcur.so (built in-tree by
+`python -m paper_2402_19147_amd.build`); this package is its ctypes binding
+plus a torch.autograd.Function for the masked CUR loss.  Importing the
+package does not load the library; the first call does, and fails loudly
+if it has not been built.
+"""
+from . import qcur  # noqa: F401
+from .qcur import (F64, F32, BF16, OP_N, OP_H, LENGTH, UNIFORM, CORE_WPINV, CORE_CAR,  # noqa: F401
+                   QcurError, probs, draw, gather, pinv, gemm, approx, residual, backward, cast,
+                   solve, sync_status, lib)
+
+__all__ = ["qcur", "probs", "draw", "gather", "pinv", "gemm", "approx", "residual", "backward", "cast",
+           "solve", "sync_status", "lib", "QcurError"]

@@ -1,0 +1,841 @@
+// libqcur C ABI: argument validation, workspace layout and the orchestration
+// of the QMCUR steps (Algorithm 1) on top of the kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "qcur_internal.hpp"
+
+using namespace qcur;
+
+struct qcur_ctx {
+  Ctx c;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+qcur_status fail(qcur_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+qcur_status fail(qcur_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(QCUR_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));             \
+  } while (0)
+
+#define CHK(expr)                       \
+  do {                                  \
+    qcur_status s_ = (expr);            \
+    if (s_ != QCUR_OK) return s_;       \
+  } while (0)
+
+bool valid_dtype(int dt) { return dt == QCUR_F64 || dt == QCUR_F32 || dt == QCUR_BF16; }
+
+// Shape/stride/dtype checks of one operand.
+qcur_status check_qmat(const qcur_qmat* m, const char* name) {
+  if (!m) return fail(QCUR_ERR_ARG, "%s is NULL", name);
+  if (m->rows < 0 || m->cols < 0) return fail(QCUR_ERR_ARG, "%s has a negative size", name);
+  if (!valid_dtype(m->dtype)) return fail(QCUR_ERR_DTYPE, "%s has an unknown dtype %d", name, (int)m->dtype);
+  if (m->rows > 0 && m->cols > 0) {
+    if (!m->p) return fail(QCUR_ERR_ARG, "%s has a NULL data pointer", name);
+    if (m->ld < m->cols) return fail(QCUR_ERR_SHAPE, "%s: ld < cols", name);
+    if (m->pstride < (m->rows - 1) * m->ld + m->cols)
+      return fail(QCUR_ERR_SHAPE, "%s: planes overlap (pstride too small)", name);
+  }
+  return QCUR_OK;
+}
+
+qcur_status check_dims(const qcur_qmat* m, const char* name, int64_t rows, int64_t cols) {
+  if (m->rows != rows || m->cols != cols)
+    return fail(QCUR_ERR_SHAPE, "%s is %lldx%lld, expected %lldx%lld", name, (long long)m->rows,
+                (long long)m->cols, (long long)rows, (long long)cols);
+  return QCUR_OK;
+}
+
+qcur_status check_handle(qcur_handle h) {
+  if (!h) return fail(QCUR_ERR_ARG, "handle is NULL");
+  return QCUR_OK;
+}
+
+// ---- workspace: a bump allocator used both to size and to carve buffers.
+struct Bump {
+  char* base;
+  size_t used;
+  explicit Bump(void* b) : base((char*)b), used(0) {}
+  void* take(size_t bytes) {
+    used = (used + 255) & ~(size_t)255;
+    void* p = base ? base + used : nullptr;
+    used += bytes;
+    return p;
+  }
+  QView mat(int64_t rows, int64_t cols, int dt) {
+    QView v;
+    v.p = take((size_t)4 * rows * cols * dtype_size(dt));
+    v.rows = rows;
+    v.cols = cols;
+    v.ld = cols;
+    v.ps = rows * cols;
+    v.dt = dt;
+    return v;
+  }
+};
+
+int acc_dt(int compute) { return compute == QCUR_F64 ? QCUR_F64 : QCUR_F32; }
+int in_dt(int compute) { return compute; }
+
+// ---- pseudoinverse -------------------------------------------------------
+struct PinvPlan {
+  int64_t p, q;     // X is p x q
+  int64_t pp, qq;   // working tall shape: pp >= qq
+  bool tall;
+};
+
+PinvPlan pinv_plan(int64_t p, int64_t q) {
+  PinvPlan pl;
+  pl.p = p;
+  pl.q = q;
+  pl.tall = p >= q;
+  pl.pp = std::max(p, q);
+  pl.qq = std::min(p, q);
+  return pl;
+}
+
+struct PinvWs {
+  double* Y;
+  double* V;
+  double* sig;
+  unsigned* flag;
+  void* gws;
+  size_t gws_bytes;
+};
+
+PinvWs pinv_carve(Bump& b, int64_t p, int64_t q) {
+  PinvPlan pl = pinv_plan(p, q);
+  PinvWs w;
+  w.Y = (double*)b.take((size_t)4 * pl.qq * pl.pp * 8);
+  w.V = (double*)b.take((size_t)4 * pl.qq * pl.qq * 8);
+  w.sig = (double*)b.take((size_t)2 * std::max<int64_t>(pl.qq, 1) * 8);
+  w.flag = (unsigned*)b.take(256);
+  // final product: tall -> (qq x pp), wide -> (pp x qq); K = qq
+  const int64_t M = pl.tall ? pl.qq : pl.pp;
+  const int64_t N = pl.tall ? pl.pp : pl.qq;
+  w.gws_bytes = gemm_workspace(M, N, pl.qq, QCUR_F64);
+  w.gws = b.take(w.gws_bytes);
+  return w;
+}
+
+size_t pinv_ws_size(int64_t p, int64_t q) {
+  Bump b(nullptr);
+  pinv_carve(b, p, q);
+  return b.used + 256;
+}
+
+constexpr int MAX_SWEEPS = 40;
+
+// X (any dtype) -> Xp (F64, q x p).
+qcur_status pinv_impl(const Ctx& c, QView X, double rtol, int64_t max_rank, QView Xp, int64_t* rank_out,
+                      PinvWs w) {
+  PinvPlan pl = pinv_plan(X.rows, X.cols);
+  if (rtol < 0) rtol = (double)std::max(pl.p, pl.q) * std::ldexp(1.0, -52);
+  if (pl.qq == 0) {
+    if (rank_out) HIPCHK(hipMemsetAsync(rank_out, 0, sizeof(int64_t), c.stream));
+    return QCUR_OK;
+  }
+  const int64_t pp = pl.pp, qq = pl.qq;
+  // column rows of the tall working matrix Z (Z = X or X^H)
+  QView Yv{w.Y, qq, pp, pp, qq * pp, QCUR_F64};
+  HIPCHK(launch_check_finite(c, X));
+  HIPCHK(launch_cast(c, X, Yv, pl.tall ? CAST_T : CAST_CONJ));
+  HIPCHK(launch_fill_identity(c, w.V, qq));
+  const double tol = std::sqrt((double)pp) * std::ldexp(1.0, -53);
+  if (jacobi_small_fits(pp, qq)) {
+    HIPCHK(launch_jacobi_small(c, w.Y, pp, qq, w.V, tol, MAX_SWEEPS, w.flag));
+  } else {
+    const int64_t qpad = (qq + 1) / 2 * 2;
+    unsigned host_flag = 1;
+    for (int sweep = 0; sweep < MAX_SWEEPS && host_flag; ++sweep) {
+      HIPCHK(hipMemsetAsync(w.flag, 0, sizeof(unsigned), c.stream));
+      for (int round = 0; round < qpad - 1; ++round)
+        HIPCHK(launch_jacobi_round(c, w.Y, pp, qq, w.V, qpad, round, tol, w.flag));
+      HIPCHK(hipMemcpyAsync(&host_flag, w.flag, sizeof(unsigned), hipMemcpyDeviceToHost, c.stream));
+      HIPCHK(hipStreamSynchronize(c.stream));
+    }
+  }
+  HIPCHK(launch_pinv_scale(c, w.Y, pp, qq, rtol, max_rank, rank_out, w.sig));
+  HIPCHK(launch_pinv_apply(c, w.Y, pp, qq, w.V, w.sig + qq));
+  // Ydc = conj(D Yc) (qq x pp), Vcc = conj(Vc) (qq x qq)
+  QView Ydc{w.Y, qq, pp, pp, qq * pp, QCUR_F64};
+  QView Vcc{w.V, qq, qq, qq, qq * qq, QCUR_F64};
+  if (pl.tall) {
+    HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, Vcc, Ydc, 0.0, Xp, QCUR_F64, w.gws, w.gws_bytes));
+  } else {
+    HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, Ydc, Vcc, 0.0, Xp, QCUR_F64, w.gws, w.gws_bytes));
+  }
+  return QCUR_OK;
+}
+
+// Returns X itself when it already has dtype dt, else a converted copy.
+QView as_dtype(const Ctx& c, QView X, int dt, Bump& b, bool count_only, hipError_t* err) {
+  if (X.dt == dt) return X;
+  QView Y = b.mat(X.rows, X.cols, dt);
+  if (!count_only) *err = launch_cast(c, X, Y, CAST_COPY);
+  return Y;
+}
+
+// ---- approx -----------------------------------------------------------------
+struct ApproxArgs {
+  QView A, C, R, W, U, B;
+  bool hasA, hasC, hasR, hasW, hasB;
+  int core, compute, refine;
+  double rtol;
+  int64_t max_rank;
+  int64_t* rank_out;
+};
+
+// Runs (or, with a null workspace base, only sizes) the approx pipeline.
+qcur_status approx_run(const Ctx& c, const ApproxArgs& a, int64_t m, int64_t n, int64_t cc, int64_t r, Bump& b,
+                       bool count_only) {
+  hipError_t err = hipSuccess;
+  const int idt = in_dt(a.compute), adt = acc_dt(a.compute);
+  if (a.core == QCUR_CORE_WPINV) {
+    // U = W^+ (c x r), FP64, then converted to the output dtype
+    QView U64 = a.U.dt == QCUR_F64 ? a.U : b.mat(cc, r, QCUR_F64);
+    PinvWs w = pinv_carve(b, r, cc);
+    if (!count_only) {
+      CHK(pinv_impl(c, a.W, a.rtol, a.max_rank, U64, a.rank_out, w));
+      if (a.rank_out) HIPCHK(hipMemcpyAsync(a.rank_out + 1, a.rank_out, 8, hipMemcpyDeviceToDevice, c.stream));
+      if (U64.p != a.U.p) HIPCHK(launch_cast(c, U64, a.U, CAST_COPY));
+    }
+  } else {
+    // C^+ (c x m) and R^+ (n x r) in FP64
+    QView Cp = b.mat(cc, m, QCUR_F64);
+    QView Rp = b.mat(n, r, QCUR_F64);
+    {
+      Bump pb = b;
+      PinvWs w1 = pinv_carve(pb, m, cc);
+      size_t u1 = pb.used;
+      Bump pb2 = b;
+      PinvWs w2 = pinv_carve(pb2, r, n);
+      size_t u2 = pb2.used;
+      if (!count_only) {
+        CHK(pinv_impl(c, a.C, a.rtol, a.max_rank, Cp, a.rank_out, w1));
+        CHK(pinv_impl(c, a.R, a.rtol, a.max_rank, Rp, a.rank_out ? a.rank_out + 1 : nullptr, w2));
+      }
+      b.used = std::max(u1, u2);
+    }
+    // operands in the product dtype
+    QView Ax = as_dtype(c, a.A, idt, b, count_only, &err);
+    QView Cx = as_dtype(c, a.C, idt, b, count_only, &err);
+    QView Rx = as_dtype(c, a.R, idt, b, count_only, &err);
+    QView Cpx = as_dtype(c, Cp, idt, b, count_only, &err);
+    QView Rpx = as_dtype(c, Rp, idt, b, count_only, &err);
+    if (err != hipSuccess) return fail(QCUR_ERR_DEVICE, "cast: %s", hipGetErrorString(err));
+    QView T = b.mat(m, r, adt);
+    size_t gw = std::max({gemm_workspace(m, r, n, a.compute), gemm_workspace(cc, r, m, a.compute),
+                          gemm_workspace(m, r, cc, a.compute), gemm_workspace(m, n, r, a.compute)});
+    void* gws = b.take(gw);
+    QView Tx = (idt == adt) ? T : b.mat(m, r, idt);
+    // U0 = C^+ (A R^+)
+    if (!count_only) {
+      HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Ax, Rpx, 0.0, T, a.compute, gws, gw));
+      if (Tx.p != T.p) HIPCHK(launch_cast(c, T, Tx, CAST_COPY));
+      HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Cpx, Tx, 0.0, a.U, a.compute, gws, gw));
+    }
+    if (a.refine > 0) {
+      QView Ux = (idt == adt) ? a.U : b.mat(cc, r, idt);
+      QView B1 = b.mat(m, r, adt);
+      QView B1x = (idt == adt) ? B1 : b.mat(m, r, idt);
+      QView E = b.mat(m, n, adt);
+      QView Ex = (idt == adt) ? E : b.mat(m, n, idt);
+      double* part = (double*)b.take(residual_tiles(m, n) * 8);
+      for (int s = 0; s < a.refine && !count_only; ++s) {
+        if (Ux.p != a.U.p) HIPCHK(launch_cast(c, a.U, Ux, CAST_COPY));
+        HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Cx, Ux, 0.0, B1, a.compute, gws, gw));
+        if (B1x.p != B1.p) HIPCHK(launch_cast(c, B1, B1x, CAST_COPY));
+        // E = A - B1 R, with A in the precision it was given
+        HIPCHK(launch_residual_gemm(c, a.A, B1x, Rx, nullptr, 0, a.compute, part, &E, 1.0));
+        if (Ex.p != E.p) HIPCHK(launch_cast(c, E, Ex, CAST_COPY));
+        HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Ex, Rpx, 0.0, T, a.compute, gws, gw));
+        if (Tx.p != T.p) HIPCHK(launch_cast(c, T, Tx, CAST_COPY));
+        HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Cpx, Tx, 1.0, a.U, a.compute, gws, gw));
+      }
+    }
+    if (a.hasB) {
+      QView Ux = (idt == adt) ? a.U : b.mat(cc, r, idt);
+      QView B1 = b.mat(m, r, adt);
+      QView B1x = (idt == adt) ? B1 : b.mat(m, r, idt);
+      if (!count_only) {
+        if (Ux.p != a.U.p) HIPCHK(launch_cast(c, a.U, Ux, CAST_COPY));
+        HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Cx, Ux, 0.0, B1, a.compute, gws, gw));
+        if (B1x.p != B1.p) HIPCHK(launch_cast(c, B1, B1x, CAST_COPY));
+        HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, B1x, Rx, 0.0, a.B, a.compute, gws, gw));
+      }
+    }
+    return QCUR_OK;
+  }
+  if (a.hasB) {
+    // B = (C U) R for the intersection core
+    QView Cx = as_dtype(c, a.C, idt, b, count_only, &err);
+    QView Rx = as_dtype(c, a.R, idt, b, count_only, &err);
+    QView Ux = as_dtype(c, a.U, idt, b, count_only, &err);
+    if (err != hipSuccess) return fail(QCUR_ERR_DEVICE, "cast: %s", hipGetErrorString(err));
+    QView B1 = b.mat(m, r, adt);
+    QView B1x = (idt == adt) ? B1 : b.mat(m, r, idt);
+    size_t gw = std::max(gemm_workspace(m, r, cc, a.compute), gemm_workspace(m, n, r, a.compute));
+    void* gws = b.take(gw);
+    if (!count_only) {
+      HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Cx, Ux, 0.0, B1, a.compute, gws, gw));
+      if (B1x.p != B1.p) HIPCHK(launch_cast(c, B1, B1x, CAST_COPY));
+      HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, B1x, Rx, 0.0, a.B, a.compute, gws, gw));
+    }
+  }
+  return QCUR_OK;
+}
+
+// Shapes of U/B views used for sizing only.
+ApproxArgs sizing_args(int64_t m, int64_t n, int64_t cc, int64_t r, int core, int compute) {
+  ApproxArgs a{};
+  const int adt = acc_dt(compute);
+  a.A = QView{nullptr, m, n, n, m * n, compute == QCUR_F64 ? QCUR_F64 : QCUR_F32};
+  a.C = QView{nullptr, m, cc, cc, m * cc, compute};
+  a.R = QView{nullptr, r, n, n, r * n, compute};
+  a.W = QView{nullptr, r, cc, cc, r * cc, compute};
+  a.U = QView{nullptr, cc, r, r, cc * r, adt};
+  a.B = QView{nullptr, m, n, n, m * n, adt};
+  a.core = core;
+  a.compute = compute;
+  a.refine = 1;
+  a.hasB = true;
+  return a;
+}
+
+// ---- residual ---------------------------------------------------------------
+qcur_status residual_run(const Ctx& c, QView A, QView C, QView U, QView R, const uint8_t* mask, int64_t mask_ld,
+                         int compute, double* out, int take_sqrt, QView* E, double e_scale, Bump& b,
+                         bool count_only) {
+  hipError_t err = hipSuccess;
+  const int idt = in_dt(compute), adt = acc_dt(compute);
+  const int64_t m = A.rows, n = A.cols, r = R.rows;
+  QView Cx = as_dtype(c, C, idt, b, count_only, &err);
+  QView Ux = as_dtype(c, U, idt, b, count_only, &err);
+  QView Rx = as_dtype(c, R, idt, b, count_only, &err);
+  if (err != hipSuccess) return fail(QCUR_ERR_DEVICE, "cast: %s", hipGetErrorString(err));
+  QView B1 = b.mat(m, r, adt);
+  QView B1x = (idt == adt) ? B1 : b.mat(m, r, idt);
+  size_t gw = gemm_workspace(m, r, C.cols, compute);
+  void* gws = b.take(gw);
+  double* part = (double*)b.take(std::max<size_t>(residual_tiles(m, n), 1) * 8);
+  if (count_only) return QCUR_OK;
+  HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Cx, Ux, 0.0, B1, compute, gws, gw));
+  if (B1x.p != B1.p) HIPCHK(launch_cast(c, B1, B1x, CAST_COPY));
+  HIPCHK(launch_residual_gemm(c, A, B1x, Rx, mask, mask_ld, compute, part, E, e_scale));
+  HIPCHK(launch_sum_partials(c, part, (int64_t)residual_tiles(m, n), out, take_sqrt));
+  return QCUR_OK;
+}
+
+// ---- backward ---------------------------------------------------------------
+struct BwdArgs {
+  QView A, gB, dA;
+  bool hasgB;
+  const int64_t* I;
+  const int64_t* J;
+  int64_t r, cc;
+  const uint8_t* mask;
+  int64_t mask_ld;
+  double rtol;
+  int64_t max_rank;
+  int compute;
+  double* loss;
+};
+
+qcur_status backward_run(const Ctx& c, const BwdArgs& a, Bump& b, bool count_only) {
+  const int dt = a.compute;  // F64 or F32 for every large operand
+  const int64_t m = a.A.rows, n = a.A.cols, r = a.r, cc = a.cc;
+  QView C = b.mat(m, cc, dt), R = b.mat(r, n, dt), W = b.mat(r, cc, QCUR_F64);
+  QView U64 = b.mat(cc, r, QCUR_F64);
+  QView Ux = dt == QCUR_F64 ? U64 : b.mat(cc, r, dt);
+  QView G = b.mat(m, n, dt);  // 2 P_Omega(A - CUR) in loss mode
+  QView X1 = b.mat(m, r, dt), X2 = b.mat(cc, n, dt);
+  QView gC = b.mat(m, cc, dt), gR = b.mat(r, n, dt), gU = b.mat(cc, r, dt);
+  QView gU64 = dt == QCUR_F64 ? gU : b.mat(cc, r, QCUR_F64);
+  // pinv adjoint temporaries (FP64)
+  QView Q1 = b.mat(r, r, QCUR_F64), M2 = b.mat(r, r, QCUR_F64), Q3 = b.mat(r, cc, QCUR_F64);
+  QView Q4 = b.mat(r, cc, QCUR_F64), M3 = b.mat(cc, cc, QCUR_F64), gW = b.mat(r, cc, QCUR_F64);
+  QView Q2 = b.mat(r, r, QCUR_F64);
+  int32_t* iinv = (int32_t*)b.take((size_t)std::max<int64_t>(m, 1) * 4);
+  int32_t* jinv = (int32_t*)b.take((size_t)std::max<int64_t>(n, 1) * 4);
+  const size_t gw = std::max({gemm_workspace(m, r, n, dt), gemm_workspace(m, cc, r, dt),
+                              gemm_workspace(cc, n, m, dt), gemm_workspace(r, n, cc, dt),
+                              gemm_workspace(cc, r, m, dt), gemm_workspace(r, r, cc, QCUR_F64),
+                              gemm_workspace(r, cc, r, QCUR_F64), gemm_workspace(cc, cc, r, QCUR_F64),
+                              gemm_workspace(r, cc, cc, QCUR_F64)});
+  void* gws = b.take(gw);
+  // the rest is shared: first the pinv of W, then the residual pass
+  const Bump shared = b;
+  Bump t1 = shared;
+  PinvWs pw = pinv_carve(t1, r, cc);
+  Bump t2 = shared;
+  double* lossbuf = (double*)t2.take(8);
+  CHK(residual_run(c, a.A, C, Ux, R, a.mask, a.mask_ld, dt, nullptr, 0, nullptr, 0.0, t2, true));
+  b.used = std::max(t1.used, t2.used);
+  if (count_only) return QCUR_OK;
+
+  HIPCHK(launch_gather(c, a.A, a.I, r, a.J, cc, &C, &R, &W));
+  HIPCHK(launch_inverse_map(c, a.I, r, m, iinv));
+  HIPCHK(launch_inverse_map(c, a.J, cc, n, jinv));
+  // U = W^+ recomputed (not stored by the forward pass)
+  CHK(pinv_impl(c, W, a.rtol, a.max_rank, U64, nullptr, pw));
+  if (Ux.p != U64.p) HIPCHK(launch_cast(c, U64, Ux, CAST_COPY));
+  double sgn;
+  QView Gb;
+  if (a.hasgB) {
+    Gb = a.gB;
+    sgn = 1.0;
+  } else {
+    // G = 2 P_Omega(A - C U R), loss = ||P_Omega(A - CUR)||^2; the cotangent of B is -G
+    Bump t = shared;
+    t.take(8);
+    double* lossp = a.loss ? a.loss : lossbuf;
+    CHK(residual_run(c, a.A, C, Ux, R, a.mask, a.mask_ld, dt, lossp, 0, &G, 2.0, t, false));
+    Gb = G;
+    sgn = -1.0;
+  }
+  // X1 = Gb R^H (m x r);  gC = sgn X1 U^H (m x c)
+  HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_H, 1.0, Gb, R, 0.0, X1, dt, gws, gw));
+  HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_H, sgn, X1, Ux, 0.0, gC, dt, gws, gw));
+  // X2 = C^H Gb (c x n);  gR = sgn U^H X2 (r x n)
+  HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, C, Gb, 0.0, X2, dt, gws, gw));
+  HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, sgn, Ux, X2, 0.0, gR, dt, gws, gw));
+  // gU = sgn C^H X1 (c x r)
+  HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, sgn, C, X1, 0.0, gU, dt, gws, gw));
+  if (gU64.p != gU.p) HIPCHK(launch_cast(c, gU, gU64, CAST_COPY));
+  // gW = -U^H gU U^H + (I - W U) gU^H U U^H + U^H U gU^H (I - U W)   (FP64)
+  HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, U64, gU64, 0.0, Q1, QCUR_F64, gws, gw));   // U^H gU
+  HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_H, -1.0, Q1, U64, 0.0, gW, QCUR_F64, gws, gw));    // t1
+  HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, W, U64, 0.0, M2, QCUR_F64, gws, gw));      // W U
+  HIPCHK(launch_identity_minus(c, M2));                                                     // I - W U
+  HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, gU64, U64, 0.0, Q2, QCUR_F64, gws, gw));   // gU^H U
+  HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_H, 1.0, Q2, U64, 0.0, Q3, QCUR_F64, gws, gw));     // gU^H U U^H
+  HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, M2, Q3, 1.0, gW, QCUR_F64, gws, gw));      // + t2
+  HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, U64, U64, 0.0, Q1, QCUR_F64, gws, gw));    // U^H U
+  HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_H, 1.0, Q1, gU64, 0.0, Q4, QCUR_F64, gws, gw));    // U^H U gU^H
+  HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, U64, W, 0.0, M3, QCUR_F64, gws, gw));      // U W
+  HIPCHK(launch_identity_minus(c, M3));                                                     // I - U W
+  HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Q4, M3, 1.0, gW, QCUR_F64, gws, gw));      // + t3
+  HIPCHK(launch_backward_assemble(c, a.dA, G, a.hasgB ? 0 : 1, gC, gR, gW, iinv, jinv));
+  return QCUR_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+int qcur_version(void) { return 100; }
+
+const char* qcur_status_string(qcur_status s) {
+  switch (s) {
+    case QCUR_OK: return "QCUR_OK";
+    case QCUR_ERR_ARG: return "QCUR_ERR_ARG";
+    case QCUR_ERR_SHAPE: return "QCUR_ERR_SHAPE";
+    case QCUR_ERR_DTYPE: return "QCUR_ERR_DTYPE";
+    case QCUR_ERR_WORKSPACE: return "QCUR_ERR_WORKSPACE";
+    case QCUR_ERR_SAMPLE: return "QCUR_ERR_SAMPLE";
+    case QCUR_ERR_NUMERIC: return "QCUR_ERR_NUMERIC";
+    case QCUR_ERR_DEVICE: return "QCUR_ERR_DEVICE";
+    case QCUR_ERR_UNSUPPORTED: return "QCUR_ERR_UNSUPPORTED";
+  }
+  return "unknown qcur_status";
+}
+
+const char* qcur_last_error(void) { return g_last_error.c_str(); }
+
+qcur_status qcur_create(qcur_handle* handle, int device) {
+  if (!handle) return fail(QCUR_ERR_ARG, "handle output pointer is NULL");
+  *handle = nullptr;
+  int count = 0;
+  HIPCHK(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return fail(QCUR_ERR_ARG, "device %d out of range (%d devices)", device, count);
+  int old = 0;
+  HIPCHK(hipGetDevice(&old));
+  HIPCHK(hipSetDevice(device));
+  unsigned* st = nullptr;
+  hipError_t e = hipMalloc(&st, 256);
+  if (e == hipSuccess) e = hipMemset(st, 0, 256);
+  (void)hipSetDevice(old);
+  if (e != hipSuccess) return fail(QCUR_ERR_DEVICE, "status word: %s", hipGetErrorString(e));
+  qcur_ctx* h = new qcur_ctx;
+  h->c.device = device;
+  h->c.stream = nullptr;
+  h->c.status = st;
+  *handle = h;
+  return QCUR_OK;
+}
+
+qcur_status qcur_destroy(qcur_handle h) {
+  if (!h) return QCUR_OK;
+  (void)hipFree(h->c.status);
+  delete h;
+  return QCUR_OK;
+}
+
+qcur_status qcur_set_stream(qcur_handle h, void* stream) {
+  CHK(check_handle(h));
+  h->c.stream = (hipStream_t)stream;
+  return QCUR_OK;
+}
+
+qcur_status qcur_sync_status(qcur_handle h) {
+  CHK(check_handle(h));
+  unsigned bits = 0;
+  HIPCHK(hipStreamSynchronize(h->c.stream));
+  HIPCHK(hipMemcpy(&bits, h->c.status, sizeof(unsigned), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemset(h->c.status, 0, sizeof(unsigned)));
+  if (bits & ST_ARG) return fail(QCUR_ERR_ARG, "a kernel reported an invalid index");
+  if (bits & ST_SAMPLE) return fail(QCUR_ERR_SAMPLE, "a kernel reported invalid sampling weights");
+  if (bits & ST_NUMERIC) return fail(QCUR_ERR_NUMERIC, "a kernel reported a zero or non-finite value");
+  return QCUR_OK;
+}
+
+size_t qcur_probs_workspace(int64_t m, int64_t n) {
+  if (m <= 0 || n <= 0) return 0;
+  int rb, nrb, ncb;
+  probs_grid(m, n, &rb, &nrb, &ncb);
+  Bump b(nullptr);
+  b.take((size_t)nrb * n * 8);
+  b.take((size_t)ncb * m * 8);
+  b.take((size_t)(m + n) * 8);
+  return b.used + 256;
+}
+
+size_t qcur_pinv_workspace(int64_t p, int64_t q) {
+  if (p < 0 || q < 0) return 0;
+  return pinv_ws_size(p, q);
+}
+
+size_t qcur_gemm_workspace(int64_t M, int64_t N, int64_t K, int compute) {
+  if (M <= 0 || N <= 0 || K <= 0 || !valid_dtype(compute)) return 0;
+  return gemm_workspace(M, N, K, compute);
+}
+
+size_t qcur_approx_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int core, int compute) {
+  if (m < 0 || n < 0 || c < 0 || r < 0 || !valid_dtype(compute)) return 0;
+  Ctx dummy{0, nullptr, nullptr};
+  ApproxArgs a = sizing_args(m, n, c, r, core, compute);
+  Bump b(nullptr);
+  // operands may arrive in any dtype: size for the worst case (all converted)
+  a.A.dt = a.C.dt = a.R.dt = a.W.dt = (compute == QCUR_F64) ? QCUR_F32 : QCUR_F64;
+  a.U.dt = (compute == QCUR_F64) ? QCUR_F32 : QCUR_F32;
+  approx_run(dummy, a, m, n, c, r, b, true);
+  return b.used + 256;
+}
+
+size_t qcur_residual_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int compute) {
+  if (m < 0 || n < 0 || c < 0 || r < 0 || !valid_dtype(compute)) return 0;
+  Ctx dummy{0, nullptr, nullptr};
+  const int other = compute == QCUR_F64 ? QCUR_F32 : QCUR_F64;
+  QView A{nullptr, m, n, n, m * n, other}, C{nullptr, m, c, c, m * c, other};
+  QView U{nullptr, c, r, r, c * r, other}, R{nullptr, r, n, n, r * n, other};
+  Bump b(nullptr);
+  residual_run(dummy, A, C, U, R, nullptr, 0, compute, nullptr, 1, nullptr, 0.0, b, true);
+  return b.used + 256;
+}
+
+size_t qcur_backward_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int compute) {
+  if (m < 0 || n < 0 || c < 0 || r < 0 || (compute != QCUR_F64 && compute != QCUR_F32)) return 0;
+  Ctx dummy{0, nullptr, nullptr};
+  BwdArgs a{};
+  a.A = QView{nullptr, m, n, n, m * n, compute};
+  a.r = r;
+  a.cc = c;
+  a.compute = compute;
+  Bump b(nullptr);
+  backward_run(dummy, a, b, true);
+  return b.used + 256 + 64;
+}
+
+// ---- probs
+qcur_status qcur_probs(qcur_handle h, const qcur_qmat* A, int sampling, double* p_col, double* q_row, double* fro2,
+                       void* ws, size_t ws_bytes) {
+  CHK(check_qmat(A, "A"));
+  if (A->rows < 1 || A->cols < 1) return fail(QCUR_ERR_SHAPE, "A must have at least one row and column");
+  if (sampling != QCUR_LENGTH && sampling != QCUR_UNIFORM) return fail(QCUR_ERR_ARG, "unknown sampling %d", sampling);
+  if (!p_col || !q_row) return fail(QCUR_ERR_ARG, "p_col and q_row must not be NULL");
+  const bool need_pass = sampling == QCUR_LENGTH || fro2 != nullptr;
+  const size_t need = need_pass ? qcur_probs_workspace(A->rows, A->cols) : 0;
+  if (need_pass && (!ws || ws_bytes < need))
+    return fail(QCUR_ERR_WORKSPACE, "probs needs %zu workspace bytes", need);
+  CHK(check_handle(h));
+  const Ctx& c = h->c;
+  QView Av = view_of(*A);
+  const int64_t m = Av.rows, n = Av.cols;
+  if (!need_pass) {
+    HIPCHK(launch_probs_finish(c, m, n, nullptr, nullptr, 0, 0, sampling, p_col, q_row, nullptr, nullptr));
+    return QCUR_OK;
+  }
+  int rb, nrb, ncb;
+  probs_grid(m, n, &rb, &nrb, &ncb);
+  Bump b(ws);
+  double* colpart = (double*)b.take((size_t)nrb * n * 8);
+  double* rowpart = (double*)b.take((size_t)ncb * m * 8);
+  double* scratch = (double*)b.take((size_t)(m + n) * 8);
+  HIPCHK(launch_probs_partials(c, Av, colpart, rowpart, rb, ncb));
+  HIPCHK(launch_probs_finish(c, m, n, colpart, rowpart, nrb, ncb, sampling, p_col, q_row, fro2, scratch));
+  return QCUR_OK;
+}
+
+// ---- draw
+qcur_status qcur_draw(qcur_handle h, const double* probs, int64_t n, int64_t count, uint64_t seed, uint64_t set_id,
+                      int with_replacement, int64_t* idx) {
+  if (n < 1) return fail(QCUR_ERR_ARG, "n must be >= 1");
+  if (count < 0 || count >= ((int64_t)1 << 31)) return fail(QCUR_ERR_ARG, "count out of range");
+  if (with_replacement != 0 && with_replacement != 1) return fail(QCUR_ERR_ARG, "with_replacement must be 0 or 1");
+  if (!with_replacement && count > n) return fail(QCUR_ERR_ARG, "count > n without replacement");
+  if (n > (with_replacement ? 8192 : 16384))
+    return fail(QCUR_ERR_UNSUPPORTED, "n = %lld exceeds the sampler's LDS limit", (long long)n);
+  if (count > 0 && (!probs || !idx)) return fail(QCUR_ERR_ARG, "probs and idx must not be NULL");
+  CHK(check_handle(h));
+  if (count == 0) return QCUR_OK;
+  HIPCHK(launch_draw(h->c, probs, n, count, seed, set_id, with_replacement, idx));
+  return QCUR_OK;
+}
+
+// ---- gather
+qcur_status qcur_gather(qcur_handle h, const qcur_qmat* A, const int64_t* I, int64_t r, const int64_t* J, int64_t c,
+                        qcur_qmat* C, qcur_qmat* R, qcur_qmat* W) {
+  CHK(check_qmat(A, "A"));
+  if (r < 0 || c < 0) return fail(QCUR_ERR_ARG, "negative index count");
+  if (C) {
+    CHK(check_qmat(C, "C"));
+    CHK(check_dims(C, "C", A->rows, c));
+    if (c > 0 && !J) return fail(QCUR_ERR_ARG, "J is NULL");
+  }
+  if (R) {
+    CHK(check_qmat(R, "R"));
+    CHK(check_dims(R, "R", r, A->cols));
+    if (r > 0 && !I) return fail(QCUR_ERR_ARG, "I is NULL");
+  }
+  if (W) {
+    CHK(check_qmat(W, "W"));
+    CHK(check_dims(W, "W", r, c));
+    if ((r > 0 && !I) || (c > 0 && !J)) return fail(QCUR_ERR_ARG, "I or J is NULL");
+  }
+  CHK(check_handle(h));
+  QView Av = view_of(*A);
+  QView Cv, Rv, Wv;
+  if (C) Cv = view_of(*C);
+  if (R) Rv = view_of(*R);
+  if (W) Wv = view_of(*W);
+  HIPCHK(launch_gather(h->c, Av, I, r, J, c, C ? &Cv : nullptr, R ? &Rv : nullptr, W ? &Wv : nullptr));
+  return QCUR_OK;
+}
+
+// ---- pinv
+qcur_status qcur_pinv(qcur_handle h, const qcur_qmat* X, double rtol, int64_t max_rank, qcur_qmat* Xp,
+                      int64_t* rank_out, void* ws, size_t ws_bytes) {
+  CHK(check_qmat(X, "X"));
+  CHK(check_qmat(Xp, "Xp"));
+  if (X->dtype != QCUR_F64 || Xp->dtype != QCUR_F64) return fail(QCUR_ERR_DTYPE, "pinv works in FP64");
+  CHK(check_dims(Xp, "Xp", X->cols, X->rows));
+  if (!std::isfinite(rtol)) return fail(QCUR_ERR_ARG, "rtol must be finite");
+  if (max_rank < 0) return fail(QCUR_ERR_ARG, "max_rank must be >= 0");
+  const size_t need = qcur_pinv_workspace(X->rows, X->cols);
+  if (!ws || ws_bytes < need) return fail(QCUR_ERR_WORKSPACE, "pinv needs %zu workspace bytes", need);
+  CHK(check_handle(h));
+  Bump b(ws);
+  PinvWs w = pinv_carve(b, X->rows, X->cols);
+  return pinv_impl(h->c, view_of(*X), rtol, max_rank, view_of(*Xp), rank_out, w);
+}
+
+// ---- gemm
+qcur_status qcur_gemm(qcur_handle h, int opA, int opB, double alpha, const qcur_qmat* A, const qcur_qmat* B,
+                      double beta, qcur_qmat* D, int compute, void* ws, size_t ws_bytes) {
+  CHK(check_qmat(A, "A"));
+  CHK(check_qmat(B, "B"));
+  CHK(check_qmat(D, "D"));
+  if ((opA != QCUR_OP_N && opA != QCUR_OP_H) || (opB != QCUR_OP_N && opB != QCUR_OP_H))
+    return fail(QCUR_ERR_ARG, "op must be QCUR_OP_N or QCUR_OP_H");
+  if (!valid_dtype(compute)) return fail(QCUR_ERR_DTYPE, "unknown compute dtype");
+  if (A->dtype != compute || B->dtype != compute || D->dtype != acc_dt(compute))
+    return fail(QCUR_ERR_DTYPE, "operands must be in the compute dtype (BF16: D FP32)");
+  const int64_t M = opA == QCUR_OP_N ? A->rows : A->cols;
+  const int64_t K = opA == QCUR_OP_N ? A->cols : A->rows;
+  const int64_t K2 = opB == QCUR_OP_N ? B->rows : B->cols;
+  const int64_t N = opB == QCUR_OP_N ? B->cols : B->rows;
+  if (K != K2) return fail(QCUR_ERR_SHAPE, "inner sizes differ (%lld vs %lld)", (long long)K, (long long)K2);
+  CHK(check_dims(D, "D", M, N));
+  if (!std::isfinite(alpha) || !std::isfinite(beta)) return fail(QCUR_ERR_ARG, "alpha/beta must be finite");
+  CHK(check_handle(h));
+  HIPCHK(launch_gemm(h->c, opA, opB, alpha, view_of(*A), view_of(*B), beta, view_of(*D), compute, ws, ws_bytes));
+  return QCUR_OK;
+}
+
+// ---- approx
+qcur_status qcur_approx(qcur_handle h, const qcur_qmat* A, const qcur_qmat* C, const qcur_qmat* R,
+                        const qcur_qmat* W, int core, int compute, int refine_steps, double rtol, int64_t max_rank,
+                        qcur_qmat* U, qcur_qmat* B, int64_t* rank_out, void* ws, size_t ws_bytes) {
+  if (core != QCUR_CORE_WPINV && core != QCUR_CORE_CAR) return fail(QCUR_ERR_ARG, "unknown core %d", core);
+  if (!valid_dtype(compute)) return fail(QCUR_ERR_DTYPE, "unknown compute dtype");
+  if (refine_steps < 0) return fail(QCUR_ERR_ARG, "refine_steps must be >= 0");
+  if (!std::isfinite(rtol)) return fail(QCUR_ERR_ARG, "rtol must be finite");
+  if (max_rank < 0) return fail(QCUR_ERR_ARG, "max_rank must be >= 0");
+  CHK(check_qmat(U, "U"));
+  if (U->dtype != acc_dt(compute)) return fail(QCUR_ERR_DTYPE, "U must be FP64 (F64 compute) or FP32");
+  int64_t m = 0, n = 0, cc = U->rows, r = U->cols;
+  ApproxArgs a{};
+  if (core == QCUR_CORE_WPINV) {
+    CHK(check_qmat(W, "W"));
+    CHK(check_dims(W, "W", r, cc));
+    a.W = view_of(*W);
+  } else {
+    CHK(check_qmat(A, "A"));
+    CHK(check_qmat(C, "C"));
+    CHK(check_qmat(R, "R"));
+    m = A->rows;
+    n = A->cols;
+    CHK(check_dims(C, "C", m, cc));
+    CHK(check_dims(R, "R", r, n));
+    a.A = view_of(*A);
+    a.C = view_of(*C);
+    a.R = view_of(*R);
+  }
+  if (B) {
+    CHK(check_qmat(B, "B"));
+    if (B->dtype != acc_dt(compute)) return fail(QCUR_ERR_DTYPE, "B must be FP64 (F64 compute) or FP32");
+    if (core == QCUR_CORE_WPINV) {
+      CHK(check_qmat(C, "C"));
+      CHK(check_qmat(R, "R"));
+      m = C->rows;
+      n = R->cols;
+      CHK(check_dims(C, "C", m, cc));
+      CHK(check_dims(R, "R", r, n));
+      a.C = view_of(*C);
+      a.R = view_of(*R);
+    }
+    CHK(check_dims(B, "B", m, n));
+    a.B = view_of(*B);
+  }
+  a.U = view_of(*U);
+  a.hasB = B != nullptr;
+  a.core = core;
+  a.compute = compute;
+  a.refine = core == QCUR_CORE_CAR ? refine_steps : 0;
+  a.rtol = rtol;
+  a.max_rank = max_rank;
+  a.rank_out = rank_out;
+  {
+    Bump sz(nullptr);
+    Ctx dummy{0, nullptr, nullptr};
+    approx_run(dummy, a, m, n, cc, r, sz, true);
+    const size_t need = sz.used + 256;
+    if (!ws || ws_bytes < need) return fail(QCUR_ERR_WORKSPACE, "approx needs %zu workspace bytes", need);
+  }
+  CHK(check_handle(h));
+  Bump b(ws);
+  return approx_run(h->c, a, m, n, cc, r, b, false);
+}
+
+// ---- residual
+qcur_status qcur_residual(qcur_handle h, const qcur_qmat* A, const qcur_qmat* C, const qcur_qmat* U,
+                          const qcur_qmat* R, const uint8_t* mask, int64_t mask_ld, int compute, double* fro,
+                          qcur_qmat* E, double e_scale, void* ws, size_t ws_bytes) {
+  CHK(check_qmat(A, "A"));
+  CHK(check_qmat(C, "C"));
+  CHK(check_qmat(U, "U"));
+  CHK(check_qmat(R, "R"));
+  if (!valid_dtype(compute)) return fail(QCUR_ERR_DTYPE, "unknown compute dtype");
+  const int64_t m = A->rows, n = A->cols, cc = C->cols, r = R->rows;
+  CHK(check_dims(C, "C", m, cc));
+  CHK(check_dims(U, "U", cc, r));
+  CHK(check_dims(R, "R", r, n));
+  if (mask && mask_ld < n) return fail(QCUR_ERR_SHAPE, "mask_ld < n");
+  if (!fro) return fail(QCUR_ERR_ARG, "fro must not be NULL");
+  if (E) {
+    CHK(check_qmat(E, "E"));
+    CHK(check_dims(E, "E", m, n));
+    if (E->dtype != acc_dt(compute)) return fail(QCUR_ERR_DTYPE, "E must be FP64 (F64 compute) or FP32");
+  }
+  if (!std::isfinite(e_scale)) return fail(QCUR_ERR_ARG, "e_scale must be finite");
+  QView Av = view_of(*A), Cv = view_of(*C), Uv = view_of(*U), Rv = view_of(*R);
+  {
+    Bump sz(nullptr);
+    Ctx dummy{0, nullptr, nullptr};
+    residual_run(dummy, Av, Cv, Uv, Rv, mask, mask_ld, compute, nullptr, 1, nullptr, 0.0, sz, true);
+    const size_t need = sz.used + 256;
+    if (!ws || ws_bytes < need) return fail(QCUR_ERR_WORKSPACE, "residual needs %zu workspace bytes", need);
+  }
+  CHK(check_handle(h));
+  Bump b(ws);
+  QView Ev;
+  if (E) Ev = view_of(*E);
+  return residual_run(h->c, Av, Cv, Uv, Rv, mask, mask_ld, compute, fro, 1, E ? &Ev : nullptr, e_scale, b, false);
+}
+
+// ---- backward
+qcur_status qcur_backward(qcur_handle h, const qcur_qmat* A, const int64_t* I, int64_t r, const int64_t* J, int64_t c,
+                          const qcur_qmat* gB, const uint8_t* mask, int64_t mask_ld, double rtol, int64_t max_rank,
+                          int compute, qcur_qmat* dA, double* loss, void* ws, size_t ws_bytes) {
+  CHK(check_qmat(A, "A"));
+  CHK(check_qmat(dA, "dA"));
+  if (compute != QCUR_F64 && compute != QCUR_F32) return fail(QCUR_ERR_DTYPE, "backward computes in FP64 or FP32");
+  if (A->dtype != compute || dA->dtype != compute) return fail(QCUR_ERR_DTYPE, "A and dA must be in the compute dtype");
+  const int64_t m = A->rows, n = A->cols;
+  CHK(check_dims(dA, "dA", m, n));
+  if (r < 1 || c < 1 || r > m || c > n) return fail(QCUR_ERR_ARG, "index counts out of range");
+  if (!I || !J) return fail(QCUR_ERR_ARG, "I and J must not be NULL");
+  if (gB) {
+    CHK(check_qmat(gB, "gB"));
+    CHK(check_dims(gB, "gB", m, n));
+    if (gB->dtype != compute) return fail(QCUR_ERR_DTYPE, "gB must be in the compute dtype");
+  }
+  if (mask && mask_ld < n) return fail(QCUR_ERR_SHAPE, "mask_ld < n");
+  if (!std::isfinite(rtol)) return fail(QCUR_ERR_ARG, "rtol must be finite");
+  if (max_rank < 0) return fail(QCUR_ERR_ARG, "max_rank must be >= 0");
+  const size_t need = qcur_backward_workspace(m, n, c, r, compute);
+  if (!ws || ws_bytes < need) return fail(QCUR_ERR_WORKSPACE, "backward needs %zu workspace bytes", need);
+  CHK(check_handle(h));
+  BwdArgs a{};
+  a.A = view_of(*A);
+  a.dA = view_of(*dA);
+  a.hasgB = gB != nullptr;
+  if (gB) a.gB = view_of(*gB);
+  a.I = I;
+  a.J = J;
+  a.r = r;
+  a.cc = c;
+  a.mask = mask;
+  a.mask_ld = mask_ld;
+  a.rtol = rtol;
+  a.max_rank = max_rank;
+  a.compute = compute;
+  a.loss = loss;
+  Bump b(ws);
+  return backward_run(h->c, a, b, false);
+}
+
+qcur_status qcur_cast(qcur_handle h, const qcur_qmat* X, qcur_qmat* Y) {
+  CHK(check_qmat(X, "X"));
+  CHK(check_qmat(Y, "Y"));
+  CHK(check_dims(Y, "Y", X->rows, X->cols));
+  CHK(check_handle(h));
+  HIPCHK(launch_cast(h->c, view_of(*X), view_of(*Y), CAST_COPY));
+  return QCUR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,206 @@
+// Index sampler for Algorithm 1, steps 1-2 (drawing J from {p_j} and I from
+// {q_i}).  The paper does not say how indices are drawn; this library uses an
+// integer-CDF sampler so that draws are exact and reproducible:
+//   w_j = floor(p_j * 2^60)                    (exact in FP64 for p_j in [0,1])
+//   u_t = SplitMix64 output number set_id*2^32 + t, state started at `seed`
+//   tau = floor(u_t * T / 2^64), T = current weight total
+//   j   = smallest index whose inclusive prefix sum exceeds tau
+//   without replacement, w_j is then removed from T.
+// One workgroup per draw.  Weights live in LDS; the search descends a
+// 64-ary tree (superblocks of 4096, blocks of 64 elements) with one
+// wave-wide prefix scan per level, so each draw costs three scans.
+#include "qcur_internal.hpp"
+
+namespace qcur {
+
+static constexpr uint64_t TAKEN = 1ull << 63;
+static constexpr int DRAW_THREADS = 256;
+static constexpr int64_t DRAW_MAX_N_NOREPL = 16384;
+static constexpr int64_t DRAW_MAX_N_REPL = 8192;
+
+__device__ inline uint64_t splitmix64_nth(uint64_t seed, uint64_t n) {
+  // state after n+1 steps of adding the golden gamma, then the output mix
+  uint64_t z = seed + (n + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Wave-wide sum of nonnegative 64-bit integers with overflow detection.
+__device__ inline uint64_t wave_sum_u64(uint64_t v, bool& ovf) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    uint64_t w = __shfl_xor(v, o, 64);
+    uint64_t s = v + w;
+    ovf |= (s < v);
+    v = s;
+  }
+  return v;
+}
+
+// Returns the first lane whose inclusive prefix of v exceeds tau and lowers
+// tau by the exclusive prefix of that lane.
+__device__ inline int select_lane(uint64_t v, uint64_t& tau, int lane) {
+  uint64_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint64_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  unsigned long long mask = __ballot(x > tau);
+  // the level sums are kept consistent, so some lane always qualifies; lane 0
+  // is a defensive fallback that keeps every index in range
+  int k = mask ? __ffsll((unsigned long long)mask) - 1 : 0;
+  uint64_t incl = __shfl(x, k, 64);
+  uint64_t vk = __shfl(v, k, 64);
+  tau -= incl - vk;
+  return k;
+}
+
+__global__ __launch_bounds__(DRAW_THREADS) void k_draw(const double* __restrict__ probs, int64_t n, int64_t count,
+                                                       uint64_t seed, uint64_t set_id, int repl,
+                                                       int64_t* __restrict__ idx, unsigned* status) {
+  extern __shared__ uint64_t lds[];
+  const int64_t npad = (n + 63) / 64 * 64;
+  const int64_t nb = npad / 64;
+  const int64_t nsb = (nb + 63) / 64;
+  uint64_t* wl = lds;              // npad weights (bit 63: taken)
+  uint64_t* L1 = wl + npad;        // nb block sums
+  uint64_t* L2 = L1 + nb;          // nsb superblock sums
+  uint32_t* cnt = (uint32_t*)(L2 + 64);  // npad pick counts (with replacement)
+  __shared__ int bad;
+  __shared__ uint64_t total;
+  __shared__ int64_t npos;
+  __shared__ int64_t chunk_off[DRAW_THREADS];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  if (tid == 0) {
+    bad = 0;
+    npos = 0;
+  }
+  __syncthreads();
+
+  // weights, block sums, positive count
+  for (int64_t b = wave; b < nb; b += DRAW_THREADS / 64) {
+    const int64_t e = b * 64 + lane;
+    uint64_t w = 0;
+    bool inv = false;
+    if (e < n) {
+      const double p = probs[e];
+      inv = !(p >= 0.0 && p <= 1.0);
+      w = inv ? 0ull : (uint64_t)(p * 0x1p60);
+    }
+    wl[e] = w;
+    if (repl) cnt[e] = 0u;
+    bool ovf = false;
+    uint64_t s = wave_sum_u64(w, ovf);
+    unsigned long long posm = __ballot(w > 0);
+    unsigned long long invm = __ballot(inv);
+    if (lane == 0) {
+      L1[b] = s;
+      if (ovf || invm) atomicOr(&bad, 1);
+      atomicAdd((unsigned long long*)&npos, (unsigned long long)__popcll(posm));
+    }
+  }
+  __syncthreads();
+  for (int64_t sb = wave; sb < nsb; sb += DRAW_THREADS / 64) {
+    const int64_t b = sb * 64 + lane;
+    uint64_t v = b < nb ? L1[b] : 0ull;
+    bool ovf = false;
+    uint64_t s = wave_sum_u64(v, ovf);
+    if (lane == 0) {
+      L2[sb] = s;
+      if (ovf) atomicOr(&bad, 1);
+    }
+  }
+  __syncthreads();
+  if (wave == 0) {
+    uint64_t v = lane < nsb ? L2[lane] : 0ull;
+    bool ovf = false;
+    uint64_t s = wave_sum_u64(v, ovf);
+    if (lane == 0) {
+      total = s;
+      if (ovf || s == 0ull || (!repl && npos < count)) atomicOr(&bad, 1);
+    }
+  }
+  __syncthreads();
+  if (bad) {
+    for (int64_t t = tid; t < count; t += DRAW_THREADS) idx[t] = -1;
+    if (tid == 0) atomicOr(status, ST_SAMPLE);
+    return;
+  }
+
+  // the draws, one wave
+  if (wave == 0) {
+    volatile uint64_t* vwl = wl;
+    volatile uint64_t* vL1 = L1;
+    volatile uint64_t* vL2 = L2;
+    volatile uint32_t* vcnt = cnt;
+    uint64_t T = total;
+    const uint64_t base = (set_id & 0xFFFFFFFFull) << 32;
+    for (int64_t t = 0; t < count; ++t) {
+      const uint64_t u = splitmix64_nth(seed, base + (uint64_t)t);
+      uint64_t tau = __umul64hi(u, T);
+      uint64_t v = lane < nsb ? vL2[lane] : 0ull;
+      const int sb = select_lane(v, tau, lane);
+      const int64_t b0 = (int64_t)sb * 64;
+      v = (b0 + lane < nb) ? vL1[b0 + lane] : 0ull;
+      const int64_t b = b0 + select_lane(v, tau, lane);
+      const uint64_t raw = vwl[b * 64 + lane];
+      v = (raw & TAKEN) ? 0ull : raw;
+      const int64_t j = b * 64 + select_lane(v, tau, lane);
+      if (lane == 0) {
+        if (repl) {
+          vcnt[j] = vcnt[j] + 1u;
+        } else {
+          const uint64_t w = vwl[j];
+          vwl[j] = w | TAKEN;
+          vL1[b] = vL1[b] - w;
+          vL2[sb] = vL2[sb] - w;
+        }
+      }
+      if (!repl) T -= __shfl(v, (int)(j - b * 64), 64);
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  __syncthreads();
+
+  // sorted output: compaction of picked elements in index order
+  const int64_t per = (npad + DRAW_THREADS - 1) / DRAW_THREADS;
+  const int64_t e0 = min(npad, tid * per), e1 = min(npad, e0 + per);
+  int64_t mine = 0;
+  for (int64_t e = e0; e < e1; ++e) mine += repl ? (int64_t)cnt[e] : (int64_t)((wl[e] & TAKEN) != 0);
+  chunk_off[tid] = mine;
+  __syncthreads();
+  if (tid == 0) {
+    int64_t run = 0;
+    for (int k = 0; k < DRAW_THREADS; ++k) {
+      int64_t x = chunk_off[k];
+      chunk_off[k] = run;
+      run += x;
+    }
+  }
+  __syncthreads();
+  int64_t o = chunk_off[tid];
+  for (int64_t e = e0; e < e1; ++e) {
+    int64_t k = repl ? (int64_t)cnt[e] : (int64_t)((wl[e] & TAKEN) != 0);
+    for (int64_t r = 0; r < k && o < count; ++r) idx[o++] = e;
+  }
+}
+
+hipError_t launch_draw(const Ctx& c, const double* probs, int64_t n, int64_t count, uint64_t seed,
+                       uint64_t set_id, int with_replacement, int64_t* idx) {
+  const int64_t npad = (n + 63) / 64 * 64;
+  const int64_t nb = npad / 64;
+  size_t lds = (size_t)(npad + nb + 64) * 8;
+  if (with_replacement) lds += (size_t)npad * 4;
+  hipError_t e = hipFuncSetAttribute((const void*)k_draw, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)(140 * 1024));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_draw, dim3(1), dim3(DRAW_THREADS), lds, c.stream, probs, n, count, seed, set_id,
+                     with_replacement, idx, c.status);
+  return hipGetLastError();
+}
+
+}  // namespace qcur

@@ -1,0 +1,460 @@
+// Bandwidth-bound kernels of the QMCUR path: length probabilities (Section
+// 3.1), gathers of C = A(:,J), R = A(I,:), W = A(I,J) (Algorithm 1 steps 1-2),
+// dtype casts and small helpers.  All reductions run in FP64 in a fixed
+// order so results do not depend on scheduling.
+#include <algorithm>
+
+#include "qcur_internal.hpp"
+
+namespace qcur {
+
+template <typename T> __device__ inline double to_d(T v);
+template <> __device__ inline double to_d<double>(double v) { return v; }
+template <> __device__ inline double to_d<float>(float v) { return (double)v; }
+template <> __device__ inline double to_d<uint16_t>(uint16_t v) { return (double)bf16_to_f32(v); }
+
+template <typename T> __device__ inline T from_d(double v);
+template <> __device__ inline double from_d<double>(double v) { return v; }
+template <> __device__ inline float from_d<float>(double v) { return (float)v; }
+template <> __device__ inline uint16_t from_d<uint16_t>(double v) { return f32_to_bf16((float)v); }
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// probs, pass 1: tile (rb rows) x (256 columns).  Thread t owns column
+// j = 256*bx + t and sums |a_ij|^2 over the tile's rows into colpart[by][j];
+// each row of the tile is reduced across the 256 columns (wave sums, then the
+// four wave results in order) into rowpart[bx][i].
+template <typename T>
+__global__ __launch_bounds__(256) void k_probs_partials(const T* __restrict__ A, int64_t m, int64_t n,
+                                                        int64_t ld, int64_t ps, int rb,
+                                                        double* __restrict__ colpart,
+                                                        double* __restrict__ rowpart) {
+  __shared__ double wsum[4][64];
+  const int t = threadIdx.x;
+  const int64_t j = (int64_t)blockIdx.x * 256 + t;
+  const int64_t i0 = (int64_t)blockIdx.y * rb;
+  const int64_t i1 = min(m, i0 + rb);
+  double cacc = 0.0;
+  for (int64_t i = i0; i < i1; ++i) {
+    double s = 0.0;
+    if (j < n) {
+      const int64_t off = i * ld + j;
+      double a0 = to_d<T>(A[off]), a1 = to_d<T>(A[off + ps]);
+      double a2 = to_d<T>(A[off + 2 * ps]), a3 = to_d<T>(A[off + 3 * ps]);
+      s = a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3;
+    }
+    cacc += s;
+    double w = wave_sum(s);
+    if ((t & 63) == 0) wsum[t >> 6][(i - i0) & 63] = w;
+    if (((i - i0) & 63) == 63 || i == i1 - 1) {
+      __syncthreads();
+      const int64_t base = i - ((i - i0) & 63);
+      for (int64_t k = t; k <= (i - base); k += 256) {
+        double r = ((wsum[0][k] + wsum[1][k]) + wsum[2][k]) + wsum[3][k];
+        rowpart[(int64_t)blockIdx.x * m + base + k] = r;
+      }
+      __syncthreads();
+    }
+  }
+  if (j < n) colpart[(int64_t)blockIdx.y * n + j] = cacc;
+}
+
+void probs_grid(int64_t m, int64_t n, int* rb, int* nrb, int* ncb) {
+  int64_t cb = (n + 255) / 256;
+  int r = 64;
+  while (r > 4 && ((m + r - 1) / r) * cb < 1024) r >>= 1;
+  *rb = r;
+  *nrb = (int)((m + r - 1) / r);
+  *ncb = (int)cb;
+}
+
+hipError_t launch_probs_partials(const Ctx& c, QView A, double* colpart, double* rowpart, int rb, int ncb) {
+  int nrb = (int)((A.rows + rb - 1) / rb);
+  dim3 grid(ncb, nrb);
+  switch (A.dt) {
+    case QCUR_F64:
+      hipLaunchKernelGGL(k_probs_partials<double>, grid, dim3(256), 0, c.stream, (const double*)A.p,
+                         A.rows, A.cols, A.ld, A.ps, rb, colpart, rowpart);
+      break;
+    case QCUR_F32:
+      hipLaunchKernelGGL(k_probs_partials<float>, grid, dim3(256), 0, c.stream, (const float*)A.p,
+                         A.rows, A.cols, A.ld, A.ps, rb, colpart, rowpart);
+      break;
+    default:
+      hipLaunchKernelGGL(k_probs_partials<uint16_t>, grid, dim3(256), 0, c.stream,
+                         (const uint16_t*)A.p, A.rows, A.cols, A.ld, A.ps, rb, colpart, rowpart);
+  }
+  return hipGetLastError();
+}
+
+// probs, pass 2: col2[j] = sum over row tiles, row2[i] = sum over column tiles
+// (fixed order), written into p and q.
+__global__ void k_probs_fold(int64_t m, int64_t n, const double* __restrict__ colpart,
+                             const double* __restrict__ rowpart, int nrb, int ncb, double* p,
+                             double* q) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) {
+    double s = 0.0;
+    for (int r = 0; r < nrb; ++r) s += colpart[(int64_t)r * n + t];
+    p[t] = s;
+  } else if (t < n + m) {
+    int64_t i = t - n;
+    double s = 0.0;
+    for (int b = 0; b < ncb; ++b) s += rowpart[(int64_t)b * m + i];
+    q[i] = s;
+  }
+}
+
+// probs, pass 3 (one workgroup): fro2 = sum of row sums by a fixed tree, then
+// normalise (length) or fill 1/n, 1/m (uniform).
+__global__ __launch_bounds__(1024) void k_probs_norm(int64_t m, int64_t n, int sampling, int have_sums,
+                                                     double* p, double* q, double* fro2,
+                                                     unsigned* status) {
+  __shared__ double red[1024];
+  __shared__ double total;
+  const int t = threadIdx.x;
+  if (have_sums) {
+    double s = 0.0;
+    for (int64_t i = t; i < m; i += 1024) s += q[i];
+    red[t] = s;
+    __syncthreads();
+    for (int w = 512; w >= 1; w >>= 1) {
+      if (t < w) red[t] += red[t + w];
+      __syncthreads();
+    }
+    if (t == 0) {
+      total = red[0];
+      if (fro2) fro2[0] = red[0];
+      if (sampling == QCUR_LENGTH && status && !(red[0] > 0.0 && red[0] < INFINITY)) atomicOr(status, ST_NUMERIC);
+    }
+    __syncthreads();
+  }
+  if (sampling == QCUR_LENGTH) {
+    const double f = total;
+    for (int64_t j = t; j < n; j += 1024) p[j] = p[j] / f;
+    for (int64_t i = t; i < m; i += 1024) q[i] = q[i] / f;
+  } else {
+    const double pn = 1.0 / (double)n, qm = 1.0 / (double)m;
+    for (int64_t j = t; j < n; j += 1024) p[j] = pn;
+    for (int64_t i = t; i < m; i += 1024) q[i] = qm;
+  }
+}
+
+hipError_t launch_probs_finish(const Ctx& c, int64_t m, int64_t n, const double* colpart,
+                               const double* rowpart, int nrb, int ncb, int sampling, double* p,
+                               double* q, double* fro2, double* scratch) {
+  const int have = colpart != nullptr;
+  double* pp = p;
+  double* qq = q;
+  if (have && sampling == QCUR_UNIFORM) {  // sums only feed fro2
+    pp = scratch;
+    qq = scratch + n;
+  }
+  if (have) {
+    int64_t tot = m + n;
+    hipLaunchKernelGGL(k_probs_fold, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c.stream, m, n,
+                       colpart, rowpart, nrb, ncb, pp, qq);
+    if (sampling == QCUR_UNIFORM) {
+      hipLaunchKernelGGL(k_probs_norm, dim3(1), dim3(1024), 0, c.stream, m, n, (int)QCUR_LENGTH, 1, pp,
+                         qq, fro2, (unsigned*)nullptr);
+    }
+  }
+  if (sampling == QCUR_LENGTH) {
+    hipLaunchKernelGGL(k_probs_norm, dim3(1), dim3(1024), 0, c.stream, m, n, sampling, 1, p, q, fro2,
+                       c.status);
+  } else {
+    hipLaunchKernelGGL(k_probs_norm, dim3(1), dim3(1024), 0, c.stream, m, n, sampling, 0, p, q,
+                       (double*)nullptr, c.status);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Gather out[c][s][t] = A[c][rows(s)][cols(t)] where rows/cols are the index
+// lists or the identity.  One thread per output element and plane group.
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_gather(const TI* __restrict__ A, int64_t am, int64_t an, int64_t ald,
+                                                int64_t aps, const int64_t* __restrict__ ridx,
+                                                const int64_t* __restrict__ cidx, TO* __restrict__ O,
+                                                int64_t om, int64_t on, int64_t old, int64_t ops,
+                                                unsigned* status) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  for (int64_t s = blockIdx.y; s < om; s += gridDim.y) {
+  if (t >= on || s >= om) continue;
+  int64_t i = ridx ? ridx[s] : s;
+  int64_t j = cidx ? cidx[t] : t;
+  const bool ok = i >= 0 && i < am && j >= 0 && j < an;
+  if (!ok) atomicOr(status, ST_ARG);
+  const int64_t src = i * ald + j;
+  const int64_t dst = s * old + t;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) O[dst + c * ops] = ok ? from_d<TO>(to_d<TI>(A[src + c * aps])) : from_d<TO>(0.0);
+  }
+}
+
+template <typename TI>
+static void gather_dispatch_out(const Ctx& c, QView A, const int64_t* ri, const int64_t* ci, QView O) {
+  dim3 grid((unsigned)((O.cols + 255) / 256), (unsigned)std::min<int64_t>(O.rows, 65535));
+  switch (O.dt) {
+    case QCUR_F64:
+      hipLaunchKernelGGL((k_gather<TI, double>), grid, dim3(256), 0, c.stream, (const TI*)A.p, A.rows,
+                         A.cols, A.ld, A.ps, ri, ci, (double*)O.p, O.rows, O.cols, O.ld, O.ps, c.status);
+      break;
+    case QCUR_F32:
+      hipLaunchKernelGGL((k_gather<TI, float>), grid, dim3(256), 0, c.stream, (const TI*)A.p, A.rows,
+                         A.cols, A.ld, A.ps, ri, ci, (float*)O.p, O.rows, O.cols, O.ld, O.ps, c.status);
+      break;
+    default:
+      hipLaunchKernelGGL((k_gather<TI, uint16_t>), grid, dim3(256), 0, c.stream, (const TI*)A.p, A.rows,
+                         A.cols, A.ld, A.ps, ri, ci, (uint16_t*)O.p, O.rows, O.cols, O.ld, O.ps,
+                         c.status);
+  }
+}
+
+static void gather_one(const Ctx& c, QView A, const int64_t* ri, const int64_t* ci, QView O) {
+  if (O.rows == 0 || O.cols == 0) return;
+  switch (A.dt) {
+    case QCUR_F64: gather_dispatch_out<double>(c, A, ri, ci, O); break;
+    case QCUR_F32: gather_dispatch_out<float>(c, A, ri, ci, O); break;
+    default: gather_dispatch_out<uint16_t>(c, A, ri, ci, O);
+  }
+}
+
+hipError_t launch_gather(const Ctx& c, QView A, const int64_t* I, int64_t r, const int64_t* J, int64_t cc,
+                         const QView* C, const QView* R, const QView* W) {
+  if (C) gather_one(c, A, nullptr, J, *C);
+  if (R) gather_one(c, A, I, nullptr, *R);
+  if (W) gather_one(c, A, I, J, *W);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Cast Y = X with optional transpose (mode bit 1) and entrywise quaternion
+// conjugation (mode bit 2): Y[c][j][i] (transposed) or Y[c][i][j] receives
+// sign_c X[c][i][j] with sign_c = -1 for c > 0 when conjugating.
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_cast(const TI* __restrict__ X, int64_t rows, int64_t cols, int64_t xld,
+                                              int64_t xps, TO* __restrict__ Y, int64_t yld, int64_t yps,
+                                              int mode) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  for (int64_t i = blockIdx.y; i < rows; i += gridDim.y) {
+  if (j >= cols) continue;
+  const int64_t src = i * xld + j;
+  const int64_t dst = (mode & 1) ? (j * yld + i) : (i * yld + j);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double v = to_d<TI>(X[src + c * xps]);
+    if ((mode & 2) && c > 0) v = -v;
+    Y[dst + c * yps] = from_d<TO>(v);
+  }
+  }
+}
+
+template <typename TI>
+static void cast_out(const Ctx& c, QView X, QView Y, int mode) {
+  dim3 grid((unsigned)((X.cols + 255) / 256), (unsigned)std::min<int64_t>(X.rows, 65535));
+  switch (Y.dt) {
+    case QCUR_F64:
+      hipLaunchKernelGGL((k_cast<TI, double>), grid, dim3(256), 0, c.stream, (const TI*)X.p, X.rows, X.cols,
+                         X.ld, X.ps, (double*)Y.p, Y.ld, Y.ps, mode);
+      break;
+    case QCUR_F32:
+      hipLaunchKernelGGL((k_cast<TI, float>), grid, dim3(256), 0, c.stream, (const TI*)X.p, X.rows, X.cols,
+                         X.ld, X.ps, (float*)Y.p, Y.ld, Y.ps, mode);
+      break;
+    default:
+      hipLaunchKernelGGL((k_cast<TI, uint16_t>), grid, dim3(256), 0, c.stream, (const TI*)X.p, X.rows,
+                         X.cols, X.ld, X.ps, (uint16_t*)Y.p, Y.ld, Y.ps, mode);
+  }
+}
+
+hipError_t launch_cast(const Ctx& c, QView X, QView Y, int mode) {
+  if (X.rows == 0 || X.cols == 0) return hipSuccess;
+  switch (X.dt) {
+    case QCUR_F64: cast_out<double>(c, X, Y, mode); break;
+    case QCUR_F32: cast_out<float>(c, X, Y, mode); break;
+    default: cast_out<uint16_t>(c, X, Y, mode);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+__global__ void k_check_finite(const void* X, int dt, int64_t rows, int64_t cols, int64_t ld, int64_t ps,
+                               unsigned* status) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  for (int64_t i = blockIdx.y; i < rows; i += gridDim.y) {
+  if (j >= cols) continue;
+  bool bad = false;
+  for (int c = 0; c < 4; ++c) {
+    double v = load_as_double(X, dt, i * ld + j + c * ps);
+    bad |= !(v - v == 0.0);
+  }
+  if (bad) atomicOr(status, ST_NUMERIC);
+  }
+}
+
+hipError_t launch_check_finite(const Ctx& c, QView X) {
+  if (X.rows == 0 || X.cols == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_check_finite, dim3((unsigned)((X.cols + 255) / 256), (unsigned)std::min<int64_t>(X.rows, 65535)), dim3(256), 0,
+                     c.stream, (const void*)X.p, X.dt, X.rows, X.cols, X.ld, X.ps, c.status);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_identity(double* V, int64_t q) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t tot = q * q;
+  if (t >= tot) return;
+  const int64_t i = t / q, j = t % q;
+  V[t] = (i == j) ? 1.0 : 0.0;
+  V[t + tot] = 0.0;
+  V[t + 2 * tot] = 0.0;
+  V[t + 3 * tot] = 0.0;
+}
+
+hipError_t launch_fill_identity(const Ctx& c, double* V, int64_t q) {
+  if (q == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_identity, dim3((unsigned)((q * q + 255) / 256)), dim3(256), 0, c.stream, V, q);
+  return hipGetLastError();
+}
+
+// Y = alpha X + beta Y, elementwise over four planes (any dtypes).
+__global__ void k_axpby(double alpha, const void* X, int xdt, int64_t xld, int64_t xps, double beta, void* Y,
+                        int ydt, int64_t yld, int64_t yps, int64_t rows, int64_t cols) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  for (int64_t i = blockIdx.y; i < rows; i += gridDim.y) {
+  if (j >= cols) continue;
+  for (int c = 0; c < 4; ++c) {
+    const int64_t yo = i * yld + j + c * yps;
+    double y = beta == 0.0 ? 0.0 : beta * load_as_double(Y, ydt, yo);
+    store_from_double(Y, ydt, yo, alpha * load_as_double(X, xdt, i * xld + j + c * xps) + y);
+  }
+  }
+}
+
+hipError_t launch_axpby(const Ctx& c, double alpha, QView X, double beta, QView Y) {
+  if (Y.rows == 0 || Y.cols == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axpby, dim3((unsigned)((Y.cols + 255) / 256), (unsigned)std::min<int64_t>(Y.rows, 65535)), dim3(256), 0, c.stream,
+                     alpha, (const void*)X.p, X.dt, X.ld, X.ps, beta, Y.p, Y.dt, Y.ld, Y.ps, Y.rows, Y.cols);
+  return hipGetLastError();
+}
+
+// X = I - X for a square matrix.
+__global__ void k_identity_minus(void* X, int dt, int64_t n, int64_t ld, int64_t ps) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  for (int64_t i = blockIdx.y; i < n; i += gridDim.y) {
+  if (j >= n) continue;
+  for (int c = 0; c < 4; ++c) {
+    const int64_t o = i * ld + j + c * ps;
+    double v = -load_as_double(X, dt, o);
+    if (c == 0 && i == j) v += 1.0;
+    store_from_double(X, dt, o, v);
+  }
+  }
+}
+
+hipError_t launch_identity_minus(const Ctx& c, QView X) {
+  if (X.rows == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_identity_minus, dim3((unsigned)((X.cols + 255) / 256), (unsigned)std::min<int64_t>(X.rows, 65535)), dim3(256), 0,
+                     c.stream, X.p, X.dt, X.rows, X.ld, X.ps);
+  return hipGetLastError();
+}
+
+// Fixed-order sum of `count` doubles by one workgroup.
+__global__ __launch_bounds__(1024) void k_sum_partials(const double* __restrict__ part, int64_t count,
+                                                       double* out, int take_sqrt) {
+  __shared__ double red[1024];
+  const int t = threadIdx.x;
+  double s = 0.0;
+  for (int64_t i = t; i < count; i += 1024) s += part[i];
+  red[t] = s;
+  __syncthreads();
+  for (int w = 512; w >= 1; w >>= 1) {
+    if (t < w) red[t] += red[t + w];
+    __syncthreads();
+  }
+  if (t == 0) out[0] = take_sqrt ? sqrt(red[0]) : red[0];
+}
+
+hipError_t launch_sum_partials(const Ctx& c, const double* partials, int64_t count, double* out, int take_sqrt) {
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, c.stream, partials, count, out, take_sqrt);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Inverse index map: inv[idx[s]] = s, -1 elsewhere; repeated or out-of-range
+// indices raise ST_ARG.
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t < n) p[t] = v;
+}
+__global__ void k_inverse_map(const int64_t* idx, int64_t cnt, int64_t n, int32_t* inv, unsigned* status) {
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= cnt) return;
+  const int64_t i = idx[s];
+  if (i < 0 || i >= n) {
+    atomicOr(status, ST_ARG);
+    return;
+  }
+  if (atomicCAS(&inv[i], -1, (int32_t)s) != -1) atomicOr(status, ST_ARG);
+}
+
+hipError_t launch_inverse_map(const Ctx& c, const int64_t* idx, int64_t cnt, int64_t n, int32_t* inv) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, inv, n, -1);
+  if (cnt > 0)
+    hipLaunchKernelGGL(k_inverse_map, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, c.stream, idx, cnt, n,
+                       inv, c.status);
+  return hipGetLastError();
+}
+
+// dA[i][j] = G[i][j] + gC[i][jinv[j]] + gR[iinv[i]][j] + gW[iinv[i]][jinv[j]]
+// (terms present only where the row/column was sampled).  No atomics.
+template <typename TO>
+__global__ __launch_bounds__(256) void k_backward_assemble(TO* __restrict__ dA, int64_t m, int64_t n, int64_t ld,
+                                                           int64_t ps, const void* G, int gdt, int64_t gld,
+                                                           int64_t gps, int has_G, const void* gC, int cdt,
+                                                           int64_t cld, int64_t cps, const void* gR, int rdt,
+                                                           int64_t rld, int64_t rps, const void* gW, int wdt,
+                                                           int64_t wld, int64_t wps,
+                                                           const int32_t* __restrict__ iinv,
+                                                           const int32_t* __restrict__ jinv) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  for (int64_t i = blockIdx.y; i < m; i += gridDim.y) {
+  if (j >= n) continue;
+  const int32_t s = iinv[i];
+  const int32_t t = jinv[j];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double v = has_G ? load_as_double(G, gdt, i * gld + j + c * gps) : 0.0;
+    if (t >= 0) v += load_as_double(gC, cdt, i * cld + t + c * cps);
+    if (s >= 0) v += load_as_double(gR, rdt, (int64_t)s * rld + j + c * rps);
+    if (s >= 0 && t >= 0) v += load_as_double(gW, wdt, (int64_t)s * wld + t + c * wps);
+    dA[i * ld + j + c * ps] = from_d<TO>(v);
+  }
+  }
+}
+
+hipError_t launch_backward_assemble(const Ctx& c, QView dA, QView G, int has_G, QView gC, QView gR, QView gW,
+                                    const int32_t* iinv, const int32_t* jinv) {
+  if (dA.rows == 0 || dA.cols == 0) return hipSuccess;
+  dim3 grid((unsigned)((dA.cols + 255) / 256), (unsigned)std::min<int64_t>(dA.rows, 65535));
+  if (dA.dt == QCUR_F64) {
+    hipLaunchKernelGGL(k_backward_assemble<double>, grid, dim3(256), 0, c.stream, (double*)dA.p, dA.rows, dA.cols,
+                       dA.ld, dA.ps, (const void*)G.p, G.dt, G.ld, G.ps, has_G, (const void*)gC.p, gC.dt, gC.ld,
+                       gC.ps, (const void*)gR.p, gR.dt, gR.ld, gR.ps, (const void*)gW.p, gW.dt, gW.ld, gW.ps,
+                       iinv, jinv);
+  } else {
+    hipLaunchKernelGGL(k_backward_assemble<float>, grid, dim3(256), 0, c.stream, (float*)dA.p, dA.rows, dA.cols,
+                       dA.ld, dA.ps, (const void*)G.p, G.dt, G.ld, G.ps, has_G, (const void*)gC.p, gC.dt, gC.ld,
+                       gC.ps, (const void*)gR.p, gR.dt, gR.ld, gR.ps, (const void*)gW.p, gW.dt, gW.ld, gW.ps,
+                       iinv, jinv);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace qcur

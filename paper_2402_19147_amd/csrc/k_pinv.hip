@@ -1,0 +1,303 @@
+// Moore-Penrose inverse of a quaternion matrix in FP64 (the (.)^+ of
+// Section 2.1, used for W^+, C^+ and R^+ in Algorithm 1 step 3).
+//
+// Method: one-sided (Hestenes) Jacobi on quaternion columns.  For a tall Z
+// (p x q, p >= q) columns are orthogonalised pairwise by right unitary
+// transformations accumulated in V, so that Y = Z V has orthogonal columns
+// and sigma_i = ||Y_i||.  For a column pair (a, b) with alpha = a^H a,
+// beta = b^H b and the quaternion gamma = a^H b, the column b is first
+// multiplied on the right by conj(mu), mu = gamma / |gamma|, which makes the
+// pair's inner product the real number |gamma|; an ordinary real Jacobi
+// rotation then zeroes it.  Pairs are visited in round-robin (circle
+// method) order: each round holds q/2 disjoint pairs that run in parallel.
+// Then Z^+ = sum over kept i of V_i Y_i^H / sigma_i^2.
+//
+// Storage: columns are stored contiguously ("column rows"): Yc[a][k] is
+// element k of column a, Vc[a][k] element k of column a of V.
+#include "qcur_internal.hpp"
+
+namespace qcur {
+
+__device__ inline void pair_of(int round, int k, int qpad, int& a, int& b) {
+  const int m = qpad - 1;
+  if (k == 0) {
+    a = m;
+    b = round;
+  } else {
+    a = (round + k) % m;
+    b = (round - k + m) % m;
+  }
+}
+
+struct Rot {
+  bool rotate;
+  double c, s;
+  double w0, w1, w2, w3;  // conj(mu)
+};
+
+__device__ inline Rot make_rot(double alpha, double beta, double g0, double g1, double g2, double g3, double tol) {
+  Rot r;
+  const double gn = sqrt(g0 * g0 + g1 * g1 + g2 * g2 + g3 * g3);
+  r.rotate = (alpha > 0.0 && beta > 0.0 && gn > tol * sqrt(alpha) * sqrt(beta));
+  r.c = 1.0;
+  r.s = 0.0;
+  r.w0 = 1.0;
+  r.w1 = r.w2 = r.w3 = 0.0;
+  if (!r.rotate) return r;
+  r.w0 = g0 / gn;
+  r.w1 = -g1 / gn;
+  r.w2 = -g2 / gn;
+  r.w3 = -g3 / gn;
+  const double zeta = (beta - alpha) / (2.0 * gn);
+  double t;
+  if (fabs(zeta) > 1e150) {
+    t = 0.5 / zeta;
+  } else {
+    t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  }
+  r.c = 1.0 / sqrt(1.0 + t * t);
+  r.s = r.c * t;
+  return r;
+}
+
+// New (a, b) = (c a - s b w, s a + c b w) elementwise, w = conj(mu).
+__device__ inline void apply_rot(const Rot& r, double* pa, double* pb, int64_t ps, int64_t k) {
+  const double a0 = pa[k], a1 = pa[k + ps], a2 = pa[k + 2 * ps], a3 = pa[k + 3 * ps];
+  const double x0 = pb[k], x1 = pb[k + ps], x2 = pb[k + 2 * ps], x3 = pb[k + 3 * ps];
+  // b w (Hamilton product, quaternion on the right)
+  const double b0 = x0 * r.w0 - x1 * r.w1 - x2 * r.w2 - x3 * r.w3;
+  const double b1 = x0 * r.w1 + x1 * r.w0 + x2 * r.w3 - x3 * r.w2;
+  const double b2 = x0 * r.w2 - x1 * r.w3 + x2 * r.w0 + x3 * r.w1;
+  const double b3 = x0 * r.w3 + x1 * r.w2 - x2 * r.w1 + x3 * r.w0;
+  pa[k] = r.c * a0 - r.s * b0;
+  pa[k + ps] = r.c * a1 - r.s * b1;
+  pa[k + 2 * ps] = r.c * a2 - r.s * b2;
+  pa[k + 3 * ps] = r.c * a3 - r.s * b3;
+  pb[k] = r.s * a0 + r.c * b0;
+  pb[k + ps] = r.s * a1 + r.c * b1;
+  pb[k + 2 * ps] = r.s * a2 + r.c * b2;
+  pb[k + 3 * ps] = r.s * a3 + r.c * b3;
+}
+
+// Partial dot products over elements k of columns a and b:
+// alpha += |a|^2, beta += |b|^2, gamma += conj(a) b.
+__device__ inline void acc_dots(const double* pa, const double* pb, int64_t ps, int64_t k, double* d) {
+  const double a0 = pa[k], a1 = pa[k + ps], a2 = pa[k + 2 * ps], a3 = pa[k + 3 * ps];
+  const double b0 = pb[k], b1 = pb[k + ps], b2 = pb[k + 2 * ps], b3 = pb[k + 3 * ps];
+  d[0] += a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3;
+  d[1] += b0 * b0 + b1 * b1 + b2 * b2 + b3 * b3;
+  d[2] += a0 * b0 + a1 * b1 + a2 * b2 + a3 * b3;
+  d[3] += a0 * b1 - a1 * b0 - a2 * b3 + a3 * b2;
+  d[4] += a0 * b2 + a1 * b3 - a2 * b0 - a3 * b1;
+  d[5] += a0 * b3 - a1 * b2 + a2 * b1 - a3 * b0;
+}
+
+__device__ inline double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// One round of the circle schedule: workgroup k rotates pair k.
+__global__ __launch_bounds__(256) void k_jacobi_round(double* __restrict__ Y, int64_t p, int64_t q,
+                                                      double* __restrict__ V, int qpad, int round, double tol,
+                                                      unsigned* rotated) {
+  __shared__ double red[4][6];
+  __shared__ Rot rot;
+  int a, b;
+  pair_of(round, blockIdx.x, qpad, a, b);
+  if (a >= q || b >= q) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t psy = q * p, psv = q * q;
+  double* ya = Y + (int64_t)a * p;
+  double* yb = Y + (int64_t)b * p;
+  double d[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t k = tid; k < p; k += 256) acc_dots(ya, yb, psy, k, d);
+#pragma unroll
+  for (int x = 0; x < 6; ++x) d[x] = wsum(d[x]);
+  if (lane == 0)
+    for (int x = 0; x < 6; ++x) red[wave][x] = d[x];
+  __syncthreads();
+  if (tid == 0) {
+    double s[6];
+    for (int x = 0; x < 6; ++x) s[x] = ((red[0][x] + red[1][x]) + red[2][x]) + red[3][x];
+    rot = make_rot(s[0], s[1], s[2], s[3], s[4], s[5], tol);
+    if (rot.rotate) atomicOr(rotated, 1u);
+  }
+  __syncthreads();
+  const Rot r = rot;
+  if (!r.rotate) return;
+  for (int64_t k = tid; k < p; k += 256) apply_rot(r, ya, yb, psy, k);
+  double* va = V + (int64_t)a * q;
+  double* vb = V + (int64_t)b * q;
+  for (int64_t k = tid; k < q; k += 256) apply_rot(r, va, vb, psv, k);
+}
+
+hipError_t launch_jacobi_round(const Ctx& c, double* Y, int64_t p, int64_t q, double* V, int64_t qpad, int round,
+                               double tol, unsigned* rotated) {
+  hipLaunchKernelGGL(k_jacobi_round, dim3((unsigned)(qpad / 2)), dim3(256), 0, c.stream, Y, p, q, V, (int)qpad,
+                     round, tol, rotated);
+  return hipGetLastError();
+}
+
+// Whole Jacobi SVD in one workgroup (16 waves, one pair per wave at a time);
+// Y and V are staged in LDS when they fit.
+static constexpr size_t SMALL_LDS = 150 * 1024;
+
+bool jacobi_small_fits(int64_t p, int64_t q) {
+  return q <= 128 && (size_t)(q * p + q * q) * 4 * sizeof(double) <= SMALL_LDS;
+}
+
+__global__ __launch_bounds__(1024) void k_jacobi_small(double* __restrict__ Yg, int64_t p, int64_t q,
+                                                       double* __restrict__ Vg, double tol, int max_sweeps,
+                                                       unsigned* rotated) {
+  extern __shared__ double lds[];
+  __shared__ int any;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t psy = q * p, psv = q * q;
+  double* Y = lds;
+  double* V = lds + 4 * psy;
+  for (int64_t e = tid; e < 4 * psy; e += 1024) Y[e] = Yg[e];
+  for (int64_t e = tid; e < 4 * psv; e += 1024) V[e] = Vg[e];
+  const int qpad = (int)((q + 1) / 2 * 2);
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
+    if (tid == 0) any = 0;
+    __syncthreads();
+    for (int round = 0; round < qpad - 1; ++round) {
+      for (int k = wave; k < qpad / 2; k += 16) {
+        int a, b;
+        pair_of(round, k, qpad, a, b);
+        if (a >= q || b >= q) continue;
+        double* ya = Y + (int64_t)a * p;
+        double* yb = Y + (int64_t)b * p;
+        double d[6] = {0, 0, 0, 0, 0, 0};
+        for (int64_t k2 = lane; k2 < p; k2 += 64) acc_dots(ya, yb, psy, k2, d);
+#pragma unroll
+        for (int x = 0; x < 6; ++x) d[x] = wsum(d[x]);
+        const Rot r = make_rot(d[0], d[1], d[2], d[3], d[4], d[5], tol);
+        if (!r.rotate) continue;
+        if (lane == 0) any = 1;
+        for (int64_t k2 = lane; k2 < p; k2 += 64) apply_rot(r, ya, yb, psy, k2);
+        double* va = V + (int64_t)a * q;
+        double* vb = V + (int64_t)b * q;
+        for (int64_t k2 = lane; k2 < q; k2 += 64) apply_rot(r, va, vb, psv, k2);
+      }
+      __syncthreads();
+    }
+    const int again = any;
+    __syncthreads();
+    if (!again) break;
+  }
+  if (tid == 0) rotated[0] = (sweep >= max_sweeps) ? 1u : 0u;
+  for (int64_t e = tid; e < 4 * psy; e += 1024) Yg[e] = Y[e];
+  for (int64_t e = tid; e < 4 * psv; e += 1024) Vg[e] = V[e];
+}
+
+hipError_t launch_jacobi_small(const Ctx& c, double* Y, int64_t p, int64_t q, double* V, double tol, int max_sweeps,
+                               unsigned* rotated) {
+  const size_t lds = (size_t)(q * p + q * q) * 4 * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)k_jacobi_small, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)SMALL_LDS);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(1024), lds, c.stream, Y, p, q, V, tol, max_sweeps, rotated);
+  return hipGetLastError();
+}
+
+// sigma_i^2 = ||Yc row i||^2, one workgroup per row.
+__global__ __launch_bounds__(256) void k_row_norm2(const double* __restrict__ Y, int64_t p, int64_t q,
+                                                   double* __restrict__ sig2) {
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  const int64_t i = blockIdx.x;
+  const int64_t ps = q * p;
+  const double* y = Y + i * p;
+  double s = 0.0;
+  for (int64_t k = tid; k < p; k += 256) {
+    const double a0 = y[k], a1 = y[k + ps], a2 = y[k + 2 * ps], a3 = y[k + 3 * ps];
+    s += a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3;
+  }
+  s = wsum(s);
+  if ((tid & 63) == 0) red[tid >> 6] = s;
+  __syncthreads();
+  if (tid == 0) sig2[i] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// Keep sigma_i > rtol * sigma_max, at most max_rank of the largest (ties by
+// index); d_i = 1 / sigma_i^2 for kept columns, 0 otherwise.
+__global__ __launch_bounds__(1024) void k_pinv_select(const double* __restrict__ sig2, int64_t q, double rtol,
+                                                      int64_t max_rank, double* __restrict__ dsc,
+                                                      int64_t* rank_out) {
+  __shared__ double red[1024];
+  __shared__ int64_t cnt[1024];
+  const int tid = threadIdx.x;
+  double mx = 0.0;
+  for (int64_t i = tid; i < q; i += 1024) mx = fmax(mx, sig2[i]);
+  red[tid] = mx;
+  __syncthreads();
+  for (int w = 512; w >= 1; w >>= 1) {
+    if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
+    __syncthreads();
+  }
+  const double smax = sqrt(red[0]);
+  const double thr = rtol * smax;
+  int64_t kept = 0;
+  for (int64_t i = tid; i < q; i += 1024) {
+    const double si2 = sig2[i];
+    const double si = sqrt(si2);
+    bool keep = smax > 0.0 && si > thr;
+    if (keep && max_rank > 0) {
+      int64_t rk = 0;
+      for (int64_t j = 0; j < q; ++j) {
+        const double sj2 = sig2[j];
+        rk += (sj2 > si2 || (sj2 == si2 && j < i)) ? 1 : 0;
+      }
+      keep = rk < max_rank;
+    }
+    dsc[i] = keep ? 1.0 / si2 : 0.0;
+    kept += keep ? 1 : 0;
+  }
+  cnt[tid] = kept;
+  __syncthreads();
+  for (int w = 512; w >= 1; w >>= 1) {
+    if (tid < w) cnt[tid] += cnt[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0 && rank_out) rank_out[0] = cnt[0];
+}
+
+// Yc[i][:] <- conj(d_i Yc[i][:]) and Vc <- conj(Vc), one workgroup per row.
+__global__ __launch_bounds__(256) void k_pinv_apply(double* __restrict__ Y, int64_t p, int64_t q,
+                                                    double* __restrict__ V, const double* __restrict__ dsc) {
+  const int64_t i = blockIdx.x;
+  const double d = dsc[i];
+  const int64_t psy = q * p, psv = q * q;
+  double* y = Y + i * p;
+  for (int64_t k = threadIdx.x; k < p; k += 256) {
+    y[k] = d * y[k];
+    y[k + psy] = -d * y[k + psy];
+    y[k + 2 * psy] = -d * y[k + 2 * psy];
+    y[k + 3 * psy] = -d * y[k + 3 * psy];
+  }
+  double* v = V + i * q;
+  for (int64_t k = threadIdx.x; k < q; k += 256) {
+    v[k + psv] = -v[k + psv];
+    v[k + 2 * psv] = -v[k + 2 * psv];
+    v[k + 3 * psv] = -v[k + 3 * psv];
+  }
+}
+
+hipError_t launch_pinv_scale(const Ctx& c, double* Y, int64_t p, int64_t q, double rtol, int64_t max_rank,
+                             int64_t* rank_out, double* sig) {
+  // sig holds 2q doubles: sigma^2 then the scale factors
+  hipLaunchKernelGGL(k_row_norm2, dim3((unsigned)q), dim3(256), 0, c.stream, Y, p, q, sig);
+  hipLaunchKernelGGL(k_pinv_select, dim3(1), dim3(1024), 0, c.stream, sig, q, rtol, max_rank, sig + q, rank_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pinv_apply(const Ctx& c, double* Y, int64_t p, int64_t q, double* V, const double* dsc) {
+  hipLaunchKernelGGL(k_pinv_apply, dim3((unsigned)q), dim3(256), 0, c.stream, Y, p, q, V, dsc);
+  return hipGetLastError();
+}
+
+}  // namespace qcur

@@ -1,0 +1,450 @@
+// Quaternion matrix product on gfx950 matrix cores.
+//
+// D = alpha * op(A) op(B) + beta * D with op(X) = X or X^H.  A quaternion
+// product expands into sixteen real products (Section 2.2 multiplication
+// laws):
+//   D0 = A0B0 - A1B1 - A2B2 - A3B3      D1 = A1B0 + A0B1 - A3B2 + A2B3
+//   D2 = A2B0 + A3B1 + A0B2 - A1B3      D3 = A3B0 - A2B1 + A1B2 + A0B3
+// i.e. stack(D) = L(A) stack(B) with the 4x4 signed block matrix L(A).  The
+// kernel never materialises L(A): each wave loads the four planes of its A
+// and B fragments once per k-step, forms -A1, -A2, -A3 in registers, and
+// issues the sixteen MFMAs, so one quaternion multiply-accumulate costs
+// exactly sixteen real ones.
+//
+// Tiles: a 256-thread workgroup owns a 64 x 64 quaternion output tile (four
+// real 64 x 64 planes); each of its four waves owns 32 x 32 (2 x 2 MFMA
+// 16x16 blocks per plane).  MFMA shapes: f64 16x16x4, f32 16x16x4,
+// bf16 16x16x32 (FP32 accumulation).  K is staged through LDS in slices of
+// 16 (f32/f64) or 32 (bf16) with the next slice prefetched into registers.
+//
+// Epilogues: (a) store alpha*acc + beta*D, or a split-K partial;
+// (b) residual: subtract the tile of A, apply the mask, square and reduce
+// in FP64 to one partial per workgroup, optionally writing e_scale*(A-CUR).
+#include <algorithm>
+
+#include "qcur_internal.hpp"
+
+namespace qcur {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 64, BN = 64, NT = 256;
+
+template <int DT> struct MT;
+template <> struct MT<QCUR_F64> {
+  typedef double In;
+  typedef double Acc;
+  typedef f64x4 AccV;
+  typedef double Frag;
+  static constexpr int BK = 16, KM = 4, PAD = 4;
+  // output element r of lane l sits at row (l/16) + 4r (rows interleaved)
+  static __device__ inline int out_row(int lane, int r) { return (lane >> 4) + 4 * r; }
+  static __device__ inline AccV mfma(Frag a, Frag b, AccV c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline Frag neg(Frag a) { return -a; }
+};
+template <> struct MT<QCUR_F32> {
+  typedef float In;
+  typedef float Acc;
+  typedef f32x4 AccV;
+  typedef float Frag;
+  static constexpr int BK = 16, KM = 4, PAD = 4;
+  // output element r of lane l sits at row 4(l/16) + r
+  static __device__ inline int out_row(int lane, int r) { return (lane >> 4) * 4 + r; }
+  static __device__ inline AccV mfma(Frag a, Frag b, AccV c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline Frag neg(Frag a) { return -a; }
+};
+template <> struct MT<QCUR_BF16> {
+  typedef uint16_t In;
+  typedef float Acc;
+  typedef f32x4 AccV;
+  typedef bf16x8 Frag;
+  static constexpr int BK = 32, KM = 32, PAD = 8;
+  static __device__ inline int out_row(int lane, int r) { return (lane >> 4) * 4 + r; }
+  static __device__ inline AccV mfma(Frag a, Frag b, AccV c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline Frag neg(Frag a) {
+    u32x4 u = __builtin_bit_cast(u32x4, a);
+    u ^= (u32x4){0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+    return __builtin_bit_cast(Frag, u);
+  }
+};
+
+template <typename T> __device__ inline T negv(T v);
+template <> __device__ inline double negv<double>(double v) { return -v; }
+template <> __device__ inline float negv<float>(float v) { return -v; }
+template <> __device__ inline uint16_t negv<uint16_t>(uint16_t v) { return (uint16_t)(v ^ 0x8000u); }
+
+struct GemmArgs {
+  const void* A;
+  int64_t lda, psa;
+  const void* B;
+  int64_t ldb, psb;
+  void* D;
+  int64_t ldd, psd;
+  int64_t M, N, K;
+  int opA, opB;
+  double alpha, beta;
+  int ktiles_per_split;
+  // residual epilogue
+  const void* R0;  // the matrix subtracted from (A of the residual)
+  int r0dt;
+  int64_t r0ld, r0ps;
+  const uint8_t* mask;
+  int64_t mask_ld;
+  double* partials;
+  void* E;
+  int edt;
+  int64_t eld, eps;
+  double e_scale;
+};
+
+enum { EPI_STORE = 0, EPI_PARTIAL = 1, EPI_RESID = 2 };
+
+// LDS layouts.  f32/f64: k-major rows [k][i] (A) and [k][j] (B) so that the
+// 16 lanes of an MFMA operand read 16 consecutive elements.  bf16: [i][k]
+// and [j][k] so that each lane reads its 8 consecutive k values at once.
+template <int DT> struct Smem {
+  typedef typename MT<DT>::In In;
+  static constexpr int BK = MT<DT>::BK, PAD = MT<DT>::PAD;
+  static constexpr bool KMAJ = (DT != QCUR_BF16);
+  static constexpr int AR = KMAJ ? BK : BM, AC = KMAJ ? BM + PAD : BK + PAD;
+  static constexpr int BR = KMAJ ? BK : BN, BC = KMAJ ? BN + PAD : BK + PAD;
+  In a[4][AR][AC];
+  In b[4][BR][BC];
+};
+
+template <int DT, int EPI>
+__global__ __launch_bounds__(NT) void k_qgemm(GemmArgs g) {
+  typedef MT<DT> T;
+  typedef typename T::In In;
+  typedef typename T::AccV AccV;
+  typedef typename T::Frag Frag;
+  constexpr int BK = T::BK;
+  constexpr bool KMAJ = Smem<DT>::KMAJ;
+  constexpr int EA = BM * BK / NT;  // elements per thread per plane
+  constexpr int EB = BK * BN / NT;
+  __shared__ Smem<DT> sm;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int64_t bm = (int64_t)blockIdx.y * BM, bn = (int64_t)blockIdx.x * BN;
+  const In* __restrict__ Ag = (const In*)g.A;
+  const In* __restrict__ Bg = (const In*)g.B;
+
+  const int64_t ktiles = (g.K + BK - 1) / BK;
+  const int64_t kt0 = (int64_t)blockIdx.z * g.ktiles_per_split;
+  const int64_t kt1 = min(ktiles, kt0 + g.ktiles_per_split);
+
+  In ra[4][EA], rb[4][EB];
+
+  auto load_tiles = [&](int64_t kt) {
+    const int64_t k0 = kt * BK;
+#pragma unroll
+    for (int r = 0; r < EA; ++r) {
+      const int e = tid + NT * r;
+      int i, k;
+      if (g.opA == QCUR_OP_N) { i = e / BK; k = e % BK; } else { i = e % BM; k = e / BM; }
+      const int64_t gi = bm + i, gk = k0 + k;
+      const bool ok = gi < g.M && gk < g.K;
+      const int64_t off = (g.opA == QCUR_OP_N) ? gi * g.lda + gk : gk * g.lda + gi;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        In v = ok ? Ag[off + q * g.psa] : (In)0;
+        if (g.opA == QCUR_OP_H && q > 0) v = negv<In>(v);
+        ra[q][r] = v;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < EB; ++r) {
+      const int e = tid + NT * r;
+      int k, j;
+      if (g.opB == QCUR_OP_N) { k = e / BN; j = e % BN; } else { k = e % BK; j = e / BK; }
+      const int64_t gk = k0 + k, gj = bn + j;
+      const bool ok = gk < g.K && gj < g.N;
+      const int64_t off = (g.opB == QCUR_OP_N) ? gk * g.ldb + gj : gj * g.ldb + gk;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        In v = ok ? Bg[off + q * g.psb] : (In)0;
+        if (g.opB == QCUR_OP_H && q > 0) v = negv<In>(v);
+        rb[q][r] = v;
+      }
+    }
+  };
+  auto store_tiles = [&]() {
+#pragma unroll
+    for (int r = 0; r < EA; ++r) {
+      const int e = tid + NT * r;
+      int i, k;
+      if (g.opA == QCUR_OP_N) { i = e / BK; k = e % BK; } else { i = e % BM; k = e / BM; }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (KMAJ) sm.a[q][k][i] = ra[q][r]; else sm.a[q][i][k] = ra[q][r];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < EB; ++r) {
+      const int e = tid + NT * r;
+      int k, j;
+      if (g.opB == QCUR_OP_N) { k = e / BN; j = e % BN; } else { k = e % BK; j = e / BK; }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (KMAJ) sm.b[q][k][j] = rb[q][r]; else sm.b[q][j][k] = rb[q][r];
+      }
+    }
+  };
+
+  AccV acc[4][2][2];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) acc[p][x][y] = (AccV){0, 0, 0, 0};
+
+  if (kt0 < kt1) load_tiles(kt0);
+  for (int64_t kt = kt0; kt < kt1; ++kt) {
+    __syncthreads();
+    store_tiles();
+    __syncthreads();
+    if (kt + 1 < kt1) load_tiles(kt + 1);
+#pragma unroll
+    for (int kk = 0; kk < BK / T::KM; ++kk) {
+      Frag a[4][2], na[4][2], b[4][2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        const int ii = wm + x * 16 + (lane & 15);
+        const int jj = wn + x * 16 + (lane & 15);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if constexpr (KMAJ) {
+            a[q][x] = sm.a[q][kk * 4 + (lane >> 4)][ii];
+            b[q][x] = sm.b[q][kk * 4 + (lane >> 4)][jj];
+          } else {
+            a[q][x] = *(const Frag*)&sm.a[q][ii][(lane >> 4) * 8];
+            b[q][x] = *(const Frag*)&sm.b[q][jj][(lane >> 4) * 8];
+          }
+        }
+#pragma unroll
+        for (int q = 1; q < 4; ++q) na[q][x] = T::neg(a[q][x]);
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          // plane 0: A0B0 - A1B1 - A2B2 - A3B3
+          acc[0][x][y] = T::mfma(a[0][x], b[0][y], acc[0][x][y]);
+          acc[0][x][y] = T::mfma(na[1][x], b[1][y], acc[0][x][y]);
+          acc[0][x][y] = T::mfma(na[2][x], b[2][y], acc[0][x][y]);
+          acc[0][x][y] = T::mfma(na[3][x], b[3][y], acc[0][x][y]);
+          // plane 1: A1B0 + A0B1 - A3B2 + A2B3
+          acc[1][x][y] = T::mfma(a[1][x], b[0][y], acc[1][x][y]);
+          acc[1][x][y] = T::mfma(a[0][x], b[1][y], acc[1][x][y]);
+          acc[1][x][y] = T::mfma(na[3][x], b[2][y], acc[1][x][y]);
+          acc[1][x][y] = T::mfma(a[2][x], b[3][y], acc[1][x][y]);
+          // plane 2: A2B0 + A3B1 + A0B2 - A1B3
+          acc[2][x][y] = T::mfma(a[2][x], b[0][y], acc[2][x][y]);
+          acc[2][x][y] = T::mfma(a[3][x], b[1][y], acc[2][x][y]);
+          acc[2][x][y] = T::mfma(a[0][x], b[2][y], acc[2][x][y]);
+          acc[2][x][y] = T::mfma(na[1][x], b[3][y], acc[2][x][y]);
+          // plane 3: A3B0 - A2B1 + A1B2 + A0B3
+          acc[3][x][y] = T::mfma(a[3][x], b[0][y], acc[3][x][y]);
+          acc[3][x][y] = T::mfma(na[2][x], b[1][y], acc[3][x][y]);
+          acc[3][x][y] = T::mfma(a[1][x], b[2][y], acc[3][x][y]);
+          acc[3][x][y] = T::mfma(a[0][x], b[3][y], acc[3][x][y]);
+        }
+    }
+  }
+
+  // Epilogue.  MFMA 16x16 output: lane holds column lane%16 and four rows
+  // given by out_row (f32/bf16: 4(lane/16)+r; f64: lane/16 + 4r).
+  if constexpr (EPI == EPI_RESID) {
+    double sq = 0.0;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t i = bm + wm + x * 16 + T::out_row(lane, r);
+          const int64_t j = bn + wn + y * 16 + (lane & 15);
+          if (i < g.M && j < g.N) {
+            const bool keep = g.mask ? (g.mask[i * g.mask_ld + j] != 0) : true;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+              double d = load_as_double(g.R0, g.r0dt, i * g.r0ld + j + p * g.r0ps) - (double)acc[p][x][y][r];
+              if (!keep) d = 0.0;
+              sq += d * d;
+              if (g.E) store_from_double(g.E, g.edt, i * g.eld + j + p * g.eps, g.e_scale * d);
+            }
+          }
+        }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) sq += __shfl_xor(sq, o, 64);
+    __shared__ double wpart[4];
+    if (lane == 0) wpart[wave] = sq;
+    __syncthreads();
+    if (tid == 0) {
+      const int64_t blin = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+      g.partials[blin] = ((wpart[0] + wpart[1]) + wpart[2]) + wpart[3];
+    }
+  } else {
+    typedef typename T::Acc Acc;
+    Acc* Dg = (Acc*)g.D;
+    int64_t ps = g.psd, ld = g.ldd;
+    if (EPI == EPI_PARTIAL) Dg += (int64_t)blockIdx.z * 4 * ps;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t i = bm + wm + x * 16 + T::out_row(lane, r);
+          const int64_t j = bn + wn + y * 16 + (lane & 15);
+          if (i < g.M && j < g.N) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+              const int64_t o = i * ld + j + p * ps;
+              if (EPI == EPI_PARTIAL) {
+                Dg[o] = acc[p][x][y][r];
+              } else {
+                double v = g.alpha * (double)acc[p][x][y][r];
+                if (g.beta != 0.0) v += g.beta * (double)Dg[o];
+                Dg[o] = (Acc)v;
+              }
+            }
+          }
+        }
+  }
+}
+
+// Split-K reduction: D = alpha * sum_z P[z] + beta * D, z in fixed order.
+template <typename Acc>
+__global__ void k_splitk_reduce(const Acc* __restrict__ P, int splits, int64_t M, int64_t N, double alpha,
+                                double beta, Acc* D, int64_t ldd, int64_t psd) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= N) return;
+  const int64_t MN = M * N;
+  for (int64_t i = blockIdx.y; i < M; i += gridDim.y) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      double s = 0.0;
+      for (int z = 0; z < splits; ++z) s += (double)P[(int64_t)z * 4 * MN + p * MN + i * N + j];
+      const int64_t o = i * ldd + j + p * psd;
+      double v = alpha * s;
+      if (beta != 0.0) v += beta * (double)D[o];
+      D[o] = (Acc)v;
+    }
+  }
+}
+
+static int choose_splits(int64_t M, int64_t N, int64_t K, int bk) {
+  const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  const int64_t kt = (K + bk - 1) / bk;
+  int s = 1;
+  while (s < 16 && tiles * s < 512 && kt / (s * 2) >= 8) s *= 2;
+  return s;
+}
+
+static int bk_of(int compute) { return compute == QCUR_BF16 ? 32 : 16; }
+static size_t acc_size(int compute) { return compute == QCUR_F64 ? 8 : 4; }
+
+size_t gemm_workspace(int64_t M, int64_t N, int64_t K, int compute) {
+  const int s = choose_splits(M, N, K, bk_of(compute));
+  if (s <= 1) return 0;
+  return (size_t)s * 4 * (size_t)M * (size_t)N * acc_size(compute);
+}
+
+template <int DT>
+static hipError_t gemm_dt(const Ctx& c, GemmArgs g, void* ws, size_t ws_bytes) {
+  constexpr int BK = MT<DT>::BK;
+  const int64_t kt = (g.K + BK - 1) / BK;
+  int splits = choose_splits(g.M, g.N, g.K, BK);
+  const size_t need = (size_t)splits * 4 * (size_t)g.M * (size_t)g.N * acc_size(DT);
+  if (splits > 1 && (ws == nullptr || ws_bytes < need)) splits = 1;
+  dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM), 1);
+  if (splits == 1) {
+    g.ktiles_per_split = (int)kt;
+    hipLaunchKernelGGL((k_qgemm<DT, EPI_STORE>), grid, dim3(NT), 0, c.stream, g);
+    return hipGetLastError();
+  }
+  const int per = (int)((kt + splits - 1) / splits);
+  splits = (int)((kt + per - 1) / per);
+  grid.z = splits;
+  g.ktiles_per_split = per;
+  typedef typename MT<DT>::Acc Acc;
+  GemmArgs gp = g;
+  gp.D = ws;
+  gp.ldd = g.N;
+  gp.psd = g.M * g.N;
+  hipLaunchKernelGGL((k_qgemm<DT, EPI_PARTIAL>), grid, dim3(NT), 0, c.stream, gp);
+  hipLaunchKernelGGL(k_splitk_reduce<Acc>, dim3((unsigned)((g.N + 255) / 256), (unsigned)std::min<int64_t>(g.M, 65535)), dim3(256), 0,
+                     c.stream, (const Acc*)ws, splits, g.M, g.N, g.alpha, g.beta, (Acc*)g.D, g.ldd, g.psd);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm(const Ctx& c, int opA, int opB, double alpha, QView A, QView B, double beta, QView D,
+                       int compute, void* ws, size_t ws_bytes) {
+  GemmArgs g = {};
+  g.A = A.p; g.lda = A.ld; g.psa = A.ps;
+  g.B = B.p; g.ldb = B.ld; g.psb = B.ps;
+  g.D = D.p; g.ldd = D.ld; g.psd = D.ps;
+  g.M = D.rows; g.N = D.cols;
+  g.K = (opA == QCUR_OP_N) ? A.cols : A.rows;
+  g.opA = opA; g.opB = opB; g.alpha = alpha; g.beta = beta;
+  if (g.M == 0 || g.N == 0) return hipSuccess;
+  if (g.K == 0) {  // D = beta * D
+    return launch_axpby(c, 0.0, D, beta, D);
+  }
+  switch (compute) {
+    case QCUR_F64: return gemm_dt<QCUR_F64>(c, g, ws, ws_bytes);
+    case QCUR_F32: return gemm_dt<QCUR_F32>(c, g, ws, ws_bytes);
+    default: return gemm_dt<QCUR_BF16>(c, g, ws, ws_bytes);
+  }
+}
+
+size_t residual_tiles(int64_t m, int64_t n) { return (size_t)((m + BM - 1) / BM) * (size_t)((n + BN - 1) / BN); }
+
+hipError_t launch_residual_gemm(const Ctx& c, QView A, QView B1, QView R, const uint8_t* mask, int64_t mask_ld,
+                                int compute, double* partials, QView* E, double e_scale) {
+  GemmArgs g = {};
+  g.A = B1.p; g.lda = B1.ld; g.psa = B1.ps;
+  g.B = R.p; g.ldb = R.ld; g.psb = R.ps;
+  g.M = A.rows; g.N = A.cols; g.K = B1.cols;
+  g.opA = QCUR_OP_N; g.opB = QCUR_OP_N;
+  g.alpha = 1.0; g.beta = 0.0;
+  g.R0 = A.p; g.r0dt = A.dt; g.r0ld = A.ld; g.r0ps = A.ps;
+  g.mask = mask; g.mask_ld = mask_ld;
+  g.partials = partials;
+  if (E) { g.E = E->p; g.edt = E->dt; g.eld = E->ld; g.eps = E->ps; g.e_scale = e_scale; }
+  if (g.M == 0 || g.N == 0) return hipSuccess;
+  dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM), 1);
+  switch (compute) {
+    case QCUR_F64: {
+      g.ktiles_per_split = (int)((g.K + 15) / 16);
+      hipLaunchKernelGGL((k_qgemm<QCUR_F64, EPI_RESID>), grid, dim3(NT), 0, c.stream, g);
+      break;
+    }
+    case QCUR_F32: {
+      g.ktiles_per_split = (int)((g.K + 15) / 16);
+      hipLaunchKernelGGL((k_qgemm<QCUR_F32, EPI_RESID>), grid, dim3(NT), 0, c.stream, g);
+      break;
+    }
+    default: {
+      g.ktiles_per_split = (int)((g.K + 31) / 32);
+      hipLaunchKernelGGL((k_qgemm<QCUR_BF16, EPI_RESID>), grid, dim3(NT), 0, c.stream, g);
+    }
+  }
+  return hipGetLastError();
+}
+
+}  // namespace qcur

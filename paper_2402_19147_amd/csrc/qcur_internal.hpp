@@ -1,0 +1,118 @@
+// Internal declarations shared by the libqcur kernels and its C ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/qcur.h"
+
+namespace qcur {
+
+// ---- device status word bits (OR-ed by kernels, read by qcur_sync_status)
+enum StatusBit : unsigned {
+  ST_ARG = 1u << 0,
+  ST_SAMPLE = 1u << 1,
+  ST_NUMERIC = 1u << 2,
+};
+
+// A quaternion matrix view: four planes of rows x cols, row stride ld,
+// plane stride ps, all in elements of the view's dtype.
+struct QView {
+  void* p;
+  int64_t rows, cols, ld, ps;
+  int dt;
+};
+
+inline QView view_of(const qcur_qmat& m) {
+  return QView{m.p, m.rows, m.cols, m.ld, m.pstride, (int)m.dtype};
+}
+
+inline size_t dtype_size(int dt) { return dt == QCUR_F64 ? 8 : dt == QCUR_F32 ? 4 : 2; }
+
+struct Ctx {
+  int device;
+  hipStream_t stream;
+  unsigned* status;  // device word
+};
+
+// ---- element conversions --------------------------------------------------
+// BF16 is stored as raw uint16 bits.  float -> bf16 rounds to nearest even
+// (the usual add-0x7FFF-plus-lsb method); NaN maps to a quiet NaN.
+__host__ __device__ inline uint16_t f32_to_bf16(float f) {
+  union { float f; uint32_t u; } v;
+  v.f = f;
+  if ((v.u & 0x7F800000u) == 0x7F800000u && (v.u & 0x007FFFFFu)) return (uint16_t)((v.u >> 16) | 0x40u);
+  uint32_t lsb = (v.u >> 16) & 1u;
+  return (uint16_t)((v.u + 0x7FFFu + lsb) >> 16);
+}
+__host__ __device__ inline float bf16_to_f32(uint16_t b) {
+  union { float f; uint32_t u; } v;
+  v.u = ((uint32_t)b) << 16;
+  return v.f;
+}
+
+template <int DT> struct Elem;
+template <> struct Elem<QCUR_F64> { typedef double T; };
+template <> struct Elem<QCUR_F32> { typedef float T; };
+template <> struct Elem<QCUR_BF16> { typedef uint16_t T; };
+
+__device__ inline double load_as_double(const void* p, int dt, int64_t off) {
+  if (dt == QCUR_F64) return ((const double*)p)[off];
+  if (dt == QCUR_F32) return (double)((const float*)p)[off];
+  return (double)bf16_to_f32(((const uint16_t*)p)[off]);
+}
+__device__ inline void store_from_double(void* p, int dt, int64_t off, double v) {
+  if (dt == QCUR_F64) ((double*)p)[off] = v;
+  else if (dt == QCUR_F32) ((float*)p)[off] = (float)v;
+  else ((uint16_t*)p)[off] = f32_to_bf16((float)v);
+}
+
+// ---- launchers (implemented in the kernel sources) ------------------------
+hipError_t launch_probs_partials(const Ctx& c, QView A, double* colpart, double* rowpart, int rb, int ncb);
+hipError_t launch_probs_finish(const Ctx& c, int64_t m, int64_t n, const double* colpart,
+                               const double* rowpart, int nrb, int ncb, int sampling, double* p,
+                               double* q, double* fro2, double* scratch);
+void probs_grid(int64_t m, int64_t n, int* rb, int* nrb, int* ncb);
+
+hipError_t launch_draw(const Ctx& c, const double* probs, int64_t n, int64_t count, uint64_t seed,
+                       uint64_t set_id, int with_replacement, int64_t* idx);
+
+hipError_t launch_gather(const Ctx& c, QView A, const int64_t* I, int64_t r, const int64_t* J,
+                         int64_t cc, const QView* C, const QView* R, const QView* W);
+// mode bit 1: transpose, bit 2: conjugate (quaternion conjugate of every entry)
+enum { CAST_COPY = 0, CAST_T = 1, CAST_CONJ = 2, CAST_H = 3 };
+hipError_t launch_cast(const Ctx& c, QView X, QView Y, int mode);
+
+// qGEMM: D = alpha * op(A) op(B) + beta * D.  ws may be NULL (no split-K).
+size_t gemm_workspace(int64_t M, int64_t N, int64_t K, int compute);
+hipError_t launch_gemm(const Ctx& c, int opA, int opB, double alpha, QView A, QView B, double beta,
+                       QView D, int compute, void* ws, size_t ws_bytes);
+// Residual: partial sums of squares of e_scale-free P_Omega(A - B1 R) per tile,
+// then a fixed-order final sum into fro (sqrt).  Optional E output.
+size_t residual_tiles(int64_t m, int64_t n);
+hipError_t launch_residual_gemm(const Ctx& c, QView A, QView B1, QView R, const uint8_t* mask,
+                                int64_t mask_ld, int compute, double* partials, QView* E,
+                                double e_scale);
+hipError_t launch_sum_partials(const Ctx& c, const double* partials, int64_t count, double* out,
+                               int take_sqrt);
+
+// Jacobi pseudoinverse pieces.
+hipError_t launch_jacobi_round(const Ctx& c, double* Y, int64_t p, int64_t q, double* V,
+                               int64_t qpad, int round, double tol, unsigned* rotated);
+hipError_t launch_jacobi_small(const Ctx& c, double* Y, int64_t p, int64_t q, double* V,
+                               double tol, int max_sweeps, unsigned* rotated);
+bool jacobi_small_fits(int64_t p, int64_t q);
+hipError_t launch_pinv_scale(const Ctx& c, double* Y, int64_t p, int64_t q, double rtol,
+                             int64_t max_rank, int64_t* rank_out, double* sig);
+hipError_t launch_check_finite(const Ctx& c, QView X);
+hipError_t launch_fill_identity(const Ctx& c, double* V, int64_t q);
+hipError_t launch_pinv_apply(const Ctx& c, double* Y, int64_t p, int64_t q, double* V, const double* dsc);
+
+// Backward assembly: dA = G + scatter(gC, gR, gW).
+hipError_t launch_inverse_map(const Ctx& c, const int64_t* idx, int64_t cnt, int64_t n, int32_t* inv);
+hipError_t launch_backward_assemble(const Ctx& c, QView dA, QView G, int has_G, QView gC, QView gR,
+                                    QView gW, const int32_t* iinv, const int32_t* jinv);
+hipError_t launch_axpby(const Ctx& c, double alpha, QView X, double beta, QView Y);
+hipError_t launch_identity_minus(const Ctx& c, QView X);
+
+}  // namespace qcur

@@ -1,0 +1,145 @@
+"""The C ABI without a GPU: the library loads, exports every function the
+header declares, sizes workspaces, and rejects bad arguments on the host
+before touching the (here NULL) handle."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2402_19147_amd import qcur as Q
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = 0x10000  # never dereferenced: every call below fails validation first
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(Q.LIB_PATH):
+        pytest.skip("libqcur.so not built")
+    return Q.lib()
+
+
+def declared_functions():
+    with open(os.path.join(ROOT, "include", "qcur.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qcur_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert len(names) >= 20
+    lib = ctypes.CDLL(Q.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    for call in ["qcur_probs", "qcur_draw", "qcur_gather", "qcur_pinv", "qcur_gemm", "qcur_approx",
+                 "qcur_residual", "qcur_backward"]:
+        assert call in names
+
+
+def test_status_strings(L):
+    for k, v in Q.STATUS.items():
+        assert L.qcur_status_string(k).decode() == v
+    assert L.qcur_version() >= 100
+
+
+def qm(rows, cols, dt=Q.F64, ld=None, ps=None, p=FAKE):
+    ld = cols if ld is None else ld
+    ps = rows * ld if ps is None else ps
+    return Q.QMat(p, rows, cols, ld, ps, dt)
+
+
+def test_gemm_validation(L):
+    A, B, D = qm(4, 5), qm(5, 3), qm(4, 3)
+    ok = L.qcur_gemm(None, Q.OP_N, Q.OP_N, 1.0, A, B, 0.0, D, Q.F64, None, 0)
+    assert ok == 1  # everything valid: only the NULL handle is rejected
+    assert L.qcur_gemm(None, Q.OP_N, Q.OP_N, 1.0, A, qm(6, 3), 0.0, D, Q.F64, None, 0) == 2
+    assert L.qcur_gemm(None, Q.OP_N, Q.OP_N, 1.0, A, B, 0.0, qm(4, 4), Q.F64, None, 0) == 2
+    assert L.qcur_gemm(None, Q.OP_H, Q.OP_N, 1.0, qm(5, 4), B, 0.0, D, Q.F64, None, 0) == 1
+    assert L.qcur_gemm(None, Q.OP_N, Q.OP_N, 1.0, A, B, 0.0, D, Q.F32, None, 0) == 3
+    assert L.qcur_gemm(None, Q.OP_N, Q.OP_N, 1.0, qm(4, 5, Q.BF16), qm(5, 3, Q.BF16), 0.0,
+                       qm(4, 3, Q.F32), Q.BF16, None, 0) == 1
+    assert L.qcur_gemm(None, 7, Q.OP_N, 1.0, A, B, 0.0, D, Q.F64, None, 0) == 1
+    assert "op must be" in L.qcur_last_error().decode()
+    # overlapping planes and short rows
+    assert L.qcur_gemm(None, Q.OP_N, Q.OP_N, 1.0, qm(4, 5, ps=10), B, 0.0, D, Q.F64, None, 0) == 2
+    assert L.qcur_gemm(None, Q.OP_N, Q.OP_N, 1.0, qm(4, 5, ld=3), B, 0.0, D, Q.F64, None, 0) == 2
+    assert L.qcur_gemm(None, Q.OP_N, Q.OP_N, 1.0, qm(4, 5, p=0), B, 0.0, D, Q.F64, None, 0) == 1
+    assert L.qcur_gemm(None, Q.OP_N, Q.OP_N, float("nan"), A, B, 0.0, D, Q.F64, None, 0) == 1
+
+
+def test_draw_validation(L):
+    assert L.qcur_draw(None, FAKE, 10, 11, 1, 0, 0, FAKE) == 1          # count > n
+    assert L.qcur_draw(None, FAKE, 10, 11, 1, 0, 1, FAKE) == 1          # ok with replacement
+    assert L.qcur_draw(None, FAKE, 0, 1, 1, 0, 0, FAKE) == 1
+    assert L.qcur_draw(None, FAKE, 20000, 5, 1, 0, 0, FAKE) == 8        # beyond the LDS limit
+    assert L.qcur_draw(None, FAKE, 10000, 5, 1, 0, 1, FAKE) == 8
+    assert L.qcur_draw(None, None, 10, 5, 1, 0, 0, FAKE) == 1
+    assert L.qcur_draw(None, FAKE, 10, -1, 1, 0, 0, FAKE) == 1
+
+
+def test_probs_gather_pinv_validation(L):
+    A = qm(6, 5)
+    assert L.qcur_probs(None, A, 2, FAKE, FAKE, None, FAKE, 1 << 20) == 1     # bad sampling
+    assert L.qcur_probs(None, A, 0, FAKE, FAKE, None, FAKE, 8) == 4           # workspace too small
+    assert L.qcur_probs(None, A, 1, FAKE, FAKE, None, None, 0) == 1           # uniform: no workspace needed
+    assert L.qcur_probs(None, qm(0, 5), 0, FAKE, FAKE, None, FAKE, 1 << 20) == 2
+    assert L.qcur_gather(None, A, FAKE, 2, FAKE, 3, qm(6, 3), qm(2, 5), qm(2, 3)) == 1
+    assert L.qcur_gather(None, A, FAKE, 2, FAKE, 3, qm(6, 4), None, None) == 2
+    assert L.qcur_gather(None, A, None, 2, FAKE, 3, None, qm(2, 5), None) == 1
+    X, Xp = qm(6, 4), qm(4, 6)
+    need = L.qcur_pinv_workspace(6, 4)
+    assert need > 0
+    assert L.qcur_pinv(None, X, -1.0, 0, Xp, None, FAKE, need) == 1
+    assert L.qcur_pinv(None, X, -1.0, 0, Xp, None, FAKE, need - 512) == 4
+    assert L.qcur_pinv(None, X, -1.0, 0, qm(6, 4), None, FAKE, need) == 2
+    assert L.qcur_pinv(None, qm(6, 4, Q.F32), -1.0, 0, Xp, None, FAKE, need) == 3
+    assert L.qcur_pinv(None, X, -1.0, -2, Xp, None, FAKE, need) == 1
+
+
+def test_approx_residual_backward_validation(L):
+    m, n, c, r = 30, 20, 6, 5
+    A, C, R, W = qm(m, n), qm(m, c), qm(r, n), qm(r, c)
+    U, B = qm(c, r), qm(m, n)
+    need = L.qcur_approx_workspace(m, n, c, r, Q.CORE_CAR, Q.F64)
+    assert L.qcur_approx(None, A, C, R, W, Q.CORE_CAR, Q.F64, 1, -1.0, 0, U, B, None, FAKE, need) == 1
+    assert L.qcur_approx(None, A, C, R, W, Q.CORE_CAR, Q.F64, 1, -1.0, 0, U, B, None, FAKE, 16) == 4
+    assert L.qcur_approx(None, A, C, R, W, Q.CORE_CAR, Q.F64, 1, -1.0, 0, qm(r, c), B, None, FAKE, need) == 2
+    assert L.qcur_approx(None, A, C, R, W, Q.CORE_CAR, Q.F32, 1, -1.0, 0, U, B, None, FAKE, need) == 3
+    assert L.qcur_approx(None, A, C, R, W, 9, Q.F64, 0, -1.0, 0, U, None, None, FAKE, need) == 1
+    needw = L.qcur_approx_workspace(m, n, c, r, Q.CORE_WPINV, Q.F64)
+    assert L.qcur_approx(None, None, None, None, W, Q.CORE_WPINV, Q.F64, 0, -1.0, 0, U, None, None, FAKE,
+                         needw) == 1
+    fro = FAKE
+    needr = L.qcur_residual_workspace(m, n, c, r, Q.F32)
+    assert L.qcur_residual(None, A, qm(m, c, Q.F32), qm(c, r, Q.F32), qm(r, n, Q.F32), None, 0, Q.F32, fro,
+                           None, 1.0, FAKE, needr) == 1
+    assert L.qcur_residual(None, A, C, U, qm(r + 1, n), None, 0, Q.F64, fro, None, 1.0, FAKE, needr) == 2
+    assert L.qcur_residual(None, A, C, U, R, FAKE, n - 1, Q.F64, fro, None, 1.0, FAKE, needr) == 2
+    needb = L.qcur_backward_workspace(m, n, c, r, Q.F64)
+    assert L.qcur_backward(None, A, FAKE, r, FAKE, c, None, None, 0, -1.0, 0, Q.F64, qm(m, n), None, FAKE,
+                           needb) == 1
+    assert L.qcur_backward(None, A, FAKE, r, FAKE, c, None, None, 0, -1.0, 0, Q.BF16, qm(m, n), None, FAKE,
+                           needb) == 3
+    assert L.qcur_backward(None, A, FAKE, m + 1, FAKE, c, None, None, 0, -1.0, 0, Q.F64, qm(m, n), None,
+                           FAKE, needb) == 1
+    assert L.qcur_backward(None, A, FAKE, r, FAKE, c, None, None, 0, -1.0, 0, Q.F64, qm(m, n), None, FAKE,
+                           needb - 4096) == 4
+
+
+def test_workspace_sizes_are_monotone(L):
+    small = L.qcur_approx_workspace(256, 256, 40, 40, Q.CORE_CAR, Q.F32)
+    big = L.qcur_approx_workspace(1024, 1024, 200, 200, Q.CORE_CAR, Q.F32)
+    assert 0 < small < big
+    assert L.qcur_gemm_workspace(1024, 200, 1024, Q.F32) >= 0
+    assert L.qcur_probs_workspace(1024, 1024) > 8 * 2048
+
+
+def test_create_without_gpu_fails_cleanly(L):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    st = L.qcur_create(ctypes.byref(h), 0)
+    assert st in (1, 7) and not h.value

@@ -1,0 +1,329 @@
+"""Parity of every libqcur call with the FP64 CPU reference checker on the
+same seeded inputs (MI355X only).  Integer, index and copy results are
+compared bit for bit; floating-point results within the stated relative
+Frobenius tolerances (FP64 1e-12 unless conditioning says otherwise, FP32
+1e-5, BF16 operands 2e-2)."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from oracle.quat import qmul, qH, fro2
+
+pytestmark = pytest.mark.gpu
+
+Q = pytest.importorskip("paper_2402_19147_amd.qcur")
+DEV = torch.device("cuda:0")
+
+
+def T(x, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(x), dtype=dtype, device=DEV)
+
+
+def N(t):
+    return t.detach().to(torch.float64).cpu().numpy()
+
+
+def rel(x, ref):
+    d = np.sqrt(fro2(np.asarray(x, dtype=np.float64) - ref))
+    return d / max(np.sqrt(fro2(ref)), 1e-300)
+
+
+def kappa(X):
+    from oracle.pinv import singular_values
+    sv = singular_values(X)
+    sv = sv[sv > sv[0] * 1e-13]
+    return float(sv[0] / sv[-1])
+
+
+def cur_tol(C, R, floor=1e-12):
+    """FP64 tolerance for U-invariant products: the projectors C C^+ and
+    R^+ R are only determined to about eps * kappa."""
+    return max(floor, 10 * 2.0 ** -52 * (kappa(C) + kappa(R)))
+
+
+def bf16_round(x):
+    return torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+@pytest.fixture(autouse=True)
+def _status_clean():
+    Q.sync_status()
+    yield
+    Q.sync_status()
+
+
+# ---------------------------------------------------------------- qgemm
+GEMM_SHAPES = [(1, 1, 1), (16, 4, 16), (70, 37, 45), (130, 50, 70), (64, 1024, 64), (200, 96, 33)]
+
+
+@pytest.mark.parametrize("M,K,Nn", GEMM_SHAPES)
+@pytest.mark.parametrize("compute", [Q.F64, Q.F32, Q.BF16])
+@pytest.mark.parametrize("opA,opB", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_gemm_small_integers_bit_exact(M, K, Nn, compute, opA, opB):
+    rng = np.random.default_rng(M * 1000 + K * 10 + Nn + opA * 3 + opB)
+    lim = 2 if K > 64 else 4
+    A = workloads.small_int_quat(M, K, rng, lim) if opA == 0 else workloads.small_int_quat(K, M, rng, lim)
+    B = workloads.small_int_quat(K, Nn, rng, lim) if opB == 0 else workloads.small_int_quat(Nn, K, rng, lim)
+    Ae = A if opA == 0 else qH(A)
+    Be = B if opB == 0 else qH(B)
+    ref = qmul(Ae, Be)
+    tdt = {Q.F64: torch.float64, Q.F32: torch.float32, Q.BF16: torch.bfloat16}[compute]
+    D = Q.gemm(T(A, tdt), T(B, tdt), opA=opA, opB=opB, compute=compute)
+    assert np.array_equal(N(D), ref)
+
+
+@pytest.mark.parametrize("compute,tol", [(Q.F64, 1e-13), (Q.F32, 1e-5), (Q.BF16, 2e-2)])
+def test_gemm_gaussian_alpha_beta(compute, tol):
+    rng = np.random.default_rng(7)
+    A = rng.standard_normal((4, 150, 90))
+    B = rng.standard_normal((4, 90, 77))
+    D0 = rng.standard_normal((4, 150, 77))
+    tdt = {Q.F64: torch.float64, Q.F32: torch.float32, Q.BF16: torch.bfloat16}[compute]
+    odt = torch.float64 if compute == Q.F64 else torch.float32
+    Dt = T(D0, odt)
+    Q.gemm(T(A, tdt), T(B, tdt), alpha=-0.5, beta=2.0, D=Dt, compute=compute)
+    if compute == Q.BF16:
+        ref = -0.5 * qmul(bf16_round(A), bf16_round(B)) + 2.0 * D0
+    else:
+        ref = -0.5 * qmul(A, B) + 2.0 * D0
+    assert rel(N(Dt), ref) < tol
+
+
+def test_gemm_strided_views():
+    rng = np.random.default_rng(8)
+    big = rng.standard_normal((4, 100, 120))
+    A = big[:, 10:80, 5:65]            # 70 x 60 view with ld 120
+    B = rng.standard_normal((4, 60, 40))
+    At = T(big)[:, 10:80, 5:65]
+    D = Q.gemm(At, T(B))
+    assert rel(N(D), qmul(A, B)) < 1e-13
+
+
+# ---------------------------------------------------------------- probs / draw / gather
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_probs_length_and_uniform(dtype):
+    A = workloads.color_like(300, 517, 7, seed=3)
+    Ad = N(T(A, dtype))
+    p, q, f2 = Q.probs(T(A, dtype), Q.LENGTH)
+    pr, qr, fr = oracle.probs_length(Ad)
+    assert np.allclose(N(p), pr, rtol=1e-12, atol=0)
+    assert np.allclose(N(q), qr, rtol=1e-12, atol=0)
+    assert abs(float(N(f2)[0]) - fr) <= 1e-13 * fr
+    p, q, _ = Q.probs(T(A, dtype), Q.UNIFORM)
+    pu, qu = oracle.probs_uniform(300, 517)
+    assert np.array_equal(N(p), pu) and np.array_equal(N(q), qu)
+
+
+def test_probs_deterministic():
+    A = T(workloads.color_like(257, 1000, 5, seed=4))
+    p1, q1, _ = Q.probs(A)
+    p2, q2, _ = Q.probs(A)
+    assert torch.equal(p1, p2) and torch.equal(q1, q2)
+
+
+def test_draw_golden_cases():
+    with open(os.path.join(os.path.dirname(__file__), "golden", "draws.json")) as f:
+        cases = json.load(f)
+    for c in cases:
+        p = np.array([float.fromhex(x) for x in c["p"]])
+        idx = Q.draw(T(p), c["count"], c["seed"], c["set_id"], c["with_replacement"])
+        assert N(idx).astype(np.int64).tolist() == c["idx"], c["name"]
+
+
+@pytest.mark.parametrize("n,count,repl", [(1, 1, False), (64, 64, False), (65, 3, False), (4096, 400, False),
+                                          (5000, 4999, False), (16384, 100, False), (777, 2000, True),
+                                          (8192, 50, True)])
+def test_draw_matches_checker(n, count, repl):
+    rng = np.random.default_rng(n + count)
+    w = rng.random(n) ** 3
+    w[rng.random(n) < 0.1] = 0.0
+    if not repl and (w > 0).sum() < count:
+        w[:count] = 1.0
+    p = w / w.sum()
+    idx = Q.draw(T(p), count, seed=n, set_id=3, with_replacement=repl)
+    ref = oracle.draw(p, count, n, 3, repl)
+    assert torch.equal(idx.cpu(), torch.tensor(ref))
+
+
+def test_draw_errors_raise_sample_status():
+    p = T(np.array([0.5, 0.0, 0.5]))
+    idx = Q.draw(p, 3, 1, 0)           # only two positive weights
+    with pytest.raises(Q.QcurError) as e:
+        Q.sync_status()
+    assert e.value.status == 5
+    assert (N(idx) == -1).all()
+    Q.draw(T(np.array([0.5, np.nan, 0.5])), 1, 1, 0)
+    with pytest.raises(Q.QcurError):
+        Q.sync_status()
+
+
+def test_probs_zero_matrix_raises_numeric():
+    Q.probs(torch.zeros((4, 5, 6), dtype=torch.float64, device=DEV))
+    with pytest.raises(Q.QcurError) as e:
+        Q.sync_status()
+    assert e.value.status == 6
+
+
+@pytest.mark.parametrize("out_dt", [torch.float64, torch.float32, torch.bfloat16])
+def test_gather_bit_exact(out_dt):
+    rng = np.random.default_rng(9)
+    A = rng.standard_normal((4, 123, 301))
+    I = np.sort(rng.choice(123, 17, replace=False))
+    J = np.sort(rng.choice(301, 29, replace=False))
+    C, R, W = Q.gather(T(A), T(I, torch.int64), T(J, torch.int64), dtype=out_dt)
+    Cr, Rr, Wr = oracle.gather(A, I, J)
+    conv = (lambda x: x) if out_dt == torch.float64 else (
+        lambda x: torch.tensor(x).to(out_dt).to(torch.float64).numpy())
+    assert np.array_equal(N(C), conv(Cr)) and np.array_equal(N(R), conv(Rr)) and np.array_equal(N(W), conv(Wr))
+
+
+def test_gather_out_of_range_flags_arg():
+    A = T(np.ones((4, 5, 5)))
+    Q.gather(A, T(np.array([0, 7]), torch.int64), T(np.array([1]), torch.int64))
+    with pytest.raises(Q.QcurError) as e:
+        Q.sync_status()
+    assert e.value.status == 1
+
+
+# ---------------------------------------------------------------- pinv
+@pytest.mark.parametrize("p,q", [(1, 1), (7, 7), (40, 40), (60, 13), (13, 60), (300, 70), (70, 300), (257, 129)])
+def test_pinv_full_rank(p, q):
+    rng = np.random.default_rng(p * q)
+    X = rng.standard_normal((4, p, q))
+    Xp, rank = Q.pinv(T(X))
+    ref, k = oracle.qpinv(X)
+    assert int(N(rank)[0]) == k == min(p, q)
+    assert rel(N(Xp), ref) < 1e-11
+
+
+@pytest.mark.parametrize("p,q,k", [(40, 40, 10), (90, 50, 7), (50, 90, 7), (200, 150, 30)])
+def test_pinv_exact_rank(p, q, k):
+    rng = np.random.default_rng(p + q + k)
+    X = qmul(rng.standard_normal((4, p, k)), rng.standard_normal((4, k, q)))
+    Xp, rank = Q.pinv(T(X))
+    ref, kr = oracle.qpinv(X)
+    assert int(N(rank)[0]) == kr == k
+    assert rel(N(Xp), ref) < 1e-10
+    G = N(Xp)
+    assert rel(qmul(qmul(X, G), X), X) < 1e-11
+
+
+def test_pinv_max_rank_and_rtol():
+    rng = np.random.default_rng(12)
+    from tests.qhelp import lowrank_svd_form
+    X, _, _ = lowrank_svd_form(30, 20, [9.0, 5.0, 2.0, 1e-2, 1e-9], rng)
+    from oracle.pinv import singular_values
+    sv = singular_values(X)
+    for rtol, mr in [(-1.0, 0), (1e-5, 0), (1e-1, 0), (-1.0, 2)]:
+        Xp, rank = Q.pinv(T(X), rtol, mr)
+        ref, k = oracle.qpinv(X, rtol, mr)
+        assert int(N(rank)[0]) == k
+        # both sides carry ~eps * kappa error in the smallest kept singular pair
+        tol = max(1e-11, 64 * 2.0 ** -52 * sv[0] / sv[k - 1])
+        assert rel(N(Xp), ref) < tol
+
+
+def test_pinv_zero_matrix():
+    Xp, rank = Q.pinv(torch.zeros((4, 6, 4), dtype=torch.float64, device=DEV))
+    assert int(N(rank)[0]) == 0 and not N(Xp).any()
+
+
+# ---------------------------------------------------------------- approx / residual
+def _noisy(m, n, k, seed, noise=1e-3):
+    L, Rt, E = workloads.lowrank_gaussian_factors(m, n, k, seed, noise)
+    return qmul(L, Rt) + E
+
+
+def test_approx_car_f64_matches_checker():
+    A = _noisy(150, 130, 6, 21)
+    rng = np.random.default_rng(1)
+    I = np.sort(rng.choice(150, 24, replace=False))
+    J = np.sort(rng.choice(130, 20, replace=False))
+    C, R, W = oracle.gather(A, I, J)
+    U, B, ranks = Q.approx(T(A), T(C), T(R), T(W), core=Q.CORE_CAR, compute=Q.F64, want_B=True)
+    Ur, kc, kr = oracle.core_car(A, C, R)
+    assert N(ranks).tolist() == [kc, kr]
+    assert rel(N(U), Ur) < 1e-10
+    assert rel(N(B), oracle.cur_product(C, Ur, R)) < cur_tol(C, R)
+
+
+def test_approx_wpinv_plain_workload_full_size():
+    cfg = workloads.WORKLOADS["plain_f64_256"]
+    L, Rt, _ = workloads.lowrank_gaussian_factors(256, 256, 10, cfg["seed"])
+    A = qmul(L, Rt)
+    out = Q.solve(T(A), 40, 40, sampling=Q.UNIFORM, core=Q.CORE_WPINV, compute=Q.F64, seed=cfg["seed"])
+    ref = oracle.solve(A, 40, 40, "uniform", "wpinv", seed=cfg["seed"])
+    assert N(out["J"]).astype(np.int64).tolist() == ref["J"].tolist()
+    assert N(out["I"]).astype(np.int64).tolist() == ref["I"].tolist()
+    assert N(out["ranks"]).tolist() == [10, 10]
+    relerr = float(N(out["residual"])[0]) / np.sqrt(fro2(A))
+    assert relerr < 1e-12
+    # U is unique for the truncated rank; compare the U-invariant product
+    assert rel(qmul(qmul(ref["C"], N(out["U"])), ref["R"]), A) < 1e-12
+
+
+@pytest.mark.parametrize("compute,tol", [(Q.F32, 1e-5), (Q.BF16, 2e-2)])
+@pytest.mark.parametrize("refine", [0, 1])
+def test_approx_car_mixed_precision(compute, tol, refine):
+    A = workloads.color_like(200, 180, 8, seed=5)
+    rng = np.random.default_rng(2)
+    I = np.sort(rng.choice(200, 32, replace=False))
+    J = np.sort(rng.choice(180, 32, replace=False))
+    C, R, W = oracle.gather(A, I, J)
+    Ur, _, _ = oracle.core_car(A, C, R)
+    Br = oracle.cur_product(C, Ur, R)
+    U, B, _ = Q.approx(T(A, torch.float32), T(C, torch.float32), T(R, torch.float32), None,
+                       core=Q.CORE_CAR, compute=compute, refine_steps=refine, want_B=True)
+    if refine == 0:
+        # rounding C^+ and R^+ to the operand precision is amplified by their conditioning
+        u = 2.0 ** -24 if compute == Q.F32 else 2.0 ** -9
+        tol = max(tol, 4 * u * (kappa(C) + kappa(R)))
+    assert rel(N(B), Br) < tol
+
+
+def test_residual_masked_matches_checker():
+    rng = np.random.default_rng(3)
+    A = _noisy(140, 150, 5, 31, 1e-2)
+    C = A[:, :, :18]
+    R = A[:, :20, :]
+    U = rng.standard_normal((4, 18, 20)) * 1e-3
+    mask = (rng.random((140, 150)) < 0.5).astype(np.uint8)
+    fro, E = Q.residual(T(A), T(C), T(U), T(R), mask=torch.tensor(mask, device=DEV), want_E=True, e_scale=2.0)
+    ref = oracle.residual(A, C, U, R, mask)
+    assert abs(float(N(fro)[0]) - ref) <= 1e-12 * ref
+    Er = 2.0 * (A - oracle.cur_product(C, U, R)) * mask[None]
+    assert rel(N(E), Er) < 1e-12
+
+
+# ---------------------------------------------------------------- backward
+@pytest.mark.parametrize("dtype,tol,noise,r,c", [(torch.float64, 1e-9, 1e-2, 12, 10),
+                                                 (torch.float32, 1e-4, 3.0, 16, 8)])
+def test_backward_vjp_and_masked_loss(dtype, tol, noise, r, c):
+    # FP32: a well-conditioned W (noise-dominated), since the pinv adjoint
+    # amplifies rounding by about kappa(W)^2
+    from oracle.grad import cur_vjp, masked_loss_grad, masked_loss
+    rng = np.random.default_rng(4)
+    A = _noisy(96, 80, 4, 41, noise)
+    I = np.sort(rng.choice(96, r, replace=False))
+    J = np.sort(rng.choice(80, c, replace=False))
+    gB = rng.standard_normal(A.shape)
+    mask = (rng.random((96, 80)) < 0.5).astype(np.uint8)
+    It, Jt = T(I, torch.int64), T(J, torch.int64)
+    dA, _ = Q.backward(T(A, dtype), It, Jt, gB=T(gB, dtype))
+    assert rel(N(dA), cur_vjp(A, I, J, gB)) < tol
+    dA, loss = Q.backward(T(A, dtype), It, Jt, mask=torch.tensor(mask, device=DEV))
+    assert rel(N(dA), masked_loss_grad(A, I, J, mask)) < tol
+    lr = masked_loss(A, I, J, mask)
+    assert abs(float(N(loss)[0]) - lr) <= max(tol, 1e-12) * lr
+
+
+def test_backward_repeated_index_flags_arg():
+    A = T(np.random.default_rng(5).standard_normal((4, 10, 10)))
+    Q.backward(A, T(np.array([1, 1, 2]), torch.int64), T(np.array([0, 3, 4]), torch.int64))
+    with pytest.raises(Q.QcurError):
+        Q.sync_status()
