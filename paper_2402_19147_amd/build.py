@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libqcur.so")
-SOURCES = ["api.cpp", "k_elem.hip", "k_draw.hip", "k_qgemm.hip", "k_pinv.hip"]
+SOURCES = ["api.cpp", "k_elem.hip", "k_draw.hip", "k_qgemm.hip", "k_pinv.hip", "k_chol.hip"]
 ARCH = os.environ.get("QCUR_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -116,6 +116,7 @@ PinvPlan pinv_plan(int64_t p, int64_t q) {
   return pl;
 }
 
+// Jacobi (general) path buffers for one matrix.
 struct PinvWs {
   double* Y;
   double* V;
@@ -127,15 +128,51 @@ struct PinvWs {
 
 PinvWs pinv_carve(Bump& b, int64_t p, int64_t q) {
   PinvPlan pl = pinv_plan(p, q);
+  const int64_t pp = pl.pp, qq = pl.qq;
   PinvWs w;
-  w.Y = (double*)b.take((size_t)4 * pl.qq * pl.pp * 8);
-  w.V = (double*)b.take((size_t)4 * pl.qq * pl.qq * 8);
-  w.sig = (double*)b.take((size_t)2 * std::max<int64_t>(pl.qq, 1) * 8);
+  w.Y = (double*)b.take((size_t)4 * qq * pp * 8);
+  w.V = (double*)b.take((size_t)4 * qq * qq * 8);
+  w.sig = (double*)b.take((size_t)2 * std::max<int64_t>(qq, 1) * 8);
   w.flag = (unsigned*)b.take(256);
-  // final product: tall -> (qq x pp), wide -> (pp x qq); K = qq
-  const int64_t M = pl.tall ? pl.qq : pl.pp;
-  const int64_t N = pl.tall ? pl.pp : pl.qq;
-  w.gws_bytes = gemm_workspace(M, N, pl.qq, QCUR_F64);
+  const int64_t M = pl.tall ? qq : pp;
+  const int64_t N = pl.tall ? pp : qq;
+  w.gws_bytes = gemm_workspace(M, N, qq, QCUR_F64);
+  w.gws = b.take(w.gws_bytes);
+  return w;
+}
+
+// CholeskyQR path buffers for a group of nb matrices padded to pp x qq.
+struct GroupWs {
+  int nb;
+  int64_t pp, qq;
+  double *Z, *Q1, *Q, *G, *L, *P1, *P2, *P, *S, *part, *norms;
+  int *fail, *ok;
+  void* gws;
+  size_t gws_bytes;
+};
+
+GroupWs group_carve(Bump& b, int nb, int64_t pp, int64_t qq) {
+  GroupWs w;
+  w.nb = nb;
+  w.pp = pp;
+  w.qq = qq;
+  const size_t zb = (size_t)nb * 4 * pp * qq * 8, gb = (size_t)nb * 4 * qq * qq * 8;
+  w.Z = (double*)b.take(zb);
+  w.Q1 = (double*)b.take(zb);
+  w.Q = (double*)b.take(zb);
+  w.G = (double*)b.take(gb);
+  w.L = (double*)b.take(gb);
+  w.P1 = (double*)b.take(gb);
+  w.P2 = (double*)b.take(gb);
+  w.P = (double*)b.take(gb);
+  w.S = (double*)b.take((size_t)nb * 4 * CHOL_BLOCK * qq * 8);
+  w.part = (double*)b.take((size_t)nb * 256 * 8);
+  w.norms = (double*)b.take((size_t)nb * 4 * 8);
+  w.fail = (int*)b.take((size_t)nb * 4);
+  w.ok = (int*)b.take((size_t)nb * 4);
+  w.gws_bytes = std::max({gemm_workspace(qq, qq, pp, QCUR_F64, nb), gemm_workspace(pp, qq, qq, QCUR_F64, nb),
+                          gemm_workspace(qq, qq, qq, QCUR_F64, nb), gemm_workspace(qq, pp, qq, QCUR_F64),
+                          gemm_workspace(pp, qq, qq, QCUR_F64)});
   w.gws = b.take(w.gws_bytes);
   return w;
 }
@@ -143,24 +180,158 @@ PinvWs pinv_carve(Bump& b, int64_t p, int64_t q) {
 size_t pinv_ws_size(int64_t p, int64_t q) {
   Bump b(nullptr);
   pinv_carve(b, p, q);
+  PinvPlan pl = pinv_plan(p, q);
+  group_carve(b, 1, pl.pp, pl.qq);
   return b.used + 256;
 }
 
 constexpr int MAX_SWEEPS = 40;
 
-// X (any dtype) -> Xp (F64, q x p).
-qcur_status pinv_impl(const Ctx& c, QView X, double rtol, int64_t max_rank, QView Xp, int64_t* rank_out,
-                      PinvWs w) {
-  PinvPlan pl = pinv_plan(X.rows, X.cols);
-  if (rtol < 0) rtol = (double)std::max(pl.p, pl.q) * std::ldexp(1.0, -52);
-  if (pl.qq == 0) {
-    if (rank_out) HIPCHK(hipMemsetAsync(rank_out, 0, sizeof(int64_t), c.stream));
-    return QCUR_OK;
+// view of the (rows x cols) block at (r0, c0) of a dense n x n FP64 matrix
+QView sq_view(double* base, int64_t n, int64_t r0, int64_t c0, int64_t rows, int64_t cols) {
+  return QView{base + r0 * n + c0, rows, cols, n, n * n, QCUR_F64};
+}
+
+BatchSpec same_stride(int nb, int64_t s) {
+  BatchSpec bs;
+  bs.count = nb;
+  bs.sA = bs.sB = bs.sD = s;
+  return bs;
+}
+
+// Blocked Cholesky G = L L^H with the explicit inverse P = L^{-1} for the
+// group's nb matrices (n x n, back to back; G is overwritten).  Diagonal
+// blocks are factored and inverted in LDS; panels, trailing updates and the
+// block rows of P are batched quaternion GEMMs on the matrix cores.
+qcur_status chol_inv(const Ctx& c, GroupWs& w, double* P) {
+  const int64_t n = w.qq, nb = CHOL_BLOCK;
+  const int64_t slab = 4 * n * n;
+  const BatchSpec bs = same_stride(w.nb, slab);
+  double *G = w.G, *L = w.L;
+  HIPCHK(launch_zero(c, P, w.nb * slab));
+  for (int64_t kb = 0; kb < n; kb += nb) {
+    const int64_t wd = std::min(nb, n - kb);
+    const int64_t rest = n - kb - wd;
+    HIPCHK(launch_chol_block(c, G + kb * n + kb, P + kb * n + kb, (int)wd, n, n * n, w.fail, w.nb, slab));
+    if (rest > 0) {
+      QView L21 = sq_view(L, n, kb + wd, kb, rest, wd);
+      HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_H, 1.0, sq_view(G, n, kb + wd, kb, rest, wd),
+                                 sq_view(P, n, kb, kb, wd, wd), 0.0, L21, QCUR_F64, w.gws, w.gws_bytes, bs));
+      HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_H, -1.0, L21, L21, 1.0,
+                                 sq_view(G, n, kb + wd, kb + wd, rest, rest), QCUR_F64, w.gws, w.gws_bytes, bs));
+    }
   }
+  const BatchSpec bsS{w.nb, slab, slab, 4 * nb * n};
+  for (int64_t kb = nb; kb < n; kb += nb) {
+    const int64_t wd = std::min(nb, n - kb);
+    QView Sv{w.S, wd, kb, kb, wd * kb, QCUR_F64};
+    HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_N, 1.0, sq_view(L, n, kb, 0, wd, kb), sq_view(P, n, 0, 0, kb, kb),
+                               0.0, Sv, QCUR_F64, w.gws, w.gws_bytes, bsS));
+    const BatchSpec bsP{w.nb, slab, 4 * nb * n, slab};
+    HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_N, -1.0, sq_view(P, n, kb, kb, wd, wd), Sv, 0.0,
+                               sq_view(P, n, kb, 0, wd, kb), QCUR_F64, w.gws, w.gws_bytes, bsP));
+  }
+  return QCUR_OK;
+}
+
+// CholeskyQR attempt on a group: Z_b = X_b (tall) or X_b^H (wide), padded
+// with zero rows/columns to pp x qq (the padded Gram gets an identity block,
+// which leaves the factors of the real block unchanged).  Two passes give Q
+// orthonormal to working precision (CholeskyQR2); one pass (the normal
+// equations, error ~ eps * kappa^2) is used when the products downstream are
+// FP32 or BF16.  done[b] reports whether the certificate of matrix b held;
+// for those Xp_b and rank_out[b] are written.
+qcur_status pinv_fast_group(const Ctx& c, int nb, const QView* X, double rtol, int64_t max_rank, const QView* Xp,
+                            int64_t* const* rank_out, GroupWs& w, int passes, bool* done) {
+  const int64_t pp = w.pp, qq = w.qq;
+  const int64_t zslab = 4 * pp * qq, gslab = 4 * qq * qq;
+  int64_t pb[MAXB], qb[MAXB];
+  bool tall[MAXB];
+  for (int b = 0; b < nb; ++b) {
+    PinvPlan pl = pinv_plan(X[b].rows, X[b].cols);
+    pb[b] = pl.pp;
+    qb[b] = pl.qq;
+    tall[b] = pl.tall;
+    done[b] = false;
+  }
+  bool padded = false;
+  for (int b = 0; b < nb; ++b) padded |= (pb[b] != pp || qb[b] != qq);
+  HIPCHK(launch_zero_i32(c, w.fail, nb));
+  if (padded) HIPCHK(launch_zero(c, w.Z, nb * zslab));
+  QView Zr[MAXB], Pr[MAXB];
+  for (int b = 0; b < nb; ++b) {
+    Zr[b] = QView{w.Z + b * zslab, pb[b], qb[b], qq, pp * qq, QCUR_F64};
+    HIPCHK(launch_cast(c, X[b], Zr[b], tall[b] ? CAST_COPY : CAST_H));
+  }
+  HIPCHK(launch_sumsq_batch(c, nb, Zr, w.part, w.norms + 0, 4));
+  const BatchSpec bz = same_stride(nb, zslab);
+  BatchSpec bzg;
+  bzg.count = nb;
+  bzg.sA = zslab;
+  bzg.sB = zslab;
+  bzg.sD = gslab;
+  QView Z{w.Z, pp, qq, qq, pp * qq, QCUR_F64};
+  QView Q1{w.Q1, pp, qq, qq, pp * qq, QCUR_F64};
+  QView Q{w.Q, pp, qq, qq, pp * qq, QCUR_F64};
+  QView G{w.G, qq, qq, qq, qq * qq, QCUR_F64};
+  QView P1{w.P1, qq, qq, qq, qq * qq, QCUR_F64};
+  QView P2{w.P2, qq, qq, qq, qq * qq, QCUR_F64};
+  QView P{w.P, qq, qq, qq, qq * qq, QCUR_F64};
+  BatchSpec bzp;  // (pp x qq) . (qq x qq)^H -> pp x qq
+  bzp.count = nb;
+  bzp.sA = zslab;
+  bzp.sB = gslab;
+  bzp.sD = zslab;
+  const BatchSpec bg = same_stride(nb, gslab);
+  // pass 1: G = Z^H Z = L1 L1^H, P1 = L1^{-1}, Q1 = Z L1^{-H}
+  HIPCHK(launch_gemm_batched(c, QCUR_OP_H, QCUR_OP_N, 1.0, Z, Z, 0.0, G, QCUR_F64, w.gws, w.gws_bytes, bzg));
+  if (padded) HIPCHK(launch_pad_identity(c, w.G, qq, gslab, nb, qb));
+  CHK(chol_inv(c, w, w.P1));
+  for (int b = 0; b < nb; ++b) Pr[b] = QView{w.P1 + b * gslab, qb[b], qb[b], qq, qq * qq, QCUR_F64};
+  HIPCHK(launch_sumsq_batch(c, nb, Pr, w.part, w.norms + 1, 4));
+  HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_H, 1.0, Z, P1, 0.0, Q1, QCUR_F64, w.gws, w.gws_bytes, bzp));
+  double* Pf = w.P1;
+  double* Qf = w.Q1;
+  if (passes >= 2) {
+    // pass 2: G = Q1^H Q1 = L2 L2^H;  P = L2^{-1} L1^{-1} = T^{-H} with Z = Q T
+    HIPCHK(launch_gemm_batched(c, QCUR_OP_H, QCUR_OP_N, 1.0, Q1, Q1, 0.0, G, QCUR_F64, w.gws, w.gws_bytes, bzg));
+    if (padded) HIPCHK(launch_pad_identity(c, w.G, qq, gslab, nb, qb));
+    CHK(chol_inv(c, w, w.P2));
+    HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_N, 1.0, P2, P1, 0.0, P, QCUR_F64, w.gws, w.gws_bytes, bg));
+    for (int b = 0; b < nb; ++b) Pr[b] = QView{w.P + b * gslab, qb[b], qb[b], qq, qq * qq, QCUR_F64};
+    HIPCHK(launch_sumsq_batch(c, nb, Pr, w.part, w.norms + 2, 4));
+    HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_H, 1.0, Q1, P2, 0.0, Q, QCUR_F64, w.gws, w.gws_bytes, bzp));
+    Pf = w.P;
+    Qf = w.Q;
+  } else {
+    HIPCHK(launch_sumsq_batch(c, nb, Pr, w.part, w.norms + 2, 4));
+  }
+  HIPCHK(launch_pinv_decide(c, w.norms, w.fail, rtol, max_rank, nb, qb, rank_out, w.ok));
+  int ok[MAXB] = {0, 0, 0, 0};
+  HIPCHK(hipMemcpyAsync(ok, w.ok, sizeof(int) * nb, hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(hipStreamSynchronize(c.stream));
+  // Z^+ = T^{-1} Q^H = P^H Q^H;  for a wide X, X^+ = (Z^+)^H = Q P
+  for (int b = 0; b < nb; ++b) {
+    if (!ok[b]) continue;
+    QView Pv{Pf + b * gslab, qb[b], qb[b], qq, qq * qq, QCUR_F64};
+    QView Qv{Qf + b * zslab, pb[b], qb[b], qq, pp * qq, QCUR_F64};
+    if (tall[b]) {
+      HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_H, 1.0, Pv, Qv, 0.0, Xp[b], QCUR_F64, w.gws, w.gws_bytes));
+    } else {
+      HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Qv, Pv, 0.0, Xp[b], QCUR_F64, w.gws, w.gws_bytes));
+    }
+    done[b] = true;
+  }
+  return QCUR_OK;
+}
+
+// Jacobi path: X (any dtype) -> Xp (F64, q x p).
+qcur_status pinv_jacobi(const Ctx& c, QView X, double rtol, int64_t max_rank, QView Xp, int64_t* rank_out,
+                        PinvWs w) {
+  PinvPlan pl = pinv_plan(X.rows, X.cols);
   const int64_t pp = pl.pp, qq = pl.qq;
   // column rows of the tall working matrix Z (Z = X or X^H)
   QView Yv{w.Y, qq, pp, pp, qq * pp, QCUR_F64};
-  HIPCHK(launch_check_finite(c, X));
   HIPCHK(launch_cast(c, X, Yv, pl.tall ? CAST_T : CAST_CONJ));
   HIPCHK(launch_fill_identity(c, w.V, qq));
   const double tol = std::sqrt((double)pp) * std::ldexp(1.0, -53);
@@ -170,7 +341,7 @@ qcur_status pinv_impl(const Ctx& c, QView X, double rtol, int64_t max_rank, QVie
     const int64_t qpad = (qq + 1) / 2 * 2;
     unsigned host_flag = 1;
     for (int sweep = 0; sweep < MAX_SWEEPS && host_flag; ++sweep) {
-      HIPCHK(hipMemsetAsync(w.flag, 0, sizeof(unsigned), c.stream));
+      HIPCHK(launch_zero_i32(c, (int*)w.flag, 1));
       for (int round = 0; round < qpad - 1; ++round)
         HIPCHK(launch_jacobi_round(c, w.Y, pp, qq, w.V, qpad, round, tol, w.flag));
       HIPCHK(hipMemcpyAsync(&host_flag, w.flag, sizeof(unsigned), hipMemcpyDeviceToHost, c.stream));
@@ -188,6 +359,53 @@ qcur_status pinv_impl(const Ctx& c, QView X, double rtol, int64_t max_rank, QVie
     HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, Ydc, Vcc, 0.0, Xp, QCUR_F64, w.gws, w.gws_bytes));
   }
   return QCUR_OK;
+}
+
+// Pseudoinverses of nb matrices (any dtype) into Xp (F64): small ones by
+// single-workgroup Jacobi, the rest by the CholeskyQR group with a Jacobi
+// fallback for each matrix whose certificate fails.
+qcur_status pinv_group(const Ctx& c, int nb, const QView* X, double rtol, int64_t max_rank, const QView* Xp,
+                       int64_t* const* rank_out, GroupWs& gw, PinvWs jw, int passes) {
+  QView fx[MAXB], fxp[MAXB];
+  int64_t* fr[MAXB];
+  int idx[MAXB];
+  int nf = 0;
+  double rt[MAXB];
+  for (int b = 0; b < nb; ++b) {
+    PinvPlan pl = pinv_plan(X[b].rows, X[b].cols);
+    rt[b] = rtol < 0 ? (double)std::max(pl.p, pl.q) * std::ldexp(1.0, -52) : rtol;
+    if (pl.qq == 0) {
+      if (rank_out[b]) HIPCHK(launch_zero(c, (double*)rank_out[b], 1));
+      continue;
+    }
+    HIPCHK(launch_check_finite(c, X[b]));
+    if (jacobi_small_fits(pl.pp, pl.qq)) {
+      CHK(pinv_jacobi(c, X[b], rt[b], max_rank, Xp[b], rank_out[b], jw));
+      continue;
+    }
+    fx[nf] = X[b];
+    fxp[nf] = Xp[b];
+    fr[nf] = rank_out[b];
+    idx[nf] = b;
+    ++nf;
+  }
+  if (nf == 0) return QCUR_OK;
+  bool done[MAXB];
+  // the certificate uses the largest default tolerance of the group
+  double rg = 0.0;
+  for (int f = 0; f < nf; ++f) rg = std::max(rg, rt[idx[f]]);
+  GroupWs w = gw;
+  w.nb = nf;
+  CHK(pinv_fast_group(c, nf, fx, rg, max_rank, fxp, fr, w, passes, done));
+  for (int f = 0; f < nf; ++f)
+    if (!done[f]) CHK(pinv_jacobi(c, fx[f], rt[idx[f]], max_rank, fxp[f], fr[f], jw));
+  return QCUR_OK;
+}
+
+qcur_status pinv_impl(const Ctx& c, QView X, double rtol, int64_t max_rank, QView Xp, int64_t* rank_out,
+                      PinvWs jw, GroupWs gw, int passes = 2) {
+  int64_t* ro[1] = {rank_out};
+  return pinv_group(c, 1, &X, rtol, max_rank, &Xp, ro, gw, jw, passes);
 }
 
 // Returns X itself when it already has dtype dt, else a converted copy.
@@ -217,8 +435,10 @@ qcur_status approx_run(const Ctx& c, const ApproxArgs& a, int64_t m, int64_t n, 
     // U = W^+ (c x r), FP64, then converted to the output dtype
     QView U64 = a.U.dt == QCUR_F64 ? a.U : b.mat(cc, r, QCUR_F64);
     PinvWs w = pinv_carve(b, r, cc);
+    PinvPlan pl = pinv_plan(r, cc);
+    GroupWs gw = group_carve(b, 1, pl.pp, pl.qq);
     if (!count_only) {
-      CHK(pinv_impl(c, a.W, a.rtol, a.max_rank, U64, a.rank_out, w));
+      CHK(pinv_impl(c, a.W, a.rtol, a.max_rank, U64, a.rank_out, w, gw));
       if (a.rank_out) HIPCHK(hipMemcpyAsync(a.rank_out + 1, a.rank_out, 8, hipMemcpyDeviceToDevice, c.stream));
       if (U64.p != a.U.p) HIPCHK(launch_cast(c, U64, a.U, CAST_COPY));
     }
@@ -227,17 +447,20 @@ qcur_status approx_run(const Ctx& c, const ApproxArgs& a, int64_t m, int64_t n, 
     QView Cp = b.mat(cc, m, QCUR_F64);
     QView Rp = b.mat(n, r, QCUR_F64);
     {
+      // both pseudoinverses run as one batched group
+      PinvPlan pc = pinv_plan(m, cc), pr = pinv_plan(r, n);
+      const int64_t pp = std::max(pc.pp, pr.pp), qq = std::max(pc.qq, pr.qq);
       Bump pb = b;
-      PinvWs w1 = pinv_carve(pb, m, cc);
-      size_t u1 = pb.used;
-      Bump pb2 = b;
-      PinvWs w2 = pinv_carve(pb2, r, n);
-      size_t u2 = pb2.used;
+      PinvWs jw = pinv_carve(pb, pp, qq);
+      GroupWs gw = group_carve(pb, 2, pp, qq);
       if (!count_only) {
-        CHK(pinv_impl(c, a.C, a.rtol, a.max_rank, Cp, a.rank_out, w1));
-        CHK(pinv_impl(c, a.R, a.rtol, a.max_rank, Rp, a.rank_out ? a.rank_out + 1 : nullptr, w2));
+        // one CholeskyQR pass suffices when the products are FP32/BF16
+        const int passes = a.compute == QCUR_F64 ? 2 : 1;
+        QView xs[2] = {a.C, a.R}, xps[2] = {Cp, Rp};
+        int64_t* ro[2] = {a.rank_out, a.rank_out ? a.rank_out + 1 : nullptr};
+        CHK(pinv_group(c, 2, xs, a.rtol, a.max_rank, xps, ro, gw, jw, passes));
       }
-      b.used = std::max(u1, u2);
+      b.used = pb.used;
     }
     // operands in the product dtype
     QView Ax = as_dtype(c, a.A, idt, b, count_only, &err);
@@ -390,6 +613,8 @@ qcur_status backward_run(const Ctx& c, const BwdArgs& a, Bump& b, bool count_onl
   const Bump shared = b;
   Bump t1 = shared;
   PinvWs pw = pinv_carve(t1, r, cc);
+  PinvPlan wpl = pinv_plan(r, cc);
+  GroupWs pgw = group_carve(t1, 1, wpl.pp, wpl.qq);
   Bump t2 = shared;
   double* lossbuf = (double*)t2.take(8);
   CHK(residual_run(c, a.A, C, Ux, R, a.mask, a.mask_ld, dt, nullptr, 0, nullptr, 0.0, t2, true));
@@ -400,7 +625,7 @@ qcur_status backward_run(const Ctx& c, const BwdArgs& a, Bump& b, bool count_onl
   HIPCHK(launch_inverse_map(c, a.I, r, m, iinv));
   HIPCHK(launch_inverse_map(c, a.J, cc, n, jinv));
   // U = W^+ recomputed (not stored by the forward pass)
-  CHK(pinv_impl(c, W, a.rtol, a.max_rank, U64, nullptr, pw));
+  CHK(pinv_impl(c, W, a.rtol, a.max_rank, U64, nullptr, pw, pgw));
   if (Ux.p != U64.p) HIPCHK(launch_cast(c, U64, Ux, CAST_COPY));
   double sgn;
   QView Gb;
@@ -660,7 +885,9 @@ qcur_status qcur_pinv(qcur_handle h, const qcur_qmat* X, double rtol, int64_t ma
   CHK(check_handle(h));
   Bump b(ws);
   PinvWs w = pinv_carve(b, X->rows, X->cols);
-  return pinv_impl(h->c, view_of(*X), rtol, max_rank, view_of(*Xp), rank_out, w);
+  PinvPlan pl = pinv_plan(X->rows, X->cols);
+  GroupWs gw = group_carve(b, 1, pl.pp, pl.qq);
+  return pinv_impl(h->c, view_of(*X), rtol, max_rank, view_of(*Xp), rank_out, w, gw);
 }
 
 // ---- gemm

@@ -38,22 +38,42 @@ __device__ inline uint64_t wave_sum_u64(uint64_t v, bool& ovf) {
   return v;
 }
 
+// 64-bit DPP move of lane data (lanes outside the pattern read 0).
+template <int CTRL, int ROWS>
+__device__ inline uint64_t dpp_u64(uint64_t v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, ROWS, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, ROWS, 0xf, true);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// Inclusive wave-wide prefix sum of 64-bit integers: shifts by 1, 2, 4, 8
+// within rows of 16 lanes, then the row totals broadcast into rows 1, 3
+// (lane 15) and rows 2, 3 (lane 31).
+__device__ inline uint64_t wave_incl_scan_u64(uint64_t x) {
+  x += dpp_u64<0x111, 0xf>(x);  // row_shr:1
+  x += dpp_u64<0x112, 0xf>(x);  // row_shr:2
+  x += dpp_u64<0x114, 0xf>(x);  // row_shr:4
+  x += dpp_u64<0x118, 0xf>(x);  // row_shr:8
+  x += dpp_u64<0x142, 0xa>(x);  // row_bcast:15
+  x += dpp_u64<0x143, 0xc>(x);  // row_bcast:31
+  return x;
+}
+
+__device__ inline uint64_t readlane_u64(uint64_t v, int k) {
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, k);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), k);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // Returns the first lane whose inclusive prefix of v exceeds tau and lowers
 // tau by the exclusive prefix of that lane.
-__device__ inline int select_lane(uint64_t v, uint64_t& tau, int lane) {
-  uint64_t x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    uint64_t y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  unsigned long long mask = __ballot(x > tau);
+__device__ inline int select_lane(uint64_t v, uint64_t& tau) {
+  const uint64_t x = wave_incl_scan_u64(v);
+  const unsigned long long mask = __ballot(x > tau);
   // the level sums are kept consistent, so some lane always qualifies; lane 0
   // is a defensive fallback that keeps every index in range
-  int k = mask ? __ffsll((unsigned long long)mask) - 1 : 0;
-  uint64_t incl = __shfl(x, k, 64);
-  uint64_t vk = __shfl(v, k, 64);
-  tau -= incl - vk;
+  const int k = mask ? __ffsll((unsigned long long)mask) - 1 : 0;
+  tau -= readlane_u64(x, k) - readlane_u64(v, k);
   return k;
 }
 
@@ -131,37 +151,39 @@ __global__ __launch_bounds__(DRAW_THREADS) void k_draw(const double* __restrict_
     return;
   }
 
-  // the draws, one wave
+  // the draws, one wave.  Lane 0 updates the tree; the memory clobber at the
+  // end of each draw makes every lane reload it (LDS operations of one wave
+  // complete in order).
   if (wave == 0) {
-    volatile uint64_t* vwl = wl;
-    volatile uint64_t* vL1 = L1;
-    volatile uint64_t* vL2 = L2;
-    volatile uint32_t* vcnt = cnt;
     uint64_t T = total;
     const uint64_t base = (set_id & 0xFFFFFFFFull) << 32;
     for (int64_t t = 0; t < count; ++t) {
       const uint64_t u = splitmix64_nth(seed, base + (uint64_t)t);
       uint64_t tau = __umul64hi(u, T);
-      uint64_t v = lane < nsb ? vL2[lane] : 0ull;
-      const int sb = select_lane(v, tau, lane);
+      int sb = 0;
+      if (nsb > 1) {
+        const uint64_t v2 = lane < nsb ? L2[lane] : 0ull;
+        sb = select_lane(v2, tau);
+      }
       const int64_t b0 = (int64_t)sb * 64;
-      v = (b0 + lane < nb) ? vL1[b0 + lane] : 0ull;
-      const int64_t b = b0 + select_lane(v, tau, lane);
-      const uint64_t raw = vwl[b * 64 + lane];
-      v = (raw & TAKEN) ? 0ull : raw;
-      const int64_t j = b * 64 + select_lane(v, tau, lane);
+      const uint64_t v1 = (b0 + lane < nb) ? L1[b0 + lane] : 0ull;
+      const int64_t b = b0 + select_lane(v1, tau);
+      const uint64_t raw = wl[b * 64 + lane];
+      const uint64_t v0 = (raw & TAKEN) ? 0ull : raw;
+      const int e = select_lane(v0, tau);
+      const int64_t j = b * 64 + e;
+      const uint64_t wj = readlane_u64(v0, e);
       if (lane == 0) {
         if (repl) {
-          vcnt[j] = vcnt[j] + 1u;
+          cnt[j] = cnt[j] + 1u;
         } else {
-          const uint64_t w = vwl[j];
-          vwl[j] = w | TAKEN;
-          vL1[b] = vL1[b] - w;
-          vL2[sb] = vL2[sb] - w;
+          wl[j] = wj | TAKEN;
+          L1[b] = L1[b] - wj;
+          L2[sb] = L2[sb] - wj;
         }
       }
-      if (!repl) T -= __shfl(v, (int)(j - b * 64), 64);
-      __builtin_amdgcn_wave_barrier();
+      if (!repl) T -= wj;
+      __asm__ __volatile__("" ::: "memory");
     }
   }
   __syncthreads();

@@ -64,11 +64,13 @@ __global__ __launch_bounds__(256) void k_probs_partials(const T* __restrict__ A,
   if (j < n) colpart[(int64_t)blockIdx.y * n + j] = cacc;
 }
 
+// Row tiles of rb rows: at most 64 row tiles per column (one wave folds them),
+// and enough tiles to cover the chip when the matrix is large.
 void probs_grid(int64_t m, int64_t n, int* rb, int* nrb, int* ncb) {
   int64_t cb = (n + 255) / 256;
-  int r = 64;
-  while (r > 4 && ((m + r - 1) / r) * cb < 1024) r >>= 1;
-  *rb = r;
+  int64_t r = std::max<int64_t>(4, (m + 63) / 64);
+  while (r > 4 && ((m + r - 1) / r) * cb < 1024 && (m + r / 2 - 1) / (r / 2) <= 64) r >>= 1;
+  *rb = (int)r;
   *nrb = (int)((m + r - 1) / r);
   *ncb = (int)cb;
 }
@@ -92,21 +94,24 @@ hipError_t launch_probs_partials(const Ctx& c, QView A, double* colpart, double*
   return hipGetLastError();
 }
 
-// probs, pass 2: col2[j] = sum over row tiles, row2[i] = sum over column tiles
-// (fixed order), written into p and q.
-__global__ void k_probs_fold(int64_t m, int64_t n, const double* __restrict__ colpart,
-                             const double* __restrict__ rowpart, int nrb, int ncb, double* p,
-                             double* q) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// probs, pass 2: col2[j] = sum over row tiles, row2[i] = sum over column
+// tiles, one wave per output (lane-strided partial sums, then a fixed
+// xor-tree), written into p and q.
+__global__ __launch_bounds__(256) void k_probs_fold(int64_t m, int64_t n, const double* __restrict__ colpart,
+                                                    const double* __restrict__ rowpart, int nrb, int ncb,
+                                                    double* p, double* q) {
+  const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (t >= n + m) return;
+  double s = 0.0;
   if (t < n) {
-    double s = 0.0;
-    for (int r = 0; r < nrb; ++r) s += colpart[(int64_t)r * n + t];
-    p[t] = s;
-  } else if (t < n + m) {
-    int64_t i = t - n;
-    double s = 0.0;
-    for (int b = 0; b < ncb; ++b) s += rowpart[(int64_t)b * m + i];
-    q[i] = s;
+    for (int r = lane; r < nrb; r += 64) s += colpart[(int64_t)r * n + t];
+  } else {
+    for (int b = lane; b < ncb; b += 64) s += rowpart[(int64_t)b * m + (t - n)];
+  }
+  s = wave_sum(s);
+  if (lane == 0) {
+    if (t < n) p[t] = s; else q[t - n] = s;
   }
 }
 
@@ -157,7 +162,7 @@ hipError_t launch_probs_finish(const Ctx& c, int64_t m, int64_t n, const double*
   }
   if (have) {
     int64_t tot = m + n;
-    hipLaunchKernelGGL(k_probs_fold, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c.stream, m, n,
+    hipLaunchKernelGGL(k_probs_fold, dim3((unsigned)((tot + 3) / 4)), dim3(256), 0, c.stream, m, n,
                        colpart, rowpart, nrb, ncb, pp, qq);
     if (sampling == QCUR_UNIFORM) {
       hipLaunchKernelGGL(k_probs_norm, dim3(1), dim3(1024), 0, c.stream, m, n, (int)QCUR_LENGTH, 1, pp,

@@ -31,7 +31,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 64, BN = 64, NT = 256;
+constexpr int NT = 256;
 
 template <int DT> struct MT;
 template <> struct MT<QCUR_F64> {
@@ -89,10 +89,18 @@ struct GemmArgs {
   int64_t ldb, psb;
   void* D;
   int64_t ldd, psd;
-  int64_t M, N, K;
+  int64_t M, N, K;  // grid extents (the largest problem of a batch)
   int opA, opB;
   double alpha, beta;
   int ktiles_per_split;
+  int splits;
+  // batches: problem b uses pointers offset by b * stride and, when the dims
+  // arrays are given, its own (M, N, K) <= the grid extents
+  int batch;
+  int64_t sA, sB, sD, sR0, sE, sMask;
+  const int* bM;
+  const int* bN;
+  const int* bK;
   // residual epilogue
   const void* R0;  // the matrix subtracted from (A of the residual)
   int r0dt;
@@ -111,7 +119,7 @@ enum { EPI_STORE = 0, EPI_PARTIAL = 1, EPI_RESID = 2 };
 // LDS layouts.  f32/f64: k-major rows [k][i] (A) and [k][j] (B) so that the
 // 16 lanes of an MFMA operand read 16 consecutive elements.  bf16: [i][k]
 // and [j][k] so that each lane reads its 8 consecutive k values at once.
-template <int DT> struct Smem {
+template <int DT, int BM, int BN> struct Smem {
   typedef typename MT<DT>::In In;
   static constexpr int BK = MT<DT>::BK, PAD = MT<DT>::PAD;
   static constexpr bool KMAJ = (DT != QCUR_BF16);
@@ -121,28 +129,33 @@ template <int DT> struct Smem {
   In b[4][BR][BC];
 };
 
-template <int DT, int EPI>
-__global__ __launch_bounds__(NT) void k_qgemm(GemmArgs g) {
+template <int DT, int EPI, int BM, int BN>
+__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile_m, int64_t tile_n, int split,
+                                          int64_t part_index, Smem<DT, BM, BN>& sm) {
   typedef MT<DT> T;
   typedef typename T::In In;
   typedef typename T::AccV AccV;
   typedef typename T::Frag Frag;
   constexpr int BK = T::BK;
-  constexpr bool KMAJ = Smem<DT>::KMAJ;
+  constexpr bool KMAJ = Smem<DT, BM, BN>::KMAJ;
   constexpr int EA = BM * BK / NT;  // elements per thread per plane
   constexpr int EB = BK * BN / NT;
-  __shared__ Smem<DT> sm;
+  constexpr int XB = BM / 32, YB = BN / 32;  // MFMA 16x16 blocks per wave (2 x 2 waves)
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  const int64_t bm = (int64_t)blockIdx.y * BM, bn = (int64_t)blockIdx.x * BN;
-  const In* __restrict__ Ag = (const In*)g.A;
-  const In* __restrict__ Bg = (const In*)g.B;
+  const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+  const int64_t bm = tile_m * BM, bn = tile_n * BN;
+  const int64_t M = g.bM ? (int64_t)g.bM[b] : g.M;
+  const int64_t N = g.bN ? (int64_t)g.bN[b] : g.N;
+  const int64_t K = g.bK ? (int64_t)g.bK[b] : g.K;
+  if (EPI != EPI_RESID && (bm >= M || bn >= N)) return;  // uniform over the workgroup
+  const In* __restrict__ Ag = (const In*)g.A + (int64_t)b * g.sA;
+  const In* __restrict__ Bg = (const In*)g.B + (int64_t)b * g.sB;
 
-  const int64_t ktiles = (g.K + BK - 1) / BK;
-  const int64_t kt0 = (int64_t)blockIdx.z * g.ktiles_per_split;
+  const int64_t ktiles = (K + BK - 1) / BK;
+  const int64_t kt0 = (int64_t)split * g.ktiles_per_split;
   const int64_t kt1 = min(ktiles, kt0 + g.ktiles_per_split);
 
   In ra[4][EA], rb[4][EB];
@@ -155,7 +168,7 @@ __global__ __launch_bounds__(NT) void k_qgemm(GemmArgs g) {
       int i, k;
       if (g.opA == QCUR_OP_N) { i = e / BK; k = e % BK; } else { i = e % BM; k = e / BM; }
       const int64_t gi = bm + i, gk = k0 + k;
-      const bool ok = gi < g.M && gk < g.K;
+      const bool ok = gi < M && gk < K;
       const int64_t off = (g.opA == QCUR_OP_N) ? gi * g.lda + gk : gk * g.lda + gi;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -170,7 +183,7 @@ __global__ __launch_bounds__(NT) void k_qgemm(GemmArgs g) {
       int k, j;
       if (g.opB == QCUR_OP_N) { k = e / BN; j = e % BN; } else { k = e % BK; j = e / BK; }
       const int64_t gk = k0 + k, gj = bn + j;
-      const bool ok = gk < g.K && gj < g.N;
+      const bool ok = gk < K && gj < N;
       const int64_t off = (g.opB == QCUR_OP_N) ? gk * g.ldb + gj : gj * g.ldb + gk;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -203,13 +216,13 @@ __global__ __launch_bounds__(NT) void k_qgemm(GemmArgs g) {
     }
   };
 
-  AccV acc[4][2][2];
+  AccV acc[4][XB][YB];
 #pragma unroll
   for (int p = 0; p < 4; ++p)
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < XB; ++x)
 #pragma unroll
-      for (int y = 0; y < 2; ++y) acc[p][x][y] = (AccV){0, 0, 0, 0};
+      for (int y = 0; y < YB; ++y) acc[p][x][y] = (AccV){0, 0, 0, 0};
 
   if (kt0 < kt1) load_tiles(kt0);
   for (int64_t kt = kt0; kt < kt1; ++kt) {
@@ -219,28 +232,31 @@ __global__ __launch_bounds__(NT) void k_qgemm(GemmArgs g) {
     if (kt + 1 < kt1) load_tiles(kt + 1);
 #pragma unroll
     for (int kk = 0; kk < BK / T::KM; ++kk) {
-      Frag a[4][2], na[4][2], b[4][2];
+      Frag a[4][XB], na[4][XB], b[4][YB];
 #pragma unroll
-      for (int x = 0; x < 2; ++x) {
+      for (int x = 0; x < XB; ++x) {
         const int ii = wm + x * 16 + (lane & 15);
-        const int jj = wn + x * 16 + (lane & 15);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          if constexpr (KMAJ) {
-            a[q][x] = sm.a[q][kk * 4 + (lane >> 4)][ii];
-            b[q][x] = sm.b[q][kk * 4 + (lane >> 4)][jj];
-          } else {
-            a[q][x] = *(const Frag*)&sm.a[q][ii][(lane >> 4) * 8];
-            b[q][x] = *(const Frag*)&sm.b[q][jj][(lane >> 4) * 8];
-          }
+          if constexpr (KMAJ) a[q][x] = sm.a[q][kk * 4 + (lane >> 4)][ii];
+          else a[q][x] = *(const Frag*)&sm.a[q][ii][(lane >> 4) * 8];
         }
 #pragma unroll
         for (int q = 1; q < 4; ++q) na[q][x] = T::neg(a[q][x]);
       }
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+      for (int y = 0; y < YB; ++y) {
+        const int jj = wn + y * 16 + (lane & 15);
 #pragma unroll
-        for (int y = 0; y < 2; ++y) {
+        for (int q = 0; q < 4; ++q) {
+          if constexpr (KMAJ) b[q][y] = sm.b[q][kk * 4 + (lane >> 4)][jj];
+          else b[q][y] = *(const Frag*)&sm.b[q][jj][(lane >> 4) * 8];
+        }
+      }
+#pragma unroll
+      for (int x = 0; x < XB; ++x)
+#pragma unroll
+        for (int y = 0; y < YB; ++y) {
           // plane 0: A0B0 - A1B1 - A2B2 - A3B3
           acc[0][x][y] = T::mfma(a[0][x], b[0][y], acc[0][x][y]);
           acc[0][x][y] = T::mfma(na[1][x], b[1][y], acc[0][x][y]);
@@ -270,21 +286,22 @@ __global__ __launch_bounds__(NT) void k_qgemm(GemmArgs g) {
   if constexpr (EPI == EPI_RESID) {
     double sq = 0.0;
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < XB; ++x)
 #pragma unroll
-      for (int y = 0; y < 2; ++y)
+      for (int y = 0; y < YB; ++y)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int64_t i = bm + wm + x * 16 + T::out_row(lane, r);
           const int64_t j = bn + wn + y * 16 + (lane & 15);
-          if (i < g.M && j < g.N) {
-            const bool keep = g.mask ? (g.mask[i * g.mask_ld + j] != 0) : true;
+          if (i < M && j < N) {
+            const bool keep = g.mask ? (g.mask[b * g.sMask + i * g.mask_ld + j] != 0) : true;
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
-              double d = load_as_double(g.R0, g.r0dt, i * g.r0ld + j + p * g.r0ps) - (double)acc[p][x][y][r];
+              double d = load_as_double(g.R0, g.r0dt, b * g.sR0 + i * g.r0ld + j + p * g.r0ps) -
+                         (double)acc[p][x][y][r];
               if (!keep) d = 0.0;
               sq += d * d;
-              if (g.E) store_from_double(g.E, g.edt, i * g.eld + j + p * g.eps, g.e_scale * d);
+              if (g.E) store_from_double(g.E, g.edt, b * g.sE + i * g.eld + j + p * g.eps, g.e_scale * d);
             }
           }
         }
@@ -293,24 +310,22 @@ __global__ __launch_bounds__(NT) void k_qgemm(GemmArgs g) {
     __shared__ double wpart[4];
     if (lane == 0) wpart[wave] = sq;
     __syncthreads();
-    if (tid == 0) {
-      const int64_t blin = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-      g.partials[blin] = ((wpart[0] + wpart[1]) + wpart[2]) + wpart[3];
-    }
+    if (tid == 0) g.partials[part_index] = ((wpart[0] + wpart[1]) + wpart[2]) + wpart[3];
   } else {
     typedef typename T::Acc Acc;
     Acc* Dg = (Acc*)g.D;
     int64_t ps = g.psd, ld = g.ldd;
-    if (EPI == EPI_PARTIAL) Dg += (int64_t)blockIdx.z * 4 * ps;
+    if (EPI == EPI_PARTIAL) Dg += ((int64_t)b * g.splits + split) * 4 * ps;
+    else Dg += (int64_t)b * g.sD;
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < XB; ++x)
 #pragma unroll
-      for (int y = 0; y < 2; ++y)
+      for (int y = 0; y < YB; ++y)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int64_t i = bm + wm + x * 16 + T::out_row(lane, r);
           const int64_t j = bn + wn + y * 16 + (lane & 15);
-          if (i < g.M && j < g.N) {
+          if (i < M && j < N) {
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
               const int64_t o = i * ld + j + p * ps;
@@ -327,18 +342,33 @@ __global__ __launch_bounds__(NT) void k_qgemm(GemmArgs g) {
   }
 }
 
+// grid: x = column tiles, y = row tiles, z = batch * splits
+template <int DT, int EPI, int BM, int BN>
+__global__ __launch_bounds__(NT) void k_qgemm(GemmArgs g) {
+  __shared__ Smem<DT, BM, BN> sm;
+  const int b = blockIdx.z / g.splits, split = blockIdx.z % g.splits;
+  const int64_t tiles = (int64_t)gridDim.x * gridDim.y;
+  gemm_tile<DT, EPI, BM, BN>(g, b, blockIdx.y, blockIdx.x, split,
+                             (int64_t)b * tiles + (int64_t)blockIdx.y * gridDim.x + blockIdx.x, sm);
+}
+
 // Split-K reduction: D = alpha * sum_z P[z] + beta * D, z in fixed order.
 template <typename Acc>
-__global__ void k_splitk_reduce(const Acc* __restrict__ P, int splits, int64_t M, int64_t N, double alpha,
-                                double beta, Acc* D, int64_t ldd, int64_t psd) {
+__global__ void k_splitk_reduce(const Acc* __restrict__ Pall, int splits, int64_t Mx, int64_t Nx, double alpha,
+                                double beta, Acc* Dall, int64_t ldd, int64_t psd, int64_t sD, const int* bM,
+                                const int* bN) {
+  const int b = blockIdx.z;
+  const int64_t M = bM ? bM[b] : Mx, N = bN ? bN[b] : Nx;
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (j >= N) return;
-  const int64_t MN = M * N;
+  const int64_t MN = Mx * Nx;
+  const Acc* P = Pall + (int64_t)b * splits * 4 * MN;
+  Acc* D = Dall + (int64_t)b * sD;
   for (int64_t i = blockIdx.y; i < M; i += gridDim.y) {
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       double s = 0.0;
-      for (int z = 0; z < splits; ++z) s += (double)P[(int64_t)z * 4 * MN + p * MN + i * N + j];
+      for (int z = 0; z < splits; ++z) s += (double)P[(int64_t)z * 4 * MN + p * MN + i * Nx + j];
       const int64_t o = i * ldd + j + p * psd;
       double v = alpha * s;
       if (beta != 0.0) v += beta * (double)D[o];
@@ -347,54 +377,80 @@ __global__ void k_splitk_reduce(const Acc* __restrict__ P, int splits, int64_t M
   }
 }
 
-static int choose_splits(int64_t M, int64_t N, int64_t K, int bk) {
-  const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+// Tile edge: 64 x 64 quaternion tiles, or 32 x 32 when 64-tiles would leave
+// most of the 256 compute units idle.
+static int tile_of(int64_t M, int64_t N) {
+  const int64_t t64 = ((M + 63) / 64) * ((N + 63) / 64);
+  return t64 >= 192 ? 64 : 32;
+}
+
+static int choose_splits(int64_t M, int64_t N, int64_t K, int bk, int tile) {
+  const int64_t tiles = ((M + tile - 1) / tile) * ((N + tile - 1) / tile);
   const int64_t kt = (K + bk - 1) / bk;
+  // split K until the grid covers the chip twice over, keeping >= 2 K-slices per split
   int s = 1;
-  while (s < 16 && tiles * s < 512 && kt / (s * 2) >= 8) s *= 2;
+  while (s < 32 && tiles * s < 512 && kt / (s * 2) >= 2) s *= 2;
   return s;
 }
 
 static int bk_of(int compute) { return compute == QCUR_BF16 ? 32 : 16; }
 static size_t acc_size(int compute) { return compute == QCUR_F64 ? 8 : 4; }
 
-size_t gemm_workspace(int64_t M, int64_t N, int64_t K, int compute) {
-  const int s = choose_splits(M, N, K, bk_of(compute));
+size_t gemm_workspace(int64_t M, int64_t N, int64_t K, int compute, int batch) {
+  const int s = choose_splits(M, N, K, bk_of(compute), tile_of(M, N));
   if (s <= 1) return 0;
-  return (size_t)s * 4 * (size_t)M * (size_t)N * acc_size(compute);
+  return (size_t)batch * s * 4 * (size_t)M * (size_t)N * acc_size(compute);
 }
 
-template <int DT>
-static hipError_t gemm_dt(const Ctx& c, GemmArgs g, void* ws, size_t ws_bytes) {
+template <int DT, int TILE>
+static hipError_t gemm_dt_tile(const Ctx& c, GemmArgs g, void* ws, size_t ws_bytes) {
   constexpr int BK = MT<DT>::BK;
   const int64_t kt = (g.K + BK - 1) / BK;
-  int splits = choose_splits(g.M, g.N, g.K, BK);
-  const size_t need = (size_t)splits * 4 * (size_t)g.M * (size_t)g.N * acc_size(DT);
+  int splits = choose_splits(g.M, g.N, g.K, BK, TILE);
+  const size_t need = (size_t)g.batch * splits * 4 * (size_t)g.M * (size_t)g.N * acc_size(DT);
   if (splits > 1 && (ws == nullptr || ws_bytes < need)) splits = 1;
-  dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM), 1);
+  dim3 grid((unsigned)((g.N + TILE - 1) / TILE), (unsigned)((g.M + TILE - 1) / TILE), 1);
   if (splits == 1) {
     g.ktiles_per_split = (int)kt;
-    hipLaunchKernelGGL((k_qgemm<DT, EPI_STORE>), grid, dim3(NT), 0, c.stream, g);
+    g.splits = 1;
+    grid.z = g.batch;
+    hipLaunchKernelGGL((k_qgemm<DT, EPI_STORE, TILE, TILE>), grid, dim3(NT), 0, c.stream, g);
     return hipGetLastError();
   }
   const int per = (int)((kt + splits - 1) / splits);
   splits = (int)((kt + per - 1) / per);
-  grid.z = splits;
+  grid.z = g.batch * splits;
   g.ktiles_per_split = per;
+  g.splits = splits;
   typedef typename MT<DT>::Acc Acc;
   GemmArgs gp = g;
   gp.D = ws;
   gp.ldd = g.N;
   gp.psd = g.M * g.N;
-  hipLaunchKernelGGL((k_qgemm<DT, EPI_PARTIAL>), grid, dim3(NT), 0, c.stream, gp);
-  hipLaunchKernelGGL(k_splitk_reduce<Acc>, dim3((unsigned)((g.N + 255) / 256), (unsigned)std::min<int64_t>(g.M, 65535)), dim3(256), 0,
-                     c.stream, (const Acc*)ws, splits, g.M, g.N, g.alpha, g.beta, (Acc*)g.D, g.ldd, g.psd);
+  hipLaunchKernelGGL((k_qgemm<DT, EPI_PARTIAL, TILE, TILE>), grid, dim3(NT), 0, c.stream, gp);
+  hipLaunchKernelGGL(k_splitk_reduce<Acc>,
+                     dim3((unsigned)((g.N + 255) / 256), (unsigned)std::min<int64_t>(g.M, 65535), (unsigned)g.batch),
+                     dim3(256), 0, c.stream, (const Acc*)ws, splits, g.M, g.N, g.alpha, g.beta, (Acc*)g.D, g.ldd,
+                     g.psd, g.sD, g.bM, g.bN);
   return hipGetLastError();
 }
 
-hipError_t launch_gemm(const Ctx& c, int opA, int opB, double alpha, QView A, QView B, double beta, QView D,
-                       int compute, void* ws, size_t ws_bytes) {
+template <int DT>
+static hipError_t gemm_dt(const Ctx& c, GemmArgs g, void* ws, size_t ws_bytes) {
+  if (tile_of(g.M, g.N) == 64) return gemm_dt_tile<DT, 64>(c, g, ws, ws_bytes);
+  return gemm_dt_tile<DT, 32>(c, g, ws, ws_bytes);
+}
+
+hipError_t launch_gemm_batched(const Ctx& c, int opA, int opB, double alpha, QView A, QView B, double beta,
+                               QView D, int compute, void* ws, size_t ws_bytes, const BatchSpec& bs) {
   GemmArgs g = {};
+  g.batch = bs.count;
+  g.sA = bs.sA;
+  g.sB = bs.sB;
+  g.sD = bs.sD;
+  g.bM = bs.M;
+  g.bN = bs.N;
+  g.bK = bs.K;
   g.A = A.p; g.lda = A.ld; g.psa = A.ps;
   g.B = B.p; g.ldb = B.ld; g.psb = B.ps;
   g.D = D.p; g.ldd = D.ld; g.psd = D.ps;
@@ -412,7 +468,12 @@ hipError_t launch_gemm(const Ctx& c, int opA, int opB, double alpha, QView A, QV
   }
 }
 
-size_t residual_tiles(int64_t m, int64_t n) { return (size_t)((m + BM - 1) / BM) * (size_t)((n + BN - 1) / BN); }
+hipError_t launch_gemm(const Ctx& c, int opA, int opB, double alpha, QView A, QView B, double beta, QView D,
+                       int compute, void* ws, size_t ws_bytes) {
+  return launch_gemm_batched(c, opA, opB, alpha, A, B, beta, D, compute, ws, ws_bytes, BatchSpec{});
+}
+
+size_t residual_tiles(int64_t m, int64_t n) { return (size_t)((m + 63) / 64) * (size_t)((n + 63) / 64); }
 
 hipError_t launch_residual_gemm(const Ctx& c, QView A, QView B1, QView R, const uint8_t* mask, int64_t mask_ld,
                                 int compute, double* partials, QView* E, double e_scale) {
@@ -425,23 +486,26 @@ hipError_t launch_residual_gemm(const Ctx& c, QView A, QView B1, QView R, const 
   g.R0 = A.p; g.r0dt = A.dt; g.r0ld = A.ld; g.r0ps = A.ps;
   g.mask = mask; g.mask_ld = mask_ld;
   g.partials = partials;
+  g.batch = 1;
+  g.splits = 1;
   if (E) { g.E = E->p; g.edt = E->dt; g.eld = E->ld; g.eps = E->ps; g.e_scale = e_scale; }
   if (g.M == 0 || g.N == 0) return hipSuccess;
-  dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM), 1);
+  dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64), 1);
+  g.splits = 1;
   switch (compute) {
     case QCUR_F64: {
       g.ktiles_per_split = (int)((g.K + 15) / 16);
-      hipLaunchKernelGGL((k_qgemm<QCUR_F64, EPI_RESID>), grid, dim3(NT), 0, c.stream, g);
+      hipLaunchKernelGGL((k_qgemm<QCUR_F64, EPI_RESID, 64, 64>), grid, dim3(NT), 0, c.stream, g);
       break;
     }
     case QCUR_F32: {
       g.ktiles_per_split = (int)((g.K + 15) / 16);
-      hipLaunchKernelGGL((k_qgemm<QCUR_F32, EPI_RESID>), grid, dim3(NT), 0, c.stream, g);
+      hipLaunchKernelGGL((k_qgemm<QCUR_F32, EPI_RESID, 64, 64>), grid, dim3(NT), 0, c.stream, g);
       break;
     }
     default: {
       g.ktiles_per_split = (int)((g.K + 31) / 32);
-      hipLaunchKernelGGL((k_qgemm<QCUR_BF16, EPI_RESID>), grid, dim3(NT), 0, c.stream, g);
+      hipLaunchKernelGGL((k_qgemm<QCUR_BF16, EPI_RESID, 64, 64>), grid, dim3(NT), 0, c.stream, g);
     }
   }
   return hipGetLastError();

@@ -84,9 +84,21 @@ enum { CAST_COPY = 0, CAST_T = 1, CAST_CONJ = 2, CAST_H = 3 };
 hipError_t launch_cast(const Ctx& c, QView X, QView Y, int mode);
 
 // qGEMM: D = alpha * op(A) op(B) + beta * D.  ws may be NULL (no split-K).
-size_t gemm_workspace(int64_t M, int64_t N, int64_t K, int compute);
+// A batch runs `count` products in one launch: problem b uses the views'
+// pointers advanced by b * stride (elements) and, when the dims arrays (device
+// int[count]) are given, its own M, N, K, at most those of the views.
+struct BatchSpec {
+  int count = 1;
+  int64_t sA = 0, sB = 0, sD = 0;
+  const int* M = nullptr;
+  const int* N = nullptr;
+  const int* K = nullptr;
+};
+size_t gemm_workspace(int64_t M, int64_t N, int64_t K, int compute, int batch = 1);
 hipError_t launch_gemm(const Ctx& c, int opA, int opB, double alpha, QView A, QView B, double beta,
                        QView D, int compute, void* ws, size_t ws_bytes);
+hipError_t launch_gemm_batched(const Ctx& c, int opA, int opB, double alpha, QView A, QView B, double beta,
+                               QView D, int compute, void* ws, size_t ws_bytes, const BatchSpec& bs);
 // Residual: partial sums of squares of e_scale-free P_Omega(A - B1 R) per tile,
 // then a fixed-order final sum into fro (sqrt).  Optional E output.
 size_t residual_tiles(int64_t m, int64_t n);
@@ -107,6 +119,19 @@ hipError_t launch_pinv_scale(const Ctx& c, double* Y, int64_t p, int64_t q, doub
 hipError_t launch_check_finite(const Ctx& c, QView X);
 hipError_t launch_fill_identity(const Ctx& c, double* V, int64_t q);
 hipError_t launch_pinv_apply(const Ctx& c, double* Y, int64_t p, int64_t q, double* V, const double* dsc);
+
+// Fast pseudoinverse pieces (CholeskyQR2), batched over up to MAXB matrices.
+constexpr int CHOL_BLOCK = 64;
+constexpr int MAXB = 4;
+hipError_t launch_chol_block(const Ctx& c, const double* G, double* P, int w, int64_t ld, int64_t ps, int* fail,
+                             int batch, int64_t sbatch);
+hipError_t launch_sumsq(const Ctx& c, QView X, double* partials, double* out);
+hipError_t launch_sumsq_batch(const Ctx& c, int nb, const QView* X, double* partials, double* out, int ostride);
+hipError_t launch_pad_identity(const Ctx& c, double* G, int64_t n, int64_t sbatch, int nb, const int64_t* q);
+hipError_t launch_pinv_decide(const Ctx& c, const double* norms, const int* fail, double rtol, int64_t max_rank,
+                              int nb, const int64_t* q, int64_t* const* rank_out, int* ok);
+hipError_t launch_zero(const Ctx& c, double* p, int64_t n);
+hipError_t launch_zero_i32(const Ctx& c, int* p, int64_t n);
 
 // Backward assembly: dA = G + scatter(gC, gR, gW).
 hipError_t launch_inverse_map(const Ctx& c, const int64_t* idx, int64_t cnt, int64_t n, int32_t* inv);

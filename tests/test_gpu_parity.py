@@ -228,6 +228,32 @@ def test_pinv_max_rank_and_rtol():
         assert rel(N(Xp), ref) < tol
 
 
+@pytest.mark.parametrize("p,q", [(1024, 200), (200, 1024), (2048, 256)])
+def test_pinv_fast_path_shapes(p, q):
+    # numerically full rank: the CholeskyQR2 path with its certificate
+    rng = np.random.default_rng(p + 7 * q)
+    X = qmul(rng.standard_normal((4, p, 40)), rng.standard_normal((4, 40, q))) + 0.05 * rng.standard_normal((4, p, q))
+    Xp, rank = Q.pinv(T(X))
+    ref, k = oracle.qpinv(X)
+    assert int(N(rank)[0]) == k == min(p, q)
+    assert rel(N(Xp), ref) < max(1e-11, 64 * 2.0 ** -52 * kappa(X))
+
+
+def test_pinv_ill_conditioned_falls_back():
+    # kappa = 1e9 > the CholeskyQR2 limit: the Jacobi path must take over
+    rng = np.random.default_rng(14)
+    from tests.qhelp import lowrank_svd_form
+    X, _, _ = lowrank_svd_form(300, 70, np.logspace(0, -9, 70), rng)
+    Xp, rank = Q.pinv(T(X))
+    ref, k = oracle.qpinv(X)
+    assert int(N(rank)[0]) == k == 70
+    assert rel(N(Xp), ref) < 64 * 2.0 ** -52 * 1e9
+    Xp2, rank2 = Q.pinv(T(X), max_rank=20)      # a rank cap also disables the fast path
+    ref2, k2 = oracle.qpinv(X, max_rank=20)
+    assert int(N(rank2)[0]) == k2 == 20
+    assert rel(N(Xp2), ref2) < 1e-9
+
+
 def test_pinv_zero_matrix():
     Xp, rank = Q.pinv(torch.zeros((4, 6, 4), dtype=torch.float64, device=DEV))
     assert int(N(rank)[0]) == 0 and not N(Xp).any()
@@ -250,6 +276,22 @@ def test_approx_car_f64_matches_checker():
     assert N(ranks).tolist() == [kc, kr]
     assert rel(N(U), Ur) < 1e-10
     assert rel(N(B), oracle.cur_product(C, Ur, R)) < cur_tol(C, R)
+
+
+@pytest.mark.parametrize("compute,tol", [(Q.F64, None), (Q.F32, 1e-5)])
+def test_approx_car_ragged_pair_fast_path(compute, tol):
+    # C (700 x 90) and R^H (500 x 110) share one padded CholeskyQR group
+    A = _noisy(700, 500, 12, 51, 1e-2)
+    rng = np.random.default_rng(6)
+    I = np.sort(rng.choice(700, 110, replace=False))
+    J = np.sort(rng.choice(500, 90, replace=False))
+    C, R, W = oracle.gather(A, I, J)
+    Ur, kc, kr = oracle.core_car(A, C, R)
+    Br = oracle.cur_product(C, Ur, R)
+    dt = torch.float64 if compute == Q.F64 else torch.float32
+    U, B, ranks = Q.approx(T(A, dt), T(C, dt), T(R, dt), None, core=Q.CORE_CAR, compute=compute, want_B=True)
+    assert N(ranks).tolist() == [kc, kr] == [90, 110]
+    assert rel(N(B), Br) < (cur_tol(C, R) if tol is None else max(tol, 4 * 2.0 ** -24 * (kappa(C) + kappa(R))))
 
 
 def test_approx_wpinv_plain_workload_full_size():
