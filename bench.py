@@ -66,20 +66,21 @@ def main():
         "bf16_refine1": dict(A=A32, compute=q.BF16, refine=1),
     }
 
-    def step(v):
-        return q.solve(v["A"], c, r, sampling=q.LENGTH, core=q.CORE_CAR, compute=v["compute"], seed=seed,
-                       refine_steps=v["refine"])
+    solvers = {name: q.Solver(m, n, c, r, core=q.CORE_CAR, compute=v["compute"]) for name, v in variants.items()}
+
+    def step(name, v):
+        return solvers[name](v["A"], sampling=q.LENGTH, seed=seed, refine_steps=v["refine"])
 
     results = {}
     stream = torch.cuda.current_stream()
     for name, v in variants.items():
         for _ in range(args.warmup):
-            step(v)
+            step(name, v)
         q.sync_status()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            step(v)
+            step(name, v)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
         q.sync_status()

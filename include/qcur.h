@@ -207,6 +207,26 @@ qcur_status qcur_backward(qcur_handle handle, const qcur_qmat* A, const int64_t*
                           int64_t mask_ld, double rtol, int64_t max_rank, int compute,
                           qcur_qmat* dA, double* loss, void* ws, size_t ws_bytes);
 
+/* ---- the whole path ------------------------------------------------------ */
+
+/* One QMCUR solve (Algorithm 1) of A (m x n): sampling probabilities
+ * (QCUR_LENGTH or QCUR_UNIFORM), J (c column indices, SplitMix64 set 0) and
+ * I (r row indices, set 1) drawn as in qcur_draw (both in one launch), the
+ * gathers, the core as in qcur_approx (core, compute, refine_steps, rtol,
+ * max_rank) and residual (device double[1]) = ||A - C U R||_F as in
+ * qcur_residual.  Outputs: I (int64[r]), J (int64[c]) sorted, U (c x r, FP64
+ * for QCUR_F64 else FP32), rank_out (device int64[2] or NULL).  Optional
+ * outputs (NULL = internal): p_col[n], q_row[m] and C, R, W in A's dtype.
+ * Same limits as qcur_draw for m and n.  Synchronises once per group of
+ * pseudoinverses (the full-rank certificate).
+ * ws: qcur_solve_workspace(m, n, c, r, core, compute) bytes. */
+qcur_status qcur_solve(qcur_handle handle, const qcur_qmat* A, int64_t c, int64_t r, int sampling, int core,
+                       int compute, uint64_t seed, int with_replacement, int refine_steps, double rtol,
+                       int64_t max_rank, int64_t* I, int64_t* J, qcur_qmat* U, double* residual,
+                       int64_t* rank_out, double* p_col, double* q_row, qcur_qmat* C, qcur_qmat* R,
+                       qcur_qmat* W, void* ws, size_t ws_bytes);
+size_t qcur_solve_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int core, int compute);
+
 /* ---- helpers ----------------------------------------------------------- */
 
 /* Elementwise dtype conversion Y = X (same shape; BF16 with

@@ -667,6 +667,79 @@ qcur_status backward_run(const Ctx& c, const BwdArgs& a, Bump& b, bool count_onl
   return QCUR_OK;
 }
 
+// ---- whole solve ------------------------------------------------------------
+struct SolveArgs {
+  QView A;
+  int64_t c, r;
+  int sampling, core, compute, with_replacement, refine;
+  uint64_t seed;
+  double rtol;
+  int64_t max_rank;
+  int64_t *I, *J;
+  QView U;
+  double* residual;
+  int64_t* rank_out;
+  double *p, *q;
+  const QView *C, *R, *W;  // optional caller buffers for the gathers
+};
+
+// Algorithm 1 end to end: probabilities, the two draws in one launch, the
+// gathers, the core and the residual, all on the handle's stream.
+qcur_status solve_run(const Ctx& c, const SolveArgs& s, Bump& b, bool count_only) {
+  const int64_t m = s.A.rows, n = s.A.cols;
+  double* p = s.p ? s.p : (double*)b.take((size_t)n * 8);
+  double* q = s.q ? s.q : (double*)b.take((size_t)m * 8);
+  int rb, nrb, ncb;
+  probs_grid(m, n, &rb, &nrb, &ncb);
+  const bool pass = s.sampling == QCUR_LENGTH;
+  double* colpart = (double*)b.take(pass ? (size_t)nrb * n * 8 : 8);
+  double* rowpart = (double*)b.take(pass ? (size_t)ncb * m * 8 : 8);
+  double* f2 = (double*)b.take(8);
+  QView C = s.C ? *s.C : b.mat(m, s.c, s.A.dt);
+  QView R = s.R ? *s.R : b.mat(s.r, n, s.A.dt);
+  QView W = s.W ? *s.W : b.mat(s.r, s.c, s.A.dt);
+  ApproxArgs a{};
+  a.A = s.A;
+  a.C = C;
+  a.R = R;
+  a.W = W;
+  a.U = s.U;
+  a.hasB = false;
+  a.core = s.core;
+  a.compute = s.compute;
+  a.refine = s.core == QCUR_CORE_CAR ? s.refine : 0;
+  a.rtol = s.rtol;
+  a.max_rank = s.max_rank;
+  int64_t* ranks = s.rank_out ? s.rank_out : (int64_t*)b.take(16);
+  a.rank_out = ranks;
+  const size_t base = b.used;
+  Bump ta = b;
+  CHK(approx_run(c, a, m, n, s.c, s.r, ta, true));
+  Bump tr = b;
+  CHK(residual_run(c, s.A, C, s.U, R, nullptr, 0, s.compute, nullptr, 1, nullptr, 0.0, tr, true));
+  b.used = std::max(ta.used, tr.used);
+  if (count_only) return QCUR_OK;
+  if (pass) {
+    HIPCHK(launch_probs_partials(c, s.A, colpart, rowpart, rb, ncb));
+    HIPCHK(launch_probs_finish(c, m, n, colpart, rowpart, nrb, ncb, s.sampling, p, q, f2, nullptr));
+  } else {
+    HIPCHK(launch_probs_finish(c, m, n, nullptr, nullptr, 0, 0, s.sampling, p, q, nullptr, nullptr));
+  }
+  HIPCHK(launch_draw_pair(c, p, n, s.c, 0, s.J, q, m, s.r, 1, s.I, s.seed, s.with_replacement));
+  HIPCHK(launch_gather(c, s.A, s.I, s.r, s.J, s.c, &C, &R, s.core == QCUR_CORE_WPINV || s.W ? &W : nullptr));
+  {
+    Bump run(b.base);
+    run.used = base;
+    CHK(approx_run(c, a, m, n, s.c, s.r, run, false));
+  }
+  {
+    Bump run(b.base);
+    run.used = base;
+    CHK(residual_run(c, s.A, C, s.U, R, nullptr, 0, s.compute, s.residual, 1, nullptr, 0.0, run, false));
+  }
+  return QCUR_OK;
+}
+
 }  // namespace
 
 // ============================================================================
@@ -1054,6 +1127,100 @@ qcur_status qcur_backward(qcur_handle h, const qcur_qmat* A, const int64_t* I, i
   a.loss = loss;
   Bump b(ws);
   return backward_run(h->c, a, b, false);
+}
+
+static qcur_status check_solve(const qcur_qmat* A, int64_t c, int64_t r, int sampling, int core, int compute,
+                               int with_replacement, int refine_steps, double rtol, int64_t max_rank) {
+  CHK(check_qmat(A, "A"));
+  if (A->rows < 1 || A->cols < 1) return fail(QCUR_ERR_SHAPE, "A must have at least one row and column");
+  if (sampling != QCUR_LENGTH && sampling != QCUR_UNIFORM) return fail(QCUR_ERR_ARG, "unknown sampling %d", sampling);
+  if (core != QCUR_CORE_WPINV && core != QCUR_CORE_CAR) return fail(QCUR_ERR_ARG, "unknown core %d", core);
+  if (!valid_dtype(compute)) return fail(QCUR_ERR_DTYPE, "unknown compute dtype");
+  if (with_replacement != 0 && with_replacement != 1) return fail(QCUR_ERR_ARG, "with_replacement must be 0 or 1");
+  if (c < 1 || r < 1) return fail(QCUR_ERR_ARG, "c and r must be >= 1");
+  if (!with_replacement && (c > A->cols || r > A->rows)) return fail(QCUR_ERR_ARG, "c > n or r > m without replacement");
+  const int64_t lim = with_replacement ? 8192 : 16384;
+  if (A->cols > lim || A->rows > lim) return fail(QCUR_ERR_UNSUPPORTED, "matrix side exceeds the sampler's LDS limit");
+  if (refine_steps < 0) return fail(QCUR_ERR_ARG, "refine_steps must be >= 0");
+  if (!std::isfinite(rtol)) return fail(QCUR_ERR_ARG, "rtol must be finite");
+  if (max_rank < 0) return fail(QCUR_ERR_ARG, "max_rank must be >= 0");
+  return QCUR_OK;
+}
+
+size_t qcur_solve_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int core, int compute) {
+  if (m < 1 || n < 1 || c < 1 || r < 1 || !valid_dtype(compute)) return 0;
+  // the input may come in any dtype: size for the largest element
+  SolveArgs s{};
+  s.A = QView{nullptr, m, n, n, m * n, QCUR_F64};
+  s.c = c;
+  s.r = r;
+  s.sampling = QCUR_LENGTH;
+  s.core = core;
+  s.compute = compute;
+  s.refine = 1;
+  s.U = QView{nullptr, c, r, r, c * r, acc_dt(compute)};
+  Ctx dummy{0, nullptr, nullptr};
+  size_t worst = 0;
+  for (int dt : {QCUR_F64, QCUR_F32, QCUR_BF16}) {
+    s.A.dt = dt;
+    Bump b(nullptr);
+    solve_run(dummy, s, b, true);
+    worst = std::max(worst, b.used);
+  }
+  return worst + 256;
+}
+
+qcur_status qcur_solve(qcur_handle h, const qcur_qmat* A, int64_t c, int64_t r, int sampling, int core, int compute,
+                       uint64_t seed, int with_replacement, int refine_steps, double rtol, int64_t max_rank,
+                       int64_t* I, int64_t* J, qcur_qmat* U, double* residual, int64_t* rank_out, double* p_col,
+                       double* q_row, qcur_qmat* C, qcur_qmat* R, qcur_qmat* W, void* ws, size_t ws_bytes) {
+  CHK(check_solve(A, c, r, sampling, core, compute, with_replacement, refine_steps, rtol, max_rank));
+  if (!I || !J || !residual) return fail(QCUR_ERR_ARG, "I, J and residual must not be NULL");
+  CHK(check_qmat(U, "U"));
+  CHK(check_dims(U, "U", c, r));
+  if (U->dtype != acc_dt(compute)) return fail(QCUR_ERR_DTYPE, "U must be FP64 (F64 compute) or FP32");
+  const qcur_qmat* outs[3] = {C, R, W};
+  const char* names[3] = {"C", "R", "W"};
+  const int64_t rows[3] = {A->rows, r, r}, cols[3] = {c, A->cols, c};
+  for (int k = 0; k < 3; ++k) {
+    if (!outs[k]) continue;
+    CHK(check_qmat(outs[k], names[k]));
+    CHK(check_dims(outs[k], names[k], rows[k], cols[k]));
+    if (outs[k]->dtype != A->dtype) return fail(QCUR_ERR_DTYPE, "%s must have A's dtype", names[k]);
+  }
+  SolveArgs s{};
+  s.A = view_of(*A);
+  s.c = c;
+  s.r = r;
+  s.sampling = sampling;
+  s.core = core;
+  s.compute = compute;
+  s.with_replacement = with_replacement;
+  s.refine = refine_steps;
+  s.seed = seed;
+  s.rtol = rtol;
+  s.max_rank = max_rank;
+  s.I = I;
+  s.J = J;
+  s.U = view_of(*U);
+  s.residual = residual;
+  s.rank_out = rank_out;
+  s.p = p_col;
+  s.q = q_row;
+  QView Cv, Rv, Wv;
+  if (C) { Cv = view_of(*C); s.C = &Cv; }
+  if (R) { Rv = view_of(*R); s.R = &Rv; }
+  if (W) { Wv = view_of(*W); s.W = &Wv; }
+  {
+    Bump sz(nullptr);
+    Ctx dummy{0, nullptr, nullptr};
+    solve_run(dummy, s, sz, true);
+    const size_t need = sz.used + 256;
+    if (!ws || ws_bytes < need) return fail(QCUR_ERR_WORKSPACE, "solve needs %zu workspace bytes", need);
+  }
+  CHK(check_handle(h));
+  Bump b(ws);
+  return solve_run(h->c, s, b, false);
 }
 
 qcur_status qcur_cast(qcur_handle h, const qcur_qmat* X, qcur_qmat* Y) {

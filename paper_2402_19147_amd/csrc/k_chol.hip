@@ -50,6 +50,22 @@ __device__ inline double rsqrt_nr(double d) {
   return r;
 }
 
+template <int CTRL, int ROWS>
+__device__ inline double dpp_f64(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROWS, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROWS, 0xf, true);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Sum over the 8 lanes 8g..8g+7; the total is valid in lane 8g+4.
+__device__ inline double sum8_dpp(double v) {
+  v += dpp_f64<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]: pairs
+  v += dpp_f64<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]: quads
+  v += dpp_f64<0x114, 0xf>(v);  // row_shr:4: lane 8g+4 adds the quad below it
+  return v;
+}
+
 __global__ __launch_bounds__(CHOL_THREADS) void k_chol_block(const double* __restrict__ G0, double* __restrict__ P0,
                                                              int w, int64_t ld, int64_t ps, int64_t sbatch,
                                                              int* fail0) {
@@ -72,34 +88,65 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_block(const double* __res
   __syncthreads();
   // Cholesky: the t(t+1)/2 trailing entries of step j are spread over the
   // threads (entry e is row r, column q of the trailing triangle with
-  // e = r(r+1)/2 + q), so the work per step shrinks with the triangle.
+  // e = r(r+1)/2 + q; a thread's (r, q) pairs do not depend on j), so the work
+  // per step shrinks with the triangle.  Each step issues all its loads
+  // before the pivot's reciprocal square root is needed.
+  constexpr int SLOTS = (CB * (CB - 1) / 2 + CHOL_THREADS - 1) / CHOL_THREADS;
+  int tr[SLOTS], tq[SLOTS];
+#pragma unroll
+  for (int m = 0; m < SLOTS; ++m) {
+    const int e = tid + m * CHOL_THREADS;
+    const int r = (int)((sqrtf((float)(8 * e + 1)) - 1.0f) * 0.5f);
+    tr[m] = r;
+    tq[m] = e - r * (r + 1) / 2;
+  }
+  const int wave_e0 = (tid >> 6) * 64;
   for (int j = 0; j < w; ++j) {
+    const int t = w - j - 1;
+    const int cnt = t * (t + 1) / 2;
     const double d = a[0][j][j];
+    Qd li[SLOTS], lk[SLOTS], x[SLOTS];
+#pragma unroll
+    for (int m = 0; m < SLOTS; ++m) {
+      if (wave_e0 + m * CHOL_THREADS < cnt) {  // uniform over the wave
+        const int e = tid + m * CHOL_THREADS;
+        const int i = j + 1 + tr[m], k = j + 1 + tq[m];
+        if (e < cnt) {
+          li[m] = Qd{a[0][i][j], a[1][i][j], a[2][i][j], a[3][i][j]};
+          lk[m] = Qd{a[0][k][j], a[1][k][j], a[2][k][j], a[3][k][j]};
+          x[m] = Qd{a[0][i][k], a[1][i][k], a[2][i][k], a[3][i][k]};
+        }
+      }
+    }
+    Qd lh{0, 0, 0, 0};
+    if (tid < t) lh = Qd{a[0][j + 1 + tid][j], a[1][j + 1 + tid][j], a[2][j + 1 + tid][j], a[3][j + 1 + tid][j]};
     const bool ok = d > 0.0 && d < INFINITY;
     const double rs = rsqrt_nr(ok ? d : 1.0);
     const double rd = rs * rs;
-    const int t = w - j - 1;
-    const int cnt = t * (t + 1) / 2;
     if (tid == 0) {
       rdg[j] = rs;
       if (!ok) bad = 1;
     }
     if (tid < t) {  // L^H row j into the upper triangle (never read in this step)
       const int k = j + 1 + tid;
-      a[0][j][k] = a[0][k][j] * rs;
-      a[1][j][k] = -a[1][k][j] * rs;
-      a[2][j][k] = -a[2][k][j] * rs;
-      a[3][j][k] = -a[3][k][j] * rs;
+      a[0][j][k] = lh.w * rs;
+      a[1][j][k] = -lh.x * rs;
+      a[2][j][k] = -lh.y * rs;
+      a[3][j][k] = -lh.z * rs;
     }
-    for (int e = tid; e < cnt; e += CHOL_THREADS) {
-      const int r = (int)((sqrtf((float)(8 * e + 1)) - 1.0f) * 0.5f);
-      const int i = j + 1 + r, k = j + 1 + (e - r * (r + 1) / 2);
-      const Qd q = qmul_conj(Qd{a[0][i][j], a[1][i][j], a[2][i][j], a[3][i][j]},
-                             Qd{a[0][k][j], a[1][k][j], a[2][k][j], a[3][k][j]});
-      a[0][i][k] -= q.w * rd;
-      a[1][i][k] -= q.x * rd;
-      a[2][i][k] -= q.y * rd;
-      a[3][i][k] -= q.z * rd;
+#pragma unroll
+    for (int m = 0; m < SLOTS; ++m) {
+      if (wave_e0 + m * CHOL_THREADS < cnt) {
+        const int e = tid + m * CHOL_THREADS;
+        const int i = j + 1 + tr[m], k = j + 1 + tq[m];
+        if (e < cnt) {
+          const Qd q = qmul_conj(li[m], lk[m]);
+          a[0][i][k] = x[m].w - q.w * rd;
+          a[1][i][k] = x[m].x - q.x * rd;
+          a[2][i][k] = x[m].y - q.y * rd;
+          a[3][i][k] = x[m].z - q.z * rd;
+        }
+      }
     }
     __syncthreads();
   }
@@ -109,34 +156,42 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_block(const double* __res
     a[1][i][i] = a[2][i][i] = a[3][i][i] = 0.0;
   }
   __syncthreads();
-  // inverse: 8 threads per row; waves whose rows are all done only wait
+  // inverse: 8 threads per row (lanes 8g..8g+7 of a wave), reduced in
+  // registers with DPP (pairs, quads, then the quad 4 lanes below); the row
+  // total lands in lane 8g+4.  Waves whose rows are all done only wait.
   const int sub = tid & 7, row = tid >> 3;
   const int wave_row0 = (tid >> 6) * 8;
   for (int j = w - 2; j >= 0; --j) {
     const int t = w - j - 1;
     if (wave_row0 < t) {
       const int i = j + 1 + row;
-      Qd s{0, 0, 0, 0};
-      if (row < t) {
-        for (int k = j + 1 + sub; k <= i; k += 8) {
-          // P[i][k] L[k][j] with L[k][j] = conj(a[j][k])
-          const Qd u = qmul_conj(Qd{a[0][i][k], a[1][i][k], a[2][i][k], a[3][i][k]},
-                                 Qd{a[0][j][k], a[1][j][k], a[2][j][k], a[3][j][k]});
-          s.w += u.w;
-          s.x += u.x;
-          s.y += u.y;
-          s.z += u.z;
+      const double f = -rdg[j];
+      Qd pk[8], lj[8];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const int k = j + 1 + sub + 8 * m;
+        if (row < t && k <= i) {
+          pk[m] = Qd{a[0][i][k], a[1][i][k], a[2][i][k], a[3][i][k]};
+          lj[m] = Qd{a[0][j][k], a[1][j][k], a[2][j][k], a[3][j][k]};  // conj(L[k][j])
+        } else {
+          pk[m] = Qd{0, 0, 0, 0};
+          lj[m] = Qd{0, 0, 0, 0};
         }
       }
+      Qd s{0, 0, 0, 0};
 #pragma unroll
-      for (int o = 4; o >= 1; o >>= 1) {
-        s.w += __shfl_xor(s.w, o, 8);
-        s.x += __shfl_xor(s.x, o, 8);
-        s.y += __shfl_xor(s.y, o, 8);
-        s.z += __shfl_xor(s.z, o, 8);
+      for (int m = 0; m < 8; ++m) {
+        const Qd u = qmul_conj(pk[m], lj[m]);  // P[i][k] L[k][j]
+        s.w += u.w;
+        s.x += u.x;
+        s.y += u.y;
+        s.z += u.z;
       }
-      if (row < t && sub == 0) {
-        const double f = -rdg[j];
+      s.w = sum8_dpp(s.w);
+      s.x = sum8_dpp(s.x);
+      s.y = sum8_dpp(s.y);
+      s.z = sum8_dpp(s.z);
+      if (row < t && sub == 4) {
         a[0][i][j] = f * s.w;
         a[1][i][j] = f * s.x;
         a[2][i][j] = f * s.y;

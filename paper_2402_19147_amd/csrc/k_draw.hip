@@ -9,6 +9,8 @@
 // One workgroup per draw.  Weights live in LDS; the search descends a
 // 64-ary tree (superblocks of 4096, blocks of 64 elements) with one
 // wave-wide prefix scan per level, so each draw costs three scans.
+#include <algorithm>
+
 #include "qcur_internal.hpp"
 
 namespace qcur {
@@ -77,9 +79,22 @@ __device__ inline int select_lane(uint64_t v, uint64_t& tau) {
   return k;
 }
 
-__global__ __launch_bounds__(DRAW_THREADS) void k_draw(const double* __restrict__ probs, int64_t n, int64_t count,
-                                                       uint64_t seed, uint64_t set_id, int repl,
-                                                       int64_t* __restrict__ idx, unsigned* status) {
+struct DrawJob {
+  const double* probs;
+  int64_t n, count;
+  uint64_t seed, set_id;
+  int64_t* idx;
+};
+struct DrawJobs {
+  DrawJob j[2];
+};
+
+__global__ __launch_bounds__(DRAW_THREADS) void k_draw(DrawJobs jobs, int repl, unsigned* status) {
+  const DrawJob& job = jobs.j[blockIdx.x];
+  const double* __restrict__ probs = job.probs;
+  const int64_t n = job.n, count = job.count;
+  const uint64_t seed = job.seed, set_id = job.set_id;
+  int64_t* __restrict__ idx = job.idx;
   extern __shared__ uint64_t lds[];
   const int64_t npad = (n + 63) / 64 * 64;
   const int64_t nb = npad / 64;
@@ -211,18 +226,39 @@ __global__ __launch_bounds__(DRAW_THREADS) void k_draw(const double* __restrict_
   }
 }
 
-hipError_t launch_draw(const Ctx& c, const double* probs, int64_t n, int64_t count, uint64_t seed,
-                       uint64_t set_id, int with_replacement, int64_t* idx) {
+static size_t draw_lds(int64_t n, int repl) {
   const int64_t npad = (n + 63) / 64 * 64;
   const int64_t nb = npad / 64;
   size_t lds = (size_t)(npad + nb + 64) * 8;
-  if (with_replacement) lds += (size_t)npad * 4;
+  if (repl) lds += (size_t)npad * 4;
+  return lds;
+}
+
+static hipError_t draw_jobs(const Ctx& c, DrawJobs jobs, int njobs, int repl, size_t lds) {
   hipError_t e = hipFuncSetAttribute((const void*)k_draw, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)(140 * 1024));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_draw, dim3(1), dim3(DRAW_THREADS), lds, c.stream, probs, n, count, seed, set_id,
-                     with_replacement, idx, c.status);
+  hipLaunchKernelGGL(k_draw, dim3(njobs), dim3(DRAW_THREADS), lds, c.stream, jobs, repl, c.status);
   return hipGetLastError();
+}
+
+hipError_t launch_draw(const Ctx& c, const double* probs, int64_t n, int64_t count, uint64_t seed,
+                       uint64_t set_id, int with_replacement, int64_t* idx) {
+  DrawJobs jobs{};
+  jobs.j[0] = DrawJob{probs, n, count, seed, set_id, idx};
+  return draw_jobs(c, jobs, 1, with_replacement, draw_lds(n, with_replacement));
+}
+
+// Two independent draws (e.g. J from the column and I from the row
+// probabilities) in one launch of two workgroups.
+hipError_t launch_draw_pair(const Ctx& c, const double* p0, int64_t n0, int64_t count0, uint64_t set0,
+                            int64_t* idx0, const double* p1, int64_t n1, int64_t count1, uint64_t set1,
+                            int64_t* idx1, uint64_t seed, int with_replacement) {
+  DrawJobs jobs{};
+  jobs.j[0] = DrawJob{p0, n0, count0, seed, set0, idx0};
+  jobs.j[1] = DrawJob{p1, n1, count1, seed, set1, idx1};
+  const size_t lds = std::max(draw_lds(n0, with_replacement), draw_lds(n1, with_replacement));
+  return draw_jobs(c, jobs, 2, with_replacement, lds);
 }
 
 }  // namespace qcur

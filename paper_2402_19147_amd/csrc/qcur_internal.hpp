@@ -76,6 +76,9 @@ void probs_grid(int64_t m, int64_t n, int* rb, int* nrb, int* ncb);
 
 hipError_t launch_draw(const Ctx& c, const double* probs, int64_t n, int64_t count, uint64_t seed,
                        uint64_t set_id, int with_replacement, int64_t* idx);
+hipError_t launch_draw_pair(const Ctx& c, const double* p0, int64_t n0, int64_t count0, uint64_t set0,
+                            int64_t* idx0, const double* p1, int64_t n1, int64_t count1, uint64_t set1,
+                            int64_t* idx1, uint64_t seed, int with_replacement);
 
 hipError_t launch_gather(const Ctx& c, QView A, const int64_t* I, int64_t r, const int64_t* J,
                          int64_t cc, const QView* C, const QView* R, const QView* W);

@@ -75,6 +75,9 @@ def _declare(L):
         "qcur_backward": (c_int, [c_p, QP, c_p, c_i64, c_p, c_i64, QP, c_p, c_i64, c_d, c_i64, c_int,
                                   QP, c_p, c_p, c_sz]),
         "qcur_cast": (c_int, [c_p, QP, QP]),
+        "qcur_solve": (c_int, [c_p, QP, c_i64, c_i64, c_int, c_int, c_int, c_u64, c_int, c_int, c_d, c_i64, c_p,
+                               c_p, QP, c_p, c_p, c_p, c_p, QP, QP, QP, c_p, c_sz]),
+        "qcur_solve_workspace": (c_sz, [c_i64, c_i64, c_i64, c_i64, c_int, c_int]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -285,6 +288,33 @@ def cast(X: torch.Tensor, dtype) -> torch.Tensor:
 
 
 # ---- the whole path ----------------------------------------------------------
+
+class Solver:
+    """Reusable buffers for repeated native solves (qcur_solve) of one shape."""
+
+    def __init__(self, m: int, n: int, c: int, r: int, core: int = CORE_CAR, compute: int = F64, device=None):
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.shape = (m, n, c, r)
+        self.core, self.compute = core, compute
+        odt = torch.float64 if compute == F64 else torch.float32
+        self.I = torch.empty(r, dtype=torch.int64, device=dev)
+        self.J = torch.empty(c, dtype=torch.int64, device=dev)
+        self.U = empty(c, r, odt, dev)
+        self.residual = torch.empty(1, dtype=torch.float64, device=dev)
+        self.ranks = torch.zeros(2, dtype=torch.int64, device=dev)
+        self.ws = _ws(lib().qcur_solve_workspace(m, n, c, r, core, compute), dev)
+
+    def __call__(self, A: torch.Tensor, sampling: int = LENGTH, seed: int = 0, refine_steps: int = 0,
+                 rtol: float = -1.0, max_rank: int = 0, with_replacement: bool = False):
+        m, n, c, r = self.shape
+        if tuple(A.shape) != (4, m, n):
+            raise ValueError("A does not match the solver's shape")
+        _check(lib().qcur_solve(_h(A), _qp(A), c, r, sampling, self.core, self.compute, seed & (2 ** 64 - 1),
+                                int(with_replacement), refine_steps, rtol, max_rank, _ptr(self.I), _ptr(self.J),
+                                _qp(self.U), _ptr(self.residual), _ptr(self.ranks), None, None, None, None, None,
+                                _ptr(self.ws), self.ws.numel()))
+        return self
+
 
 def solve(A: torch.Tensor, c: int, r: int, sampling: int = LENGTH, core: int = CORE_CAR, compute: int = F64,
           seed: int = 0, refine_steps: int = 0, rtol: float = -1.0, max_rank: int = 0,

@@ -369,3 +369,30 @@ def test_backward_repeated_index_flags_arg():
     Q.backward(A, T(np.array([1, 1, 2]), torch.int64), T(np.array([0, 3, 4]), torch.int64))
     with pytest.raises(Q.QcurError):
         Q.sync_status()
+
+
+# ---------------------------------------------------------------- the native solve
+@pytest.mark.parametrize("sampling,core,compute", [(Q.UNIFORM, Q.CORE_WPINV, Q.F64), (Q.LENGTH, Q.CORE_CAR, Q.F64),
+                                                   (Q.LENGTH, Q.CORE_CAR, Q.F32), (Q.LENGTH, Q.CORE_CAR, Q.BF16)])
+def test_native_solve_matches_checker(sampling, core, compute):
+    if core == Q.CORE_WPINV:
+        L, Rt, _ = workloads.lowrank_gaussian_factors(256, 240, 10, 1)
+        A = qmul(L, Rt)
+        c = r = 40
+    else:
+        A = workloads.color_like(320, 288, 12, seed=8, noise=0.01)
+        c, r = 60, 72
+    dt = torch.float64 if compute == Q.F64 else torch.float32
+    S = Q.Solver(A.shape[1], A.shape[2], c, r, core=core, compute=compute)
+    S(T(A, dt), sampling=sampling, seed=13, refine_steps=1 if compute == Q.BF16 else 0)
+    ref = oracle.solve(np.asarray(N(T(A, dt))), c, r, "uniform" if sampling == Q.UNIFORM else "length",
+                       "wpinv" if core == Q.CORE_WPINV else "car", seed=13)
+    Q.sync_status()
+    assert N(S.J).astype(np.int64).tolist() == ref["J"].tolist()
+    assert N(S.I).astype(np.int64).tolist() == ref["I"].tolist()
+    res = float(N(S.residual)[0])
+    # |res - res_ref| <= ||CUR - (CUR)_ref||_F, bounded by the product tolerance times ||A||_F
+    k = kappa(ref["C"]) + kappa(ref["R"])
+    tol = {Q.F64: cur_tol(ref["C"], ref["R"]), Q.F32: max(1e-5, 4 * 2.0 ** -24 * k),
+           Q.BF16: max(2e-2, 4 * 2.0 ** -9 * k)}[compute]
+    assert abs(res - ref["residual"]) <= tol * np.sqrt(fro2(A))
