@@ -227,6 +227,52 @@ qcur_status qcur_solve(qcur_handle handle, const qcur_qmat* A, int64_t c, int64_
                        qcur_qmat* W, void* ws, size_t ws_bytes);
 size_t qcur_solve_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int core, int compute);
 
+/* ---- many independent solves of uneven sizes --------------------------- */
+
+/* Batched QMCUR (Algorithm 1 on `count` independent problems, e.g. the patch
+ * groups of an image), least-squares core U_b = C_b^+ A_b R_b^+ (Section 3.1,
+ * eq. (2)) and residual_b = ||A_b - C_b U_b R_b||_F, all problems advancing
+ * through one sequence of batched launches with no host synchronisation, so
+ * that the whole call can be captured into one graph and replayed.
+ *
+ * dims: host int32[count][4] = (m_b, n_b, c_b, r_b), 1 <= count <= 16384,
+ * 1 <= m_b, n_b <= 4096,
+ * 1 <= c_b, r_b <= 1024, c_b <= n_b and r_b <= m_b without replacement.
+ * Slots: with mx, nx, cx, rx the largest m_b, n_b, c_b, r_b, problem b's A_b
+ * is the top-left m_b x n_b corner of slot b of A (A->rows >= mx,
+ * A->cols >= nx, planes A->pstride apart, slots a_bstride elements apart);
+ * U_b (c_b x r_b, FP64 for QCUR_F64 else FP32) is the corner of slot b of U
+ * (u_bstride apart).  I: device int64[count][rx] (row b holds I_b, sorted,
+ * in its first r_b entries); J: int64[count][cx].  residual: device
+ * double[count].  rank_out: device int64[count][2] (ranks of C_b, R_b) or
+ * NULL.  p_col: device double[count][nx], q_row: double[count][mx] or NULL.
+ * Problem b draws with the seed seed + b (J_b set 0, I_b set 1), so it
+ * repeats qcur_solve of A_b with that seed; its probabilities are folded in
+ * another order, equal to qcur_solve's up to rounding.
+ * The pseudoinverses run batched in FP64: CholeskyQR (two passes for
+ * QCUR_F64, one otherwise) with the kappa_F certificate of qcur_pinv, and
+ * for each problem that fails it, the Jacobi SVD inside the same launch
+ * sequence.  Errors found in kernels go to the status word.
+ *
+ * Before the first call, qcur_batch_prepare(handle, count, dims, A's dtype,
+ * sampling, compute, refine_steps, ws, ws_bytes) writes the batch's size
+ * tables into the workspace (synchronously; not under stream capture) and
+ * records the workspace in the handle; qcur_solve_batched refuses a
+ * workspace that was not prepared for the same sizes and options.  Calls
+ * that share one workspace must not overlap.
+ * ws: qcur_batch_workspace(count, dims, A's dtype, sampling, compute,
+ * refine_steps) bytes (0 for invalid arguments). */
+size_t qcur_batch_workspace(int32_t count, const int32_t* dims, int a_dtype, int sampling, int compute,
+                            int refine_steps);
+qcur_status qcur_batch_prepare(qcur_handle handle, int32_t count, const int32_t* dims, int a_dtype,
+                               int sampling, int compute, int refine_steps, void* ws, size_t ws_bytes);
+qcur_status qcur_solve_batched(qcur_handle handle, int32_t count, const int32_t* dims,
+                               const qcur_qmat* A, int64_t a_bstride, int sampling, int compute,
+                               uint64_t seed, int with_replacement, int refine_steps, double rtol,
+                               int64_t max_rank, int64_t* I, int64_t* J, qcur_qmat* U, int64_t u_bstride,
+                               double* residual, int64_t* rank_out, double* p_col, double* q_row,
+                               void* ws, size_t ws_bytes);
+
 /* ---- helpers ----------------------------------------------------------- */
 
 /* Elementwise dtype conversion Y = X (same shape; BF16 with

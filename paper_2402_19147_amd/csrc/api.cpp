@@ -8,13 +8,23 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "qcur_internal.hpp"
 
 using namespace qcur;
 
+// A prepared batch layout: the workspace it was uploaded into and a key of
+// the sizes and options it was prepared for.
+struct BatchRecord {
+  const void* ws = nullptr;
+  uint64_t key = 0;
+};
+
 struct qcur_ctx {
   Ctx c;
+  BatchRecord batches[8];
+  int next_batch = 0;
 };
 
 namespace {
@@ -740,6 +750,372 @@ qcur_status solve_run(const Ctx& c, const SolveArgs& s, Bump& b, bool count_only
   return QCUR_OK;
 }
 
+
+// ---- batched solve ----------------------------------------------------------
+struct BatchShape {
+  int count;
+  const int32_t* dims;  // host [count][4]: m, n, c, r
+  int64_t mx, nx, cx, rx;
+  int a_dt, sampling, compute, refine;
+};
+
+struct BatchWs {
+  int *dm, *dn, *dc, *dr, *zp, *zq;  // header (uploaded by qcur_batch_prepare)
+  double *colpart, *rowpart, *p, *q;
+  Slots Ax, C64, R64, Cx, Rx;
+  double *G, *L, *P1, *P2, *P, *Sch, *Q1, *Q, *norms;
+  int *fail, *ok;
+  double *Y, *V;
+  Slots Qcx, Qrx, T, Tx, M, Mx, B1, B1x, E, Ex, M64, W1, U64;
+  double* part;
+  int64_t tiles;
+  int64_t* ranks;
+  void* gws;
+  size_t gws_bytes;
+  int64_t px, qx;
+};
+
+Slots slots_of(Bump& b, int count, int64_t rows, int64_t cols, int dt) {
+  Slots s;
+  s.ld = std::max<int64_t>(cols, 1);
+  s.ps = std::max<int64_t>(rows, 1) * s.ld;
+  s.slab = 4 * s.ps;
+  s.dt = dt;
+  s.p = b.take((size_t)count * s.slab * dtype_size(dt));
+  return s;
+}
+
+QView slot_view(const Slots& s, int64_t rows, int64_t cols) { return QView{s.p, rows, cols, s.ld, s.ps, s.dt}; }
+
+Slots sl(double* p, int64_t rows, int64_t cols, int64_t ld) {
+  return Slots{p, ld, rows * ld, 4 * rows * ld, QCUR_F64};
+}
+
+// Workspace layout of a batch; the same code sizes (null base) and carves.
+BatchWs batch_carve(Bump& b, const BatchShape& s) {
+  BatchWs w{};
+  const int n = s.count, n2 = 2 * s.count;
+  const int idt = in_dt(s.compute), adt = acc_dt(s.compute);
+  w.dm = (int*)b.take((size_t)n * 4);
+  w.dn = (int*)b.take((size_t)n * 4);
+  w.dc = (int*)b.take((size_t)n * 4);
+  w.dr = (int*)b.take((size_t)n * 4);
+  w.zp = (int*)b.take((size_t)n2 * 4);
+  w.zq = (int*)b.take((size_t)n2 * 4);
+  const int64_t nrbx = (s.mx + BATCH_RB - 1) / BATCH_RB, ncbx = (s.nx + 255) / 256;
+  w.colpart = (double*)b.take((size_t)n * nrbx * s.nx * 8);
+  w.rowpart = (double*)b.take((size_t)n * ncbx * s.mx * 8);
+  w.p = (double*)b.take((size_t)n * s.nx * 8);
+  w.q = (double*)b.take((size_t)n * s.mx * 8);
+  w.Ax = s.a_dt != idt ? slots_of(b, n, s.mx, s.nx, idt) : Slots{};
+  w.C64 = slots_of(b, n, s.mx, s.cx, QCUR_F64);
+  w.R64 = slots_of(b, n, s.rx, s.nx, QCUR_F64);
+  w.Cx = idt != QCUR_F64 ? slots_of(b, n, s.mx, s.cx, idt) : w.C64;
+  w.Rx = idt != QCUR_F64 ? slots_of(b, n, s.rx, s.nx, idt) : w.R64;
+  w.px = std::max(s.mx, s.nx);
+  w.qx = std::max(s.cx, s.rx);
+  const size_t gsl = (size_t)n2 * 4 * w.qx * w.qx * 8, zsl = (size_t)n2 * 4 * w.px * w.qx * 8;
+  w.G = (double*)b.take(gsl);
+  w.L = (double*)b.take(gsl);
+  w.P1 = (double*)b.take(gsl);
+  w.Sch = (double*)b.take((size_t)n2 * 4 * CHOL_BLOCK * w.qx * 8);
+  w.Q = (double*)b.take(zsl);
+  w.P2 = (double*)b.take(gsl);
+  w.P = (double*)b.take(gsl);
+  w.Q1 = (double*)b.take(zsl);
+  w.norms = (double*)b.take((size_t)n2 * 4 * 8);
+  w.fail = (int*)b.take((size_t)n2 * 4);
+  w.ok = (int*)b.take((size_t)n2 * 4);
+  w.Y = (double*)b.take(zsl);
+  w.V = (double*)b.take(gsl);
+  if (idt != QCUR_F64) {
+    w.Qcx = slots_of(b, n, s.mx, s.cx, idt);
+    w.Qrx = slots_of(b, n, s.nx, s.rx, idt);
+  }
+  w.T = slots_of(b, n, s.mx, s.rx, adt);
+  w.Tx = idt != adt ? slots_of(b, n, s.mx, s.rx, idt) : w.T;
+  w.M = slots_of(b, n, s.cx, s.rx, adt);
+  w.Mx = idt != adt ? slots_of(b, n, s.cx, s.rx, idt) : w.M;
+  w.B1 = slots_of(b, n, s.mx, s.rx, adt);
+  w.B1x = idt != adt ? slots_of(b, n, s.mx, s.rx, idt) : w.B1;
+  if (s.refine > 0) {
+    w.E = slots_of(b, n, s.mx, s.nx, adt);
+    w.Ex = idt != adt ? slots_of(b, n, s.mx, s.nx, idt) : w.E;
+  }
+  w.M64 = adt != QCUR_F64 ? slots_of(b, n, s.cx, s.rx, QCUR_F64) : w.M;
+  w.W1 = slots_of(b, n, s.cx, s.rx, QCUR_F64);
+  w.U64 = adt != QCUR_F64 ? slots_of(b, n, s.cx, s.rx, QCUR_F64) : Slots{};
+  w.tiles = (int64_t)((s.mx + 63) / 64) * ((s.nx + 63) / 64);
+  w.part = (double*)b.take((size_t)n * w.tiles * 8);
+  w.ranks = (int64_t*)b.take((size_t)n * 2 * 8);
+  const int64_t px = w.px, qx = w.qx;
+  const int cp = s.compute;
+  w.gws_bytes = std::max({gemm_workspace(qx, qx, px, QCUR_F64, n), gemm_workspace(qx, qx, qx, QCUR_F64, n2),
+                          gemm_workspace(px, qx, qx, QCUR_F64, n), gemm_workspace(px, qx, qx, QCUR_F64, n2),
+                          gemm_workspace(qx, qx, px, QCUR_F64, n2), gemm_workspace(s.mx, s.rx, s.nx, cp, n),
+                          gemm_workspace(s.cx, s.rx, s.mx, cp, n), gemm_workspace(s.mx, s.rx, s.cx, cp, n),
+                          gemm_workspace(s.cx, s.rx, qx, QCUR_F64, n)});
+  w.gws = b.take(w.gws_bytes);
+  return w;
+}
+
+uint64_t batch_key(const BatchShape& s) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) {
+    for (int k = 0; k < 8; ++k) {
+      h ^= (v >> (8 * k)) & 0xff;
+      h *= 1099511628211ull;
+    }
+  };
+  mix((uint64_t)s.count);
+  for (int64_t e = 0; e < 4 * (int64_t)s.count; ++e) mix((uint64_t)(uint32_t)s.dims[e]);
+  mix((uint64_t)s.a_dt);
+  mix((uint64_t)s.sampling);
+  mix((uint64_t)s.compute);
+  mix((uint64_t)(s.refine > 0));
+  return h;
+}
+
+constexpr int64_t BATCH_MAX_SIDE = 4096;
+
+qcur_status check_batch_shape(int count, const int32_t* dims, int a_dt, int sampling, int compute, int refine,
+                              int with_replacement, BatchShape* out) {
+  if (count < 1 || count > 16384) return fail(QCUR_ERR_ARG, "count must be in [1, 16384]");
+  if (!dims) return fail(QCUR_ERR_ARG, "dims is NULL");
+  if (!valid_dtype(a_dt)) return fail(QCUR_ERR_DTYPE, "unknown dtype of A");
+  if (!valid_dtype(compute)) return fail(QCUR_ERR_DTYPE, "unknown compute dtype");
+  if (sampling != QCUR_LENGTH && sampling != QCUR_UNIFORM) return fail(QCUR_ERR_ARG, "unknown sampling %d", sampling);
+  if (refine < 0) return fail(QCUR_ERR_ARG, "refine_steps must be >= 0");
+  BatchShape s{};
+  s.count = count;
+  s.dims = dims;
+  for (int b = 0; b < count; ++b) {
+    const int64_t m = dims[4 * b], n = dims[4 * b + 1], c = dims[4 * b + 2], r = dims[4 * b + 3];
+    if (m < 1 || n < 1 || m > BATCH_MAX_SIDE || n > BATCH_MAX_SIDE)
+      return fail(QCUR_ERR_SHAPE, "problem %d: m and n must be in [1, %lld]", b, (long long)BATCH_MAX_SIDE);
+    if (c < 1 || r < 1 || c > JB_MAXQ || r > JB_MAXQ)
+      return fail(QCUR_ERR_SHAPE, "problem %d: c and r must be in [1, %d]", b, JB_MAXQ);
+    if (!with_replacement && (c > n || r > m))
+      return fail(QCUR_ERR_SHAPE, "problem %d: c > n or r > m without replacement", b);
+    s.mx = std::max(s.mx, m);
+    s.nx = std::max(s.nx, n);
+    s.cx = std::max(s.cx, c);
+    s.rx = std::max(s.rx, r);
+  }
+  s.a_dt = a_dt;
+  s.sampling = sampling;
+  s.compute = compute;
+  s.refine = refine;
+  *out = s;
+  return QCUR_OK;
+}
+
+// A slotted operand: rows x cols at least (mx, nx), slots bstride apart.
+qcur_status check_slotted(const qcur_qmat* X, const char* name, int64_t rows, int64_t cols, int64_t bstride) {
+  CHK(check_qmat(X, name));
+  if (X->rows < rows || X->cols < cols)
+    return fail(QCUR_ERR_SHAPE, "%s slots are %lldx%lld, need at least %lldx%lld", name, (long long)X->rows,
+                (long long)X->cols, (long long)rows, (long long)cols);
+  if (bstride < 3 * X->pstride + (X->rows - 1) * X->ld + X->cols)
+    return fail(QCUR_ERR_SHAPE, "%s: slots overlap (bstride too small)", name);
+  return QCUR_OK;
+}
+
+struct BatchArgs {
+  Slots A;
+  uint64_t seed;
+  int repl;
+  double rtol;
+  int64_t max_rank;
+  int64_t *I, *J;
+  Slots U;
+  double* residual;
+  int64_t* rank_out;
+  double *p, *q;
+};
+
+BatchSpec bspec(int count, const Slots& A, const Slots& B, const Slots& D, const int* M, const int* N,
+                const int* K) {
+  BatchSpec bs;
+  bs.count = count;
+  bs.sA = A.slab;
+  bs.sB = B.slab;
+  bs.sD = D.slab;
+  bs.M = M;
+  bs.N = N;
+  bs.K = K;
+  return bs;
+}
+
+// The batched pipeline: one pass of launches over all problems, no host
+// synchronisation, so a caller may capture it in a graph.
+//
+// The least-squares core is evaluated in an orthonormal form.  Each tall
+// Z = C_b or R_b^H is factored Z = Q T (CholeskyQR, or the Jacobi SVD where
+// the certificate fails) with Z^+ = P^H Q^H, P = T^{-H}.  Then
+//   U = C^+ A R^+ = P_C^H M P_R,   M = Q_C^H A Q_R,   C U R = Q_C M Q_R^H,
+// so the products that touch A run on the orthonormal Q's in the product
+// dtype (rounding errors stay near u ||A||, whatever the conditioning of C
+// and R), and only the small triangular factors P meet M, in FP64.
+qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, BatchWs& w) {
+  const int n = s.count, n2 = 2 * n;
+  const int idt = in_dt(s.compute), adt = acc_dt(s.compute);
+  const int64_t mx = s.mx, nx = s.nx, cx = s.cx, rx = s.rx, px = w.px, qx = w.qx;
+  const bool cast_A = s.a_dt != idt;
+  // probabilities and draws
+  double* p = a.p ? a.p : w.p;
+  double* q = a.q ? a.q : w.q;
+  if (s.sampling == QCUR_LENGTH || cast_A)
+    HIPCHK(launch_norms_batch(c, n, a.A, w.dm, w.dn, mx, nx, w.colpart, w.rowpart, cast_A ? &w.Ax : nullptr));
+  DrawBatch d{};
+  d.dm = w.dm; d.dn = w.dn; d.dc = w.dc; d.dr = w.dr;
+  d.colpart = w.colpart; d.rowpart = w.rowpart;
+  d.mx = mx; d.nx = nx; d.cx = cx; d.rx = rx;
+  d.p = p; d.q = q; d.I = a.I; d.J = a.J;
+  d.seed = a.seed; d.sampling = s.sampling; d.repl = a.repl;
+  HIPCHK(launch_draw_batch(c, n, d));
+  // gathers: C_b = A_b(:, J_b), R_b = A_b(I_b, :)
+  HIPCHK(launch_gather_batch(c, n, a.A, w.dm, w.dn, nullptr, 0, a.J, cx, w.dm, w.dc, mx, cx, w.C64,
+                             idt != QCUR_F64 ? &w.Cx : nullptr));
+  HIPCHK(launch_gather_batch(c, n, a.A, w.dm, w.dn, a.I, rx, nullptr, 0, w.dr, w.dn, rx, nx, w.R64,
+                             idt != QCUR_F64 ? &w.Rx : nullptr));
+  // factors of C_b and R_b^H in FP64
+  const Slots G = sl(w.G, qx, qx, qx), P1 = sl(w.P1, qx, qx, qx), Q = sl(w.Q, px, qx, qx);
+  auto half = [&](const Slots& x) {  // the R_b half of a 2*count array
+    Slots y = x;
+    y.p = (char*)x.p + (size_t)n * x.slab * dtype_size(x.dt);
+    return y;
+  };
+  GroupWs gw{};
+  gw.nb = n2;
+  gw.qq = qx;
+  gw.G = w.G;
+  gw.L = w.L;
+  gw.S = w.Sch;
+  gw.fail = w.fail;
+  gw.gws = w.gws;
+  gw.gws_bytes = w.gws_bytes;
+  HIPCHK(launch_zero_i32(c, w.fail, n2));
+  // G = Z^H Z:  C_b^H C_b  and  R_b R_b^H
+  HIPCHK(launch_gemm_batched(c, QCUR_OP_H, QCUR_OP_N, 1.0, slot_view(w.C64, mx, cx), slot_view(w.C64, mx, cx), 0.0,
+                             slot_view(G, cx, cx), QCUR_F64, w.gws, w.gws_bytes,
+                             bspec(n, w.C64, w.C64, G, w.dc, w.dc, w.dm)));
+  HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_H, 1.0, slot_view(w.R64, rx, nx), slot_view(w.R64, rx, nx), 0.0,
+                             slot_view(half(G), rx, rx), QCUR_F64, w.gws, w.gws_bytes,
+                             bspec(n, w.R64, w.R64, G, w.dr, w.dr, w.dn)));
+  HIPCHK(launch_pad_gram_batch(c, n2, w.G, qx, G.slab, w.zq));
+  CHK(chol_inv(c, gw, w.P1));
+  HIPCHK(launch_sumsq_ragged(c, n, w.C64, w.dm, w.dc, w.norms, 4));
+  HIPCHK(launch_sumsq_ragged(c, n, w.R64, w.dr, w.dn, w.norms + 4 * n, 4));
+  HIPCHK(launch_sumsq_ragged(c, n2, P1, w.zq, w.zq, w.norms + 1, 4));
+  // Q1 = Z P1^H:  C_b P1^H  and  R_b^H P1^H.  The second pass (CholeskyQR2)
+  // runs for every product dtype: one pass leaves Q1^H Q1 - I near
+  // eps kappa^2, which the orthonormal form would carry into C U R.
+  const bool two = true;
+  const Slots Q1 = two ? sl(w.Q1, px, qx, qx) : Q;
+  HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_H, 1.0, slot_view(w.C64, mx, cx), slot_view(P1, cx, cx), 0.0,
+                             slot_view(Q1, mx, cx), QCUR_F64, w.gws, w.gws_bytes,
+                             bspec(n, w.C64, P1, Q1, w.dm, w.dc, w.dc)));
+  HIPCHK(launch_gemm_batched(c, QCUR_OP_H, QCUR_OP_H, 1.0, slot_view(w.R64, rx, nx), slot_view(half(P1), rx, rx),
+                             0.0, slot_view(half(Q1), nx, rx), QCUR_F64, w.gws, w.gws_bytes,
+                             bspec(n, w.R64, P1, Q1, w.dn, w.dr, w.dr)));
+  Slots Pf = P1;
+  if (two) {
+    // CholeskyQR2: Q1^H Q1 = L2 L2^H, P = P2 P1, Q = Q1 P2^H
+    const Slots P2 = sl(w.P2, qx, qx, qx), P = sl(w.P, qx, qx, qx);
+    HIPCHK(launch_gemm_batched(c, QCUR_OP_H, QCUR_OP_N, 1.0, slot_view(Q1, px, qx), slot_view(Q1, px, qx), 0.0,
+                               slot_view(G, qx, qx), QCUR_F64, w.gws, w.gws_bytes,
+                               bspec(n2, Q1, Q1, G, w.zq, w.zq, w.zp)));
+    HIPCHK(launch_pad_gram_batch(c, n2, w.G, qx, G.slab, w.zq));
+    CHK(chol_inv(c, gw, w.P2));
+    HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_N, 1.0, slot_view(P2, qx, qx), slot_view(P1, qx, qx), 0.0,
+                               slot_view(P, qx, qx), QCUR_F64, w.gws, w.gws_bytes,
+                               bspec(n2, P2, P1, P, w.zq, w.zq, w.zq)));
+    HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_H, 1.0, slot_view(Q1, px, qx), slot_view(P2, qx, qx), 0.0,
+                               slot_view(Q, px, qx), QCUR_F64, w.gws, w.gws_bytes,
+                               bspec(n2, Q1, P2, Q, w.zp, w.zq, w.zq)));
+    Pf = P;
+  }
+  HIPCHK(launch_sumsq_ragged(c, n2, Pf, w.zq, w.zq, w.norms + 2, 4));
+  int64_t* ranks = a.rank_out ? a.rank_out : w.ranks;
+  HIPCHK(launch_decide_batch(c, n2, n, w.norms, w.fail, a.rtol, a.max_rank, w.zp, w.zq, ranks, w.ok));
+  {
+    // problems whose certificate failed: Jacobi SVD, same (Q, P) form
+    JacobiBatch jb{};
+    jb.ok = w.ok;
+    jb.Cz = (const double*)w.C64.p; jb.cld = w.C64.ld; jb.cps = w.C64.ps; jb.cslab = w.C64.slab;
+    jb.Rz = (const double*)w.R64.p; jb.rld = w.R64.ld; jb.rps = w.R64.ps; jb.rslab = w.R64.slab;
+    jb.dm = w.dm; jb.dn = w.dn; jb.dc = w.dc; jb.dr = w.dr;
+    jb.Y = w.Y; jb.V = w.V;
+    jb.yslab = 4 * px * qx;
+    jb.vslab = 4 * qx * qx;
+    jb.Q = (double*)Q.p; jb.qld = Q.ld; jb.qps = Q.ps; jb.qslab = Q.slab;
+    jb.P = (double*)Pf.p; jb.pld = Pf.ld; jb.pps = Pf.ps; jb.pslab = Pf.slab;
+    jb.rank_out = ranks;
+    jb.rtol = a.rtol;
+    jb.max_rank = a.max_rank;
+    jb.count = n;
+    jb.max_sweeps = MAX_SWEEPS;
+    HIPCHK(launch_jacobi_pinv_batch(c, jb, n2));
+  }
+  // orthonormal factors in the product dtype
+  Slots Qc = Q, Qr = half(Q);
+  if (idt != QCUR_F64) {
+    HIPCHK(launch_cast_batch(c, n, Q, w.Qcx, w.dm, w.dc, mx, cx, CAST_COPY));
+    HIPCHK(launch_cast_batch(c, n, half(Q), w.Qrx, w.dn, w.dr, nx, rx, CAST_COPY));
+    Qc = w.Qcx;
+    Qr = w.Qrx;
+  }
+  // M = Q_C^H (A Q_R)
+  const Slots Ain = cast_A ? w.Ax : a.A;
+  HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_N, 1.0, slot_view(Ain, mx, nx), slot_view(Qr, nx, rx), 0.0,
+                             slot_view(w.T, mx, rx), s.compute, w.gws, w.gws_bytes,
+                             bspec(n, Ain, Qr, w.T, w.dm, w.dr, w.dn)));
+  if (w.Tx.p != w.T.p) HIPCHK(launch_cast_batch(c, n, w.T, w.Tx, w.dm, w.dr, mx, rx, CAST_COPY));
+  HIPCHK(launch_gemm_batched(c, QCUR_OP_H, QCUR_OP_N, 1.0, slot_view(Qc, mx, cx), slot_view(w.Tx, mx, rx), 0.0,
+                             slot_view(w.M, cx, rx), s.compute, w.gws, w.gws_bytes,
+                             bspec(n, Qc, w.Tx, w.M, w.dc, w.dr, w.dm)));
+  auto left_factor = [&]() -> qcur_status {  // B1 = Q_C M in the product dtype
+    if (w.Mx.p != w.M.p) HIPCHK(launch_cast_batch(c, n, w.M, w.Mx, w.dc, w.dr, cx, rx, CAST_COPY));
+    HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_N, 1.0, slot_view(Qc, mx, cx), slot_view(w.Mx, cx, rx), 0.0,
+                               slot_view(w.B1, mx, rx), s.compute, w.gws, w.gws_bytes,
+                               bspec(n, Qc, w.Mx, w.B1, w.dm, w.dr, w.dc)));
+    if (w.B1x.p != w.B1.p) HIPCHK(launch_cast_batch(c, n, w.B1, w.B1x, w.dm, w.dr, mx, rx, CAST_COPY));
+    return QCUR_OK;
+  };
+  for (int st = 0; st < s.refine; ++st) {
+    // E = A - Q_C M Q_R^H;  M += Q_C^H (E Q_R)
+    CHK(left_factor());
+    HIPCHK(launch_residual_gemm_batched(c, n, a.A, w.B1x, Qr, QCUR_OP_H, mx, nx, rx, w.dm, w.dn, w.dr, s.compute,
+                                        w.part, &w.E, 1.0));
+    if (w.Ex.p != w.E.p) HIPCHK(launch_cast_batch(c, n, w.E, w.Ex, w.dm, w.dn, mx, nx, CAST_COPY));
+    HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_N, 1.0, slot_view(w.Ex, mx, nx), slot_view(Qr, nx, rx), 0.0,
+                               slot_view(w.T, mx, rx), s.compute, w.gws, w.gws_bytes,
+                               bspec(n, w.Ex, Qr, w.T, w.dm, w.dr, w.dn)));
+    if (w.Tx.p != w.T.p) HIPCHK(launch_cast_batch(c, n, w.T, w.Tx, w.dm, w.dr, mx, rx, CAST_COPY));
+    HIPCHK(launch_gemm_batched(c, QCUR_OP_H, QCUR_OP_N, 1.0, slot_view(Qc, mx, cx), slot_view(w.Tx, mx, rx), 1.0,
+                               slot_view(w.M, cx, rx), s.compute, w.gws, w.gws_bytes,
+                               bspec(n, Qc, w.Tx, w.M, w.dc, w.dr, w.dm)));
+  }
+  // residual_b = ||A_b - Q_C M Q_R^H||_F = ||A_b - C_b U_b R_b||_F
+  CHK(left_factor());
+  HIPCHK(launch_residual_gemm_batched(c, n, a.A, w.B1x, Qr, QCUR_OP_H, mx, nx, rx, w.dm, w.dn, w.dr, s.compute,
+                                      w.part, nullptr, 0.0));
+  HIPCHK(launch_resid_sum_batch(c, n, w.part, w.tiles, a.residual));
+  // U = P_C^H M P_R in FP64
+  if (w.M64.p != w.M.p) HIPCHK(launch_cast_batch(c, n, w.M, w.M64, w.dc, w.dr, cx, rx, CAST_COPY));
+  HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_N, 1.0, slot_view(w.M64, cx, rx), slot_view(half(Pf), rx, rx), 0.0,
+                             slot_view(w.W1, cx, rx), QCUR_F64, w.gws, w.gws_bytes,
+                             bspec(n, w.M64, Pf, w.W1, w.dc, w.dr, w.dr)));
+  const Slots U64 = adt == QCUR_F64 ? a.U : w.U64;
+  HIPCHK(launch_gemm_batched(c, QCUR_OP_H, QCUR_OP_N, 1.0, slot_view(Pf, cx, cx), slot_view(w.W1, cx, rx), 0.0,
+                             slot_view(U64, cx, rx), QCUR_F64, w.gws, w.gws_bytes,
+                             bspec(n, Pf, w.W1, U64, w.dc, w.dr, w.dc)));
+  if (U64.p != a.U.p) HIPCHK(launch_cast_batch(c, n, U64, a.U, w.dc, w.dr, cx, rx, CAST_COPY));
+  (void)adt;
+  return QCUR_OK;
+}
+
 }  // namespace
 
 // ============================================================================
@@ -1221,6 +1597,109 @@ qcur_status qcur_solve(qcur_handle h, const qcur_qmat* A, int64_t c, int64_t r, 
   CHK(check_handle(h));
   Bump b(ws);
   return solve_run(h->c, s, b, false);
+}
+
+// ---- batched solve ------------------------------------------------------------
+size_t qcur_batch_workspace(int32_t count, const int32_t* dims, int a_dtype, int sampling, int compute,
+                            int refine_steps) {
+  BatchShape s{};
+  if (check_batch_shape(count, dims, a_dtype, sampling, compute, refine_steps, 1, &s) != QCUR_OK) return 0;
+  Bump b(nullptr);
+  batch_carve(b, s);
+  return b.used + 256;
+}
+
+qcur_status qcur_batch_prepare(qcur_handle h, int32_t count, const int32_t* dims, int a_dtype, int sampling,
+                               int compute, int refine_steps, void* ws, size_t ws_bytes) {
+  BatchShape s{};
+  CHK(check_batch_shape(count, dims, a_dtype, sampling, compute, refine_steps, 1, &s));
+  {
+    Bump sz(nullptr);
+    batch_carve(sz, s);
+    if (!ws || ws_bytes < sz.used + 256) return fail(QCUR_ERR_WORKSPACE, "batch needs %zu workspace bytes", sz.used + 256);
+  }
+  CHK(check_handle(h));
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  HIPCHK(hipStreamIsCapturing(h->c.stream, &cap));
+  if (cap != hipStreamCaptureStatusNone) return fail(QCUR_ERR_ARG, "qcur_batch_prepare cannot run under stream capture");
+  Bump b(ws);
+  BatchWs w = batch_carve(b, s);
+  // dm, dn, dc, dr (count each), then zp, zq (2 * count each)
+  std::vector<int> hdr((size_t)8 * count);
+  int* hm = hdr.data();
+  int *hn = hm + count, *hc = hn + count, *hr = hc + count, *hp = hr + count, *hq = hp + 2 * count;
+  for (int i = 0; i < count; ++i) {
+    hm[i] = dims[4 * i];
+    hn[i] = dims[4 * i + 1];
+    hc[i] = dims[4 * i + 2];
+    hr[i] = dims[4 * i + 3];
+    hp[i] = hm[i];
+    hq[i] = hc[i];
+    hp[count + i] = hn[i];
+    hq[count + i] = hr[i];
+  }
+  // the header arrays were carved back to back except for 256-byte alignment
+  const int* srcs[6] = {hm, hn, hc, hr, hp, hq};
+  int* dsts[6] = {w.dm, w.dn, w.dc, w.dr, w.zp, w.zq};
+  const size_t lens[6] = {(size_t)count, (size_t)count, (size_t)count, (size_t)count, (size_t)2 * count,
+                          (size_t)2 * count};
+  for (int k = 0; k < 6; ++k)
+    HIPCHK(hipMemcpyAsync(dsts[k], srcs[k], lens[k] * sizeof(int), hipMemcpyHostToDevice, h->c.stream));
+  HIPCHK(hipStreamSynchronize(h->c.stream));
+  const uint64_t key = batch_key(s);
+  int slot = -1;
+  for (int k = 0; k < 8; ++k)
+    if (h->batches[k].ws == ws) slot = k;
+  if (slot < 0) {
+    slot = h->next_batch;
+    h->next_batch = (h->next_batch + 1) % 8;
+  }
+  h->batches[slot].ws = ws;
+  h->batches[slot].key = key;
+  return QCUR_OK;
+}
+
+qcur_status qcur_solve_batched(qcur_handle h, int32_t count, const int32_t* dims, const qcur_qmat* A,
+                               int64_t a_bstride, int sampling, int compute, uint64_t seed, int with_replacement,
+                               int refine_steps, double rtol, int64_t max_rank, int64_t* I, int64_t* J,
+                               qcur_qmat* U, int64_t u_bstride, double* residual, int64_t* rank_out, double* p_col,
+                               double* q_row, void* ws, size_t ws_bytes) {
+  if (with_replacement != 0 && with_replacement != 1) return fail(QCUR_ERR_ARG, "with_replacement must be 0 or 1");
+  if (!A) return fail(QCUR_ERR_ARG, "A is NULL");
+  BatchShape s{};
+  CHK(check_batch_shape(count, dims, (int)A->dtype, sampling, compute, refine_steps, with_replacement, &s));
+  CHK(check_slotted(A, "A", s.mx, s.nx, a_bstride));
+  CHK(check_slotted(U, "U", s.cx, s.rx, u_bstride));
+  if (U->dtype != acc_dt(compute)) return fail(QCUR_ERR_DTYPE, "U must be FP64 (F64 compute) or FP32");
+  if (!I || !J || !residual) return fail(QCUR_ERR_ARG, "I, J and residual must not be NULL");
+  if (!std::isfinite(rtol)) return fail(QCUR_ERR_ARG, "rtol must be finite");
+  if (max_rank < 0) return fail(QCUR_ERR_ARG, "max_rank must be >= 0");
+  {
+    Bump sz(nullptr);
+    batch_carve(sz, s);
+    if (!ws || ws_bytes < sz.used + 256) return fail(QCUR_ERR_WORKSPACE, "batch needs %zu workspace bytes", sz.used + 256);
+  }
+  CHK(check_handle(h));
+  const uint64_t key = batch_key(s);
+  bool prepared = false;
+  for (int k = 0; k < 8; ++k) prepared |= (h->batches[k].ws == ws && h->batches[k].key == key);
+  if (!prepared) return fail(QCUR_ERR_ARG, "the workspace was not prepared for this batch (qcur_batch_prepare)");
+  Bump b(ws);
+  BatchWs w = batch_carve(b, s);
+  BatchArgs a{};
+  a.A = Slots{A->p, A->ld, A->pstride, a_bstride, (int)A->dtype};
+  a.seed = seed;
+  a.repl = with_replacement;
+  a.rtol = rtol;
+  a.max_rank = max_rank;
+  a.I = I;
+  a.J = J;
+  a.U = Slots{U->p, U->ld, U->pstride, u_bstride, (int)U->dtype};
+  a.residual = residual;
+  a.rank_out = rank_out;
+  a.p = p_col;
+  a.q = q_row;
+  return batch_run(h->c, s, a, w);
 }
 
 qcur_status qcur_cast(qcur_handle h, const qcur_qmat* X, qcur_qmat* Y) {

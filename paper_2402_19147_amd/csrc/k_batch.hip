@@ -1,0 +1,316 @@
+// Element-wise and reduction kernels of the batched QMCUR path: many
+// independent problems of uneven sizes, each in its own slot of the batched
+// arrays.  The grid spans the largest problem; the z (or x) index selects the
+// problem, and a workgroup whose tile lies outside its problem returns at
+// once.  Every reduction runs in a fixed order, so results do not depend on
+// scheduling.
+#include <algorithm>
+
+#include "qcur_internal.hpp"
+
+namespace qcur {
+
+namespace {
+
+template <typename T> __device__ inline double ld_d(const T* p, int64_t o);
+template <> __device__ inline double ld_d<double>(const double* p, int64_t o) { return p[o]; }
+template <> __device__ inline double ld_d<float>(const float* p, int64_t o) { return (double)p[o]; }
+template <> __device__ inline double ld_d<uint16_t>(const uint16_t* p, int64_t o) {
+  return (double)bf16_to_f32(p[o]);
+}
+template <typename T> __device__ inline void st_d(T* p, int64_t o, double v);
+template <> __device__ inline void st_d<double>(double* p, int64_t o, double v) { p[o] = v; }
+template <> __device__ inline void st_d<float>(float* p, int64_t o, double v) { p[o] = (float)v; }
+template <> __device__ inline void st_d<uint16_t>(uint16_t* p, int64_t o, double v) {
+  p[o] = f32_to_bf16((float)v);
+}
+
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Fixed-order sum of one value per thread of a 256-thread workgroup.
+__device__ inline double block_sum_256(double v, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+// Dispatch on the run-time dtype of a slot array.
+template <typename F>
+hipError_t by_dtype(int dt, F&& f) {
+  switch (dt) {
+    case QCUR_F64: f((double*)nullptr); break;
+    case QCUR_F32: f((float*)nullptr); break;
+    default: f((uint16_t*)nullptr);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// ---- norm pass (length probabilities, Section 3.1) ------------------------
+// Workgroup (x, y, b) covers rows [32y, 32y+32) and columns [256x, 256x+256)
+// of A_b: colpart[b][y][j] = sum over its rows of |a_ij|^2 and
+// rowpart[b][x][i] = sum over its columns.  With Ax, the tile is also copied
+// into the product dtype (fusing the cast into the one pass over A).
+template <typename TI, typename TX>
+__global__ __launch_bounds__(256) void kb_norms(const TI* __restrict__ A, int64_t lda, int64_t psa, int64_t sa,
+                                                const int* __restrict__ dm, const int* __restrict__ dn,
+                                                int64_t mx, int64_t nx, double* __restrict__ colpart,
+                                                double* __restrict__ rowpart, TX* __restrict__ Ax, int64_t ldx,
+                                                int64_t psx, int64_t sx) {
+  __shared__ double ws[4][BATCH_RB];
+  const int b = blockIdx.z, t = threadIdx.x;
+  const int64_t m = dm[b], n = dn[b];
+  const int64_t i0 = (int64_t)blockIdx.y * BATCH_RB, j0 = (int64_t)blockIdx.x * 256;
+  if (i0 >= m || j0 >= n) return;  // uniform over the workgroup
+  const int64_t nrbx = (mx + BATCH_RB - 1) / BATCH_RB, ncbx = (nx + 255) / 256;
+  const int64_t j = j0 + t;
+  const int64_t i1 = min(m, i0 + BATCH_RB);
+  const TI* Ab = A + (int64_t)b * sa;
+  double cacc = 0.0;
+  for (int64_t i = i0; i < i1; ++i) {
+    double s = 0.0;
+    if (j < n) {
+      const int64_t o = i * lda + j;
+      const double a0 = ld_d(Ab, o), a1 = ld_d(Ab, o + psa), a2 = ld_d(Ab, o + 2 * psa), a3 = ld_d(Ab, o + 3 * psa);
+      s = a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3;
+      if (Ax) {
+        TX* X = Ax + (int64_t)b * sx + i * ldx + j;
+        st_d(X, 0, a0);
+        st_d(X, psx, a1);
+        st_d(X, 2 * psx, a2);
+        st_d(X, 3 * psx, a3);
+      }
+    }
+    cacc += s;
+    const double w = wave_sum_d(s);
+    if ((t & 63) == 0) ws[t >> 6][i - i0] = w;
+  }
+  __syncthreads();
+  for (int64_t k = t; k < i1 - i0; k += 256)
+    rowpart[((int64_t)b * ncbx + blockIdx.x) * mx + i0 + k] = ((ws[0][k] + ws[1][k]) + ws[2][k]) + ws[3][k];
+  if (j < n) colpart[((int64_t)b * nrbx + blockIdx.y) * nx + j] = cacc;
+}
+
+hipError_t launch_norms_batch(const Ctx& c, int count, Slots A, const int* dm, const int* dn, int64_t mx,
+                              int64_t nx, double* colpart, double* rowpart, const Slots* Ax) {
+  if (count <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((nx + 255) / 256), (unsigned)((mx + BATCH_RB - 1) / BATCH_RB), (unsigned)count);
+  return by_dtype(A.dt, [&](auto* ti) {
+    typedef std::remove_pointer_t<decltype(ti)> TI;
+    const int xdt = Ax ? Ax->dt : QCUR_F32;
+    by_dtype(xdt, [&](auto* tx) {
+      typedef std::remove_pointer_t<decltype(tx)> TX;
+      hipLaunchKernelGGL((kb_norms<TI, TX>), grid, dim3(256), 0, c.stream, (const TI*)A.p, A.ld, A.ps, A.slab, dm,
+                         dn, mx, nx, colpart, rowpart, Ax ? (TX*)Ax->p : (TX*)nullptr, Ax ? Ax->ld : 0,
+                         Ax ? Ax->ps : 0, Ax ? Ax->slab : 0);
+    });
+  });
+}
+
+// ---- gathers (Algorithm 1, steps 1-2) ----------------------------------------
+// O_b[s][t] = A_b[rows(s)][cols(t)] for s < orows[b], t < ocols[b], where the
+// index lists (slots of stride ris/cis) or the identity give rows and
+// columns.  An index outside A_b writes zeros and raises ST_ARG; a
+// non-finite gathered value raises ST_NUMERIC.
+template <typename TI, typename TX>
+__global__ __launch_bounds__(256) void kb_gather(const TI* __restrict__ A, int64_t lda, int64_t psa, int64_t sa,
+                                                 const int* __restrict__ dm, const int* __restrict__ dn,
+                                                 const int64_t* __restrict__ ridx, int64_t ris,
+                                                 const int64_t* __restrict__ cidx, int64_t cis,
+                                                 const int* __restrict__ orows, const int* __restrict__ ocols,
+                                                 double* __restrict__ O, int64_t ldo, int64_t pso, int64_t so,
+                                                 TX* __restrict__ Ox, int64_t ldx, int64_t psx, int64_t sx,
+                                                 unsigned* status) {
+  const int b = blockIdx.z;
+  const int64_t rows = orows[b], cols = ocols[b];
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= cols) return;  // no barriers below
+  const int64_t m = dm[b], n = dn[b];
+  const TI* Ab = A + (int64_t)b * sa;
+  const int64_t j = cidx ? cidx[(int64_t)b * cis + t] : t;
+  for (int64_t s = blockIdx.y; s < rows; s += gridDim.y) {
+    const int64_t i = ridx ? ridx[(int64_t)b * ris + s] : s;
+    const bool ok = i >= 0 && i < m && j >= 0 && j < n;
+    if (!ok) atomicOr(status, ST_ARG);
+    const int64_t src = i * lda + j;
+    const int64_t dst = s * ldo + t, dx = s * ldx + t;
+    bool finite = true;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double v = ok ? ld_d(Ab, src + k * psa) : 0.0;
+      finite &= isfinite(v);
+      O[(int64_t)b * so + dst + k * pso] = v;
+      if (Ox) st_d(Ox + (int64_t)b * sx, dx + k * psx, v);
+    }
+    if (!finite) atomicOr(status, ST_NUMERIC);
+  }
+}
+
+hipError_t launch_gather_batch(const Ctx& c, int count, Slots A, const int* dm, const int* dn,
+                               const int64_t* ridx, int64_t ris, const int64_t* cidx, int64_t cis,
+                               const int* orows, const int* ocols, int64_t rowsx, int64_t colsx, Slots O,
+                               const Slots* Ox) {
+  if (count <= 0 || rowsx <= 0 || colsx <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((colsx + 255) / 256), (unsigned)std::min<int64_t>(rowsx, 1024), (unsigned)count);
+  return by_dtype(A.dt, [&](auto* ti) {
+    typedef std::remove_pointer_t<decltype(ti)> TI;
+    const int xdt = Ox ? Ox->dt : QCUR_F32;
+    by_dtype(xdt, [&](auto* tx) {
+      typedef std::remove_pointer_t<decltype(tx)> TX;
+      hipLaunchKernelGGL((kb_gather<TI, TX>), grid, dim3(256), 0, c.stream, (const TI*)A.p, A.ld, A.ps, A.slab,
+                         dm, dn, ridx, ris, cidx, cis, orows, ocols, (double*)O.p, O.ld, O.ps, O.slab,
+                         Ox ? (TX*)Ox->p : (TX*)nullptr, Ox ? Ox->ld : 0, Ox ? Ox->ps : 0, Ox ? Ox->slab : 0,
+                         c.status);
+    });
+  });
+}
+
+// ---- casts --------------------------------------------------------------------
+// Y_b = X_b (rows[b] x cols[b]) with optional transpose (mode bit 1) and
+// quaternion conjugation (mode bit 2).
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void kb_cast(const TI* __restrict__ X, int64_t ldx, int64_t psx, int64_t sx,
+                                               TO* __restrict__ Y, int64_t ldy, int64_t psy, int64_t sy,
+                                               const int* __restrict__ rows, const int* __restrict__ cols,
+                                               int mode) {
+  const int b = blockIdx.z;
+  const int64_t R = rows[b], C = cols[b];
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= C) return;
+  const TI* Xb = X + (int64_t)b * sx;
+  TO* Yb = Y + (int64_t)b * sy;
+  for (int64_t i = blockIdx.y; i < R; i += gridDim.y) {
+    const int64_t src = i * ldx + j;
+    const int64_t dst = (mode & 1) ? (j * ldy + i) : (i * ldy + j);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double v = ld_d(Xb, src + k * psx);
+      if ((mode & 2) && k > 0) v = -v;
+      st_d(Yb, dst + k * psy, v);
+    }
+  }
+}
+
+hipError_t launch_cast_batch(const Ctx& c, int count, Slots X, Slots Y, const int* rows, const int* cols,
+                             int64_t rowsx, int64_t colsx, int mode) {
+  if (count <= 0 || rowsx <= 0 || colsx <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((colsx + 255) / 256), (unsigned)std::min<int64_t>(rowsx, 1024), (unsigned)count);
+  return by_dtype(X.dt, [&](auto* ti) {
+    typedef std::remove_pointer_t<decltype(ti)> TI;
+    by_dtype(Y.dt, [&](auto* to) {
+      typedef std::remove_pointer_t<decltype(to)> TO;
+      hipLaunchKernelGGL((kb_cast<TI, TO>), grid, dim3(256), 0, c.stream, (const TI*)X.p, X.ld, X.ps, X.slab,
+                         (TO*)Y.p, Y.ld, Y.ps, Y.slab, rows, cols, mode);
+    });
+  });
+}
+
+// ---- pseudoinverse helpers ---------------------------------------------------
+// The Gram matrices of the problems share n x n slots; outside problem t's
+// q_t x q_t block the slot is set to the identity, which leaves the Cholesky
+// factor and its inverse of the real block unchanged.
+__global__ __launch_bounds__(256) void kb_pad_gram(double* G, int64_t n, int64_t slab, const int* __restrict__ zq) {
+  const int t = blockIdx.y;
+  const int64_t q = zq[t];
+  const int64_t nn = n * n;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nn; e += (int64_t)gridDim.x * 256) {
+    const int64_t i = e / n, j = e % n;
+    if (i < q && j < q) continue;
+    double* g = G + (int64_t)t * slab + e;
+    g[0] = (i == j) ? 1.0 : 0.0;
+    g[nn] = 0.0;
+    g[2 * nn] = 0.0;
+    g[3 * nn] = 0.0;
+  }
+}
+
+hipError_t launch_pad_gram_batch(const Ctx& c, int count, double* G, int64_t n, int64_t slab, const int* zq) {
+  if (count <= 0 || n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n * n + 255) / 256, 64);
+  hipLaunchKernelGGL(kb_pad_gram, dim3((unsigned)blocks, (unsigned)count), dim3(256), 0, c.stream, G, n, slab, zq);
+  return hipGetLastError();
+}
+
+// out[b * ostride] = ||X_b||_F^2 over its rows[b] x cols[b] block.
+__global__ __launch_bounds__(256) void kb_sumsq(const double* __restrict__ X, int64_t ld, int64_t ps, int64_t slab,
+                                                const int* __restrict__ rows, const int* __restrict__ cols,
+                                                double* out, int ostride) {
+  __shared__ double red[256];
+  const int b = blockIdx.x;
+  const int64_t R = rows[b], C = cols[b];
+  const double* Xb = X + (int64_t)b * slab;
+  double s = 0.0;
+  for (int64_t e = threadIdx.x; e < R * C; e += 256) {
+    const int64_t o = (e / C) * ld + (e % C);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s += Xb[o + k * ps] * Xb[o + k * ps];
+  }
+  s = block_sum_256(s, red);
+  if (threadIdx.x == 0) out[(int64_t)b * ostride] = s;
+}
+
+hipError_t launch_sumsq_ragged(const Ctx& c, int count, Slots X, const int* rows, const int* cols, double* out,
+                               int ostride) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kb_sumsq, dim3((unsigned)count), dim3(256), 0, c.stream, (const double*)X.p, X.ld, X.ps,
+                     X.slab, rows, cols, out, ostride);
+  return hipGetLastError();
+}
+
+// CholeskyQR certificate per problem (the rule of the single-matrix path):
+// kappa_F = ||Z||_F ||P||_F bounds the condition number; the fast result is
+// kept when Cholesky succeeded, kappa_F1 < 1e7, kappa_F * rtol < 1e-2 and no
+// rank cap below q applies.  rtol < 0 means max(p, q) * 2^-52.
+__global__ __launch_bounds__(256) void kb_decide(const double* __restrict__ norms, const int* __restrict__ fail,
+                                                 double rtol, int64_t max_rank, const int* __restrict__ zp,
+                                                 const int* __restrict__ zq, int count2, int count,
+                                                 int64_t* rank_out, int* ok) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= count2) return;
+  const int64_t p = zp[t], q = zq[t];
+  const double rt = rtol < 0.0 ? (double)(p > q ? p : q) * 0x1p-52 : rtol;
+  const double z2 = norms[4 * t], p1 = norms[4 * t + 1], p2 = norms[4 * t + 2];
+  const double k1 = sqrt(z2) * sqrt(p1);
+  const double k = sqrt(z2) * sqrt(p2);
+  const bool good = fail[t] == 0 && z2 > 0.0 && k1 < 1e7 && k * rt < 1e-2 && k < INFINITY &&
+                    (max_rank <= 0 || max_rank >= q);
+  ok[t] = good ? 1 : 0;
+  if (good && rank_out) rank_out[t < count ? 2 * t : 2 * (t - count) + 1] = q;
+}
+
+hipError_t launch_decide_batch(const Ctx& c, int count2, int count, const double* norms, const int* fail,
+                               double rtol, int64_t max_rank, const int* zp, const int* zq, int64_t* rank_out,
+                               int* ok) {
+  if (count2 <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kb_decide, dim3((unsigned)((count2 + 255) / 256)), dim3(256), 0, c.stream, norms, fail, rtol,
+                     max_rank, zp, zq, count2, count, rank_out, ok);
+  return hipGetLastError();
+}
+
+// residual_b = sqrt(sum of problem b's tile partials), in tile order.
+__global__ __launch_bounds__(256) void kb_resid_sum(const double* __restrict__ part, int64_t tiles, double* out) {
+  __shared__ double red[256];
+  const int b = blockIdx.x;
+  double s = 0.0;
+  for (int64_t k = threadIdx.x; k < tiles; k += 256) s += part[(int64_t)b * tiles + k];
+  s = block_sum_256(s, red);
+  if (threadIdx.x == 0) out[b] = sqrt(s);
+}
+
+hipError_t launch_resid_sum_batch(const Ctx& c, int count, const double* part, int64_t tiles, double* out) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kb_resid_sum, dim3((unsigned)count), dim3(256), 0, c.stream, part, tiles, out);
+  return hipGetLastError();
+}
+
+}  // namespace qcur

@@ -89,13 +89,10 @@ struct DrawJobs {
   DrawJob j[2];
 };
 
-__global__ __launch_bounds__(DRAW_THREADS) void k_draw(DrawJobs jobs, int repl, unsigned* status) {
-  const DrawJob& job = jobs.j[blockIdx.x];
-  const double* __restrict__ probs = job.probs;
-  const int64_t n = job.n, count = job.count;
-  const uint64_t seed = job.seed, set_id = job.set_id;
-  int64_t* __restrict__ idx = job.idx;
-  extern __shared__ uint64_t lds[];
+// One draw job run by the whole workgroup (DRAW_THREADS threads); lds holds
+// draw_lds(n, repl) bytes.
+__device__ void draw_body(const double* __restrict__ probs, int64_t n, int64_t count, uint64_t seed,
+                          uint64_t set_id, int repl, int64_t* __restrict__ idx, unsigned* status, uint64_t* lds) {
   const int64_t npad = (n + 63) / 64 * 64;
   const int64_t nb = npad / 64;
   const int64_t nsb = (nb + 63) / 64;
@@ -226,7 +223,13 @@ __global__ __launch_bounds__(DRAW_THREADS) void k_draw(DrawJobs jobs, int repl, 
   }
 }
 
-static size_t draw_lds(int64_t n, int repl) {
+__global__ __launch_bounds__(DRAW_THREADS) void k_draw(DrawJobs jobs, int repl, unsigned* status) {
+  extern __shared__ uint64_t lds[];
+  const DrawJob& job = jobs.j[blockIdx.x];
+  draw_body(job.probs, job.n, job.count, job.seed, job.set_id, repl, job.idx, status, lds);
+}
+
+size_t draw_lds(int64_t n, int repl) {
   const int64_t npad = (n + 63) / 64 * 64;
   const int64_t nb = npad / 64;
   size_t lds = (size_t)(npad + nb + 64) * 8;
@@ -259,6 +262,70 @@ hipError_t launch_draw_pair(const Ctx& c, const double* p0, int64_t n0, int64_t 
   jobs.j[1] = DrawJob{p1, n1, count1, seed, set1, idx1};
   const size_t lds = std::max(draw_lds(n0, with_replacement), draw_lds(n1, with_replacement));
   return draw_jobs(c, jobs, 2, with_replacement, lds);
+}
+
+// Batched draws: workgroup (set, b) draws J_b (set 0: c_b indices from the
+// column probabilities) or I_b (set 1: r_b indices from the row
+// probabilities) of problem b with the seed seed + b, so that problem b
+// repeats the single solve seeded with seed + b.  Length probabilities are
+// folded here from the batched norm pass: col2_j sums the row tiles and
+// row2_i the column tiles in index order, ||A_b||_F^2 is a fixed-order sum
+// of col2 (computed alike by both workgroups of a problem), and
+// p_j = col2_j / ||A_b||_F^2 (Section 3.1).  Uniform: p_j = 1/n_b.
+__global__ __launch_bounds__(DRAW_THREADS) void kb_draw(DrawBatch d, unsigned* status) {
+  extern __shared__ uint64_t lds[];
+  __shared__ double red[DRAW_THREADS];
+  const int set = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+  const int64_t m = d.dm[b], n = d.dn[b];
+  const int64_t len = set == 0 ? n : m;
+  double* pr = set == 0 ? d.p + (int64_t)b * d.nx : d.q + (int64_t)b * d.mx;
+  if (d.sampling == QCUR_UNIFORM) {
+    const double u = 1.0 / (double)len;
+    for (int64_t j = tid; j < len; j += DRAW_THREADS) pr[j] = u;
+  } else {
+    const int64_t nrbx = (d.mx + BATCH_RB - 1) / BATCH_RB, ncbx = (d.nx + 255) / 256;
+    const int64_t nrb = (m + BATCH_RB - 1) / BATCH_RB, ncb = (n + 255) / 256;
+    const double* cp = d.colpart + (int64_t)b * nrbx * d.nx;
+    double s = 0.0;
+    for (int64_t j = tid; j < n; j += DRAW_THREADS) {
+      double c2 = 0.0;
+      for (int64_t r = 0; r < nrb; ++r) c2 += cp[r * d.nx + j];
+      s += c2;
+    }
+    red[tid] = s;
+    __syncthreads();
+    for (int w = DRAW_THREADS / 2; w >= 1; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    const double fro2 = red[0];
+    if (tid == 0 && set == 0 && !(fro2 > 0.0 && fro2 < INFINITY)) atomicOr(status, ST_NUMERIC);
+    if (set == 0) {
+      for (int64_t j = tid; j < n; j += DRAW_THREADS) {
+        double c2 = 0.0;
+        for (int64_t r = 0; r < nrb; ++r) c2 += cp[r * d.nx + j];
+        pr[j] = c2 / fro2;
+      }
+    } else {
+      const double* rp = d.rowpart + (int64_t)b * ncbx * d.mx;
+      for (int64_t i = tid; i < m; i += DRAW_THREADS) {
+        double r2 = 0.0;
+        for (int64_t cb = 0; cb < ncb; ++cb) r2 += rp[cb * d.mx + i];
+        pr[i] = r2 / fro2;
+      }
+    }
+  }
+  __syncthreads();  // the probabilities written above are read back by the whole workgroup
+  const int64_t count = set == 0 ? d.dc[b] : d.dr[b];
+  int64_t* idx = set == 0 ? d.J + (int64_t)b * d.cx : d.I + (int64_t)b * d.rx;
+  draw_body(pr, len, count, d.seed + (uint64_t)b, (uint64_t)set, d.repl, idx, status, lds);
+}
+
+hipError_t launch_draw_batch(const Ctx& c, int count, const DrawBatch& d) {
+  if (count <= 0) return hipSuccess;
+  const size_t lds = draw_lds(std::max(d.mx, d.nx), d.repl);
+  hipLaunchKernelGGL(kb_draw, dim3(2, (unsigned)count), dim3(DRAW_THREADS), lds, c.stream, d, c.status);
+  return hipGetLastError();
 }
 
 }  // namespace qcur

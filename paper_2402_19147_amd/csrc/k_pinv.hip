@@ -301,3 +301,149 @@ hipError_t launch_pinv_apply(const Ctx& c, double* Y, int64_t p, int64_t q, doub
 }
 
 }  // namespace qcur
+
+namespace qcur {
+
+// ---------------------------------------------------------------------------
+// Batched fallback.  For every problem t whose CholeskyQR certificate failed
+// (ok[t] == 0), one workgroup runs the whole one-sided Jacobi SVD above on a
+// working copy in global memory and writes the factors of the orthonormal
+// form Z^+ = P^H Q^H used by the batched core: with s_k = 1/sigma_k for kept
+// singular values and 0 otherwise, Q[:, k] = Y_k s_k (orthonormal or zero
+// columns) and P[k][a] = conj(V_{a,k}) s_k, so that P^H Q^H = V D Y^H.
+// Problem t < count is C_b (m_b x c_b, Z = C_b); t >= count is R_b
+// (r_b x n_b), handled as Z = R_b^H.
+__global__ __launch_bounds__(1024) void kb_jacobi_pinv(JacobiBatch jb) {
+  const int t = blockIdx.x;
+  if (jb.ok[t]) return;  // uniform over the workgroup
+  __shared__ int any;
+  __shared__ double sig2[JB_MAXQ];
+  __shared__ double scl[JB_MAXQ];
+  __shared__ double red[1024];
+  __shared__ long long cnt[1024];
+  const bool isC = t < jb.count;
+  const int b = isC ? t : t - jb.count;
+  const int64_t p = isC ? jb.dm[b] : jb.dn[b];
+  const int64_t q = isC ? jb.dc[b] : jb.dr[b];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* Y = jb.Y + (int64_t)t * jb.yslab;
+  double* V = jb.V + (int64_t)t * jb.vslab;
+  const int64_t psy = q * p, psv = q * q;
+  // Y[a][i] = Z[i][a]
+  for (int64_t e = tid; e < q * p; e += 1024) {
+    const int64_t a = e / p, i = e % p;
+    if (isC) {
+      const double* src = jb.Cz + (int64_t)b * jb.cslab + i * jb.cld + a;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) Y[e + k * psy] = src[k * jb.cps];
+    } else {
+      const double* src = jb.Rz + (int64_t)b * jb.rslab + a * jb.rld + i;
+      Y[e] = src[0];
+#pragma unroll
+      for (int k = 1; k < 4; ++k) Y[e + k * psy] = -src[k * jb.rps];
+    }
+  }
+  for (int64_t e = tid; e < q * q; e += 1024) {
+    const int64_t a = e / q, k = e % q;
+    V[e] = (a == k) ? 1.0 : 0.0;
+    V[e + psv] = V[e + 2 * psv] = V[e + 3 * psv] = 0.0;
+  }
+  __syncthreads();
+  const double tol = sqrt((double)p) * 0x1p-53;
+  const int qpad = (int)((q + 1) / 2 * 2);
+  for (int sweep = 0; sweep < jb.max_sweeps; ++sweep) {
+    if (tid == 0) any = 0;
+    __syncthreads();
+    for (int round = 0; round < qpad - 1; ++round) {
+      for (int k = wave; k < qpad / 2; k += 16) {
+        int a, c;
+        pair_of(round, k, qpad, a, c);
+        if (a >= q || c >= q) continue;
+        double* ya = Y + (int64_t)a * p;
+        double* yb = Y + (int64_t)c * p;
+        double d[6] = {0, 0, 0, 0, 0, 0};
+        for (int64_t k2 = lane; k2 < p; k2 += 64) acc_dots(ya, yb, psy, k2, d);
+#pragma unroll
+        for (int x = 0; x < 6; ++x) d[x] = wsum(d[x]);
+        const Rot r = make_rot(d[0], d[1], d[2], d[3], d[4], d[5], tol);
+        if (!r.rotate) continue;
+        if (lane == 0) any = 1;
+        for (int64_t k2 = lane; k2 < p; k2 += 64) apply_rot(r, ya, yb, psy, k2);
+        double* va = V + (int64_t)a * q;
+        double* vb = V + (int64_t)c * q;
+        for (int64_t k2 = lane; k2 < q; k2 += 64) apply_rot(r, va, vb, psv, k2);
+      }
+      __syncthreads();
+    }
+    const int again = any;
+    __syncthreads();
+    if (!again) break;
+  }
+  // sigma_k^2 = ||Y_k||^2, one wave per column
+  for (int64_t k = wave; k < q; k += 16) {
+    const double* y = Y + k * p;
+    double s = 0.0;
+    for (int64_t i = lane; i < p; i += 64) {
+      const double a0 = y[i], a1 = y[i + psy], a2 = y[i + 2 * psy], a3 = y[i + 3 * psy];
+      s += a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3;
+    }
+    s = wsum(s);
+    if (lane == 0) sig2[k] = s;
+  }
+  __syncthreads();
+  // keep sigma_k > rtol * sigma_max, at most max_rank of the largest (ties by index)
+  double mx = 0.0;
+  for (int64_t k = tid; k < q; k += 1024) mx = fmax(mx, sig2[k]);
+  red[tid] = mx;
+  __syncthreads();
+  for (int w = 512; w >= 1; w >>= 1) {
+    if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
+    __syncthreads();
+  }
+  const double smax = sqrt(red[0]);
+  const double rt = jb.rtol < 0.0 ? (double)(p > q ? p : q) * 0x1p-52 : jb.rtol;
+  long long kept = 0;
+  for (int64_t k = tid; k < q; k += 1024) {
+    const double s2 = sig2[k];
+    bool keep = smax > 0.0 && sqrt(s2) > rt * smax;
+    if (keep && jb.max_rank > 0) {
+      int64_t rk = 0;
+      for (int64_t j = 0; j < q; ++j) rk += (sig2[j] > s2 || (sig2[j] == s2 && j < k)) ? 1 : 0;
+      keep = rk < jb.max_rank;
+    }
+    scl[k] = keep ? 1.0 / sqrt(s2) : 0.0;
+    kept += keep ? 1 : 0;
+  }
+  cnt[tid] = kept;
+  __syncthreads();
+  for (int w = 512; w >= 1; w >>= 1) {
+    if (tid < w) cnt[tid] += cnt[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0 && jb.rank_out) jb.rank_out[isC ? 2 * b : 2 * b + 1] = cnt[0];
+  // Q[i][k] = Y_k[i] s_k
+  double* Qo = jb.Q + (int64_t)t * jb.qslab;
+  for (int64_t e = tid; e < q * p; e += 1024) {
+    const int64_t k = e / p, i = e % p;
+    const double s = scl[k];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Qo[i * jb.qld + k + c * jb.qps] = Y[e + c * psy] * s;
+  }
+  // P[k][a] = conj(V_{a,k}) s_k,  V_{a,k} = Vc[k][a]
+  double* Po = jb.P + (int64_t)t * jb.pslab;
+  for (int64_t e = tid; e < q * q; e += 1024) {
+    const int64_t k = e / q, a = e % q;
+    const double s = scl[k];
+    Po[k * jb.pld + a] = V[e] * s;
+#pragma unroll
+    for (int c = 1; c < 4; ++c) Po[k * jb.pld + a + c * jb.pps] = -V[e + c * psv] * s;
+  }
+}
+
+hipError_t launch_jacobi_pinv_batch(const Ctx& c, const JacobiBatch& jb, int count2) {
+  if (count2 <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kb_jacobi_pinv, dim3((unsigned)count2), dim3(1024), 0, c.stream, jb);
+  return hipGetLastError();
+}
+
+}  // namespace qcur

@@ -150,7 +150,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
   const int64_t M = g.bM ? (int64_t)g.bM[b] : g.M;
   const int64_t N = g.bN ? (int64_t)g.bN[b] : g.N;
   const int64_t K = g.bK ? (int64_t)g.bK[b] : g.K;
-  if (EPI != EPI_RESID && (bm >= M || bn >= N)) return;  // uniform over the workgroup
+  if (bm >= M || bn >= N) {  // uniform over the workgroup
+    if (EPI == EPI_RESID && threadIdx.x == 0) g.partials[part_index] = 0.0;
+    return;
+  }
   const In* __restrict__ Ag = (const In*)g.A + (int64_t)b * g.sA;
   const In* __restrict__ Bg = (const In*)g.B + (int64_t)b * g.sB;
 
@@ -384,8 +387,8 @@ static int tile_of(int64_t M, int64_t N) {
   return t64 >= 192 ? 64 : 32;
 }
 
-static int choose_splits(int64_t M, int64_t N, int64_t K, int bk, int tile) {
-  const int64_t tiles = ((M + tile - 1) / tile) * ((N + tile - 1) / tile);
+static int choose_splits(int64_t M, int64_t N, int64_t K, int bk, int tile, int batch) {
+  const int64_t tiles = ((M + tile - 1) / tile) * ((N + tile - 1) / tile) * std::max(batch, 1);
   const int64_t kt = (K + bk - 1) / bk;
   // split K until the grid covers the chip twice over, keeping >= 2 K-slices per split
   int s = 1;
@@ -397,7 +400,7 @@ static int bk_of(int compute) { return compute == QCUR_BF16 ? 32 : 16; }
 static size_t acc_size(int compute) { return compute == QCUR_F64 ? 8 : 4; }
 
 size_t gemm_workspace(int64_t M, int64_t N, int64_t K, int compute, int batch) {
-  const int s = choose_splits(M, N, K, bk_of(compute), tile_of(M, N));
+  const int s = choose_splits(M, N, K, bk_of(compute), tile_of(M, N), batch);
   if (s <= 1) return 0;
   return (size_t)batch * s * 4 * (size_t)M * (size_t)N * acc_size(compute);
 }
@@ -406,7 +409,7 @@ template <int DT, int TILE>
 static hipError_t gemm_dt_tile(const Ctx& c, GemmArgs g, void* ws, size_t ws_bytes) {
   constexpr int BK = MT<DT>::BK;
   const int64_t kt = (g.K + BK - 1) / BK;
-  int splits = choose_splits(g.M, g.N, g.K, BK, TILE);
+  int splits = choose_splits(g.M, g.N, g.K, BK, TILE, g.batch);
   const size_t need = (size_t)g.batch * splits * 4 * (size_t)g.M * (size_t)g.N * acc_size(DT);
   if (splits > 1 && (ws == nullptr || ws_bytes < need)) splits = 1;
   dim3 grid((unsigned)((g.N + TILE - 1) / TILE), (unsigned)((g.M + TILE - 1) / TILE), 1);
@@ -507,6 +510,42 @@ hipError_t launch_residual_gemm(const Ctx& c, QView A, QView B1, QView R, const 
       g.ktiles_per_split = (int)((g.K + 31) / 32);
       hipLaunchKernelGGL((k_qgemm<QCUR_BF16, EPI_RESID, 64, 64>), grid, dim3(NT), 0, c.stream, g);
     }
+  }
+  return hipGetLastError();
+}
+
+// Batched residual: problem b's tiles write partials[b * tiles + tile]
+// (zero for tiles outside the problem); E_b = e_scale (A_b - B1_b op(R_b))
+// when E is given.
+hipError_t launch_residual_gemm_batched(const Ctx& c, int count, Slots A, Slots B1, Slots R, int opR, int64_t mx,
+                                        int64_t nx, int64_t kx, const int* bM, const int* bN, const int* bK,
+                                        int compute, double* partials, const Slots* E, double e_scale) {
+  if (count <= 0 || mx <= 0 || nx <= 0) return hipSuccess;
+  GemmArgs g = {};
+  g.A = B1.p; g.lda = B1.ld; g.psa = B1.ps; g.sA = B1.slab;
+  g.B = R.p; g.ldb = R.ld; g.psb = R.ps; g.sB = R.slab;
+  g.M = mx; g.N = nx; g.K = kx;
+  g.bM = bM; g.bN = bN; g.bK = bK;
+  g.opA = QCUR_OP_N; g.opB = opR;
+  g.alpha = 1.0; g.beta = 0.0;
+  g.R0 = A.p; g.r0dt = A.dt; g.r0ld = A.ld; g.r0ps = A.ps; g.sR0 = A.slab;
+  g.partials = partials;
+  g.batch = count;
+  g.splits = 1;
+  if (E) { g.E = E->p; g.edt = E->dt; g.eld = E->ld; g.eps = E->ps; g.sE = E->slab; g.e_scale = e_scale; }
+  const dim3 grid((unsigned)((nx + 63) / 64), (unsigned)((mx + 63) / 64), (unsigned)count);
+  switch (compute) {
+    case QCUR_F64:
+      g.ktiles_per_split = (int)((kx + 15) / 16);
+      hipLaunchKernelGGL((k_qgemm<QCUR_F64, EPI_RESID, 64, 64>), grid, dim3(NT), 0, c.stream, g);
+      break;
+    case QCUR_F32:
+      g.ktiles_per_split = (int)((kx + 15) / 16);
+      hipLaunchKernelGGL((k_qgemm<QCUR_F32, EPI_RESID, 64, 64>), grid, dim3(NT), 0, c.stream, g);
+      break;
+    default:
+      g.ktiles_per_split = (int)((kx + 31) / 32);
+      hipLaunchKernelGGL((k_qgemm<QCUR_BF16, EPI_RESID, 64, 64>), grid, dim3(NT), 0, c.stream, g);
   }
   return hipGetLastError();
 }

@@ -143,4 +143,76 @@ hipError_t launch_backward_assemble(const Ctx& c, QView dA, QView G, int has_G, 
 hipError_t launch_axpby(const Ctx& c, double alpha, QView X, double beta, QView Y);
 hipError_t launch_identity_minus(const Ctx& c, QView X);
 
+// ---- batched solve (many independent problems of uneven sizes) ------------
+// Problem b owns slot b of every batched array: its matrix is the top-left
+// corner of the slot, with the slot's row stride.  Sizes live in device int
+// arrays (dm, dn, dc, dr: m_b, n_b, c_b, r_b); zp/zq hold the tall shapes
+// p x q of the 2*count pseudoinverse problems (C_b, then R_b^H).
+constexpr int JB_MAXQ = 1024;
+struct JacobiBatch {
+  const int* ok;
+  const double* Cz;
+  int64_t cld, cps, cslab;
+  const double* Rz;
+  int64_t rld, rps, rslab;
+  const int *dm, *dn, *dc, *dr;
+  double* Y;
+  double* V;
+  int64_t yslab, vslab;
+  double* Q;  // [2*count] slots: p_t x q_t orthonormal factor
+  int64_t qld, qps, qslab;
+  double* P;  // [2*count] slots: q_t x q_t, Z^+ = P^H Q^H
+  int64_t pld, pps, pslab;
+  int64_t* rank_out;  // [count][2]
+  double rtol;
+  int64_t max_rank;
+  int count;
+  int max_sweeps;
+};
+hipError_t launch_jacobi_pinv_batch(const Ctx& c, const JacobiBatch& jb, int count2);
+
+// A slot array: element (i, j) of plane k of problem b at
+// p + b*slab + k*ps + i*ld + j (elements of dt).
+struct Slots {
+  void* p;
+  int64_t ld, ps, slab;
+  int dt;
+};
+constexpr int BATCH_RB = 32;  // rows per tile of the batched norm pass
+hipError_t launch_norms_batch(const Ctx& c, int count, Slots A, const int* dm, const int* dn, int64_t mx,
+                              int64_t nx, double* colpart, double* rowpart, const Slots* Ax);
+struct DrawBatch {
+  const int *dm, *dn, *dc, *dr;
+  const double* colpart;  // [count][ceil(mx/BATCH_RB)][nx]
+  const double* rowpart;  // [count][ceil(nx/256)][mx]
+  int64_t mx, nx, cx, rx;
+  double* p;  // [count][nx]
+  double* q;  // [count][mx]
+  int64_t* I;  // [count][rx]
+  int64_t* J;  // [count][cx]
+  uint64_t seed;
+  int sampling, repl;
+};
+size_t draw_lds(int64_t n, int repl);
+hipError_t launch_draw_batch(const Ctx& c, int count, const DrawBatch& d);
+// out_b = A_b(rows idx, cols idx) with NULL index lists meaning the identity;
+// written in FP64 (O) and, if Ox is given, in its dtype.
+hipError_t launch_gather_batch(const Ctx& c, int count, Slots A, const int* dm, const int* dn,
+                               const int64_t* ridx, int64_t ris, const int64_t* cidx, int64_t cis,
+                               const int* orows, const int* ocols, int64_t rowsx, int64_t colsx, Slots O,
+                               const Slots* Ox);
+hipError_t launch_cast_batch(const Ctx& c, int count, Slots X, Slots Y, const int* rows, const int* cols,
+                             int64_t rowsx, int64_t colsx, int mode);
+hipError_t launch_pad_gram_batch(const Ctx& c, int count, double* G, int64_t n, int64_t slab, const int* zq);
+hipError_t launch_sumsq_ragged(const Ctx& c, int count, Slots X, const int* rows, const int* cols, double* out,
+                               int ostride);
+hipError_t launch_decide_batch(const Ctx& c, int count2, int count, const double* norms, const int* fail,
+                               double rtol, int64_t max_rank, const int* zp, const int* zq, int64_t* rank_out,
+                               int* ok);
+hipError_t launch_resid_sum_batch(const Ctx& c, int count, const double* part, int64_t tiles, double* out);
+// Batched residual A_b - B1_b op(R_b) (op = QCUR_OP_N or QCUR_OP_H).
+hipError_t launch_residual_gemm_batched(const Ctx& c, int count, Slots A, Slots B1, Slots R, int opR, int64_t mx,
+                                        int64_t nx, int64_t kx, const int* bM, const int* bN, const int* bK,
+                                        int compute, double* partials, const Slots* E, double e_scale);
+
 }  // namespace qcur

@@ -78,6 +78,10 @@ def _declare(L):
         "qcur_solve": (c_int, [c_p, QP, c_i64, c_i64, c_int, c_int, c_int, c_u64, c_int, c_int, c_d, c_i64, c_p,
                                c_p, QP, c_p, c_p, c_p, c_p, QP, QP, QP, c_p, c_sz]),
         "qcur_solve_workspace": (c_sz, [c_i64, c_i64, c_i64, c_i64, c_int, c_int]),
+        "qcur_batch_workspace": (c_sz, [ctypes.c_int32, c_p, c_int, c_int, c_int, c_int]),
+        "qcur_batch_prepare": (c_int, [c_p, ctypes.c_int32, c_p, c_int, c_int, c_int, c_int, c_p, c_sz]),
+        "qcur_solve_batched": (c_int, [c_p, ctypes.c_int32, c_p, QP, c_i64, c_int, c_int, c_u64, c_int, c_int, c_d,
+                                       c_i64, c_p, c_p, QP, c_i64, c_p, c_p, c_p, c_p, c_p, c_sz]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -329,3 +333,83 @@ def solve(A: torch.Tensor, c: int, r: int, sampling: int = LENGTH, core: int = C
                          max_rank=max_rank, want_B=want_B)
     fro, _ = residual(A, C, U, R, compute=compute)
     return dict(p=p, q=q, fro2=f2, I=I, J=J, C=C, R=R, W=W, U=U, B=B, ranks=ranks, residual=fro)
+
+
+def _slots(t: torch.Tensor) -> tuple:
+    """(QMat of slot 0, slot stride) for a (count, 4, rows, cols) tensor."""
+    if t.dim() != 4 or t.shape[1] != 4:
+        raise ValueError(f"batched quaternion matrices are (count, 4, rows, cols) tensors, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError("batched operands must be contiguous")
+    if t.dtype not in _QCUR_DT:
+        raise ValueError(f"unsupported dtype {t.dtype}")
+    _, _, rows, cols = t.shape
+    return QMat(t.data_ptr(), rows, cols, cols, rows * cols, _QCUR_DT[t.dtype]), t.stride(0)
+
+
+class BatchSolver:
+    """Batched QMCUR (qcur_solve_batched) for a fixed list of problem sizes.
+
+    dims: (count, 4) integers (m_b, n_b, c_b, r_b).  Inputs are (count, 4,
+    MX, NX) tensors holding A_b in the top-left corner of slot b (MX, NX at
+    least the largest m_b, n_b); see pack_batch.  Outputs after a call:
+    I (count, rx), J (count, cx), U (count, 4, cx, rx), residual (count,),
+    ranks (count, 2), p (count, nx), q (count, mx), each problem in the
+    leading part of its row/slot.  The call enqueues kernels only, so it may
+    be captured in a torch.cuda.CUDAGraph after one eager call."""
+
+    def __init__(self, dims, compute: int = F32, sampling: int = LENGTH, refine_steps: int = 0,
+                 a_dtype=torch.float32, device=None):
+        import numpy as np
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        d = np.ascontiguousarray(np.asarray(dims, dtype=np.int32).reshape(-1, 4))
+        self.dims = d
+        self.count = int(d.shape[0])
+        self.mx, self.nx, self.cx, self.rx = (int(v) for v in d.max(axis=0))
+        self.compute, self.sampling, self.refine_steps = compute, sampling, refine_steps
+        self.a_dtype = a_dtype
+        odt = torch.float64 if compute == F64 else torch.float32
+        n = self.count
+        self.I = torch.full((n, self.rx), -1, dtype=torch.int64, device=dev)
+        self.J = torch.full((n, self.cx), -1, dtype=torch.int64, device=dev)
+        self.U = torch.zeros((n, 4, self.cx, self.rx), dtype=odt, device=dev)
+        self.residual = torch.zeros(n, dtype=torch.float64, device=dev)
+        self.ranks = torch.zeros((n, 2), dtype=torch.int64, device=dev)
+        self.p = torch.zeros((n, self.nx), dtype=torch.float64, device=dev)
+        self.q = torch.zeros((n, self.mx), dtype=torch.float64, device=dev)
+        dptr = ctypes.c_void_p(d.ctypes.data)
+        nbytes = lib().qcur_batch_workspace(n, dptr, _QCUR_DT[a_dtype], sampling, compute, refine_steps)
+        if nbytes == 0:
+            raise QcurError(1, "invalid batch sizes or options")
+        self.ws = _ws(nbytes, dev)
+        with torch.cuda.device(dev):
+            _check(lib().qcur_batch_prepare(handle(dev).bind(), n, dptr, _QCUR_DT[a_dtype], sampling, compute,
+                                            refine_steps, _ptr(self.ws), self.ws.numel()))
+
+    def __call__(self, A: torch.Tensor, seed: int = 0, rtol: float = -1.0, max_rank: int = 0,
+                 with_replacement: bool = False):
+        if A.dtype != self.a_dtype:
+            raise ValueError(f"A must be {self.a_dtype} (the dtype the batch was prepared for)")
+        if A.shape[0] != self.count:
+            raise ValueError("A has the wrong number of slots")
+        qa, sa = _slots(A)
+        qu, su = _slots(self.U)
+        _check(lib().qcur_solve_batched(_h(A), self.count, ctypes.c_void_p(self.dims.ctypes.data), ctypes.byref(qa),
+                                        sa, self.sampling, self.compute, seed & (2 ** 64 - 1), int(with_replacement),
+                                        self.refine_steps, rtol, max_rank, _ptr(self.I), _ptr(self.J),
+                                        ctypes.byref(qu), su, _ptr(self.residual), _ptr(self.ranks), _ptr(self.p),
+                                        _ptr(self.q), _ptr(self.ws), self.ws.numel()))
+        return self
+
+
+def pack_batch(mats, dtype=torch.float32, device="cuda", slot=None) -> torch.Tensor:
+    """Copies a list of (4, m_b, n_b) arrays into the top-left corners of the
+    slots of a zero (count, 4, MX, NX) tensor (MX, NX = the largest sizes, or
+    `slot`)."""
+    mx = max(int(a.shape[1]) for a in mats) if slot is None else slot[0]
+    nx = max(int(a.shape[2]) for a in mats) if slot is None else slot[1]
+    out = torch.zeros((len(mats), 4, mx, nx), dtype=dtype)
+    for b, a in enumerate(mats):
+        t = torch.as_tensor(a)
+        out[b, :, : t.shape[1], : t.shape[2]] = t.to(dtype)
+    return out.to(device)

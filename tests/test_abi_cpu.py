@@ -143,3 +143,42 @@ def test_create_without_gpu_fails_cleanly(L):
     h = ctypes.c_void_p()
     st = L.qcur_create(ctypes.byref(h), 0)
     assert st in (1, 7) and not h.value
+
+
+def _dims(rows):
+    import numpy as np
+    d = np.ascontiguousarray(np.asarray(rows, dtype=np.int32).reshape(-1, 4))
+    return d, ctypes.c_void_p(d.ctypes.data)
+
+
+def test_batch_workspace_and_validation(L):
+    d, dp = _dims([(64, 80, 16, 12), (100, 70, 20, 30)])
+    ws = L.qcur_batch_workspace(2, dp, Q.F32, Q.LENGTH, Q.F32, 0)
+    assert ws > 0
+    assert L.qcur_batch_workspace(2, dp, Q.F32, Q.LENGTH, Q.F32, 1) > ws  # refinement adds E
+    assert L.qcur_batch_workspace(0, dp, Q.F32, Q.LENGTH, Q.F32, 0) == 0
+    assert L.qcur_batch_workspace(2, None, Q.F32, Q.LENGTH, Q.F32, 0) == 0
+    bad, bp = _dims([(64, 80, 16, 12), (0, 70, 20, 30)])
+    assert L.qcur_batch_workspace(2, bp, Q.F32, Q.LENGTH, Q.F32, 0) == 0
+    big, gp = _dims([(5000, 80, 16, 12)])
+    assert L.qcur_batch_workspace(1, gp, Q.F32, Q.LENGTH, Q.F32, 0) == 0
+
+    # slots: (count, 4, 100, 80) for A, (count, 4, 20, 30) for U
+    A = qm(100, 80, Q.F32)
+    U = qm(20, 30, Q.F32)
+    sa, su = 4 * 100 * 80, 4 * 20 * 30
+
+    def solve(count=2, dims=dp, A=A, sa=sa, U=U, su=su, I=FAKE, ws=FAKE, nbytes=ws, compute=Q.F32, repl=0):
+        return L.qcur_solve_batched(None, count, dims, A, sa, Q.LENGTH, compute, 1, repl, 0, -1.0, 0, I, FAKE, U,
+                                    su, FAKE, None, None, None, ws, nbytes)
+
+    assert solve() == 1  # valid: only the NULL handle is rejected
+    assert "handle" in L.qcur_last_error().decode()
+    assert solve(nbytes=ws - 1) == 4
+    assert solve(sa=sa - 1) == 2                 # slots overlap
+    assert solve(A=qm(99, 80, Q.F32)) == 2       # slot smaller than the largest problem
+    assert solve(U=qm(20, 30, Q.F64)) == 3       # U must be FP32 for FP32 products
+    assert solve(I=None) == 1
+    over, op = _dims([(64, 80, 100, 12)])        # c > n without replacement
+    assert solve(count=1, dims=op) == 2
+    assert solve(count=0) == 1
