@@ -161,14 +161,19 @@ qcur_status qcur_gemm(qcur_handle handle, int opA, int opB, double alpha, const 
 
 /* Core and optional product (Algorithm 1 step 3; Section 3.1).
  * core QCUR_CORE_WPINV: U = W^+ (W r x c, any dtype; A, C, R may be NULL).
- * core QCUR_CORE_CAR: U = C^+ (A R^+) with C (m x c), R (r x n), A (m x n).
- * Pseudoinverses are FP64.  compute selects the dtype of the products:
- * QCUR_F64 (U, B FP64), QCUR_F32 (FP32 products; U, B FP32) or QCUR_BF16
- * (BF16 operands with FP32 accumulation; U, B FP32).  A, C, R and W may be
- * given in any dtype: operands are converted to the product dtype in the
- * workspace, while the refinement residual A - C U R subtracts A in the
- * precision it was given.  refine_steps >= 0 applies U <- U + C^+ ((A - C U R) R^+)
- * that many times (CAR only).  B (m x n, may be NULL) receives C U R.
+ * core QCUR_CORE_CAR: U = C^+ (A R^+) with C (m x c), R (r x n), A (m x n),
+ * evaluated in orthonormal form: C = Q_C T_C and R^H = Q_R T_R (FP64
+ * CholeskyQR2, or the Jacobi SVD when its certificate fails) give
+ * U = P_C^H (Q_C^H A Q_R) P_R with P = T^{-H}, so that C U R =
+ * Q_C M Q_R^H, M = Q_C^H A Q_R.  compute selects the dtype of the products
+ * with A: QCUR_F64 (U, B FP64), QCUR_F32 (FP32 products; U, B FP32) or
+ * QCUR_BF16 (BF16 operands with FP32 accumulation; U, B FP32); the small
+ * products with P run in FP64.  A, C, R and W may be given in any dtype:
+ * operands are converted to the product dtype in the workspace, while the
+ * refinement residual A - C U R subtracts A in the precision it was given.
+ * refine_steps >= 0 applies M <- M + Q_C^H (A - C U R) Q_R (equivalently
+ * U <- U + C^+ ((A - C U R) R^+)) that many times (CAR only).  B (m x n,
+ * may be NULL) receives C U R.
  * rank_out (device int64[2], may be NULL): kept ranks of the pseudoinverses
  * (W: [rank, rank]; CAR: [rank C, rank R]).
  * ws: qcur_approx_workspace(m, n, c, r, core, compute) bytes. */

@@ -320,9 +320,14 @@ qcur_status pinv_fast_group(const Ctx& c, int nb, const QView* X, double rtol, i
   int ok[MAXB] = {0, 0, 0, 0};
   HIPCHK(hipMemcpyAsync(ok, w.ok, sizeof(int) * nb, hipMemcpyDeviceToHost, c.stream));
   HIPCHK(hipStreamSynchronize(c.stream));
-  // Z^+ = T^{-1} Q^H = P^H Q^H;  for a wide X, X^+ = (Z^+)^H = Q P
+  // Z^+ = T^{-1} Q^H = P^H Q^H;  for a wide X, X^+ = (Z^+)^H = Q P.  Without
+  // Xp the factors stay in the group's Q and P slots (orthonormal form).
   for (int b = 0; b < nb; ++b) {
     if (!ok[b]) continue;
+    if (!Xp) {
+      done[b] = true;
+      continue;
+    }
     QView Pv{Pf + b * gslab, qb[b], qb[b], qq, qq * qq, QCUR_F64};
     QView Qv{Qf + b * zslab, pb[b], qb[b], qq, pp * qq, QCUR_F64};
     if (tall[b]) {
@@ -367,6 +372,93 @@ qcur_status pinv_jacobi(const Ctx& c, QView X, double rtol, int64_t max_rank, QV
     HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, Vcc, Ydc, 0.0, Xp, QCUR_F64, w.gws, w.gws_bytes));
   } else {
     HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, Ydc, Vcc, 0.0, Xp, QCUR_F64, w.gws, w.gws_bytes));
+  }
+  return QCUR_OK;
+}
+
+// Jacobi path in orthonormal form: Z^+ = P^H Q^H written into the views
+// Q (pp x qq) and P (qq x qq).
+qcur_status pinv_jacobi_qp(const Ctx& c, QView X, double rtol, int64_t max_rank, QView Qv, QView Pv,
+                           int64_t* rank_out, PinvWs w) {
+  PinvPlan pl = pinv_plan(X.rows, X.cols);
+  const int64_t pp = pl.pp, qq = pl.qq;
+  QView Yv{w.Y, qq, pp, pp, qq * pp, QCUR_F64};
+  HIPCHK(launch_cast(c, X, Yv, pl.tall ? CAST_T : CAST_CONJ));
+  HIPCHK(launch_fill_identity(c, w.V, qq));
+  const double tol = std::sqrt((double)pp) * std::ldexp(1.0, -53);
+  if (jacobi_small_fits(pp, qq)) {
+    HIPCHK(launch_jacobi_small(c, w.Y, pp, qq, w.V, tol, MAX_SWEEPS, w.flag));
+  } else {
+    const int64_t qpad = (qq + 1) / 2 * 2;
+    unsigned host_flag = 1;
+    for (int sweep = 0; sweep < MAX_SWEEPS && host_flag; ++sweep) {
+      HIPCHK(launch_zero_i32(c, (int*)w.flag, 1));
+      for (int round = 0; round < qpad - 1; ++round)
+        HIPCHK(launch_jacobi_round(c, w.Y, pp, qq, w.V, qpad, round, tol, w.flag));
+      HIPCHK(hipMemcpyAsync(&host_flag, w.flag, sizeof(unsigned), hipMemcpyDeviceToHost, c.stream));
+      HIPCHK(hipStreamSynchronize(c.stream));
+    }
+  }
+  HIPCHK(launch_pinv_scale(c, w.Y, pp, qq, rtol, max_rank, rank_out, w.sig));
+  HIPCHK(launch_pinv_qp(c, w.Y, pp, qq, w.V, w.sig + qq, Qv, Pv));
+  return QCUR_OK;
+}
+
+// Orthonormal factors of nb matrices (any dtype), FP64: for each X_b with
+// Z_b = X_b (tall) or X_b^H (wide), Z_b^+ = P_b^H Q_b^H with Q_b
+// (pp_b x qq_b, orthonormal or zero columns) and P_b (qq_b x qq_b) left in
+// the views Qv[b], Pv[b] inside the group workspace.  CholeskyQR2 where its
+// certificate holds, else the Jacobi SVD.
+qcur_status pinv_group_qp(const Ctx& c, int nb, const QView* X, double rtol, int64_t max_rank,
+                          int64_t* const* rank_out, GroupWs& gw, PinvWs jw, QView* Qv, QView* Pv) {
+  const int64_t pp = gw.pp, qq = gw.qq;
+  const int64_t zslab = 4 * pp * qq, gslab = 4 * qq * qq;
+  QView fx[MAXB];
+  int64_t* fr[MAXB];
+  int idx[MAXB], small[MAXB];
+  int nf = 0, ns = 0;
+  double rt[MAXB];
+  for (int b = 0; b < nb; ++b) {
+    PinvPlan pl = pinv_plan(X[b].rows, X[b].cols);
+    rt[b] = rtol < 0 ? (double)std::max(pl.p, pl.q) * std::ldexp(1.0, -52) : rtol;
+    if (pl.qq == 0) {
+      if (rank_out[b]) HIPCHK(launch_zero(c, (double*)rank_out[b], 1));
+      Qv[b] = QView{gw.Q, pl.pp, 0, 1, 1, QCUR_F64};
+      Pv[b] = QView{gw.P, 0, 0, 1, 1, QCUR_F64};
+      continue;
+    }
+    HIPCHK(launch_check_finite(c, X[b]));
+    if (jacobi_small_fits(pl.pp, pl.qq)) {
+      small[ns++] = b;
+      continue;
+    }
+    fx[nf] = X[b];
+    fr[nf] = rank_out[b];
+    idx[nf] = b;
+    ++nf;
+  }
+  // slots: the CholeskyQR problems first, then the small ones
+  auto slot = [&](int s, int b) {
+    PinvPlan pl = pinv_plan(X[b].rows, X[b].cols);
+    Qv[b] = QView{gw.Q + s * zslab, pl.pp, pl.qq, qq, pp * qq, QCUR_F64};
+    Pv[b] = QView{gw.P + s * gslab, pl.qq, pl.qq, qq, qq * qq, QCUR_F64};
+  };
+  if (nf > 0) {
+    bool done[MAXB];
+    double rg = 0.0;
+    for (int f = 0; f < nf; ++f) rg = std::max(rg, rt[idx[f]]);
+    GroupWs w = gw;
+    w.nb = nf;
+    CHK(pinv_fast_group(c, nf, fx, rg, max_rank, nullptr, fr, w, 2, done));
+    for (int f = 0; f < nf; ++f) {
+      slot(f, idx[f]);
+      if (!done[f]) CHK(pinv_jacobi_qp(c, fx[f], rt[idx[f]], max_rank, Qv[idx[f]], Pv[idx[f]], fr[f], jw));
+    }
+  }
+  for (int k = 0; k < ns; ++k) {
+    const int b = small[k];
+    slot(nf + k, b);
+    CHK(pinv_jacobi_qp(c, X[b], rt[b], max_rank, Qv[b], Pv[b], rank_out[b], jw));
   }
   return QCUR_OK;
 }
@@ -430,6 +522,7 @@ QView as_dtype(const Ctx& c, QView X, int dt, Bump& b, bool count_only, hipError
 struct ApproxArgs {
   QView A, C, R, W, U, B;
   bool hasA, hasC, hasR, hasW, hasB;
+  double* fro;  // least-squares core: ||A - CUR||_F (device double[1]) or NULL
   int core, compute, refine;
   double rtol;
   int64_t max_rank;
@@ -453,73 +546,86 @@ qcur_status approx_run(const Ctx& c, const ApproxArgs& a, int64_t m, int64_t n, 
       if (U64.p != a.U.p) HIPCHK(launch_cast(c, U64, a.U, CAST_COPY));
     }
   } else {
-    // C^+ (c x m) and R^+ (n x r) in FP64
-    QView Cp = b.mat(cc, m, QCUR_F64);
-    QView Rp = b.mat(n, r, QCUR_F64);
+    // Least-squares core in orthonormal form.  C = Q_C T_C and R^H = Q_R T_R
+    // (CholeskyQR2 or Jacobi, FP64) give C^+ = P_C^H Q_C^H and
+    // R^+ = Q_R P_R with P = T^{-H}; then
+    //   U = P_C^H M P_R,  M = Q_C^H A Q_R,  C U R = Q_C M Q_R^H.
+    // The products that touch A use the orthonormal Q's in the product
+    // dtype, so their rounding stays near u ||A|| whatever the conditioning
+    // of C and R; only the small factors P meet M, in FP64.
+    QView Qv[2], Pv[2];
     {
-      // both pseudoinverses run as one batched group
       PinvPlan pc = pinv_plan(m, cc), pr = pinv_plan(r, n);
       const int64_t pp = std::max(pc.pp, pr.pp), qq = std::max(pc.qq, pr.qq);
       Bump pb = b;
       PinvWs jw = pinv_carve(pb, pp, qq);
       GroupWs gw = group_carve(pb, 2, pp, qq);
       if (!count_only) {
-        // one CholeskyQR pass suffices when the products are FP32/BF16
-        const int passes = a.compute == QCUR_F64 ? 2 : 1;
-        QView xs[2] = {a.C, a.R}, xps[2] = {Cp, Rp};
+        QView xs[2] = {a.C, a.R};
         int64_t* ro[2] = {a.rank_out, a.rank_out ? a.rank_out + 1 : nullptr};
-        CHK(pinv_group(c, 2, xs, a.rtol, a.max_rank, xps, ro, gw, jw, passes));
+        CHK(pinv_group_qp(c, 2, xs, a.rtol, a.max_rank, ro, gw, jw, Qv, Pv));
+      } else {
+        Qv[0] = QView{nullptr, m, cc, cc, m * cc, QCUR_F64};
+        Qv[1] = QView{nullptr, n, r, r, n * r, QCUR_F64};
+        Pv[0] = QView{nullptr, cc, cc, cc, cc * cc, QCUR_F64};
+        Pv[1] = QView{nullptr, r, r, r, r * r, QCUR_F64};
       }
       b.used = pb.used;
     }
     // operands in the product dtype
     QView Ax = as_dtype(c, a.A, idt, b, count_only, &err);
-    QView Cx = as_dtype(c, a.C, idt, b, count_only, &err);
-    QView Rx = as_dtype(c, a.R, idt, b, count_only, &err);
-    QView Cpx = as_dtype(c, Cp, idt, b, count_only, &err);
-    QView Rpx = as_dtype(c, Rp, idt, b, count_only, &err);
+    QView Qc = as_dtype(c, Qv[0], idt, b, count_only, &err);
+    QView Qr = as_dtype(c, Qv[1], idt, b, count_only, &err);
     if (err != hipSuccess) return fail(QCUR_ERR_DEVICE, "cast: %s", hipGetErrorString(err));
     QView T = b.mat(m, r, adt);
-    size_t gw = std::max({gemm_workspace(m, r, n, a.compute), gemm_workspace(cc, r, m, a.compute),
-                          gemm_workspace(m, r, cc, a.compute), gemm_workspace(m, n, r, a.compute)});
-    void* gws = b.take(gw);
     QView Tx = (idt == adt) ? T : b.mat(m, r, idt);
-    // U0 = C^+ (A R^+)
-    if (!count_only) {
-      HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Ax, Rpx, 0.0, T, a.compute, gws, gw));
+    QView M = b.mat(cc, r, adt);
+    QView Mx = (idt == adt) ? M : b.mat(cc, r, idt);
+    QView B1 = b.mat(m, r, adt);
+    QView B1x = (idt == adt) ? B1 : b.mat(m, r, idt);
+    QView M64 = adt == QCUR_F64 ? M : b.mat(cc, r, QCUR_F64);
+    QView W1 = b.mat(cc, r, QCUR_F64);
+    QView U64 = a.U.dt == QCUR_F64 ? a.U : b.mat(cc, r, QCUR_F64);
+    const bool need_E = a.refine > 0;
+    QView E = need_E ? b.mat(m, n, adt) : QView{};
+    QView Ex = need_E ? ((idt == adt) ? E : b.mat(m, n, idt)) : QView{};
+    double* part = (double*)b.take(std::max<size_t>(residual_tiles(m, n), 1) * 8);
+    size_t gw = std::max({gemm_workspace(m, r, n, a.compute), gemm_workspace(cc, r, m, a.compute),
+                          gemm_workspace(m, r, cc, a.compute), gemm_workspace(m, n, r, a.compute),
+                          gemm_workspace(cc, r, r, QCUR_F64), gemm_workspace(cc, r, cc, QCUR_F64)});
+    void* gws = b.take(gw);
+    if (count_only) return QCUR_OK;
+    // M = Q_C^H (A Q_R)
+    HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Ax, Qr, 0.0, T, a.compute, gws, gw));
+    if (Tx.p != T.p) HIPCHK(launch_cast(c, T, Tx, CAST_COPY));
+    HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, Qc, Tx, 0.0, M, a.compute, gws, gw));
+    auto left_factor = [&]() -> qcur_status {  // B1 = Q_C M in the product dtype
+      if (Mx.p != M.p) HIPCHK(launch_cast(c, M, Mx, CAST_COPY));
+      HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Qc, Mx, 0.0, B1, a.compute, gws, gw));
+      if (B1x.p != B1.p) HIPCHK(launch_cast(c, B1, B1x, CAST_COPY));
+      return QCUR_OK;
+    };
+    for (int st = 0; st < a.refine; ++st) {
+      // E = A - Q_C M Q_R^H (A in the precision it was given);  M += Q_C^H (E Q_R)
+      CHK(left_factor());
+      HIPCHK(launch_residual_gemm(c, a.A, B1x, Qr, nullptr, 0, a.compute, part, &E, 1.0, QCUR_OP_H));
+      if (Ex.p != E.p) HIPCHK(launch_cast(c, E, Ex, CAST_COPY));
+      HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Ex, Qr, 0.0, T, a.compute, gws, gw));
       if (Tx.p != T.p) HIPCHK(launch_cast(c, T, Tx, CAST_COPY));
-      HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Cpx, Tx, 0.0, a.U, a.compute, gws, gw));
+      HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, Qc, Tx, 1.0, M, a.compute, gws, gw));
     }
-    if (a.refine > 0) {
-      QView Ux = (idt == adt) ? a.U : b.mat(cc, r, idt);
-      QView B1 = b.mat(m, r, adt);
-      QView B1x = (idt == adt) ? B1 : b.mat(m, r, idt);
-      QView E = b.mat(m, n, adt);
-      QView Ex = (idt == adt) ? E : b.mat(m, n, idt);
-      double* part = (double*)b.take(residual_tiles(m, n) * 8);
-      for (int s = 0; s < a.refine && !count_only; ++s) {
-        if (Ux.p != a.U.p) HIPCHK(launch_cast(c, a.U, Ux, CAST_COPY));
-        HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Cx, Ux, 0.0, B1, a.compute, gws, gw));
-        if (B1x.p != B1.p) HIPCHK(launch_cast(c, B1, B1x, CAST_COPY));
-        // E = A - B1 R, with A in the precision it was given
-        HIPCHK(launch_residual_gemm(c, a.A, B1x, Rx, nullptr, 0, a.compute, part, &E, 1.0));
-        if (Ex.p != E.p) HIPCHK(launch_cast(c, E, Ex, CAST_COPY));
-        HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Ex, Rpx, 0.0, T, a.compute, gws, gw));
-        if (Tx.p != T.p) HIPCHK(launch_cast(c, T, Tx, CAST_COPY));
-        HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Cpx, Tx, 1.0, a.U, a.compute, gws, gw));
-      }
+    if (a.fro || a.hasB) CHK(left_factor());
+    if (a.fro) {
+      // ||A - C U R||_F = ||A - Q_C M Q_R^H||_F
+      HIPCHK(launch_residual_gemm(c, a.A, B1x, Qr, nullptr, 0, a.compute, part, nullptr, 0.0, QCUR_OP_H));
+      HIPCHK(launch_sum_partials(c, part, (int64_t)residual_tiles(m, n), a.fro, 1));
     }
-    if (a.hasB) {
-      QView Ux = (idt == adt) ? a.U : b.mat(cc, r, idt);
-      QView B1 = b.mat(m, r, adt);
-      QView B1x = (idt == adt) ? B1 : b.mat(m, r, idt);
-      if (!count_only) {
-        if (Ux.p != a.U.p) HIPCHK(launch_cast(c, a.U, Ux, CAST_COPY));
-        HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Cx, Ux, 0.0, B1, a.compute, gws, gw));
-        if (B1x.p != B1.p) HIPCHK(launch_cast(c, B1, B1x, CAST_COPY));
-        HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, B1x, Rx, 0.0, a.B, a.compute, gws, gw));
-      }
-    }
+    if (a.hasB) HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_H, 1.0, B1x, Qr, 0.0, a.B, a.compute, gws, gw));
+    // U = P_C^H (M P_R) in FP64
+    if (M64.p != M.p) HIPCHK(launch_cast(c, M, M64, CAST_COPY));
+    HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, M64, Pv[1], 0.0, W1, QCUR_F64, gws, gw));
+    HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, Pv[0], W1, 0.0, U64, QCUR_F64, gws, gw));
+    if (U64.p != a.U.p) HIPCHK(launch_cast(c, U64, a.U, CAST_COPY));
     return QCUR_OK;
   }
   if (a.hasB) {
@@ -722,11 +828,14 @@ qcur_status solve_run(const Ctx& c, const SolveArgs& s, Bump& b, bool count_only
   a.max_rank = s.max_rank;
   int64_t* ranks = s.rank_out ? s.rank_out : (int64_t*)b.take(16);
   a.rank_out = ranks;
+  // the least-squares core computes the residual itself (orthonormal form)
+  const bool car = s.core == QCUR_CORE_CAR;
+  a.fro = car ? s.residual : nullptr;
   const size_t base = b.used;
   Bump ta = b;
   CHK(approx_run(c, a, m, n, s.c, s.r, ta, true));
   Bump tr = b;
-  CHK(residual_run(c, s.A, C, s.U, R, nullptr, 0, s.compute, nullptr, 1, nullptr, 0.0, tr, true));
+  if (!car) CHK(residual_run(c, s.A, C, s.U, R, nullptr, 0, s.compute, nullptr, 1, nullptr, 0.0, tr, true));
   b.used = std::max(ta.used, tr.used);
   if (count_only) return QCUR_OK;
   if (pass) {
@@ -742,7 +851,7 @@ qcur_status solve_run(const Ctx& c, const SolveArgs& s, Bump& b, bool count_only
     run.used = base;
     CHK(approx_run(c, a, m, n, s.c, s.r, run, false));
   }
-  {
+  if (!car) {
     Bump run(b.base);
     run.used = base;
     CHK(residual_run(c, s.A, C, s.U, R, nullptr, 0, s.compute, s.residual, 1, nullptr, 0.0, run, false));

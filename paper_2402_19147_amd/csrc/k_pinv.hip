@@ -14,6 +14,8 @@
 //
 // Storage: columns are stored contiguously ("column rows"): Yc[a][k] is
 // element k of column a, Vc[a][k] element k of column a of V.
+#include <algorithm>
+
 #include "qcur_internal.hpp"
 
 namespace qcur {
@@ -443,6 +445,45 @@ __global__ __launch_bounds__(1024) void kb_jacobi_pinv(JacobiBatch jb) {
 hipError_t launch_jacobi_pinv_batch(const Ctx& c, const JacobiBatch& jb, int count2) {
   if (count2 <= 0) return hipSuccess;
   hipLaunchKernelGGL(kb_jacobi_pinv, dim3((unsigned)count2), dim3(1024), 0, c.stream, jb);
+  return hipGetLastError();
+}
+
+}  // namespace qcur
+
+namespace qcur {
+
+// Orthonormal form of a Jacobi pseudoinverse: with s_k = sqrt(dsc_k)
+// (1/sigma_k for kept columns, else 0), Q[i][k] = Y_k[i] s_k and
+// P[k][a] = conj(V_{a,k}) s_k = conj(Vc[k][a]) s_k, so Z^+ = P^H Q^H.
+__global__ __launch_bounds__(256) void k_pinv_qp(const double* __restrict__ Y, int64_t p, int64_t q,
+                                                 const double* __restrict__ V, const double* __restrict__ dsc,
+                                                 double* __restrict__ Qo, int64_t qld, int64_t qps,
+                                                 double* __restrict__ Po, int64_t pld, int64_t pps) {
+  const int64_t psy = q * p, psv = q * q;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < psy + psv; e += (int64_t)gridDim.x * 256) {
+    if (e < psy) {
+      const int64_t k = e / p, i = e % p;
+      const double s = sqrt(dsc[k]);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) Qo[i * qld + k + c * qps] = Y[e + c * psy] * s;
+    } else {
+      const int64_t f = e - psy;
+      const int64_t k = f / q, a = f % q;
+      const double s = sqrt(dsc[k]);
+      Po[k * pld + a] = V[f] * s;
+#pragma unroll
+      for (int c = 1; c < 4; ++c) Po[k * pld + a + c * pps] = -V[f + c * psv] * s;
+    }
+  }
+}
+
+hipError_t launch_pinv_qp(const Ctx& c, const double* Y, int64_t p, int64_t q, const double* V, const double* dsc,
+                          QView Q, QView P) {
+  const int64_t total = q * p + q * q;
+  if (total <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_pinv_qp, dim3((unsigned)blocks), dim3(256), 0, c.stream, Y, p, q, V, dsc, (double*)Q.p, Q.ld,
+                     Q.ps, (double*)P.p, P.ld, P.ps);
   return hipGetLastError();
 }
 

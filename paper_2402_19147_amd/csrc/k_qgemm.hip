@@ -479,12 +479,12 @@ hipError_t launch_gemm(const Ctx& c, int opA, int opB, double alpha, QView A, QV
 size_t residual_tiles(int64_t m, int64_t n) { return (size_t)((m + 63) / 64) * (size_t)((n + 63) / 64); }
 
 hipError_t launch_residual_gemm(const Ctx& c, QView A, QView B1, QView R, const uint8_t* mask, int64_t mask_ld,
-                                int compute, double* partials, QView* E, double e_scale) {
+                                int compute, double* partials, QView* E, double e_scale, int opR) {
   GemmArgs g = {};
   g.A = B1.p; g.lda = B1.ld; g.psa = B1.ps;
   g.B = R.p; g.ldb = R.ld; g.psb = R.ps;
   g.M = A.rows; g.N = A.cols; g.K = B1.cols;
-  g.opA = QCUR_OP_N; g.opB = QCUR_OP_N;
+  g.opA = QCUR_OP_N; g.opB = opR;
   g.alpha = 1.0; g.beta = 0.0;
   g.R0 = A.p; g.r0dt = A.dt; g.r0ld = A.ld; g.r0ps = A.ps;
   g.mask = mask; g.mask_ld = mask_ld;

@@ -107,7 +107,7 @@ hipError_t launch_gemm_batched(const Ctx& c, int opA, int opB, double alpha, QVi
 size_t residual_tiles(int64_t m, int64_t n);
 hipError_t launch_residual_gemm(const Ctx& c, QView A, QView B1, QView R, const uint8_t* mask,
                                 int64_t mask_ld, int compute, double* partials, QView* E,
-                                double e_scale);
+                                double e_scale, int opR = QCUR_OP_N);
 hipError_t launch_sum_partials(const Ctx& c, const double* partials, int64_t count, double* out,
                                int take_sqrt);
 
@@ -122,6 +122,10 @@ hipError_t launch_pinv_scale(const Ctx& c, double* Y, int64_t p, int64_t q, doub
 hipError_t launch_check_finite(const Ctx& c, QView X);
 hipError_t launch_fill_identity(const Ctx& c, double* V, int64_t q);
 hipError_t launch_pinv_apply(const Ctx& c, double* Y, int64_t p, int64_t q, double* V, const double* dsc);
+// Orthonormal-form output of the Jacobi pseudoinverse: Z^+ = P^H Q^H with
+// Q (p x q, orthonormal or zero columns) and P (q x q), both FP64.
+hipError_t launch_pinv_qp(const Ctx& c, const double* Y, int64_t p, int64_t q, const double* V, const double* dsc,
+                          QView Q, QView P);
 
 // Fast pseudoinverse pieces (CholeskyQR2), batched over up to MAXB matrices.
 constexpr int CHOL_BLOCK = 64;
