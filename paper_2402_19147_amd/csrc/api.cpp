@@ -247,12 +247,14 @@ qcur_status chol_inv(const Ctx& c, GroupWs& w, double* P) {
 // CholeskyQR attempt on a group: Z_b = X_b (tall) or X_b^H (wide), padded
 // with zero rows/columns to pp x qq (the padded Gram gets an identity block,
 // which leaves the factors of the real block unchanged).  Two passes give Q
-// orthonormal to working precision (CholeskyQR2); one pass (the normal
+// orthonormal to working precision (CholeskyQR2); passes == 0 keeps one pass
+// when its measured orthogonality defect is below orth_tol; one pass (the normal
 // equations, error ~ eps * kappa^2) is used when the products downstream are
 // FP32 or BF16.  done[b] reports whether the certificate of matrix b held;
 // for those Xp_b and rank_out[b] are written.
 qcur_status pinv_fast_group(const Ctx& c, int nb, const QView* X, double rtol, int64_t max_rank, const QView* Xp,
-                            int64_t* const* rank_out, GroupWs& w, int passes, bool* done) {
+                            int64_t* const* rank_out, GroupWs& w, int passes, bool* done, double orth_tol = 0.0,
+                            int* final_pass = nullptr) {
   const int64_t pp = w.pp, qq = w.qq;
   const int64_t zslab = 4 * pp * qq, gslab = 4 * qq * qq;
   int64_t pb[MAXB], qb[MAXB];
@@ -302,9 +304,32 @@ qcur_status pinv_fast_group(const Ctx& c, int nb, const QView* X, double rtol, i
   HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_H, 1.0, Z, P1, 0.0, Q1, QCUR_F64, w.gws, w.gws_bytes, bzp));
   double* Pf = w.P1;
   double* Qf = w.Q1;
-  if (passes >= 2) {
-    // pass 2: G = Q1^H Q1 = L2 L2^H;  P = L2^{-1} L1^{-1} = T^{-H} with Z = Q T
+  int ok[MAXB] = {0, 0, 0, 0};
+  auto decide_and_read = [&]() -> qcur_status {
+    HIPCHK(launch_pinv_decide(c, w.norms, w.fail, rtol, max_rank, nb, qb, rank_out, w.ok));
+    HIPCHK(hipMemcpyAsync(ok, w.ok, sizeof(int) * nb, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    return QCUR_OK;
+  };
+  bool second = passes >= 2;
+  bool have_g2 = false;
+  if (passes == 0) {
+    // adaptive: keep the first pass when its orthogonality defect
+    // ||Q1^H Q1 - I||_F is below orth_tol, else run the second
     HIPCHK(launch_gemm_batched(c, QCUR_OP_H, QCUR_OP_N, 1.0, Q1, Q1, 0.0, G, QCUR_F64, w.gws, w.gws_bytes, bzg));
+    have_g2 = true;
+    HIPCHK(launch_defect_batch(c, nb, w.G, qq, gslab, qb, w.norms + 3, 4));
+    HIPCHK(launch_sumsq_batch(c, nb, Pr, w.part, w.norms + 2, 4));
+    CHK(decide_and_read());
+    double nrm[4 * MAXB];
+    HIPCHK(hipMemcpyAsync(nrm, w.norms, sizeof(double) * 4 * nb, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    for (int b = 0; b < nb; ++b) second |= ok[b] && !(nrm[4 * b + 3] <= orth_tol * orth_tol);
+  }
+  if (second) {
+    // pass 2: G = Q1^H Q1 = L2 L2^H;  P = L2^{-1} L1^{-1} = T^{-H} with Z = Q T
+    if (!have_g2)
+      HIPCHK(launch_gemm_batched(c, QCUR_OP_H, QCUR_OP_N, 1.0, Q1, Q1, 0.0, G, QCUR_F64, w.gws, w.gws_bytes, bzg));
     if (padded) HIPCHK(launch_pad_identity(c, w.G, qq, gslab, nb, qb));
     CHK(chol_inv(c, w, w.P2));
     HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_N, 1.0, P2, P1, 0.0, P, QCUR_F64, w.gws, w.gws_bytes, bg));
@@ -313,13 +338,12 @@ qcur_status pinv_fast_group(const Ctx& c, int nb, const QView* X, double rtol, i
     HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_H, 1.0, Q1, P2, 0.0, Q, QCUR_F64, w.gws, w.gws_bytes, bzp));
     Pf = w.P;
     Qf = w.Q;
-  } else {
+    CHK(decide_and_read());
+  } else if (passes == 1) {
     HIPCHK(launch_sumsq_batch(c, nb, Pr, w.part, w.norms + 2, 4));
+    CHK(decide_and_read());
   }
-  HIPCHK(launch_pinv_decide(c, w.norms, w.fail, rtol, max_rank, nb, qb, rank_out, w.ok));
-  int ok[MAXB] = {0, 0, 0, 0};
-  HIPCHK(hipMemcpyAsync(ok, w.ok, sizeof(int) * nb, hipMemcpyDeviceToHost, c.stream));
-  HIPCHK(hipStreamSynchronize(c.stream));
+  if (final_pass) *final_pass = second ? 2 : 1;
   // Z^+ = T^{-1} Q^H = P^H Q^H;  for a wide X, X^+ = (Z^+)^H = Q P.  Without
   // Xp the factors stay in the group's Q and P slots (orthonormal form).
   for (int b = 0; b < nb; ++b) {
@@ -410,7 +434,8 @@ qcur_status pinv_jacobi_qp(const Ctx& c, QView X, double rtol, int64_t max_rank,
 // the views Qv[b], Pv[b] inside the group workspace.  CholeskyQR2 where its
 // certificate holds, else the Jacobi SVD.
 qcur_status pinv_group_qp(const Ctx& c, int nb, const QView* X, double rtol, int64_t max_rank,
-                          int64_t* const* rank_out, GroupWs& gw, PinvWs jw, QView* Qv, QView* Pv) {
+                          int64_t* const* rank_out, GroupWs& gw, PinvWs jw, QView* Qv, QView* Pv,
+                          double orth_tol) {
   const int64_t pp = gw.pp, qq = gw.qq;
   const int64_t zslab = 4 * pp * qq, gslab = 4 * qq * qq;
   QView fx[MAXB];
@@ -437,11 +462,15 @@ qcur_status pinv_group_qp(const Ctx& c, int nb, const QView* X, double rtol, int
     idx[nf] = b;
     ++nf;
   }
-  // slots: the CholeskyQR problems first, then the small ones
+  // slots: the CholeskyQR problems first, then the small ones; the factors
+  // live in the buffers of the last CholeskyQR pass that ran
+  int final_pass = 2;
   auto slot = [&](int s, int b) {
     PinvPlan pl = pinv_plan(X[b].rows, X[b].cols);
-    Qv[b] = QView{gw.Q + s * zslab, pl.pp, pl.qq, qq, pp * qq, QCUR_F64};
-    Pv[b] = QView{gw.P + s * gslab, pl.qq, pl.qq, qq, qq * qq, QCUR_F64};
+    double* qb = final_pass == 2 ? gw.Q : gw.Q1;
+    double* pb = final_pass == 2 ? gw.P : gw.P1;
+    Qv[b] = QView{qb + s * zslab, pl.pp, pl.qq, qq, pp * qq, QCUR_F64};
+    Pv[b] = QView{pb + s * gslab, pl.qq, pl.qq, qq, qq * qq, QCUR_F64};
   };
   if (nf > 0) {
     bool done[MAXB];
@@ -449,7 +478,8 @@ qcur_status pinv_group_qp(const Ctx& c, int nb, const QView* X, double rtol, int
     for (int f = 0; f < nf; ++f) rg = std::max(rg, rt[idx[f]]);
     GroupWs w = gw;
     w.nb = nf;
-    CHK(pinv_fast_group(c, nf, fx, rg, max_rank, nullptr, fr, w, 2, done));
+    CHK(pinv_fast_group(c, nf, fx, rg, max_rank, nullptr, fr, w, orth_tol > 0.0 ? 0 : 2, done, orth_tol,
+                        &final_pass));
     for (int f = 0; f < nf; ++f) {
       slot(f, idx[f]);
       if (!done[f]) CHK(pinv_jacobi_qp(c, fx[f], rt[idx[f]], max_rank, Qv[idx[f]], Pv[idx[f]], fr[f], jw));
@@ -563,7 +593,11 @@ qcur_status approx_run(const Ctx& c, const ApproxArgs& a, int64_t m, int64_t n, 
       if (!count_only) {
         QView xs[2] = {a.C, a.R};
         int64_t* ro[2] = {a.rank_out, a.rank_out ? a.rank_out + 1 : nullptr};
-        CHK(pinv_group_qp(c, 2, xs, a.rtol, a.max_rank, ro, gw, jw, Qv, Pv));
+        // FP64 products: CholeskyQR2; FP32/BF16 products: a second pass only
+        // when the first leaves Q^H Q - I above a small fraction of their
+        // rounding unit
+        const double orth_tol = a.compute == QCUR_F64 ? 0.0 : a.compute == QCUR_F32 ? 0x1p-26 : 0x1p-12;
+        CHK(pinv_group_qp(c, 2, xs, a.rtol, a.max_rank, ro, gw, jw, Qv, Pv, orth_tol));
       } else {
         Qv[0] = QView{nullptr, m, cc, cc, m * cc, QCUR_F64};
         Qv[1] = QView{nullptr, n, r, r, n * r, QCUR_F64};

@@ -382,4 +382,40 @@ hipError_t launch_zero_i32(const Ctx& c, int* p, int64_t n) {
   return hipGetLastError();
 }
 
+// ||G_b - I||_F^2 over the leading q_b x q_b block of up to MAXB Gram
+// matrices (n x n, sbatch apart), one workgroup each, fixed-order sums:
+// the orthogonality defect of Q after a CholeskyQR pass (G = Q^H Q).
+struct DefectBatch {
+  int q[MAXB];
+};
+__global__ __launch_bounds__(256) void k_defect(const double* __restrict__ G, int64_t n, int64_t sbatch,
+                                                DefectBatch db, double* out, int ostride) {
+  __shared__ double red[256];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int64_t q = db.q[b], nn = n * n;
+  const double* g = G + (int64_t)b * sbatch;
+  double s = 0.0;
+  for (int64_t e = tid; e < q * q; e += 256) {
+    const int64_t i = e / q, j = e % q;
+    const int64_t o = i * n + j;
+    const double d0 = g[o] - (i == j ? 1.0 : 0.0);
+    s += d0 * d0 + g[o + nn] * g[o + nn] + g[o + 2 * nn] * g[o + 2 * nn] + g[o + 3 * nn] * g[o + 3 * nn];
+  }
+  red[tid] = s;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) out[(int64_t)b * ostride] = red[0];
+}
+
+hipError_t launch_defect_batch(const Ctx& c, int nb, const double* G, int64_t n, int64_t sbatch, const int64_t* q,
+                               double* out, int ostride) {
+  DefectBatch db{};
+  for (int b = 0; b < nb; ++b) db.q[b] = (int)q[b];
+  hipLaunchKernelGGL(k_defect, dim3(nb), dim3(256), 0, c.stream, G, n, sbatch, db, out, ostride);
+  return hipGetLastError();
+}
+
 }  // namespace qcur
