@@ -318,7 +318,7 @@ qcur_status pinv_fast_group(const Ctx& c, int nb, const QView* X, double rtol, i
     // ||Q1^H Q1 - I||_F is below orth_tol, else run the second
     HIPCHK(launch_gemm_batched(c, QCUR_OP_H, QCUR_OP_N, 1.0, Q1, Q1, 0.0, G, QCUR_F64, w.gws, w.gws_bytes, bzg));
     have_g2 = true;
-    HIPCHK(launch_defect_batch(c, nb, w.G, qq, gslab, qb, w.norms + 3, 4));
+    HIPCHK(launch_defect_batch(c, nb, w.G, qq, gslab, qb, w.part, w.norms + 3, 4));
     HIPCHK(launch_sumsq_batch(c, nb, Pr, w.part, w.norms + 2, 4));
     CHK(decide_and_read());
     double nrm[4 * MAXB];

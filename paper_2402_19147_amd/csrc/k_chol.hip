@@ -28,18 +28,20 @@ __device__ inline Qd qmul(Qd a, Qd b) {
             a.w * b.y - a.x * b.z + a.y * b.w + a.z * b.x, a.w * b.z + a.x * b.y - a.y * b.x + a.z * b.w};
 }
 
-// In-place factorisation of one w x w Hermitian diagonal block (w <= 64)
-// with one barrier per step and every operand of a step loaded before any
-// store.  Cholesky (right-looking): at step j every
-// thread subtracts a[i][j] conj(a[k][j]) / d_j from its trailing elements
-// (j < k <= i), while the scaled column L[i][j] = a[i][j] / sqrt(d_j) is
-// stored conjugated in the unused upper triangle (a[j][i] = conj(L[i][j]),
-// i.e. L^H).  Then the triangular inverse P = L^{-1} overwrites the stale
-// lower triangle, column by column from the last one:
-//   P[i][j] = -(sum_{k=j+1..i} P[i][k] L[k][j]) / L[j][j]   (i > j).
+// Factorisation G = L L^H and inverse P = L^{-1} of one w x w Hermitian
+// positive definite diagonal block (w <= 64) in LDS, blocked by 16:
+//  1. one wave factors the 16 x 16 diagonal block in place (right-looking,
+//     no barriers: a wave's LDS operations complete in order) and inverts it
+//     by forward substitution with four lanes per column; the inverse's
+//     strict lower part is kept transposed in the block's unused upper
+//     triangle and 1/L[j][j] in rdg;
+//  2. the panel below becomes L_ik = A_ik (L_kk^{-1})^H;
+//  3. the trailing lower triangle loses L_ik L_jk^H;
+// then block row by block row P_ij = -P_ii sum_{k=j}^{i-1} L_ik P_kj.
 // Only P is written back (lower triangle; the upper one is zeroed).  A pivot
 // that is not finite and positive sets *fail.
 constexpr int CHOL_THREADS = 512;
+constexpr int SB = 16;  // sub-block edge
 
 // 1/sqrt(d) from the hardware estimate refined by two Newton steps (the
 // pivot feeds only products, so correct rounding is not needed).
@@ -58,12 +60,113 @@ __device__ inline double dpp_f64(double v) {
   return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
-// Sum over the 8 lanes 8g..8g+7; the total is valid in lane 8g+4.
-__device__ inline double sum8_dpp(double v) {
-  v += dpp_f64<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]: pairs
-  v += dpp_f64<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]: quads
-  v += dpp_f64<0x114, 0xf>(v);  // row_shr:4: lane 8g+4 adds the quad below it
+// Sum over the 4 lanes of a quad (every lane gets the total).
+__device__ inline double sum4_dpp(double v) {
+  v += dpp_f64<0xB1, 0xf>(v);  // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E, 0xf>(v);  // quad_perm [2,3,0,1]
   return v;
+}
+
+#define LDS_FENCE() __asm__ __volatile__("" ::: "memory")
+
+typedef double Tile[4][CB][CB + 1];
+
+__device__ inline Qd ldq(const Tile& a, int i, int j) { return Qd{a[0][i][j], a[1][i][j], a[2][i][j], a[3][i][j]}; }
+__device__ inline void stq(Tile& a, int i, int j, Qd v) {
+  a[0][i][j] = v.w;
+  a[1][i][j] = v.x;
+  a[2][i][j] = v.y;
+  a[3][i][j] = v.z;
+}
+__device__ inline void qacc(Qd& s, Qd u) {
+  s.w += u.w;
+  s.x += u.x;
+  s.y += u.y;
+  s.z += u.z;
+}
+// Element (r, c) (r >= c) of the inverse of diagonal block at kb: 1/L on the
+// diagonal, else kept transposed in the block's upper triangle.
+__device__ inline Qd pdiag(const Tile& a, const double* rdg, int kb, int r, int c) {
+  return r == c ? Qd{rdg[kb + r], 0.0, 0.0, 0.0} : ldq(a, kb + c, kb + r);
+}
+
+// Wave-level factorisation and inversion of the diagonal block at kb.
+__device__ void chol_diag(Tile& a, double* rdg, int kb, int kw, int lane, int* bad) {
+  for (int j = 0; j < kw; ++j) {
+    const int t = kw - j - 1;
+    const int cnt = t * (t + 1) / 2;
+    const double d = a[0][kb + j][kb + j];
+    Qd li[2], lk[2], x[2], lh{0, 0, 0, 0};
+    int ii[2], kk[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int e = lane + 64 * m;
+      ii[m] = kk[m] = -1;
+      if (e < cnt) {
+        const int r = (int)((sqrtf((float)(8 * e + 1)) - 1.0f) * 0.5f);
+        const int q = e - r * (r + 1) / 2;
+        ii[m] = kb + j + 1 + r;
+        kk[m] = kb + j + 1 + q;
+        li[m] = ldq(a, ii[m], kb + j);
+        lk[m] = ldq(a, kk[m], kb + j);
+        x[m] = ldq(a, ii[m], kk[m]);
+      }
+    }
+    if (lane < t) lh = ldq(a, kb + j + 1 + lane, kb + j);
+    LDS_FENCE();
+    const bool ok = d > 0.0 && d < INFINITY;
+    const double rs = rsqrt_nr(ok ? d : 1.0);
+    const double rd = rs * rs;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      if (ii[m] >= 0) {
+        const Qd q = qmul_conj(li[m], lk[m]);
+        stq(a, ii[m], kk[m], Qd{x[m].w - q.w * rd, x[m].x - q.x * rd, x[m].y - q.y * rd, x[m].z - q.z * rd});
+      }
+    }
+    if (lane < t) stq(a, kb + j + 1 + lane, kb + j, Qd{lh.w * rs, lh.x * rs, lh.y * rs, lh.z * rs});
+    if (lane == 0) {
+      a[0][kb + j][kb + j] = ok ? d * rs : 1.0;
+      rdg[kb + j] = rs;
+      if (!ok) *bad = 1;
+    }
+    LDS_FENCE();
+  }
+  // forward substitution, four lanes per column c = lane / 4 (lane's k are
+  // sub, sub + 4, ...):  P[i][c] = -(1/L[i][i]) sum_{k=c}^{i-1} L[i][k] P[k][c]
+  const int c = lane >> 2, sub = lane & 3;
+  Qd pk[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int k = sub + 4 * m;
+    pk[m] = (k == c && c < kw) ? Qd{rdg[kb + c], 0.0, 0.0, 0.0} : Qd{0, 0, 0, 0};
+  }
+  for (int i = 1; i < kw; ++i) {
+    Qd s{0, 0, 0, 0};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int k = sub + 4 * m;
+      if (k < i) qacc(s, qmul(ldq(a, kb + i, kb + k), pk[m]));
+    }
+    s.w = sum4_dpp(s.w);
+    s.x = sum4_dpp(s.x);
+    s.y = sum4_dpp(s.y);
+    s.z = sum4_dpp(s.z);
+    const double f = -rdg[kb + i];
+    if (c < kw && i > c && (i & 3) == sub) {
+      const Qd v{f * s.w, f * s.x, f * s.y, f * s.z};
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+        if (sub + 4 * m == i) pk[m] = v;
+    }
+  }
+  // strict lower part, transposed into the upper triangle: a[c][k] = P[k][c]
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int k = sub + 4 * m;
+    if (c < kw && k < kw && k > c) stq(a, kb + c, kb + k, pk[m]);
+  }
+  LDS_FENCE();
 }
 
 __global__ __launch_bounds__(CHOL_THREADS) void k_chol_block(const double* __restrict__ G0, double* __restrict__ P0,
@@ -72,10 +175,11 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_block(const double* __res
   const double* __restrict__ G = G0 + (int64_t)blockIdx.x * sbatch;
   double* __restrict__ Pg = P0 + (int64_t)blockIdx.x * sbatch;
   int* fail = fail0 + blockIdx.x;
-  __shared__ double a[4][CB][CB + 1];
-  __shared__ double rdg[CB];  // 1 / L[j][j]
+  __shared__ Tile a;
+  __shared__ double sbuf[3][4][SB][SB + 1];  // block-row sums of the inverse phase
+  __shared__ double rdg[CB];                 // 1 / L[j][j]
   __shared__ int bad;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) bad = 0;
   for (int e = tid; e < w * w; e += CHOL_THREADS) {
     const int i = e / w, j = e % w;
@@ -86,125 +190,94 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_block(const double* __res
     }
   }
   __syncthreads();
-  // Cholesky: the t(t+1)/2 trailing entries of step j are spread over the
-  // threads (entry e is row r, column q of the trailing triangle with
-  // e = r(r+1)/2 + q; a thread's (r, q) pairs do not depend on j), so the work
-  // per step shrinks with the triangle.  Each step issues all its loads
-  // before the pivot's reciprocal square root is needed.
-  constexpr int SLOTS = (CB * (CB - 1) / 2 + CHOL_THREADS - 1) / CHOL_THREADS;
-  int tr[SLOTS], tq[SLOTS];
+  for (int kb = 0; kb < w; kb += SB) {
+    const int kw = min(SB, w - kb);
+    if (wave == 0) chol_diag(a, rdg, kb, kw, lane, &bad);
+    __syncthreads();
+    const int r0 = kb + kw, rows = w - r0;
+    if (rows <= 0) break;
+    // panel: L[i][kb + c] = sum_{t <= c} A[i][kb + t] conj(P_kk[c][t])
+    Qd pv[2];
+    int pi[2], pc[2];
 #pragma unroll
-  for (int m = 0; m < SLOTS; ++m) {
-    const int e = tid + m * CHOL_THREADS;
-    const int r = (int)((sqrtf((float)(8 * e + 1)) - 1.0f) * 0.5f);
-    tr[m] = r;
-    tq[m] = e - r * (r + 1) / 2;
-  }
-  const int wave_e0 = (tid >> 6) * 64;
-  for (int j = 0; j < w; ++j) {
-    const int t = w - j - 1;
-    const int cnt = t * (t + 1) / 2;
-    const double d = a[0][j][j];
-    Qd li[SLOTS], lk[SLOTS], x[SLOTS];
-#pragma unroll
-    for (int m = 0; m < SLOTS; ++m) {
-      if (wave_e0 + m * CHOL_THREADS < cnt) {  // uniform over the wave
-        const int e = tid + m * CHOL_THREADS;
-        const int i = j + 1 + tr[m], k = j + 1 + tq[m];
-        if (e < cnt) {
-          li[m] = Qd{a[0][i][j], a[1][i][j], a[2][i][j], a[3][i][j]};
-          lk[m] = Qd{a[0][k][j], a[1][k][j], a[2][k][j], a[3][k][j]};
-          x[m] = Qd{a[0][i][k], a[1][i][k], a[2][i][k], a[3][i][k]};
-        }
-      }
-    }
-    Qd lh{0, 0, 0, 0};
-    if (tid < t) lh = Qd{a[0][j + 1 + tid][j], a[1][j + 1 + tid][j], a[2][j + 1 + tid][j], a[3][j + 1 + tid][j]};
-    const bool ok = d > 0.0 && d < INFINITY;
-    const double rs = rsqrt_nr(ok ? d : 1.0);
-    const double rd = rs * rs;
-    if (tid == 0) {
-      rdg[j] = rs;
-      if (!ok) bad = 1;
-    }
-    if (tid < t) {  // L^H row j into the upper triangle (never read in this step)
-      const int k = j + 1 + tid;
-      a[0][j][k] = lh.w * rs;
-      a[1][j][k] = -lh.x * rs;
-      a[2][j][k] = -lh.y * rs;
-      a[3][j][k] = -lh.z * rs;
-    }
-#pragma unroll
-    for (int m = 0; m < SLOTS; ++m) {
-      if (wave_e0 + m * CHOL_THREADS < cnt) {
-        const int e = tid + m * CHOL_THREADS;
-        const int i = j + 1 + tr[m], k = j + 1 + tq[m];
-        if (e < cnt) {
-          const Qd q = qmul_conj(li[m], lk[m]);
-          a[0][i][k] = x[m].w - q.w * rd;
-          a[1][i][k] = x[m].x - q.x * rd;
-          a[2][i][k] = x[m].y - q.y * rd;
-          a[3][i][k] = x[m].z - q.z * rd;
-        }
+    for (int m = 0; m < 2; ++m) {
+      const int e = tid + CHOL_THREADS * m;
+      pi[m] = -1;
+      if (e < rows * kw) {
+        pi[m] = r0 + e / kw;
+        pc[m] = e % kw;
+        Qd s{0, 0, 0, 0};
+        for (int t = 0; t <= pc[m]; ++t) qacc(s, qmul_conj(ldq(a, pi[m], kb + t), pdiag(a, rdg, kb, pc[m], t)));
+        pv[m] = s;
       }
     }
     __syncthreads();
-  }
-  // P's diagonal (1 / L[i][i]) replaces the stale lower diagonal
-  for (int i = tid; i < w; i += CHOL_THREADS) {
-    a[0][i][i] = rdg[i];
-    a[1][i][i] = a[2][i][i] = a[3][i][i] = 0.0;
-  }
-  __syncthreads();
-  // inverse: 8 threads per row (lanes 8g..8g+7 of a wave), reduced in
-  // registers with DPP (pairs, quads, then the quad 4 lanes below); the row
-  // total lands in lane 8g+4.  Waves whose rows are all done only wait.
-  const int sub = tid & 7, row = tid >> 3;
-  const int wave_row0 = (tid >> 6) * 8;
-  for (int j = w - 2; j >= 0; --j) {
-    const int t = w - j - 1;
-    if (wave_row0 < t) {
-      const int i = j + 1 + row;
-      const double f = -rdg[j];
-      Qd pk[8], lj[8];
 #pragma unroll
-      for (int m = 0; m < 8; ++m) {
-        const int k = j + 1 + sub + 8 * m;
-        if (row < t && k <= i) {
-          pk[m] = Qd{a[0][i][k], a[1][i][k], a[2][i][k], a[3][i][k]};
-          lj[m] = Qd{a[0][j][k], a[1][j][k], a[2][j][k], a[3][j][k]};  // conj(L[k][j])
-        } else {
-          pk[m] = Qd{0, 0, 0, 0};
-          lj[m] = Qd{0, 0, 0, 0};
+    for (int m = 0; m < 2; ++m)
+      if (pi[m] >= 0) stq(a, pi[m], kb + pc[m], pv[m]);
+    __syncthreads();
+    // trailing: A[i][j] -= sum_t L[i][kb + t] conj(L[j][kb + t]),  r0 <= j <= i < w
+    const int tcnt = rows * (rows + 1) / 2;
+    for (int e = tid; e < tcnt; e += CHOL_THREADS) {
+      const int r = (int)((sqrtf((float)(8 * e + 1)) - 1.0f) * 0.5f);
+      const int q = e - r * (r + 1) / 2;
+      const int i = r0 + r, j = r0 + q;
+      Qd s = ldq(a, i, j);
+      for (int t = 0; t < kw; ++t) {
+        const Qd u = qmul_conj(ldq(a, i, kb + t), ldq(a, j, kb + t));
+        s.w -= u.w;
+        s.x -= u.x;
+        s.y -= u.y;
+        s.z -= u.z;
+      }
+      stq(a, i, j, s);
+    }
+    __syncthreads();
+  }
+  // inverse, block row by block row: S_j = sum_{k=j}^{i-1} L_ik P_kj for all
+  // j < i at once, then P_ij = -P_ii S_j overwrites L_ij
+  const int nsb = (w + SB - 1) / SB;
+  for (int bi = 1; bi < nsb; ++bi) {
+    const int i0 = bi * SB, iw = min(SB, w - i0);
+    for (int e = tid; e < bi * SB * SB; e += CHOL_THREADS) {
+      const int bj = e / (SB * SB), r = (e / SB) % SB, c = e % SB;
+      if (r >= iw) continue;
+      const int j0 = bj * SB;
+      Qd s{0, 0, 0, 0};
+      for (int bk = bj; bk < bi; ++bk) {
+        const int k0 = bk * SB;
+        for (int t = 0; t < SB; ++t) {
+          const Qd pkj = bk == bj ? (t >= c ? pdiag(a, rdg, k0, t, c) : Qd{0, 0, 0, 0}) : ldq(a, k0 + t, j0 + c);
+          qacc(s, qmul(ldq(a, i0 + r, k0 + t), pkj));
         }
       }
+      sbuf[bj][0][r][c] = s.w;
+      sbuf[bj][1][r][c] = s.x;
+      sbuf[bj][2][r][c] = s.y;
+      sbuf[bj][3][r][c] = s.z;
+    }
+    __syncthreads();
+    for (int e = tid; e < bi * SB * SB; e += CHOL_THREADS) {
+      const int bj = e / (SB * SB), r = (e / SB) % SB, c = e % SB;
+      if (r >= iw) continue;
       Qd s{0, 0, 0, 0};
-#pragma unroll
-      for (int m = 0; m < 8; ++m) {
-        const Qd u = qmul_conj(pk[m], lj[m]);  // P[i][k] L[k][j]
-        s.w += u.w;
-        s.x += u.x;
-        s.y += u.y;
-        s.z += u.z;
+      for (int t = 0; t <= r; ++t) {
+        const Qd sv{sbuf[bj][0][t][c], sbuf[bj][1][t][c], sbuf[bj][2][t][c], sbuf[bj][3][t][c]};
+        qacc(s, qmul(pdiag(a, rdg, i0, r, t), sv));
       }
-      s.w = sum8_dpp(s.w);
-      s.x = sum8_dpp(s.x);
-      s.y = sum8_dpp(s.y);
-      s.z = sum8_dpp(s.z);
-      if (row < t && sub == 4) {
-        a[0][i][j] = f * s.w;
-        a[1][i][j] = f * s.x;
-        a[2][i][j] = f * s.y;
-        a[3][i][j] = f * s.z;
-      }
+      stq(a, i0 + r, bj * SB + c, Qd{-s.w, -s.x, -s.y, -s.z});
     }
     __syncthreads();
   }
   for (int e = tid; e < w * w; e += CHOL_THREADS) {
     const int i = e / w, j = e % w;
     const int64_t o = (int64_t)i * ld + j;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) Pg[o + c * ps] = (j <= i) ? a[c][i][j] : 0.0;
+    Qd v{0, 0, 0, 0};
+    if (j <= i) v = (i / SB == j / SB) ? pdiag(a, rdg, (i / SB) * SB, i % SB, j % SB) : ldq(a, i, j);
+    Pg[o] = v.w;
+    Pg[o + ps] = v.x;
+    Pg[o + 2 * ps] = v.y;
+    Pg[o + 3 * ps] = v.z;
   }
   if (tid == 0 && bad) atomicOr(fail, 1);
 }
@@ -383,38 +456,39 @@ hipError_t launch_zero_i32(const Ctx& c, int* p, int64_t n) {
 }
 
 // ||G_b - I||_F^2 over the leading q_b x q_b block of up to MAXB Gram
-// matrices (n x n, sbatch apart), one workgroup each, fixed-order sums:
-// the orthogonality defect of Q after a CholeskyQR pass (G = Q^H Q).
+// matrices (n x n, sbatch apart): the orthogonality defect of Q after a
+// CholeskyQR pass (G = Q^H Q).  Grid (SUMSQ_BLOCKS, nb) of partial sums,
+// then the fixed-order fold of the sums of squares.
 struct DefectBatch {
   int q[MAXB];
 };
 __global__ __launch_bounds__(256) void k_defect(const double* __restrict__ G, int64_t n, int64_t sbatch,
-                                                DefectBatch db, double* out, int ostride) {
-  __shared__ double red[256];
-  const int b = blockIdx.x, tid = threadIdx.x;
+                                                DefectBatch db, double* partials) {
+  __shared__ double red[4];
+  const int b = blockIdx.y, tid = threadIdx.x;
   const int64_t q = db.q[b], nn = n * n;
   const double* g = G + (int64_t)b * sbatch;
   double s = 0.0;
-  for (int64_t e = tid; e < q * q; e += 256) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + tid; e < q * q; e += (int64_t)gridDim.x * 256) {
     const int64_t i = e / q, j = e % q;
     const int64_t o = i * n + j;
     const double d0 = g[o] - (i == j ? 1.0 : 0.0);
     s += d0 * d0 + g[o + nn] * g[o + nn] + g[o + 2 * nn] * g[o + 2 * nn] + g[o + 3 * nn] * g[o + 3 * nn];
   }
-  red[tid] = s;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = s;
   __syncthreads();
-  for (int w = 128; w >= 1; w >>= 1) {
-    if (tid < w) red[tid] += red[tid + w];
-    __syncthreads();
-  }
-  if (tid == 0) out[(int64_t)b * ostride] = red[0];
+  if (tid == 0) partials[(int64_t)b * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 hipError_t launch_defect_batch(const Ctx& c, int nb, const double* G, int64_t n, int64_t sbatch, const int64_t* q,
-                               double* out, int ostride) {
+                               double* partials, double* out, int ostride) {
   DefectBatch db{};
   for (int b = 0; b < nb; ++b) db.q[b] = (int)q[b];
-  hipLaunchKernelGGL(k_defect, dim3(nb), dim3(256), 0, c.stream, G, n, sbatch, db, out, ostride);
+  hipLaunchKernelGGL(k_defect, dim3(SUMSQ_BLOCKS, nb), dim3(256), 0, c.stream, G, n, sbatch, db, partials);
+  hipLaunchKernelGGL(k_fold_batch, dim3(nb), dim3(256), 0, c.stream, (const double*)partials, SUMSQ_BLOCKS, out,
+                     ostride);
   return hipGetLastError();
 }
 

@@ -138,7 +138,7 @@ hipError_t launch_pad_identity(const Ctx& c, double* G, int64_t n, int64_t sbatc
 hipError_t launch_pinv_decide(const Ctx& c, const double* norms, const int* fail, double rtol, int64_t max_rank,
                               int nb, const int64_t* q, int64_t* const* rank_out, int* ok);
 hipError_t launch_defect_batch(const Ctx& c, int nb, const double* G, int64_t n, int64_t sbatch, const int64_t* q,
-                               double* out, int ostride);
+                               double* partials, double* out, int ostride);
 hipError_t launch_zero(const Ctx& c, double* p, int64_t n);
 hipError_t launch_zero_i32(const Ctx& c, int* p, int64_t n);
 
