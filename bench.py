@@ -6,13 +6,20 @@ A step is one whole QMCUR solve (Algorithm 1) of the colour-image-shaped
 workload: a 1024 x 1024 pure quaternion matrix of rank 50 plus N(0, 0.01^2)
 noise, length sampling of c = r = 200 columns and rows, the least-squares
 core U = C^+ A R^+ and the residual ||A - CUR||_F.  Every step runs
-probabilities -> draws -> gathers -> FP64 pseudoinverses -> core products ->
-residual on the GPU, with the input already resident in HBM.
+probabilities -> draws -> gathers -> FP64 factors of C and R -> core
+products -> residual on the GPU, with the input already resident in HBM.
 
-Variants: plain FP64 (the reference rate), FP32 matrix-core products with one
-refinement step, and BF16-operand products with one refinement step.  The
-headline value is the fastest mixed variant whose CUR product is within
-1e-3 relative Frobenius error of the FP64 one.  Prints one JSON line.
+Variants: plain FP64 (the reference rate), FP32 matrix-core products
+(with and without one refinement step) and BF16-operand products with one
+refinement step.  The headline value is the fastest mixed variant whose CUR
+product is within 1e-3 relative Frobenius error of the FP64 one.
+
+Also reported on the same JSON line: the roofline of the dominant
+matrix-core kernel (T = A Q_R, timed alone with HIP events on the stream
+the library launches on), the quaternion GEMM rate at the 4096 x 400 x 4096
+shapes in each dtype, the 512-problem uneven batch (graph replay) against
+plain FP64 solves one at a time, the 4096 x 4096 dense workload, and the
+FP64 reference checker timed on the host cores.
 """
 from __future__ import annotations
 
@@ -36,14 +43,19 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--gemm-reps", type=int, default=20)
+    ap.add_argument("--no-extra", action="store_true", help="skip the batch and dense workloads")
     return ap.parse_args()
+
+
+def log(msg):
+    print(f"# {msg}", file=sys.stderr, flush=True)
 
 
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the batched and single-matrix paths shard as described in DESIGN.md).", file=sys.stderr)
+              "(how the path would shard is described in DESIGN.md).", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -53,6 +65,7 @@ def main():
     cfg = workloads.WORKLOADS[WORKLOAD]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
     A_host = workloads.color_like(cfg["m"], cfg["n"], cfg["k"], cfg["seed"], cfg["noise"])
     A64 = torch.tensor(A_host, device=dev)
     A32 = A64.to(torch.float32)
@@ -65,14 +78,12 @@ def main():
         "f32_refine1": dict(A=A32, compute=q.F32, refine=1),
         "bf16_refine1": dict(A=A32, compute=q.BF16, refine=1),
     }
-
     solvers = {name: q.Solver(m, n, c, r, core=q.CORE_CAR, compute=v["compute"]) for name, v in variants.items()}
 
     def step(name, v):
         return solvers[name](v["A"], sampling=q.LENGTH, seed=seed, refine_steps=v["refine"])
 
     results = {}
-    stream = torch.cuda.current_stream()
     for name, v in variants.items():
         for _ in range(args.warmup):
             step(name, v)
@@ -85,7 +96,7 @@ def main():
         dt = (time.perf_counter() - t0) / args.steps
         q.sync_status()
         results[name] = dict(ms_per_step=dt * 1e3, solves_per_s=1.0 / dt)
-        print(f"# {name}: {dt * 1e3:.3f} ms/solve", file=sys.stderr, flush=True)
+        log(f"{name}: {dt * 1e3:.3f} ms/solve")
 
     # accuracy of each variant: CUR product against the FP64 one (same draws)
     ref = q.solve(A64, c, r, sampling=q.LENGTH, core=q.CORE_CAR, compute=q.F64, seed=seed, want_B=True)
@@ -95,54 +106,64 @@ def main():
         out = q.solve(v["A"], c, r, sampling=q.LENGTH, core=q.CORE_CAR, compute=v["compute"], seed=seed,
                       refine_steps=v["refine"], want_B=True)
         B = out["B"].to(torch.float64)
-        err = float(torch.linalg.vector_norm(B - Bref) / torch.linalg.vector_norm(Bref))
-        results[name]["cur_rel_err_vs_f64"] = err
+        results[name]["cur_rel_err_vs_f64"] = float(torch.linalg.vector_norm(B - Bref) / torch.linalg.vector_norm(Bref))
         results[name]["rel_residual"] = float(out["residual"].cpu()[0]) / nA
         results[name]["same_draws"] = bool(torch.equal(out["I"], ref["I"]) and torch.equal(out["J"], ref["J"]))
     q.sync_status()
 
-    # headline: fastest mixed variant within 1e-3 of the FP64 CUR product
     mixed = [k for k in ("f32", "f32_refine1", "bf16_refine1") if results[k]["cur_rel_err_vs_f64"] <= 1e-3]
     head = max(mixed, key=lambda k: results[k]["solves_per_s"]) if mixed else "plain_f64"
 
-    # dominant qGEMM of the solve, timed alone with HIP events on the library's stream:
-    # T = A R^+ with A 1024 x 1024 and R^+ 1024 x 200 (FP32 matrix cores)
-    def time_gemm(Aop, Bop, compute, reps):
-        D = q.gemm(Aop, Bop, compute=compute)
+    def time_gemm(Aop, Bop, compute, reps, opB=q.OP_N):
+        D = q.gemm(Aop, Bop, opB=opB, compute=compute)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(reps):
-            q.gemm(Aop, Bop, D=D, compute=compute)
+            q.gemm(Aop, Bop, opB=opB, D=D, compute=compute)
         e1.record(stream)
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps * 1e-3
 
+    # dominant matrix-core kernel of the solve: T = A Q_R with A 1024 x 1024
+    # and the orthonormal factor Q_R 1024 x 200, in the headline's dtype
     rng = np.random.default_rng(0)
-    Rp32 = torch.tensor(rng.standard_normal((4, n, r)), dtype=torch.float32, device=dev)
     hd = variants[head]["compute"]
     tdt = {q.F64: torch.float64, q.F32: torch.float32, q.BF16: torch.bfloat16}[hd]
-    Ag = A64.to(tdt)
-    Bg = Rp32.to(tdt)
-    t_gemm = time_gemm(Ag, Bg, hd, args.gemm_reps)
+    Qr = torch.tensor(rng.standard_normal((4, n, r)), dtype=tdt, device=dev)
+    t_gemm = time_gemm(A64.to(tdt), Qr, hd, args.gemm_reps)
     flops = 32.0 * m * n * r
     peak = {q.F64: 78.6, q.F32: 157.3, q.BF16: 2500.0}[hd]
     achieved = flops / t_gemm / 1e12
-    roofline = dict(bound="mfma", kernel="qgemm T = A R^+ (1024x1024 . 1024x200)",
-                    achieved=achieved, peak=peak, unit="TFLOP/s", frac=achieved / peak, traffic=None,
-                    avg_launch_us=t_gemm * 1e6)
+    roofline = dict(bound="mfma", kernel=f"qgemm T = A Q_R ({m}x{n} . {n}x{r})", achieved=achieved, peak=peak,
+                    unit="TFLOP/s", frac=achieved / peak, traffic=None, avg_launch_us=t_gemm * 1e6,
+                    algorithmic_flop_per_launch=flops)
 
-    # qGEMM throughput on the large dense shapes (4096 x 400 x 4096), each dtype
+    # quaternion GEMM rate at the dense shapes, every dtype
     qg = {}
     for dname, dcode, dt in (("f64", q.F64, torch.float64), ("f32", q.F32, torch.float32),
                              ("bf16", q.BF16, torch.bfloat16)):
-        X = torch.tensor(rng.standard_normal((4, 4096, 400)), dtype=dt, device=dev)
-        Y = torch.tensor(rng.standard_normal((4, 400, 4096)), dtype=dt, device=dev)
-        t = time_gemm(X, Y, dcode, 5)
-        tf = 32.0 * 4096 * 400 * 4096 / t / 1e12
         pk = {q.F64: 78.6, q.F32: 157.3, q.BF16: 2500.0}[dcode]
-        qg[dname] = dict(shape="4096x400x4096", tflops=tf, frac_of_peak=tf / pk, ms=t * 1e3)
-        del X, Y
+        for shape in ((4096, 400, 4096), (4096, 4096, 400)):
+            M, K, N = shape
+            X = torch.tensor(rng.standard_normal((4, M, K)), dtype=dt, device=dev)
+            Y = torch.tensor(rng.standard_normal((4, K, N)), dtype=dt, device=dev)
+            t = time_gemm(X, Y, dcode, 5)
+            tf = 32.0 * M * K * N / t / 1e12
+            qg[f"{dname}_{M}x{K}x{N}"] = dict(tflops=tf, frac_of_peak=tf / pk, ms=t * 1e3)
+            del X, Y
+    log("qgemm: " + ", ".join(f"{k} {v['tflops']:.1f}" for k, v in qg.items()))
+
+    extra = {}
+    if not args.no_extra:
+        extra["batch_512"] = bench_batch(q, torch, workloads, dev, args)
+        extra["dense_4096"] = bench_dense(q, torch, workloads, dev, args)
+    # a plain copy of known size, for scaling HBM byte counters of profiled runs
+    src = torch.empty(64 * 2 ** 20, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -162,7 +183,7 @@ def main():
         "dtype": {"plain_f64": "f64", "f32": "f32", "f32_refine1": "f32", "bf16_refine1": "bf16"}[head],
         "data": "synthetic",
         "config": {"workload": "color_1024: 1024x1024 pure quaternion, rank 50 + N(0,0.01^2), length "
-                               "sampling c=r=200, U=C^+AR^+, FP64 pinv", "variant": head},
+                               "sampling c=r=200, U=C^+AR^+, FP64 factors of C and R", "variant": head},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "variants": results,
@@ -170,7 +191,112 @@ def main():
         "speedup_vs_plain_f64": results[head]["solves_per_s"] / results["plain_f64"]["solves_per_s"],
         "qgemm": qg,
     }
+    line.update(extra)
     print(json.dumps(line))
+
+
+def bench_batch(q, torch, workloads, dev, args):
+    """512 uneven problems (m, n ~ U{64..512}, k ~ U{8..32}, c = r = 2k):
+    the batched solve replayed from a captured graph, against plain FP64
+    solves of the same problems one at a time."""
+    cfg = workloads.WORKLOADS["batch_512"]
+    probs = workloads.batch_problems(cfg["count"], cfg["seed"], cfg["mn_range"], cfg["k_range"], cfg["noise"])
+    dims = [(P["m"], P["n"], 2 * P["k"], 2 * P["k"]) for P in probs]
+    A32 = q.pack_batch([P["A"] for P in probs], dtype=torch.float32, device=dev)
+    out = {"workload": "512 pure quaternion problems, m,n ~ U{64..512}, rank k ~ U{8..32} + N(0,1e-3^2), "
+                       "length sampling c=r=2k, U=C^+AR^+", "problems": len(dims)}
+    seed = cfg["seed"]
+    ref_res = None
+    for name, comp, refine in (("f32", q.F32, 0), ("f32_refine1", q.F32, 1), ("bf16_refine1", q.BF16, 1)):
+        bs = q.BatchSolver(dims, compute=comp, refine_steps=refine, a_dtype=torch.float32)
+        bs(A32, seed=seed)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            bs(A32, seed=seed)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            bs(A32, seed=seed)
+        for _ in range(args.warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.replay()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        q.sync_status()
+        res = bs.residual.cpu().numpy()
+        out[name] = dict(ms_per_batch=dt * 1e3, solves_per_s=len(dims) / dt, residual_sum=float(res.sum()))
+        if ref_res is None:
+            ref_res = res
+        log(f"batch {name}: {dt * 1e3:.3f} ms per {len(dims)} solves")
+        del bs, g
+    # plain FP64: one qcur_solve per problem, no graph
+    A64 = A32.to(torch.float64)
+    t_total = 0.0
+    for b, (m, n, c, r) in enumerate(dims):
+        S = q.Solver(m, n, c, r, core=q.CORE_CAR, compute=q.F64)
+        Ab = A64[b, :, :m, :n].contiguous()
+        S(Ab, seed=seed + b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S(Ab, seed=seed + b)
+        torch.cuda.synchronize()
+        t_total += time.perf_counter() - t0
+    q.sync_status()
+    out["plain_f64_single"] = dict(ms_per_batch=t_total * 1e3, solves_per_s=len(dims) / t_total)
+    out["speedup_f32_vs_plain_f64"] = out["f32"]["solves_per_s"] / out["plain_f64_single"]["solves_per_s"]
+    log(f"batch plain f64 one at a time: {t_total * 1e3:.1f} ms")
+    return out
+
+
+def bench_dense(q, torch, workloads, dev, args):
+    """4096 x 4096, rank 100 N(0,1) factors + N(0, 1e-3^2), c = r = 400:
+    FP32 products (without and with one refinement step) against plain FP64."""
+    cfg = workloads.WORKLOADS["dense_4096"]
+    L, Rt, E = workloads.lowrank_gaussian_factors(cfg["m"], cfg["n"], cfg["k"], cfg["seed"], cfg["noise"])
+    Lt = torch.tensor(L, device=dev)
+    Rtt = torch.tensor(Rt, device=dev)
+    # A = L Rt (quaternion product, formed with torch matmuls) + E
+    sgn = {(0, 0): 1, (1, 1): -1, (2, 2): -1, (3, 3): -1, (1, 0): 1, (0, 1): 1, (3, 2): -1, (2, 3): 1,
+           (2, 0): 1, (3, 1): 1, (0, 2): 1, (1, 3): -1, (3, 0): 1, (2, 1): -1, (1, 2): 1, (0, 3): 1}
+    prod = {(0, 0): 0, (1, 1): 0, (2, 2): 0, (3, 3): 0, (1, 0): 1, (0, 1): 1, (3, 2): 1, (2, 3): 1,
+            (2, 0): 2, (3, 1): 2, (0, 2): 2, (1, 3): 2, (3, 0): 3, (2, 1): 3, (1, 2): 3, (0, 3): 3}
+    A64 = torch.tensor(E, device=dev)
+    for (a, b), d in prod.items():
+        A64[d] += sgn[(a, b)] * (Lt[a] @ Rtt[b])
+    del Lt, Rtt
+    A32 = A64.to(torch.float32)
+    m, n, c, r, seed = cfg["m"], cfg["n"], cfg["c"], cfg["r"], cfg["seed"]
+    out = {"workload": "4096x4096 quaternion, rank 100 N(0,1) factors + N(0,1e-3^2), length sampling c=r=400, "
+                       "U=C^+AR^+"}
+    Bs = {}
+    for name, A, comp, refine in (("plain_f64", A64, q.F64, 0), ("f32", A32, q.F32, 0), ("f32_refine1", A32, q.F32, 1)):
+        S = q.Solver(m, n, c, r, core=q.CORE_CAR, compute=comp)
+        S(A, seed=seed, refine_steps=refine)
+        torch.cuda.synchronize()
+        reps = max(2, args.steps // 2)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            S(A, seed=seed, refine_steps=refine)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        q.sync_status()
+        out[name] = dict(ms_per_step=dt * 1e3, solves_per_s=1.0 / dt,
+                         rel_residual=float(S.residual.cpu()[0]) / float(torch.linalg.vector_norm(A64)))
+        sol = q.solve(A, c, r, core=q.CORE_CAR, compute=comp, seed=seed, refine_steps=refine, want_B=True)
+        Bs[name] = sol["B"].to(torch.float64)
+        log(f"dense {name}: {dt * 1e3:.2f} ms/solve")
+        del S, sol
+    for name in ("f32", "f32_refine1"):
+        out[name]["cur_rel_err_vs_f64"] = float(torch.linalg.vector_norm(Bs[name] - Bs["plain_f64"]) /
+                                                torch.linalg.vector_norm(Bs["plain_f64"]))
+        out[f"speedup_{name}_vs_plain_f64"] = out[name]["solves_per_s"] / out["plain_f64"]["solves_per_s"]
+    q.sync_status()
+    return out
 
 
 def cpu_baseline(A, c, r, seed, seconds):

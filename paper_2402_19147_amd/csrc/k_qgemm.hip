@@ -345,14 +345,31 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
   }
 }
 
-// grid: x = column tiles, y = row tiles, z = batch * splits
+// XCD-aware order of the tiles.  Workgroups are handed to the eight XCDs
+// round-robin by linear id, and each XCD has its own L2; the logical tile
+// index gives every XCD one contiguous range of tiles (column tiles fastest),
+// so the tiles that share a row block of A, and the same B, run behind the
+// same L2 instead of being spread over all eight.
+constexpr int NXCD = 8;
+__device__ inline int64_t xcd_tile(int64_t id, int64_t total) {
+  const int64_t x = id % NXCD, s = id / NXCD;
+  const int64_t per = total / NXCD, rem = total % NXCD;
+  return x * per + (x < rem ? x : rem) + s;
+}
+
+// grid: x = column tiles, y = row tiles, z = batch * splits (tile order
+// remapped per XCD as above)
 template <int DT, int EPI, int BM, int BN>
 __global__ __launch_bounds__(NT) void k_qgemm(GemmArgs g) {
   __shared__ Smem<DT, BM, BN> sm;
-  const int b = blockIdx.z / g.splits, split = blockIdx.z % g.splits;
-  const int64_t tiles = (int64_t)gridDim.x * gridDim.y;
-  gemm_tile<DT, EPI, BM, BN>(g, b, blockIdx.y, blockIdx.x, split,
-                             (int64_t)b * tiles + (int64_t)blockIdx.y * gridDim.x + blockIdx.x, sm);
+  const int64_t gx = gridDim.x, gy = gridDim.y;
+  const int64_t total = gx * gy * gridDim.z;
+  const int64_t id = blockIdx.x + gx * (blockIdx.y + gy * (int64_t)blockIdx.z);
+  const int64_t L = xcd_tile(id, total);
+  const int64_t tx = L % gx, ty = (L / gx) % gy, tz = L / (gx * gy);
+  const int b = (int)(tz / g.splits), split = (int)(tz % g.splits);
+  const int64_t tiles = gx * gy;
+  gemm_tile<DT, EPI, BM, BN>(g, b, ty, tx, split, (int64_t)b * tiles + ty * gx + tx, sm);
 }
 
 // Split-K reduction: D = alpha * sum_z P[z] + beta * D, z in fixed order.
