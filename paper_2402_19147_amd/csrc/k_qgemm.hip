@@ -112,6 +112,9 @@ struct GemmArgs {
   int edt;
   int64_t eld, eps;
   double e_scale;
+  // BF16: operands are 16-byte aligned with row, plane and batch strides that
+  // are multiples of 8, so eight consecutive elements load as one vector
+  int vec;
 };
 
 enum { EPI_STORE = 0, EPI_PARTIAL = 1, EPI_RESID = 2 };
@@ -119,7 +122,7 @@ enum { EPI_STORE = 0, EPI_PARTIAL = 1, EPI_RESID = 2 };
 // LDS layouts.  f32/f64: k-major rows [k][i] (A) and [k][j] (B) so that the
 // 16 lanes of an MFMA operand read 16 consecutive elements.  bf16: [i][k]
 // and [j][k] so that each lane reads its 8 consecutive k values at once.
-template <int DT, int BM, int BN> struct Smem {
+template <int DT, int BM, int BN> struct alignas(16) Smem {
   typedef typename MT<DT>::In In;
   static constexpr int BK = MT<DT>::BK, PAD = MT<DT>::PAD;
   static constexpr bool KMAJ = (DT != QCUR_BF16);
@@ -227,12 +230,126 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
 #pragma unroll
       for (int y = 0; y < YB; ++y) acc[p][x][y] = (AccV){0, 0, 0, 0};
 
-  if (kt0 < kt1) load_tiles(kt0);
+  // BF16 with aligned operands: each thread moves whole 8-element vectors
+  // along the contiguous dimension of each operand (one 16-byte load per
+  // plane); operands stored along the other dimension are transposed into
+  // LDS with 2-byte stores.  Vectors that cross a matrix edge fall back to
+  // element loads.
+  constexpr int VA = (DT == QCUR_BF16) ? (BM * BK / 8 + NT - 1) / NT : 1;
+  constexpr int VB = (DT == QCUR_BF16) ? (BN * BK / 8 + NT - 1) / NT : 1;
+  u32x4 va[4][VA], vb[4][VB];
+  // vector v of A: contiguous in k (op N: row i, k = kv..kv+7) or in i (op H)
+  auto vec_load = [&](int64_t kt) {
+    if constexpr (DT == QCUR_BF16) {
+    const int64_t k0 = kt * BK;
+#pragma unroll
+    for (int r = 0; r < VA; ++r) {
+      const int v = tid + NT * r;
+      if (v >= BM * BK / 8) break;
+      int i, k;
+      if (g.opA == QCUR_OP_N) { i = v / (BK / 8); k = (v % (BK / 8)) * 8; } else { k = v / (BM / 8); i = (v % (BM / 8)) * 8; }
+      const int64_t gi = bm + i, gk = k0 + k;
+      const bool full = (g.opA == QCUR_OP_N) ? (gi < M && gk + 7 < K) : (gk < K && gi + 7 < M);
+      const int64_t off = (g.opA == QCUR_OP_N) ? gi * g.lda + gk : gk * g.lda + gi;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        u32x4 w;
+        if (full) {
+          w = *(const u32x4*)(Ag + off + q * g.psa);
+        } else {
+          uint16_t e[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const bool ok = (g.opA == QCUR_OP_N) ? (gi < M && gk + t < K) : (gk < K && gi + t < M);
+            e[t] = ok ? Ag[off + t + q * g.psa] : (uint16_t)0;
+          }
+          w = __builtin_bit_cast(u32x4, e);
+        }
+        if (g.opA == QCUR_OP_H && q > 0) w ^= (u32x4){0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+        va[q][r] = w;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < VB; ++r) {
+      const int v = tid + NT * r;
+      if (v >= BN * BK / 8) break;
+      int k, j;
+      if (g.opB == QCUR_OP_H) { j = v / (BK / 8); k = (v % (BK / 8)) * 8; } else { k = v / (BN / 8); j = (v % (BN / 8)) * 8; }
+      const int64_t gk = k0 + k, gj = bn + j;
+      const bool full = (g.opB == QCUR_OP_H) ? (gj < N && gk + 7 < K) : (gk < K && gj + 7 < N);
+      const int64_t off = (g.opB == QCUR_OP_N) ? gk * g.ldb + gj : gj * g.ldb + gk;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        u32x4 w;
+        if (full) {
+          w = *(const u32x4*)(Bg + off + q * g.psb);
+        } else {
+          uint16_t e[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const bool ok = (g.opB == QCUR_OP_H) ? (gj < N && gk + t < K) : (gk < K && gj + t < N);
+            e[t] = ok ? Bg[off + t + q * g.psb] : (uint16_t)0;
+          }
+          w = __builtin_bit_cast(u32x4, e);
+        }
+        if (g.opB == QCUR_OP_H && q > 0) w ^= (u32x4){0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+        vb[q][r] = w;
+      }
+    }
+    }
+  };
+  auto vec_store = [&]() {
+    if constexpr (DT == QCUR_BF16) {
+#pragma unroll
+      for (int r = 0; r < VA; ++r) {
+        const int v = tid + NT * r;
+        if (v >= BM * BK / 8) break;
+        int i, k;
+        if (g.opA == QCUR_OP_N) { i = v / (BK / 8); k = (v % (BK / 8)) * 8; } else { k = v / (BM / 8); i = (v % (BM / 8)) * 8; }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (g.opA == QCUR_OP_N) {
+            *(u32x4*)&sm.a[q][i][k] = va[q][r];
+          } else {
+            uint16_t e[8];
+            *(u32x4*)e = va[q][r];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) sm.a[q][i + t][k] = e[t];
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < VB; ++r) {
+        const int v = tid + NT * r;
+        if (v >= BN * BK / 8) break;
+        int k, j;
+        if (g.opB == QCUR_OP_H) { j = v / (BK / 8); k = (v % (BK / 8)) * 8; } else { k = v / (BN / 8); j = (v % (BN / 8)) * 8; }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (g.opB == QCUR_OP_H) {
+            *(u32x4*)&sm.b[q][j][k] = vb[q][r];
+          } else {
+            uint16_t e[8];
+            *(u32x4*)e = vb[q][r];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) sm.b[q][j + t][k] = e[t];
+          }
+        }
+      }
+    }
+  };
+  const bool use_vec = (DT == QCUR_BF16) && g.vec;
+
+  if (kt0 < kt1) {
+    if (use_vec) vec_load(kt0); else load_tiles(kt0);
+  }
   for (int64_t kt = kt0; kt < kt1; ++kt) {
     __syncthreads();
-    store_tiles();
+    if (use_vec) vec_store(); else store_tiles();
     __syncthreads();
-    if (kt + 1 < kt1) load_tiles(kt + 1);
+    if (kt + 1 < kt1) {
+      if (use_vec) vec_load(kt + 1); else load_tiles(kt + 1);
+    }
 #pragma unroll
     for (int kk = 0; kk < BK / T::KM; ++kk) {
       Frag a[4][XB], na[4][XB], b[4][YB];
@@ -461,6 +578,10 @@ static hipError_t gemm_dt(const Ctx& c, GemmArgs g, void* ws, size_t ws_bytes) {
   return gemm_dt_tile<DT, 32>(c, g, ws, ws_bytes);
 }
 
+static bool vec_ok(const QView& X, int64_t sbatch) {
+  return X.dt == QCUR_BF16 && ((uintptr_t)X.p % 16) == 0 && X.ld % 8 == 0 && X.ps % 8 == 0 && sbatch % 8 == 0;
+}
+
 hipError_t launch_gemm_batched(const Ctx& c, int opA, int opB, double alpha, QView A, QView B, double beta,
                                QView D, int compute, void* ws, size_t ws_bytes, const BatchSpec& bs) {
   GemmArgs g = {};
@@ -477,6 +598,7 @@ hipError_t launch_gemm_batched(const Ctx& c, int opA, int opB, double alpha, QVi
   g.M = D.rows; g.N = D.cols;
   g.K = (opA == QCUR_OP_N) ? A.cols : A.rows;
   g.opA = opA; g.opB = opB; g.alpha = alpha; g.beta = beta;
+  g.vec = compute == QCUR_BF16 && vec_ok(A, bs.sA) && vec_ok(B, bs.sB);
   if (g.M == 0 || g.N == 0) return hipSuccess;
   if (g.K == 0) {  // D = beta * D
     return launch_axpby(c, 0.0, D, beta, D);
@@ -508,6 +630,7 @@ hipError_t launch_residual_gemm(const Ctx& c, QView A, QView B1, QView R, const 
   g.partials = partials;
   g.batch = 1;
   g.splits = 1;
+  g.vec = compute == QCUR_BF16 && vec_ok(B1, 0) && vec_ok(R, 0);
   if (E) { g.E = E->p; g.edt = E->dt; g.eld = E->ld; g.eps = E->ps; g.e_scale = e_scale; }
   if (g.M == 0 || g.N == 0) return hipSuccess;
   dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64), 1);
@@ -549,6 +672,8 @@ hipError_t launch_residual_gemm_batched(const Ctx& c, int count, Slots A, Slots 
   g.partials = partials;
   g.batch = count;
   g.splits = 1;
+  g.vec = compute == QCUR_BF16 && vec_ok(QView{B1.p, 1, 1, B1.ld, B1.ps, B1.dt}, B1.slab) &&
+          vec_ok(QView{R.p, 1, 1, R.ld, R.ps, R.dt}, R.slab);
   if (E) { g.E = E->p; g.edt = E->dt; g.eld = E->ld; g.eps = E->ps; g.sE = E->slab; g.e_scale = e_scale; }
   const dim3 grid((unsigned)((nx + 63) / 64), (unsigned)((mx + 63) / 64), (unsigned)count);
   switch (compute) {

@@ -58,7 +58,8 @@ def _status_clean():
 
 
 # ---------------------------------------------------------------- qgemm
-GEMM_SHAPES = [(1, 1, 1), (16, 4, 16), (70, 37, 45), (130, 50, 70), (64, 1024, 64), (200, 96, 33)]
+GEMM_SHAPES = [(1, 1, 1), (16, 4, 16), (70, 37, 45), (130, 50, 70), (64, 1024, 64), (200, 96, 33), (72, 40, 88),
+               (136, 200, 104)]
 
 
 @pytest.mark.parametrize("M,K,Nn", GEMM_SHAPES)
