@@ -514,27 +514,29 @@ __global__ void k_splitk_reduce(const Acc* __restrict__ Pall, int splits, int64_
   }
 }
 
-// Tile edge: 64 x 64 quaternion tiles, or 32 x 32 when 64-tiles would leave
-// most of the 256 compute units idle.
-static int tile_of(int64_t M, int64_t N) {
+// Launch plan: 64 x 64 quaternion tiles, or 32 x 32 when 64-tiles would
+// leave most of the 256 compute units idle (measured faster on the thin
+// products of the solve than 64-tiles split further along K); then K is
+// split until the grid covers the chip twice over, keeping at least two
+// K-steps per split.
+struct Plan {
+  int tile, splits;
+};
+static Plan plan_of(int64_t M, int64_t N, int64_t K, int bk, int batch) {
   const int64_t t64 = ((M + 63) / 64) * ((N + 63) / 64);
-  return t64 >= 192 ? 64 : 32;
-}
-
-static int choose_splits(int64_t M, int64_t N, int64_t K, int bk, int tile, int batch) {
+  const int tile = t64 >= 192 ? 64 : 32;
   const int64_t tiles = ((M + tile - 1) / tile) * ((N + tile - 1) / tile) * std::max(batch, 1);
   const int64_t kt = (K + bk - 1) / bk;
-  // split K until the grid covers the chip twice over, keeping >= 2 K-slices per split
   int s = 1;
   while (s < 32 && tiles * s < 512 && kt / (s * 2) >= 2) s *= 2;
-  return s;
+  return Plan{tile, s};
 }
 
 static int bk_of(int compute) { return compute == QCUR_BF16 ? 32 : 16; }
 static size_t acc_size(int compute) { return compute == QCUR_F64 ? 8 : 4; }
 
 size_t gemm_workspace(int64_t M, int64_t N, int64_t K, int compute, int batch) {
-  const int s = choose_splits(M, N, K, bk_of(compute), tile_of(M, N), batch);
+  const int s = plan_of(M, N, K, bk_of(compute), batch).splits;
   if (s <= 1) return 0;
   return (size_t)batch * s * 4 * (size_t)M * (size_t)N * acc_size(compute);
 }
@@ -543,7 +545,7 @@ template <int DT, int TILE>
 static hipError_t gemm_dt_tile(const Ctx& c, GemmArgs g, void* ws, size_t ws_bytes) {
   constexpr int BK = MT<DT>::BK;
   const int64_t kt = (g.K + BK - 1) / BK;
-  int splits = choose_splits(g.M, g.N, g.K, BK, TILE, g.batch);
+  int splits = plan_of(g.M, g.N, g.K, BK, g.batch).splits;
   const size_t need = (size_t)g.batch * splits * 4 * (size_t)g.M * (size_t)g.N * acc_size(DT);
   if (splits > 1 && (ws == nullptr || ws_bytes < need)) splits = 1;
   dim3 grid((unsigned)((g.N + TILE - 1) / TILE), (unsigned)((g.M + TILE - 1) / TILE), 1);
@@ -574,7 +576,7 @@ static hipError_t gemm_dt_tile(const Ctx& c, GemmArgs g, void* ws, size_t ws_byt
 
 template <int DT>
 static hipError_t gemm_dt(const Ctx& c, GemmArgs g, void* ws, size_t ws_bytes) {
-  if (tile_of(g.M, g.N) == 64) return gemm_dt_tile<DT, 64>(c, g, ws, ws_bytes);
+  if (plan_of(g.M, g.N, g.K, MT<DT>::BK, g.batch).tile == 64) return gemm_dt_tile<DT, 64>(c, g, ws, ws_bytes);
   return gemm_dt_tile<DT, 32>(c, g, ws, ws_bytes);
 }
 
