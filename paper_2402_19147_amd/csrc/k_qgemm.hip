@@ -39,7 +39,7 @@ template <> struct MT<QCUR_F64> {
   typedef double Acc;
   typedef f64x4 AccV;
   typedef double Frag;
-  static constexpr int BK = 16, KM = 4, PAD = 4;
+  static constexpr int BK = 16, KM = 4, PAD = 1;
   // output element r of lane l sits at row (l/16) + 4r (rows interleaved)
   static __device__ inline int out_row(int lane, int r) { return (lane >> 4) + 4 * r; }
   static __device__ inline AccV mfma(Frag a, Frag b, AccV c) {
@@ -52,7 +52,7 @@ template <> struct MT<QCUR_F32> {
   typedef float Acc;
   typedef f32x4 AccV;
   typedef float Frag;
-  static constexpr int BK = 16, KM = 4, PAD = 4;
+  static constexpr int BK = 16, KM = 4, PAD = 1;
   // output element r of lane l sits at row 4(l/16) + r
   static __device__ inline int out_row(int lane, int r) { return (lane >> 4) * 4 + r; }
   static __device__ inline AccV mfma(Frag a, Frag b, AccV c) {
@@ -119,13 +119,16 @@ struct GemmArgs {
 
 enum { EPI_STORE = 0, EPI_PARTIAL = 1, EPI_RESID = 2 };
 
-// LDS layouts.  f32/f64: k-major rows [k][i] (A) and [k][j] (B) so that the
-// 16 lanes of an MFMA operand read 16 consecutive elements.  bf16: [i][k]
-// and [j][k] so that each lane reads its 8 consecutive k values at once.
+// LDS layouts: [i][k] (A) and [j][k] (B), rows of BK + PAD elements.
+// f32/f64 (PAD 1, an odd row length in elements): the 16 lanes of an MFMA
+// operand read 16 different rows at the same k and the staging stores of
+// consecutive threads hit consecutive or odd-strided addresses, so neither
+// conflicts on the LDS banks.  bf16: each lane reads its 8 consecutive k
+// values at once (PAD 8 keeps rows 16-byte aligned).
 template <int DT, int BM, int BN> struct alignas(16) Smem {
   typedef typename MT<DT>::In In;
   static constexpr int BK = MT<DT>::BK, PAD = MT<DT>::PAD;
-  static constexpr bool KMAJ = (DT != QCUR_BF16);
+  static constexpr bool KMAJ = false;
   static constexpr int AR = KMAJ ? BK : BM, AC = KMAJ ? BM + PAD : BK + PAD;
   static constexpr int BR = KMAJ ? BK : BN, BC = KMAJ ? BN + PAD : BK + PAD;
   In a[4][AR][AC];
@@ -358,8 +361,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
         const int ii = wm + x * 16 + (lane & 15);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          if constexpr (KMAJ) a[q][x] = sm.a[q][kk * 4 + (lane >> 4)][ii];
-          else a[q][x] = *(const Frag*)&sm.a[q][ii][(lane >> 4) * 8];
+          if constexpr (DT == QCUR_BF16) a[q][x] = *(const Frag*)&sm.a[q][ii][(lane >> 4) * 8];
+          else a[q][x] = sm.a[q][ii][kk * 4 + (lane >> 4)];
         }
 #pragma unroll
         for (int q = 1; q < 4; ++q) na[q][x] = T::neg(a[q][x]);
@@ -369,8 +372,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
         const int jj = wn + y * 16 + (lane & 15);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          if constexpr (KMAJ) b[q][y] = sm.b[q][kk * 4 + (lane >> 4)][jj];
-          else b[q][y] = *(const Frag*)&sm.b[q][jj][(lane >> 4) * 8];
+          if constexpr (DT == QCUR_BF16) b[q][y] = *(const Frag*)&sm.b[q][jj][(lane >> 4) * 8];
+          else b[q][y] = sm.b[q][jj][kk * 4 + (lane >> 4)];
         }
       }
 #pragma unroll
