@@ -197,8 +197,9 @@ def main():
 
 def bench_batch(q, torch, workloads, dev, args):
     """512 uneven problems (m, n ~ U{64..512}, k ~ U{8..32}, c = r = 2k):
-    the batched solve replayed from a captured graph, against plain FP64
-    solves of the same problems one at a time."""
+    the batched solve (GEMM launch plans chosen by the autotuner on the first
+    call, and with fixed plans for comparison) replayed from a captured
+    graph, against plain FP64 solves of the same problems one at a time."""
     cfg = workloads.WORKLOADS["batch_512"]
     probs = workloads.batch_problems(cfg["count"], cfg["seed"], cfg["mn_range"], cfg["k_range"], cfg["noise"])
     dims = [(P["m"], P["n"], 2 * P["k"], 2 * P["k"]) for P in probs]
@@ -207,9 +208,10 @@ def bench_batch(q, torch, workloads, dev, args):
                        "length sampling c=r=2k, U=C^+AR^+", "problems": len(dims)}
     seed = cfg["seed"]
     ref_res = None
-    for name, comp, refine in (("f32", q.F32, 0), ("f32_refine1", q.F32, 1), ("bf16_refine1", q.BF16, 1)):
-        bs = q.BatchSolver(dims, compute=comp, refine_steps=refine, a_dtype=torch.float32)
-        bs(A32, seed=seed)
+    for name, comp, refine, tune in (("f32", q.F32, 0, True), ("f32_fixed_plans", q.F32, 0, False),
+                                     ("f32_refine1", q.F32, 1, True), ("bf16_refine1", q.BF16, 1, True)):
+        bs = q.BatchSolver(dims, compute=comp, refine_steps=refine, a_dtype=torch.float32, autotune=tune)
+        bs(A32, seed=seed)  # with autotune: times the candidate plans of every GEMM stage
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
@@ -230,6 +232,8 @@ def bench_batch(q, torch, workloads, dev, args):
         q.sync_status()
         res = bs.residual.cpu().numpy()
         out[name] = dict(ms_per_batch=dt * 1e3, solves_per_s=len(dims) / dt, residual_sum=float(res.sum()))
+        if tune:
+            out[name]["plans"] = {k: list(v) for k, v in bs.plans().items()}
         if ref_res is None:
             ref_res = res
         log(f"batch {name}: {dt * 1e3:.3f} ms per {len(dims)} solves")

@@ -260,17 +260,32 @@ size_t qcur_solve_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int core
  * sequence.  Errors found in kernels go to the status word.
  *
  * Before the first call, qcur_batch_prepare(handle, count, dims, A's dtype,
- * sampling, compute, refine_steps, ws, ws_bytes) writes the batch's size
- * tables into the workspace (synchronously; not under stream capture) and
- * records the workspace in the handle; qcur_solve_batched refuses a
- * workspace that was not prepared for the same sizes and options.  Calls
- * that share one workspace must not overlap.
+ * sampling, compute, refine_steps, autotune, ws, ws_bytes) writes the
+ * batch's size tables into the workspace (synchronously; not under stream
+ * capture) and records the workspace in the handle; qcur_solve_batched
+ * refuses a workspace that was not prepared for the same sizes and options.
+ * Calls that share one workspace must not overlap.
+ * autotune = 1: the first qcur_solve_batched call on this workspace that is
+ * not being captured times every candidate launch plan (tile edge 32 or 64,
+ * 1, 2 or 4 slices of K) of each of its quaternion GEMM stages on the real
+ * operands (and 32- or 64-tiles for the residual) and keeps the fastest;
+ * later calls, captured ones included, reuse those plans.  The measuring
+ * call synchronises with the host.  Plans change only the summation order,
+ * so results of differently tuned runs differ by rounding.  autotune = 0:
+ * fixed plans from the problem shapes (bitwise reproducible).
  * ws: qcur_batch_workspace(count, dims, A's dtype, sampling, compute,
- * refine_steps) bytes (0 for invalid arguments). */
+ * refine_steps, autotune) bytes (0 for invalid arguments). */
 size_t qcur_batch_workspace(int32_t count, const int32_t* dims, int a_dtype, int sampling, int compute,
-                            int refine_steps);
+                            int refine_steps, int autotune);
 qcur_status qcur_batch_prepare(qcur_handle handle, int32_t count, const int32_t* dims, int a_dtype,
-                               int sampling, int compute, int refine_steps, void* ws, size_t ws_bytes);
+                               int sampling, int compute, int refine_steps, int autotune, void* ws,
+                               size_t ws_bytes);
+/* Launch plans kept by the autotuner for a prepared workspace: tiles[i] and
+ * splits[i] (host int[n]) for stage i of the batched solve (factor Grams of
+ * C and R, first-pass factors of C and R, second-pass Gram, P2 P1, Q1 P2^H,
+ * A Q_R, Q_C^H T, Q_C M, M P_R, P_C^H W, residual).  Returns the number of
+ * stages (13) once the plans have been measured, else 0. */
+int qcur_batch_plans(qcur_handle handle, const void* ws, int* tiles, int* splits, int n);
 qcur_status qcur_solve_batched(qcur_handle handle, int32_t count, const int32_t* dims,
                                const qcur_qmat* A, int64_t a_bstride, int sampling, int compute,
                                uint64_t seed, int with_replacement, int refine_steps, double rtol,

@@ -14,11 +14,28 @@
 
 using namespace qcur;
 
-// A prepared batch layout: the workspace it was uploaded into and a key of
-// the sizes and options it was prepared for.
+// Launch plans of the GEMM stages of a batched solve, chosen by timing the
+// candidates on the first eager call (the autotuner) or left automatic.
+enum BatchStage {
+  BS_GRAM_C, BS_GRAM_R, BS_Q1_C, BS_Q1_R, BS_G2, BS_P, BS_Q, BS_T, BS_M, BS_B1, BS_W1, BS_U, BS_RESID, BS_COUNT
+};
+struct StagePlan {
+  int tile = 0, splits = 0;  // 0: automatic
+};
+struct BatchTuning {
+  bool measure = false;  // time the candidates during this call
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  StagePlan plan[BS_COUNT];
+};
+
+// A prepared batch layout: the workspace it was uploaded into, a key of the
+// sizes and options it was prepared for, and its stage plans.
 struct BatchRecord {
   const void* ws = nullptr;
   uint64_t key = 0;
+  int autotune = 0;
+  bool tuned = false;
+  BatchTuning tun;
 };
 
 struct qcur_ctx {
@@ -900,7 +917,10 @@ struct BatchShape {
   const int32_t* dims;  // host [count][4]: m, n, c, r
   int64_t mx, nx, cx, rx;
   int a_dt, sampling, compute, refine;
+  int autotune;
 };
+
+constexpr int TUNE_MAX_SPLITS = 4;
 
 struct BatchWs {
   int *dm, *dn, *dc, *dr, *zp, *zq;  // header (uploaded by qcur_batch_prepare)
@@ -911,7 +931,7 @@ struct BatchWs {
   double *Y, *V;
   Slots Qcx, Qrx, T, Tx, M, Mx, B1, B1x, E, Ex, M64, W1, U64;
   double* part;
-  int64_t tiles;
+  int64_t tiles, tiles32;
   int64_t* ranks;
   void* gws;
   size_t gws_bytes;
@@ -989,7 +1009,8 @@ BatchWs batch_carve(Bump& b, const BatchShape& s) {
   w.W1 = slots_of(b, n, s.cx, s.rx, QCUR_F64);
   w.U64 = adt != QCUR_F64 ? slots_of(b, n, s.cx, s.rx, QCUR_F64) : Slots{};
   w.tiles = (int64_t)((s.mx + 63) / 64) * ((s.nx + 63) / 64);
-  w.part = (double*)b.take((size_t)n * w.tiles * 8);
+  w.tiles32 = (int64_t)((s.mx + 31) / 32) * ((s.nx + 31) / 32);
+  w.part = (double*)b.take((size_t)n * (s.autotune ? w.tiles32 : w.tiles) * 8);
   w.ranks = (int64_t*)b.take((size_t)n * 2 * 8);
   const int64_t px = w.px, qx = w.qx;
   const int cp = s.compute;
@@ -998,6 +1019,14 @@ BatchWs batch_carve(Bump& b, const BatchShape& s) {
                           gemm_workspace(qx, qx, px, QCUR_F64, n2), gemm_workspace(s.mx, s.rx, s.nx, cp, n),
                           gemm_workspace(s.cx, s.rx, s.mx, cp, n), gemm_workspace(s.mx, s.rx, s.cx, cp, n),
                           gemm_workspace(s.cx, s.rx, qx, QCUR_F64, n)});
+  if (s.autotune) {
+    // room for every candidate plan (up to TUNE_MAX_SPLITS slices of K)
+    const int T = TUNE_MAX_SPLITS;
+    w.gws_bytes = std::max({w.gws_bytes, gemm_workspace_splits(qx, qx, QCUR_F64, n2, T),
+                            gemm_workspace_splits(px, qx, QCUR_F64, n2, T),
+                            gemm_workspace_splits(s.mx, s.rx, cp, n, T), gemm_workspace_splits(s.cx, s.rx, cp, n, T),
+                            gemm_workspace_splits(s.cx, s.rx, QCUR_F64, n, T)});
+  }
   w.gws = b.take(w.gws_bytes);
   return w;
 }
@@ -1016,21 +1045,24 @@ uint64_t batch_key(const BatchShape& s) {
   mix((uint64_t)s.sampling);
   mix((uint64_t)s.compute);
   mix((uint64_t)(s.refine > 0));
+  mix((uint64_t)s.autotune);
   return h;
 }
 
 constexpr int64_t BATCH_MAX_SIDE = 4096;
 
 qcur_status check_batch_shape(int count, const int32_t* dims, int a_dt, int sampling, int compute, int refine,
-                              int with_replacement, BatchShape* out) {
+                              int with_replacement, int autotune, BatchShape* out) {
   if (count < 1 || count > 16384) return fail(QCUR_ERR_ARG, "count must be in [1, 16384]");
   if (!dims) return fail(QCUR_ERR_ARG, "dims is NULL");
   if (!valid_dtype(a_dt)) return fail(QCUR_ERR_DTYPE, "unknown dtype of A");
   if (!valid_dtype(compute)) return fail(QCUR_ERR_DTYPE, "unknown compute dtype");
   if (sampling != QCUR_LENGTH && sampling != QCUR_UNIFORM) return fail(QCUR_ERR_ARG, "unknown sampling %d", sampling);
   if (refine < 0) return fail(QCUR_ERR_ARG, "refine_steps must be >= 0");
+  if (autotune != 0 && autotune != 1) return fail(QCUR_ERR_ARG, "autotune must be 0 or 1");
   BatchShape s{};
   s.count = count;
+  s.autotune = autotune;
   s.dims = dims;
   for (int b = 0; b < count; ++b) {
     const int64_t m = dims[4 * b], n = dims[4 * b + 1], c = dims[4 * b + 2], r = dims[4 * b + 3];
@@ -1100,11 +1132,71 @@ BatchSpec bspec(int count, const Slots& A, const Slots& B, const Slots& D, const
 // so the products that touch A run on the orthonormal Q's in the product
 // dtype (rounding errors stay near u ||A||, whatever the conditioning of C
 // and R), and only the small triangular factors P meet M, in FP64.
-qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, BatchWs& w) {
+qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, BatchWs& w, BatchTuning* tu) {
   const int n = s.count, n2 = 2 * n;
   const int idt = in_dt(s.compute), adt = acc_dt(s.compute);
   const int64_t mx = s.mx, nx = s.nx, cx = s.cx, rx = s.rx, px = w.px, qx = w.qx;
   const bool cast_A = s.a_dt != idt;
+  Slots resid_R{};
+  int64_t resid_tiles = w.tiles;
+
+  // One GEMM stage: with the autotuner measuring, every candidate plan (tile
+  // 32 or 64, 1..TUNE_MAX_SPLITS slices of K) is timed on the real operands
+  // and the fastest kept; stages that accumulate into D (beta != 0) reuse the
+  // plan of their beta = 0 twin.  The last launch uses the kept plan.
+  auto timed = [&](auto&& launch, float* ms) -> qcur_status {
+    HIPCHK(launch());
+    HIPCHK(hipEventRecord(tu->e0, c.stream));
+    HIPCHK(launch());
+    HIPCHK(launch());
+    HIPCHK(hipEventRecord(tu->e1, c.stream));
+    HIPCHK(hipEventSynchronize(tu->e1));
+    HIPCHK(hipEventElapsedTime(ms, tu->e0, tu->e1));
+    return QCUR_OK;
+  };
+  auto stage = [&](int id, int opA, int opB, double alpha, QView A, QView B, double beta, QView D, int compute,
+                   BatchSpec bs) -> qcur_status {
+    if (tu && tu->measure && beta == 0.0 && tu->plan[id].tile == 0) {
+      float best = INFINITY;
+      StagePlan bp{};
+      for (int tile : {32, 64})
+        for (int sp = 1; sp <= TUNE_MAX_SPLITS; sp *= 2) {
+          BatchSpec t = bs;
+          t.tile = tile;
+          t.splits = sp;
+          float ms = 0.f;
+          CHK(timed([&] { return launch_gemm_batched(c, opA, opB, alpha, A, B, beta, D, compute, w.gws, w.gws_bytes, t); },
+                    &ms));
+          if (ms < best) {
+            best = ms;
+            bp = StagePlan{tile, sp};
+          }
+        }
+      tu->plan[id] = bp;
+    }
+    if (tu) {
+      bs.tile = tu->plan[id].tile;
+      bs.splits = tu->plan[id].splits;
+    }
+    HIPCHK(launch_gemm_batched(c, opA, opB, alpha, A, B, beta, D, compute, w.gws, w.gws_bytes, bs));
+    return QCUR_OK;
+  };
+  auto resid = [&](const Slots* E) -> qcur_status {
+    auto run = [&](int tile) {
+      return launch_residual_gemm_batched(c, s.count, a.A, w.B1x, resid_R, QCUR_OP_H, s.mx, s.nx, s.rx, w.dm, w.dn,
+                                          w.dr, s.compute, w.part, E, 1.0, tile);
+    };
+    if (tu && tu->measure && tu->plan[BS_RESID].tile == 0) {
+      float t64 = 0.f, t32 = 0.f;
+      CHK(timed([&] { return run(64); }, &t64));
+      CHK(timed([&] { return run(32); }, &t32));
+      tu->plan[BS_RESID].tile = t32 < t64 ? 32 : 64;
+    }
+    const int tile = (s.autotune && tu && tu->plan[BS_RESID].tile) ? tu->plan[BS_RESID].tile : 64;
+    HIPCHK(run(tile));
+    resid_tiles = tile == 32 ? w.tiles32 : w.tiles;
+    return QCUR_OK;
+  };
   // probabilities and draws
   double* p = a.p ? a.p : w.p;
   double* q = a.q ? a.q : w.q;
@@ -1140,12 +1232,10 @@ qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, Bat
   gw.gws_bytes = w.gws_bytes;
   HIPCHK(launch_zero_i32(c, w.fail, n2));
   // G = Z^H Z:  C_b^H C_b  and  R_b R_b^H
-  HIPCHK(launch_gemm_batched(c, QCUR_OP_H, QCUR_OP_N, 1.0, slot_view(w.C64, mx, cx), slot_view(w.C64, mx, cx), 0.0,
-                             slot_view(G, cx, cx), QCUR_F64, w.gws, w.gws_bytes,
-                             bspec(n, w.C64, w.C64, G, w.dc, w.dc, w.dm)));
-  HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_H, 1.0, slot_view(w.R64, rx, nx), slot_view(w.R64, rx, nx), 0.0,
-                             slot_view(half(G), rx, rx), QCUR_F64, w.gws, w.gws_bytes,
-                             bspec(n, w.R64, w.R64, G, w.dr, w.dr, w.dn)));
+  CHK(stage(BS_GRAM_C, QCUR_OP_H, QCUR_OP_N, 1.0, slot_view(w.C64, mx, cx), slot_view(w.C64, mx, cx), 0.0,
+                             slot_view(G, cx, cx), QCUR_F64, bspec(n, w.C64, w.C64, G, w.dc, w.dc, w.dm)));
+  CHK(stage(BS_GRAM_R, QCUR_OP_N, QCUR_OP_H, 1.0, slot_view(w.R64, rx, nx), slot_view(w.R64, rx, nx), 0.0,
+                             slot_view(half(G), rx, rx), QCUR_F64, bspec(n, w.R64, w.R64, G, w.dr, w.dr, w.dn)));
   HIPCHK(launch_pad_gram_batch(c, n2, w.G, qx, G.slab, w.zq));
   CHK(chol_inv(c, gw, w.P1));
   HIPCHK(launch_sumsq_ragged(c, n, w.C64, w.dm, w.dc, w.norms, 4));
@@ -1156,27 +1246,22 @@ qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, Bat
   // eps kappa^2, which the orthonormal form would carry into C U R.
   const bool two = true;
   const Slots Q1 = two ? sl(w.Q1, px, qx, qx) : Q;
-  HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_H, 1.0, slot_view(w.C64, mx, cx), slot_view(P1, cx, cx), 0.0,
-                             slot_view(Q1, mx, cx), QCUR_F64, w.gws, w.gws_bytes,
-                             bspec(n, w.C64, P1, Q1, w.dm, w.dc, w.dc)));
-  HIPCHK(launch_gemm_batched(c, QCUR_OP_H, QCUR_OP_H, 1.0, slot_view(w.R64, rx, nx), slot_view(half(P1), rx, rx),
-                             0.0, slot_view(half(Q1), nx, rx), QCUR_F64, w.gws, w.gws_bytes,
-                             bspec(n, w.R64, P1, Q1, w.dn, w.dr, w.dr)));
+  CHK(stage(BS_Q1_C, QCUR_OP_N, QCUR_OP_H, 1.0, slot_view(w.C64, mx, cx), slot_view(P1, cx, cx), 0.0,
+                             slot_view(Q1, mx, cx), QCUR_F64, bspec(n, w.C64, P1, Q1, w.dm, w.dc, w.dc)));
+  CHK(stage(BS_Q1_R, QCUR_OP_H, QCUR_OP_H, 1.0, slot_view(w.R64, rx, nx), slot_view(half(P1), rx, rx),
+                             0.0, slot_view(half(Q1), nx, rx), QCUR_F64, bspec(n, w.R64, P1, Q1, w.dn, w.dr, w.dr)));
   Slots Pf = P1;
   if (two) {
     // CholeskyQR2: Q1^H Q1 = L2 L2^H, P = P2 P1, Q = Q1 P2^H
     const Slots P2 = sl(w.P2, qx, qx, qx), P = sl(w.P, qx, qx, qx);
-    HIPCHK(launch_gemm_batched(c, QCUR_OP_H, QCUR_OP_N, 1.0, slot_view(Q1, px, qx), slot_view(Q1, px, qx), 0.0,
-                               slot_view(G, qx, qx), QCUR_F64, w.gws, w.gws_bytes,
-                               bspec(n2, Q1, Q1, G, w.zq, w.zq, w.zp)));
+    CHK(stage(BS_G2, QCUR_OP_H, QCUR_OP_N, 1.0, slot_view(Q1, px, qx), slot_view(Q1, px, qx), 0.0,
+                               slot_view(G, qx, qx), QCUR_F64, bspec(n2, Q1, Q1, G, w.zq, w.zq, w.zp)));
     HIPCHK(launch_pad_gram_batch(c, n2, w.G, qx, G.slab, w.zq));
     CHK(chol_inv(c, gw, w.P2));
-    HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_N, 1.0, slot_view(P2, qx, qx), slot_view(P1, qx, qx), 0.0,
-                               slot_view(P, qx, qx), QCUR_F64, w.gws, w.gws_bytes,
-                               bspec(n2, P2, P1, P, w.zq, w.zq, w.zq)));
-    HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_H, 1.0, slot_view(Q1, px, qx), slot_view(P2, qx, qx), 0.0,
-                               slot_view(Q, px, qx), QCUR_F64, w.gws, w.gws_bytes,
-                               bspec(n2, Q1, P2, Q, w.zp, w.zq, w.zq)));
+    CHK(stage(BS_P, QCUR_OP_N, QCUR_OP_N, 1.0, slot_view(P2, qx, qx), slot_view(P1, qx, qx), 0.0,
+                               slot_view(P, qx, qx), QCUR_F64, bspec(n2, P2, P1, P, w.zq, w.zq, w.zq)));
+    CHK(stage(BS_Q, QCUR_OP_N, QCUR_OP_H, 1.0, slot_view(Q1, px, qx), slot_view(P2, qx, qx), 0.0,
+                               slot_view(Q, px, qx), QCUR_F64, bspec(n2, Q1, P2, Q, w.zp, w.zq, w.zq)));
     Pf = P;
   }
   HIPCHK(launch_sumsq_ragged(c, n2, Pf, w.zq, w.zq, w.norms + 2, 4));
@@ -1211,49 +1296,42 @@ qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, Bat
   }
   // M = Q_C^H (A Q_R)
   const Slots Ain = cast_A ? w.Ax : a.A;
-  HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_N, 1.0, slot_view(Ain, mx, nx), slot_view(Qr, nx, rx), 0.0,
-                             slot_view(w.T, mx, rx), s.compute, w.gws, w.gws_bytes,
-                             bspec(n, Ain, Qr, w.T, w.dm, w.dr, w.dn)));
+  CHK(stage(BS_T, QCUR_OP_N, QCUR_OP_N, 1.0, slot_view(Ain, mx, nx), slot_view(Qr, nx, rx), 0.0,
+                             slot_view(w.T, mx, rx), s.compute, bspec(n, Ain, Qr, w.T, w.dm, w.dr, w.dn)));
   if (w.Tx.p != w.T.p) HIPCHK(launch_cast_batch(c, n, w.T, w.Tx, w.dm, w.dr, mx, rx, CAST_COPY));
-  HIPCHK(launch_gemm_batched(c, QCUR_OP_H, QCUR_OP_N, 1.0, slot_view(Qc, mx, cx), slot_view(w.Tx, mx, rx), 0.0,
-                             slot_view(w.M, cx, rx), s.compute, w.gws, w.gws_bytes,
-                             bspec(n, Qc, w.Tx, w.M, w.dc, w.dr, w.dm)));
+  CHK(stage(BS_M, QCUR_OP_H, QCUR_OP_N, 1.0, slot_view(Qc, mx, cx), slot_view(w.Tx, mx, rx), 0.0,
+                             slot_view(w.M, cx, rx), s.compute, bspec(n, Qc, w.Tx, w.M, w.dc, w.dr, w.dm)));
   auto left_factor = [&]() -> qcur_status {  // B1 = Q_C M in the product dtype
     if (w.Mx.p != w.M.p) HIPCHK(launch_cast_batch(c, n, w.M, w.Mx, w.dc, w.dr, cx, rx, CAST_COPY));
-    HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_N, 1.0, slot_view(Qc, mx, cx), slot_view(w.Mx, cx, rx), 0.0,
-                               slot_view(w.B1, mx, rx), s.compute, w.gws, w.gws_bytes,
-                               bspec(n, Qc, w.Mx, w.B1, w.dm, w.dr, w.dc)));
+    CHK(stage(BS_B1, QCUR_OP_N, QCUR_OP_N, 1.0, slot_view(Qc, mx, cx), slot_view(w.Mx, cx, rx), 0.0,
+                               slot_view(w.B1, mx, rx), s.compute, bspec(n, Qc, w.Mx, w.B1, w.dm, w.dr, w.dc)));
     if (w.B1x.p != w.B1.p) HIPCHK(launch_cast_batch(c, n, w.B1, w.B1x, w.dm, w.dr, mx, rx, CAST_COPY));
     return QCUR_OK;
   };
   for (int st = 0; st < s.refine; ++st) {
     // E = A - Q_C M Q_R^H;  M += Q_C^H (E Q_R)
     CHK(left_factor());
-    HIPCHK(launch_residual_gemm_batched(c, n, a.A, w.B1x, Qr, QCUR_OP_H, mx, nx, rx, w.dm, w.dn, w.dr, s.compute,
-                                        w.part, &w.E, 1.0));
+    resid_R = Qr;
+    CHK(resid(&w.E));
     if (w.Ex.p != w.E.p) HIPCHK(launch_cast_batch(c, n, w.E, w.Ex, w.dm, w.dn, mx, nx, CAST_COPY));
-    HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_N, 1.0, slot_view(w.Ex, mx, nx), slot_view(Qr, nx, rx), 0.0,
-                               slot_view(w.T, mx, rx), s.compute, w.gws, w.gws_bytes,
-                               bspec(n, w.Ex, Qr, w.T, w.dm, w.dr, w.dn)));
+    CHK(stage(BS_T, QCUR_OP_N, QCUR_OP_N, 1.0, slot_view(w.Ex, mx, nx), slot_view(Qr, nx, rx), 0.0,
+                               slot_view(w.T, mx, rx), s.compute, bspec(n, w.Ex, Qr, w.T, w.dm, w.dr, w.dn)));
     if (w.Tx.p != w.T.p) HIPCHK(launch_cast_batch(c, n, w.T, w.Tx, w.dm, w.dr, mx, rx, CAST_COPY));
-    HIPCHK(launch_gemm_batched(c, QCUR_OP_H, QCUR_OP_N, 1.0, slot_view(Qc, mx, cx), slot_view(w.Tx, mx, rx), 1.0,
-                               slot_view(w.M, cx, rx), s.compute, w.gws, w.gws_bytes,
-                               bspec(n, Qc, w.Tx, w.M, w.dc, w.dr, w.dm)));
+    CHK(stage(BS_M, QCUR_OP_H, QCUR_OP_N, 1.0, slot_view(Qc, mx, cx), slot_view(w.Tx, mx, rx), 1.0,
+                               slot_view(w.M, cx, rx), s.compute, bspec(n, Qc, w.Tx, w.M, w.dc, w.dr, w.dm)));
   }
   // residual_b = ||A_b - Q_C M Q_R^H||_F = ||A_b - C_b U_b R_b||_F
   CHK(left_factor());
-  HIPCHK(launch_residual_gemm_batched(c, n, a.A, w.B1x, Qr, QCUR_OP_H, mx, nx, rx, w.dm, w.dn, w.dr, s.compute,
-                                      w.part, nullptr, 0.0));
-  HIPCHK(launch_resid_sum_batch(c, n, w.part, w.tiles, a.residual));
+  resid_R = Qr;
+  CHK(resid(nullptr));
+  HIPCHK(launch_resid_sum_batch(c, n, w.part, resid_tiles, a.residual));
   // U = P_C^H M P_R in FP64
   if (w.M64.p != w.M.p) HIPCHK(launch_cast_batch(c, n, w.M, w.M64, w.dc, w.dr, cx, rx, CAST_COPY));
-  HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_N, 1.0, slot_view(w.M64, cx, rx), slot_view(half(Pf), rx, rx), 0.0,
-                             slot_view(w.W1, cx, rx), QCUR_F64, w.gws, w.gws_bytes,
-                             bspec(n, w.M64, Pf, w.W1, w.dc, w.dr, w.dr)));
+  CHK(stage(BS_W1, QCUR_OP_N, QCUR_OP_N, 1.0, slot_view(w.M64, cx, rx), slot_view(half(Pf), rx, rx), 0.0,
+                             slot_view(w.W1, cx, rx), QCUR_F64, bspec(n, w.M64, Pf, w.W1, w.dc, w.dr, w.dr)));
   const Slots U64 = adt == QCUR_F64 ? a.U : w.U64;
-  HIPCHK(launch_gemm_batched(c, QCUR_OP_H, QCUR_OP_N, 1.0, slot_view(Pf, cx, cx), slot_view(w.W1, cx, rx), 0.0,
-                             slot_view(U64, cx, rx), QCUR_F64, w.gws, w.gws_bytes,
-                             bspec(n, Pf, w.W1, U64, w.dc, w.dr, w.dc)));
+  CHK(stage(BS_U, QCUR_OP_H, QCUR_OP_N, 1.0, slot_view(Pf, cx, cx), slot_view(w.W1, cx, rx), 0.0,
+                             slot_view(U64, cx, rx), QCUR_F64, bspec(n, Pf, w.W1, U64, w.dc, w.dr, w.dc)));
   if (U64.p != a.U.p) HIPCHK(launch_cast_batch(c, n, U64, a.U, w.dc, w.dr, cx, rx, CAST_COPY));
   (void)adt;
   return QCUR_OK;
@@ -1307,6 +1385,10 @@ qcur_status qcur_create(qcur_handle* handle, int device) {
 
 qcur_status qcur_destroy(qcur_handle h) {
   if (!h) return QCUR_OK;
+  for (auto& rec : h->batches) {
+    if (rec.tun.e0) (void)hipEventDestroy(rec.tun.e0);
+    if (rec.tun.e1) (void)hipEventDestroy(rec.tun.e1);
+  }
   (void)hipFree(h->c.status);
   delete h;
   return QCUR_OK;
@@ -1744,18 +1826,18 @@ qcur_status qcur_solve(qcur_handle h, const qcur_qmat* A, int64_t c, int64_t r, 
 
 // ---- batched solve ------------------------------------------------------------
 size_t qcur_batch_workspace(int32_t count, const int32_t* dims, int a_dtype, int sampling, int compute,
-                            int refine_steps) {
+                            int refine_steps, int autotune) {
   BatchShape s{};
-  if (check_batch_shape(count, dims, a_dtype, sampling, compute, refine_steps, 1, &s) != QCUR_OK) return 0;
+  if (check_batch_shape(count, dims, a_dtype, sampling, compute, refine_steps, 1, autotune, &s) != QCUR_OK) return 0;
   Bump b(nullptr);
   batch_carve(b, s);
   return b.used + 256;
 }
 
 qcur_status qcur_batch_prepare(qcur_handle h, int32_t count, const int32_t* dims, int a_dtype, int sampling,
-                               int compute, int refine_steps, void* ws, size_t ws_bytes) {
+                               int compute, int refine_steps, int autotune, void* ws, size_t ws_bytes) {
   BatchShape s{};
-  CHK(check_batch_shape(count, dims, a_dtype, sampling, compute, refine_steps, 1, &s));
+  CHK(check_batch_shape(count, dims, a_dtype, sampling, compute, refine_steps, 1, autotune, &s));
   {
     Bump sz(nullptr);
     batch_carve(sz, s);
@@ -1781,7 +1863,6 @@ qcur_status qcur_batch_prepare(qcur_handle h, int32_t count, const int32_t* dims
     hp[count + i] = hn[i];
     hq[count + i] = hr[i];
   }
-  // the header arrays were carved back to back except for 256-byte alignment
   const int* srcs[6] = {hm, hn, hc, hr, hp, hq};
   int* dsts[6] = {w.dm, w.dn, w.dc, w.dr, w.zp, w.zq};
   const size_t lens[6] = {(size_t)count, (size_t)count, (size_t)count, (size_t)count, (size_t)2 * count,
@@ -1789,7 +1870,6 @@ qcur_status qcur_batch_prepare(qcur_handle h, int32_t count, const int32_t* dims
   for (int k = 0; k < 6; ++k)
     HIPCHK(hipMemcpyAsync(dsts[k], srcs[k], lens[k] * sizeof(int), hipMemcpyHostToDevice, h->c.stream));
   HIPCHK(hipStreamSynchronize(h->c.stream));
-  const uint64_t key = batch_key(s);
   int slot = -1;
   for (int k = 0; k < 8; ++k)
     if (h->batches[k].ws == ws) slot = k;
@@ -1797,9 +1877,33 @@ qcur_status qcur_batch_prepare(qcur_handle h, int32_t count, const int32_t* dims
     slot = h->next_batch;
     h->next_batch = (h->next_batch + 1) % 8;
   }
-  h->batches[slot].ws = ws;
-  h->batches[slot].key = key;
+  BatchRecord& rec = h->batches[slot];
+  if (rec.tun.e0) (void)hipEventDestroy(rec.tun.e0);
+  if (rec.tun.e1) (void)hipEventDestroy(rec.tun.e1);
+  rec = BatchRecord{};
+  rec.ws = ws;
+  rec.key = batch_key(s);
+  rec.autotune = autotune;
+  if (autotune) {
+    HIPCHK(hipEventCreate(&rec.tun.e0));
+    HIPCHK(hipEventCreate(&rec.tun.e1));
+  }
   return QCUR_OK;
+}
+
+int qcur_batch_plans(qcur_handle h, const void* ws, int* tiles, int* splits, int n) {
+  if (!h) return 0;
+  for (int k = 0; k < 8; ++k) {
+    const BatchRecord& rec = h->batches[k];
+    if (rec.ws != ws || !rec.ws) continue;
+    const int cnt = std::min<int>(n, BS_COUNT);
+    for (int i = 0; i < cnt; ++i) {
+      if (tiles) tiles[i] = rec.tun.plan[i].tile;
+      if (splits) splits[i] = rec.tun.plan[i].splits;
+    }
+    return rec.tuned ? BS_COUNT : 0;
+  }
+  return 0;
 }
 
 qcur_status qcur_solve_batched(qcur_handle h, int32_t count, const int32_t* dims, const qcur_qmat* A,
@@ -1810,7 +1914,7 @@ qcur_status qcur_solve_batched(qcur_handle h, int32_t count, const int32_t* dims
   if (with_replacement != 0 && with_replacement != 1) return fail(QCUR_ERR_ARG, "with_replacement must be 0 or 1");
   if (!A) return fail(QCUR_ERR_ARG, "A is NULL");
   BatchShape s{};
-  CHK(check_batch_shape(count, dims, (int)A->dtype, sampling, compute, refine_steps, with_replacement, &s));
+  CHK(check_batch_shape(count, dims, (int)A->dtype, sampling, compute, refine_steps, with_replacement, 0, &s));
   CHK(check_slotted(A, "A", s.mx, s.nx, a_bstride));
   CHK(check_slotted(U, "U", s.cx, s.rx, u_bstride));
   if (U->dtype != acc_dt(compute)) return fail(QCUR_ERR_DTYPE, "U must be FP64 (F64 compute) or FP32");
@@ -1819,14 +1923,23 @@ qcur_status qcur_solve_batched(qcur_handle h, int32_t count, const int32_t* dims
   if (max_rank < 0) return fail(QCUR_ERR_ARG, "max_rank must be >= 0");
   {
     Bump sz(nullptr);
-    batch_carve(sz, s);
+    batch_carve(sz, s);  // the smaller layout (no autotuning)
     if (!ws || ws_bytes < sz.used + 256) return fail(QCUR_ERR_WORKSPACE, "batch needs %zu workspace bytes", sz.used + 256);
   }
   CHK(check_handle(h));
-  const uint64_t key = batch_key(s);
-  bool prepared = false;
-  for (int k = 0; k < 8; ++k) prepared |= (h->batches[k].ws == ws && h->batches[k].key == key);
-  if (!prepared) return fail(QCUR_ERR_ARG, "the workspace was not prepared for this batch (qcur_batch_prepare)");
+  // the record of this workspace fixes the layout (with or without autotuning)
+  BatchRecord* rec = nullptr;
+  for (int k = 0; k < 8; ++k) {
+    if (h->batches[k].ws != ws || !ws) continue;
+    s.autotune = h->batches[k].autotune;
+    if (h->batches[k].key == batch_key(s)) rec = &h->batches[k];
+  }
+  if (!rec) return fail(QCUR_ERR_ARG, "the workspace was not prepared for this batch (qcur_batch_prepare)");
+  {
+    Bump sz(nullptr);
+    batch_carve(sz, s);
+    if (ws_bytes < sz.used + 256) return fail(QCUR_ERR_WORKSPACE, "batch needs %zu workspace bytes", sz.used + 256);
+  }
   Bump b(ws);
   BatchWs w = batch_carve(b, s);
   BatchArgs a{};
@@ -1842,7 +1955,18 @@ qcur_status qcur_solve_batched(qcur_handle h, int32_t count, const int32_t* dims
   a.rank_out = rank_out;
   a.p = p_col;
   a.q = q_row;
-  return batch_run(h->c, s, a, w);
+  BatchTuning* tu = nullptr;
+  if (rec->autotune) {
+    tu = &rec->tun;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIPCHK(hipStreamIsCapturing(h->c.stream, &cap));
+    // measure on the first call that is not being captured
+    tu->measure = !rec->tuned && cap == hipStreamCaptureStatusNone;
+  }
+  const qcur_status st = batch_run(h->c, s, a, w, tu);
+  if (tu && tu->measure && st == QCUR_OK) rec->tuned = true;
+  if (tu) tu->measure = false;
+  return st;
 }
 
 qcur_status qcur_cast(qcur_handle h, const qcur_qmat* X, qcur_qmat* Y) {

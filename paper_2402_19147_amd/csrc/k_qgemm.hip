@@ -115,6 +115,8 @@ struct GemmArgs {
   // BF16: operands are 16-byte aligned with row, plane and batch strides that
   // are multiples of 8, so eight consecutive elements load as one vector
   int vec;
+  // launch plan overrides (0: automatic)
+  int force_tile, force_splits;
 };
 
 enum { EPI_STORE = 0, EPI_PARTIAL = 1, EPI_RESID = 2 };
@@ -538,6 +540,11 @@ static Plan plan_of(int64_t M, int64_t N, int64_t K, int bk, int batch) {
 static int bk_of(int compute) { return compute == QCUR_BF16 ? 32 : 16; }
 static size_t acc_size(int compute) { return compute == QCUR_F64 ? 8 : 4; }
 
+size_t gemm_workspace_splits(int64_t M, int64_t N, int compute, int batch, int max_splits) {
+  if (max_splits <= 1) return 0;
+  return (size_t)batch * max_splits * 4 * (size_t)M * (size_t)N * acc_size(compute);
+}
+
 size_t gemm_workspace(int64_t M, int64_t N, int64_t K, int compute, int batch) {
   const int s = plan_of(M, N, K, bk_of(compute), batch).splits;
   if (s <= 1) return 0;
@@ -548,7 +555,7 @@ template <int DT, int TILE>
 static hipError_t gemm_dt_tile(const Ctx& c, GemmArgs g, void* ws, size_t ws_bytes) {
   constexpr int BK = MT<DT>::BK;
   const int64_t kt = (g.K + BK - 1) / BK;
-  int splits = plan_of(g.M, g.N, g.K, BK, g.batch).splits;
+  int splits = g.force_splits > 0 ? g.force_splits : plan_of(g.M, g.N, g.K, BK, g.batch).splits;
   const size_t need = (size_t)g.batch * splits * 4 * (size_t)g.M * (size_t)g.N * acc_size(DT);
   if (splits > 1 && (ws == nullptr || ws_bytes < need)) splits = 1;
   dim3 grid((unsigned)((g.N + TILE - 1) / TILE), (unsigned)((g.M + TILE - 1) / TILE), 1);
@@ -579,7 +586,8 @@ static hipError_t gemm_dt_tile(const Ctx& c, GemmArgs g, void* ws, size_t ws_byt
 
 template <int DT>
 static hipError_t gemm_dt(const Ctx& c, GemmArgs g, void* ws, size_t ws_bytes) {
-  if (plan_of(g.M, g.N, g.K, MT<DT>::BK, g.batch).tile == 64) return gemm_dt_tile<DT, 64>(c, g, ws, ws_bytes);
+  const int tile = g.force_tile ? g.force_tile : plan_of(g.M, g.N, g.K, MT<DT>::BK, g.batch).tile;
+  if (tile == 64) return gemm_dt_tile<DT, 64>(c, g, ws, ws_bytes);
   return gemm_dt_tile<DT, 32>(c, g, ws, ws_bytes);
 }
 
@@ -597,6 +605,8 @@ hipError_t launch_gemm_batched(const Ctx& c, int opA, int opB, double alpha, QVi
   g.bM = bs.M;
   g.bN = bs.N;
   g.bK = bs.K;
+  g.force_tile = bs.tile;
+  g.force_splits = bs.splits;
   g.A = A.p; g.lda = A.ld; g.psa = A.ps;
   g.B = B.p; g.ldb = B.ld; g.psb = B.ps;
   g.D = D.p; g.ldd = D.ld; g.psd = D.ps;
@@ -664,7 +674,7 @@ hipError_t launch_residual_gemm(const Ctx& c, QView A, QView B1, QView R, const 
 // when E is given.
 hipError_t launch_residual_gemm_batched(const Ctx& c, int count, Slots A, Slots B1, Slots R, int opR, int64_t mx,
                                         int64_t nx, int64_t kx, const int* bM, const int* bN, const int* bK,
-                                        int compute, double* partials, const Slots* E, double e_scale) {
+                                        int compute, double* partials, const Slots* E, double e_scale, int tile) {
   if (count <= 0 || mx <= 0 || nx <= 0) return hipSuccess;
   GemmArgs g = {};
   g.A = B1.p; g.lda = B1.ld; g.psa = B1.ps; g.sA = B1.slab;
@@ -680,19 +690,23 @@ hipError_t launch_residual_gemm_batched(const Ctx& c, int count, Slots A, Slots 
   g.vec = compute == QCUR_BF16 && vec_ok(QView{B1.p, 1, 1, B1.ld, B1.ps, B1.dt}, B1.slab) &&
           vec_ok(QView{R.p, 1, 1, R.ld, R.ps, R.dt}, R.slab);
   if (E) { g.E = E->p; g.edt = E->dt; g.eld = E->ld; g.eps = E->ps; g.sE = E->slab; g.e_scale = e_scale; }
-  const dim3 grid((unsigned)((nx + 63) / 64), (unsigned)((mx + 63) / 64), (unsigned)count);
+  const int t = tile == 32 ? 32 : 64;
+  const dim3 grid((unsigned)((nx + t - 1) / t), (unsigned)((mx + t - 1) / t), (unsigned)count);
   switch (compute) {
     case QCUR_F64:
       g.ktiles_per_split = (int)((kx + 15) / 16);
-      hipLaunchKernelGGL((k_qgemm<QCUR_F64, EPI_RESID, 64, 64>), grid, dim3(NT), 0, c.stream, g);
+      if (t == 64) hipLaunchKernelGGL((k_qgemm<QCUR_F64, EPI_RESID, 64, 64>), grid, dim3(NT), 0, c.stream, g);
+      else hipLaunchKernelGGL((k_qgemm<QCUR_F64, EPI_RESID, 32, 32>), grid, dim3(NT), 0, c.stream, g);
       break;
     case QCUR_F32:
       g.ktiles_per_split = (int)((kx + 15) / 16);
-      hipLaunchKernelGGL((k_qgemm<QCUR_F32, EPI_RESID, 64, 64>), grid, dim3(NT), 0, c.stream, g);
+      if (t == 64) hipLaunchKernelGGL((k_qgemm<QCUR_F32, EPI_RESID, 64, 64>), grid, dim3(NT), 0, c.stream, g);
+      else hipLaunchKernelGGL((k_qgemm<QCUR_F32, EPI_RESID, 32, 32>), grid, dim3(NT), 0, c.stream, g);
       break;
     default:
       g.ktiles_per_split = (int)((kx + 31) / 32);
-      hipLaunchKernelGGL((k_qgemm<QCUR_BF16, EPI_RESID, 64, 64>), grid, dim3(NT), 0, c.stream, g);
+      if (t == 64) hipLaunchKernelGGL((k_qgemm<QCUR_BF16, EPI_RESID, 64, 64>), grid, dim3(NT), 0, c.stream, g);
+      else hipLaunchKernelGGL((k_qgemm<QCUR_BF16, EPI_RESID, 32, 32>), grid, dim3(NT), 0, c.stream, g);
   }
   return hipGetLastError();
 }

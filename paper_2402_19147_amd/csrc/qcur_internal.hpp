@@ -96,8 +96,12 @@ struct BatchSpec {
   const int* M = nullptr;
   const int* N = nullptr;
   const int* K = nullptr;
+  int tile = 0;    // launch plan override: tile edge 32 or 64 (0: automatic)
+  int splits = 0;  // K slices (0: automatic; reduced to 1 without enough workspace)
 };
 size_t gemm_workspace(int64_t M, int64_t N, int64_t K, int compute, int batch = 1);
+// Workspace for any plan with at most max_splits K slices.
+size_t gemm_workspace_splits(int64_t M, int64_t N, int compute, int batch, int max_splits);
 hipError_t launch_gemm(const Ctx& c, int opA, int opB, double alpha, QView A, QView B, double beta,
                        QView D, int compute, void* ws, size_t ws_bytes);
 hipError_t launch_gemm_batched(const Ctx& c, int opA, int opB, double alpha, QView A, QView B, double beta,
@@ -217,8 +221,10 @@ hipError_t launch_decide_batch(const Ctx& c, int count2, int count, const double
                                int* ok);
 hipError_t launch_resid_sum_batch(const Ctx& c, int count, const double* part, int64_t tiles, double* out);
 // Batched residual A_b - B1_b op(R_b) (op = QCUR_OP_N or QCUR_OP_H).
+// tile: 64 or 32 (partials per problem: ceil(mx/tile) * ceil(nx/tile)).
 hipError_t launch_residual_gemm_batched(const Ctx& c, int count, Slots A, Slots B1, Slots R, int opR, int64_t mx,
                                         int64_t nx, int64_t kx, const int* bM, const int* bN, const int* bK,
-                                        int compute, double* partials, const Slots* E, double e_scale);
+                                        int compute, double* partials, const Slots* E, double e_scale,
+                                        int tile = 64);
 
 }  // namespace qcur

@@ -78,8 +78,9 @@ def _declare(L):
         "qcur_solve": (c_int, [c_p, QP, c_i64, c_i64, c_int, c_int, c_int, c_u64, c_int, c_int, c_d, c_i64, c_p,
                                c_p, QP, c_p, c_p, c_p, c_p, QP, QP, QP, c_p, c_sz]),
         "qcur_solve_workspace": (c_sz, [c_i64, c_i64, c_i64, c_i64, c_int, c_int]),
-        "qcur_batch_workspace": (c_sz, [ctypes.c_int32, c_p, c_int, c_int, c_int, c_int]),
-        "qcur_batch_prepare": (c_int, [c_p, ctypes.c_int32, c_p, c_int, c_int, c_int, c_int, c_p, c_sz]),
+        "qcur_batch_workspace": (c_sz, [ctypes.c_int32, c_p, c_int, c_int, c_int, c_int, c_int]),
+        "qcur_batch_prepare": (c_int, [c_p, ctypes.c_int32, c_p, c_int, c_int, c_int, c_int, c_int, c_p, c_sz]),
+        "qcur_batch_plans": (c_int, [c_p, c_p, c_p, c_p, c_int]),
         "qcur_solve_batched": (c_int, [c_p, ctypes.c_int32, c_p, QP, c_i64, c_int, c_int, c_u64, c_int, c_int, c_d,
                                        c_i64, c_p, c_p, QP, c_i64, c_p, c_p, c_p, c_p, c_p, c_sz]),
     }
@@ -356,10 +357,12 @@ class BatchSolver:
     I (count, rx), J (count, cx), U (count, 4, cx, rx), residual (count,),
     ranks (count, 2), p (count, nx), q (count, mx), each problem in the
     leading part of its row/slot.  The call enqueues kernels only, so it may
-    be captured in a torch.cuda.CUDAGraph after one eager call."""
+    be captured in a torch.cuda.CUDAGraph after one eager call.  With
+    autotune=True the first eager call times the candidate launch plans of
+    every GEMM stage and keeps the fastest (see plans())."""
 
     def __init__(self, dims, compute: int = F32, sampling: int = LENGTH, refine_steps: int = 0,
-                 a_dtype=torch.float32, device=None):
+                 a_dtype=torch.float32, device=None, autotune: bool = False):
         import numpy as np
         dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         d = np.ascontiguousarray(np.asarray(dims, dtype=np.int32).reshape(-1, 4))
@@ -378,13 +381,29 @@ class BatchSolver:
         self.p = torch.zeros((n, self.nx), dtype=torch.float64, device=dev)
         self.q = torch.zeros((n, self.mx), dtype=torch.float64, device=dev)
         dptr = ctypes.c_void_p(d.ctypes.data)
-        nbytes = lib().qcur_batch_workspace(n, dptr, _QCUR_DT[a_dtype], sampling, compute, refine_steps)
+        self.autotune = int(bool(autotune))
+        nbytes = lib().qcur_batch_workspace(n, dptr, _QCUR_DT[a_dtype], sampling, compute, refine_steps,
+                                            self.autotune)
         if nbytes == 0:
             raise QcurError(1, "invalid batch sizes or options")
         self.ws = _ws(nbytes, dev)
         with torch.cuda.device(dev):
             _check(lib().qcur_batch_prepare(handle(dev).bind(), n, dptr, _QCUR_DT[a_dtype], sampling, compute,
-                                            refine_steps, _ptr(self.ws), self.ws.numel()))
+                                            refine_steps, self.autotune, _ptr(self.ws), self.ws.numel()))
+        self.device = dev
+
+    STAGES = ("gram_C", "gram_R", "q1_C", "q1_R", "gram2", "p2p1", "q1p2", "AQr", "QcT", "QcM", "MPr", "PcW",
+              "residual")
+
+    def plans(self):
+        """{stage: (tile, splits)} kept by the autotuner, or None before it ran."""
+        n = len(self.STAGES)
+        tiles = (ctypes.c_int * n)()
+        splits = (ctypes.c_int * n)()
+        got = lib().qcur_batch_plans(handle(self.device).h, _ptr(self.ws), tiles, splits, n)
+        if got == 0:
+            return None
+        return {name: (tiles[i], splits[i]) for i, name in enumerate(self.STAGES)}
 
     def __call__(self, A: torch.Tensor, seed: int = 0, rtol: float = -1.0, max_rank: int = 0,
                  with_replacement: bool = False):

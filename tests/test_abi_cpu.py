@@ -153,15 +153,17 @@ def _dims(rows):
 
 def test_batch_workspace_and_validation(L):
     d, dp = _dims([(64, 80, 16, 12), (100, 70, 20, 30)])
-    ws = L.qcur_batch_workspace(2, dp, Q.F32, Q.LENGTH, Q.F32, 0)
+    ws = L.qcur_batch_workspace(2, dp, Q.F32, Q.LENGTH, Q.F32, 0, 0)
     assert ws > 0
-    assert L.qcur_batch_workspace(2, dp, Q.F32, Q.LENGTH, Q.F32, 1) > ws  # refinement adds E
-    assert L.qcur_batch_workspace(0, dp, Q.F32, Q.LENGTH, Q.F32, 0) == 0
-    assert L.qcur_batch_workspace(2, None, Q.F32, Q.LENGTH, Q.F32, 0) == 0
+    assert L.qcur_batch_workspace(2, dp, Q.F32, Q.LENGTH, Q.F32, 1, 0) > ws  # refinement adds E
+    assert L.qcur_batch_workspace(2, dp, Q.F32, Q.LENGTH, Q.F32, 0, 1) > ws  # room for tuned plans
+    assert L.qcur_batch_workspace(2, dp, Q.F32, Q.LENGTH, Q.F32, 0, 2) == 0
+    assert L.qcur_batch_workspace(0, dp, Q.F32, Q.LENGTH, Q.F32, 0, 0) == 0
+    assert L.qcur_batch_workspace(2, None, Q.F32, Q.LENGTH, Q.F32, 0, 0) == 0
     bad, bp = _dims([(64, 80, 16, 12), (0, 70, 20, 30)])
-    assert L.qcur_batch_workspace(2, bp, Q.F32, Q.LENGTH, Q.F32, 0) == 0
+    assert L.qcur_batch_workspace(2, bp, Q.F32, Q.LENGTH, Q.F32, 0, 0) == 0
     big, gp = _dims([(5000, 80, 16, 12)])
-    assert L.qcur_batch_workspace(1, gp, Q.F32, Q.LENGTH, Q.F32, 0) == 0
+    assert L.qcur_batch_workspace(1, gp, Q.F32, Q.LENGTH, Q.F32, 0, 0) == 0
 
     # slots: (count, 4, 100, 80) for A, (count, 4, 20, 30) for U
     A = qm(100, 80, Q.F32)

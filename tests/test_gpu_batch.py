@@ -241,3 +241,42 @@ def test_batch_512_workload(compute):
     # a sample of problems against the checker, element by element
     for b in (0, 1, 97, 255, 256, 511):
         check_problem(bs, A, b, dims, 40, compute)
+
+
+@pytest.mark.parametrize("compute", [Q.F32, Q.BF16])
+def test_batch_autotuned_plans(compute):
+    probs, dims = make_batch(12, seed=28, mn=(40, 260), k=(3, 12))
+    A = Q.pack_batch([P["A"] for P in probs], dtype=torch.float32, device=DEV)
+    bs = Q.BatchSolver(dims, compute=compute, refine_steps=1, a_dtype=torch.float32, autotune=True)
+    assert bs.plans() is None
+    bs(A, seed=6)  # measures the candidate plans
+    Q.sync_status()
+    plans = bs.plans()
+    assert plans is not None and len(plans) == 13
+    assert all(t in (32, 64) for (t, s) in plans.values())
+    assert all(1 <= s <= 4 for name, (t, s) in plans.items() if name != "residual")
+    first = [t.clone() for t in (bs.I, bs.J, bs.U, bs.residual)]
+    for b in range(len(dims)):
+        check_problem(bs, A, b, dims, 6, compute)
+    # later calls reuse the plans: bitwise repeatable, also from a captured graph
+    bs(A, seed=6)
+    torch.cuda.synchronize()
+    for t, r in zip((bs.I, bs.J, bs.U, bs.residual), first):
+        assert torch.equal(t, r)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        bs(A, seed=6)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        bs(A, seed=6)
+    bs.U.zero_()
+    bs.residual.zero_()
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    for t, r in zip((bs.I, bs.J, bs.U, bs.residual), first):
+        assert torch.equal(t, r)
+    Q.sync_status()
