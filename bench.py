@@ -158,6 +158,7 @@ def main():
     if not args.no_extra:
         extra["batch_512"] = bench_batch(q, torch, workloads, dev, args)
         extra["dense_4096"] = bench_dense(q, torch, workloads, dev, args)
+        extra["complete_512x768"] = bench_complete(q, torch, workloads, dev)
     # a plain copy of known size, for scaling HBM byte counters of profiled runs
     src = torch.empty(64 * 2 ** 20, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
@@ -300,6 +301,44 @@ def bench_dense(q, torch, workloads, dev, args):
                                                 torch.linalg.vector_norm(Bs["plain_f64"]))
         out[f"speedup_{name}_vs_plain_f64"] = out[name]["solves_per_s"] / out["plain_f64"]["solves_per_s"]
     q.sync_status()
+    return out
+
+
+def bench_complete(q, torch, workloads, dev):
+    """Completion from 30% observed entries (Algorithm 2) of a 512 x 768
+    colour-image-shaped matrix: time per step, next to the paper's reported
+    seconds per iteration for its 512 x 768 test images (hardware not
+    stated; context only)."""
+    import numpy as np
+    cfg = workloads.WORKLOADS["complete_512x768"]
+    m, n, k, seed = cfg["m"], cfg["n"], cfg["k"], cfg["seed"]
+    A = workloads.color_like(m, n, k, seed, cfg["noise"])
+    truth = workloads.color_like(m, n, k, seed, 0.0)
+    mask = workloads.bernoulli_mask(m, n, cfg["mask_p"], seed)
+    I = workloads.uniform_index_set(m, cfg["r"], seed, 0)
+    J = workloads.uniform_index_set(n, cfg["c"], seed, 1)
+    out = {"workload": "512x768 pure quaternion, rank 20 + N(0,0.01^2), 70% of entries missing, c=r=60 fixed "
+                       "uniform index sets, t_max=200, tol=1e-4",
+           "paper_s_per_iter_range": [0.135, 0.351]}
+    miss = mask == 0
+    for name, comp, dt in (("f64", q.F64, torch.float64), ("f32", q.F32, torch.float32)):
+        Y = torch.tensor(A, dtype=dt, device=dev)
+        Mk = torch.tensor(mask, device=dev)
+        It = torch.tensor(I, device=dev)
+        Jt = torch.tensor(J, device=dev)
+        q.complete(Y, Mk, It, Jt, compute=comp, max_iter=2, tol=0.0)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X, iters, rel = q.complete(Y, Mk, It, Jt, compute=comp, max_rank=k, max_iter=cfg["max_iter"],
+                                   tol=cfg["tol"])
+        torch.cuda.synchronize()
+        dt_s = time.perf_counter() - t0
+        q.sync_status()
+        Xh = X.to(torch.float64).cpu().numpy()
+        err = float(np.sqrt(((Xh - truth)[:, miss] ** 2).sum() / ((truth[:, miss]) ** 2).sum()))
+        out[name] = dict(iterations=iters, last_rel_change=rel, ms_per_iter=dt_s * 1e3 / max(iters, 1),
+                         total_ms=dt_s * 1e3, rel_err_missing_vs_noiseless=err)
+        log(f"complete {name}: {iters} steps, {dt_s * 1e3 / max(iters, 1):.3f} ms/step")
     return out
 
 

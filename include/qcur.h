@@ -293,6 +293,29 @@ qcur_status qcur_solve_batched(qcur_handle handle, int32_t count, const int32_t*
                                double* residual, int64_t* rank_out, double* p_col, double* q_row,
                                void* ws, size_t ws_bytes);
 
+/* ---- completion from partially observed entries (Algorithm 2) ---------- */
+
+/* Quaternion matrix completion with QMCUR (Algorithm 2; Example 4.4): from
+ * the observed Y (m x n, any dtype; entries where mask == 0 are ignored)
+ * and the fixed index sets I (r rows) and J (c columns, device int64),
+ * X^0 = P_Omega(Y), then for t = 0, 1, ...: M^{t+1} = C U R of X^t
+ * (Algorithm 1 with C = X^t(:,J), R = X^t(I,:), U = C^+ X^t R^+, evaluated
+ * as in qcur_approx), X^{t+1} = P_Omega(Y) + P_Omega^c(M^{t+1}) (fused into
+ * the last product), until ||X^{t+1} - X^t||_F / ||X^t||_F <= tol or
+ * max_iter steps (the paper's t_max = 200 and 1e-4).
+ * mask: device uint8 m x n, row stride mask_ld (nonzero = observed).
+ * compute: product dtype as in qcur_approx; X (m x n, FP64 for QCUR_F64 else
+ * FP32) receives the last iterate.  rtol and max_rank (the predefined rank
+ * k) apply to the pseudoinverses.  iters (host int, may be NULL): steps
+ * taken; rel (host double, may be NULL): the last relative change.
+ * Synchronises with the host once per step (the stopping test) and inside
+ * the pseudoinverse.  ws: qcur_complete_workspace(m, n, c, r, compute). */
+qcur_status qcur_complete(qcur_handle handle, const qcur_qmat* Y, const uint8_t* mask, int64_t mask_ld,
+                          const int64_t* I, int64_t r, const int64_t* J, int64_t c, int compute, double rtol,
+                          int64_t max_rank, int max_iter, double tol, qcur_qmat* X, int* iters, double* rel,
+                          void* ws, size_t ws_bytes);
+size_t qcur_complete_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int compute);
+
 /* ---- helpers ----------------------------------------------------------- */
 
 /* Elementwise dtype conversion Y = X (same shape; BF16 with

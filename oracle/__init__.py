@@ -17,8 +17,9 @@ Modules
   sampling  length / uniform probabilities, the index sampler
   cur       gathers, the two cores, CUR, the residual, the whole solve
   grad      derivatives of B = CUR(A) and of the masked loss
+  complete  completion from partially observed entries (Algorithm 2)
 """
-from . import quat, pinv, sampling, cur, grad  # noqa: F401
+from . import quat, pinv, sampling, cur, grad, complete  # noqa: F401
 from .quat import qmul, qH, fro2, chi, unchi, real_rep, inner  # noqa: F401
 from .pinv import pinv as qpinv  # noqa: F401
 from .sampling import probs_length, probs_uniform, draw, splitmix64_nth  # noqa: F401

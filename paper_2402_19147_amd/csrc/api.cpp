@@ -1337,6 +1337,95 @@ qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, Bat
   return QCUR_OK;
 }
 
+
+// ---- completion (Algorithm 2) ------------------------------------------------
+struct CompleteArgs {
+  QView Y, X;
+  const uint8_t* mask;
+  int64_t mask_ld;
+  const int64_t *I, *J;
+  int64_t r, cc;
+  int compute;
+  double rtol;
+  int64_t max_rank;
+  int max_iter;
+  double tol;
+  int* iters;
+  double* rel;
+};
+
+// X^0 = P_Omega(Y); then M^{t+1} = C U R of X^t (Algorithm 1 on the fixed
+// index sets I, J, least-squares core in orthonormal form) and
+// X^{t+1} = P_Omega(Y) + P_Omega^c(M^{t+1}) in one fused product, until
+// ||X^{t+1} - X^t||_F / ||X^t||_F <= tol or max_iter steps.  The iterates
+// alternate between the output X and one workspace copy; the last one is
+// left in X.
+qcur_status complete_run(const Ctx& c, const CompleteArgs& a, Bump& b, bool count_only) {
+  const int64_t m = a.Y.rows, n = a.Y.cols, r = a.r, cc = a.cc;
+  const int xdt = a.X.dt, idt = in_dt(a.compute), adt = acc_dt(a.compute);
+  QView Xw = b.mat(m, n, xdt);
+  QView C = b.mat(m, cc, xdt), R = b.mat(r, n, xdt);
+  PinvPlan pc = pinv_plan(m, cc), pr = pinv_plan(r, n);
+  const int64_t pp = std::max(pc.pp, pr.pp), qq = std::max(pc.qq, pr.qq);
+  PinvWs jw = pinv_carve(b, pp, qq);
+  GroupWs gw = group_carve(b, 2, pp, qq);
+  QView Qc = b.mat(m, cc, idt), Qr = b.mat(n, r, idt);
+  QView Xx = (idt == xdt) ? QView{} : b.mat(m, n, idt);
+  QView T = b.mat(m, r, adt), Tx = (idt == adt) ? T : b.mat(m, r, idt);
+  QView M = b.mat(cc, r, adt), Mx = (idt == adt) ? M : b.mat(cc, r, idt);
+  QView B1 = b.mat(m, r, adt), B1x = (idt == adt) ? B1 : b.mat(m, r, idt);
+  const int64_t tiles = (int64_t)std::max<size_t>(residual_tiles(m, n), 1);
+  double* pd = (double*)b.take((size_t)tiles * 8);
+  double* po = (double*)b.take((size_t)tiles * 8);
+  double* sums = (double*)b.take(16);
+  int64_t* ranks = (int64_t*)b.take(16);
+  const size_t gwb = std::max({gemm_workspace(m, r, n, a.compute), gemm_workspace(cc, r, m, a.compute),
+                              gemm_workspace(m, r, cc, a.compute)});
+  void* gws = b.take(gwb);
+  if (count_only) return QCUR_OK;
+  HIPCHK(launch_mask_init(c, a.Y, a.mask, a.mask_ld, a.X));
+  // the iterate of step t lives in cur; the next goes to nxt
+  QView cur = a.X, nxt = Xw;
+  const double orth_tol = a.compute == QCUR_F64 ? 0.0 : a.compute == QCUR_F32 ? 0x1p-26 : 0x1p-12;
+  int t = 0;
+  double rel = INFINITY;
+  while (t < a.max_iter) {
+    HIPCHK(launch_gather(c, cur, a.I, r, a.J, cc, &C, &R, nullptr));
+    QView Qv[2], Pv[2];
+    QView xs[2] = {C, R};
+    int64_t* ro[2] = {ranks, ranks + 1};
+    CHK(pinv_group_qp(c, 2, xs, a.rtol, a.max_rank, ro, gw, jw, Qv, Pv, orth_tol));
+    HIPCHK(launch_cast(c, Qv[0], Qc, CAST_COPY));
+    HIPCHK(launch_cast(c, Qv[1], Qr, CAST_COPY));
+    QView Xin = cur;
+    if (Xx.p) {
+      HIPCHK(launch_cast(c, cur, Xx, CAST_COPY));
+      Xin = Xx;
+    }
+    // M = Q_C^H (X^t Q_R);  B1 = Q_C M;  X^{t+1} = P_Omega(Y) + P_Omega^c(B1 Q_R^H)
+    HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Xin, Qr, 0.0, T, a.compute, gws, gwb));
+    if (Tx.p != T.p) HIPCHK(launch_cast(c, T, Tx, CAST_COPY));
+    HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, Qc, Tx, 0.0, M, a.compute, gws, gwb));
+    if (Mx.p != M.p) HIPCHK(launch_cast(c, M, Mx, CAST_COPY));
+    HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Qc, Mx, 0.0, B1, a.compute, gws, gwb));
+    if (B1x.p != B1.p) HIPCHK(launch_cast(c, B1, B1x, CAST_COPY));
+    HIPCHK(launch_merge_gemm(c, a.Y, a.mask, a.mask_ld, cur, B1x, Qr, QCUR_OP_H, a.compute, nxt, pd, po));
+    HIPCHK(launch_sum_partials(c, pd, tiles, sums, 0));
+    HIPCHK(launch_sum_partials(c, po, tiles, sums + 1, 0));
+    double h2[2] = {0.0, 0.0};
+    HIPCHK(hipMemcpyAsync(h2, sums, 16, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    rel = h2[1] > 0.0 ? std::sqrt(h2[0] / h2[1]) : (h2[0] > 0.0 ? INFINITY : 0.0);
+    std::swap(cur, nxt);
+    ++t;
+    if (rel <= a.tol) break;
+  }
+  if (cur.p != a.X.p) HIPCHK(launch_cast(c, cur, a.X, CAST_COPY));
+  if (a.iters) *a.iters = t;
+  if (a.rel) *a.rel = rel;
+  return QCUR_OK;
+}
+
 }  // namespace
 
 // ============================================================================
@@ -1967,6 +2056,65 @@ qcur_status qcur_solve_batched(qcur_handle h, int32_t count, const int32_t* dims
   if (tu && tu->measure && st == QCUR_OK) rec->tuned = true;
   if (tu) tu->measure = false;
   return st;
+}
+
+// ---- completion -----------------------------------------------------------------
+size_t qcur_complete_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int compute) {
+  if (m < 1 || n < 1 || c < 1 || r < 1 || (compute != QCUR_F64 && compute != QCUR_F32 && compute != QCUR_BF16))
+    return 0;
+  CompleteArgs a{};
+  a.Y = QView{nullptr, m, n, n, m * n, QCUR_F64};
+  a.X = QView{nullptr, m, n, n, m * n, acc_dt(compute)};
+  a.r = r;
+  a.cc = c;
+  a.compute = compute;
+  Bump b(nullptr);
+  Ctx dummy{0, nullptr, nullptr};
+  complete_run(dummy, a, b, true);
+  return b.used + 256;
+}
+
+qcur_status qcur_complete(qcur_handle h, const qcur_qmat* Y, const uint8_t* mask, int64_t mask_ld, const int64_t* I,
+                          int64_t r, const int64_t* J, int64_t c, int compute, double rtol, int64_t max_rank,
+                          int max_iter, double tol, qcur_qmat* X, int* iters, double* rel, void* ws,
+                          size_t ws_bytes) {
+  CHK(check_qmat(Y, "Y"));
+  CHK(check_qmat(X, "X"));
+  if (Y->rows < 1 || Y->cols < 1) return fail(QCUR_ERR_SHAPE, "Y must have at least one row and column");
+  CHK(check_dims(X, "X", Y->rows, Y->cols));
+  if (compute != QCUR_F64 && compute != QCUR_F32 && compute != QCUR_BF16)
+    return fail(QCUR_ERR_DTYPE, "unknown compute dtype");
+  if (X->dtype != acc_dt(compute)) return fail(QCUR_ERR_DTYPE, "X must be FP64 (F64 compute) or FP32");
+  if (!mask || mask_ld < Y->cols) return fail(QCUR_ERR_ARG, "mask is NULL or mask_ld < n");
+  if (!I || !J || r < 1 || c < 1 || r > Y->rows || c > Y->cols) return fail(QCUR_ERR_ARG, "bad index sets");
+  if (max_iter < 0) return fail(QCUR_ERR_ARG, "max_iter must be >= 0");
+  if (!std::isfinite(rtol) || !(tol >= 0.0)) return fail(QCUR_ERR_ARG, "rtol must be finite and tol >= 0");
+  if (max_rank < 0) return fail(QCUR_ERR_ARG, "max_rank must be >= 0");
+  CompleteArgs a{};
+  a.Y = view_of(*Y);
+  a.X = view_of(*X);
+  a.mask = mask;
+  a.mask_ld = mask_ld;
+  a.I = I;
+  a.J = J;
+  a.r = r;
+  a.cc = c;
+  a.compute = compute;
+  a.rtol = rtol;
+  a.max_rank = max_rank;
+  a.max_iter = max_iter;
+  a.tol = tol;
+  a.iters = iters;
+  a.rel = rel;
+  {
+    Bump sz(nullptr);
+    Ctx dummy{0, nullptr, nullptr};
+    complete_run(dummy, a, sz, true);
+    if (!ws || ws_bytes < sz.used + 256) return fail(QCUR_ERR_WORKSPACE, "completion needs %zu workspace bytes", sz.used + 256);
+  }
+  CHK(check_handle(h));
+  Bump b(ws);
+  return complete_run(h->c, a, b, false);
 }
 
 qcur_status qcur_cast(qcur_handle h, const qcur_qmat* X, qcur_qmat* Y) {

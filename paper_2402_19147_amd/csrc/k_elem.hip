@@ -462,4 +462,29 @@ hipError_t launch_backward_assemble(const Ctx& c, QView dA, QView G, int has_G, 
   return hipGetLastError();
 }
 
+// X = P_Omega(Y): observed entries copied (converted to X's dtype), the
+// others set to zero (the starting point of Algorithm 2).
+__global__ __launch_bounds__(256) void k_mask_init(const void* Y, int ydt, int64_t rows, int64_t cols, int64_t yld,
+                                                   int64_t yps, const uint8_t* __restrict__ mask, int64_t mask_ld,
+                                                   void* X, int xdt, int64_t xld, int64_t xps) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= cols) return;
+  for (int64_t i = blockIdx.y; i < rows; i += gridDim.y) {
+    const bool obs = mask[i * mask_ld + j] != 0;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const double v = obs ? load_as_double(Y, ydt, i * yld + j + p * yps) : 0.0;
+      store_from_double(X, xdt, i * xld + j + p * xps, v);
+    }
+  }
+}
+
+hipError_t launch_mask_init(const Ctx& c, QView Y, const uint8_t* mask, int64_t mask_ld, QView X) {
+  if (Y.rows == 0 || Y.cols == 0) return hipSuccess;
+  dim3 grid((unsigned)((Y.cols + 255) / 256), (unsigned)std::min<int64_t>(Y.rows, 65535));
+  hipLaunchKernelGGL(k_mask_init, grid, dim3(256), 0, c.stream, Y.p, Y.dt, Y.rows, Y.cols, Y.ld, Y.ps, mask,
+                     mask_ld, X.p, X.dt, X.ld, X.ps);
+  return hipGetLastError();
+}
+
 }  // namespace qcur

@@ -117,9 +117,14 @@ struct GemmArgs {
   int vec;
   // launch plan overrides (0: automatic)
   int force_tile, force_splits;
+  // merge epilogue (completion step): X0 = current iterate, partials2
+  const void* X0;
+  int x0dt;
+  int64_t x0ld, x0ps;
+  double* partials2;
 };
 
-enum { EPI_STORE = 0, EPI_PARTIAL = 1, EPI_RESID = 2 };
+enum { EPI_STORE = 0, EPI_PARTIAL = 1, EPI_RESID = 2, EPI_MERGE = 3 };
 
 // LDS layouts: [i][k] (A) and [j][k] (B), rows of BK + PAD elements.
 // f32/f64 (PAD 1, an odd row length in elements): the 16 lanes of an MFMA
@@ -159,7 +164,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
   const int64_t N = g.bN ? (int64_t)g.bN[b] : g.N;
   const int64_t K = g.bK ? (int64_t)g.bK[b] : g.K;
   if (bm >= M || bn >= N) {  // uniform over the workgroup
-    if (EPI == EPI_RESID && threadIdx.x == 0) g.partials[part_index] = 0.0;
+    if ((EPI == EPI_RESID || EPI == EPI_MERGE) && threadIdx.x == 0) g.partials[part_index] = 0.0;
+    if (EPI == EPI_MERGE && threadIdx.x == 0) g.partials2[part_index] = 0.0;
     return;
   }
   const In* __restrict__ Ag = (const In*)g.A + (int64_t)b * g.sA;
@@ -436,6 +442,47 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
     if (lane == 0) wpart[wave] = sq;
     __syncthreads();
     if (tid == 0) g.partials[part_index] = ((wpart[0] + wpart[1]) + wpart[2]) + wpart[3];
+  } else if constexpr (EPI == EPI_MERGE) {
+    // X1 = P_Omega(Y) + P_Omega^c(B) with B the product tile, written in the
+    // dtype of X1; per tile, sum |X1 - X0|^2 and |X0|^2 (FP64)
+    double sd = 0.0, so = 0.0;
+#pragma unroll
+    for (int x = 0; x < XB; ++x)
+#pragma unroll
+      for (int y = 0; y < YB; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t i = bm + wm + x * 16 + T::out_row(lane, r);
+          const int64_t j = bn + wn + y * 16 + (lane & 15);
+          if (i < M && j < N) {
+            const bool obs = g.mask[i * g.mask_ld + j] != 0;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+              const double xo = load_as_double(g.X0, g.x0dt, i * g.x0ld + j + p * g.x0ps);
+              const double xn = obs ? load_as_double(g.R0, g.r0dt, i * g.r0ld + j + p * g.r0ps)
+                                    : (double)acc[p][x][y][r];
+              store_from_double(g.E, g.edt, i * g.eld + j + p * g.eps, xn);
+              const double xs = load_as_double(g.E, g.edt, i * g.eld + j + p * g.eps);  // as stored
+              sd += (xs - xo) * (xs - xo);
+              so += xo * xo;
+            }
+          }
+        }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      sd += __shfl_xor(sd, o, 64);
+      so += __shfl_xor(so, o, 64);
+    }
+    __shared__ double wpart[2][4];
+    if (lane == 0) {
+      wpart[0][wave] = sd;
+      wpart[1][wave] = so;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      g.partials[part_index] = ((wpart[0][0] + wpart[0][1]) + wpart[0][2]) + wpart[0][3];
+      g.partials2[part_index] = ((wpart[1][0] + wpart[1][1]) + wpart[1][2]) + wpart[1][3];
+    }
   } else {
     typedef typename T::Acc Acc;
     Acc* Dg = (Acc*)g.D;
@@ -707,6 +754,43 @@ hipError_t launch_residual_gemm_batched(const Ctx& c, int count, Slots A, Slots 
       g.ktiles_per_split = (int)((kx + 31) / 32);
       if (t == 64) hipLaunchKernelGGL((k_qgemm<QCUR_BF16, EPI_RESID, 64, 64>), grid, dim3(NT), 0, c.stream, g);
       else hipLaunchKernelGGL((k_qgemm<QCUR_BF16, EPI_RESID, 32, 32>), grid, dim3(NT), 0, c.stream, g);
+  }
+  return hipGetLastError();
+}
+
+// Completion step: X1 = P_Omega(Y) + P_Omega^c(B1 op(R)), tile partials of
+// |X1 - X0|^2 into partials and of |X0|^2 into partials2 (64 x 64 tiles).
+hipError_t launch_merge_gemm(const Ctx& c, QView Y, const uint8_t* mask, int64_t mask_ld, QView X0, QView B1,
+                             QView R, int opR, int compute, QView X1, double* partials, double* partials2) {
+  GemmArgs g = {};
+  g.A = B1.p; g.lda = B1.ld; g.psa = B1.ps;
+  g.B = R.p; g.ldb = R.ld; g.psb = R.ps;
+  g.M = Y.rows; g.N = Y.cols; g.K = B1.cols;
+  g.opA = QCUR_OP_N; g.opB = opR;
+  g.alpha = 1.0; g.beta = 0.0;
+  g.R0 = Y.p; g.r0dt = Y.dt; g.r0ld = Y.ld; g.r0ps = Y.ps;
+  g.X0 = X0.p; g.x0dt = X0.dt; g.x0ld = X0.ld; g.x0ps = X0.ps;
+  g.E = X1.p; g.edt = X1.dt; g.eld = X1.ld; g.eps = X1.ps;
+  g.mask = mask; g.mask_ld = mask_ld;
+  g.partials = partials;
+  g.partials2 = partials2;
+  g.batch = 1;
+  g.splits = 1;
+  g.vec = compute == QCUR_BF16 && vec_ok(B1, 0) && vec_ok(R, 0);
+  if (g.M == 0 || g.N == 0) return hipSuccess;
+  dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64), 1);
+  switch (compute) {
+    case QCUR_F64:
+      g.ktiles_per_split = (int)((g.K + 15) / 16);
+      hipLaunchKernelGGL((k_qgemm<QCUR_F64, EPI_MERGE, 64, 64>), grid, dim3(NT), 0, c.stream, g);
+      break;
+    case QCUR_F32:
+      g.ktiles_per_split = (int)((g.K + 15) / 16);
+      hipLaunchKernelGGL((k_qgemm<QCUR_F32, EPI_MERGE, 64, 64>), grid, dim3(NT), 0, c.stream, g);
+      break;
+    default:
+      g.ktiles_per_split = (int)((g.K + 31) / 32);
+      hipLaunchKernelGGL((k_qgemm<QCUR_BF16, EPI_MERGE, 64, 64>), grid, dim3(NT), 0, c.stream, g);
   }
   return hipGetLastError();
 }

@@ -114,6 +114,13 @@ hipError_t launch_residual_gemm(const Ctx& c, QView A, QView B1, QView R, const 
                                 double e_scale, int opR = QCUR_OP_N);
 hipError_t launch_sum_partials(const Ctx& c, const double* partials, int64_t count, double* out,
                                int take_sqrt);
+// Completion step (Algorithm 2): X1 = P_Omega(Y) + P_Omega^c(B1 op(R)) with
+// per-tile sums of |X1 - X0|^2 (partials) and |X0|^2 (partials2), 64 x 64
+// tiles (residual_tiles(m, n) of each).
+hipError_t launch_merge_gemm(const Ctx& c, QView Y, const uint8_t* mask, int64_t mask_ld, QView X0, QView B1,
+                             QView R, int opR, int compute, QView X1, double* partials, double* partials2);
+// X = P_Omega(Y) (zeros where mask is 0), X in its own dtype.
+hipError_t launch_mask_init(const Ctx& c, QView Y, const uint8_t* mask, int64_t mask_ld, QView X);
 
 // Jacobi pseudoinverse pieces.
 hipError_t launch_jacobi_round(const Ctx& c, double* Y, int64_t p, int64_t q, double* V,

@@ -81,6 +81,9 @@ def _declare(L):
         "qcur_batch_workspace": (c_sz, [ctypes.c_int32, c_p, c_int, c_int, c_int, c_int, c_int]),
         "qcur_batch_prepare": (c_int, [c_p, ctypes.c_int32, c_p, c_int, c_int, c_int, c_int, c_int, c_p, c_sz]),
         "qcur_batch_plans": (c_int, [c_p, c_p, c_p, c_p, c_int]),
+        "qcur_complete": (c_int, [c_p, QP, c_p, c_i64, c_p, c_i64, c_p, c_i64, c_int, c_d, c_i64, c_int, c_d, QP,
+                                  c_p, c_p, c_p, c_sz]),
+        "qcur_complete_workspace": (c_sz, [c_i64, c_i64, c_i64, c_i64, c_int]),
         "qcur_solve_batched": (c_int, [c_p, ctypes.c_int32, c_p, QP, c_i64, c_int, c_int, c_u64, c_int, c_int, c_d,
                                        c_i64, c_p, c_p, QP, c_i64, c_p, c_p, c_p, c_p, c_p, c_sz]),
     }
@@ -432,3 +435,21 @@ def pack_batch(mats, dtype=torch.float32, device="cuda", slot=None) -> torch.Ten
         t = torch.as_tensor(a)
         out[b, :, : t.shape[1], : t.shape[2]] = t.to(dtype)
     return out.to(device)
+
+
+def complete(Y: torch.Tensor, mask: torch.Tensor, I: torch.Tensor, J: torch.Tensor, compute: int = F64,
+             rtol: float = -1.0, max_rank: int = 0, max_iter: int = 200, tol: float = 1e-4):
+    """Completion from the observed entries (Algorithm 2) with the fixed index
+    sets I, J.  Returns (X, iterations, last relative change)."""
+    _, m, n = Y.shape
+    if mask.dtype != torch.uint8 or tuple(mask.shape) != (m, n) or mask.stride(1) != 1:
+        raise ValueError("mask must be a row-major uint8 (m, n) tensor")
+    r, c = I.numel(), J.numel()
+    odt = torch.float64 if compute == F64 else torch.float32
+    X = empty(m, n, odt, Y.device)
+    ws = _ws(lib().qcur_complete_workspace(m, n, c, r, compute), Y.device)
+    iters, rel = ctypes.c_int(0), ctypes.c_double(0.0)
+    _check(lib().qcur_complete(_h(Y), _qp(Y), _ptr(mask), mask.stride(0), _ptr(I), r, _ptr(J), c, compute, rtol,
+                               max_rank, max_iter, tol, _qp(X), ctypes.byref(iters), ctypes.byref(rel), _ptr(ws),
+                               ws.numel()))
+    return X, iters.value, rel.value

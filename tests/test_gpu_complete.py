@@ -1,0 +1,92 @@
+"""Completion from partially observed entries (Algorithm 2) on the GPU
+against the checker's loop (MI355X only)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle.complete import complete as ref_complete
+from oracle.quat import qmul, fro2
+
+pytestmark = pytest.mark.gpu
+
+Q = pytest.importorskip("paper_2402_19147_amd.qcur")
+DEV = torch.device("cuda:0")
+
+
+def T(x, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(x), dtype=dtype, device=DEV)
+
+
+def N(t):
+    return t.detach().to(torch.float64).cpu().numpy()
+
+
+def problem(m, n, k, p_obs, c, seed, full_cross=False, noise=0.0):
+    L, Rt, E = workloads.lowrank_gaussian_factors(m, n, k, seed, noise)
+    A = qmul(L, Rt) + E
+    rng = np.random.default_rng(seed)
+    mask = (rng.random((m, n)) < p_obs).astype(np.uint8)
+    I = np.sort(rng.choice(m, c, replace=False)).astype(np.int64)
+    J = np.sort(rng.choice(n, c, replace=False)).astype(np.int64)
+    if full_cross:
+        mask[I, :] = 1
+        mask[:, J] = 1
+    Y = np.where(mask[None] == 1, A, rng.standard_normal(A.shape))
+    return A, Y, mask, I, J
+
+
+@pytest.fixture(autouse=True)
+def _status_clean():
+    Q.sync_status()
+    yield
+    Q.sync_status()
+
+
+@pytest.mark.parametrize("compute,tol", [(Q.F64, 1e-9), (Q.F32, 2e-4)])
+def test_fixed_steps_match_checker(compute, tol):
+    # 150 x 130 (several 64-tiles with ragged edges), rank 4, half observed
+    A, Y, mask, I, J = problem(150, 130, 4, 0.5, 12, seed=31, noise=1e-3)
+    dt = torch.float64 if compute == Q.F64 else torch.float32
+    Yg = T(Y, dt)
+    Yc = N(Yg)
+    X, iters, rel = Q.complete(Yg, T(mask, torch.uint8), T(I, torch.int64), T(J, torch.int64), compute=compute,
+                               max_iter=6, tol=0.0)
+    Q.sync_status()
+    ref = ref_complete(Yc, mask, I, J, max_iter=6, tol=0.0)
+    assert iters == 6
+    Xg = N(X)
+    assert np.sqrt(fro2(Xg - ref["X"]) / fro2(ref["X"])) < tol
+    assert abs(rel - ref["rel"]) <= tol * 10 * max(ref["rel"], 1e-300) + tol
+    # observed entries are the observations, bit for bit
+    keep = np.broadcast_to(mask[None] == 1, Y.shape)
+    assert np.array_equal(Xg[keep], Yc[keep])
+
+
+def test_exact_recovery_with_observed_cross():
+    A, Y, mask, I, J = problem(130, 110, 3, 0.25, 8, seed=32, full_cross=True)
+    X, iters, rel = Q.complete(T(Y), T(mask, torch.uint8), T(I, torch.int64), T(J, torch.int64), compute=Q.F64,
+                               max_iter=400, tol=1e-12)
+    Q.sync_status()
+    ref = ref_complete(Y, mask, I, J, max_iter=400, tol=1e-12)
+    assert rel <= 1e-12 and iters < 400
+    assert abs(iters - ref["iters"]) <= 1
+    assert np.sqrt(fro2(N(X) - A) / fro2(A)) < 1e-9
+
+
+def test_stopping_and_degenerate_cases():
+    A, Y, mask, I, J = problem(90, 70, 3, 0.4, 8, seed=33, full_cross=True)
+    X, iters, rel = Q.complete(T(Y), T(mask, torch.uint8), T(I, torch.int64), T(J, torch.int64), max_iter=200,
+                               tol=1e-4)
+    assert iters < 200 and rel <= 1e-4
+    # every entry observed: one step, X = Y
+    full = np.ones_like(mask)
+    X, iters, rel = Q.complete(T(A), T(full, torch.uint8), T(I, torch.int64), T(J, torch.int64), max_iter=50,
+                               tol=1e-4)
+    assert iters == 1 and rel == 0.0
+    assert np.array_equal(N(X), A)
+    # no step: the observed entries with zeros elsewhere
+    X, iters, rel = Q.complete(T(Y), T(mask, torch.uint8), T(I, torch.int64), T(J, torch.int64), max_iter=0)
+    assert iters == 0
+    assert np.array_equal(N(X), np.where(mask[None] == 1, Y, 0.0))
+    Q.sync_status()

@@ -145,4 +145,9 @@ WORKLOADS = {
                       noise=1e-3, sampling="length", core="car", seed=4),
     "adjoint_2048": dict(kind="product", m=2048, n=2048, k=64, noise=0.0, c=256, r=256,
                          sampling="fixed", core="wpinv", max_rank=64, mask_p=0.5, seed=5),
+    # completion (Algorithm 2): colour-image-shaped 512 x 768 (the size of the
+    # paper's completion test images), rank 20 + N(0, 0.01^2), 70% missing,
+    # c = r = ceil(20 ln 20) = 60 fixed uniform index sets, t_max 200, tol 1e-4
+    "complete_512x768": dict(kind="color", m=512, n=768, k=20, noise=0.01, c=60, r=60, mask_p=0.3,
+                             max_iter=200, tol=1e-4, seed=6),
 }
