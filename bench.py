@@ -329,8 +329,7 @@ def bench_complete(q, torch, workloads, dev):
         q.complete(Y, Mk, It, Jt, compute=comp, max_iter=2, tol=0.0)  # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        X, iters, rel = q.complete(Y, Mk, It, Jt, compute=comp, max_rank=k, max_iter=cfg["max_iter"],
-                                   tol=cfg["tol"])
+        X, iters, rel = q.complete(Y, Mk, It, Jt, compute=comp, max_iter=cfg["max_iter"], tol=cfg["tol"])
         torch.cuda.synchronize()
         dt_s = time.perf_counter() - t0
         q.sync_status()
