@@ -33,6 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOAD = "color_1024"
+T_AQR_F32_HBM_BYTES = 54.7e6
 
 
 def parse():
@@ -135,9 +136,15 @@ def main():
     flops = 32.0 * m * n * r
     peak = {q.F64: 78.6, q.F32: 157.3, q.BF16: 2500.0}[hd]
     achieved = flops / t_gemm / 1e12
+    # HBM bytes per GEMM of this kernel (FP32 split-K partials + reduction),
+    # FETCH_SIZE + WRITE_SIZE from rocprofv3 --pmc runs of this script scaled
+    # by a copy of known size (profiles/qgemm_f32_T_AQr_color_1024.md); only
+    # valid for the FP32 kernel as profiled
+    traffic = T_AQR_F32_HBM_BYTES if hd == q.F32 else None
     roofline = dict(bound="mfma", kernel=f"qgemm T = A Q_R ({m}x{n} . {n}x{r})", achieved=achieved, peak=peak,
-                    unit="TFLOP/s", frac=achieved / peak, traffic=None, avg_launch_us=t_gemm * 1e6,
-                    algorithmic_flop_per_launch=flops)
+                    unit="TFLOP/s", frac=achieved / peak, traffic=traffic, avg_launch_us=t_gemm * 1e6,
+                    algorithmic_flop_per_launch=flops, algorithmic_bytes_per_launch=4.0 * (m * n + n * r + m * r) *
+                    {q.F64: 8, q.F32: 4, q.BF16: 2}[hd])
 
     # quaternion GEMM rate at the dense shapes, every dtype
     qg = {}
