@@ -166,6 +166,7 @@ def main():
         extra["batch_512"] = bench_batch(q, torch, workloads, dev, args)
         extra["dense_4096"] = bench_dense(q, torch, workloads, dev, args)
         extra["complete_512x768"] = bench_complete(q, torch, workloads, dev)
+        extra["adjoint_2048"] = bench_adjoint(q, torch, workloads, dev, args)
     # a plain copy of known size, for scaling HBM byte counters of profiled runs
     src = torch.empty(64 * 2 ** 20, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
@@ -273,13 +274,7 @@ def bench_dense(q, torch, workloads, dev, args):
     Lt = torch.tensor(L, device=dev)
     Rtt = torch.tensor(Rt, device=dev)
     # A = L Rt (quaternion product, formed with torch matmuls) + E
-    sgn = {(0, 0): 1, (1, 1): -1, (2, 2): -1, (3, 3): -1, (1, 0): 1, (0, 1): 1, (3, 2): -1, (2, 3): 1,
-           (2, 0): 1, (3, 1): 1, (0, 2): 1, (1, 3): -1, (3, 0): 1, (2, 1): -1, (1, 2): 1, (0, 3): 1}
-    prod = {(0, 0): 0, (1, 1): 0, (2, 2): 0, (3, 3): 0, (1, 0): 1, (0, 1): 1, (3, 2): 1, (2, 3): 1,
-            (2, 0): 2, (3, 1): 2, (0, 2): 2, (1, 3): 2, (3, 0): 3, (2, 1): 3, (1, 2): 3, (0, 3): 3}
-    A64 = torch.tensor(E, device=dev)
-    for (a, b), d in prod.items():
-        A64[d] += sgn[(a, b)] * (Lt[a] @ Rtt[b])
+    A64 = quaternion_product_torch(torch, Lt, Rtt) + torch.tensor(E, device=dev)
     del Lt, Rtt
     A32 = A64.to(torch.float32)
     m, n, c, r, seed = cfg["m"], cfg["n"], cfg["c"], cfg["r"], cfg["seed"]
@@ -308,6 +303,54 @@ def bench_dense(q, torch, workloads, dev, args):
                                                 torch.linalg.vector_norm(Bs["plain_f64"]))
         out[f"speedup_{name}_vs_plain_f64"] = out[name]["solves_per_s"] / out["plain_f64"]["solves_per_s"]
     q.sync_status()
+    return out
+
+
+def quaternion_product_torch(torch, L, Rt):
+    """A = L Rt with the sixteen plane products of the Hamilton table
+    (input generation for the benchmark only)."""
+    terms = {(0, 0, 0, 1), (1, 1, 0, -1), (2, 2, 0, -1), (3, 3, 0, -1), (1, 0, 1, 1), (0, 1, 1, 1), (3, 2, 1, -1),
+             (2, 3, 1, 1), (2, 0, 2, 1), (3, 1, 2, 1), (0, 2, 2, 1), (1, 3, 2, -1), (3, 0, 3, 1), (2, 1, 3, -1),
+             (1, 2, 3, 1), (0, 3, 3, 1)}
+    out = torch.zeros((4, L.shape[1], Rt.shape[2]), dtype=L.dtype, device=L.device)
+    for a, b, d, sg in terms:
+        out[d] += sg * (L[a] @ Rt[b])
+    return out
+
+
+def bench_adjoint(q, torch, workloads, dev, args):
+    """Masked CUR loss and its gradient through the adjoint kernels at
+    2048 x 2048 (rank-64 N(0,1) factors, c = r = 256 fixed index sets,
+    U = W^+ capped at rank 64, Bernoulli(0.5) mask): one forward + backward."""
+    cfg = workloads.WORKLOADS["adjoint_2048"]
+    m, k, c = cfg["m"], cfg["k"], cfg["c"]
+    L, Rt, _ = workloads.lowrank_gaussian_factors(m, m, k, cfg["seed"])
+    A64 = quaternion_product_torch(torch, torch.tensor(L, device=dev), torch.tensor(Rt, device=dev))
+    I = torch.tensor(workloads.uniform_index_set(m, c, cfg["seed"], 0), device=dev)
+    J = torch.tensor(workloads.uniform_index_set(m, c, cfg["seed"], 1), device=dev)
+    mask = torch.tensor(workloads.bernoulli_mask(m, m, cfg["mask_p"], cfg["seed"]), device=dev)
+    out = {"workload": "2048x2048 quaternion, rank-64 N(0,1) factors, c=r=256 fixed uniform index sets, U=W^+ "
+                       "(max_rank 64), Bernoulli(0.5) mask, loss ||P_Omega(A - CUR(A))||_F^2, forward + backward"}
+    for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        A = A64.to(dt)
+
+        def step():
+            At = A.detach().requires_grad_(True)
+            loss = q.cur_loss(At, I, J, mask, max_rank=cfg["max_rank"])
+            loss.backward()
+            return At.grad
+
+        step()
+        torch.cuda.synchronize()
+        reps = max(2, args.steps // 2)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            step()
+        torch.cuda.synchronize()
+        dt_s = (time.perf_counter() - t0) / reps
+        q.sync_status()
+        out[name] = dict(ms_per_step=dt_s * 1e3, steps_per_s=1.0 / dt_s)
+        log(f"adjoint {name}: {dt_s * 1e3:.2f} ms per forward+backward")
     return out
 
 

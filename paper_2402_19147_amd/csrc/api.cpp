@@ -233,7 +233,10 @@ BatchSpec same_stride(int nb, int64_t s) {
 qcur_status chol_inv(const Ctx& c, GroupWs& w, double* P) {
   const int64_t n = w.qq, nb = CHOL_BLOCK;
   const int64_t slab = 4 * n * n;
-  const BatchSpec bs = same_stride(w.nb, slab);
+  BatchSpec bs = same_stride(w.nb, slab);
+  BatchSpec bs_up = bs, bs_low = bs;
+  bs_up.tri = TRI_B_UPPER;     // op(B) = P_kk^H
+  bs_low.tri = TRI_LOWER_OUT;  // the trailing Gram block: lower triangle only
   double *G = w.G, *L = w.L;
   HIPCHK(launch_zero(c, P, w.nb * slab));
   for (int64_t kb = 0; kb < n; kb += nb) {
@@ -243,18 +246,20 @@ qcur_status chol_inv(const Ctx& c, GroupWs& w, double* P) {
     if (rest > 0) {
       QView L21 = sq_view(L, n, kb + wd, kb, rest, wd);
       HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_H, 1.0, sq_view(G, n, kb + wd, kb, rest, wd),
-                                 sq_view(P, n, kb, kb, wd, wd), 0.0, L21, QCUR_F64, w.gws, w.gws_bytes, bs));
+                                 sq_view(P, n, kb, kb, wd, wd), 0.0, L21, QCUR_F64, w.gws, w.gws_bytes, bs_up));
       HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_H, -1.0, L21, L21, 1.0,
-                                 sq_view(G, n, kb + wd, kb + wd, rest, rest), QCUR_F64, w.gws, w.gws_bytes, bs));
+                                 sq_view(G, n, kb + wd, kb + wd, rest, rest), QCUR_F64, w.gws, w.gws_bytes, bs_low));
     }
   }
-  const BatchSpec bsS{w.nb, slab, slab, 4 * nb * n};
+  BatchSpec bsS{w.nb, slab, slab, 4 * nb * n};
+  bsS.tri = TRI_B_LOWER;  // op(B) = P[0:kb, 0:kb], lower triangular
   for (int64_t kb = nb; kb < n; kb += nb) {
     const int64_t wd = std::min(nb, n - kb);
     QView Sv{w.S, wd, kb, kb, wd * kb, QCUR_F64};
     HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_N, 1.0, sq_view(L, n, kb, 0, wd, kb), sq_view(P, n, 0, 0, kb, kb),
                                0.0, Sv, QCUR_F64, w.gws, w.gws_bytes, bsS));
-    const BatchSpec bsP{w.nb, slab, 4 * nb * n, slab};
+    BatchSpec bsP{w.nb, slab, 4 * nb * n, slab};
+    bsP.tri = TRI_A_LOWER;  // op(A) = P_kk, lower triangular
     HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_N, -1.0, sq_view(P, n, kb, kb, wd, wd), Sv, 0.0,
                                sq_view(P, n, kb, 0, wd, kb), QCUR_F64, w.gws, w.gws_bytes, bsP));
   }
@@ -294,11 +299,12 @@ qcur_status pinv_fast_group(const Ctx& c, int nb, const QView* X, double rtol, i
   }
   HIPCHK(launch_sumsq_batch(c, nb, Zr, w.part, w.norms + 0, 4));
   const BatchSpec bz = same_stride(nb, zslab);
-  BatchSpec bzg;
+  BatchSpec bzg;  // Gram matrices: lower triangle only (all the Cholesky reads)
   bzg.count = nb;
   bzg.sA = zslab;
   bzg.sB = zslab;
   bzg.sD = gslab;
+  bzg.tri = TRI_LOWER_OUT;
   QView Z{w.Z, pp, qq, qq, pp * qq, QCUR_F64};
   QView Q1{w.Q1, pp, qq, qq, pp * qq, QCUR_F64};
   QView Q{w.Q, pp, qq, qq, pp * qq, QCUR_F64};
@@ -306,12 +312,14 @@ qcur_status pinv_fast_group(const Ctx& c, int nb, const QView* X, double rtol, i
   QView P1{w.P1, qq, qq, qq, qq * qq, QCUR_F64};
   QView P2{w.P2, qq, qq, qq, qq * qq, QCUR_F64};
   QView P{w.P, qq, qq, qq, qq * qq, QCUR_F64};
-  BatchSpec bzp;  // (pp x qq) . (qq x qq)^H -> pp x qq
+  BatchSpec bzp;  // (pp x qq) . (qq x qq)^H -> pp x qq, op(B) = P^H upper triangular
   bzp.count = nb;
   bzp.sA = zslab;
   bzp.sB = gslab;
   bzp.sD = zslab;
-  const BatchSpec bg = same_stride(nb, gslab);
+  bzp.tri = TRI_B_UPPER;
+  BatchSpec bg = same_stride(nb, gslab);  // P2 P1: both lower triangular
+  bg.tri = TRI_A_LOWER | TRI_B_LOWER;
   // pass 1: G = Z^H Z = L1 L1^H, P1 = L1^{-1}, Q1 = Z L1^{-H}
   HIPCHK(launch_gemm_batched(c, QCUR_OP_H, QCUR_OP_N, 1.0, Z, Z, 0.0, G, QCUR_F64, w.gws, w.gws_bytes, bzg));
   if (padded) HIPCHK(launch_pad_identity(c, w.G, qq, gslab, nb, qb));
@@ -371,10 +379,13 @@ qcur_status pinv_fast_group(const Ctx& c, int nb, const QView* X, double rtol, i
     }
     QView Pv{Pf + b * gslab, qb[b], qb[b], qq, qq * qq, QCUR_F64};
     QView Qv{Qf + b * zslab, pb[b], qb[b], qq, pp * qq, QCUR_F64};
+    BatchSpec one;
     if (tall[b]) {
-      HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_H, 1.0, Pv, Qv, 0.0, Xp[b], QCUR_F64, w.gws, w.gws_bytes));
+      one.tri = TRI_A_UPPER;  // op(A) = P^H
+      HIPCHK(launch_gemm_batched(c, QCUR_OP_H, QCUR_OP_H, 1.0, Pv, Qv, 0.0, Xp[b], QCUR_F64, w.gws, w.gws_bytes, one));
     } else {
-      HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Qv, Pv, 0.0, Xp[b], QCUR_F64, w.gws, w.gws_bytes));
+      one.tri = TRI_B_LOWER;  // op(B) = P
+      HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_N, 1.0, Qv, Pv, 0.0, Xp[b], QCUR_F64, w.gws, w.gws_bytes, one));
     }
     done[b] = true;
   }
@@ -1110,8 +1121,9 @@ struct BatchArgs {
 };
 
 BatchSpec bspec(int count, const Slots& A, const Slots& B, const Slots& D, const int* M, const int* N,
-                const int* K) {
+                const int* K, int tri = 0) {
   BatchSpec bs;
+  bs.tri = tri;
   bs.count = count;
   bs.sA = A.slab;
   bs.sB = B.slab;
@@ -1233,9 +1245,9 @@ qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, Bat
   HIPCHK(launch_zero_i32(c, w.fail, n2));
   // G = Z^H Z:  C_b^H C_b  and  R_b R_b^H
   CHK(stage(BS_GRAM_C, QCUR_OP_H, QCUR_OP_N, 1.0, slot_view(w.C64, mx, cx), slot_view(w.C64, mx, cx), 0.0,
-                             slot_view(G, cx, cx), QCUR_F64, bspec(n, w.C64, w.C64, G, w.dc, w.dc, w.dm)));
+                             slot_view(G, cx, cx), QCUR_F64, bspec(n, w.C64, w.C64, G, w.dc, w.dc, w.dm, TRI_LOWER_OUT)));
   CHK(stage(BS_GRAM_R, QCUR_OP_N, QCUR_OP_H, 1.0, slot_view(w.R64, rx, nx), slot_view(w.R64, rx, nx), 0.0,
-                             slot_view(half(G), rx, rx), QCUR_F64, bspec(n, w.R64, w.R64, G, w.dr, w.dr, w.dn)));
+                             slot_view(half(G), rx, rx), QCUR_F64, bspec(n, w.R64, w.R64, G, w.dr, w.dr, w.dn, TRI_LOWER_OUT)));
   HIPCHK(launch_pad_gram_batch(c, n2, w.G, qx, G.slab, w.zq));
   CHK(chol_inv(c, gw, w.P1));
   HIPCHK(launch_sumsq_ragged(c, n, w.C64, w.dm, w.dc, w.norms, 4));
@@ -1247,21 +1259,21 @@ qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, Bat
   const bool two = true;
   const Slots Q1 = two ? sl(w.Q1, px, qx, qx) : Q;
   CHK(stage(BS_Q1_C, QCUR_OP_N, QCUR_OP_H, 1.0, slot_view(w.C64, mx, cx), slot_view(P1, cx, cx), 0.0,
-                             slot_view(Q1, mx, cx), QCUR_F64, bspec(n, w.C64, P1, Q1, w.dm, w.dc, w.dc)));
+                             slot_view(Q1, mx, cx), QCUR_F64, bspec(n, w.C64, P1, Q1, w.dm, w.dc, w.dc, TRI_B_UPPER)));
   CHK(stage(BS_Q1_R, QCUR_OP_H, QCUR_OP_H, 1.0, slot_view(w.R64, rx, nx), slot_view(half(P1), rx, rx),
-                             0.0, slot_view(half(Q1), nx, rx), QCUR_F64, bspec(n, w.R64, P1, Q1, w.dn, w.dr, w.dr)));
+                             0.0, slot_view(half(Q1), nx, rx), QCUR_F64, bspec(n, w.R64, P1, Q1, w.dn, w.dr, w.dr, TRI_B_UPPER)));
   Slots Pf = P1;
   if (two) {
     // CholeskyQR2: Q1^H Q1 = L2 L2^H, P = P2 P1, Q = Q1 P2^H
     const Slots P2 = sl(w.P2, qx, qx, qx), P = sl(w.P, qx, qx, qx);
     CHK(stage(BS_G2, QCUR_OP_H, QCUR_OP_N, 1.0, slot_view(Q1, px, qx), slot_view(Q1, px, qx), 0.0,
-                               slot_view(G, qx, qx), QCUR_F64, bspec(n2, Q1, Q1, G, w.zq, w.zq, w.zp)));
+                               slot_view(G, qx, qx), QCUR_F64, bspec(n2, Q1, Q1, G, w.zq, w.zq, w.zp, TRI_LOWER_OUT)));
     HIPCHK(launch_pad_gram_batch(c, n2, w.G, qx, G.slab, w.zq));
     CHK(chol_inv(c, gw, w.P2));
     CHK(stage(BS_P, QCUR_OP_N, QCUR_OP_N, 1.0, slot_view(P2, qx, qx), slot_view(P1, qx, qx), 0.0,
-                               slot_view(P, qx, qx), QCUR_F64, bspec(n2, P2, P1, P, w.zq, w.zq, w.zq)));
+                               slot_view(P, qx, qx), QCUR_F64, bspec(n2, P2, P1, P, w.zq, w.zq, w.zq, TRI_A_LOWER | TRI_B_LOWER)));
     CHK(stage(BS_Q, QCUR_OP_N, QCUR_OP_H, 1.0, slot_view(Q1, px, qx), slot_view(P2, qx, qx), 0.0,
-                               slot_view(Q, px, qx), QCUR_F64, bspec(n2, Q1, P2, Q, w.zp, w.zq, w.zq)));
+                               slot_view(Q, px, qx), QCUR_F64, bspec(n2, Q1, P2, Q, w.zp, w.zq, w.zq, TRI_B_UPPER)));
     Pf = P;
   }
   HIPCHK(launch_sumsq_ragged(c, n2, Pf, w.zq, w.zq, w.norms + 2, 4));

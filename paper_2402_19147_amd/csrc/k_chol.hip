@@ -456,8 +456,8 @@ hipError_t launch_zero_i32(const Ctx& c, int* p, int64_t n) {
 }
 
 // ||G_b - I||_F^2 over the leading q_b x q_b block of up to MAXB Gram
-// matrices (n x n, sbatch apart): the orthogonality defect of Q after a
-// CholeskyQR pass (G = Q^H Q).  Grid (SUMSQ_BLOCKS, nb) of partial sums,
+// matrices (n x n, sbatch apart, lower triangle valid): the orthogonality
+// defect of Q after a CholeskyQR pass (G = Q^H Q).  Grid (SUMSQ_BLOCKS, nb) of partial sums,
 // then the fixed-order fold of the sums of squares.
 struct DefectBatch {
   int q[MAXB];
@@ -469,11 +469,15 @@ __global__ __launch_bounds__(256) void k_defect(const double* __restrict__ G, in
   const int64_t q = db.q[b], nn = n * n;
   const double* g = G + (int64_t)b * sbatch;
   double s = 0.0;
+  // G is Hermitian and only its lower triangle is formed: off-diagonal
+  // entries count twice
   for (int64_t e = (int64_t)blockIdx.x * 256 + tid; e < q * q; e += (int64_t)gridDim.x * 256) {
     const int64_t i = e / q, j = e % q;
+    if (j > i) continue;
     const int64_t o = i * n + j;
     const double d0 = g[o] - (i == j ? 1.0 : 0.0);
-    s += d0 * d0 + g[o + nn] * g[o + nn] + g[o + 2 * nn] * g[o + 2 * nn] + g[o + 3 * nn] * g[o + 3 * nn];
+    const double v = d0 * d0 + g[o + nn] * g[o + nn] + g[o + 2 * nn] * g[o + 2 * nn] + g[o + 3 * nn] * g[o + 3 * nn];
+    s += (i == j) ? v : 2.0 * v;
   }
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);

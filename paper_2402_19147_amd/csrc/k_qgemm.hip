@@ -117,6 +117,8 @@ struct GemmArgs {
   int vec;
   // launch plan overrides (0: automatic)
   int force_tile, force_splits;
+  // triangular structure of op(A), op(B) and of the wanted output (TRI_*)
+  int tri;
   // merge epilogue (completion step): X0 = current iterate, partials2
   const void* X0;
   int x0dt;
@@ -172,8 +174,22 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
   const In* __restrict__ Bg = (const In*)g.B + (int64_t)b * g.sB;
 
   const int64_t ktiles = (K + BK - 1) / BK;
-  const int64_t kt0 = (int64_t)split * g.ktiles_per_split;
-  const int64_t kt1 = min(ktiles, kt0 + g.ktiles_per_split);
+  int64_t kt0 = (int64_t)split * g.ktiles_per_split;
+  int64_t kt1 = min(ktiles, kt0 + g.ktiles_per_split);
+  if (g.tri) {
+    // triangular operands: only the K steps that can meet nonzeros (an
+    // empty range leaves an exact zero tile)
+    if (g.tri & TRI_A_LOWER) kt1 = min(kt1, (bm + BM + BK - 1) / BK);
+    if (g.tri & TRI_A_UPPER) kt0 = max(kt0, bm / BK);
+    if (g.tri & TRI_B_UPPER) kt1 = min(kt1, (bn + BN + BK - 1) / BK);
+    if (g.tri & TRI_B_LOWER) kt0 = max(kt0, bn / BK);
+    // lower triangle wanted only: tiles wholly above the diagonal are left
+    // alone (split-K partials still write their zero tile)
+    if ((g.tri & TRI_LOWER_OUT) && bm + BM <= bn) {
+      if (EPI != EPI_PARTIAL) return;
+      kt1 = kt0;
+    }
+  }
 
   In ra[4][EA], rb[4][EB];
 
@@ -653,6 +669,7 @@ hipError_t launch_gemm_batched(const Ctx& c, int opA, int opB, double alpha, QVi
   g.bN = bs.N;
   g.bK = bs.K;
   g.force_tile = bs.tile;
+  g.tri = bs.tri;
   g.force_splits = bs.splits;
   g.A = A.p; g.lda = A.ld; g.psa = A.ps;
   g.B = B.p; g.ldb = B.ld; g.psb = B.ps;

@@ -98,7 +98,12 @@ struct BatchSpec {
   const int* K = nullptr;
   int tile = 0;    // launch plan override: tile edge 32 or 64 (0: automatic)
   int splits = 0;  // K slices (0: automatic; reduced to 1 without enough workspace)
+  int tri = 0;     // TRI_* flags: zero triangles of op(A), op(B), lower output only
 };
+// op(A) / op(B) lower or upper triangular (exact zeros elsewhere): K steps
+// that meet only zeros are skipped.  TRI_LOWER_OUT: only the lower triangle
+// of D is wanted; tiles wholly above the diagonal are not written.
+enum { TRI_LOWER_OUT = 1, TRI_A_LOWER = 2, TRI_A_UPPER = 4, TRI_B_LOWER = 8, TRI_B_UPPER = 16 };
 size_t gemm_workspace(int64_t M, int64_t N, int64_t K, int compute, int batch = 1);
 // Workspace for any plan with at most max_splits K slices.
 size_t gemm_workspace_splits(int64_t M, int64_t N, int compute, int batch, int max_splits);
