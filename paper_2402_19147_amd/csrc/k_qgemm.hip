@@ -14,8 +14,9 @@
 // Tiles: a 256-thread workgroup owns a 64 x 64 quaternion output tile (four
 // real 64 x 64 planes); each of its four waves owns 32 x 32 (2 x 2 MFMA
 // 16x16 blocks per plane).  MFMA shapes: f64 16x16x4, f32 16x16x4,
-// bf16 16x16x32 (FP32 accumulation).  K is staged through LDS in slices of
-// 16 (f32/f64) or 32 (bf16) with the next slice prefetched into registers.
+// bf16 16x16x32 (FP32 accumulation).  K is staged through two LDS buffers
+// in slices of 16 (f32/f64) or 32 (bf16): the MFMAs of one slice overlap the
+// store of the next and the global loads of the one after.
 //
 // Epilogues: (a) store alpha*acc + beta*D, or a split-K partial;
 // (b) residual: subtract the tile of A, apply the mask, square and reduce
@@ -140,8 +141,8 @@ template <int DT, int BM, int BN> struct alignas(16) Smem {
   static constexpr bool KMAJ = false;
   static constexpr int AR = KMAJ ? BK : BM, AC = KMAJ ? BM + PAD : BK + PAD;
   static constexpr int BR = KMAJ ? BK : BN, BC = KMAJ ? BN + PAD : BK + PAD;
-  In a[4][AR][AC];
-  In b[4][BR][BC];
+  In a[2][4][AR][AC];  // two stages: one is read by the MFMAs while the
+  In b[2][4][BR][BC];  // next K slice is stored into the other
 };
 
 template <int DT, int EPI, int BM, int BN>
@@ -205,9 +206,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
       const int64_t off = (g.opA == QCUR_OP_N) ? gi * g.lda + gk : gk * g.lda + gi;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        In v = ok ? Ag[off + q * g.psa] : (In)0;
-        if (g.opA == QCUR_OP_H && q > 0) v = negv<In>(v);
-        ra[q][r] = v;
+        ra[q][r] = ok ? Ag[off + q * g.psa] : (In)0;
       }
     }
 #pragma unroll
@@ -220,13 +219,11 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
       const int64_t off = (g.opB == QCUR_OP_N) ? gk * g.ldb + gj : gj * g.ldb + gk;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        In v = ok ? Bg[off + q * g.psb] : (In)0;
-        if (g.opB == QCUR_OP_H && q > 0) v = negv<In>(v);
-        rb[q][r] = v;
+        rb[q][r] = ok ? Bg[off + q * g.psb] : (In)0;
       }
     }
   };
-  auto store_tiles = [&]() {
+  auto store_tiles = [&](int st) {
 #pragma unroll
     for (int r = 0; r < EA; ++r) {
       const int e = tid + NT * r;
@@ -234,7 +231,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
       if (g.opA == QCUR_OP_N) { i = e / BK; k = e % BK; } else { i = e % BM; k = e / BM; }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        if (KMAJ) sm.a[q][k][i] = ra[q][r]; else sm.a[q][i][k] = ra[q][r];
+        // conjugation (op H) is applied here, not at the load, so that the
+        // loads stay in flight through the MFMAs of the current slice
+        const In v = (g.opA == QCUR_OP_H && q > 0) ? negv<In>(ra[q][r]) : ra[q][r];
+        if (KMAJ) sm.a[st][q][k][i] = v; else sm.a[st][q][i][k] = v;
       }
     }
 #pragma unroll
@@ -244,7 +244,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
       if (g.opB == QCUR_OP_N) { k = e / BN; j = e % BN; } else { k = e % BK; j = e / BK; }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        if (KMAJ) sm.b[q][k][j] = rb[q][r]; else sm.b[q][j][k] = rb[q][r];
+        const In v = (g.opB == QCUR_OP_H && q > 0) ? negv<In>(rb[q][r]) : rb[q][r];
+        if (KMAJ) sm.b[st][q][k][j] = v; else sm.b[st][q][j][k] = v;
       }
     }
   };
@@ -257,125 +258,145 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
 #pragma unroll
       for (int y = 0; y < YB; ++y) acc[p][x][y] = (AccV){0, 0, 0, 0};
 
-  // BF16 with aligned operands: each thread moves whole 8-element vectors
-  // along the contiguous dimension of each operand (one 16-byte load per
-  // plane); operands stored along the other dimension are transposed into
-  // LDS with 2-byte stores.  Vectors that cross a matrix edge fall back to
-  // element loads.
-  constexpr int VA = (DT == QCUR_BF16) ? (BM * BK / 8 + NT - 1) / NT : 1;
-  constexpr int VB = (DT == QCUR_BF16) ? (BN * BK / 8 + NT - 1) / NT : 1;
-  u32x4 va[4][VA], vb[4][VB];
-  // vector v of A: contiguous in k (op N: row i, k = kv..kv+7) or in i (op H)
+  // BF16 operands.  One stored contiguous in k (A op N, B op H) moves as
+  // whole 8-element vectors, one 16-byte load per plane and thread, stored
+  // unchanged.  An operand stored contiguous in i or j (A op
+  // H, B op N) is moved in 4 (k) x 8 (i or j) blocks, one plane per wave:
+  // a lane loads four 16-byte rows, transposes them in registers and writes
+  // eight 8-byte k-runs into the [i][k] / [j][k] layout.  Vectors or blocks
+  // that cross a matrix edge, or operands without that alignment, fall back
+  // to element loads.
+  // NV: 16-byte vectors per plane and thread (k-contiguous) = 4 x 8 blocks
+  // per lane (x-contiguous)
+  static_assert(BM == BN, "square tiles");
+  constexpr int NV = (DT == QCUR_BF16) ? (BM * BK / 8 + NT - 1) / NT : 1;
+  u32x4 va[4 * NV], vb[4 * NV];
+  constexpr uint32_t SIGN2 = 0x80008000u;
+  const bool aligned = g.vec != 0;
+  // k-contiguous operand: vector v of plane q holds X[x][k..k+7]
+  auto kvec_load = [&](const uint16_t* __restrict__ Xg, int64_t ld, int64_t ps, int64_t x0, int64_t X, int BX,
+                       int64_t kbase, int64_t K, u32x4* out) {
+#pragma unroll
+    for (int r = 0; r < NV; ++r) {
+      const int v = tid + NT * r;
+      if (v >= BX * BK / 8) break;
+      const int x = v / (BK / 8), k = (v % (BK / 8)) * 8;
+      const int64_t gx = x0 + x, gk = kbase + k;
+      const int64_t off = gx * ld + gk;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        u32x4 w = (u32x4){0, 0, 0, 0};
+        if (aligned && gx < X && gk + 7 < K) {
+          w = *(const u32x4*)(Xg + off + q * ps);
+        } else if (gx < X) {
+          uint16_t e[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) e[t] = (gk + t < K) ? Xg[off + t + q * ps] : (uint16_t)0;
+          w = __builtin_bit_cast(u32x4, e);
+        }
+        out[4 * r + q] = w;
+      }
+    }
+  };
+  auto kvec_store = [&](In (*dst)[BK + T::PAD], int BX, const u32x4* in, bool conj, int plane_stride_rows) {
+#pragma unroll
+    for (int r = 0; r < NV; ++r) {
+      const int v = tid + NT * r;
+      if (v >= BX * BK / 8) break;
+      const int x = v / (BK / 8), k = (v % (BK / 8)) * 8;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        u32x4 w = in[4 * r + q];
+        if (conj && q > 0) w ^= (u32x4){SIGN2, SIGN2, SIGN2, SIGN2};
+        *(u32x4*)&dst[q * plane_stride_rows + x][k] = w;
+      }
+    }
+  };
+  // x-contiguous operand: lane l of wave q takes rows k0..k0+3 of X[k][x0..x0+7]
+  auto xblk_load = [&](const uint16_t* __restrict__ Xg, int64_t ld, int64_t ps, int64_t xbase, int64_t X, int BX,
+                       int64_t kbase, int64_t K, u32x4* out) {
+    const int xbl = BX / 8;
+    const uint16_t* base = Xg + wave * ps;
+#pragma unroll
+    for (int n = 0; n < NV; ++n) {
+      const int blk = lane + 64 * n;
+      if (blk >= (BK / 4) * xbl) break;
+      const int x0 = (blk % xbl) * 8, k0 = (blk / xbl) * 4;
+      const int64_t gx = xbase + x0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gk = kbase + k0 + r;
+        const int64_t off = gk * ld + gx;
+        u32x4 w = (u32x4){0, 0, 0, 0};
+        if (aligned && gk < K && gx + 7 < X) {
+          w = *(const u32x4*)(base + off);
+        } else if (gk < K) {
+          uint16_t e[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) e[t] = (gx + t < X) ? base[off + t] : (uint16_t)0;
+          w = __builtin_bit_cast(u32x4, e);
+        }
+        out[4 * n + r] = w;
+      }
+    }
+  };
+  auto xblk_store = [&](In (*dst)[BK + T::PAD], int BX, const u32x4* in, bool conj, int plane_stride_rows) {
+    const int xbl = BX / 8;
+    const uint32_t flip = (conj && wave > 0) ? SIGN2 : 0u;
+#pragma unroll
+    for (int n = 0; n < NV; ++n) {
+    const int blk = lane + 64 * n;
+    if (blk >= (BK / 4) * xbl) break;
+    const int x0 = (blk % xbl) * 8, k0 = (blk / xbl) * 4;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const uint32_t r0 = in[4 * n][d], r1 = in[4 * n + 1][d], r2 = in[4 * n + 2][d], r3 = in[4 * n + 3][d];
+      // element 2d (low halves) and 2d+1 (high halves) of the four k rows
+      const uint32_t lo0 = ((r0 & 0xFFFFu) | (r1 << 16)) ^ flip, hi0 = ((r2 & 0xFFFFu) | (r3 << 16)) ^ flip;
+      const uint32_t lo1 = ((r0 >> 16) | (r1 & 0xFFFF0000u)) ^ flip, hi1 = ((r2 >> 16) | (r3 & 0xFFFF0000u)) ^ flip;
+      typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+      *(u32x2*)&dst[wave * plane_stride_rows + x0 + 2 * d][k0] = (u32x2){lo0, hi0};
+      *(u32x2*)&dst[wave * plane_stride_rows + x0 + 2 * d + 1][k0] = (u32x2){lo1, hi1};
+    }
+    }
+  };
   auto vec_load = [&](int64_t kt) {
     if constexpr (DT == QCUR_BF16) {
-    const int64_t k0 = kt * BK;
-#pragma unroll
-    for (int r = 0; r < VA; ++r) {
-      const int v = tid + NT * r;
-      if (v >= BM * BK / 8) break;
-      int i, k;
-      if (g.opA == QCUR_OP_N) { i = v / (BK / 8); k = (v % (BK / 8)) * 8; } else { k = v / (BM / 8); i = (v % (BM / 8)) * 8; }
-      const int64_t gi = bm + i, gk = k0 + k;
-      const bool full = (g.opA == QCUR_OP_N) ? (gi < M && gk + 7 < K) : (gk < K && gi + 7 < M);
-      const int64_t off = (g.opA == QCUR_OP_N) ? gi * g.lda + gk : gk * g.lda + gi;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        u32x4 w;
-        if (full) {
-          w = *(const u32x4*)(Ag + off + q * g.psa);
-        } else {
-          uint16_t e[8];
-#pragma unroll
-          for (int t = 0; t < 8; ++t) {
-            const bool ok = (g.opA == QCUR_OP_N) ? (gi < M && gk + t < K) : (gk < K && gi + t < M);
-            e[t] = ok ? Ag[off + t + q * g.psa] : (uint16_t)0;
-          }
-          w = __builtin_bit_cast(u32x4, e);
-        }
-        if (g.opA == QCUR_OP_H && q > 0) w ^= (u32x4){0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
-        va[q][r] = w;
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < VB; ++r) {
-      const int v = tid + NT * r;
-      if (v >= BN * BK / 8) break;
-      int k, j;
-      if (g.opB == QCUR_OP_H) { j = v / (BK / 8); k = (v % (BK / 8)) * 8; } else { k = v / (BN / 8); j = (v % (BN / 8)) * 8; }
-      const int64_t gk = k0 + k, gj = bn + j;
-      const bool full = (g.opB == QCUR_OP_H) ? (gj < N && gk + 7 < K) : (gk < K && gj + 7 < N);
-      const int64_t off = (g.opB == QCUR_OP_N) ? gk * g.ldb + gj : gj * g.ldb + gk;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        u32x4 w;
-        if (full) {
-          w = *(const u32x4*)(Bg + off + q * g.psb);
-        } else {
-          uint16_t e[8];
-#pragma unroll
-          for (int t = 0; t < 8; ++t) {
-            const bool ok = (g.opB == QCUR_OP_H) ? (gj < N && gk + t < K) : (gk < K && gj + t < N);
-            e[t] = ok ? Bg[off + t + q * g.psb] : (uint16_t)0;
-          }
-          w = __builtin_bit_cast(u32x4, e);
-        }
-        if (g.opB == QCUR_OP_H && q > 0) w ^= (u32x4){0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
-        vb[q][r] = w;
-      }
-    }
+      const int64_t k0 = kt * BK;
+      if (g.opA == QCUR_OP_N) kvec_load(Ag, g.lda, g.psa, bm, M, BM, k0, K, va);
+      else xblk_load(Ag, g.lda, g.psa, bm, M, BM, k0, K, va);
+      if (g.opB == QCUR_OP_H) kvec_load(Bg, g.ldb, g.psb, bn, N, BN, k0, K, vb);
+      else xblk_load(Bg, g.ldb, g.psb, bn, N, BN, k0, K, vb);
     }
   };
-  auto vec_store = [&]() {
+  auto vec_store = [&](int st) {
     if constexpr (DT == QCUR_BF16) {
-#pragma unroll
-      for (int r = 0; r < VA; ++r) {
-        const int v = tid + NT * r;
-        if (v >= BM * BK / 8) break;
-        int i, k;
-        if (g.opA == QCUR_OP_N) { i = v / (BK / 8); k = (v % (BK / 8)) * 8; } else { k = v / (BM / 8); i = (v % (BM / 8)) * 8; }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (g.opA == QCUR_OP_N) {
-            *(u32x4*)&sm.a[q][i][k] = va[q][r];
-          } else {
-            uint16_t e[8];
-            *(u32x4*)e = va[q][r];
-#pragma unroll
-            for (int t = 0; t < 8; ++t) sm.a[q][i + t][k] = e[t];
-          }
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < VB; ++r) {
-        const int v = tid + NT * r;
-        if (v >= BN * BK / 8) break;
-        int k, j;
-        if (g.opB == QCUR_OP_H) { j = v / (BK / 8); k = (v % (BK / 8)) * 8; } else { k = v / (BN / 8); j = (v % (BN / 8)) * 8; }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (g.opB == QCUR_OP_H) {
-            *(u32x4*)&sm.b[q][j][k] = vb[q][r];
-          } else {
-            uint16_t e[8];
-            *(u32x4*)e = vb[q][r];
-#pragma unroll
-            for (int t = 0; t < 8; ++t) sm.b[q][j + t][k] = e[t];
-          }
-        }
-      }
+      if (g.opA == QCUR_OP_N) kvec_store(sm.a[st][0], BM, va, false, BM);
+      else xblk_store(sm.a[st][0], BM, va, true, BM);
+      if (g.opB == QCUR_OP_H) kvec_store(sm.b[st][0], BN, vb, true, BN);
+      else xblk_store(sm.b[st][0], BN, vb, false, BN);
     }
   };
-  const bool use_vec = (DT == QCUR_BF16) && g.vec;
+  constexpr bool use_vec = DT == QCUR_BF16;
 
+  // Pipeline: while the MFMAs read stage st, the slice kt+1 (in registers
+  // since the previous step) goes to stage st^1 and slice kt+2 is fetched;
+  // one barrier per K step.
   if (kt0 < kt1) {
-    if (use_vec) vec_load(kt0); else load_tiles(kt0);
+    if constexpr (use_vec) vec_load(kt0); else load_tiles(kt0);
+    if constexpr (use_vec) vec_store(0); else store_tiles(0);
+    if (kt0 + 1 < kt1) {
+      if constexpr (use_vec) vec_load(kt0 + 1); else load_tiles(kt0 + 1);
+    }
   }
+  __syncthreads();
   for (int64_t kt = kt0; kt < kt1; ++kt) {
-    __syncthreads();
-    if (use_vec) vec_store(); else store_tiles();
-    __syncthreads();
+    const int st = (int)((kt - kt0) & 1);
     if (kt + 1 < kt1) {
-      if (use_vec) vec_load(kt + 1); else load_tiles(kt + 1);
+      if constexpr (use_vec) vec_store(st ^ 1); else store_tiles(st ^ 1);
+      if (kt + 2 < kt1) {
+        if constexpr (use_vec) vec_load(kt + 2); else load_tiles(kt + 2);
+      }
     }
 #pragma unroll
     for (int kk = 0; kk < BK / T::KM; ++kk) {
@@ -385,8 +406,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
         const int ii = wm + x * 16 + (lane & 15);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          if constexpr (DT == QCUR_BF16) a[q][x] = *(const Frag*)&sm.a[q][ii][(lane >> 4) * 8];
-          else a[q][x] = sm.a[q][ii][kk * 4 + (lane >> 4)];
+          if constexpr (DT == QCUR_BF16) a[q][x] = *(const Frag*)&sm.a[st][q][ii][kk * 32 + (lane >> 4) * 8];
+          else a[q][x] = sm.a[st][q][ii][kk * 4 + (lane >> 4)];
         }
 #pragma unroll
         for (int q = 1; q < 4; ++q) na[q][x] = T::neg(a[q][x]);
@@ -396,8 +417,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
         const int jj = wn + y * 16 + (lane & 15);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          if constexpr (DT == QCUR_BF16) b[q][y] = *(const Frag*)&sm.b[q][jj][(lane >> 4) * 8];
-          else b[q][y] = sm.b[q][jj][kk * 4 + (lane >> 4)];
+          if constexpr (DT == QCUR_BF16) b[q][y] = *(const Frag*)&sm.b[st][q][jj][kk * 32 + (lane >> 4) * 8];
+          else b[q][y] = sm.b[st][q][jj][kk * 4 + (lane >> 4)];
         }
       }
 #pragma unroll
@@ -426,6 +447,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
           acc[3][x][y] = T::mfma(a[0][x], b[3][y], acc[3][x][y]);
         }
     }
+    __syncthreads();
   }
 
   // Epilogue.  MFMA 16x16 output: lane holds column lane%16 and four rows
