@@ -138,8 +138,8 @@ def main():
     achieved = flops / t_gemm / 1e12
     # HBM bytes per GEMM of this kernel (FP32 split-K partials + reduction),
     # FETCH_SIZE + WRITE_SIZE from rocprofv3 --pmc runs of this script scaled
-    # by a copy of known size (profiles/qgemm_f32_T_AQr_color_1024.md); only
-    # valid for the FP32 kernel as profiled
+    # by a copy of known size (profiles/qgemm_f32_T_AQr_color_1024.md, taken
+    # on the two-stage LDS pipeline of k_qgemm); only valid for that kernel
     traffic = T_AQR_F32_HBM_BYTES if hd == q.F32 else None
     roofline = dict(bound="mfma", kernel=f"qgemm T = A Q_R ({m}x{n} . {n}x{r})", achieved=achieved, peak=peak,
                     unit="TFLOP/s", frac=achieved / peak, traffic=traffic, avg_launch_us=t_gemm * 1e6,
