@@ -392,6 +392,39 @@ qcur_status pinv_fast_group(const Ctx& c, int nb, const QView* X, double rtol, i
   return QCUR_OK;
 }
 
+// Cyclic one-sided Jacobi sweeps on the working matrix (too large for the
+// single-workgroup kernel), one launch per round of disjoint pairs, until a
+// sweep makes no rotation.  Pairs of negligible columns (below the
+// truncation threshold set by rtol) are left alone.
+qcur_status jacobi_sweeps(const Ctx& c, const PinvWs& w, int64_t pp, int64_t qq, double tol, double rtol) {
+  double* cmax = (double*)((char*)w.flag + 64);
+  unsigned* bad = (unsigned*)((char*)w.flag + 128);
+  HIPCHK(launch_zero(c, cmax, 1));
+  const int64_t qpad = (qq + 1) / 2 * 2;
+  // negligible pairs: first the per-column bound rtol sigma_max / 2, checked
+  // on the result; if the skipped columns add up to more, sweeps go on with
+  // the bound divided by sqrt(q)
+  double drop2 = rtol > 0.0 ? rtol * rtol / 4.0 : 0.0;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    unsigned host_flag = 1;
+    for (int sweep = 0; sweep < MAX_SWEEPS && host_flag; ++sweep) {
+      HIPCHK(launch_zero_i32(c, (int*)w.flag, 1));
+      for (int round = 0; round < qpad - 1; ++round)
+        HIPCHK(launch_jacobi_round(c, w.Y, pp, qq, w.V, qpad, round, tol, w.flag, drop2, cmax));
+      HIPCHK(hipMemcpyAsync(&host_flag, w.flag, sizeof(unsigned), hipMemcpyDeviceToHost, c.stream));
+      HIPCHK(hipStreamSynchronize(c.stream));
+    }
+    if (drop2 == 0.0 || attempt == 1) break;
+    unsigned host_bad = 0;
+    HIPCHK(launch_deflation_check(c, w.Y, pp, qq, drop2, rtol * rtol / 4.0, bad));
+    HIPCHK(hipMemcpyAsync(&host_bad, bad, sizeof(unsigned), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    if (!host_bad) break;
+    drop2 = rtol * rtol / (4.0 * (double)qq);
+  }
+  return QCUR_OK;
+}
+
 // Jacobi path: X (any dtype) -> Xp (F64, q x p).
 qcur_status pinv_jacobi(const Ctx& c, QView X, double rtol, int64_t max_rank, QView Xp, int64_t* rank_out,
                         PinvWs w) {
@@ -405,15 +438,7 @@ qcur_status pinv_jacobi(const Ctx& c, QView X, double rtol, int64_t max_rank, QV
   if (jacobi_small_fits(pp, qq)) {
     HIPCHK(launch_jacobi_small(c, w.Y, pp, qq, w.V, tol, MAX_SWEEPS, w.flag));
   } else {
-    const int64_t qpad = (qq + 1) / 2 * 2;
-    unsigned host_flag = 1;
-    for (int sweep = 0; sweep < MAX_SWEEPS && host_flag; ++sweep) {
-      HIPCHK(launch_zero_i32(c, (int*)w.flag, 1));
-      for (int round = 0; round < qpad - 1; ++round)
-        HIPCHK(launch_jacobi_round(c, w.Y, pp, qq, w.V, qpad, round, tol, w.flag));
-      HIPCHK(hipMemcpyAsync(&host_flag, w.flag, sizeof(unsigned), hipMemcpyDeviceToHost, c.stream));
-      HIPCHK(hipStreamSynchronize(c.stream));
-    }
+    CHK(jacobi_sweeps(c, w, pp, qq, tol, rtol));
   }
   HIPCHK(launch_pinv_scale(c, w.Y, pp, qq, rtol, max_rank, rank_out, w.sig));
   HIPCHK(launch_pinv_apply(c, w.Y, pp, qq, w.V, w.sig + qq));
@@ -441,15 +466,7 @@ qcur_status pinv_jacobi_qp(const Ctx& c, QView X, double rtol, int64_t max_rank,
   if (jacobi_small_fits(pp, qq)) {
     HIPCHK(launch_jacobi_small(c, w.Y, pp, qq, w.V, tol, MAX_SWEEPS, w.flag));
   } else {
-    const int64_t qpad = (qq + 1) / 2 * 2;
-    unsigned host_flag = 1;
-    for (int sweep = 0; sweep < MAX_SWEEPS && host_flag; ++sweep) {
-      HIPCHK(launch_zero_i32(c, (int*)w.flag, 1));
-      for (int round = 0; round < qpad - 1; ++round)
-        HIPCHK(launch_jacobi_round(c, w.Y, pp, qq, w.V, qpad, round, tol, w.flag));
-      HIPCHK(hipMemcpyAsync(&host_flag, w.flag, sizeof(unsigned), hipMemcpyDeviceToHost, c.stream));
-      HIPCHK(hipStreamSynchronize(c.stream));
-    }
+    CHK(jacobi_sweeps(c, w, pp, qq, tol, rtol));
   }
   HIPCHK(launch_pinv_scale(c, w.Y, pp, qq, rtol, max_rank, rank_out, w.sig));
   HIPCHK(launch_pinv_qp(c, w.Y, pp, qq, w.V, w.sig + qq, Qv, Pv));

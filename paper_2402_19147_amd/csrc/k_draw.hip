@@ -6,16 +6,15 @@
 //   tau = floor(u_t * T / 2^64), T = current weight total
 //   j   = smallest index whose inclusive prefix sum exceeds tau
 //   without replacement, w_j is then removed from T.
-// One workgroup per draw.  Weights live in LDS; the search descends a
-// 64-ary tree (superblocks of 4096, blocks of 64 elements) with one
-// wave-wide prefix scan per level, so each draw costs three scans.
+// One workgroup per draw.  The search descends a 64-ary tree (superblocks
+// of 4096, blocks of 64 elements) of inclusive prefix sums, updated in place
+// when a weight is removed: a draw costs one ballot per level.
 #include <algorithm>
 
 #include "qcur_internal.hpp"
 
 namespace qcur {
 
-static constexpr uint64_t TAKEN = 1ull << 63;
 static constexpr int DRAW_THREADS = 256;
 static constexpr int64_t DRAW_MAX_N_NOREPL = 16384;
 static constexpr int64_t DRAW_MAX_N_REPL = 8192;
@@ -67,18 +66,6 @@ __device__ inline uint64_t readlane_u64(uint64_t v, int k) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// Returns the first lane whose inclusive prefix of v exceeds tau and lowers
-// tau by the exclusive prefix of that lane.
-__device__ inline int select_lane(uint64_t v, uint64_t& tau) {
-  const uint64_t x = wave_incl_scan_u64(v);
-  const unsigned long long mask = __ballot(x > tau);
-  // the level sums are kept consistent, so some lane always qualifies; lane 0
-  // is a defensive fallback that keeps every index in range
-  const int k = mask ? __ffsll((unsigned long long)mask) - 1 : 0;
-  tau -= readlane_u64(x, k) - readlane_u64(v, k);
-  return k;
-}
-
 struct DrawJob {
   const double* probs;
   int64_t n, count;
@@ -96,14 +83,15 @@ __device__ void draw_body(const double* __restrict__ probs, int64_t n, int64_t c
   const int64_t npad = (n + 63) / 64 * 64;
   const int64_t nb = npad / 64;
   const int64_t nsb = (nb + 63) / 64;
-  uint64_t* wl = lds;              // npad weights (bit 63: taken)
+  uint64_t* wl = lds;              // npad weights, then in-block inclusive prefix sums
   uint64_t* L1 = wl + npad;        // nb block sums
   uint64_t* L2 = L1 + nb;          // nsb superblock sums
   uint32_t* cnt = (uint32_t*)(L2 + 64);  // npad pick counts (with replacement)
+  uint8_t* taken = (uint8_t*)(L2 + 64);  // npad taken flags (without replacement)
   __shared__ int bad;
   __shared__ uint64_t total;
   __shared__ int64_t npos;
-  __shared__ int64_t chunk_off[DRAW_THREADS];
+  __shared__ uint64_t wave_tot[DRAW_THREADS / 64];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -123,10 +111,11 @@ __device__ void draw_body(const double* __restrict__ probs, int64_t n, int64_t c
       inv = !(p >= 0.0 && p <= 1.0);
       w = inv ? 0ull : (uint64_t)(p * 0x1p60);
     }
-    wl[e] = w;
     if (repl) cnt[e] = 0u;
+    else taken[e] = 0;
     bool ovf = false;
     uint64_t s = wave_sum_u64(w, ovf);
+    wl[e] = wave_incl_scan_u64(w);  // exact: the block total did not overflow
     unsigned long long posm = __ballot(w > 0);
     unsigned long long invm = __ballot(inv);
     if (lane == 0) {
@@ -163,62 +152,77 @@ __device__ void draw_body(const double* __restrict__ probs, int64_t n, int64_t c
     return;
   }
 
-  // the draws, one wave.  Lane 0 updates the tree; the memory clobber at the
-  // end of each draw makes every lane reload it (LDS operations of one wave
-  // complete in order).
+  // the draws, one wave.  Every level keeps inclusive prefix sums: the
+  // superblock sums (one per lane) and the block sums within each superblock
+  // (lane b % 64, register b / 64) in registers, the weights of each block in
+  // LDS.  A draw picks at each level the first entry whose prefix exceeds
+  // tau (a ballot) and lowers tau by the prefix before it; without
+  // replacement it then subtracts the drawn weight from the prefixes at and
+  // after its position, so no scan is needed per draw.  LDS operations of one
+  // wave complete in order; the memory clobber makes every lane reload the
+  // weights of the next draw's block.
   if (wave == 0) {
+    constexpr int NB1 = (int)(DRAW_MAX_N_NOREPL / 64 / 64);  // block registers per lane
+    uint64_t l2p = wave_incl_scan_u64(lane < nsb ? L2[lane] : 0ull);
+    uint64_t l1p[NB1];
+#pragma unroll
+    for (int m = 0; m < NB1; ++m) l1p[m] = wave_incl_scan_u64((m * 64 + lane < nb) ? L1[m * 64 + lane] : 0ull);
+    // first lane whose prefix x exceeds tau (lane 0 if none: the sums are
+    // kept consistent, so this only keeps indices in range), and the prefix
+    // before it
+    auto pick = [&](uint64_t x, uint64_t& tau_) -> int {
+      const unsigned long long mask = __ballot(x > tau_);
+      const int k = mask ? __ffsll((unsigned long long)mask) - 1 : 0;
+      if (k > 0) tau_ -= readlane_u64(x, k - 1);
+      return k;
+    };
     uint64_t T = total;
     const uint64_t base = (set_id & 0xFFFFFFFFull) << 32;
+    uint64_t uvec = 0;  // u_{t..t+63}, one per lane, made 64 draws at a time
     for (int64_t t = 0; t < count; ++t) {
-      const uint64_t u = splitmix64_nth(seed, base + (uint64_t)t);
+      if ((t & 63) == 0) uvec = splitmix64_nth(seed, base + (uint64_t)(t + lane));
+      const uint64_t u = readlane_u64(uvec, (int)(t & 63));
       uint64_t tau = __umul64hi(u, T);
-      int sb = 0;
-      if (nsb > 1) {
-        const uint64_t v2 = lane < nsb ? L2[lane] : 0ull;
-        sb = select_lane(v2, tau);
-      }
-      const int64_t b0 = (int64_t)sb * 64;
-      const uint64_t v1 = (b0 + lane < nb) ? L1[b0 + lane] : 0ull;
-      const int64_t b = b0 + select_lane(v1, tau);
-      const uint64_t raw = wl[b * 64 + lane];
-      const uint64_t v0 = (raw & TAKEN) ? 0ull : raw;
-      const int e = select_lane(v0, tau);
+      const int sb = nsb > 1 ? pick(l2p, tau) : 0;
+      uint64_t v1 = l1p[0];
+#pragma unroll
+      for (int m = 1; m < NB1; ++m)
+        if (sb == m) v1 = l1p[m];
+      const int eb = pick(v1, tau);
+      const int64_t b = (int64_t)sb * 64 + eb;
+      const uint64_t pe = wl[b * 64 + lane];
+      const int e = pick(pe, tau);
       const int64_t j = b * 64 + e;
-      const uint64_t wj = readlane_u64(v0, e);
-      if (lane == 0) {
-        if (repl) {
-          cnt[j] = cnt[j] + 1u;
-        } else {
-          wl[j] = wj | TAKEN;
-          L1[b] = L1[b] - wj;
-          L2[sb] = L2[sb] - wj;
-        }
+      const uint64_t wj = readlane_u64(pe, e) - (e > 0 ? readlane_u64(pe, e - 1) : 0ull);
+      if (repl) {
+        if (lane == 0) cnt[j] = cnt[j] + 1u;
+      } else {
+        wl[b * 64 + lane] = pe - (lane >= e ? wj : 0ull);
+        if (lane == 0) taken[j] = 1;
+#pragma unroll
+        for (int m = 0; m < NB1; ++m)
+          if (sb == m && lane >= eb) l1p[m] -= wj;
+        if (lane >= sb) l2p -= wj;
+        T -= wj;
       }
-      if (!repl) T -= wj;
       __asm__ __volatile__("" ::: "memory");
     }
   }
   __syncthreads();
 
-  // sorted output: compaction of picked elements in index order
+  // sorted output: compaction of picked elements in index order (each
+  // thread counts its chunk; a workgroup-wide exclusive scan gives offsets)
   const int64_t per = (npad + DRAW_THREADS - 1) / DRAW_THREADS;
   const int64_t e0 = min(npad, tid * per), e1 = min(npad, e0 + per);
   int64_t mine = 0;
-  for (int64_t e = e0; e < e1; ++e) mine += repl ? (int64_t)cnt[e] : (int64_t)((wl[e] & TAKEN) != 0);
-  chunk_off[tid] = mine;
+  for (int64_t e = e0; e < e1; ++e) mine += repl ? (int64_t)cnt[e] : (int64_t)taken[e];
+  const uint64_t incl = wave_incl_scan_u64((uint64_t)mine);
+  if (lane == 63) wave_tot[wave] = incl;
   __syncthreads();
-  if (tid == 0) {
-    int64_t run = 0;
-    for (int k = 0; k < DRAW_THREADS; ++k) {
-      int64_t x = chunk_off[k];
-      chunk_off[k] = run;
-      run += x;
-    }
-  }
-  __syncthreads();
-  int64_t o = chunk_off[tid];
+  int64_t o = (int64_t)(incl - (uint64_t)mine);
+  for (int w = 0; w < wave; ++w) o += (int64_t)wave_tot[w];
   for (int64_t e = e0; e < e1; ++e) {
-    int64_t k = repl ? (int64_t)cnt[e] : (int64_t)((wl[e] & TAKEN) != 0);
+    int64_t k = repl ? (int64_t)cnt[e] : (int64_t)taken[e];
     for (int64_t r = 0; r < k && o < count; ++r) idx[o++] = e;
   }
 }
@@ -232,14 +236,12 @@ __global__ __launch_bounds__(DRAW_THREADS) void k_draw(DrawJobs jobs, int repl, 
 size_t draw_lds(int64_t n, int repl) {
   const int64_t npad = (n + 63) / 64 * 64;
   const int64_t nb = npad / 64;
-  size_t lds = (size_t)(npad + nb + 64) * 8;
-  if (repl) lds += (size_t)npad * 4;
-  return lds;
+  return (size_t)(npad + nb + 64) * 8 + (size_t)npad * (repl ? 4 : 1);
 }
 
 static hipError_t draw_jobs(const Ctx& c, DrawJobs jobs, int njobs, int repl, size_t lds) {
   hipError_t e = hipFuncSetAttribute((const void*)k_draw, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)(140 * 1024));
+                                     (int)(156 * 1024));  // 160 KiB less the static LDS
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_draw, dim3(njobs), dim3(DRAW_THREADS), lds, c.stream, jobs, repl, c.status);
   return hipGetLastError();

@@ -94,16 +94,56 @@ __device__ inline void acc_dots(const double* pa, const double* pb, int64_t ps, 
   d[5] += a0 * b3 - a1 * b2 + a2 * b1 - a3 * b0;
 }
 
+// 64-bit DPP move (lanes outside the pattern read 0).
+template <int CTRL, int ROWS>
+__device__ inline double dpp_d(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROWS, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROWS, 0xf, true);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Sum over the 64 lanes of a wave (all lanes active), the same value in
+// every lane: scans within rows of 16 by row shifts, row totals carried by
+// the row broadcasts, the total read from lane 63.
 __device__ inline double wsum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_d<0x111, 0xf>(v);  // row_shr:1
+  v += dpp_d<0x112, 0xf>(v);  // row_shr:2
+  v += dpp_d<0x114, 0xf>(v);  // row_shr:4
+  v += dpp_d<0x118, 0xf>(v);  // row_shr:8
+  v += dpp_d<0x142, 0xa>(v);  // row_bcast:15
+  v += dpp_d<0x143, 0xc>(v);  // row_bcast:31
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)u, 63);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 63);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Pairs of negligible columns.  Any column of Y = Z V has norm at most
+// sigma_max(Z), so the largest squared column norm seen so far (*cmax, kept
+// by atomicMax on its bit pattern: positive doubles order like their bits)
+// bounds sigma_max^2 from below.  A pair whose squared norms are both at
+// most drop2 * (*cmax) is not rotated.  When the sweeps stop, those columns
+// D hold a block Y_D orthogonal to all other columns; if ||Y_D||_F <=
+// rtol sigma_max / 2 its singular values fall below the truncation
+// threshold rtol sigma_max and the kept singular triplets are those of the
+// full SVD.  The caller takes drop2 = rtol^2 / 4 and checks that sum over D
+// afterwards (k_deflation_check), else sweeps again with drop2 =
+// rtol^2 / (4 q), for which the bound holds whatever D is.  Such pairs only
+// slow convergence (columns of rounding noise of a rank-deficient Z).
+__device__ inline bool negligible_pair(double alpha, double beta, double drop2, const double* cmax) {
+  const double t = drop2 * *(volatile const double*)cmax;
+  return alpha <= t && beta <= t;
+}
+__device__ inline void note_norms(double alpha, double beta, double* cmax) {
+  const double m = alpha > beta ? alpha : beta;
+  if (m > 0.0) atomicMax((unsigned long long*)cmax, (unsigned long long)__double_as_longlong(m));
 }
 
 // One round of the circle schedule: workgroup k rotates pair k.
 __global__ __launch_bounds__(256) void k_jacobi_round(double* __restrict__ Y, int64_t p, int64_t q,
                                                       double* __restrict__ V, int qpad, int round, double tol,
-                                                      unsigned* rotated) {
+                                                      unsigned* rotated, double drop2, double* cmax) {
   __shared__ double red[4][6];
   __shared__ Rot rot;
   int a, b;
@@ -123,7 +163,9 @@ __global__ __launch_bounds__(256) void k_jacobi_round(double* __restrict__ Y, in
   if (tid == 0) {
     double s[6];
     for (int x = 0; x < 6; ++x) s[x] = ((red[0][x] + red[1][x]) + red[2][x]) + red[3][x];
+    note_norms(s[0], s[1], cmax);
     rot = make_rot(s[0], s[1], s[2], s[3], s[4], s[5], tol);
+    if (negligible_pair(s[0], s[1], drop2, cmax)) rot.rotate = false;
     if (rot.rotate) atomicOr(rotated, 1u);
   }
   __syncthreads();
@@ -135,11 +177,68 @@ __global__ __launch_bounds__(256) void k_jacobi_round(double* __restrict__ Y, in
   for (int64_t k = tid; k < q; k += 256) apply_rot(r, va, vb, psv, k);
 }
 
-hipError_t launch_jacobi_round(const Ctx& c, double* Y, int64_t p, int64_t q, double* V, int64_t qpad, int round,
-                               double tol, unsigned* rotated) {
-  hipLaunchKernelGGL(k_jacobi_round, dim3((unsigned)(qpad / 2)), dim3(256), 0, c.stream, Y, p, q, V, (int)qpad,
-                     round, tol, rotated);
+// After deflated sweeps: bad = 1 unless the columns with ||y||^2 <= drop2 *
+// max ||y||^2 have sum ||y||^2 <= (rtol^2 / 4) max ||y||^2.
+__global__ __launch_bounds__(1024) void k_deflation_check(const double* __restrict__ Y, int64_t p, int64_t q,
+                                                          double drop2, double rtol2q, unsigned* bad) {
+  __shared__ double part[2][16];
+  __shared__ double mx;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t psy = q * p;
+  for (int pass = 0; pass < 2; ++pass) {
+    double acc = 0.0;
+    for (int64_t k = wave; k < q; k += 16) {
+      const double* y = Y + k * p;
+      double s = 0.0;
+      for (int64_t i = lane; i < p; i += 64) {
+        const double a0 = y[i], a1 = y[i + psy], a2 = y[i + 2 * psy], a3 = y[i + 3 * psy];
+        s += a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3;
+      }
+      s = wsum(s);
+      if (pass == 0) acc = fmax(acc, s);
+      else if (s <= drop2 * mx) acc += s;
+    }
+    if (lane == 0) part[pass][wave] = acc;
+    __syncthreads();
+    if (tid == 0) {
+      double r = 0.0;
+      for (int w = 0; w < 16; ++w) r = pass == 0 ? fmax(r, part[0][w]) : r + part[1][w];
+      if (pass == 0) mx = r;
+      else *bad = (r <= rtol2q * mx) ? 0u : 1u;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_deflation_check(const Ctx& c, const double* Y, int64_t p, int64_t q, double drop2, double rtol2q,
+                                  unsigned* bad) {
+  hipLaunchKernelGGL(k_deflation_check, dim3(1), dim3(1024), 0, c.stream, Y, p, q, drop2, rtol2q, bad);
   return hipGetLastError();
+}
+
+hipError_t launch_jacobi_round(const Ctx& c, double* Y, int64_t p, int64_t q, double* V, int64_t qpad, int round,
+                               double tol, unsigned* rotated, double drop2, double* cmax) {
+  hipLaunchKernelGGL(k_jacobi_round, dim3((unsigned)(qpad / 2)), dim3(256), 0, c.stream, Y, p, q, V, (int)qpad,
+                     round, tol, rotated, drop2, cmax);
+  return hipGetLastError();
+}
+
+// dst[e] = src[e], e < n (global to LDS), eight loads in flight per thread.
+__device__ inline void copy_in8(double* __restrict__ dst, const double* __restrict__ src, int64_t n, int tid,
+                                int nthr) {
+  for (int64_t e0 = tid; e0 < n; e0 += 8 * (int64_t)nthr) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t e = e0 + (int64_t)u * nthr;
+      v[u] = e < n ? src[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t e = e0 + (int64_t)u * nthr;
+      if (e < n) dst[e] = v[u];
+    }
+  }
 }
 
 // Whole Jacobi SVD in one workgroup (16 waves, one pair per wave at a time);
@@ -159,8 +258,8 @@ __global__ __launch_bounds__(1024) void k_jacobi_small(double* __restrict__ Yg, 
   const int64_t psy = q * p, psv = q * q;
   double* Y = lds;
   double* V = lds + 4 * psy;
-  for (int64_t e = tid; e < 4 * psy; e += 1024) Y[e] = Yg[e];
-  for (int64_t e = tid; e < 4 * psv; e += 1024) V[e] = Vg[e];
+  copy_in8(Y, Yg, 4 * psy, tid, 1024);
+  copy_in8(V, Vg, 4 * psv, tid, 1024);
   const int qpad = (int)((q + 1) / 2 * 2);
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {

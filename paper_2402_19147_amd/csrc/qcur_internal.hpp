@@ -128,8 +128,10 @@ hipError_t launch_merge_gemm(const Ctx& c, QView Y, const uint8_t* mask, int64_t
 hipError_t launch_mask_init(const Ctx& c, QView Y, const uint8_t* mask, int64_t mask_ld, QView X);
 
 // Jacobi pseudoinverse pieces.
-hipError_t launch_jacobi_round(const Ctx& c, double* Y, int64_t p, int64_t q, double* V,
-                               int64_t qpad, int round, double tol, unsigned* rotated);
+hipError_t launch_jacobi_round(const Ctx& c, double* Y, int64_t p, int64_t q, double* V, int64_t qpad, int round,
+                               double tol, unsigned* rotated, double drop2, double* cmax);
+hipError_t launch_deflation_check(const Ctx& c, const double* Y, int64_t p, int64_t q, double drop2, double rtol2q,
+                                  unsigned* bad);
 hipError_t launch_jacobi_small(const Ctx& c, double* Y, int64_t p, int64_t q, double* V,
                                double tol, int max_sweeps, unsigned* rotated);
 bool jacobi_small_fits(int64_t p, int64_t q);

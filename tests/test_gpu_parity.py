@@ -255,6 +255,20 @@ def test_pinv_ill_conditioned_falls_back():
     assert rel(N(Xp2), ref2) < 1e-9
 
 
+@pytest.mark.parametrize("p,q,k,mr", [(256, 256, 64, 64), (256, 256, 64, 0), (300, 230, 45, 0)])
+def test_pinv_rank_deficient_deflated_jacobi(p, q, k, mr):
+    # exact-rank products of Gaussian factors (the differentiation workload's
+    # W = A(I, J)): multi-launch Jacobi sweeps with the pairs of rounding-noise
+    # columns left unrotated
+    rng = np.random.default_rng(p + q + k)
+    X = qmul(rng.standard_normal((4, p, k)), rng.standard_normal((4, k, q)))
+    Xp, rank = Q.pinv(T(X), max_rank=mr)
+    ref, kr = oracle.qpinv(X, max_rank=mr)
+    assert int(N(rank)[0]) == kr == k
+    assert rel(N(Xp), ref) < 1e-10
+    assert rel(qmul(qmul(X, N(Xp)), X), X) < 1e-11
+
+
 def test_pinv_zero_matrix():
     Xp, rank = Q.pinv(torch.zeros((4, 6, 4), dtype=torch.float64, device=DEV))
     assert int(N(rank)[0]) == 0 and not N(Xp).any()
