@@ -131,13 +131,14 @@ __device__ inline double wsum(double v) {
 // afterwards (k_deflation_check), else sweeps again with drop2 =
 // rtol^2 / (4 q), for which the bound holds whatever D is.  Such pairs only
 // slow convergence (columns of rounding noise of a rank-deficient Z).
-__device__ inline bool negligible_pair(double alpha, double beta, double drop2, const double* cmax) {
-  const double t = drop2 * *(volatile const double*)cmax;
-  return alpha <= t && beta <= t;
-}
-__device__ inline void note_norms(double alpha, double beta, double* cmax) {
+// Records max(alpha, beta) in *cmax (an atomic only when it is larger than
+// the value read) and tells whether the pair is negligible.
+__device__ inline bool negligible_pair(double alpha, double beta, double drop2, double* cmax) {
+  const double seen = *(volatile const double*)cmax;
   const double m = alpha > beta ? alpha : beta;
-  if (m > 0.0) atomicMax((unsigned long long*)cmax, (unsigned long long)__double_as_longlong(m));
+  if (m > seen) atomicMax((unsigned long long*)cmax, (unsigned long long)__double_as_longlong(m));
+  const double t = drop2 * (m > seen ? m : seen);
+  return alpha <= t && beta <= t;
 }
 
 // One round of the circle schedule: workgroup k rotates pair k.
@@ -163,7 +164,6 @@ __global__ __launch_bounds__(256) void k_jacobi_round(double* __restrict__ Y, in
   if (tid == 0) {
     double s[6];
     for (int x = 0; x < 6; ++x) s[x] = ((red[0][x] + red[1][x]) + red[2][x]) + red[3][x];
-    note_norms(s[0], s[1], cmax);
     rot = make_rot(s[0], s[1], s[2], s[3], s[4], s[5], tol);
     if (negligible_pair(s[0], s[1], drop2, cmax)) rot.rotate = false;
     if (rot.rotate) atomicOr(rotated, 1u);
