@@ -316,6 +316,27 @@ qcur_status qcur_complete(qcur_handle handle, const qcur_qmat* Y, const uint8_t*
                           void* ws, size_t ws_bytes);
 size_t qcur_complete_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int compute);
 
+/* Algorithm 2 with the index sets drawn again at every step: step t draws
+ * J (c columns, set 0) and I (r rows, set 1) from the sampling
+ * probabilities of the current iterate X^t (sampling = QCUR_LENGTH or
+ * QCUR_UNIFORM, Section 3.1; without replacement) with seed + t, then
+ * proceeds as qcur_complete.  I (device int64[r]) and J (device int64[c])
+ * are outputs: the index sets of the last step.  Other arguments and the
+ * stopping rule as in qcur_complete.  Also errors with QCUR_ERR_SAMPLE (on
+ * the status word) when an iterate has fewer nonzero rows or columns than
+ * r or c.  ws: qcur_complete_resampled_workspace(m, n, c, r, sampling,
+ * compute). */
+qcur_status qcur_complete_resampled(qcur_handle handle, const qcur_qmat* Y, const uint8_t* mask, int64_t mask_ld,
+                                    int64_t r, int64_t c, int sampling, uint64_t seed, int compute, double rtol,
+                                    int64_t max_rank, int max_iter, double tol, qcur_qmat* X, int64_t* I,
+                                    int64_t* J, int* iters, double* rel, void* ws, size_t ws_bytes);
+size_t qcur_complete_resampled_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int sampling, int compute);
+
+/* Sample size for a target rank k (Section 3.1 sizes C and R as k log k):
+ * ceil(k ln k), at least k and at most limit (k = 1 gives 1).  Host only;
+ * returns 0 when k < 1 or limit < 1. */
+int64_t qcur_sample_size(int64_t k, int64_t limit);
+
 /* ---- helpers ----------------------------------------------------------- */
 
 /* Elementwise dtype conversion Y = X (same shape; BF16 with

@@ -1373,6 +1373,11 @@ struct CompleteArgs {
   const uint8_t* mask;
   int64_t mask_ld;
   const int64_t *I, *J;
+  // index sets drawn again at every step (I, J then point to the caller's
+  // output arrays)
+  bool resample;
+  int sampling;
+  uint64_t seed;
   int64_t r, cc;
   int compute;
   double rtol;
@@ -1411,6 +1416,15 @@ qcur_status complete_run(const Ctx& c, const CompleteArgs& a, Bump& b, bool coun
   const size_t gwb = std::max({gemm_workspace(m, r, n, a.compute), gemm_workspace(cc, r, m, a.compute),
                               gemm_workspace(m, r, cc, a.compute)});
   void* gws = b.take(gwb);
+  // probabilities of the iterate (resampled variant)
+  int rb = 0, nrb = 0, ncb = 0;
+  probs_grid(m, n, &rb, &nrb, &ncb);
+  const bool pass = a.resample && a.sampling == QCUR_LENGTH;
+  double* pcol = a.resample ? (double*)b.take((size_t)n * 8) : nullptr;
+  double* qrow = a.resample ? (double*)b.take((size_t)m * 8) : nullptr;
+  double* colpart = pass ? (double*)b.take((size_t)nrb * n * 8) : nullptr;
+  double* rowpart = pass ? (double*)b.take((size_t)ncb * m * 8) : nullptr;
+  double* f2 = a.resample ? (double*)b.take(8) : nullptr;
   if (count_only) return QCUR_OK;
   HIPCHK(launch_mask_init(c, a.Y, a.mask, a.mask_ld, a.X));
   // the iterate of step t lives in cur; the next goes to nxt
@@ -1419,6 +1433,17 @@ qcur_status complete_run(const Ctx& c, const CompleteArgs& a, Bump& b, bool coun
   int t = 0;
   double rel = INFINITY;
   while (t < a.max_iter) {
+    if (a.resample) {
+      // step t draws J (set 0) and I (set 1) from the probabilities of X^t
+      // with seed + t
+      if (pass) {
+        HIPCHK(launch_probs_partials(c, cur, colpart, rowpart, rb, ncb));
+        HIPCHK(launch_probs_finish(c, m, n, colpart, rowpart, nrb, ncb, a.sampling, pcol, qrow, f2, nullptr));
+      } else {
+        HIPCHK(launch_probs_finish(c, m, n, nullptr, nullptr, 0, 0, a.sampling, pcol, qrow, nullptr, nullptr));
+      }
+      HIPCHK(launch_draw_pair(c, pcol, n, cc, 0, (int64_t*)a.J, qrow, m, r, 1, (int64_t*)a.I, a.seed + (uint64_t)t, 0));
+    }
     HIPCHK(launch_gather(c, cur, a.I, r, a.J, cc, &C, &R, nullptr));
     QView Qv[2], Pv[2];
     QView xs[2] = {C, R};
@@ -1454,6 +1479,12 @@ qcur_status complete_run(const Ctx& c, const CompleteArgs& a, Bump& b, bool coun
   if (a.rel) *a.rel = rel;
   return QCUR_OK;
 }
+
+// Validation and dispatch shared by qcur_complete and qcur_complete_resampled.
+qcur_status complete_entry(qcur_handle h, const qcur_qmat* Y, const uint8_t* mask, int64_t mask_ld,
+                           const int64_t* I, int64_t r, const int64_t* J, int64_t c, int compute, double rtol,
+                           int64_t max_rank, int max_iter, double tol, qcur_qmat* X, int* iters, double* rel,
+                           void* ws, size_t ws_bytes, bool resample, int sampling, uint64_t seed);
 
 }  // namespace
 
@@ -2103,10 +2134,53 @@ size_t qcur_complete_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int c
   return b.used + 256;
 }
 
+size_t qcur_complete_resampled_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int sampling, int compute) {
+  if (m < 1 || n < 1 || c < 1 || r < 1) return 0;
+  CompleteArgs a{};
+  a.Y = QView{nullptr, m, n, n, m * n, QCUR_F64};
+  a.X = QView{nullptr, m, n, n, m * n, acc_dt(compute)};
+  a.r = r;
+  a.cc = c;
+  a.compute = compute;
+  a.resample = true;
+  a.sampling = sampling;
+  Bump b(nullptr);
+  Ctx dummy{0, nullptr, nullptr};
+  complete_run(dummy, a, b, true);
+  return b.used + 256;
+}
+
+int64_t qcur_sample_size(int64_t k, int64_t limit) {
+  if (k < 1 || limit < 1) return 0;
+  const int64_t s = k > 1 ? (int64_t)std::ceil((double)k * std::log((double)k)) : 1;
+  return std::min(limit, std::max(k, s));
+}
+
+qcur_status qcur_complete_resampled(qcur_handle h, const qcur_qmat* Y, const uint8_t* mask, int64_t mask_ld,
+                                    int64_t r, int64_t c, int sampling, uint64_t seed, int compute, double rtol,
+                                    int64_t max_rank, int max_iter, double tol, qcur_qmat* X, int64_t* I, int64_t* J,
+                                    int* iters, double* rel, void* ws, size_t ws_bytes) {
+  if (sampling != QCUR_LENGTH && sampling != QCUR_UNIFORM) return fail(QCUR_ERR_ARG, "unknown sampling mode");
+  if (Y && (r > Y->rows || c > Y->cols)) return fail(QCUR_ERR_ARG, "r and c must not exceed m and n");
+  return complete_entry(h, Y, mask, mask_ld, I, r, J, c, compute, rtol, max_rank, max_iter, tol, X, iters, rel, ws,
+                        ws_bytes, true, sampling, seed);
+}
+
 qcur_status qcur_complete(qcur_handle h, const qcur_qmat* Y, const uint8_t* mask, int64_t mask_ld, const int64_t* I,
                           int64_t r, const int64_t* J, int64_t c, int compute, double rtol, int64_t max_rank,
                           int max_iter, double tol, qcur_qmat* X, int* iters, double* rel, void* ws,
                           size_t ws_bytes) {
+  return complete_entry(h, Y, mask, mask_ld, I, r, J, c, compute, rtol, max_rank, max_iter, tol, X, iters, rel, ws,
+                        ws_bytes, false, 0, 0);
+}
+
+}  // extern "C"
+
+namespace {
+qcur_status complete_entry(qcur_handle h, const qcur_qmat* Y, const uint8_t* mask, int64_t mask_ld,
+                           const int64_t* I, int64_t r, const int64_t* J, int64_t c, int compute, double rtol,
+                           int64_t max_rank, int max_iter, double tol, qcur_qmat* X, int* iters, double* rel,
+                           void* ws, size_t ws_bytes, bool resample, int sampling, uint64_t seed) {
   CHK(check_qmat(Y, "Y"));
   CHK(check_qmat(X, "X"));
   if (Y->rows < 1 || Y->cols < 1) return fail(QCUR_ERR_SHAPE, "Y must have at least one row and column");
@@ -2135,6 +2209,9 @@ qcur_status qcur_complete(qcur_handle h, const qcur_qmat* Y, const uint8_t* mask
   a.tol = tol;
   a.iters = iters;
   a.rel = rel;
+  a.resample = resample;
+  a.sampling = sampling;
+  a.seed = seed;
   {
     Bump sz(nullptr);
     Ctx dummy{0, nullptr, nullptr};
@@ -2145,6 +2222,9 @@ qcur_status qcur_complete(qcur_handle h, const qcur_qmat* Y, const uint8_t* mask
   Bump b(ws);
   return complete_run(h->c, a, b, false);
 }
+}  // namespace
+
+extern "C" {
 
 qcur_status qcur_cast(qcur_handle h, const qcur_qmat* X, qcur_qmat* Y) {
   CHK(check_qmat(X, "X"));

@@ -84,6 +84,10 @@ def _declare(L):
         "qcur_complete": (c_int, [c_p, QP, c_p, c_i64, c_p, c_i64, c_p, c_i64, c_int, c_d, c_i64, c_int, c_d, QP,
                                   c_p, c_p, c_p, c_sz]),
         "qcur_complete_workspace": (c_sz, [c_i64, c_i64, c_i64, c_i64, c_int]),
+        "qcur_complete_resampled": (c_int, [c_p, QP, c_p, c_i64, c_i64, c_i64, c_int, c_u64, c_int, c_d, c_i64,
+                                            c_int, c_d, QP, c_p, c_p, c_p, c_p, c_p, c_sz]),
+        "qcur_complete_resampled_workspace": (c_sz, [c_i64, c_i64, c_i64, c_i64, c_int, c_int]),
+        "qcur_sample_size": (c_i64, [c_i64, c_i64]),
         "qcur_solve_batched": (c_int, [c_p, ctypes.c_int32, c_p, QP, c_i64, c_int, c_int, c_u64, c_int, c_int, c_d,
                                        c_i64, c_p, c_p, QP, c_i64, c_p, c_p, c_p, c_p, c_p, c_sz]),
     }
@@ -453,3 +457,29 @@ def complete(Y: torch.Tensor, mask: torch.Tensor, I: torch.Tensor, J: torch.Tens
                                max_rank, max_iter, tol, _qp(X), ctypes.byref(iters), ctypes.byref(rel), _ptr(ws),
                                ws.numel()))
     return X, iters.value, rel.value
+
+
+def complete_resampled(Y: torch.Tensor, mask: torch.Tensor, r: int, c: int, sampling: int = LENGTH, seed: int = 0,
+                       compute: int = F64, rtol: float = -1.0, max_rank: int = 0, max_iter: int = 200,
+                       tol: float = 1e-4):
+    """Completion (Algorithm 2) with I (r rows) and J (c columns) drawn again
+    at every step from the probabilities of the iterate (seed + step).
+    Returns (X, iterations, last relative change, I, J of the last step)."""
+    _, m, n = Y.shape
+    if mask.dtype != torch.uint8 or tuple(mask.shape) != (m, n) or mask.stride(1) != 1:
+        raise ValueError("mask must be a row-major uint8 (m, n) tensor")
+    odt = torch.float64 if compute == F64 else torch.float32
+    X = empty(m, n, odt, Y.device)
+    I = torch.empty(r, dtype=torch.int64, device=Y.device)
+    J = torch.empty(c, dtype=torch.int64, device=Y.device)
+    ws = _ws(lib().qcur_complete_resampled_workspace(m, n, c, r, sampling, compute), Y.device)
+    iters, rel = ctypes.c_int(0), ctypes.c_double(0.0)
+    _check(lib().qcur_complete_resampled(_h(Y), _qp(Y), _ptr(mask), mask.stride(0), r, c, sampling, seed, compute,
+                                         rtol, max_rank, max_iter, tol, _qp(X), _ptr(I), _ptr(J),
+                                         ctypes.byref(iters), ctypes.byref(rel), _ptr(ws), ws.numel()))
+    return X, iters.value, rel.value, I, J
+
+
+def sample_size(k: int, limit: int) -> int:
+    """ceil(k ln k) clipped to [k, limit]: the k log k size of C and R."""
+    return int(lib().qcur_sample_size(k, limit))

@@ -184,3 +184,28 @@ def test_batch_workspace_and_validation(L):
     over, op = _dims([(64, 80, 100, 12)])        # c > n without replacement
     assert solve(count=1, dims=op) == 2
     assert solve(count=0) == 1
+
+
+def test_sample_size_matches_checker(L):
+    from oracle.complete import sample_size
+    for k in list(range(1, 400)) + [1000, 4096]:
+        for limit in (k, 2 * k, 10 ** 6):
+            assert L.qcur_sample_size(k, limit) == sample_size(k, limit)
+    assert L.qcur_sample_size(0, 10) == 0 and L.qcur_sample_size(5, 0) == 0
+
+
+def test_complete_resampled_workspace_and_validation(L):
+    ws = L.qcur_complete_resampled_workspace(512, 768, 60, 60, Q.LENGTH, Q.F32)
+    assert ws > L.qcur_complete_workspace(512, 768, 60, 60, Q.F32) > 0
+    assert L.qcur_complete_resampled_workspace(0, 768, 60, 60, Q.LENGTH, Q.F32) == 0
+    Y, X = qm(50, 40, Q.F32), qm(50, 40, Q.F32)
+
+    def call(r=5, c=6, sampling=Q.LENGTH, X=X, nbytes=1 << 30):
+        return L.qcur_complete_resampled(None, Y, FAKE, 40, r, c, sampling, 7, Q.F32, -1.0, 0, 10, 1e-4, X,
+                                         FAKE, FAKE, None, None, FAKE, nbytes)
+
+    assert call() == 1                    # valid: only the NULL handle is rejected
+    assert call(sampling=9) == 1 and "sampling" in L.qcur_last_error().decode()
+    assert call(r=51) == 1 and "exceed" in L.qcur_last_error().decode()
+    assert call(nbytes=16) == 4
+    assert call(X=qm(50, 40, Q.F64)) == 3

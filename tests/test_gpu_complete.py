@@ -90,3 +90,37 @@ def test_stopping_and_degenerate_cases():
     assert iters == 0
     assert np.array_equal(N(X), np.where(mask[None] == 1, Y, 0.0))
     Q.sync_status()
+
+
+@pytest.mark.parametrize("sampling,name", [(Q.LENGTH, "length"), (Q.UNIFORM, "uniform")])
+def test_resampled_steps_match_checker(sampling, name):
+    # index sets drawn again from every iterate: the same draws as the
+    # checker's (exact integer sampler) and the same iterates
+    from oracle.complete import complete_resampled as ref_resampled
+    A, Y, mask, _, _ = problem(150, 130, 4, 0.5, 12, seed=41, noise=1e-3)
+    X, iters, rel, I, J = Q.complete_resampled(T(Y), T(mask, torch.uint8), 14, 12, sampling=sampling, seed=77,
+                                               compute=Q.F64, max_iter=5, tol=0.0)
+    Q.sync_status()
+    ref = ref_resampled(Y, mask, 14, 12, name, seed=77, max_iter=5, tol=0.0)
+    assert iters == 5
+    assert np.array_equal(N(I).astype(np.int64), ref["I"]) and np.array_equal(N(J).astype(np.int64), ref["J"])
+    assert np.sqrt(fro2(N(X) - ref["X"]) / fro2(ref["X"])) < 1e-9
+    assert abs(rel - ref["rel"]) <= 1e-8 * ref["rel"] + 1e-12
+
+
+def test_resampled_fp32_first_step_and_convergence():
+    from oracle.complete import complete_resampled as ref_resampled
+    A, Y, mask, _, _ = problem(130, 110, 3, 0.6, 10, seed=42)
+    Yg = T(Y, torch.float32)
+    X, iters, rel, I, J = Q.complete_resampled(Yg, T(mask, torch.uint8), 10, 10, seed=5, compute=Q.F32, max_iter=1,
+                                               tol=0.0)
+    Q.sync_status()
+    ref = ref_resampled(N(Yg), mask, 10, 10, "length", seed=5, max_iter=1, tol=0.0)
+    assert np.array_equal(N(I).astype(np.int64), ref["I"]) and np.array_equal(N(J).astype(np.int64), ref["J"])
+    assert np.sqrt(fro2(N(X) - ref["X"]) / fro2(ref["X"])) < 2e-4
+    # the rank-3 matrix with 40% of its entries missing is recovered
+    X, iters, rel, I, J = Q.complete_resampled(T(Y), T(mask, torch.uint8), 10, 10, seed=5, compute=Q.F64,
+                                               max_iter=300, tol=1e-10)
+    Q.sync_status()
+    miss = np.broadcast_to(mask[None] == 0, A.shape)
+    assert np.linalg.norm((N(X) - A)[miss]) / np.linalg.norm(A[miss]) < 1e-6
