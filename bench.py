@@ -388,6 +388,25 @@ def bench_complete(q, torch, workloads, dev):
         out[name] = dict(iterations=iters, last_rel_change=rel, ms_per_iter=dt_s * 1e3 / max(iters, 1),
                          total_ms=dt_s * 1e3, rel_err_missing_vs_noiseless=err)
         log(f"complete {name}: {iters} steps, {dt_s * 1e3 / max(iters, 1):.3f} ms/step")
+    # the same problem with I, J drawn again from every iterate (length
+    # probabilities), c = r = ceil(k ln k)
+    cr = q.sample_size(k, min(m, n))
+    Y = torch.tensor(A, dtype=torch.float32, device=dev)
+    Mk = torch.tensor(mask, device=dev)
+    q.complete_resampled(Y, Mk, cr, cr, sampling=q.LENGTH, seed=seed, compute=q.F32, max_iter=2, tol=0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    X, iters, rel, _, _ = q.complete_resampled(Y, Mk, cr, cr, sampling=q.LENGTH, seed=seed, compute=q.F32,
+                                               max_iter=cfg["max_iter"], tol=cfg["tol"])
+    torch.cuda.synchronize()
+    dt_s = time.perf_counter() - t0
+    q.sync_status()
+    Xh = X.to(torch.float64).cpu().numpy()
+    err = float(np.sqrt(((Xh - truth)[:, miss] ** 2).sum() / ((truth[:, miss]) ** 2).sum()))
+    out["f32_resampled_length"] = dict(c=cr, r=cr, iterations=iters, last_rel_change=rel,
+                                       ms_per_iter=dt_s * 1e3 / max(iters, 1), total_ms=dt_s * 1e3,
+                                       rel_err_missing_vs_noiseless=err)
+    log(f"complete f32 resampled: {iters} steps, {dt_s * 1e3 / max(iters, 1):.3f} ms/step, err {err:.4f}")
     return out
 
 

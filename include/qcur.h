@@ -91,6 +91,7 @@ int qcur_version(void);
 /* ---- workspace queries (host only, no GPU needed) --------------------- */
 size_t qcur_probs_workspace(int64_t m, int64_t n);
 size_t qcur_pinv_workspace(int64_t p, int64_t q);
+size_t qcur_svd_workspace(int64_t p, int64_t q);
 size_t qcur_approx_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int core, int compute);
 size_t qcur_residual_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int compute);
 size_t qcur_backward_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int compute);
@@ -144,6 +145,19 @@ qcur_status qcur_gather(qcur_handle handle, const qcur_qmat* A, const int64_t* I
  * QCUR_ERR_NUMERIC in the status word. */
 qcur_status qcur_pinv(qcur_handle handle, const qcur_qmat* X, double rtol, int64_t max_rank,
                       qcur_qmat* Xp, int64_t* rank_out, void* ws, size_t ws_bytes);
+
+/* Thin quaternion SVD X = U diag(s) V^H of X (p x q, any dtype), k =
+ * min(p, q), computed in FP64 by the same one-sided Jacobi method as
+ * qcur_pinv (Section 2.1's QSVD; the costly route that QMCUR avoids, kept
+ * as the baseline).  s: device double[k], descending.  U (p x k) and V
+ * (q x k): FP64 outputs with orthonormal columns for the nonzero singular
+ * values; for zero singular values the columns of U (p >= q) or of V
+ * (p < q) are zero and the other factor keeps orthonormal columns.  Either
+ * may be NULL.  Synchronises the
+ * stream once per Jacobi sweep.  ws: qcur_svd_workspace(p, q) bytes.
+ * Non-finite input raises QCUR_ERR_NUMERIC in the status word. */
+qcur_status qcur_svd(qcur_handle handle, const qcur_qmat* X, double* s, qcur_qmat* U, qcur_qmat* V, void* ws,
+                     size_t ws_bytes);
 
 /* Quaternion product D = alpha * op(A) op(B) + beta * D (Section 2.2
  * multiplication laws) with real alpha, beta; op(X) is X or X^H.

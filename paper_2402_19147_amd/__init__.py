@@ -12,8 +12,8 @@ from .autograd import cur_loss, cur  # noqa: F401
 from .qcur import (F64, F32, BF16, OP_N, OP_H, LENGTH, UNIFORM, CORE_WPINV, CORE_CAR,  # noqa: F401
                    QcurError, probs, draw, gather, pinv, gemm, approx, residual, backward, cast,
                    solve, sync_status, lib, Solver, BatchSolver, pack_batch, complete,
-                   complete_resampled, sample_size)
+                   complete_resampled, sample_size, svd)
 
 __all__ = ["qcur", "autograd", "cur_loss", "cur", "probs", "draw", "gather", "pinv", "gemm", "approx", "residual", "backward", "cast",
            "solve", "sync_status", "lib", "QcurError", "Solver",
-           "BatchSolver", "pack_batch", "complete", "complete_resampled", "sample_size"]
+           "BatchSolver", "pack_batch", "complete", "complete_resampled", "sample_size", "svd"]

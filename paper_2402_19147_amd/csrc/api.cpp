@@ -1577,6 +1577,14 @@ size_t qcur_pinv_workspace(int64_t p, int64_t q) {
   return pinv_ws_size(p, q);
 }
 
+size_t qcur_svd_workspace(int64_t p, int64_t q) {
+  if (p < 1 || q < 1) return 0;
+  Bump b(nullptr);
+  pinv_carve(b, p, q);
+  b.take((size_t)std::min(p, q) * 4);
+  return b.used + 256;
+}
+
 size_t qcur_gemm_workspace(int64_t M, int64_t N, int64_t K, int compute) {
   if (M <= 0 || N <= 0 || K <= 0 || !valid_dtype(compute)) return 0;
   return gemm_workspace(M, N, K, compute);
@@ -1711,6 +1719,49 @@ qcur_status qcur_pinv(qcur_handle h, const qcur_qmat* X, double rtol, int64_t ma
   PinvPlan pl = pinv_plan(X->rows, X->cols);
   GroupWs gw = group_carve(b, 1, pl.pp, pl.qq);
   return pinv_impl(h->c, view_of(*X), rtol, max_rank, view_of(*Xp), rank_out, w, gw);
+}
+
+// ---- thin QSVD
+qcur_status qcur_svd(qcur_handle h, const qcur_qmat* X, double* s, qcur_qmat* U, qcur_qmat* V, void* ws,
+                     size_t ws_bytes) {
+  CHK(check_qmat(X, "X"));
+  if (X->rows < 1 || X->cols < 1) return fail(QCUR_ERR_SHAPE, "X must have at least one row and column");
+  if (!s) return fail(QCUR_ERR_ARG, "s is NULL");
+  const int64_t p = X->rows, q = X->cols, k = std::min(p, q);
+  if (U) {
+    CHK(check_qmat(U, "U"));
+    CHK(check_dims(U, "U", p, k));
+    if (U->dtype != QCUR_F64) return fail(QCUR_ERR_DTYPE, "U must be FP64");
+  }
+  if (V) {
+    CHK(check_qmat(V, "V"));
+    CHK(check_dims(V, "V", q, k));
+    if (V->dtype != QCUR_F64) return fail(QCUR_ERR_DTYPE, "V must be FP64");
+  }
+  const size_t need = qcur_svd_workspace(p, q);
+  if (!ws || ws_bytes < need) return fail(QCUR_ERR_WORKSPACE, "svd needs %zu workspace bytes", need);
+  CHK(check_handle(h));
+  const Ctx& c = h->c;
+  Bump b(ws);
+  PinvWs w = pinv_carve(b, p, q);
+  int32_t* rank = (int32_t*)b.take((size_t)k * 4);
+  PinvPlan pl = pinv_plan(p, q);
+  const int64_t pp = pl.pp, qq = pl.qq;
+  const QView Xv = view_of(*X);
+  HIPCHK(launch_check_finite(c, Xv));
+  QView Yv{w.Y, qq, pp, pp, qq * pp, QCUR_F64};
+  HIPCHK(launch_cast(c, Xv, Yv, pl.tall ? CAST_T : CAST_CONJ));
+  HIPCHK(launch_fill_identity(c, w.V, qq));
+  const double tol = std::sqrt((double)pp) * std::ldexp(1.0, -53);
+  if (jacobi_small_fits(pp, qq)) {
+    HIPCHK(launch_jacobi_small(c, w.Y, pp, qq, w.V, tol, MAX_SWEEPS, w.flag));
+  } else {
+    CHK(jacobi_sweeps(c, w, pp, qq, tol, 0.0));  // rtol 0: every column is kept
+  }
+  HIPCHK(launch_svd_out(c, w.Y, pp, qq, w.V, w.sig, rank, s, pl.tall, U ? (double*)U->p : nullptr,
+                        U ? U->ld : 0, U ? U->pstride : 0, V ? (double*)V->p : nullptr, V ? V->ld : 0,
+                        V ? V->pstride : 0));
+  return QCUR_OK;
 }
 
 // ---- gemm

@@ -401,6 +401,64 @@ hipError_t launch_pinv_apply(const Ctx& c, double* Y, int64_t p, int64_t q, doub
   return hipGetLastError();
 }
 
+// ---- thin QSVD output ---------------------------------------------------
+// After the sweeps the columns Y_i of Y = Z V are orthogonal with
+// sigma_i = ||Y_i||.  Rank of column i in descending order (ties by index).
+__global__ __launch_bounds__(1024) void k_svd_rank(const double* __restrict__ sig2, int64_t q,
+                                                   int32_t* __restrict__ rank, double* __restrict__ s) {
+  for (int64_t i = threadIdx.x; i < q; i += 1024) {
+    const double v = sig2[i];
+    int64_t r = 0;
+    for (int64_t j = 0; j < q; ++j) {
+      const double w = sig2[j];
+      r += (w > v || (w == v && j < i)) ? 1 : 0;
+    }
+    rank[i] = (int32_t)r;
+    s[r] = sqrt(v);
+  }
+}
+
+// Column i goes to output column rank[i]: Y_i / sigma_i and V_i into the
+// left / right factors (tall: U <- Y, Vout <- V; wide: U <- V, Vout <- Y).
+// Columns with sigma_i = 0 give zero vectors.  One workgroup per column.
+__global__ __launch_bounds__(256) void k_svd_vectors(const double* __restrict__ Y, int64_t pp, int64_t qq,
+                                                     const double* __restrict__ V, const double* __restrict__ sig2,
+                                                     const int32_t* __restrict__ rank, int tall, double* U,
+                                                     int64_t uld, int64_t ups, double* Vo, int64_t vld,
+                                                     int64_t vps) {
+  const int64_t i = blockIdx.x;
+  const int64_t r = rank[i];
+  const double sg = sqrt(sig2[i]);
+  const double inv = sg > 0.0 ? 1.0 / sg : 0.0;
+  const int64_t psy = qq * pp, psv = qq * qq;
+  double* Yo = tall ? U : Vo;  // destination of Y_i / sigma_i (pp rows)
+  const int64_t yld = tall ? uld : vld, yps = tall ? ups : vps;
+  double* Vd = tall ? Vo : U;  // destination of V_i (qq rows)
+  const int64_t dld = tall ? vld : uld, dps = tall ? vps : ups;
+  if (Yo) {
+    for (int64_t k = threadIdx.x; k < pp; k += 256) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) Yo[k * yld + r + c * yps] = Y[c * psy + i * pp + k] * inv;
+    }
+  }
+  if (Vd) {
+    for (int64_t k = threadIdx.x; k < qq; k += 256) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) Vd[k * dld + r + c * dps] = V[c * psv + i * qq + k];
+    }
+  }
+}
+
+hipError_t launch_svd_out(const Ctx& c, const double* Y, int64_t pp, int64_t qq, const double* V, double* sig2,
+                          int32_t* rank, double* s, bool tall, double* U, int64_t uld, int64_t ups, double* Vo,
+                          int64_t vld, int64_t vps) {
+  hipLaunchKernelGGL(k_row_norm2, dim3((unsigned)qq), dim3(256), 0, c.stream, Y, pp, qq, sig2);
+  hipLaunchKernelGGL(k_svd_rank, dim3(1), dim3(1024), 0, c.stream, sig2, qq, rank, s);
+  hipLaunchKernelGGL(k_svd_vectors, dim3((unsigned)qq), dim3(256), 0, c.stream, Y, pp, qq, V, sig2, rank,
+                     tall ? 1 : 0, U, uld, ups, Vo, vld, vps);
+  return hipGetLastError();
+}
+
 }  // namespace qcur
 
 namespace qcur {

@@ -135,6 +135,9 @@ hipError_t launch_deflation_check(const Ctx& c, const double* Y, int64_t p, int6
 hipError_t launch_jacobi_small(const Ctx& c, double* Y, int64_t p, int64_t q, double* V,
                                double tol, int max_sweeps, unsigned* rotated);
 bool jacobi_small_fits(int64_t p, int64_t q);
+hipError_t launch_svd_out(const Ctx& c, const double* Y, int64_t pp, int64_t qq, const double* V, double* sig2,
+                          int32_t* rank, double* s, bool tall, double* U, int64_t uld, int64_t ups, double* Vo,
+                          int64_t vld, int64_t vps);
 hipError_t launch_pinv_scale(const Ctx& c, double* Y, int64_t p, int64_t q, double rtol,
                              int64_t max_rank, int64_t* rank_out, double* sig);
 hipError_t launch_check_finite(const Ctx& c, QView X);

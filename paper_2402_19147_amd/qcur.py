@@ -88,6 +88,8 @@ def _declare(L):
                                             c_int, c_d, QP, c_p, c_p, c_p, c_p, c_p, c_sz]),
         "qcur_complete_resampled_workspace": (c_sz, [c_i64, c_i64, c_i64, c_i64, c_int, c_int]),
         "qcur_sample_size": (c_i64, [c_i64, c_i64]),
+        "qcur_svd": (c_int, [c_p, QP, c_p, QP, QP, c_p, c_sz]),
+        "qcur_svd_workspace": (c_sz, [c_i64, c_i64]),
         "qcur_solve_batched": (c_int, [c_p, ctypes.c_int32, c_p, QP, c_i64, c_int, c_int, c_u64, c_int, c_int, c_d,
                                        c_i64, c_p, c_p, QP, c_i64, c_p, c_p, c_p, c_p, c_p, c_sz]),
     }
@@ -478,6 +480,20 @@ def complete_resampled(Y: torch.Tensor, mask: torch.Tensor, r: int, c: int, samp
                                          rtol, max_rank, max_iter, tol, _qp(X), _ptr(I), _ptr(J),
                                          ctypes.byref(iters), ctypes.byref(rel), _ptr(ws), ws.numel()))
     return X, iters.value, rel.value, I, J
+
+
+def svd(X: torch.Tensor, vectors: bool = True):
+    """Thin QSVD X = U diag(s) V^H (one-sided Jacobi, FP64).  Returns (s, U, V)
+    with s descending (k = min(p, q)); U, V are None when vectors is False."""
+    _, p, q = X.shape
+    k = min(p, q)
+    s = torch.empty(k, dtype=torch.float64, device=X.device)
+    U = empty(p, k, torch.float64, X.device) if vectors else None
+    V = empty(q, k, torch.float64, X.device) if vectors else None
+    ws = _ws(lib().qcur_svd_workspace(p, q), X.device)
+    _check(lib().qcur_svd(_h(X), _qp(X), _ptr(s), _qp(U) if vectors else None, _qp(V) if vectors else None,
+                          _ptr(ws), ws.numel()))
+    return s, U, V
 
 
 def sample_size(k: int, limit: int) -> int:

@@ -209,3 +209,20 @@ def test_complete_resampled_workspace_and_validation(L):
     assert call(r=51) == 1 and "exceed" in L.qcur_last_error().decode()
     assert call(nbytes=16) == 4
     assert call(X=qm(50, 40, Q.F64)) == 3
+
+
+def test_svd_workspace_and_validation(L):
+    assert L.qcur_svd_workspace(300, 70) > 0 and L.qcur_svd_workspace(0, 5) == 0
+    X = qm(30, 20)
+
+    def call(X=X, s=FAKE, U=qm(30, 20), V=qm(20, 20), nbytes=1 << 30):
+        return L.qcur_svd(None, X, s, U, V, FAKE, nbytes)
+
+    assert call() == 1                      # valid: only the NULL handle is rejected
+    assert call(U=None, V=None) == 1
+    assert call(s=None) == 1 and "s is NULL" in L.qcur_last_error().decode()
+    assert call(U=qm(30, 21)) == 2
+    assert call(V=qm(21, 20)) == 2
+    assert call(U=qm(30, 20, Q.F32)) == 3
+    assert call(nbytes=8) == 4
+    assert call(X=qm(0, 20)) == 2

@@ -269,6 +269,58 @@ def test_pinv_rank_deficient_deflated_jacobi(p, q, k, mr):
     assert rel(qmul(qmul(X, N(Xp)), X), X) < 1e-11
 
 
+# ---------------------------------------------------------------- thin QSVD
+def _qH(X):
+    Y = np.swapaxes(X, 1, 2).copy()
+    Y[1:] *= -1
+    return Y
+
+
+@pytest.mark.parametrize("p,q,k", [(1, 1, 0), (7, 5, 0), (40, 40, 0), (60, 13, 0), (13, 60, 0), (300, 70, 0),
+                                   (70, 300, 0), (257, 129, 0), (200, 150, 30)])
+def test_svd_matches_checker(p, q, k):
+    # singular values against the checker; U, V orthonormal on the nonzero
+    # singular values and U diag(s) V^H = X
+    from oracle.pinv import singular_values
+    rng = np.random.default_rng(p * 1000 + q + k)
+    X = (qmul(rng.standard_normal((4, p, k)), rng.standard_normal((4, k, q))) if k
+         else rng.standard_normal((4, p, q)))
+    s, U, V = Q.svd(T(X))
+    Q.sync_status()
+    s, U, V = N(s), N(U), N(V)
+    sv = singular_values(X)
+    n = min(p, q)
+    assert s.shape == (n,) and np.all(np.diff(s) <= 0)
+    keep = sv > 1e-10 * sv[0]
+    assert np.max(np.abs(s[keep] - sv[keep]) / sv[keep]) < 1e-12
+    assert np.all(s[~keep] < 1e-10 * sv[0])
+    nk = int(keep.sum())
+    G = qmul(_qH(U[:, :, :nk]), U[:, :, :nk])
+    H = qmul(_qH(V[:, :, :nk]), V[:, :, :nk])
+    E = np.zeros_like(G)
+    E[0] = np.eye(nk)
+    assert np.abs(G - E).max() < 1e-12 and np.abs(H - E).max() < 1e-12
+    B = qmul(U * s[None, None, :], _qH(V))
+    assert rel(B, X) < 1e-12
+
+
+def test_svd_zero_matrix_and_values_only():
+    # p >= q: the left factor comes from the (zero) orthogonalised columns,
+    # the right factor stays unitary
+    s, U, V = Q.svd(torch.zeros((4, 9, 6), dtype=torch.float64, device=DEV))
+    Q.sync_status()
+    assert not N(s).any() and not N(U).any()
+    H = qmul(_qH(N(V)), N(V))
+    assert np.abs(H[0] - np.eye(6)).max() < 1e-15 and not H[1:].any()
+    rng = np.random.default_rng(8)
+    X = rng.standard_normal((4, 50, 30))
+    s, U, V = Q.svd(T(X), vectors=False)
+    Q.sync_status()
+    from oracle.pinv import singular_values
+    assert U is None and V is None
+    assert np.max(np.abs(N(s) - singular_values(X)) / singular_values(X)) < 1e-12
+
+
 def test_pinv_zero_matrix():
     Xp, rank = Q.pinv(torch.zeros((4, 6, 4), dtype=torch.float64, device=DEV))
     assert int(N(rank)[0]) == 0 and not N(Xp).any()
