@@ -167,6 +167,7 @@ def main():
         extra["dense_4096"] = bench_dense(q, torch, workloads, dev, args)
         extra["complete_512x768"] = bench_complete(q, torch, workloads, dev)
         extra["adjoint_2048"] = bench_adjoint(q, torch, workloads, dev, args)
+        extra["qsvd_500"] = bench_qsvd(q, torch, workloads, dev)
     # a plain copy of known size, for scaling HBM byte counters of profiled runs
     src = torch.empty(64 * 2 ** 20, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
@@ -407,6 +408,46 @@ def bench_complete(q, torch, workloads, dev):
                                        ms_per_iter=dt_s * 1e3 / max(iters, 1), total_ms=dt_s * 1e3,
                                        rel_err_missing_vs_noiseless=err)
     log(f"complete f32 resampled: {iters} steps, {dt_s * 1e3 / max(iters, 1):.3f} ms/step, err {err:.4f}")
+    return out
+
+
+def bench_qsvd(q, torch, workloads, dev):
+    """Example 4.2's comparison on one 500 x 500 rank-10 + N(0, 1e-4^2)
+    quaternion matrix: QMCUR (length sampling, c = r = ceil(k ln k), FP64,
+    least-squares core) against the thin QSVD of the whole matrix (Jacobi,
+    FP64) and its rank-k truncation."""
+    cfg = workloads.WORKLOADS["qsvd_500"]
+    m, n, k, seed = cfg["m"], cfg["n"], cfg["k"], cfg["seed"]
+    L, Rt, E = workloads.lowrank_gaussian_factors(m, n, k, seed, cfg["noise"])
+    A = quaternion_product_torch(torch, torch.tensor(L, device=dev), torch.tensor(Rt, device=dev))
+    A = A + torch.tensor(E, device=dev)
+    nA = float(torch.linalg.vector_norm(A))
+    c = q.sample_size(k, min(m, n))
+    S = q.Solver(m, n, c, c, core=q.CORE_CAR, compute=q.F64)
+    for _ in range(3):
+        S(A, seed=seed)
+    torch.cuda.synchronize()
+    reps = 20
+    t0 = time.perf_counter()
+    for i in range(reps):
+        S(A, seed=seed + i)
+    torch.cuda.synchronize()
+    t_cur = (time.perf_counter() - t0) / reps
+    res = float(S.residual.cpu()[0]) / nA
+    q.svd(A)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s, U, V = q.svd(A)
+    torch.cuda.synchronize()
+    t_svd = time.perf_counter() - t0
+    q.sync_status()
+    sv = s.cpu().numpy()
+    err_k = float((sv[k:] ** 2).sum() ** 0.5 / nA)
+    out = {"workload": "500x500 quaternion, rank 10 N(0,1) factors + N(0,1e-4^2); QMCUR length sampling "
+                       f"c=r={c}, FP64, U=C^+AR^+; QSVD: thin Jacobi SVD of A, FP64",
+           "qmcur_ms": t_cur * 1e3, "qmcur_rel_err": res, "qsvd_ms": t_svd * 1e3, "qsvd_rank_k_rel_err": err_k,
+           "qsvd_over_qmcur_time": t_svd / t_cur}
+    log(f"qsvd 500: {t_svd * 1e3:.1f} ms (rank-10 err {err_k:.2e}) vs QMCUR {t_cur * 1e3:.3f} ms (err {res:.2e})")
     return out
 
 

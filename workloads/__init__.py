@@ -150,4 +150,6 @@ WORKLOADS = {
     # c = r = ceil(20 ln 20) = 60 fixed uniform index sets, t_max 200, tol 1e-4
     "complete_512x768": dict(kind="color", m=512, n=768, k=20, noise=0.01, c=60, r=60, mask_p=0.3,
                              max_iter=200, tol=1e-4, seed=6),
+    # Example 4.2 shape: rank 10 plus noise, QMCUR against the QSVD baseline
+    "qsvd_500": dict(kind="product", m=500, n=500, k=10, noise=1e-4, sampling="length", core="car", seed=7),
 }
