@@ -330,9 +330,12 @@ qcur_status pinv_fast_group(const Ctx& c, int nb, const QView* X, double rtol, i
   double* Pf = w.P1;
   double* Qf = w.Q1;
   int ok[MAXB] = {0, 0, 0, 0};
-  auto decide_and_read = [&]() -> qcur_status {
+  // one host synchronisation: the fast-path verdicts and, when given, the
+  // norms behind them
+  auto decide_and_read = [&](double* nrm_out = nullptr) -> qcur_status {
     HIPCHK(launch_pinv_decide(c, w.norms, w.fail, rtol, max_rank, nb, qb, rank_out, w.ok));
     HIPCHK(hipMemcpyAsync(ok, w.ok, sizeof(int) * nb, hipMemcpyDeviceToHost, c.stream));
+    if (nrm_out) HIPCHK(hipMemcpyAsync(nrm_out, w.norms, sizeof(double) * 4 * nb, hipMemcpyDeviceToHost, c.stream));
     HIPCHK(hipStreamSynchronize(c.stream));
     return QCUR_OK;
   };
@@ -345,10 +348,8 @@ qcur_status pinv_fast_group(const Ctx& c, int nb, const QView* X, double rtol, i
     have_g2 = true;
     HIPCHK(launch_defect_batch(c, nb, w.G, qq, gslab, qb, w.part, w.norms + 3, 4));
     HIPCHK(launch_sumsq_batch(c, nb, Pr, w.part, w.norms + 2, 4));
-    CHK(decide_and_read());
     double nrm[4 * MAXB];
-    HIPCHK(hipMemcpyAsync(nrm, w.norms, sizeof(double) * 4 * nb, hipMemcpyDeviceToHost, c.stream));
-    HIPCHK(hipStreamSynchronize(c.stream));
+    CHK(decide_and_read(nrm));
     for (int b = 0; b < nb; ++b) second |= ok[b] && !(nrm[4 * b + 3] <= orth_tol * orth_tol);
   }
   if (second) {
