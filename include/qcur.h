@@ -57,6 +57,14 @@ typedef enum {
 } qcur_status;
 
 typedef enum { QCUR_F64 = 0, QCUR_F32 = 1, QCUR_BF16 = 2 } qcur_dtype;
+/* Product precision ("compute") of the calls that take one: a qcur_dtype
+ * (operands stored in that dtype; BF16 products accumulate in FP32), or
+ * QCUR_BF16X3: FP32 operands, each element split into BF16 hi = bf16(x) and
+ * lo = bf16(x - hi) when staged, products hi.hi + hi.lo + lo.hi on BF16
+ * matrix cores with FP32 accumulation (about 2^-16 relative error per
+ * product, against 2^-24 for FP32 and 2^-9 for BF16).  Not offered by the
+ * batched solve. */
+enum { QCUR_BF16X3 = 3 };
 typedef enum { QCUR_OP_N = 0, QCUR_OP_H = 1 } qcur_op;           /* H: conjugate transpose */
 typedef enum { QCUR_LENGTH = 0, QCUR_UNIFORM = 1 } qcur_sampling;
 typedef enum { QCUR_CORE_WPINV = 0, QCUR_CORE_CAR = 1 } qcur_core;

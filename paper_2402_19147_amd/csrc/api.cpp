@@ -73,6 +73,7 @@ qcur_status fail(qcur_status s, const char* fmt, ...) {
   } while (0)
 
 bool valid_dtype(int dt) { return dt == QCUR_F64 || dt == QCUR_F32 || dt == QCUR_BF16; }
+bool valid_compute(int c) { return valid_dtype(c) || c == QCUR_BF16X3; }
 
 // Shape/stride/dtype checks of one operand.
 qcur_status check_qmat(const qcur_qmat* m, const char* name) {
@@ -124,7 +125,7 @@ struct Bump {
 };
 
 int acc_dt(int compute) { return compute == QCUR_F64 ? QCUR_F64 : QCUR_F32; }
-int in_dt(int compute) { return compute; }
+int in_dt(int compute) { return compute == QCUR_BF16X3 ? QCUR_F32 : compute; }
 
 // ---- pseudoinverse -------------------------------------------------------
 struct PinvPlan {
@@ -642,7 +643,7 @@ qcur_status approx_run(const Ctx& c, const ApproxArgs& a, int64_t m, int64_t n, 
         // FP64 products: CholeskyQR2; FP32/BF16 products: a second pass only
         // when the first leaves Q^H Q - I above a small fraction of their
         // rounding unit
-        const double orth_tol = a.compute == QCUR_F64 ? 0.0 : a.compute == QCUR_F32 ? 0x1p-26 : 0x1p-12;
+        const double orth_tol = a.compute == QCUR_F64 ? 0.0 : a.compute == QCUR_BF16 ? 0x1p-12 : 0x1p-26;
         CHK(pinv_group_qp(c, 2, xs, a.rtol, a.max_rank, ro, gw, jw, Qv, Pv, orth_tol));
       } else {
         Qv[0] = QView{nullptr, m, cc, cc, m * cc, QCUR_F64};
@@ -669,7 +670,7 @@ qcur_status approx_run(const Ctx& c, const ApproxArgs& a, int64_t m, int64_t n, 
     const bool need_E = a.refine > 0;
     QView E = need_E ? b.mat(m, n, adt) : QView{};
     QView Ex = need_E ? ((idt == adt) ? E : b.mat(m, n, idt)) : QView{};
-    double* part = (double*)b.take(std::max<size_t>(residual_tiles(m, n), 1) * 8);
+    double* part = (double*)b.take(std::max<size_t>(residual_tiles(m, n, a.compute), 1) * 8);
     size_t gw = std::max({gemm_workspace(m, r, n, a.compute), gemm_workspace(cc, r, m, a.compute),
                           gemm_workspace(m, r, cc, a.compute), gemm_workspace(m, n, r, a.compute),
                           gemm_workspace(cc, r, r, QCUR_F64), gemm_workspace(cc, r, cc, QCUR_F64)});
@@ -698,7 +699,7 @@ qcur_status approx_run(const Ctx& c, const ApproxArgs& a, int64_t m, int64_t n, 
     if (a.fro) {
       // ||A - C U R||_F = ||A - Q_C M Q_R^H||_F
       HIPCHK(launch_residual_gemm(c, a.A, B1x, Qr, nullptr, 0, a.compute, part, nullptr, 0.0, QCUR_OP_H));
-      HIPCHK(launch_sum_partials(c, part, (int64_t)residual_tiles(m, n), a.fro, 1));
+      HIPCHK(launch_sum_partials(c, part, (int64_t)residual_tiles(m, n, a.compute), a.fro, 1));
     }
     if (a.hasB) HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_H, 1.0, B1x, Qr, 0.0, a.B, a.compute, gws, gw));
     // U = P_C^H (M P_R) in FP64
@@ -759,12 +760,12 @@ qcur_status residual_run(const Ctx& c, QView A, QView C, QView U, QView R, const
   QView B1x = (idt == adt) ? B1 : b.mat(m, r, idt);
   size_t gw = gemm_workspace(m, r, C.cols, compute);
   void* gws = b.take(gw);
-  double* part = (double*)b.take(std::max<size_t>(residual_tiles(m, n), 1) * 8);
+  double* part = (double*)b.take(std::max<size_t>(residual_tiles(m, n, compute), 1) * 8);
   if (count_only) return QCUR_OK;
   HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Cx, Ux, 0.0, B1, compute, gws, gw));
   if (B1x.p != B1.p) HIPCHK(launch_cast(c, B1, B1x, CAST_COPY));
   HIPCHK(launch_residual_gemm(c, A, B1x, Rx, mask, mask_ld, compute, part, E, e_scale));
-  HIPCHK(launch_sum_partials(c, part, (int64_t)residual_tiles(m, n), out, take_sqrt));
+  HIPCHK(launch_sum_partials(c, part, (int64_t)residual_tiles(m, n, compute), out, take_sqrt));
   return QCUR_OK;
 }
 
@@ -1085,6 +1086,7 @@ qcur_status check_batch_shape(int count, const int32_t* dims, int a_dt, int samp
   if (count < 1 || count > 16384) return fail(QCUR_ERR_ARG, "count must be in [1, 16384]");
   if (!dims) return fail(QCUR_ERR_ARG, "dims is NULL");
   if (!valid_dtype(a_dt)) return fail(QCUR_ERR_DTYPE, "unknown dtype of A");
+  if (compute == QCUR_BF16X3) return fail(QCUR_ERR_UNSUPPORTED, "split BF16 is not offered for batches");
   if (!valid_dtype(compute)) return fail(QCUR_ERR_DTYPE, "unknown compute dtype");
   if (sampling != QCUR_LENGTH && sampling != QCUR_UNIFORM) return fail(QCUR_ERR_ARG, "unknown sampling %d", sampling);
   if (refine < 0) return fail(QCUR_ERR_ARG, "refine_steps must be >= 0");
@@ -1409,7 +1411,7 @@ qcur_status complete_run(const Ctx& c, const CompleteArgs& a, Bump& b, bool coun
   QView T = b.mat(m, r, adt), Tx = (idt == adt) ? T : b.mat(m, r, idt);
   QView M = b.mat(cc, r, adt), Mx = (idt == adt) ? M : b.mat(cc, r, idt);
   QView B1 = b.mat(m, r, adt), B1x = (idt == adt) ? B1 : b.mat(m, r, idt);
-  const int64_t tiles = (int64_t)std::max<size_t>(residual_tiles(m, n), 1);
+  const int64_t tiles = (int64_t)std::max<size_t>(residual_tiles(m, n, a.compute), 1);
   double* pd = (double*)b.take((size_t)tiles * 8);
   double* po = (double*)b.take((size_t)tiles * 8);
   double* sums = (double*)b.take(16);
@@ -1430,7 +1432,7 @@ qcur_status complete_run(const Ctx& c, const CompleteArgs& a, Bump& b, bool coun
   HIPCHK(launch_mask_init(c, a.Y, a.mask, a.mask_ld, a.X));
   // the iterate of step t lives in cur; the next goes to nxt
   QView cur = a.X, nxt = Xw;
-  const double orth_tol = a.compute == QCUR_F64 ? 0.0 : a.compute == QCUR_F32 ? 0x1p-26 : 0x1p-12;
+  const double orth_tol = a.compute == QCUR_F64 ? 0.0 : a.compute == QCUR_BF16 ? 0x1p-12 : 0x1p-26;
   int t = 0;
   double rel = INFINITY;
   while (t < a.max_iter) {
@@ -1587,12 +1589,12 @@ size_t qcur_svd_workspace(int64_t p, int64_t q) {
 }
 
 size_t qcur_gemm_workspace(int64_t M, int64_t N, int64_t K, int compute) {
-  if (M <= 0 || N <= 0 || K <= 0 || !valid_dtype(compute)) return 0;
+  if (M <= 0 || N <= 0 || K <= 0 || !valid_compute(compute)) return 0;
   return gemm_workspace(M, N, K, compute);
 }
 
 size_t qcur_approx_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int core, int compute) {
-  if (m < 0 || n < 0 || c < 0 || r < 0 || !valid_dtype(compute)) return 0;
+  if (m < 0 || n < 0 || c < 0 || r < 0 || !valid_compute(compute)) return 0;
   Ctx dummy{0, nullptr, nullptr};
   ApproxArgs a = sizing_args(m, n, c, r, core, compute);
   Bump b(nullptr);
@@ -1604,7 +1606,7 @@ size_t qcur_approx_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int cor
 }
 
 size_t qcur_residual_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int compute) {
-  if (m < 0 || n < 0 || c < 0 || r < 0 || !valid_dtype(compute)) return 0;
+  if (m < 0 || n < 0 || c < 0 || r < 0 || !valid_compute(compute)) return 0;
   Ctx dummy{0, nullptr, nullptr};
   const int other = compute == QCUR_F64 ? QCUR_F32 : QCUR_F64;
   QView A{nullptr, m, n, n, m * n, other}, C{nullptr, m, c, c, m * c, other};
@@ -1773,9 +1775,9 @@ qcur_status qcur_gemm(qcur_handle h, int opA, int opB, double alpha, const qcur_
   CHK(check_qmat(D, "D"));
   if ((opA != QCUR_OP_N && opA != QCUR_OP_H) || (opB != QCUR_OP_N && opB != QCUR_OP_H))
     return fail(QCUR_ERR_ARG, "op must be QCUR_OP_N or QCUR_OP_H");
-  if (!valid_dtype(compute)) return fail(QCUR_ERR_DTYPE, "unknown compute dtype");
-  if (A->dtype != compute || B->dtype != compute || D->dtype != acc_dt(compute))
-    return fail(QCUR_ERR_DTYPE, "operands must be in the compute dtype (BF16: D FP32)");
+  if (!valid_compute(compute)) return fail(QCUR_ERR_DTYPE, "unknown compute dtype");
+  if (A->dtype != in_dt(compute) || B->dtype != in_dt(compute) || D->dtype != acc_dt(compute))
+    return fail(QCUR_ERR_DTYPE, "operands must be in the compute dtype (BF16: D FP32; split BF16: all FP32)");
   const int64_t M = opA == QCUR_OP_N ? A->rows : A->cols;
   const int64_t K = opA == QCUR_OP_N ? A->cols : A->rows;
   const int64_t K2 = opB == QCUR_OP_N ? B->rows : B->cols;
@@ -1793,7 +1795,7 @@ qcur_status qcur_approx(qcur_handle h, const qcur_qmat* A, const qcur_qmat* C, c
                         const qcur_qmat* W, int core, int compute, int refine_steps, double rtol, int64_t max_rank,
                         qcur_qmat* U, qcur_qmat* B, int64_t* rank_out, void* ws, size_t ws_bytes) {
   if (core != QCUR_CORE_WPINV && core != QCUR_CORE_CAR) return fail(QCUR_ERR_ARG, "unknown core %d", core);
-  if (!valid_dtype(compute)) return fail(QCUR_ERR_DTYPE, "unknown compute dtype");
+  if (!valid_compute(compute)) return fail(QCUR_ERR_DTYPE, "unknown compute dtype");
   if (refine_steps < 0) return fail(QCUR_ERR_ARG, "refine_steps must be >= 0");
   if (!std::isfinite(rtol)) return fail(QCUR_ERR_ARG, "rtol must be finite");
   if (max_rank < 0) return fail(QCUR_ERR_ARG, "max_rank must be >= 0");
@@ -1861,7 +1863,7 @@ qcur_status qcur_residual(qcur_handle h, const qcur_qmat* A, const qcur_qmat* C,
   CHK(check_qmat(C, "C"));
   CHK(check_qmat(U, "U"));
   CHK(check_qmat(R, "R"));
-  if (!valid_dtype(compute)) return fail(QCUR_ERR_DTYPE, "unknown compute dtype");
+  if (!valid_compute(compute)) return fail(QCUR_ERR_DTYPE, "unknown compute dtype");
   const int64_t m = A->rows, n = A->cols, cc = C->cols, r = R->rows;
   CHK(check_dims(C, "C", m, cc));
   CHK(check_dims(U, "U", cc, r));
@@ -1937,7 +1939,7 @@ static qcur_status check_solve(const qcur_qmat* A, int64_t c, int64_t r, int sam
   if (A->rows < 1 || A->cols < 1) return fail(QCUR_ERR_SHAPE, "A must have at least one row and column");
   if (sampling != QCUR_LENGTH && sampling != QCUR_UNIFORM) return fail(QCUR_ERR_ARG, "unknown sampling %d", sampling);
   if (core != QCUR_CORE_WPINV && core != QCUR_CORE_CAR) return fail(QCUR_ERR_ARG, "unknown core %d", core);
-  if (!valid_dtype(compute)) return fail(QCUR_ERR_DTYPE, "unknown compute dtype");
+  if (!valid_compute(compute)) return fail(QCUR_ERR_DTYPE, "unknown compute dtype");
   if (with_replacement != 0 && with_replacement != 1) return fail(QCUR_ERR_ARG, "with_replacement must be 0 or 1");
   if (c < 1 || r < 1) return fail(QCUR_ERR_ARG, "c and r must be >= 1");
   if (!with_replacement && (c > A->cols || r > A->rows)) return fail(QCUR_ERR_ARG, "c > n or r > m without replacement");
@@ -1950,7 +1952,7 @@ static qcur_status check_solve(const qcur_qmat* A, int64_t c, int64_t r, int sam
 }
 
 size_t qcur_solve_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int core, int compute) {
-  if (m < 1 || n < 1 || c < 1 || r < 1 || !valid_dtype(compute)) return 0;
+  if (m < 1 || n < 1 || c < 1 || r < 1 || !valid_compute(compute)) return 0;
   // the input may come in any dtype: size for the largest element
   SolveArgs s{};
   s.A = QView{nullptr, m, n, n, m * n, QCUR_F64};
@@ -2172,7 +2174,7 @@ qcur_status qcur_solve_batched(qcur_handle h, int32_t count, const int32_t* dims
 
 // ---- completion -----------------------------------------------------------------
 size_t qcur_complete_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int compute) {
-  if (m < 1 || n < 1 || c < 1 || r < 1 || (compute != QCUR_F64 && compute != QCUR_F32 && compute != QCUR_BF16))
+  if (m < 1 || n < 1 || c < 1 || r < 1 || !valid_compute(compute))
     return 0;
   CompleteArgs a{};
   a.Y = QView{nullptr, m, n, n, m * n, QCUR_F64};
@@ -2237,8 +2239,7 @@ qcur_status complete_entry(qcur_handle h, const qcur_qmat* Y, const uint8_t* mas
   CHK(check_qmat(X, "X"));
   if (Y->rows < 1 || Y->cols < 1) return fail(QCUR_ERR_SHAPE, "Y must have at least one row and column");
   CHK(check_dims(X, "X", Y->rows, Y->cols));
-  if (compute != QCUR_F64 && compute != QCUR_F32 && compute != QCUR_BF16)
-    return fail(QCUR_ERR_DTYPE, "unknown compute dtype");
+  if (!valid_compute(compute)) return fail(QCUR_ERR_DTYPE, "unknown compute dtype");
   if (X->dtype != acc_dt(compute)) return fail(QCUR_ERR_DTYPE, "X must be FP64 (F64 compute) or FP32");
   if (!mask || mask_ld < Y->cols) return fail(QCUR_ERR_ARG, "mask is NULL or mask_ld < n");
   if (!I || !J || r < 1 || c < 1 || r > Y->rows || c > Y->cols) return fail(QCUR_ERR_ARG, "bad index sets");

@@ -78,6 +78,22 @@ template <> struct MT<QCUR_BF16> {
   }
 };
 
+// Split BF16: FP32 operands, each element x staged as hi = bf16(x) and
+// lo = bf16(x - hi); a product is hi.hi + hi.lo + lo.hi on BF16 MFMAs with
+// FP32 accumulation (the lo.lo term is below FP32 rounding of the sum).
+template <> struct MT<QCUR_BF16X3> {
+  typedef float In;
+  typedef float Acc;
+  typedef f32x4 AccV;
+  typedef bf16x8 Frag;
+  static constexpr int BK = 32, KM = 32, PAD = 8;
+  static __device__ inline int out_row(int lane, int r) { return (lane >> 4) * 4 + r; }
+  static __device__ inline AccV mfma(Frag a, Frag b, AccV c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline Frag neg(Frag a) { return MT<QCUR_BF16>::neg(a); }
+};
+
 template <typename T> __device__ inline T negv(T v);
 template <> __device__ inline double negv<double>(double v) { return -v; }
 template <> __device__ inline float negv<float>(float v) { return -v; }
@@ -143,6 +159,14 @@ template <int DT, int BM, int BN> struct alignas(16) Smem {
   static constexpr int BR = KMAJ ? BK : BN, BC = KMAJ ? BN + PAD : BK + PAD;
   In a[2][4][AR][AC];  // two stages: one is read by the MFMAs while the
   In b[2][4][BR][BC];  // next K slice is stored into the other
+};
+
+// Split BF16: both halves of each staged FP32 element, [stage][hi, lo][plane][row][k]
+template <int BM, int BN> struct alignas(16) Smem<QCUR_BF16X3, BM, BN> {
+  static constexpr int BK = 32, PAD = 8;
+  static constexpr bool KMAJ = false;
+  uint16_t a[2][2][4][BM][BK + PAD];
+  uint16_t b[2][2][4][BN][BK + PAD];
 };
 
 template <int DT, int EPI, int BM, int BN>
@@ -234,7 +258,13 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
         // conjugation (op H) is applied here, not at the load, so that the
         // loads stay in flight through the MFMAs of the current slice
         const In v = (g.opA == QCUR_OP_H && q > 0) ? negv<In>(ra[q][r]) : ra[q][r];
-        if (KMAJ) sm.a[st][q][k][i] = v; else sm.a[st][q][i][k] = v;
+        if constexpr (DT == QCUR_BF16X3) {
+          const uint16_t hi = f32_to_bf16(v);
+          sm.a[st][0][q][i][k] = hi;
+          sm.a[st][1][q][i][k] = f32_to_bf16(v - bf16_to_f32(hi));
+        } else {
+          if (KMAJ) sm.a[st][q][k][i] = v; else sm.a[st][q][i][k] = v;
+        }
       }
     }
 #pragma unroll
@@ -245,7 +275,13 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const In v = (g.opB == QCUR_OP_H && q > 0) ? negv<In>(rb[q][r]) : rb[q][r];
-        if (KMAJ) sm.b[st][q][k][j] = v; else sm.b[st][q][j][k] = v;
+        if constexpr (DT == QCUR_BF16X3) {
+          const uint16_t hi = f32_to_bf16(v);
+          sm.b[st][0][q][j][k] = hi;
+          sm.b[st][1][q][j][k] = f32_to_bf16(v - bf16_to_f32(hi));
+        } else {
+          if (KMAJ) sm.b[st][q][k][j] = v; else sm.b[st][q][j][k] = v;
+        }
       }
     }
   };
@@ -400,52 +436,87 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
     }
 #pragma unroll
     for (int kk = 0; kk < BK / T::KM; ++kk) {
-      Frag a[4][XB], na[4][XB], b[4][YB];
+      // one quaternion multiply-accumulate of the fragments: sixteen MFMAs
+      auto qmac = [&](const Frag (&a)[4][XB], const Frag (&na)[4][XB], const Frag (&b)[4][YB]) {
 #pragma unroll
-      for (int x = 0; x < XB; ++x) {
-        const int ii = wm + x * 16 + (lane & 15);
+        for (int x = 0; x < XB; ++x)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if constexpr (DT == QCUR_BF16) a[q][x] = *(const Frag*)&sm.a[st][q][ii][kk * 32 + (lane >> 4) * 8];
-          else a[q][x] = sm.a[st][q][ii][kk * 4 + (lane >> 4)];
+          for (int y = 0; y < YB; ++y) {
+            // plane 0: A0B0 - A1B1 - A2B2 - A3B3
+            acc[0][x][y] = T::mfma(a[0][x], b[0][y], acc[0][x][y]);
+            acc[0][x][y] = T::mfma(na[1][x], b[1][y], acc[0][x][y]);
+            acc[0][x][y] = T::mfma(na[2][x], b[2][y], acc[0][x][y]);
+            acc[0][x][y] = T::mfma(na[3][x], b[3][y], acc[0][x][y]);
+            // plane 1: A1B0 + A0B1 - A3B2 + A2B3
+            acc[1][x][y] = T::mfma(a[1][x], b[0][y], acc[1][x][y]);
+            acc[1][x][y] = T::mfma(a[0][x], b[1][y], acc[1][x][y]);
+            acc[1][x][y] = T::mfma(na[3][x], b[2][y], acc[1][x][y]);
+            acc[1][x][y] = T::mfma(a[2][x], b[3][y], acc[1][x][y]);
+            // plane 2: A2B0 + A3B1 + A0B2 - A1B3
+            acc[2][x][y] = T::mfma(a[2][x], b[0][y], acc[2][x][y]);
+            acc[2][x][y] = T::mfma(a[3][x], b[1][y], acc[2][x][y]);
+            acc[2][x][y] = T::mfma(a[0][x], b[2][y], acc[2][x][y]);
+            acc[2][x][y] = T::mfma(na[1][x], b[3][y], acc[2][x][y]);
+            // plane 3: A3B0 - A2B1 + A1B2 + A0B3
+            acc[3][x][y] = T::mfma(a[3][x], b[0][y], acc[3][x][y]);
+            acc[3][x][y] = T::mfma(na[2][x], b[1][y], acc[3][x][y]);
+            acc[3][x][y] = T::mfma(a[1][x], b[2][y], acc[3][x][y]);
+            acc[3][x][y] = T::mfma(a[0][x], b[3][y], acc[3][x][y]);
+          }
+      };
+      if constexpr (DT == QCUR_BF16X3) {
+        // hi.hi + hi.lo + lo.hi, the small terms first
+        Frag ah[4][XB], nah[4][XB], al[4][XB], nal[4][XB], bh[4][YB], bl[4][YB];
+#pragma unroll
+        for (int x = 0; x < XB; ++x) {
+          const int ii = wm + x * 16 + (lane & 15);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            ah[q][x] = *(const Frag*)&sm.a[st][0][q][ii][(lane >> 4) * 8];
+            al[q][x] = *(const Frag*)&sm.a[st][1][q][ii][(lane >> 4) * 8];
+          }
+#pragma unroll
+          for (int q = 1; q < 4; ++q) {
+            nah[q][x] = T::neg(ah[q][x]);
+            nal[q][x] = T::neg(al[q][x]);
+          }
         }
-#pragma unroll
-        for (int q = 1; q < 4; ++q) na[q][x] = T::neg(a[q][x]);
-      }
-#pragma unroll
-      for (int y = 0; y < YB; ++y) {
-        const int jj = wn + y * 16 + (lane & 15);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if constexpr (DT == QCUR_BF16) b[q][y] = *(const Frag*)&sm.b[st][q][jj][kk * 32 + (lane >> 4) * 8];
-          else b[q][y] = sm.b[st][q][jj][kk * 4 + (lane >> 4)];
-        }
-      }
-#pragma unroll
-      for (int x = 0; x < XB; ++x)
 #pragma unroll
         for (int y = 0; y < YB; ++y) {
-          // plane 0: A0B0 - A1B1 - A2B2 - A3B3
-          acc[0][x][y] = T::mfma(a[0][x], b[0][y], acc[0][x][y]);
-          acc[0][x][y] = T::mfma(na[1][x], b[1][y], acc[0][x][y]);
-          acc[0][x][y] = T::mfma(na[2][x], b[2][y], acc[0][x][y]);
-          acc[0][x][y] = T::mfma(na[3][x], b[3][y], acc[0][x][y]);
-          // plane 1: A1B0 + A0B1 - A3B2 + A2B3
-          acc[1][x][y] = T::mfma(a[1][x], b[0][y], acc[1][x][y]);
-          acc[1][x][y] = T::mfma(a[0][x], b[1][y], acc[1][x][y]);
-          acc[1][x][y] = T::mfma(na[3][x], b[2][y], acc[1][x][y]);
-          acc[1][x][y] = T::mfma(a[2][x], b[3][y], acc[1][x][y]);
-          // plane 2: A2B0 + A3B1 + A0B2 - A1B3
-          acc[2][x][y] = T::mfma(a[2][x], b[0][y], acc[2][x][y]);
-          acc[2][x][y] = T::mfma(a[3][x], b[1][y], acc[2][x][y]);
-          acc[2][x][y] = T::mfma(a[0][x], b[2][y], acc[2][x][y]);
-          acc[2][x][y] = T::mfma(na[1][x], b[3][y], acc[2][x][y]);
-          // plane 3: A3B0 - A2B1 + A1B2 + A0B3
-          acc[3][x][y] = T::mfma(a[3][x], b[0][y], acc[3][x][y]);
-          acc[3][x][y] = T::mfma(na[2][x], b[1][y], acc[3][x][y]);
-          acc[3][x][y] = T::mfma(a[1][x], b[2][y], acc[3][x][y]);
-          acc[3][x][y] = T::mfma(a[0][x], b[3][y], acc[3][x][y]);
+          const int jj = wn + y * 16 + (lane & 15);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            bh[q][y] = *(const Frag*)&sm.b[st][0][q][jj][(lane >> 4) * 8];
+            bl[q][y] = *(const Frag*)&sm.b[st][1][q][jj][(lane >> 4) * 8];
+          }
         }
+        qmac(al, nal, bh);
+        qmac(ah, nah, bl);
+        qmac(ah, nah, bh);
+      } else {
+        Frag a[4][XB], na[4][XB], b[4][YB];
+#pragma unroll
+        for (int x = 0; x < XB; ++x) {
+          const int ii = wm + x * 16 + (lane & 15);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            if constexpr (DT == QCUR_BF16) a[q][x] = *(const Frag*)&sm.a[st][q][ii][kk * 32 + (lane >> 4) * 8];
+            else a[q][x] = sm.a[st][q][ii][kk * 4 + (lane >> 4)];
+          }
+#pragma unroll
+          for (int q = 1; q < 4; ++q) na[q][x] = T::neg(a[q][x]);
+        }
+#pragma unroll
+        for (int y = 0; y < YB; ++y) {
+          const int jj = wn + y * 16 + (lane & 15);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            if constexpr (DT == QCUR_BF16) b[q][y] = *(const Frag*)&sm.b[st][q][jj][kk * 32 + (lane >> 4) * 8];
+            else b[q][y] = sm.b[st][q][jj][kk * 4 + (lane >> 4)];
+          }
+        }
+        qmac(a, na, b);
+      }
     }
     __syncthreads();
   }
@@ -612,9 +683,9 @@ __global__ void k_splitk_reduce(const Acc* __restrict__ Pall, int splits, int64_
 struct Plan {
   int tile, splits;
 };
-static Plan plan_of(int64_t M, int64_t N, int64_t K, int bk, int batch) {
+static Plan plan_of(int64_t M, int64_t N, int64_t K, int bk, int batch, int force_tile = 0) {
   const int64_t t64 = ((M + 63) / 64) * ((N + 63) / 64);
-  const int tile = t64 >= 192 ? 64 : 32;
+  const int tile = force_tile ? force_tile : (t64 >= 192 ? 64 : 32);
   const int64_t tiles = ((M + tile - 1) / tile) * ((N + tile - 1) / tile) * std::max(batch, 1);
   const int64_t kt = (K + bk - 1) / bk;
   int s = 1;
@@ -622,7 +693,9 @@ static Plan plan_of(int64_t M, int64_t N, int64_t K, int bk, int batch) {
   return Plan{tile, s};
 }
 
-static int bk_of(int compute) { return compute == QCUR_BF16 ? 32 : 16; }
+static int bk_of(int compute) { return compute == QCUR_BF16 || compute == QCUR_BF16X3 ? 32 : 16; }
+// split BF16 stages two BF16 halves per operand: 32-tiles only
+static int tile_of(int compute) { return compute == QCUR_BF16X3 ? 32 : 0; }
 static size_t acc_size(int compute) { return compute == QCUR_F64 ? 8 : 4; }
 
 size_t gemm_workspace_splits(int64_t M, int64_t N, int compute, int batch, int max_splits) {
@@ -631,7 +704,7 @@ size_t gemm_workspace_splits(int64_t M, int64_t N, int compute, int batch, int m
 }
 
 size_t gemm_workspace(int64_t M, int64_t N, int64_t K, int compute, int batch) {
-  const int s = plan_of(M, N, K, bk_of(compute), batch).splits;
+  const int s = plan_of(M, N, K, bk_of(compute), batch, tile_of(compute)).splits;
   if (s <= 1) return 0;
   return (size_t)batch * s * 4 * (size_t)M * (size_t)N * acc_size(compute);
 }
@@ -640,7 +713,7 @@ template <int DT, int TILE>
 static hipError_t gemm_dt_tile(const Ctx& c, GemmArgs g, void* ws, size_t ws_bytes) {
   constexpr int BK = MT<DT>::BK;
   const int64_t kt = (g.K + BK - 1) / BK;
-  int splits = g.force_splits > 0 ? g.force_splits : plan_of(g.M, g.N, g.K, BK, g.batch).splits;
+  int splits = g.force_splits > 0 ? g.force_splits : plan_of(g.M, g.N, g.K, BK, g.batch, TILE).splits;
   const size_t need = (size_t)g.batch * splits * 4 * (size_t)g.M * (size_t)g.N * acc_size(DT);
   if (splits > 1 && (ws == nullptr || ws_bytes < need)) splits = 1;
   dim3 grid((unsigned)((g.N + TILE - 1) / TILE), (unsigned)((g.M + TILE - 1) / TILE), 1);
@@ -707,6 +780,7 @@ hipError_t launch_gemm_batched(const Ctx& c, int opA, int opB, double alpha, QVi
   switch (compute) {
     case QCUR_F64: return gemm_dt<QCUR_F64>(c, g, ws, ws_bytes);
     case QCUR_F32: return gemm_dt<QCUR_F32>(c, g, ws, ws_bytes);
+    case QCUR_BF16X3: return gemm_dt_tile<QCUR_BF16X3, 32>(c, g, ws, ws_bytes);
     default: return gemm_dt<QCUR_BF16>(c, g, ws, ws_bytes);
   }
 }
@@ -716,7 +790,10 @@ hipError_t launch_gemm(const Ctx& c, int opA, int opB, double alpha, QView A, QV
   return launch_gemm_batched(c, opA, opB, alpha, A, B, beta, D, compute, ws, ws_bytes, BatchSpec{});
 }
 
-size_t residual_tiles(int64_t m, int64_t n) { return (size_t)((m + 63) / 64) * (size_t)((n + 63) / 64); }
+size_t residual_tiles(int64_t m, int64_t n, int compute) {
+  const int64_t t = compute == QCUR_BF16X3 ? 32 : 64;
+  return (size_t)((m + t - 1) / t) * (size_t)((n + t - 1) / t);
+}
 
 hipError_t launch_residual_gemm(const Ctx& c, QView A, QView B1, QView R, const uint8_t* mask, int64_t mask_ld,
                                 int compute, double* partials, QView* E, double e_scale, int opR) {
@@ -734,8 +811,14 @@ hipError_t launch_residual_gemm(const Ctx& c, QView A, QView B1, QView R, const 
   g.vec = compute == QCUR_BF16 && vec_ok(B1, 0) && vec_ok(R, 0);
   if (E) { g.E = E->p; g.edt = E->dt; g.eld = E->ld; g.eps = E->ps; g.e_scale = e_scale; }
   if (g.M == 0 || g.N == 0) return hipSuccess;
-  dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64), 1);
   g.splits = 1;
+  if (compute == QCUR_BF16X3) {
+    const dim3 g32((unsigned)((g.N + 31) / 32), (unsigned)((g.M + 31) / 32), 1);
+    g.ktiles_per_split = (int)((g.K + 31) / 32);
+    hipLaunchKernelGGL((k_qgemm<QCUR_BF16X3, EPI_RESID, 32, 32>), g32, dim3(NT), 0, c.stream, g);
+    return hipGetLastError();
+  }
+  dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64), 1);
   switch (compute) {
     case QCUR_F64: {
       g.ktiles_per_split = (int)((g.K + 15) / 16);
@@ -776,6 +859,7 @@ hipError_t launch_residual_gemm_batched(const Ctx& c, int count, Slots A, Slots 
   g.vec = compute == QCUR_BF16 && vec_ok(QView{B1.p, 1, 1, B1.ld, B1.ps, B1.dt}, B1.slab) &&
           vec_ok(QView{R.p, 1, 1, R.ld, R.ps, R.dt}, R.slab);
   if (E) { g.E = E->p; g.edt = E->dt; g.eld = E->ld; g.eps = E->ps; g.sE = E->slab; g.e_scale = e_scale; }
+  if (compute == QCUR_BF16X3) return hipErrorInvalidValue;  // not offered for batches
   const int t = tile == 32 ? 32 : 64;
   const dim3 grid((unsigned)((nx + t - 1) / t), (unsigned)((mx + t - 1) / t), (unsigned)count);
   switch (compute) {
@@ -817,6 +901,12 @@ hipError_t launch_merge_gemm(const Ctx& c, QView Y, const uint8_t* mask, int64_t
   g.splits = 1;
   g.vec = compute == QCUR_BF16 && vec_ok(B1, 0) && vec_ok(R, 0);
   if (g.M == 0 || g.N == 0) return hipSuccess;
+  if (compute == QCUR_BF16X3) {
+    const dim3 g32((unsigned)((g.N + 31) / 32), (unsigned)((g.M + 31) / 32), 1);
+    g.ktiles_per_split = (int)((g.K + 31) / 32);
+    hipLaunchKernelGGL((k_qgemm<QCUR_BF16X3, EPI_MERGE, 32, 32>), g32, dim3(NT), 0, c.stream, g);
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64), 1);
   switch (compute) {
     case QCUR_F64:

@@ -113,7 +113,7 @@ hipError_t launch_gemm_batched(const Ctx& c, int opA, int opB, double alpha, QVi
                                QView D, int compute, void* ws, size_t ws_bytes, const BatchSpec& bs);
 // Residual: partial sums of squares of e_scale-free P_Omega(A - B1 R) per tile,
 // then a fixed-order final sum into fro (sqrt).  Optional E output.
-size_t residual_tiles(int64_t m, int64_t n);
+size_t residual_tiles(int64_t m, int64_t n, int compute);
 hipError_t launch_residual_gemm(const Ctx& c, QView A, QView B1, QView R, const uint8_t* mask,
                                 int64_t mask_ld, int compute, double* partials, QView* E,
                                 double e_scale, int opR = QCUR_OP_N);

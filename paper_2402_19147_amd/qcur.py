@@ -19,6 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqcur.so")
 
 F64, F32, BF16 = 0, 1, 2
+BF16X3 = 3  # compute only: FP32 operands as BF16 hi + lo, three BF16 products
 OP_N, OP_H = 0, 1
 LENGTH, UNIFORM = 0, 1
 CORE_WPINV, CORE_CAR = 0, 1

@@ -226,3 +226,15 @@ def test_svd_workspace_and_validation(L):
     assert call(U=qm(30, 20, Q.F32)) == 3
     assert call(nbytes=8) == 4
     assert call(X=qm(0, 20)) == 2
+
+
+def test_split_bf16_compute_validation(L):
+    A, B = qm(4, 5, Q.F32), qm(5, 3, Q.F32)
+    assert L.qcur_gemm(None, Q.OP_N, Q.OP_N, 1.0, A, B, 0.0, qm(4, 3, Q.F32), Q.BF16X3, None, 0) == 1
+    assert L.qcur_gemm(None, Q.OP_N, Q.OP_N, 1.0, qm(4, 5, Q.BF16), qm(5, 3, Q.BF16), 0.0, qm(4, 3, Q.F32),
+                       Q.BF16X3, None, 0) == 3
+    assert L.qcur_gemm(None, Q.OP_N, Q.OP_N, 1.0, A, B, 0.0, qm(4, 3, Q.F32), 4, None, 0) == 3
+    assert L.qcur_gemm_workspace(1024, 200, 1024, Q.BF16X3) > 0
+    assert L.qcur_approx_workspace(1024, 1024, 200, 200, Q.CORE_CAR, Q.BF16X3) > 0
+    d, dp = _dims([(64, 80, 16, 12)])
+    assert L.qcur_batch_workspace(1, dp, Q.F32, Q.LENGTH, Q.BF16X3, 0, 0) == 0

@@ -63,7 +63,7 @@ GEMM_SHAPES = [(1, 1, 1), (16, 4, 16), (70, 37, 45), (130, 50, 70), (64, 1024, 6
 
 
 @pytest.mark.parametrize("M,K,Nn", GEMM_SHAPES)
-@pytest.mark.parametrize("compute", [Q.F64, Q.F32, Q.BF16])
+@pytest.mark.parametrize("compute", [Q.F64, Q.F32, Q.BF16, Q.BF16X3])
 @pytest.mark.parametrize("opA,opB", [(0, 0), (1, 0), (0, 1), (1, 1)])
 def test_gemm_small_integers_bit_exact(M, K, Nn, compute, opA, opB):
     rng = np.random.default_rng(M * 1000 + K * 10 + Nn + opA * 3 + opB)
@@ -73,26 +73,45 @@ def test_gemm_small_integers_bit_exact(M, K, Nn, compute, opA, opB):
     Ae = A if opA == 0 else qH(A)
     Be = B if opB == 0 else qH(B)
     ref = qmul(Ae, Be)
-    tdt = {Q.F64: torch.float64, Q.F32: torch.float32, Q.BF16: torch.bfloat16}[compute]
+    tdt = {Q.F64: torch.float64, Q.F32: torch.float32, Q.BF16: torch.bfloat16, Q.BF16X3: torch.float32}[compute]
     D = Q.gemm(T(A, tdt), T(B, tdt), opA=opA, opB=opB, compute=compute)
     assert np.array_equal(N(D), ref)
 
 
-@pytest.mark.parametrize("compute,tol", [(Q.F64, 1e-13), (Q.F32, 1e-5), (Q.BF16, 2e-2)])
+@pytest.mark.parametrize("compute,tol", [(Q.F64, 1e-13), (Q.F32, 1e-5), (Q.BF16, 2e-2), (Q.BF16X3, 1e-4)])
 def test_gemm_gaussian_alpha_beta(compute, tol):
     rng = np.random.default_rng(7)
     A = rng.standard_normal((4, 150, 90))
     B = rng.standard_normal((4, 90, 77))
     D0 = rng.standard_normal((4, 150, 77))
-    tdt = {Q.F64: torch.float64, Q.F32: torch.float32, Q.BF16: torch.bfloat16}[compute]
+    tdt = {Q.F64: torch.float64, Q.F32: torch.float32, Q.BF16: torch.bfloat16, Q.BF16X3: torch.float32}[compute]
     odt = torch.float64 if compute == Q.F64 else torch.float32
     Dt = T(D0, odt)
     Q.gemm(T(A, tdt), T(B, tdt), alpha=-0.5, beta=2.0, D=Dt, compute=compute)
     if compute == Q.BF16:
         ref = -0.5 * qmul(bf16_round(A), bf16_round(B)) + 2.0 * D0
+    elif compute == Q.BF16X3:
+        ref = -0.5 * qmul(N(T(A, torch.float32)), N(T(B, torch.float32))) + 2.0 * N(T(D0, torch.float32))
     else:
         ref = -0.5 * qmul(A, B) + 2.0 * D0
     assert rel(N(Dt), ref) < tol
+
+
+@pytest.mark.parametrize("opA,opB", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_gemm_split_bf16_error(opA, opB):
+    # hi + lo halves carry about 16 bits of each FP32 operand: the product
+    # error stays near 2^-16, far below BF16's 2^-9, at split-K sizes
+    rng = np.random.default_rng(70 + 2 * opA + opB)
+    M, K, Nn = 300, 1024, 200
+    A = rng.standard_normal((4, M, K) if opA == 0 else (4, K, M))
+    B = rng.standard_normal((4, K, Nn) if opB == 0 else (4, Nn, K))
+    A32, B32 = N(T(A, torch.float32)), N(T(B, torch.float32))
+    ref = qmul(A32 if opA == 0 else qH(A32), B32 if opB == 0 else qH(B32))
+    D = Q.gemm(T(A, torch.float32), T(B, torch.float32), opA=opA, opB=opB, compute=Q.BF16X3)
+    err = rel(N(D), ref)
+    assert err < 4e-5, err
+    Db = Q.gemm(T(A, torch.bfloat16), T(B, torch.bfloat16), opA=opA, opB=opB, compute=Q.BF16)
+    assert err < rel(N(Db), ref) / 20
 
 
 def test_gemm_strided_views():
@@ -376,7 +395,7 @@ def test_approx_wpinv_plain_workload_full_size():
     assert rel(qmul(qmul(ref["C"], N(out["U"])), ref["R"]), A) < 1e-12
 
 
-@pytest.mark.parametrize("compute,tol", [(Q.F32, 1e-5), (Q.BF16, 2e-2)])
+@pytest.mark.parametrize("compute,tol", [(Q.F32, 1e-5), (Q.BF16, 2e-2), (Q.BF16X3, 1e-4)])
 @pytest.mark.parametrize("refine", [0, 1])
 def test_approx_car_mixed_precision(compute, tol, refine):
     A = workloads.color_like(200, 180, 8, seed=5)
@@ -390,7 +409,7 @@ def test_approx_car_mixed_precision(compute, tol, refine):
                        core=Q.CORE_CAR, compute=compute, refine_steps=refine, want_B=True)
     if refine == 0:
         # rounding C^+ and R^+ to the operand precision is amplified by their conditioning
-        u = 2.0 ** -24 if compute == Q.F32 else 2.0 ** -9
+        u = {Q.F32: 2.0 ** -24, Q.BF16: 2.0 ** -9, Q.BF16X3: 2.0 ** -16}[compute]
         tol = max(tol, 4 * u * (kappa(C) + kappa(R)))
     assert rel(N(B), Br) < tol
 
@@ -440,7 +459,8 @@ def test_backward_repeated_index_flags_arg():
 
 # ---------------------------------------------------------------- the native solve
 @pytest.mark.parametrize("sampling,core,compute", [(Q.UNIFORM, Q.CORE_WPINV, Q.F64), (Q.LENGTH, Q.CORE_CAR, Q.F64),
-                                                   (Q.LENGTH, Q.CORE_CAR, Q.F32), (Q.LENGTH, Q.CORE_CAR, Q.BF16)])
+                                                   (Q.LENGTH, Q.CORE_CAR, Q.F32), (Q.LENGTH, Q.CORE_CAR, Q.BF16),
+                                                   (Q.LENGTH, Q.CORE_CAR, Q.BF16X3)])
 def test_native_solve_matches_checker(sampling, core, compute):
     if core == Q.CORE_WPINV:
         L, Rt, _ = workloads.lowrank_gaussian_factors(256, 240, 10, 1)
@@ -461,5 +481,5 @@ def test_native_solve_matches_checker(sampling, core, compute):
     # |res - res_ref| <= ||CUR - (CUR)_ref||_F, bounded by the product tolerance times ||A||_F
     k = kappa(ref["C"]) + kappa(ref["R"])
     tol = {Q.F64: cur_tol(ref["C"], ref["R"]), Q.F32: max(1e-5, 4 * 2.0 ** -24 * k),
-           Q.BF16: max(2e-2, 4 * 2.0 ** -9 * k)}[compute]
+           Q.BF16: max(2e-2, 4 * 2.0 ** -9 * k), Q.BF16X3: max(1e-4, 4 * 2.0 ** -16 * k)}[compute]
     assert abs(res - ref["residual"]) <= tol * np.sqrt(fro2(A))

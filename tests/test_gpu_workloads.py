@@ -35,8 +35,8 @@ def kappa(X):
 
 def tolerance(compute, C, R):
     k = kappa(C) + kappa(R)
-    u = {Q.F64: 2.0 ** -52, Q.F32: 2.0 ** -24, Q.BF16: 2.0 ** -9}[compute]
-    floor = {Q.F64: 1e-12, Q.F32: 1e-5, Q.BF16: 2e-2}[compute]
+    u = {Q.F64: 2.0 ** -52, Q.F32: 2.0 ** -24, Q.BF16: 2.0 ** -9, Q.BF16X3: 2.0 ** -16}[compute]
+    floor = {Q.F64: 1e-12, Q.F32: 1e-5, Q.BF16: 2e-2, Q.BF16X3: 1e-4}[compute]
     return max(floor, 10 * u * k)
 
 
@@ -48,7 +48,7 @@ def color():
     return cfg, A, ref
 
 
-@pytest.mark.parametrize("compute,refine", [(Q.F64, 0), (Q.F32, 0), (Q.F32, 1), (Q.BF16, 1)])
+@pytest.mark.parametrize("compute,refine", [(Q.F64, 0), (Q.F32, 0), (Q.F32, 1), (Q.BF16, 1), (Q.BF16X3, 0)])
 def test_color_workload(color, compute, refine):
     cfg, A, ref = color
     dt = torch.float64 if compute == Q.F64 else torch.float32
