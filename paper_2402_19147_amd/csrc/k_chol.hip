@@ -30,11 +30,9 @@ __device__ inline Qd qmul(Qd a, Qd b) {
 
 // Factorisation G = L L^H and inverse P = L^{-1} of one w x w Hermitian
 // positive definite diagonal block (w <= 64) in LDS, blocked by 16:
-//  1. one wave factors the 16 x 16 diagonal block in place (right-looking,
-//     no barriers: a wave's LDS operations complete in order) and inverts it
-//     by forward substitution with four lanes per column; the inverse's
-//     strict lower part is kept transposed in the block's unused upper
-//     triangle and 1/L[j][j] in rdg;
+//  1. the 16 x 16 diagonal block is factored and inverted in one pass (below);
+//     the inverse's strict lower part is kept transposed in the block's unused
+//     upper triangle and 1/L[j][j] in rdg;
 //  2. the panel below becomes L_ik = A_ik (L_kk^{-1})^H;
 //  3. the trailing lower triangle loses L_ik L_jk^H;
 // then block row by block row P_ij = -P_ii sum_{k=j}^{i-1} L_ik P_kj.
@@ -51,23 +49,6 @@ __device__ inline double rsqrt_nr(double d) {
   r = r * (1.5 - 0.5 * d * r * r);
   return r;
 }
-
-template <int CTRL, int ROWS>
-__device__ inline double dpp_f64(double v) {
-  const uint64_t u = __builtin_bit_cast(uint64_t, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROWS, 0xf, true);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROWS, 0xf, true);
-  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-}
-
-// Sum over the 4 lanes of a quad (every lane gets the total).
-__device__ inline double sum4_dpp(double v) {
-  v += dpp_f64<0xB1, 0xf>(v);  // quad_perm [1,0,3,2]
-  v += dpp_f64<0x4E, 0xf>(v);  // quad_perm [2,3,0,1]
-  return v;
-}
-
-#define LDS_FENCE() __asm__ __volatile__("" ::: "memory")
 
 typedef double Tile[4][CB][CB + 1];
 
@@ -90,83 +71,70 @@ __device__ inline Qd pdiag(const Tile& a, const double* rdg, int kb, int r, int 
   return r == c ? Qd{rdg[kb + r], 0.0, 0.0, 0.0} : ldq(a, kb + c, kb + r);
 }
 
-// Wave-level factorisation and inversion of the diagonal block at kb.
-__device__ void chol_diag(Tile& a, double* rdg, int kb, int kw, int lane, int* bad) {
+// Column j of the reduced block and row j of the unscaled inverse, published
+// once per pivot (double-buffered by the pivot's parity).
+struct DiagBuf {
+  double col[2][4][SB];
+  double row[2][4][SB];
+};
+
+// Factorisation and inversion of the diagonal sub-block at kb (kw <= 16) by
+// the workgroup's first 256 threads, thread (i, c) = (tid / 16, tid % 16)
+// holding element (i, c) of the lower triangle in registers.  Pivot j is the
+// elementary lower-triangular step E_j that clears column j below the
+// diagonal; the same step applied to the identity accumulates E_j ... E_0 =
+// L^{-1}.  Keeping the rows unscaled until the end, step j is
+//   A_ic -= (A_ij / d_j) conj(A_cj)   for j < c <= i   (trailing update),
+//   X_ij  = -A_ij / d_j                                  (column j retires),
+//   X_ic -= (A_ij / d_j) X_jc          for c < j < i    (inverse rows),
+// with d_j = A_jj, and finally P = diag(d_j^{-1/2}) (X + I).  Every element
+// of the lower triangle is either still a reduced entry (c > j) or an entry
+// of X (c <= j), so the thread keeps one value; column j and row j travel
+// through LDS with one barrier per pivot.
+__device__ void chol_diag(Tile& a, double* rdg, DiagBuf& db, int kb, int kw, int tid, int* bad) {
+  const int i = tid >> 4, c = tid & 15;
+  const bool in = tid < SB * SB && i < kw && c <= i;
+  Qd x = in ? ldq(a, kb + i, kb + c) : Qd{0, 0, 0, 0};
+  double rsi = 1.0;
   for (int j = 0; j < kw; ++j) {
-    const int t = kw - j - 1;
-    const int cnt = t * (t + 1) / 2;
-    const double d = a[0][kb + j][kb + j];
-    Qd li[2], lk[2], x[2], lh{0, 0, 0, 0};
-    int ii[2], kk[2];
-#pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      const int e = lane + 64 * m;
-      ii[m] = kk[m] = -1;
-      if (e < cnt) {
-        const int r = (int)((sqrtf((float)(8 * e + 1)) - 1.0f) * 0.5f);
-        const int q = e - r * (r + 1) / 2;
-        ii[m] = kb + j + 1 + r;
-        kk[m] = kb + j + 1 + q;
-        li[m] = ldq(a, ii[m], kb + j);
-        lk[m] = ldq(a, kk[m], kb + j);
-        x[m] = ldq(a, ii[m], kk[m]);
-      }
+    const int par = j & 1;
+    if (in && c == j) {
+      db.col[par][0][i] = x.w;
+      db.col[par][1][i] = x.x;
+      db.col[par][2][i] = x.y;
+      db.col[par][3][i] = x.z;
     }
-    if (lane < t) lh = ldq(a, kb + j + 1 + lane, kb + j);
-    LDS_FENCE();
+    if (in && i == j && c < j) {
+      db.row[par][0][c] = x.w;
+      db.row[par][1][c] = x.x;
+      db.row[par][2][c] = x.y;
+      db.row[par][3][c] = x.z;
+    }
+    __syncthreads();
+    const double d = db.col[par][0][j];
     const bool ok = d > 0.0 && d < INFINITY;
     const double rs = rsqrt_nr(ok ? d : 1.0);
     const double rd = rs * rs;
-#pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      if (ii[m] >= 0) {
-        const Qd q = qmul_conj(li[m], lk[m]);
-        stq(a, ii[m], kk[m], Qd{x[m].w - q.w * rd, x[m].x - q.x * rd, x[m].y - q.y * rd, x[m].z - q.z * rd});
+    if (i == j) rsi = rs;
+    if (tid == 0 && !ok) *bad = 1;
+    if (in && i > j) {
+      if (c == j) {
+        x = Qd{-x.w * rd, -x.x * rd, -x.y * rd, -x.z * rd};
+      } else {
+        const Qd u{db.col[par][0][i] * rd, db.col[par][1][i] * rd, db.col[par][2][i] * rd, db.col[par][3][i] * rd};
+        const Qd v = c > j ? Qd{db.col[par][0][c], -db.col[par][1][c], -db.col[par][2][c], -db.col[par][3][c]}
+                           : Qd{db.row[par][0][c], db.row[par][1][c], db.row[par][2][c], db.row[par][3][c]};
+        const Qd q = qmul(u, v);
+        x = Qd{x.w - q.w, x.x - q.x, x.y - q.y, x.z - q.z};
       }
     }
-    if (lane < t) stq(a, kb + j + 1 + lane, kb + j, Qd{lh.w * rs, lh.x * rs, lh.y * rs, lh.z * rs});
-    if (lane == 0) {
-      a[0][kb + j][kb + j] = ok ? d * rs : 1.0;
-      rdg[kb + j] = rs;
-      if (!ok) *bad = 1;
-    }
-    LDS_FENCE();
   }
-  // forward substitution, four lanes per column c = lane / 4 (lane's k are
-  // sub, sub + 4, ...):  P[i][c] = -(1/L[i][i]) sum_{k=c}^{i-1} L[i][k] P[k][c]
-  const int c = lane >> 2, sub = lane & 3;
-  Qd pk[4];
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const int k = sub + 4 * m;
-    pk[m] = (k == c && c < kw) ? Qd{rdg[kb + c], 0.0, 0.0, 0.0} : Qd{0, 0, 0, 0};
+  if (in) {
+    if (c < i)
+      stq(a, kb + c, kb + i, Qd{x.w * rsi, x.x * rsi, x.y * rsi, x.z * rsi});
+    else
+      rdg[kb + i] = rsi;
   }
-  for (int i = 1; i < kw; ++i) {
-    Qd s{0, 0, 0, 0};
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int k = sub + 4 * m;
-      if (k < i) qacc(s, qmul(ldq(a, kb + i, kb + k), pk[m]));
-    }
-    s.w = sum4_dpp(s.w);
-    s.x = sum4_dpp(s.x);
-    s.y = sum4_dpp(s.y);
-    s.z = sum4_dpp(s.z);
-    const double f = -rdg[kb + i];
-    if (c < kw && i > c && (i & 3) == sub) {
-      const Qd v{f * s.w, f * s.x, f * s.y, f * s.z};
-#pragma unroll
-      for (int m = 0; m < 4; ++m)
-        if (sub + 4 * m == i) pk[m] = v;
-    }
-  }
-  // strict lower part, transposed into the upper triangle: a[c][k] = P[k][c]
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const int k = sub + 4 * m;
-    if (c < kw && k < kw && k > c) stq(a, kb + c, kb + k, pk[m]);
-  }
-  LDS_FENCE();
 }
 
 __global__ __launch_bounds__(CHOL_THREADS) void k_chol_block(const double* __restrict__ G0, double* __restrict__ P0,
@@ -178,8 +146,9 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_block(const double* __res
   __shared__ Tile a;
   __shared__ double sbuf[3][4][SB][SB + 1];  // block-row sums of the inverse phase
   __shared__ double rdg[CB];                 // 1 / L[j][j]
+  __shared__ DiagBuf db;
   __shared__ int bad;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x;
   if (tid == 0) bad = 0;
   for (int e = tid; e < w * w; e += CHOL_THREADS) {
     const int i = e / w, j = e % w;
@@ -192,7 +161,7 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_block(const double* __res
   __syncthreads();
   for (int kb = 0; kb < w; kb += SB) {
     const int kw = min(SB, w - kb);
-    if (wave == 0) chol_diag(a, rdg, kb, kw, lane, &bad);
+    chol_diag(a, rdg, db, kb, kw, tid, &bad);
     __syncthreads();
     const int r0 = kb + kw, rows = w - r0;
     if (rows <= 0) break;
