@@ -72,11 +72,21 @@ __device__ inline Qd pdiag(const Tile& a, const double* rdg, int kb, int r, int 
 }
 
 // Column j of the reduced block and row j of the unscaled inverse, published
-// once per pivot (double-buffered by the pivot's parity).
+// once per pivot (double-buffered by the pivot's parity).  The pivot's own
+// slot carries (d, 1/sqrt(d), 1/d, failed) instead of (d, 0, 0, 0).
 struct DiagBuf {
-  double col[2][4][SB];
-  double row[2][4][SB];
+  double col[2][SB][4];
+  double row[2][SB][4];
 };
+
+__device__ inline Qd ldq4(const double* p) {
+  const double2 a = *reinterpret_cast<const double2*>(p), b = *reinterpret_cast<const double2*>(p + 2);
+  return Qd{a.x, a.y, b.x, b.y};
+}
+__device__ inline void stq4(double* p, Qd v) {
+  *reinterpret_cast<double2*>(p) = double2{v.w, v.x};
+  *reinterpret_cast<double2*>(p + 2) = double2{v.y, v.z};
+}
 
 // Factorisation and inversion of the diagonal sub-block at kb (kw <= 16) by
 // the workgroup's first 256 threads, thread (i, c) = (tid / 16, tid % 16)
@@ -90,7 +100,8 @@ struct DiagBuf {
 // with d_j = A_jj, and finally P = diag(d_j^{-1/2}) (X + I).  Every element
 // of the lower triangle is either still a reduced entry (c > j) or an entry
 // of X (c <= j), so the thread keeps one value; column j and row j travel
-// through LDS with one barrier per pivot.
+// through LDS with one barrier per pivot, and every thread issues all of its
+// reads right after the barrier.
 __device__ void chol_diag(Tile& a, double* rdg, DiagBuf& db, int kb, int kw, int tid, int* bad) {
   const int i = tid >> 4, c = tid & 15;
   const bool in = tid < SB * SB && i < kw && c <= i;
@@ -99,35 +110,33 @@ __device__ void chol_diag(Tile& a, double* rdg, DiagBuf& db, int kb, int kw, int
   for (int j = 0; j < kw; ++j) {
     const int par = j & 1;
     if (in && c == j) {
-      db.col[par][0][i] = x.w;
-      db.col[par][1][i] = x.x;
-      db.col[par][2][i] = x.y;
-      db.col[par][3][i] = x.z;
-    }
-    if (in && i == j && c < j) {
-      db.row[par][0][c] = x.w;
-      db.row[par][1][c] = x.x;
-      db.row[par][2][c] = x.y;
-      db.row[par][3][c] = x.z;
-    }
-    __syncthreads();
-    const double d = db.col[par][0][j];
-    const bool ok = d > 0.0 && d < INFINITY;
-    const double rs = rsqrt_nr(ok ? d : 1.0);
-    const double rd = rs * rs;
-    if (i == j) rsi = rs;
-    if (tid == 0 && !ok) *bad = 1;
-    if (in && i > j) {
-      if (c == j) {
-        x = Qd{-x.w * rd, -x.x * rd, -x.y * rd, -x.z * rd};
+      if (i == j) {
+        const bool ok = x.w > 0.0 && x.w < INFINITY;
+        const double rs = rsqrt_nr(ok ? x.w : 1.0);
+        stq4(db.col[par][i], Qd{x.w, rs, rs * rs, ok ? 0.0 : 1.0});
       } else {
-        const Qd u{db.col[par][0][i] * rd, db.col[par][1][i] * rd, db.col[par][2][i] * rd, db.col[par][3][i] * rd};
-        const Qd v = c > j ? Qd{db.col[par][0][c], -db.col[par][1][c], -db.col[par][2][c], -db.col[par][3][c]}
-                           : Qd{db.row[par][0][c], db.row[par][1][c], db.row[par][2][c], db.row[par][3][c]};
-        const Qd q = qmul(u, v);
-        x = Qd{x.w - q.w, x.x - q.x, x.y - q.y, x.z - q.z};
+        stq4(db.col[par][i], x);
       }
     }
+    if (in && i == j && c < j) stq4(db.row[par][c], x);
+    __syncthreads();
+    const Qd piv = ldq4(db.col[par][j]);
+    const Qd ar = ldq4(db.col[par][i & (SB - 1)]);
+    const Qd vr = ldq4(c > j ? db.col[par][c] : db.row[par][c]);
+    const double rs = piv.x, rd = piv.y;
+    const bool act = in && i > j, ret = c == j;
+    // inactive rows take u = 0 and the retiring column v = 0 (selects, so
+    // that stale LDS contents never reach the arithmetic); then one fused
+    // form covers the three cases with the roundings of the plain formulas
+    const Qd u = act ? Qd{ar.w * rd, ar.x * rd, ar.y * rd, ar.z * rd} : Qd{0, 0, 0, 0};
+    const double sg = c > j ? -1.0 : 1.0;
+    const Qd v = ret ? Qd{0, 0, 0, 0} : Qd{vr.w, sg * vr.x, sg * vr.y, sg * vr.z};
+    const Qd q = qmul(u, v);
+    const double m = ret && act ? -rd : 1.0;
+    x = Qd{__builtin_fma(x.w, m, -q.w), __builtin_fma(x.x, m, -q.x), __builtin_fma(x.y, m, -q.y),
+           __builtin_fma(x.z, m, -q.z)};
+    rsi = i == j ? rs : rsi;
+    if (tid == 0 && piv.z != 0.0) *bad = 1;
   }
   if (in) {
     if (c < i)
@@ -146,7 +155,7 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_block(const double* __res
   __shared__ Tile a;
   __shared__ double sbuf[3][4][SB][SB + 1];  // block-row sums of the inverse phase
   __shared__ double rdg[CB];                 // 1 / L[j][j]
-  __shared__ DiagBuf db;
+  __shared__ __align__(16) DiagBuf db;
   __shared__ int bad;
   const int tid = threadIdx.x;
   if (tid == 0) bad = 0;
