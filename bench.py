@@ -182,6 +182,7 @@ def main():
         extra["complete_512x768"] = bench_complete(q, torch, workloads, dev)
         extra["adjoint_2048"] = bench_adjoint(q, torch, workloads, dev, args)
         extra["qsvd_500"] = bench_qsvd(q, torch, workloads, dev)
+        extra["theorem1_500"] = bench_theorem1(q, torch, workloads, dev)
     # a plain copy of known size, for scaling HBM byte counters of profiled runs
     src = torch.empty(64 * 2 ** 20, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
@@ -464,6 +465,44 @@ def bench_qsvd(q, torch, workloads, dev):
            "qsvd_over_qmcur_time": t_svd / t_cur}
     log(f"qsvd 500: {t_svd * 1e3:.1f} ms (rank-10 err {err_k:.2e}) vs QMCUR {t_cur * 1e3:.3f} ms (err {res:.2e})")
     return out
+
+
+def bench_theorem1(q, torch, workloads, dev):
+    """Example 4.1 (Theorem 1): X = W_k Sigma_k V_k^H (500 x 500, k = 50,
+    polar factors of Gaussian matrices, Sigma_k ~ U(1, 10)) plus Gaussian
+    noise of variance sigma per component, sigma = 1e-1 .. 1e-6; QMCUR with
+    length sampling, c = r = ceil(k ln k), FP64, least-squares core.  Per
+    level: ||E||_2, ||X - C~U~R~||_2 and Theorem 1's bound; the log-log
+    slope of the error against ||E||_2 (one for linear growth)."""
+    from paper_2402_19147_amd import perturbation as pt
+    import math
+    import numpy as np
+    cfg = workloads.WORKLOADS["theorem1_500"]
+    m, n, k, seed = cfg["m"], cfg["n"], cfg["k"], cfg["seed"]
+    GW, GV, sig, E0 = workloads.perturbation_factors(m, n, k, seed)
+    t0 = time.perf_counter()
+    W = pt.polar_factor(torch.tensor(GW, device=dev))
+    V = pt.polar_factor(torch.tensor(GV, device=dev))
+    X = pt.lowrank_product(W, torch.tensor(sig), V)
+    E0g = torch.tensor(E0, device=dev)
+    nE0 = pt.spectral_norm(E0g)
+    c = q.sample_size(k, min(m, n))
+    levels = []
+    for var in cfg["variances"]:
+        out = pt.perturbation_errors(X, E0g, math.sqrt(var), W, V, c, c, q.LENGTH, seed, norm_E0=nE0)
+        levels.append({"variance": var, "norm_E": out["norm_E"], "err": out["err"], "bound": out["bound"],
+                       "err_over_norm_E": out["err"] / out["norm_E"], "w_pinv": out["w_pinv"],
+                       "v_pinv": out["v_pinv"]})
+    torch.cuda.synchronize()
+    q.sync_status()
+    elapsed = time.perf_counter() - t0
+    slope = float(np.polyfit(np.log([v["norm_E"] for v in levels]), np.log([v["err"] for v in levels]), 1)[0])
+    ok = all(v["err"] <= v["bound"] for v in levels)
+    log(f"theorem1 500: slope {slope:.3f}, bound holds {ok}, err/|E| " +
+        " ".join(f"{v['err_over_norm_E']:.2f}" for v in levels) + f" ({elapsed:.2f} s)")
+    return {"workload": f"500x500, X = W_k Sigma_k V_k^H, k={k}, Gaussian noise of variance 1e-1..1e-6; QMCUR "
+                        f"length sampling c=r={c}, FP64, U=C^+AR^+", "levels": levels, "loglog_slope": slope,
+            "bound_holds": ok, "seconds": elapsed}
 
 
 def cpu_baseline(A, c, r, seed, seconds):

@@ -18,8 +18,9 @@ Modules
   cur       gathers, the two cores, CUR, the residual, the whole solve
   grad      derivatives of B = CUR(A) and of the masked loss
   complete  completion from partially observed entries (Algorithm 2)
+  perturbation  Theorem 1's error bound and the Example 4.1 experiment
 """
-from . import quat, pinv, sampling, cur, grad, complete  # noqa: F401
+from . import quat, pinv, sampling, cur, grad, complete, perturbation  # noqa: F401
 from .quat import qmul, qH, fro2, chi, unchi, real_rep, inner  # noqa: F401
 from .pinv import pinv as qpinv  # noqa: F401
 from .sampling import probs_length, probs_uniform, draw, splitmix64_nth  # noqa: F401

@@ -29,6 +29,10 @@ Workloads (sizes as used by the benchmark and the large parity tests):
   * uniform_index_set: a fixed, sorted index set drawn uniformly without
     replacement (used where an index set is an input, not a draw of the
     method).
+  * perturbation_factors: the inputs of the Theorem 1 experiment
+    (Example 4.1): Gaussian quaternion matrices whose polar factors the
+    caller takes as W_k and V_k, the positive diagonal of Sigma_k and a
+    unit Gaussian noise matrix E0 (the caller scales it).
 """
 from __future__ import annotations
 
@@ -41,6 +45,7 @@ __all__ = [
     "batch_problems",
     "bernoulli_mask",
     "uniform_index_set",
+    "perturbation_factors",
     "gaussian_quat",
     "small_int_quat",
     "WORKLOADS",
@@ -134,6 +139,22 @@ def uniform_index_set(n: int, count: int, seed: int, stream: int) -> np.ndarray:
 
 # The five workloads with their sizes.  "product" marks workloads whose
 # matrix is the quaternion product L * Rt (+E) formed by the caller.
+def perturbation_factors(m: int, n: int, k: int, seed: int):
+    """Inputs of the Theorem 1 experiment (Example 4.1).
+
+    Returns (GW, GV, sig, E0): GW (4,m,k) and GV (4,n,k) with i.i.d. N(0,1)
+    components (the caller orthonormalises them: the polar factor of each is
+    the unitary W_k, V_k), sig (k,) i.i.d. U(1, 10) sorted descending (the
+    positive diagonal of Sigma_k) and E0 (4,m,n) i.i.d. N(0,1) (the noise
+    E = s * E0 for a scale s chosen by the caller).
+    """
+    GW = gaussian_quat(m, k, rng_for(seed, 0))
+    GV = gaussian_quat(n, k, rng_for(seed, 1))
+    sig = np.sort(1.0 + 9.0 * rng_for(seed, 2).random(k))[::-1].copy()
+    E0 = gaussian_quat(m, n, rng_for(seed, 3))
+    return GW, GV, sig, E0
+
+
 WORKLOADS = {
     "plain_f64_256": dict(kind="product", m=256, n=256, k=10, noise=0.0, c=40, r=40,
                           sampling="uniform", core="wpinv", seed=1),
@@ -152,4 +173,8 @@ WORKLOADS = {
                              max_iter=200, tol=1e-4, seed=6),
     # Example 4.2 shape: rank 10 plus noise, QMCUR against the QSVD baseline
     "qsvd_500": dict(kind="product", m=500, n=500, k=10, noise=1e-4, sampling="length", core="car", seed=7),
+    # Example 4.1: X = W_k Sigma_k V_k^H (500 x 500, k = 50) plus Gaussian noise
+    # of variance sigma per component, c = r = ceil(k ln k)
+    "theorem1_500": dict(kind="perturbation", m=500, n=500, k=50,
+                         variances=[1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6], sampling="length", seed=11),
 }
