@@ -470,7 +470,7 @@ def bench_qsvd(q, torch, workloads, dev):
 def bench_theorem1(q, torch, workloads, dev):
     """Example 4.1 (Theorem 1): X = W_k Sigma_k V_k^H (500 x 500, k = 50,
     polar factors of Gaussian matrices, Sigma_k ~ U(1, 10)) plus Gaussian
-    noise of variance sigma per component, sigma = 1e-1 .. 1e-6; QMCUR with
+    noise of standard deviation sigma per component, sigma = 1e-1 .. 1e-6; QMCUR with
     length sampling, c = r = ceil(k ln k), FP64, least-squares core.  Per
     level: ||E||_2, ||X - C~U~R~||_2 and Theorem 1's bound; the log-log
     slope of the error against ||E||_2 (one for linear growth)."""
@@ -488,9 +488,9 @@ def bench_theorem1(q, torch, workloads, dev):
     nE0 = pt.spectral_norm(E0g)
     c = q.sample_size(k, min(m, n))
     levels = []
-    for var in cfg["variances"]:
-        out = pt.perturbation_errors(X, E0g, math.sqrt(var), W, V, c, c, q.LENGTH, seed, norm_E0=nE0)
-        levels.append({"variance": var, "norm_E": out["norm_E"], "err": out["err"], "bound": out["bound"],
+    for sigma in cfg["sigmas"]:
+        out = pt.perturbation_errors(X, E0g, sigma, W, V, c, c, q.LENGTH, seed, norm_E0=nE0)
+        levels.append({"sigma": sigma, "norm_E": out["norm_E"], "err": out["err"], "bound": out["bound"],
                        "err_over_norm_E": out["err"] / out["norm_E"], "w_pinv": out["w_pinv"],
                        "v_pinv": out["v_pinv"]})
     torch.cuda.synchronize()
@@ -500,7 +500,7 @@ def bench_theorem1(q, torch, workloads, dev):
     ok = all(v["err"] <= v["bound"] for v in levels)
     log(f"theorem1 500: slope {slope:.3f}, bound holds {ok}, err/|E| " +
         " ".join(f"{v['err_over_norm_E']:.2f}" for v in levels) + f" ({elapsed:.2f} s)")
-    return {"workload": f"500x500, X = W_k Sigma_k V_k^H, k={k}, Gaussian noise of variance 1e-1..1e-6; QMCUR "
+    return {"workload": f"500x500, X = W_k Sigma_k V_k^H, k={k}, Gaussian noise N(0, sigma^2), sigma=1e-1..1e-6; QMCUR "
                         f"length sampling c=r={c}, FP64, U=C^+AR^+", "levels": levels, "loglog_slope": slope,
             "bound_holds": ok, "seconds": elapsed}
 

@@ -15,9 +15,10 @@ and plots the error against ||E||_2.
 
 Readings where the paper leaves a choice open: the unitary factors are the
 polar factors of Gaussian quaternion matrices (unique, so two independent
-implementations build the same X); "variance sigma" is read literally, so
-E = sqrt(sigma) * E0 with E0 standard Gaussian in every component; C and R
-have ceil(k ln k) columns and rows (the sizing of Section 3.1).
+implementations build the same X); the noise level sigma of the example is
+read as the standard deviation of every component, E = sigma * E0 with E0
+standard Gaussian; C and R have ceil(k ln k) columns and rows (the sizing of
+Section 3.1).
 """
 from __future__ import annotations
 

@@ -49,14 +49,14 @@ def test_construction_matches_checker():
     assert math.sqrt(fro2(N(X) - Xr) / fro2(Xr)) < 1e-12
 
 
-@pytest.mark.parametrize("sampling,var", [("length", 1e-2), ("length", 1e-6), ("uniform", 1e-3)])
-def test_one_noise_level_matches_checker(sampling, var):
+@pytest.mark.parametrize("sampling,sigma", [("length", 1e-1), ("length", 1e-3), ("uniform", 3e-2)])
+def test_one_noise_level_matches_checker(sampling, sigma):
     m, n, k = 72, 66, 6
     GW, GV, sig, E0 = workloads.perturbation_factors(m, n, k, seed=22)
     Wr, Vr = ref_polar(GW), ref_polar(GV)
     Xr = ref_lowrank(Wr, sig, Vr)
     c = r = Q.sample_size(k, min(m, n))
-    s = math.sqrt(var)
+    s = sigma
     smode = Q.LENGTH if sampling == "length" else Q.UNIFORM
     out = P.perturbation_errors(T(Xr), T(E0), s, T(Wr), T(Vr), c, r, smode, seed=5)
     Q.sync_status()
@@ -70,7 +70,7 @@ def test_one_noise_level_matches_checker(sampling, var):
 
 def test_example_4_1_full_size():
     # X = W_k Sigma_k V_k^H, 500 x 500, k = 50, c = r = ceil(50 ln 50) = 196,
-    # noise variances 1e-1 .. 1e-6
+    # noise levels (standard deviations) 1e-1 .. 1e-6
     m = n = 500
     k = 50
     GW, GV, sig, E0 = workloads.perturbation_factors(m, n, k, seed=11)
@@ -81,10 +81,10 @@ def test_example_4_1_full_size():
     E0g = T(E0)
     nE0 = P.spectral_norm(E0g)
     rows = []
-    for var in (1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6):
-        out = P.perturbation_errors(X, E0g, math.sqrt(var), W, V, c, r, Q.LENGTH, seed=3, norm_E0=nE0)
+    for sigma in (1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6):
+        out = P.perturbation_errors(X, E0g, sigma, W, V, c, r, Q.LENGTH, seed=3, norm_E0=nE0)
         Q.sync_status()
-        assert out["err"] <= out["bound"], var
+        assert out["err"] <= out["bound"], sigma
         rows.append((out["norm_E"], out["err"]))
     # linear in ||E||_2: the log-log slope over the six levels is one
     x = np.log([a for a, _ in rows])

@@ -68,11 +68,11 @@ def _setup(m=40, n=36, k=4, seed=3):
 @pytest.mark.parametrize("sampling", ["length", "uniform"])
 def test_theorem1_bound_holds(sampling):
     X, W, V, E0, c, r = _setup()
-    for var in (1e-1, 1e-2, 1e-4, 1e-6):
-        out = perturbation_errors(X, math.sqrt(var) * E0, W, V, c, r, sampling, seed=4)
+    for sigma in (1e-1, 1e-2, 1e-4, 1e-6):
+        out = perturbation_errors(X, sigma * E0, W, V, c, r, sampling, seed=4)
         assert np.isfinite(out["bound"])
         assert out["err"] <= out["bound"]
-        assert out["norm_E"] == pytest.approx(math.sqrt(var) * spectral_norm(E0), rel=1e-12)
+        assert out["norm_E"] == pytest.approx(sigma * spectral_norm(E0), rel=1e-12)
 
 
 def test_noiseless_matrix_is_recovered():

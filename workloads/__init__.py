@@ -174,7 +174,7 @@ WORKLOADS = {
     # Example 4.2 shape: rank 10 plus noise, QMCUR against the QSVD baseline
     "qsvd_500": dict(kind="product", m=500, n=500, k=10, noise=1e-4, sampling="length", core="car", seed=7),
     # Example 4.1: X = W_k Sigma_k V_k^H (500 x 500, k = 50) plus Gaussian noise
-    # of variance sigma per component, c = r = ceil(k ln k)
+    # N(0, sigma^2) in every component, c = r = ceil(k ln k)
     "theorem1_500": dict(kind="perturbation", m=500, n=500, k=50,
-                         variances=[1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6], sampling="length", seed=11),
+                         sigmas=[1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6], sampling="length", seed=11),
 }
