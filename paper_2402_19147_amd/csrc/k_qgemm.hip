@@ -66,7 +66,7 @@ template <> struct MT<QCUR_BF16> {
   typedef float Acc;
   typedef f32x4 AccV;
   typedef bf16x8 Frag;
-  static constexpr int BK = 32, KM = 32, PAD = 8;
+  static constexpr int BK = 32, KM = 32, PAD = 0;
   static __device__ inline int out_row(int lane, int r) { return (lane >> 4) * 4 + r; }
   static __device__ inline AccV mfma(Frag a, Frag b, AccV c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -150,7 +150,11 @@ enum { EPI_STORE = 0, EPI_PARTIAL = 1, EPI_RESID = 2, EPI_MERGE = 3 };
 // operand read 16 different rows at the same k and the staging stores of
 // consecutive threads hit consecutive or odd-strided addresses, so neither
 // conflicts on the LDS banks.  bf16: each lane reads its 8 consecutive k
-// values at once (PAD 8 keeps rows 16-byte aligned).
+// values (one 16-byte chunk) at once; rows are 64 bytes without padding and
+// the four chunks of row r are stored in the order chunk ^ ((r >> 2) & 3),
+// so that the eight rows read in one LDS cycle fall on distinct banks.  The
+// unpadded stages (64 KiB for 64 x 64 tiles) let two workgroups share a
+// compute unit.
 template <int DT, int BM, int BN> struct alignas(16) Smem {
   typedef typename MT<DT>::In In;
   static constexpr int BK = MT<DT>::BK, PAD = MT<DT>::PAD;
@@ -168,6 +172,9 @@ template <int BM, int BN> struct alignas(16) Smem<QCUR_BF16X3, BM, BN> {
   uint16_t a[2][2][4][BM][BK + PAD];
   uint16_t b[2][2][4][BN][BK + PAD];
 };
+
+// element offset of k-chunk c (8 bf16) in row r of a BF16 stage
+__device__ inline int bf16_chunk(int r, int c) { return (c ^ ((r >> 2) & 3)) * 8; }
 
 template <int DT, int EPI, int BM, int BN>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile_m, int64_t tile_n, int split,
@@ -305,6 +312,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
   // NV: 16-byte vectors per plane and thread (k-contiguous) = 4 x 8 blocks
   // per lane (x-contiguous)
   static_assert(BM == BN, "square tiles");
+  static_assert(DT != QCUR_BF16 || BK == T::KM, "one BF16 MFMA k-step per staged slice");
   constexpr int NV = (DT == QCUR_BF16) ? (BM * BK / 8 + NT - 1) / NT : 1;
   u32x4 va[4 * NV], vb[4 * NV];
   constexpr uint32_t SIGN2 = 0x80008000u;
@@ -344,11 +352,18 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
       for (int q = 0; q < 4; ++q) {
         u32x4 w = in[4 * r + q];
         if (conj && q > 0) w ^= (u32x4){SIGN2, SIGN2, SIGN2, SIGN2};
-        *(u32x4*)&dst[q * plane_stride_rows + x][k] = w;
+        const int row = q * plane_stride_rows + x;
+        *(u32x4*)&dst[row][bf16_chunk(row, k / 8)] = w;
       }
     }
   };
-  // x-contiguous operand: lane l of wave q takes rows k0..k0+3 of X[k][x0..x0+7]
+  // x-contiguous operand: lane l of wave q takes rows k0..k0+3 of X[k][x0..x0+7].
+  // Consecutive lanes take consecutive k blocks of one x block: a load
+  // instruction covers the same eight whole 128-byte rows of X as with the x
+  // blocks fastest, while the eight lanes sharing an x block write one
+  // contiguous 64-byte run of an LDS row, so the 16 lanes of an LDS write
+  // cycle hit distinct banks (x blocks fastest put rows 8 apart, 32 banks
+  // apart at this row length, into the same cycle).
   auto xblk_load = [&](const uint16_t* __restrict__ Xg, int64_t ld, int64_t ps, int64_t xbase, int64_t X, int BX,
                        int64_t kbase, int64_t K, u32x4* out) {
     const int xbl = BX / 8;
@@ -357,7 +372,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
     for (int n = 0; n < NV; ++n) {
       const int blk = lane + 64 * n;
       if (blk >= (BK / 4) * xbl) break;
-      const int x0 = (blk % xbl) * 8, k0 = (blk / xbl) * 4;
+      const int k0 = (blk % (BK / 4)) * 4, x0 = (blk / (BK / 4)) * 8;
       const int64_t gx = xbase + x0;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -383,7 +398,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
     for (int n = 0; n < NV; ++n) {
     const int blk = lane + 64 * n;
     if (blk >= (BK / 4) * xbl) break;
-    const int x0 = (blk % xbl) * 8, k0 = (blk / xbl) * 4;
+    const int k0 = (blk % (BK / 4)) * 4, x0 = (blk / (BK / 4)) * 8;
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
       const uint32_t r0 = in[4 * n][d], r1 = in[4 * n + 1][d], r2 = in[4 * n + 2][d], r3 = in[4 * n + 3][d];
@@ -391,8 +406,15 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
       const uint32_t lo0 = ((r0 & 0xFFFFu) | (r1 << 16)) ^ flip, hi0 = ((r2 & 0xFFFFu) | (r3 << 16)) ^ flip;
       const uint32_t lo1 = ((r0 >> 16) | (r1 & 0xFFFF0000u)) ^ flip, hi1 = ((r2 >> 16) | (r3 & 0xFFFF0000u)) ^ flip;
       typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-      *(u32x2*)&dst[wave * plane_stride_rows + x0 + 2 * d][k0] = (u32x2){lo0, hi0};
-      *(u32x2*)&dst[wave * plane_stride_rows + x0 + 2 * d + 1][k0] = (u32x2){lo1, hi1};
+      // rows 2d and 2d + 1 of the x block; lanes of odd x blocks write the
+      // odd row first, so that the two x blocks of one LDS write cycle
+      // (64-byte rows: banks repeat every four rows) never share banks
+      const bool odd = (x0 >> 3) & 1;
+      const int ra = wave * plane_stride_rows + x0 + 2 * d + (odd ? 1 : 0);
+      const int rb2 = wave * plane_stride_rows + x0 + 2 * d + (odd ? 0 : 1);
+      const int kc = k0 / 8, ko = k0 & 7;
+      *(u32x2*)&dst[ra][bf16_chunk(ra, kc) + ko] = odd ? (u32x2){lo1, hi1} : (u32x2){lo0, hi0};
+      *(u32x2*)&dst[rb2][bf16_chunk(rb2, kc) + ko] = odd ? (u32x2){lo0, hi0} : (u32x2){lo1, hi1};
     }
     }
   };
@@ -500,7 +522,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
           const int ii = wm + x * 16 + (lane & 15);
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            if constexpr (DT == QCUR_BF16) a[q][x] = *(const Frag*)&sm.a[st][q][ii][kk * 32 + (lane >> 4) * 8];
+            if constexpr (DT == QCUR_BF16) a[q][x] = *(const Frag*)&sm.a[st][q][ii][bf16_chunk(ii, lane >> 4)];
             else a[q][x] = sm.a[st][q][ii][kk * 4 + (lane >> 4)];
           }
 #pragma unroll
@@ -511,7 +533,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
           const int jj = wn + y * 16 + (lane & 15);
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            if constexpr (DT == QCUR_BF16) b[q][y] = *(const Frag*)&sm.b[st][q][jj][kk * 32 + (lane >> 4) * 8];
+            if constexpr (DT == QCUR_BF16) b[q][y] = *(const Frag*)&sm.b[st][q][jj][bf16_chunk(jj, lane >> 4)];
             else b[q][y] = sm.b[st][q][jj][kk * 4 + (lane >> 4)];
           }
         }
