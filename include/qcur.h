@@ -198,6 +198,11 @@ qcur_status qcur_gemm(qcur_handle handle, int opA, int opB, double alpha, const 
  * may be NULL) receives C U R.
  * rank_out (device int64[2], may be NULL): kept ranks of the pseudoinverses
  * (W: [rank, rank]; CAR: [rank C, rank R]).
+ * CAR synchronises once with the host for the factors' full-rank
+ * certificate.  When 32 m n r <= 4e10 the products of the fast path are
+ * enqueued before that wait and, if the certificate rejects the fast path
+ * or asks for a second CholeskyQR pass, computed again after the
+ * fallback; outputs do not depend on this.
  * ws: qcur_approx_workspace(m, n, c, r, core, compute) bytes. */
 qcur_status qcur_approx(qcur_handle handle, const qcur_qmat* A, const qcur_qmat* C,
                         const qcur_qmat* R, const qcur_qmat* W, int core, int compute,
@@ -245,7 +250,8 @@ qcur_status qcur_backward(qcur_handle handle, const qcur_qmat* A, const int64_t*
  * for QCUR_F64 else FP32), rank_out (device int64[2] or NULL).  Optional
  * outputs (NULL = internal): p_col[n], q_row[m] and C, R, W in A's dtype.
  * Same limits as qcur_draw for m and n.  Synchronises once per group of
- * pseudoinverses (the full-rank certificate).
+ * pseudoinverses (the full-rank certificate), after the products that follow
+ * it when they are cheap (as in qcur_approx).
  * ws: qcur_solve_workspace(m, n, c, r, core, compute) bytes. */
 qcur_status qcur_solve(qcur_handle handle, const qcur_qmat* A, int64_t c, int64_t r, int sampling, int core,
                        int compute, uint64_t seed, int with_replacement, int refine_steps, double rtol,
@@ -330,8 +336,9 @@ qcur_status qcur_solve_batched(qcur_handle handle, int32_t count, const int32_t*
  * FP32) receives the last iterate.  rtol and max_rank (the predefined rank
  * k) apply to the pseudoinverses.  iters (host int, may be NULL): steps
  * taken; rel (host double, may be NULL): the last relative change.
- * Synchronises with the host once per step (the stopping test) and inside
- * the pseudoinverse.  ws: qcur_complete_workspace(m, n, c, r, compute). */
+ * Synchronises with the host once per step (the stopping test) and once for
+ * the pseudoinverses' certificate (after the step's products when they are
+ * cheap, as in qcur_approx).  ws: qcur_complete_workspace(m, n, c, r, compute). */
 qcur_status qcur_complete(qcur_handle handle, const qcur_qmat* Y, const uint8_t* mask, int64_t mask_ld,
                           const int64_t* I, int64_t r, const int64_t* J, int64_t c, int compute, double rtol,
                           int64_t max_rank, int max_iter, double tol, qcur_qmat* X, int* iters, double* rel,

@@ -275,9 +275,41 @@ qcur_status chol_inv(const Ctx& c, GroupWs& w, double* P) {
 // equations, error ~ eps * kappa^2) is used when the products downstream are
 // FP32 or BF16.  done[b] reports whether the certificate of matrix b held;
 // for those Xp_b and rank_out[b] are written.
+// Fast-path verdicts of a CholeskyQR group, copied to the handle's pinned
+// buffer.
+struct HostVerdict {
+  int ok[MAXB];
+  double nrm[4 * MAXB];
+  double aux[4];  // other small read-backs (the completion's stopping sums)
+};
+
+// A verdict left pending by pinv_fast_group: the decision kernel has run and
+// its result is on its way to pinned host memory (c.done marks its arrival).
+// The factors of the fast path (the first pass when `adaptive`, which then
+// also requires the orthogonality defect to be small) are in place, so the
+// caller can enqueue the work that follows before it waits; if the verdict
+// rejects the fast path, the caller recomputes without speculation.
+struct PinvSpec {
+  bool pending = false;
+  int nb = 0;
+  bool adaptive = false;
+  double orth_tol = 0.0;
+};
+
+// Did the pending verdict confirm the fast path?  Waits for it.
+qcur_status pinv_spec_resolve(const Ctx& c, const PinvSpec& spec, bool* valid) {
+  *valid = true;
+  if (!spec.pending) return QCUR_OK;
+  HIPCHK(hipEventSynchronize(c.done));
+  const HostVerdict* hv = (const HostVerdict*)c.pinned;
+  for (int b = 0; b < spec.nb; ++b)
+    *valid = *valid && hv->ok[b] && (!spec.adaptive || hv->nrm[4 * b + 3] <= spec.orth_tol * spec.orth_tol);
+  return QCUR_OK;
+}
+
 qcur_status pinv_fast_group(const Ctx& c, int nb, const QView* X, double rtol, int64_t max_rank, const QView* Xp,
                             int64_t* const* rank_out, GroupWs& w, int passes, bool* done, double orth_tol = 0.0,
-                            int* final_pass = nullptr) {
+                            int* final_pass = nullptr, PinvSpec* spec = nullptr) {
   const int64_t pp = w.pp, qq = w.qq;
   const int64_t zslab = 4 * pp * qq, gslab = 4 * qq * qq;
   int64_t pb[MAXB], qb[MAXB];
@@ -340,6 +372,23 @@ qcur_status pinv_fast_group(const Ctx& c, int nb, const QView* X, double rtol, i
     HIPCHK(hipStreamSynchronize(c.stream));
     return QCUR_OK;
   };
+  // speculation (orthonormal-form output only): launch the verdict, copy it
+  // to pinned memory and return the fast path's factors without waiting
+  auto decide_async = [&](bool adaptive, int fp) -> qcur_status {
+    HIPCHK(launch_pinv_decide(c, w.norms, w.fail, rtol, max_rank, nb, qb, rank_out, w.ok));
+    HostVerdict* hv = (HostVerdict*)c.pinned;
+    HIPCHK(hipMemcpyAsync(hv->ok, w.ok, sizeof(int) * nb, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipMemcpyAsync(hv->nrm, w.norms, sizeof(double) * 4 * nb, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipEventRecord(c.done, c.stream));
+    spec->pending = true;
+    spec->nb = nb;
+    spec->adaptive = adaptive;
+    spec->orth_tol = orth_tol;
+    if (final_pass) *final_pass = fp;
+    for (int b = 0; b < nb; ++b) done[b] = true;
+    return QCUR_OK;
+  };
+  if (spec && Xp) spec = nullptr;
   bool second = passes >= 2;
   bool have_g2 = false;
   if (passes == 0) {
@@ -349,6 +398,7 @@ qcur_status pinv_fast_group(const Ctx& c, int nb, const QView* X, double rtol, i
     have_g2 = true;
     HIPCHK(launch_defect_batch(c, nb, w.G, qq, gslab, qb, w.part, w.norms + 3, 4));
     HIPCHK(launch_sumsq_batch(c, nb, Pr, w.part, w.norms + 2, 4));
+    if (spec) return decide_async(true, 1);
     double nrm[4 * MAXB];
     CHK(decide_and_read(nrm));
     for (int b = 0; b < nb; ++b) second |= ok[b] && !(nrm[4 * b + 3] <= orth_tol * orth_tol);
@@ -365,9 +415,11 @@ qcur_status pinv_fast_group(const Ctx& c, int nb, const QView* X, double rtol, i
     HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_H, 1.0, Q1, P2, 0.0, Q, QCUR_F64, w.gws, w.gws_bytes, bzp));
     Pf = w.P;
     Qf = w.Q;
+    if (spec && passes == 2) return decide_async(false, 2);
     CHK(decide_and_read());
   } else if (passes == 1) {
     HIPCHK(launch_sumsq_batch(c, nb, Pr, w.part, w.norms + 2, 4));
+    if (spec) return decide_async(false, 1);
     CHK(decide_and_read());
   }
   if (final_pass) *final_pass = second ? 2 : 1;
@@ -482,7 +534,7 @@ qcur_status pinv_jacobi_qp(const Ctx& c, QView X, double rtol, int64_t max_rank,
 // certificate holds, else the Jacobi SVD.
 qcur_status pinv_group_qp(const Ctx& c, int nb, const QView* X, double rtol, int64_t max_rank,
                           int64_t* const* rank_out, GroupWs& gw, PinvWs jw, QView* Qv, QView* Pv,
-                          double orth_tol) {
+                          double orth_tol, PinvSpec* spec = nullptr) {
   const int64_t pp = gw.pp, qq = gw.qq;
   const int64_t zslab = 4 * pp * qq, gslab = 4 * qq * qq;
   QView fx[MAXB];
@@ -526,7 +578,7 @@ qcur_status pinv_group_qp(const Ctx& c, int nb, const QView* X, double rtol, int
     GroupWs w = gw;
     w.nb = nf;
     CHK(pinv_fast_group(c, nf, fx, rg, max_rank, nullptr, fr, w, orth_tol > 0.0 ? 0 : 2, done, orth_tol,
-                        &final_pass));
+                        &final_pass, spec));
     for (int f = 0; f < nf; ++f) {
       slot(f, idx[f]);
       if (!done[f]) CHK(pinv_jacobi_qp(c, fx[f], rt[idx[f]], max_rank, Qv[idx[f]], Pv[idx[f]], fr[f], jw));
@@ -631,33 +683,24 @@ qcur_status approx_run(const Ctx& c, const ApproxArgs& a, int64_t m, int64_t n, 
     // dtype, so their rounding stays near u ||A|| whatever the conditioning
     // of C and R; only the small factors P meet M, in FP64.
     QView Qv[2], Pv[2];
-    {
-      PinvPlan pc = pinv_plan(m, cc), pr = pinv_plan(r, n);
-      const int64_t pp = std::max(pc.pp, pr.pp), qq = std::max(pc.qq, pr.qq);
-      Bump pb = b;
-      PinvWs jw = pinv_carve(pb, pp, qq);
-      GroupWs gw = group_carve(pb, 2, pp, qq);
-      if (!count_only) {
-        QView xs[2] = {a.C, a.R};
-        int64_t* ro[2] = {a.rank_out, a.rank_out ? a.rank_out + 1 : nullptr};
-        // FP64 products: CholeskyQR2; FP32/BF16 products: a second pass only
-        // when the first leaves Q^H Q - I above a small fraction of their
-        // rounding unit
-        const double orth_tol = a.compute == QCUR_F64 ? 0.0 : a.compute == QCUR_BF16 ? 0x1p-12 : 0x1p-26;
-        CHK(pinv_group_qp(c, 2, xs, a.rtol, a.max_rank, ro, gw, jw, Qv, Pv, orth_tol));
-      } else {
-        Qv[0] = QView{nullptr, m, cc, cc, m * cc, QCUR_F64};
-        Qv[1] = QView{nullptr, n, r, r, n * r, QCUR_F64};
-        Pv[0] = QView{nullptr, cc, cc, cc, cc * cc, QCUR_F64};
-        Pv[1] = QView{nullptr, r, r, r, r * r, QCUR_F64};
-      }
-      b.used = pb.used;
-    }
-    // operands in the product dtype
+    PinvPlan pc = pinv_plan(m, cc), pr = pinv_plan(r, n);
+    const int64_t pp = std::max(pc.pp, pr.pp), qq = std::max(pc.qq, pr.qq);
+    Bump pb = b;
+    PinvWs jw = pinv_carve(pb, pp, qq);
+    GroupWs gw = group_carve(pb, 2, pp, qq);
+    b.used = pb.used;
+    QView xs[2] = {a.C, a.R};
+    int64_t* ro[2] = {a.rank_out, a.rank_out ? a.rank_out + 1 : nullptr};
+    // FP64 products: CholeskyQR2; FP32/BF16 products: a second pass only
+    // when the first leaves Q^H Q - I above a small fraction of their
+    // rounding unit
+    const double orth_tol = a.compute == QCUR_F64 ? 0.0 : a.compute == QCUR_BF16 ? 0x1p-12 : 0x1p-26;
+    // operands in the product dtype (Q_C, Q_R are cast into fixed buffers,
+    // so that a recomputation reuses them)
     QView Ax = as_dtype(c, a.A, idt, b, count_only, &err);
-    QView Qc = as_dtype(c, Qv[0], idt, b, count_only, &err);
-    QView Qr = as_dtype(c, Qv[1], idt, b, count_only, &err);
     if (err != hipSuccess) return fail(QCUR_ERR_DEVICE, "cast: %s", hipGetErrorString(err));
+    QView QcB = idt == QCUR_F64 ? QView{} : b.mat(m, cc, idt);
+    QView QrB = idt == QCUR_F64 ? QView{} : b.mat(n, r, idt);
     QView T = b.mat(m, r, adt);
     QView Tx = (idt == adt) ? T : b.mat(m, r, idt);
     QView M = b.mat(cc, r, adt);
@@ -671,42 +714,76 @@ qcur_status approx_run(const Ctx& c, const ApproxArgs& a, int64_t m, int64_t n, 
     QView E = need_E ? b.mat(m, n, adt) : QView{};
     QView Ex = need_E ? ((idt == adt) ? E : b.mat(m, n, idt)) : QView{};
     double* part = (double*)b.take(std::max<size_t>(residual_tiles(m, n, a.compute), 1) * 8);
-    size_t gw = std::max({gemm_workspace(m, r, n, a.compute), gemm_workspace(cc, r, m, a.compute),
-                          gemm_workspace(m, r, cc, a.compute), gemm_workspace(m, n, r, a.compute),
-                          gemm_workspace(cc, r, r, QCUR_F64), gemm_workspace(cc, r, cc, QCUR_F64)});
-    void* gws = b.take(gw);
+    size_t gw_bytes = std::max({gemm_workspace(m, r, n, a.compute), gemm_workspace(cc, r, m, a.compute),
+                                gemm_workspace(m, r, cc, a.compute), gemm_workspace(m, n, r, a.compute),
+                                gemm_workspace(cc, r, r, QCUR_F64), gemm_workspace(cc, r, cc, QCUR_F64)});
+    void* gws = b.take(gw_bytes);
     if (count_only) return QCUR_OK;
-    // M = Q_C^H (A Q_R)
-    HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Ax, Qr, 0.0, T, a.compute, gws, gw));
-    if (Tx.p != T.p) HIPCHK(launch_cast(c, T, Tx, CAST_COPY));
-    HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, Qc, Tx, 0.0, M, a.compute, gws, gw));
-    auto left_factor = [&]() -> qcur_status {  // B1 = Q_C M in the product dtype
-      if (Mx.p != M.p) HIPCHK(launch_cast(c, M, Mx, CAST_COPY));
-      HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Qc, Mx, 0.0, B1, a.compute, gws, gw));
-      if (B1x.p != B1.p) HIPCHK(launch_cast(c, B1, B1x, CAST_COPY));
+    // Everything after the factors: M = Q_C^H (A Q_R), refinement, residual,
+    // B and U = P_C^H M P_R.
+    auto products = [&]() -> qcur_status {
+      QView Qc = Qv[0], Qr = Qv[1];
+      if (idt != QCUR_F64) {
+        // dense copies with the factors' shapes (same element counts as the
+        // buffers carved above)
+        const QView Qc2{QcB.p, Qc.rows, Qc.cols, Qc.cols, Qc.rows * Qc.cols, idt};
+        const QView Qr2{QrB.p, Qr.rows, Qr.cols, Qr.cols, Qr.rows * Qr.cols, idt};
+        HIPCHK(launch_cast(c, Qc, Qc2, CAST_COPY));
+        HIPCHK(launch_cast(c, Qr, Qr2, CAST_COPY));
+        Qc = Qc2;
+        Qr = Qr2;
+      }
+      const size_t gw = gw_bytes;
+      HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Ax, Qr, 0.0, T, a.compute, gws, gw));
+      if (Tx.p != T.p) HIPCHK(launch_cast(c, T, Tx, CAST_COPY));
+      HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, Qc, Tx, 0.0, M, a.compute, gws, gw));
+      auto left_factor = [&]() -> qcur_status {  // B1 = Q_C M in the product dtype
+        if (Mx.p != M.p) HIPCHK(launch_cast(c, M, Mx, CAST_COPY));
+        HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Qc, Mx, 0.0, B1, a.compute, gws, gw));
+        if (B1x.p != B1.p) HIPCHK(launch_cast(c, B1, B1x, CAST_COPY));
+        return QCUR_OK;
+      };
+      for (int st = 0; st < a.refine; ++st) {
+        // E = A - Q_C M Q_R^H (A in the precision it was given);  M += Q_C^H (E Q_R)
+        CHK(left_factor());
+        HIPCHK(launch_residual_gemm(c, a.A, B1x, Qr, nullptr, 0, a.compute, part, &E, 1.0, QCUR_OP_H));
+        if (Ex.p != E.p) HIPCHK(launch_cast(c, E, Ex, CAST_COPY));
+        HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Ex, Qr, 0.0, T, a.compute, gws, gw));
+        if (Tx.p != T.p) HIPCHK(launch_cast(c, T, Tx, CAST_COPY));
+        HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, Qc, Tx, 1.0, M, a.compute, gws, gw));
+      }
+      if (a.fro || a.hasB) CHK(left_factor());
+      if (a.fro) {
+        // ||A - C U R||_F = ||A - Q_C M Q_R^H||_F
+        HIPCHK(launch_residual_gemm(c, a.A, B1x, Qr, nullptr, 0, a.compute, part, nullptr, 0.0, QCUR_OP_H));
+        HIPCHK(launch_sum_partials(c, part, (int64_t)residual_tiles(m, n, a.compute), a.fro, 1));
+      }
+      if (a.hasB) HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_H, 1.0, B1x, Qr, 0.0, a.B, a.compute, gws, gw));
+      // U = P_C^H (M P_R) in FP64
+      if (M64.p != M.p) HIPCHK(launch_cast(c, M, M64, CAST_COPY));
+      HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, M64, Pv[1], 0.0, W1, QCUR_F64, gws, gw));
+      HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, Pv[0], W1, 0.0, U64, QCUR_F64, gws, gw));
+      if (U64.p != a.U.p) HIPCHK(launch_cast(c, U64, a.U, CAST_COPY));
       return QCUR_OK;
     };
-    for (int st = 0; st < a.refine; ++st) {
-      // E = A - Q_C M Q_R^H (A in the precision it was given);  M += Q_C^H (E Q_R)
-      CHK(left_factor());
-      HIPCHK(launch_residual_gemm(c, a.A, B1x, Qr, nullptr, 0, a.compute, part, &E, 1.0, QCUR_OP_H));
-      if (Ex.p != E.p) HIPCHK(launch_cast(c, E, Ex, CAST_COPY));
-      HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Ex, Qr, 0.0, T, a.compute, gws, gw));
-      if (Tx.p != T.p) HIPCHK(launch_cast(c, T, Tx, CAST_COPY));
-      HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, Qc, Tx, 1.0, M, a.compute, gws, gw));
+    // The factors' certificate needs one host synchronisation.  When the
+    // products are cheap next to that round trip (A Q_R at most 4e10 flops,
+    // about 0.4 ms), the products of the fast path are enqueued before it, so
+    // the GPU stays busy while the host waits; if the certificate then
+    // rejects the fast path (or asks for a second CholeskyQR pass), the
+    // factors are recomputed without speculation and the products run again.
+    // Larger problems wait first: a rejected guess would cost more than the
+    // round trip saves.
+    PinvSpec spec;
+    const bool speculate = 32.0 * (double)m * (double)n * (double)r <= 4e10;
+    CHK(pinv_group_qp(c, 2, xs, a.rtol, a.max_rank, ro, gw, jw, Qv, Pv, orth_tol, speculate ? &spec : nullptr));
+    CHK(products());
+    bool valid = true;
+    CHK(pinv_spec_resolve(c, spec, &valid));
+    if (!valid) {
+      CHK(pinv_group_qp(c, 2, xs, a.rtol, a.max_rank, ro, gw, jw, Qv, Pv, orth_tol));
+      CHK(products());
     }
-    if (a.fro || a.hasB) CHK(left_factor());
-    if (a.fro) {
-      // ||A - C U R||_F = ||A - Q_C M Q_R^H||_F
-      HIPCHK(launch_residual_gemm(c, a.A, B1x, Qr, nullptr, 0, a.compute, part, nullptr, 0.0, QCUR_OP_H));
-      HIPCHK(launch_sum_partials(c, part, (int64_t)residual_tiles(m, n, a.compute), a.fro, 1));
-    }
-    if (a.hasB) HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_H, 1.0, B1x, Qr, 0.0, a.B, a.compute, gws, gw));
-    // U = P_C^H (M P_R) in FP64
-    if (M64.p != M.p) HIPCHK(launch_cast(c, M, M64, CAST_COPY));
-    HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, M64, Pv[1], 0.0, W1, QCUR_F64, gws, gw));
-    HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, Pv[0], W1, 0.0, U64, QCUR_F64, gws, gw));
-    if (U64.p != a.U.p) HIPCHK(launch_cast(c, U64, a.U, CAST_COPY));
     return QCUR_OK;
   }
   if (a.hasB) {
@@ -1433,6 +1510,7 @@ qcur_status complete_run(const Ctx& c, const CompleteArgs& a, Bump& b, bool coun
   // the iterate of step t lives in cur; the next goes to nxt
   QView cur = a.X, nxt = Xw;
   const double orth_tol = a.compute == QCUR_F64 ? 0.0 : a.compute == QCUR_BF16 ? 0x1p-12 : 0x1p-26;
+  const bool speculate = 32.0 * (double)m * (double)n * (double)r <= 4e10;
   int t = 0;
   double rel = INFINITY;
   while (t < a.max_iter) {
@@ -1451,25 +1529,38 @@ qcur_status complete_run(const Ctx& c, const CompleteArgs& a, Bump& b, bool coun
     QView Qv[2], Pv[2];
     QView xs[2] = {C, R};
     int64_t* ro[2] = {ranks, ranks + 1};
-    CHK(pinv_group_qp(c, 2, xs, a.rtol, a.max_rank, ro, gw, jw, Qv, Pv, orth_tol));
-    HIPCHK(launch_cast(c, Qv[0], Qc, CAST_COPY));
-    HIPCHK(launch_cast(c, Qv[1], Qr, CAST_COPY));
-    QView Xin = cur;
-    if (Xx.p) {
-      HIPCHK(launch_cast(c, cur, Xx, CAST_COPY));
-      Xin = Xx;
+    auto products = [&]() -> qcur_status {
+      HIPCHK(launch_cast(c, Qv[0], Qc, CAST_COPY));
+      HIPCHK(launch_cast(c, Qv[1], Qr, CAST_COPY));
+      QView Xin = cur;
+      if (Xx.p) {
+        HIPCHK(launch_cast(c, cur, Xx, CAST_COPY));
+        Xin = Xx;
+      }
+      // M = Q_C^H (X^t Q_R);  B1 = Q_C M;  X^{t+1} = P_Omega(Y) + P_Omega^c(B1 Q_R^H)
+      HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Xin, Qr, 0.0, T, a.compute, gws, gwb));
+      if (Tx.p != T.p) HIPCHK(launch_cast(c, T, Tx, CAST_COPY));
+      HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, Qc, Tx, 0.0, M, a.compute, gws, gwb));
+      if (Mx.p != M.p) HIPCHK(launch_cast(c, M, Mx, CAST_COPY));
+      HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Qc, Mx, 0.0, B1, a.compute, gws, gwb));
+      if (B1x.p != B1.p) HIPCHK(launch_cast(c, B1, B1x, CAST_COPY));
+      HIPCHK(launch_merge_gemm(c, a.Y, a.mask, a.mask_ld, cur, B1x, Qr, QCUR_OP_H, a.compute, nxt, pd, po));
+      HIPCHK(launch_sum_partials(c, pd, tiles, sums, 0));
+      HIPCHK(launch_sum_partials(c, po, tiles, sums + 1, 0));
+      return QCUR_OK;
+    };
+    // as in the solve: the step's products are enqueued before the factors'
+    // certificate is read when they are cheap, and redone if it rejects them
+    PinvSpec spec;
+    CHK(pinv_group_qp(c, 2, xs, a.rtol, a.max_rank, ro, gw, jw, Qv, Pv, orth_tol, speculate ? &spec : nullptr));
+    CHK(products());
+    bool valid = true;
+    CHK(pinv_spec_resolve(c, spec, &valid));
+    if (!valid) {
+      CHK(pinv_group_qp(c, 2, xs, a.rtol, a.max_rank, ro, gw, jw, Qv, Pv, orth_tol));
+      CHK(products());
     }
-    // M = Q_C^H (X^t Q_R);  B1 = Q_C M;  X^{t+1} = P_Omega(Y) + P_Omega^c(B1 Q_R^H)
-    HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Xin, Qr, 0.0, T, a.compute, gws, gwb));
-    if (Tx.p != T.p) HIPCHK(launch_cast(c, T, Tx, CAST_COPY));
-    HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, Qc, Tx, 0.0, M, a.compute, gws, gwb));
-    if (Mx.p != M.p) HIPCHK(launch_cast(c, M, Mx, CAST_COPY));
-    HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Qc, Mx, 0.0, B1, a.compute, gws, gwb));
-    if (B1x.p != B1.p) HIPCHK(launch_cast(c, B1, B1x, CAST_COPY));
-    HIPCHK(launch_merge_gemm(c, a.Y, a.mask, a.mask_ld, cur, B1x, Qr, QCUR_OP_H, a.compute, nxt, pd, po));
-    HIPCHK(launch_sum_partials(c, pd, tiles, sums, 0));
-    HIPCHK(launch_sum_partials(c, po, tiles, sums + 1, 0));
-    double h2[2] = {0.0, 0.0};
+    double* h2 = ((HostVerdict*)c.pinned)->aux;
     HIPCHK(hipMemcpyAsync(h2, sums, 16, hipMemcpyDeviceToHost, c.stream));
     HIPCHK(hipStreamSynchronize(c.stream));
     rel = h2[1] > 0.0 ? std::sqrt(h2[0] / h2[1]) : (h2[0] > 0.0 ? INFINITY : 0.0);
@@ -1523,14 +1614,24 @@ qcur_status qcur_create(qcur_handle* handle, int device) {
   HIPCHK(hipGetDevice(&old));
   HIPCHK(hipSetDevice(device));
   unsigned* st = nullptr;
+  void* pinned = nullptr;
+  hipEvent_t done = nullptr;
   hipError_t e = hipMalloc(&st, 256);
   if (e == hipSuccess) e = hipMemset(st, 0, 256);
+  if (e == hipSuccess) e = hipHostMalloc(&pinned, sizeof(HostVerdict), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
   (void)hipSetDevice(old);
-  if (e != hipSuccess) return fail(QCUR_ERR_DEVICE, "status word: %s", hipGetErrorString(e));
+  if (e != hipSuccess) {
+    if (st) (void)hipFree(st);
+    if (pinned) (void)hipHostFree(pinned);
+    return fail(QCUR_ERR_DEVICE, "handle resources: %s", hipGetErrorString(e));
+  }
   qcur_ctx* h = new qcur_ctx;
   h->c.device = device;
   h->c.stream = nullptr;
   h->c.status = st;
+  h->c.pinned = pinned;
+  h->c.done = done;
   *handle = h;
   return QCUR_OK;
 }
@@ -1542,6 +1643,8 @@ qcur_status qcur_destroy(qcur_handle h) {
     if (rec.tun.e1) (void)hipEventDestroy(rec.tun.e1);
   }
   (void)hipFree(h->c.status);
+  (void)hipHostFree(h->c.pinned);
+  (void)hipEventDestroy(h->c.done);
   delete h;
   return QCUR_OK;
 }

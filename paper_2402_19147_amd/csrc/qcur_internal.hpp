@@ -33,6 +33,8 @@ struct Ctx {
   int device;
   hipStream_t stream;
   unsigned* status;  // device word
+  void* pinned;      // small pinned host buffer (fast-path verdicts)
+  hipEvent_t done;   // marks the arrival of those verdicts
 };
 
 // ---- element conversions --------------------------------------------------

@@ -414,6 +414,46 @@ def test_approx_car_mixed_precision(compute, tol, refine):
     assert rel(N(B), Br) < tol
 
 
+@pytest.mark.parametrize("compute", [Q.F64, Q.F32])
+def test_approx_car_rejected_fast_path_recomputes(compute):
+    # exact rank 5 with 12 sampled columns and rows: the Gram matrices of C
+    # and R are singular, the certificate rejects the fast path after its
+    # products were enqueued, and the Jacobi factors replace it
+    L, Rt, _ = workloads.lowrank_gaussian_factors(90, 80, 5, 61)
+    A = qmul(L, Rt)
+    rng = np.random.default_rng(8)
+    I = np.sort(rng.choice(90, 12, replace=False))
+    J = np.sort(rng.choice(80, 12, replace=False))
+    C, R, W = oracle.gather(A, I, J)
+    dt = torch.float64 if compute == Q.F64 else torch.float32
+    # FP32 inputs carry rounding of relative size 2^-24: truncate below it
+    rtol = -1.0 if compute == Q.F64 else 1e-5
+    U, B, ranks = Q.approx(T(A, dt), T(C, dt), T(R, dt), None, core=Q.CORE_CAR, compute=compute, rtol=rtol,
+                           want_B=True)
+    assert N(ranks).tolist() == [5, 5]
+    # Lemma 1: C U R = A when rank C = rank R = rank A
+    assert rel(N(B), A) < (1e-10 if compute == Q.F64 else 1e-5)
+
+
+def test_approx_car_f32_second_pass_matches_checker():
+    # columns graded over five decades: kappa(C), kappa(R) near 1e5 keep the
+    # fast path but leave the first CholeskyQR pass non-orthogonal beyond
+    # 2^-26, so the second pass runs after the speculative products
+    rng = np.random.default_rng(9)
+    m, n = 160, 120
+    A = rng.standard_normal((4, m, n)) * (10.0 ** (-5.0 * np.arange(n) / (n - 1)))[None, None, :]
+    I = np.sort(rng.choice(m, 40, replace=False))
+    J = np.sort(rng.choice(n, 30, replace=False))
+    J[0], J[-1] = 0, n - 1
+    C, R, W = oracle.gather(A, I, J)
+    Ur, kc, kr = oracle.core_car(A, C, R)
+    Br = oracle.cur_product(C, Ur, R)
+    U, B, ranks = Q.approx(T(A, torch.float32), T(C, torch.float32), T(R, torch.float32), None,
+                           core=Q.CORE_CAR, compute=Q.F32, want_B=True)
+    assert N(ranks).tolist() == [kc, kr] == [30, 40]
+    assert rel(N(B), Br) < max(1e-5, 4 * 2.0 ** -24 * (kappa(C) + kappa(R)))
+
+
 def test_residual_masked_matches_checker():
     rng = np.random.default_rng(3)
     A = _noisy(140, 150, 5, 31, 1e-2)
