@@ -104,10 +104,12 @@ def main():
     ref = q.solve(A64, c, r, sampling=q.LENGTH, core=q.CORE_CAR, compute=q.F64, seed=seed, want_B=True)
     Bref = ref["B"].to(torch.float64)
     nA = float(torch.linalg.vector_norm(A64))
+    B_host = {}
     for name, v in variants.items():
         out = q.solve(v["A"], c, r, sampling=q.LENGTH, core=q.CORE_CAR, compute=v["compute"], seed=seed,
                       refine_steps=v["refine"], want_B=True)
         B = out["B"].to(torch.float64)
+        B_host[name] = (B.cpu().numpy(), out["I"].cpu().numpy(), out["J"].cpu().numpy())
         results[name]["cur_rel_err_vs_f64"] = float(torch.linalg.vector_norm(B - Bref) / torch.linalg.vector_norm(Bref))
         results[name]["rel_residual"] = float(out["residual"].cpu()[0]) / nA
         results[name]["same_draws"] = bool(torch.equal(out["I"], ref["I"]) and torch.equal(out["J"], ref["J"]))
@@ -149,6 +151,12 @@ def main():
                     unit="TFLOP/s", frac=achieved / peak, traffic=traffic, avg_launch_us=t_gemm * 1e6,
                     algorithmic_flop_per_launch=flops, algorithmic_bytes_per_launch=4.0 * (m * n + n * r + m * r) *
                     {q.F64: 8, q.F32: 4, q.BF16: 2}[hd])
+    ceil = measured_ceilings(torch, dev)
+    mkey = {q.F64: "f64", q.F32: "f32", q.BF16: "bf16"}[hd]
+    roofline["measured_peak"] = ceil["mfma_tflops"][mkey]
+    roofline["frac_of_measured"] = achieved / ceil["mfma_tflops"][mkey] if ceil["mfma_tflops"][mkey] else None
+    log("measured ceilings: MFMA " + ", ".join(f"{k} {v:.1f}" for k, v in ceil["mfma_tflops"].items()) +
+        f" TFLOP/s, copy {ceil['copy_gbps']:.0f} GB/s")
 
     # quaternion GEMM rate at the dense shapes, every dtype
     qg = {}
@@ -161,7 +169,8 @@ def main():
             Y = torch.tensor(rng.standard_normal((4, K, N)), dtype=dt, device=dev)
             t = time_gemm(X, Y, dcode, 5)
             tf = 32.0 * M * K * N / t / 1e12
-            qg[f"{dname}_{M}x{K}x{N}"] = dict(tflops=tf, frac_of_peak=tf / pk, ms=t * 1e3)
+            qg[f"{dname}_{M}x{K}x{N}"] = dict(tflops=tf, frac_of_peak=tf / pk, ms=t * 1e3,
+                                              frac_of_measured=tf / ceil["mfma_tflops"][dname])
             del X, Y
     # split BF16: FP32 operands, three BF16 products; tflops counts the
     # quaternion product once, the fraction counts the three MFMA products
@@ -175,7 +184,7 @@ def main():
         del X, Y
     log("qgemm: " + ", ".join(f"{k} {v['tflops']:.1f}" for k, v in qg.items()))
 
-    extra = {}
+    extra = {"measured_ceilings": ceil, "hbm_kernels": bench_hbm(q, torch, dev, A32, ceil)}
     if not args.no_extra:
         extra["batch_512"] = bench_batch(q, torch, workloads, dev, args)
         extra["dense_4096"] = bench_dense(q, torch, workloads, dev, args)
@@ -192,7 +201,13 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(A_host, c, r, seed, args.cpu_seconds)
+        cpu, ref_cpu = cpu_baseline(A_host, c, r, seed, args.cpu_seconds)
+        # every variant's C U R against the oracle's (same draws required)
+        for name, (Bv, Iv, Jv) in B_host.items():
+            same = bool(np.array_equal(Iv, ref_cpu["I"]) and np.array_equal(Jv, ref_cpu["J"]))
+            results[name]["oracle_same_draws"] = same
+            results[name]["cur_rel_err_vs_oracle"] = (float(np.linalg.norm(Bv - ref_cpu["B"]) /
+                                                            np.linalg.norm(ref_cpu["B"])) if same else None)
 
     line = {
         "metric": "QMCUR solves/s (mixed precision, rel. err <= 1e-3 vs FP64)",
@@ -506,25 +521,115 @@ def bench_theorem1(q, torch, workloads, dev):
 
 
 def cpu_baseline(A, c, r, seed, seconds):
-    """The FP64 reference checker timed on the host cores, whole solves."""
+    """The FP64 reference checker timed on the host cores, whole solves: with
+    the BLAS threads it starts with, then with one thread.  Also returns one
+    solve's I, J and C U R for the accuracy comparison."""
     import numpy as np
     import oracle
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
     except Exception:
+        threadpool_limits = None
         threads = os.cpu_count()
-    times = []
-    t_end = time.perf_counter() + seconds
-    while True:
-        t0 = time.perf_counter()
-        oracle.solve(A, c, r, "length", "car", seed=seed)
-        times.append(time.perf_counter() - t0)
-        if time.perf_counter() > t_end or len(times) >= 50:
-            break
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+    except OSError:
+        pass
+
+    def timed(budget, cap):
+        times, out = [], None
+        t_end = time.perf_counter() + budget
+        while True:
+            t0 = time.perf_counter()
+            out = oracle.solve(A, c, r, "length", "car", seed=seed)
+            times.append(time.perf_counter() - t0)
+            if time.perf_counter() > t_end or len(times) >= cap:
+                return times, out
+
+    times, ref = timed(seconds, 50)
     med = float(np.median(times))
-    return {"value": 1.0 / med, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(times)} full FP64 solves of the same 1024x1024 workload, median"}
+    one = None
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            t1, _ = timed(seconds / 2, 10)
+        one = {"value": 1.0 / float(np.median(t1)), "cores": 1, "sample": f"{len(t1)} solves, median"}
+    B = oracle.cur_product(ref["C"], ref["U"], ref["R"])
+    cpu = {"value": 1.0 / med, "unit": "solves/s", "cores": threads, "kind": "oracle",
+           "sample": f"{len(times)} full FP64 solves of the same 1024x1024 workload, median",
+           "host_cpus": os.cpu_count(), "cpu_model": model, "one_thread": one}
+    return cpu, {"I": ref["I"], "J": ref["J"], "B": B}
+
+
+def measured_ceilings(torch, dev):
+    """Achievable MFMA rate per dtype and streaming-copy bandwidth on this
+    device (libqcur_probe: a loop of independent MFMAs, a 1 GiB copy)."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2402_19147_amd", "libqcur_probe.so"))
+    lib.qcur_probe_mfma.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    lib.qcur_probe_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_double)]
+    torch.cuda.synchronize()
+    out = {"mfma_tflops": {}}
+    for name, code in (("f64", 0), ("f32", 1), ("bf16", 2)):
+        v = ctypes.c_double(0.0)
+        rc = lib.qcur_probe_mfma(code, 4096, ctypes.byref(v))
+        if rc != 0:
+            raise RuntimeError(f"qcur_probe_mfma({name}) failed: {rc}")
+        out["mfma_tflops"][name] = v.value
+    src = torch.empty(2 ** 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    torch.cuda.synchronize()
+    g = ctypes.c_double(0.0)
+    rc = lib.qcur_probe_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), 2 ** 30, 10,
+                             ctypes.byref(g))
+    if rc != 0:
+        raise RuntimeError(f"qcur_probe_copy failed: {rc}")
+    out["copy_gbps"] = g.value
+    out["copy_bytes"] = 2 ** 30
+    del src, dst
+    return out
+
+
+def bench_hbm(q, torch, dev, A32, ceil):
+    """Achieved HBM bandwidth of the HBM-bound steps: the probabilities (a1,
+    one read of A) on the 1024^2 workload and on a 4096^2 FP32 matrix, and the
+    gathers (a3) at 4096^2 with c = r = 400.  Algorithmic bytes over the time
+    of one call (all of its launches), against 8 TB/s and the measured copy."""
+    import numpy as np
+
+    def timed(fn, reps=20):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    out = {}
+    big = torch.randn((4, 4096, 4096), dtype=torch.float32, device=dev)
+    for name, X in (("probs_f32_1024x1024", A32), ("probs_f32_4096x4096", big)):
+        _, mm, nn = X.shape
+        t = timed(lambda: q.probs(X, q.LENGTH))
+        byt = 4.0 * mm * nn * 4
+        out[name] = {"bytes": byt, "us": t * 1e6, "gbps": byt / t / 1e9, "frac_of_peak": byt / t / 8e12,
+                     "frac_of_measured": byt / t / 1e9 / ceil["copy_gbps"]}
+    rng = np.random.default_rng(3)
+    I = torch.tensor(np.sort(rng.choice(4096, 400, replace=False)), device=dev)
+    J = torch.tensor(np.sort(rng.choice(4096, 400, replace=False)), device=dev)
+    t = timed(lambda: q.gather(big, I, J))
+    byt = 2.0 * 4 * (4096 * 400 + 400 * 4096 + 400 * 400) * 4
+    out["gather_f32_4096_c400"] = {"bytes": byt, "us": t * 1e6, "gbps": byt / t / 1e9, "frac_of_peak": byt / t / 8e12,
+                                   "frac_of_measured": byt / t / 1e9 / ceil["copy_gbps"]}
+    del big
+    log("hbm: " + ", ".join(f"{k} {v['gbps']:.0f} GB/s" for k, v in out.items()))
+    return out
 
 
 if __name__ == "__main__":

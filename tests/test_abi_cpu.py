@@ -38,6 +38,29 @@ def test_every_declared_symbol_is_exported(L):
         assert call in names
 
 
+def test_probe_library_exports_and_validates():
+    # the measured-ceiling probes (measurement only) live in their own library
+    path = os.path.join(os.path.dirname(Q.LIB_PATH), "libqcur_probe.so")
+    if not os.path.exists(path):
+        pytest.skip("libqcur_probe.so not built")
+    with open(os.path.join(ROOT, "include", "qcur_probe.h")) as f:
+        text = re.sub(r"/\*.*?\*/", "", f.read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(qcur_[a-z0-9_]+)\s*\(", text)))
+    assert names == ["qcur_probe_copy", "qcur_probe_mfma"]
+    lib = ctypes.CDLL(path)
+    assert all(hasattr(lib, n) for n in names)
+    lib.qcur_probe_mfma.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    lib.qcur_probe_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_double)]
+    v = ctypes.c_double(0.0)
+    # rejected before any device call: unknown dtype, empty or misaligned copies
+    assert lib.qcur_probe_mfma(3, 16, ctypes.byref(v)) == 1
+    assert lib.qcur_probe_mfma(0, 0, ctypes.byref(v)) == 1
+    assert lib.qcur_probe_copy(FAKE, FAKE + 4096, 0, 1, ctypes.byref(v)) == 1
+    assert lib.qcur_probe_copy(FAKE + 8, FAKE + 4096, 64, 1, ctypes.byref(v)) == 1
+    assert lib.qcur_probe_copy(FAKE, FAKE + 4096, 40, 1, ctypes.byref(v)) == 1
+
+
 def test_status_strings(L):
     for k, v in Q.STATUS.items():
         assert L.qcur_status_string(k).decode() == v
