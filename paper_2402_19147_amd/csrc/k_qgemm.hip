@@ -812,9 +812,43 @@ hipError_t launch_gemm(const Ctx& c, int opA, int opB, double alpha, QView A, QV
   return launch_gemm_batched(c, opA, opB, alpha, A, B, beta, D, compute, ws, ws_bytes, BatchSpec{});
 }
 
+// Tile edge of the fused residual and merge products (no K split: their
+// epilogues reduce): 32 when 64-tiles would give fewer than two workgroups
+// per compute unit, and always for split BF16.
+static int resid_tile(int64_t m, int64_t n, int compute) {
+  if (compute == QCUR_BF16X3) return 32;
+  return ((m + 63) / 64) * ((n + 63) / 64) < 512 ? 32 : 64;
+}
+
 size_t residual_tiles(int64_t m, int64_t n, int compute) {
-  const int64_t t = compute == QCUR_BF16X3 ? 32 : 64;
+  const int64_t t = resid_tile(m, n, compute);
   return (size_t)((m + t - 1) / t) * (size_t)((n + t - 1) / t);
+}
+
+// One launch of the fused epilogue product on tiles of edge t.
+template <int EPI>
+static void launch_fused(const Ctx& c, GemmArgs& g, int compute, int t) {
+  const dim3 grid((unsigned)((g.N + t - 1) / t), (unsigned)((g.M + t - 1) / t), 1);
+  switch (compute) {
+    case QCUR_F64:
+      g.ktiles_per_split = (int)((g.K + 15) / 16);
+      if (t == 64) hipLaunchKernelGGL((k_qgemm<QCUR_F64, EPI, 64, 64>), grid, dim3(NT), 0, c.stream, g);
+      else hipLaunchKernelGGL((k_qgemm<QCUR_F64, EPI, 32, 32>), grid, dim3(NT), 0, c.stream, g);
+      break;
+    case QCUR_F32:
+      g.ktiles_per_split = (int)((g.K + 15) / 16);
+      if (t == 64) hipLaunchKernelGGL((k_qgemm<QCUR_F32, EPI, 64, 64>), grid, dim3(NT), 0, c.stream, g);
+      else hipLaunchKernelGGL((k_qgemm<QCUR_F32, EPI, 32, 32>), grid, dim3(NT), 0, c.stream, g);
+      break;
+    case QCUR_BF16X3:
+      g.ktiles_per_split = (int)((g.K + 31) / 32);
+      hipLaunchKernelGGL((k_qgemm<QCUR_BF16X3, EPI, 32, 32>), grid, dim3(NT), 0, c.stream, g);
+      break;
+    default:
+      g.ktiles_per_split = (int)((g.K + 31) / 32);
+      if (t == 64) hipLaunchKernelGGL((k_qgemm<QCUR_BF16, EPI, 64, 64>), grid, dim3(NT), 0, c.stream, g);
+      else hipLaunchKernelGGL((k_qgemm<QCUR_BF16, EPI, 32, 32>), grid, dim3(NT), 0, c.stream, g);
+  }
 }
 
 hipError_t launch_residual_gemm(const Ctx& c, QView A, QView B1, QView R, const uint8_t* mask, int64_t mask_ld,
@@ -834,29 +868,7 @@ hipError_t launch_residual_gemm(const Ctx& c, QView A, QView B1, QView R, const 
   if (E) { g.E = E->p; g.edt = E->dt; g.eld = E->ld; g.eps = E->ps; g.e_scale = e_scale; }
   if (g.M == 0 || g.N == 0) return hipSuccess;
   g.splits = 1;
-  if (compute == QCUR_BF16X3) {
-    const dim3 g32((unsigned)((g.N + 31) / 32), (unsigned)((g.M + 31) / 32), 1);
-    g.ktiles_per_split = (int)((g.K + 31) / 32);
-    hipLaunchKernelGGL((k_qgemm<QCUR_BF16X3, EPI_RESID, 32, 32>), g32, dim3(NT), 0, c.stream, g);
-    return hipGetLastError();
-  }
-  dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64), 1);
-  switch (compute) {
-    case QCUR_F64: {
-      g.ktiles_per_split = (int)((g.K + 15) / 16);
-      hipLaunchKernelGGL((k_qgemm<QCUR_F64, EPI_RESID, 64, 64>), grid, dim3(NT), 0, c.stream, g);
-      break;
-    }
-    case QCUR_F32: {
-      g.ktiles_per_split = (int)((g.K + 15) / 16);
-      hipLaunchKernelGGL((k_qgemm<QCUR_F32, EPI_RESID, 64, 64>), grid, dim3(NT), 0, c.stream, g);
-      break;
-    }
-    default: {
-      g.ktiles_per_split = (int)((g.K + 31) / 32);
-      hipLaunchKernelGGL((k_qgemm<QCUR_BF16, EPI_RESID, 64, 64>), grid, dim3(NT), 0, c.stream, g);
-    }
-  }
+  launch_fused<EPI_RESID>(c, g, compute, resid_tile(g.M, g.N, compute));
   return hipGetLastError();
 }
 
@@ -923,26 +935,7 @@ hipError_t launch_merge_gemm(const Ctx& c, QView Y, const uint8_t* mask, int64_t
   g.splits = 1;
   g.vec = compute == QCUR_BF16 && vec_ok(B1, 0) && vec_ok(R, 0);
   if (g.M == 0 || g.N == 0) return hipSuccess;
-  if (compute == QCUR_BF16X3) {
-    const dim3 g32((unsigned)((g.N + 31) / 32), (unsigned)((g.M + 31) / 32), 1);
-    g.ktiles_per_split = (int)((g.K + 31) / 32);
-    hipLaunchKernelGGL((k_qgemm<QCUR_BF16X3, EPI_MERGE, 32, 32>), g32, dim3(NT), 0, c.stream, g);
-    return hipGetLastError();
-  }
-  dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64), 1);
-  switch (compute) {
-    case QCUR_F64:
-      g.ktiles_per_split = (int)((g.K + 15) / 16);
-      hipLaunchKernelGGL((k_qgemm<QCUR_F64, EPI_MERGE, 64, 64>), grid, dim3(NT), 0, c.stream, g);
-      break;
-    case QCUR_F32:
-      g.ktiles_per_split = (int)((g.K + 15) / 16);
-      hipLaunchKernelGGL((k_qgemm<QCUR_F32, EPI_MERGE, 64, 64>), grid, dim3(NT), 0, c.stream, g);
-      break;
-    default:
-      g.ktiles_per_split = (int)((g.K + 31) / 32);
-      hipLaunchKernelGGL((k_qgemm<QCUR_BF16, EPI_MERGE, 64, 64>), grid, dim3(NT), 0, c.stream, g);
-  }
+  launch_fused<EPI_MERGE>(c, g, compute, resid_tile(g.M, g.N, compute));
   return hipGetLastError();
 }
 
