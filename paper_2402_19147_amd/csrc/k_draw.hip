@@ -183,11 +183,14 @@ __device__ void draw_body(const double* __restrict__ probs, int64_t n, int64_t c
       if ((t & 63) == 0) uvec = splitmix64_nth(seed, base + (uint64_t)(t + lane));
       const uint64_t u = readlane_u64(uvec, (int)(t & 63));
       uint64_t tau = __umul64hi(u, T);
-      const int sb = nsb > 1 ? pick(l2p, tau) : 0;
+      int sb = 0;
       uint64_t v1 = l1p[0];
+      if (nsb > 1) {  // more than one superblock (n > 4096)
+        sb = pick(l2p, tau);
 #pragma unroll
-      for (int m = 1; m < NB1; ++m)
-        if (sb == m) v1 = l1p[m];
+        for (int m = 1; m < NB1; ++m)
+          if (sb == m) v1 = l1p[m];
+      }
       const int eb = pick(v1, tau);
       const int64_t b = (int64_t)sb * 64 + eb;
       const uint64_t pe = wl[b * 64 + lane];
