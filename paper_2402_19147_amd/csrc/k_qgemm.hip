@@ -342,15 +342,18 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
       }
     }
   };
-  auto kvec_store = [&](In (*dst)[BK + T::PAD], int BX, const u32x4* in, bool conj, int plane_stride_rows) {
+  // okbits: bit r clear zeroes vector r (a clamped load past K)
+  auto kvec_store = [&](In (*dst)[BK + T::PAD], int BX, const u32x4* in, bool conj, int plane_stride_rows,
+                        uint32_t okbits) {
 #pragma unroll
     for (int r = 0; r < NV; ++r) {
       const int v = tid + NT * r;
       if (v >= BX * BK / 8) break;
       const int x = v / (BK / 8), k = (v % (BK / 8)) * 8;
+      const bool ok = (okbits >> r) & 1u;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        u32x4 w = in[4 * r + q];
+        u32x4 w = ok ? in[4 * r + q] : (u32x4){0, 0, 0, 0};
         if (conj && q > 0) w ^= (u32x4){SIGN2, SIGN2, SIGN2, SIGN2};
         const int row = q * plane_stride_rows + x;
         *(u32x4*)&dst[row][bf16_chunk(row, k / 8)] = w;
@@ -391,7 +394,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
       }
     }
   };
-  auto xblk_store = [&](In (*dst)[BK + T::PAD], int BX, const u32x4* in, bool conj, int plane_stride_rows) {
+  // okbits: bit 4n + r clear zeroes row r of block n (a clamped load past K)
+  auto xblk_store = [&](In (*dst)[BK + T::PAD], int BX, const u32x4* in, bool conj, int plane_stride_rows,
+                        uint32_t okbits) {
     const int xbl = BX / 8;
     const uint32_t flip = (conj && wave > 0) ? SIGN2 : 0u;
 #pragma unroll
@@ -401,7 +406,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
     const int k0 = (blk % (BK / 4)) * 4, x0 = (blk / (BK / 4)) * 8;
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
-      const uint32_t r0 = in[4 * n][d], r1 = in[4 * n + 1][d], r2 = in[4 * n + 2][d], r3 = in[4 * n + 3][d];
+      const uint32_t r0 = ((okbits >> (4 * n)) & 1u) ? in[4 * n][d] : 0u;
+      const uint32_t r1 = ((okbits >> (4 * n + 1)) & 1u) ? in[4 * n + 1][d] : 0u;
+      const uint32_t r2 = ((okbits >> (4 * n + 2)) & 1u) ? in[4 * n + 2][d] : 0u;
+      const uint32_t r3 = ((okbits >> (4 * n + 3)) & 1u) ? in[4 * n + 3][d] : 0u;
       // element 2d (low halves) and 2d+1 (high halves) of the four k rows
       const uint32_t lo0 = ((r0 & 0xFFFFu) | (r1 << 16)) ^ flip, hi0 = ((r2 & 0xFFFFu) | (r3 << 16)) ^ flip;
       const uint32_t lo1 = ((r0 >> 16) | (r1 & 0xFFFF0000u)) ^ flip, hi1 = ((r2 >> 16) | (r3 & 0xFFFF0000u)) ^ flip;
@@ -427,120 +435,177 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
       else xblk_load(Bg, g.ldb, g.psb, bn, N, BN, k0, K, vb);
     }
   };
-  auto vec_store = [&](int st) {
-    if constexpr (DT == QCUR_BF16) {
-      if (g.opA == QCUR_OP_N) kvec_store(sm.a[st][0], BM, va, false, BM);
-      else xblk_store(sm.a[st][0], BM, va, true, BM);
-      if (g.opB == QCUR_OP_H) kvec_store(sm.b[st][0], BN, vb, true, BN);
-      else xblk_store(sm.b[st][0], BN, vb, false, BN);
+  // Interior tiles of aligned operands (with K a multiple of 8 when an
+  // operand is contiguous in k): every vector load is unconditional, from a
+  // clamped in-range address when its k lies past K, and such data is
+  // zeroed at the LDS store.  With no branch around a load its value stays
+  // in the register it was loaded into, so the wait for it falls at the LDS
+  // store one K step later instead of right after the load (a load path
+  // that merges with the element path needs a register copy, hence an
+  // immediate wait that exposes the whole load latency every step).
+  uint32_t oka = ~0u, okb = ~0u;
+  auto kvec_load_fast = [&](const uint16_t* __restrict__ Xg, int64_t ld, int64_t ps, int64_t x0, int BX,
+                            int64_t kbase, int64_t K, u32x4* out, uint32_t& okbits) {
+    const int nvec = BX * BK / 8;
+    okbits = 0;
+#pragma unroll
+    for (int r = 0; r < NV; ++r) {
+      const int v = (tid + NT * r) % nvec;  // lanes past nvec repeat a load and store nothing
+      const int x = v / (BK / 8), k = (v % (BK / 8)) * 8;
+      const int64_t gk = kbase + k;
+      const bool ok = gk < K;
+      const int64_t off = (x0 + x) * ld + (ok ? gk : 0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) out[4 * r + q] = *(const u32x4*)(Xg + off + q * ps);
+      okbits |= (ok ? 1u : 0u) << r;
     }
   };
-  constexpr bool use_vec = DT == QCUR_BF16;
+  auto xblk_load_fast = [&](const uint16_t* __restrict__ Xg, int64_t ld, int64_t ps, int64_t xbase, int BX,
+                            int64_t kbase, int64_t K, u32x4* out, uint32_t& okbits) {
+    const int nblk = (BK / 4) * (BX / 8);
+    const uint16_t* base = Xg + wave * ps;
+    okbits = 0;
+#pragma unroll
+    for (int n = 0; n < NV; ++n) {
+      const int blk = (lane + 64 * n) % nblk;  // lanes past nblk repeat a load and store nothing
+      const int k0 = (blk % (BK / 4)) * 4, x0 = (blk / (BK / 4)) * 8;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gk = kbase + k0 + r;
+        const bool ok = gk < K;
+        out[4 * n + r] = *(const u32x4*)(base + (ok ? gk : 0) * ld + xbase + x0);
+        okbits |= (ok ? 1u : 0u) << (4 * n + r);
+      }
+    }
+  };
+  auto fast_load = [&](int64_t kt) {
+    if constexpr (DT == QCUR_BF16) {
+      const int64_t k0 = kt * BK;
+      if (g.opA == QCUR_OP_N) kvec_load_fast(Ag, g.lda, g.psa, bm, BM, k0, K, va, oka);
+      else xblk_load_fast(Ag, g.lda, g.psa, bm, BM, k0, K, va, oka);
+      if (g.opB == QCUR_OP_H) kvec_load_fast(Bg, g.ldb, g.psb, bn, BN, k0, K, vb, okb);
+      else xblk_load_fast(Bg, g.ldb, g.psb, bn, BN, k0, K, vb, okb);
+    }
+  };
+  auto vec_store = [&](int st) {
+    if constexpr (DT == QCUR_BF16) {
+      if (g.opA == QCUR_OP_N) kvec_store(sm.a[st][0], BM, va, false, BM, oka);
+      else xblk_store(sm.a[st][0], BM, va, true, BM, oka);
+      if (g.opB == QCUR_OP_H) kvec_store(sm.b[st][0], BN, vb, true, BN, okb);
+      else xblk_store(sm.b[st][0], BN, vb, false, BN, okb);
+    }
+  };
 
   // Pipeline: while the MFMAs read stage st, the slice kt+1 (in registers
   // since the previous step) goes to stage st^1 and slice kt+2 is fetched;
   // one barrier per K step.
-  if (kt0 < kt1) {
-    if constexpr (use_vec) vec_load(kt0); else load_tiles(kt0);
-    if constexpr (use_vec) vec_store(0); else store_tiles(0);
-    if (kt0 + 1 < kt1) {
-      if constexpr (use_vec) vec_load(kt0 + 1); else load_tiles(kt0 + 1);
-    }
-  }
-  __syncthreads();
-  for (int64_t kt = kt0; kt < kt1; ++kt) {
-    const int st = (int)((kt - kt0) & 1);
-    if (kt + 1 < kt1) {
-      if constexpr (use_vec) vec_store(st ^ 1); else store_tiles(st ^ 1);
-      if (kt + 2 < kt1) {
-        if constexpr (use_vec) vec_load(kt + 2); else load_tiles(kt + 2);
-      }
-    }
-#pragma unroll
-    for (int kk = 0; kk < BK / T::KM; ++kk) {
-      // one quaternion multiply-accumulate of the fragments: sixteen MFMAs
-      auto qmac = [&](const Frag (&a)[4][XB], const Frag (&na)[4][XB], const Frag (&b)[4][YB]) {
-#pragma unroll
-        for (int x = 0; x < XB; ++x)
-#pragma unroll
-          for (int y = 0; y < YB; ++y) {
-            // plane 0: A0B0 - A1B1 - A2B2 - A3B3
-            acc[0][x][y] = T::mfma(a[0][x], b[0][y], acc[0][x][y]);
-            acc[0][x][y] = T::mfma(na[1][x], b[1][y], acc[0][x][y]);
-            acc[0][x][y] = T::mfma(na[2][x], b[2][y], acc[0][x][y]);
-            acc[0][x][y] = T::mfma(na[3][x], b[3][y], acc[0][x][y]);
-            // plane 1: A1B0 + A0B1 - A3B2 + A2B3
-            acc[1][x][y] = T::mfma(a[1][x], b[0][y], acc[1][x][y]);
-            acc[1][x][y] = T::mfma(a[0][x], b[1][y], acc[1][x][y]);
-            acc[1][x][y] = T::mfma(na[3][x], b[2][y], acc[1][x][y]);
-            acc[1][x][y] = T::mfma(a[2][x], b[3][y], acc[1][x][y]);
-            // plane 2: A2B0 + A3B1 + A0B2 - A1B3
-            acc[2][x][y] = T::mfma(a[2][x], b[0][y], acc[2][x][y]);
-            acc[2][x][y] = T::mfma(a[3][x], b[1][y], acc[2][x][y]);
-            acc[2][x][y] = T::mfma(a[0][x], b[2][y], acc[2][x][y]);
-            acc[2][x][y] = T::mfma(na[1][x], b[3][y], acc[2][x][y]);
-            // plane 3: A3B0 - A2B1 + A1B2 + A0B3
-            acc[3][x][y] = T::mfma(a[3][x], b[0][y], acc[3][x][y]);
-            acc[3][x][y] = T::mfma(na[2][x], b[1][y], acc[3][x][y]);
-            acc[3][x][y] = T::mfma(a[1][x], b[2][y], acc[3][x][y]);
-            acc[3][x][y] = T::mfma(a[0][x], b[3][y], acc[3][x][y]);
-          }
-      };
-      if constexpr (DT == QCUR_BF16X3) {
-        // hi.hi + hi.lo + lo.hi, the small terms first
-        Frag ah[4][XB], nah[4][XB], al[4][XB], nal[4][XB], bh[4][YB], bl[4][YB];
-#pragma unroll
-        for (int x = 0; x < XB; ++x) {
-          const int ii = wm + x * 16 + (lane & 15);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            ah[q][x] = *(const Frag*)&sm.a[st][0][q][ii][(lane >> 4) * 8];
-            al[q][x] = *(const Frag*)&sm.a[st][1][q][ii][(lane >> 4) * 8];
-          }
-#pragma unroll
-          for (int q = 1; q < 4; ++q) {
-            nah[q][x] = T::neg(ah[q][x]);
-            nal[q][x] = T::neg(al[q][x]);
-          }
-        }
-#pragma unroll
-        for (int y = 0; y < YB; ++y) {
-          const int jj = wn + y * 16 + (lane & 15);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            bh[q][y] = *(const Frag*)&sm.b[st][0][q][jj][(lane >> 4) * 8];
-            bl[q][y] = *(const Frag*)&sm.b[st][1][q][jj][(lane >> 4) * 8];
-          }
-        }
-        qmac(al, nal, bh);
-        qmac(ah, nah, bl);
-        qmac(ah, nah, bh);
-      } else {
-        Frag a[4][XB], na[4][XB], b[4][YB];
-#pragma unroll
-        for (int x = 0; x < XB; ++x) {
-          const int ii = wm + x * 16 + (lane & 15);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            if constexpr (DT == QCUR_BF16) a[q][x] = *(const Frag*)&sm.a[st][q][ii][bf16_chunk(ii, lane >> 4)];
-            else a[q][x] = sm.a[st][q][ii][kk * 4 + (lane >> 4)];
-          }
-#pragma unroll
-          for (int q = 1; q < 4; ++q) na[q][x] = T::neg(a[q][x]);
-        }
-#pragma unroll
-        for (int y = 0; y < YB; ++y) {
-          const int jj = wn + y * 16 + (lane & 15);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            if constexpr (DT == QCUR_BF16) b[q][y] = *(const Frag*)&sm.b[st][q][jj][bf16_chunk(jj, lane >> 4)];
-            else b[q][y] = sm.b[st][q][jj][kk * 4 + (lane >> 4)];
-          }
-        }
-        qmac(a, na, b);
-      }
+  auto run = [&](auto&& load, auto&& store) {
+    if (kt0 < kt1) {
+      load(kt0);
+      store(0);
+      if (kt0 + 1 < kt1) load(kt0 + 1);
     }
     __syncthreads();
+    for (int64_t kt = kt0; kt < kt1; ++kt) {
+      const int st = (int)((kt - kt0) & 1);
+      if (kt + 1 < kt1) {
+        store(st ^ 1);
+        if (kt + 2 < kt1) load(kt + 2);
+      }
+#pragma unroll
+      for (int kk = 0; kk < BK / T::KM; ++kk) {
+        // one quaternion multiply-accumulate of the fragments: sixteen MFMAs
+        auto qmac = [&](const Frag (&a)[4][XB], const Frag (&na)[4][XB], const Frag (&b)[4][YB]) {
+#pragma unroll
+          for (int x = 0; x < XB; ++x)
+#pragma unroll
+            for (int y = 0; y < YB; ++y) {
+              // plane 0: A0B0 - A1B1 - A2B2 - A3B3
+              acc[0][x][y] = T::mfma(a[0][x], b[0][y], acc[0][x][y]);
+              acc[0][x][y] = T::mfma(na[1][x], b[1][y], acc[0][x][y]);
+              acc[0][x][y] = T::mfma(na[2][x], b[2][y], acc[0][x][y]);
+              acc[0][x][y] = T::mfma(na[3][x], b[3][y], acc[0][x][y]);
+              // plane 1: A1B0 + A0B1 - A3B2 + A2B3
+              acc[1][x][y] = T::mfma(a[1][x], b[0][y], acc[1][x][y]);
+              acc[1][x][y] = T::mfma(a[0][x], b[1][y], acc[1][x][y]);
+              acc[1][x][y] = T::mfma(na[3][x], b[2][y], acc[1][x][y]);
+              acc[1][x][y] = T::mfma(a[2][x], b[3][y], acc[1][x][y]);
+              // plane 2: A2B0 + A3B1 + A0B2 - A1B3
+              acc[2][x][y] = T::mfma(a[2][x], b[0][y], acc[2][x][y]);
+              acc[2][x][y] = T::mfma(a[3][x], b[1][y], acc[2][x][y]);
+              acc[2][x][y] = T::mfma(a[0][x], b[2][y], acc[2][x][y]);
+              acc[2][x][y] = T::mfma(na[1][x], b[3][y], acc[2][x][y]);
+              // plane 3: A3B0 - A2B1 + A1B2 + A0B3
+              acc[3][x][y] = T::mfma(a[3][x], b[0][y], acc[3][x][y]);
+              acc[3][x][y] = T::mfma(na[2][x], b[1][y], acc[3][x][y]);
+              acc[3][x][y] = T::mfma(a[1][x], b[2][y], acc[3][x][y]);
+              acc[3][x][y] = T::mfma(a[0][x], b[3][y], acc[3][x][y]);
+            }
+        };
+        if constexpr (DT == QCUR_BF16X3) {
+          // hi.hi + hi.lo + lo.hi, the small terms first
+          Frag ah[4][XB], nah[4][XB], al[4][XB], nal[4][XB], bh[4][YB], bl[4][YB];
+#pragma unroll
+          for (int x = 0; x < XB; ++x) {
+            const int ii = wm + x * 16 + (lane & 15);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              ah[q][x] = *(const Frag*)&sm.a[st][0][q][ii][(lane >> 4) * 8];
+              al[q][x] = *(const Frag*)&sm.a[st][1][q][ii][(lane >> 4) * 8];
+            }
+#pragma unroll
+            for (int q = 1; q < 4; ++q) {
+              nah[q][x] = T::neg(ah[q][x]);
+              nal[q][x] = T::neg(al[q][x]);
+            }
+          }
+#pragma unroll
+          for (int y = 0; y < YB; ++y) {
+            const int jj = wn + y * 16 + (lane & 15);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              bh[q][y] = *(const Frag*)&sm.b[st][0][q][jj][(lane >> 4) * 8];
+              bl[q][y] = *(const Frag*)&sm.b[st][1][q][jj][(lane >> 4) * 8];
+            }
+          }
+          qmac(al, nal, bh);
+          qmac(ah, nah, bl);
+          qmac(ah, nah, bh);
+        } else {
+          Frag a[4][XB], na[4][XB], b[4][YB];
+#pragma unroll
+          for (int x = 0; x < XB; ++x) {
+            const int ii = wm + x * 16 + (lane & 15);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              if constexpr (DT == QCUR_BF16) a[q][x] = *(const Frag*)&sm.a[st][q][ii][bf16_chunk(ii, lane >> 4)];
+              else a[q][x] = sm.a[st][q][ii][kk * 4 + (lane >> 4)];
+            }
+#pragma unroll
+            for (int q = 1; q < 4; ++q) na[q][x] = T::neg(a[q][x]);
+          }
+#pragma unroll
+          for (int y = 0; y < YB; ++y) {
+            const int jj = wn + y * 16 + (lane & 15);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              if constexpr (DT == QCUR_BF16) b[q][y] = *(const Frag*)&sm.b[st][q][jj][bf16_chunk(jj, lane >> 4)];
+              else b[q][y] = sm.b[st][q][jj][kk * 4 + (lane >> 4)];
+            }
+          }
+          qmac(a, na, b);
+        }
+      }
+    __syncthreads();
+    }
+  };
+  if constexpr (DT == QCUR_BF16) {
+    const bool kvec_op = g.opA == QCUR_OP_N || g.opB == QCUR_OP_H;
+    const bool fast = aligned && bm + BM <= M && bn + BN <= N && (!kvec_op || (K & 7) == 0);
+    if (fast) run(fast_load, vec_store);
+    else run(vec_load, vec_store);
+  } else {
+    run(load_tiles, store_tiles);
   }
 
   // Epilogue.  MFMA 16x16 output: lane holds column lane%16 and four rows

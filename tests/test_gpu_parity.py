@@ -78,6 +78,20 @@ def test_gemm_small_integers_bit_exact(M, K, Nn, compute, opA, opB):
     assert np.array_equal(N(D), ref)
 
 
+@pytest.mark.parametrize("M,K,Nn", [(896, 72, 960), (900, 64, 963), (896, 70, 960)])
+@pytest.mark.parametrize("opA,opB", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_gemm_bf16_64_tiles_bit_exact(M, K, Nn, opA, opB):
+    # enough 64-tiles to select them: interior tiles take the unconditional
+    # vector loads (K = 72: a last K slice of 8 valid columns; K = 70: only
+    # the x-contiguous operands qualify), ragged M and N the guarded loads
+    rng = np.random.default_rng(M + K + Nn + 2 * opA + opB)
+    A = workloads.small_int_quat(M, K, rng, 4) if opA == 0 else workloads.small_int_quat(K, M, rng, 4)
+    B = workloads.small_int_quat(K, Nn, rng, 4) if opB == 0 else workloads.small_int_quat(Nn, K, rng, 4)
+    ref = qmul(A if opA == 0 else qH(A), B if opB == 0 else qH(B))
+    D = Q.gemm(T(A, torch.bfloat16), T(B, torch.bfloat16), opA=opA, opB=opB, compute=Q.BF16)
+    assert np.array_equal(N(D), ref)
+
+
 @pytest.mark.parametrize("compute,tol", [(Q.F64, 1e-13), (Q.F32, 1e-5), (Q.BF16, 2e-2), (Q.BF16X3, 1e-4)])
 def test_gemm_gaussian_alpha_beta(compute, tol):
     rng = np.random.default_rng(7)
