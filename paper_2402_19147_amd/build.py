@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libqcur.so")
-SOURCES = ["api.cpp", "k_elem.hip", "k_draw.hip", "k_qgemm.hip", "k_pinv.hip", "k_chol.hip", "k_batch.hip"]
+SOURCES = ["api.cpp", "k_elem.hip", "k_draw.hip", "k_qgemm.hip", "k_pinv.hip", "k_chol.hip", "k_batch.hip", "k_thin.hip"]
 PROBE_LIB = os.path.join(HERE, "libqcur_probe.so")
 PROBE_SOURCES = ["probe_ceiling.hip"]
 ARCH = os.environ.get("QCUR_OFFLOAD_ARCH", "gfx950")
@@ -34,11 +34,11 @@ def _hipcc() -> str:
     return "hipcc"
 
 
-# The MFMA loop of the probe keeps its accumulators in ordinary VGPRs; with
-# the default form the compiler copies them between VGPRs and AGPRs around
-# every round of MFMAs, which would make the measured ceiling a measure of
-# those copies.
-EXTRA = {"probe_ceiling.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+# The MFMA loops of the probe and of the thin products keep their
+# accumulators in ordinary VGPRs; with the default form the compiler copies
+# them between VGPRs and AGPRs around every round of MFMAs.
+EXTRA = {"probe_ceiling.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+         "k_thin.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def _compile(src: str) -> str:

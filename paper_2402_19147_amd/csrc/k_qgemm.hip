@@ -864,6 +864,11 @@ hipError_t launch_gemm_batched(const Ctx& c, int opA, int opB, double alpha, QVi
   if (g.K == 0) {  // D = beta * D
     return launch_axpby(c, 0.0, D, beta, D);
   }
+  // thin FP64 / FP32 products with a long K (Gram matrices, cores): the
+  // fragment-streaming kernel
+  if (bs.tile == 0 && bs.splits == 0 && thin_hn_applies(compute, opA, opB, g.M, g.N, g.K, g.tri, bs.M || bs.N || bs.K))
+    return launch_thin_hn(c, compute, alpha, A, B, beta, D, g.K, g.batch, bs.sA, bs.sB, bs.sD,
+                          (g.tri & TRI_LOWER_OUT) != 0, ws, ws_bytes);
   switch (compute) {
     case QCUR_F64: return gemm_dt<QCUR_F64>(c, g, ws, ws_bytes);
     case QCUR_F32: return gemm_dt<QCUR_F32>(c, g, ws, ws_bytes);

@@ -107,6 +107,15 @@ struct BatchSpec {
 // of D is wanted; tiles wholly above the diagonal are not written.
 enum { TRI_LOWER_OUT = 1, TRI_A_LOWER = 2, TRI_A_UPPER = 4, TRI_B_LOWER = 8, TRI_B_UPPER = 16 };
 size_t gemm_workspace(int64_t M, int64_t N, int64_t K, int compute, int batch = 1);
+// Thin FP64 / FP32 products D = alpha A^H B + beta D (A: K x M, B: K x N,
+// both K-major; M, N <= 256, K >= 4 max(M, N), equal sizes over a batch):
+// one wave per 16 x 16 block of D streaming its fragments from global
+// memory.  Needs no more workspace than gemm_workspace gives the tiled plan
+// (fewer K splits); lower_only computes the blocks on and below the diagonal.
+bool thin_hn_applies(int compute, int opA, int opB, int64_t M, int64_t N, int64_t K, int tri, bool per_problem_dims);
+hipError_t launch_thin_hn(const Ctx& c, int compute, double alpha, QView A, QView B, double beta, QView D,
+                          int64_t K, int batch, int64_t sA, int64_t sB, int64_t sD, bool lower_only, void* ws,
+                          size_t ws_bytes);
 // Workspace for any plan with at most max_splits K slices.
 size_t gemm_workspace_splits(int64_t M, int64_t N, int compute, int batch, int max_splits);
 hipError_t launch_gemm(const Ctx& c, int opA, int opB, double alpha, QView A, QView B, double beta,

@@ -92,6 +92,26 @@ def test_gemm_bf16_64_tiles_bit_exact(M, K, Nn, opA, opB):
     assert np.array_equal(N(D), ref)
 
 
+@pytest.mark.parametrize("M,K,Nn", [(200, 1024, 200), (37, 301, 45), (256, 1024, 256), (1, 64, 1), (16, 4099, 16),
+                                    (200, 800, 13)])
+@pytest.mark.parametrize("compute,tol", [(Q.F64, 1e-13), (Q.F32, 1e-5)])
+def test_gemm_thin_hn(M, K, Nn, compute, tol):
+    # A^H B with a long K and a small output: the fragment-streaming kernel
+    # (ragged 16-blocks, K not a multiple of 4, several K splits)
+    rng = np.random.default_rng(M + K + Nn)
+    dt = torch.float64 if compute == Q.F64 else torch.float32
+    A = N(T(rng.standard_normal((4, K, M)), dt))
+    B = N(T(rng.standard_normal((4, K, Nn)), dt))
+    D0 = N(T(rng.standard_normal((4, M, Nn)), dt))
+    Dt = T(D0, dt)
+    Q.gemm(T(A, dt), T(B, dt), opA=1, opB=0, alpha=0.75, beta=-1.5, D=Dt, compute=compute)
+    ref = 0.75 * qmul(qH(A), B) - 1.5 * D0
+    assert rel(N(Dt), ref) < tol
+    Ai = workloads.small_int_quat(K, M, rng, 2)
+    Bi = workloads.small_int_quat(K, Nn, rng, 2)
+    assert np.array_equal(N(Q.gemm(T(Ai, dt), T(Bi, dt), opA=1, opB=0, compute=compute)), qmul(qH(Ai), Bi))
+
+
 @pytest.mark.parametrize("compute,tol", [(Q.F64, 1e-13), (Q.F32, 1e-5), (Q.BF16, 2e-2), (Q.BF16X3, 1e-4)])
 def test_gemm_gaussian_alpha_beta(compute, tol):
     rng = np.random.default_rng(7)
