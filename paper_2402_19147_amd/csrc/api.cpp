@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -170,11 +171,20 @@ PinvWs pinv_carve(Bump& b, int64_t p, int64_t q) {
 }
 
 // CholeskyQR path buffers for a group of nb matrices padded to pp x qq.
+// The certificate inputs and verdicts of a group, one block of device
+// memory laid out like the start of the pinned HostVerdict so that a single
+// copy reads them back.
+struct DevVerdict {
+  int ok[MAXB];
+  double nrm[4 * MAXB];
+};
+
 struct GroupWs {
   int nb;
   int64_t pp, qq;
   double *Z, *Q1, *Q, *G, *L, *P1, *P2, *P, *S, *part, *norms;
   int *fail, *ok;
+  void* verdict;  // DevVerdict holding ok and norms
   void* gws;
   size_t gws_bytes;
 };
@@ -195,9 +205,11 @@ GroupWs group_carve(Bump& b, int nb, int64_t pp, int64_t qq) {
   w.P = (double*)b.take(gb);
   w.S = (double*)b.take((size_t)nb * 4 * CHOL_BLOCK * qq * 8);
   w.part = (double*)b.take((size_t)nb * 256 * 8);
-  w.norms = (double*)b.take((size_t)nb * 4 * 8);
+  char* vb = (char*)b.take(sizeof(DevVerdict));  // nb <= MAXB
+  w.verdict = vb;
+  w.norms = vb ? (double*)(vb + offsetof(DevVerdict, nrm)) : nullptr;
+  w.ok = vb ? (int*)(vb + offsetof(DevVerdict, ok)) : nullptr;
   w.fail = (int*)b.take((size_t)nb * 4);
-  w.ok = (int*)b.take((size_t)nb * 4);
   w.gws_bytes = std::max({gemm_workspace(qq, qq, pp, QCUR_F64, nb), gemm_workspace(pp, qq, qq, QCUR_F64, nb),
                           gemm_workspace(qq, qq, qq, QCUR_F64, nb), gemm_workspace(qq, pp, qq, QCUR_F64),
                           gemm_workspace(pp, qq, qq, QCUR_F64)});
@@ -282,6 +294,10 @@ struct HostVerdict {
   double nrm[4 * MAXB];
   double aux[4];  // other small read-backs (the completion's stopping sums)
 };
+static_assert(offsetof(HostVerdict, ok) == offsetof(DevVerdict, ok) &&
+                  offsetof(HostVerdict, nrm) == offsetof(DevVerdict, nrm) &&
+                  sizeof(DevVerdict) <= offsetof(HostVerdict, aux),
+              "one copy moves a DevVerdict into the head of a HostVerdict, short of aux");
 
 // A verdict left pending by pinv_fast_group: the decision kernel has run and
 // its result is on its way to pinned host memory (c.done marks its arrival).
@@ -376,9 +392,7 @@ qcur_status pinv_fast_group(const Ctx& c, int nb, const QView* X, double rtol, i
   // to pinned memory and return the fast path's factors without waiting
   auto decide_async = [&](bool adaptive, int fp) -> qcur_status {
     HIPCHK(launch_pinv_decide(c, w.norms, w.fail, rtol, max_rank, nb, qb, rank_out, w.ok));
-    HostVerdict* hv = (HostVerdict*)c.pinned;
-    HIPCHK(hipMemcpyAsync(hv->ok, w.ok, sizeof(int) * nb, hipMemcpyDeviceToHost, c.stream));
-    HIPCHK(hipMemcpyAsync(hv->nrm, w.norms, sizeof(double) * 4 * nb, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipMemcpyAsync(c.pinned, w.verdict, sizeof(DevVerdict), hipMemcpyDeviceToHost, c.stream));
     HIPCHK(hipEventRecord(c.done, c.stream));
     spec->pending = true;
     spec->nb = nb;
