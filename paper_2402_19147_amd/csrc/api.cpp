@@ -344,7 +344,8 @@ qcur_status pinv_fast_group(const Ctx& c, int nb, const QView* X, double rtol, i
   QView Zr[MAXB], Pr[MAXB];
   for (int b = 0; b < nb; ++b) {
     Zr[b] = QView{w.Z + b * zslab, pb[b], qb[b], qq, pp * qq, QCUR_F64};
-    HIPCHK(launch_cast(c, X[b], Zr[b], tall[b] ? CAST_COPY : CAST_H));
+    // the cast also checks the input for non-finite entries
+    HIPCHK(launch_cast(c, X[b], Zr[b], (tall[b] ? CAST_COPY : CAST_H) | CAST_CHECK));
   }
   HIPCHK(launch_sumsq_batch(c, nb, Zr, w.part, w.norms + 0, 4));
   const BatchSpec bz = same_stride(nb, zslab);
@@ -565,8 +566,8 @@ qcur_status pinv_group_qp(const Ctx& c, int nb, const QView* X, double rtol, int
       Pv[b] = QView{gw.P, 0, 0, 1, 1, QCUR_F64};
       continue;
     }
-    HIPCHK(launch_check_finite(c, X[b]));
     if (jacobi_small_fits(pl.pp, pl.qq)) {
+      HIPCHK(launch_check_finite(c, X[b]));  // the CholeskyQR group checks in its cast
       small[ns++] = b;
       continue;
     }
@@ -623,8 +624,8 @@ qcur_status pinv_group(const Ctx& c, int nb, const QView* X, double rtol, int64_
       if (rank_out[b]) HIPCHK(launch_zero(c, (double*)rank_out[b], 1));
       continue;
     }
-    HIPCHK(launch_check_finite(c, X[b]));
     if (jacobi_small_fits(pl.pp, pl.qq)) {
+      HIPCHK(launch_check_finite(c, X[b]));  // the CholeskyQR group checks in its cast
       CHK(pinv_jacobi(c, X[b], rt[b], max_rank, Xp[b], rank_out[b], jw));
       continue;
     }

@@ -241,12 +241,15 @@ hipError_t launch_gather(const Ctx& c, QView A, const int64_t* I, int64_t r, con
 // ---------------------------------------------------------------------------
 // Cast Y = X with optional transpose (mode bit 1) and entrywise quaternion
 // conjugation (mode bit 2): Y[c][j][i] (transposed) or Y[c][i][j] receives
-// sign_c X[c][i][j] with sign_c = -1 for c > 0 when conjugating.
+// sign_c X[c][i][j] with sign_c = -1 for c > 0 when conjugating.  Mode bit 4
+// also checks every element read and raises ST_NUMERIC for one that is not
+// finite (the check a separate pass would make).
 template <typename TI, typename TO>
 __global__ __launch_bounds__(256) void k_cast(const TI* __restrict__ X, int64_t rows, int64_t cols, int64_t xld,
                                               int64_t xps, TO* __restrict__ Y, int64_t yld, int64_t yps,
-                                              int mode) {
+                                              int mode, unsigned* status) {
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  bool bad = false;
   for (int64_t i = blockIdx.y; i < rows; i += gridDim.y) {
   if (j >= cols) continue;
   const int64_t src = i * xld + j;
@@ -254,10 +257,12 @@ __global__ __launch_bounds__(256) void k_cast(const TI* __restrict__ X, int64_t 
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     double v = to_d<TI>(X[src + c * xps]);
+    bad |= !(v - v == 0.0);
     if ((mode & 2) && c > 0) v = -v;
     Y[dst + c * yps] = from_d<TO>(v);
   }
   }
+  if ((mode & 4) && bad) atomicOr(status, ST_NUMERIC);
 }
 
 template <typename TI>
@@ -266,15 +271,15 @@ static void cast_out(const Ctx& c, QView X, QView Y, int mode) {
   switch (Y.dt) {
     case QCUR_F64:
       hipLaunchKernelGGL((k_cast<TI, double>), grid, dim3(256), 0, c.stream, (const TI*)X.p, X.rows, X.cols,
-                         X.ld, X.ps, (double*)Y.p, Y.ld, Y.ps, mode);
+                         X.ld, X.ps, (double*)Y.p, Y.ld, Y.ps, mode, c.status);
       break;
     case QCUR_F32:
       hipLaunchKernelGGL((k_cast<TI, float>), grid, dim3(256), 0, c.stream, (const TI*)X.p, X.rows, X.cols,
-                         X.ld, X.ps, (float*)Y.p, Y.ld, Y.ps, mode);
+                         X.ld, X.ps, (float*)Y.p, Y.ld, Y.ps, mode, c.status);
       break;
     default:
       hipLaunchKernelGGL((k_cast<TI, uint16_t>), grid, dim3(256), 0, c.stream, (const TI*)X.p, X.rows,
-                         X.cols, X.ld, X.ps, (uint16_t*)Y.p, Y.ld, Y.ps, mode);
+                         X.cols, X.ld, X.ps, (uint16_t*)Y.p, Y.ld, Y.ps, mode, c.status);
   }
 }
 

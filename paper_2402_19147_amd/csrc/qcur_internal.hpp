@@ -85,7 +85,8 @@ hipError_t launch_draw_pair(const Ctx& c, const double* p0, int64_t n0, int64_t 
 hipError_t launch_gather(const Ctx& c, QView A, const int64_t* I, int64_t r, const int64_t* J,
                          int64_t cc, const QView* C, const QView* R, const QView* W);
 // mode bit 1: transpose, bit 2: conjugate (quaternion conjugate of every entry)
-enum { CAST_COPY = 0, CAST_T = 1, CAST_CONJ = 2, CAST_H = 3 };
+// CAST_CHECK: also raise ST_NUMERIC in the status word for an element that is not finite
+enum { CAST_COPY = 0, CAST_T = 1, CAST_CONJ = 2, CAST_H = 3, CAST_CHECK = 4 };
 hipError_t launch_cast(const Ctx& c, QView X, QView Y, int mode);
 
 // qGEMM: D = alpha * op(A) op(B) + beta * D.  ws may be NULL (no split-K).

@@ -223,6 +223,22 @@ def test_probs_zero_matrix_raises_numeric():
     assert e.value.status == 6
 
 
+@pytest.mark.parametrize("compute", [Q.F64, Q.F32])
+def test_approx_nonfinite_factor_raises_numeric(compute):
+    # C large enough for the CholeskyQR group, whose FP64 cast checks every
+    # element; one NaN must reach the status word
+    rng = np.random.default_rng(31)
+    A = rng.standard_normal((4, 300, 260))
+    C = np.ascontiguousarray(A[:, :, :40])
+    R = np.ascontiguousarray(A[:, :40, :])
+    C[2, 17, 5] = np.nan
+    dt = torch.float64 if compute == Q.F64 else torch.float32
+    Q.approx(T(A, dt), T(C, dt), T(R, dt), None, core=Q.CORE_CAR, compute=compute)
+    with pytest.raises(Q.QcurError) as e:
+        Q.sync_status()
+    assert e.value.status == 6
+
+
 @pytest.mark.parametrize("out_dt", [torch.float64, torch.float32, torch.bfloat16])
 def test_gather_bit_exact(out_dt):
     rng = np.random.default_rng(9)
