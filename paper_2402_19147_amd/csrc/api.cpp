@@ -342,11 +342,12 @@ qcur_status pinv_fast_group(const Ctx& c, int nb, const QView* X, double rtol, i
   HIPCHK(launch_zero_i32(c, w.fail, nb));
   if (padded) HIPCHK(launch_zero(c, w.Z, nb * zslab));
   QView Zr[MAXB], Pr[MAXB];
+  int cmode[MAXB];
   for (int b = 0; b < nb; ++b) {
     Zr[b] = QView{w.Z + b * zslab, pb[b], qb[b], qq, pp * qq, QCUR_F64};
-    // the cast also checks the input for non-finite entries
-    HIPCHK(launch_cast(c, X[b], Zr[b], (tall[b] ? CAST_COPY : CAST_H) | CAST_CHECK));
+    cmode[b] = (tall[b] ? CAST_COPY : CAST_H) | CAST_CHECK;  // also checks for non-finite entries
   }
+  HIPCHK(launch_cast_set(c, nb, X, Zr, cmode));
   HIPCHK(launch_sumsq_batch(c, nb, Zr, w.part, w.norms + 0, 4));
   const BatchSpec bz = same_stride(nb, zslab);
   BatchSpec bzg;  // Gram matrices: lower triangle only (all the Cholesky reads)
@@ -743,8 +744,9 @@ qcur_status approx_run(const Ctx& c, const ApproxArgs& a, int64_t m, int64_t n, 
         // buffers carved above)
         const QView Qc2{QcB.p, Qc.rows, Qc.cols, Qc.cols, Qc.rows * Qc.cols, idt};
         const QView Qr2{QrB.p, Qr.rows, Qr.cols, Qr.cols, Qr.rows * Qr.cols, idt};
-        HIPCHK(launch_cast(c, Qc, Qc2, CAST_COPY));
-        HIPCHK(launch_cast(c, Qr, Qr2, CAST_COPY));
+        const QView qs[2] = {Qc, Qr}, qd[2] = {Qc2, Qr2};
+        const int cm[2] = {CAST_COPY, CAST_COPY};
+        HIPCHK(launch_cast_set(c, 2, qs, qd, cm));
         Qc = Qc2;
         Qr = Qr2;
       }
@@ -1545,13 +1547,13 @@ qcur_status complete_run(const Ctx& c, const CompleteArgs& a, Bump& b, bool coun
     QView xs[2] = {C, R};
     int64_t* ro[2] = {ranks, ranks + 1};
     auto products = [&]() -> qcur_status {
-      HIPCHK(launch_cast(c, Qv[0], Qc, CAST_COPY));
-      HIPCHK(launch_cast(c, Qv[1], Qr, CAST_COPY));
+      // the factors and, when needed, the iterate in the product dtype:
+      // one launch when the dtypes agree
+      const QView cs[3] = {Qv[0], Qv[1], cur}, cd[3] = {Qc, Qr, Xx};
+      const int cm[3] = {CAST_COPY, CAST_COPY, CAST_COPY};
+      HIPCHK(launch_cast_set(c, Xx.p ? 3 : 2, cs, cd, cm));
       QView Xin = cur;
-      if (Xx.p) {
-        HIPCHK(launch_cast(c, cur, Xx, CAST_COPY));
-        Xin = Xx;
-      }
+      if (Xx.p) Xin = Xx;
       // M = Q_C^H (X^t Q_R);  B1 = Q_C M;  X^{t+1} = P_Omega(Y) + P_Omega^c(B1 Q_R^H)
       HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Xin, Qr, 0.0, T, a.compute, gws, gwb));
       if (Tx.p != T.p) HIPCHK(launch_cast(c, T, Tx, CAST_COPY));

@@ -283,6 +283,88 @@ static void cast_out(const Ctx& c, QView X, QView Y, int mode) {
   }
 }
 
+// Up to MAXB casts with one input and one output dtype in one launch (grid z
+// = the view), each as k_cast above.
+struct CastSet {
+  const void* X[MAXB];
+  void* Y[MAXB];
+  int64_t rows[MAXB], cols[MAXB], xld[MAXB], xps[MAXB], yld[MAXB], yps[MAXB];
+  int mode[MAXB];
+};
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_cast_set(CastSet s, unsigned* status) {
+  const int v = blockIdx.z;
+  const TI* __restrict__ X = (const TI*)s.X[v];
+  TO* __restrict__ Y = (TO*)s.Y[v];
+  const int64_t rows = s.rows[v], cols = s.cols[v], xld = s.xld[v], xps = s.xps[v], yld = s.yld[v], yps = s.yps[v];
+  const int mode = s.mode[v];
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  bool bad = false;
+  for (int64_t i = blockIdx.y; i < rows; i += gridDim.y) {
+    if (j >= cols) continue;
+    const int64_t src = i * xld + j;
+    const int64_t dst = (mode & 1) ? (j * yld + i) : (i * yld + j);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      double x = to_d<TI>(X[src + c * xps]);
+      bad |= !(x - x == 0.0);
+      if ((mode & 2) && c > 0) x = -x;
+      Y[dst + c * yps] = from_d<TO>(x);
+    }
+  }
+  if ((mode & 4) && bad) atomicOr(status, ST_NUMERIC);
+}
+
+template <typename TI, typename TO>
+static void cast_set_out(const Ctx& c, const CastSet& s, int n, int64_t maxr, int64_t maxc) {
+  const dim3 grid((unsigned)((maxc + 255) / 256), (unsigned)std::min<int64_t>(maxr, 65535), (unsigned)n);
+  hipLaunchKernelGGL((k_cast_set<TI, TO>), grid, dim3(256), 0, c.stream, s, c.status);
+}
+
+template <typename TI>
+static void cast_set_in(const Ctx& c, const CastSet& s, int n, int64_t maxr, int64_t maxc, int odt) {
+  switch (odt) {
+    case QCUR_F64: cast_set_out<TI, double>(c, s, n, maxr, maxc); break;
+    case QCUR_F32: cast_set_out<TI, float>(c, s, n, maxr, maxc); break;
+    default: cast_set_out<TI, uint16_t>(c, s, n, maxr, maxc);
+  }
+}
+
+hipError_t launch_cast_set(const Ctx& c, int n, const QView* X, const QView* Y, const int* modes) {
+  bool same = n >= 1 && n <= MAXB;
+  for (int v = 1; v < n && same; ++v) same = X[v].dt == X[0].dt && Y[v].dt == Y[0].dt;
+  if (!same) {  // one launch per view
+    for (int v = 0; v < n; ++v) {
+      const hipError_t e = launch_cast(c, X[v], Y[v], modes[v]);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  CastSet s = {};
+  int64_t maxr = 0, maxc = 0;
+  for (int v = 0; v < n; ++v) {
+    s.X[v] = X[v].p;
+    s.Y[v] = Y[v].p;
+    s.rows[v] = X[v].rows;
+    s.cols[v] = X[v].cols;
+    s.xld[v] = X[v].ld;
+    s.xps[v] = X[v].ps;
+    s.yld[v] = Y[v].ld;
+    s.yps[v] = Y[v].ps;
+    s.mode[v] = modes[v];
+    maxr = std::max(maxr, X[v].rows);
+    maxc = std::max(maxc, X[v].cols);
+  }
+  if (maxr == 0 || maxc == 0) return hipSuccess;
+  switch (X[0].dt) {
+    case QCUR_F64: cast_set_in<double>(c, s, n, maxr, maxc, Y[0].dt); break;
+    case QCUR_F32: cast_set_in<float>(c, s, n, maxr, maxc, Y[0].dt); break;
+    default: cast_set_in<uint16_t>(c, s, n, maxr, maxc, Y[0].dt);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_cast(const Ctx& c, QView X, QView Y, int mode) {
   if (X.rows == 0 || X.cols == 0) return hipSuccess;
   switch (X.dt) {

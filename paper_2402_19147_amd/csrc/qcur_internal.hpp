@@ -88,6 +88,8 @@ hipError_t launch_gather(const Ctx& c, QView A, const int64_t* I, int64_t r, con
 // CAST_CHECK: also raise ST_NUMERIC in the status word for an element that is not finite
 enum { CAST_COPY = 0, CAST_T = 1, CAST_CONJ = 2, CAST_H = 3, CAST_CHECK = 4 };
 hipError_t launch_cast(const Ctx& c, QView X, QView Y, int mode);
+// n <= MAXB casts in one launch when they share the input and the output dtype
+hipError_t launch_cast_set(const Ctx& c, int n, const QView* X, const QView* Y, const int* modes);
 
 // qGEMM: D = alpha * op(A) op(B) + beta * D.  ws may be NULL (no split-K).
 // A batch runs `count` products in one launch: problem b uses the views'
