@@ -230,11 +230,87 @@ static void gather_one(const Ctx& c, QView A, const int64_t* ri, const int64_t* 
   }
 }
 
+// Up to three gathers from one A into outputs of one dtype in a single
+// launch: a flat grid over the output elements of all of them (output v
+// starts at element first[v]), each element as in k_gather.
+struct GatherSet {
+  const int64_t* ridx[3];
+  const int64_t* cidx[3];
+  void* O[3];
+  int64_t om[3], on[3], old[3], ops[3], first[4];
+  int n;
+};
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_gather_set(const TI* __restrict__ A, int64_t am, int64_t an, int64_t ald,
+                                                    int64_t aps, GatherSet g, unsigned* status) {
+  const int64_t total = g.first[g.n];
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    int v = 0;
+    while (v + 1 < g.n && e >= g.first[v + 1]) ++v;
+    const int64_t l = e - g.first[v], s = l / g.on[v], t = l % g.on[v];
+    const int64_t i = g.ridx[v] ? g.ridx[v][s] : s;
+    const int64_t j = g.cidx[v] ? g.cidx[v][t] : t;
+    const bool ok = i >= 0 && i < am && j >= 0 && j < an;
+    if (!ok) atomicOr(status, ST_ARG);
+    const int64_t src = i * ald + j;
+    TO* __restrict__ O = (TO*)g.O[v] + s * g.old[v] + t;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) O[c * g.ops[v]] = ok ? from_d<TO>(to_d<TI>(A[src + c * aps])) : from_d<TO>(0.0);
+  }
+}
+
+template <typename TI, typename TO>
+static void gather_set_out(const Ctx& c, QView A, const GatherSet& g) {
+  const int64_t blocks = std::min<int64_t>((g.first[g.n] + 255) / 256, 65536);
+  hipLaunchKernelGGL((k_gather_set<TI, TO>), dim3((unsigned)blocks), dim3(256), 0, c.stream, (const TI*)A.p, A.rows,
+                     A.cols, A.ld, A.ps, g, c.status);
+}
+
+template <typename TI>
+static void gather_set_in(const Ctx& c, QView A, const GatherSet& g, int odt) {
+  switch (odt) {
+    case QCUR_F64: gather_set_out<TI, double>(c, A, g); break;
+    case QCUR_F32: gather_set_out<TI, float>(c, A, g); break;
+    default: gather_set_out<TI, uint16_t>(c, A, g);
+  }
+}
+
 hipError_t launch_gather(const Ctx& c, QView A, const int64_t* I, int64_t r, const int64_t* J, int64_t cc,
                          const QView* C, const QView* R, const QView* W) {
-  if (C) gather_one(c, A, nullptr, J, *C);
-  if (R) gather_one(c, A, I, nullptr, *R);
-  if (W) gather_one(c, A, I, J, *W);
+  const QView* outs[3] = {C, R, W};
+  const int64_t* ri[3] = {nullptr, I, I};
+  const int64_t* ci[3] = {J, nullptr, J};
+  GatherSet g = {};
+  int odt = -1;
+  bool same = true;
+  for (int k = 0; k < 3; ++k) {
+    const QView* o = outs[k];
+    if (!o || o->rows == 0 || o->cols == 0) continue;
+    if (odt >= 0 && o->dt != odt) same = false;
+    odt = o->dt;
+    g.ridx[g.n] = ri[k];
+    g.cidx[g.n] = ci[k];
+    g.O[g.n] = o->p;
+    g.om[g.n] = o->rows;
+    g.on[g.n] = o->cols;
+    g.old[g.n] = o->ld;
+    g.ops[g.n] = o->ps;
+    g.first[g.n + 1] = g.first[g.n] + o->rows * o->cols;
+    ++g.n;
+  }
+  if (g.n == 0) return hipSuccess;
+  if (!same) {  // outputs of different dtypes: one launch each
+    if (C) gather_one(c, A, nullptr, J, *C);
+    if (R) gather_one(c, A, I, nullptr, *R);
+    if (W) gather_one(c, A, I, J, *W);
+    return hipGetLastError();
+  }
+  switch (A.dt) {
+    case QCUR_F64: gather_set_in<double>(c, A, g, odt); break;
+    case QCUR_F32: gather_set_in<float>(c, A, g, odt); break;
+    default: gather_set_in<uint16_t>(c, A, g, odt);
+  }
   return hipGetLastError();
 }
 
@@ -283,51 +359,51 @@ static void cast_out(const Ctx& c, QView X, QView Y, int mode) {
   }
 }
 
-// Up to MAXB casts with one input and one output dtype in one launch (grid z
-// = the view), each as k_cast above.
+// Up to MAXB casts with one input and one output dtype in one launch: a
+// flat grid over the elements of all inputs (view v starts at element
+// first[v]), each element as in k_cast above.
 struct CastSet {
   const void* X[MAXB];
   void* Y[MAXB];
-  int64_t rows[MAXB], cols[MAXB], xld[MAXB], xps[MAXB], yld[MAXB], yps[MAXB];
+  int64_t cols[MAXB], xld[MAXB], xps[MAXB], yld[MAXB], yps[MAXB], first[MAXB + 1];
   int mode[MAXB];
+  int n;
 };
 
 template <typename TI, typename TO>
 __global__ __launch_bounds__(256) void k_cast_set(CastSet s, unsigned* status) {
-  const int v = blockIdx.z;
-  const TI* __restrict__ X = (const TI*)s.X[v];
-  TO* __restrict__ Y = (TO*)s.Y[v];
-  const int64_t rows = s.rows[v], cols = s.cols[v], xld = s.xld[v], xps = s.xps[v], yld = s.yld[v], yps = s.yps[v];
-  const int mode = s.mode[v];
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  bool bad = false;
-  for (int64_t i = blockIdx.y; i < rows; i += gridDim.y) {
-    if (j >= cols) continue;
-    const int64_t src = i * xld + j;
-    const int64_t dst = (mode & 1) ? (j * yld + i) : (i * yld + j);
+  const int64_t total = s.first[s.n];
+  bool bad = false;  // a non-finite element of a view that asks for the check
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    int v = 0;
+    while (v + 1 < s.n && e >= s.first[v + 1]) ++v;
+    const int64_t l = e - s.first[v], i = l / s.cols[v], j = l % s.cols[v];
+    const int mode = s.mode[v];
+    const TI* __restrict__ X = (const TI*)s.X[v] + i * s.xld[v] + j;
+    TO* __restrict__ Y = (TO*)s.Y[v] + ((mode & 1) ? (j * s.yld[v] + i) : (i * s.yld[v] + j));
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      double x = to_d<TI>(X[src + c * xps]);
-      bad |= !(x - x == 0.0);
+      double x = to_d<TI>(X[c * s.xps[v]]);
+      bad |= (mode & 4) && !(x - x == 0.0);
       if ((mode & 2) && c > 0) x = -x;
-      Y[dst + c * yps] = from_d<TO>(x);
+      Y[c * s.yps[v]] = from_d<TO>(x);
     }
   }
-  if ((mode & 4) && bad) atomicOr(status, ST_NUMERIC);
+  if (bad) atomicOr(status, ST_NUMERIC);
 }
 
 template <typename TI, typename TO>
-static void cast_set_out(const Ctx& c, const CastSet& s, int n, int64_t maxr, int64_t maxc) {
-  const dim3 grid((unsigned)((maxc + 255) / 256), (unsigned)std::min<int64_t>(maxr, 65535), (unsigned)n);
-  hipLaunchKernelGGL((k_cast_set<TI, TO>), grid, dim3(256), 0, c.stream, s, c.status);
+static void cast_set_out(const Ctx& c, const CastSet& s) {
+  const int64_t blocks = std::min<int64_t>((s.first[s.n] + 255) / 256, 65536);
+  hipLaunchKernelGGL((k_cast_set<TI, TO>), dim3((unsigned)blocks), dim3(256), 0, c.stream, s, c.status);
 }
 
 template <typename TI>
-static void cast_set_in(const Ctx& c, const CastSet& s, int n, int64_t maxr, int64_t maxc, int odt) {
+static void cast_set_in(const Ctx& c, const CastSet& s, int odt) {
   switch (odt) {
-    case QCUR_F64: cast_set_out<TI, double>(c, s, n, maxr, maxc); break;
-    case QCUR_F32: cast_set_out<TI, float>(c, s, n, maxr, maxc); break;
-    default: cast_set_out<TI, uint16_t>(c, s, n, maxr, maxc);
+    case QCUR_F64: cast_set_out<TI, double>(c, s); break;
+    case QCUR_F32: cast_set_out<TI, float>(c, s); break;
+    default: cast_set_out<TI, uint16_t>(c, s);
   }
 }
 
@@ -342,25 +418,24 @@ hipError_t launch_cast_set(const Ctx& c, int n, const QView* X, const QView* Y, 
     return hipSuccess;
   }
   CastSet s = {};
-  int64_t maxr = 0, maxc = 0;
   for (int v = 0; v < n; ++v) {
-    s.X[v] = X[v].p;
-    s.Y[v] = Y[v].p;
-    s.rows[v] = X[v].rows;
-    s.cols[v] = X[v].cols;
-    s.xld[v] = X[v].ld;
-    s.xps[v] = X[v].ps;
-    s.yld[v] = Y[v].ld;
-    s.yps[v] = Y[v].ps;
-    s.mode[v] = modes[v];
-    maxr = std::max(maxr, X[v].rows);
-    maxc = std::max(maxc, X[v].cols);
+    if (X[v].rows == 0 || X[v].cols == 0) continue;  // nothing to cast
+    const int k = s.n++;
+    s.X[k] = X[v].p;
+    s.Y[k] = Y[v].p;
+    s.cols[k] = X[v].cols;
+    s.xld[k] = X[v].ld;
+    s.xps[k] = X[v].ps;
+    s.yld[k] = Y[v].ld;
+    s.yps[k] = Y[v].ps;
+    s.mode[k] = modes[v];
+    s.first[k + 1] = s.first[k] + X[v].rows * X[v].cols;
   }
-  if (maxr == 0 || maxc == 0) return hipSuccess;
+  if (s.n == 0) return hipSuccess;
   switch (X[0].dt) {
-    case QCUR_F64: cast_set_in<double>(c, s, n, maxr, maxc, Y[0].dt); break;
-    case QCUR_F32: cast_set_in<float>(c, s, n, maxr, maxc, Y[0].dt); break;
-    default: cast_set_in<uint16_t>(c, s, n, maxr, maxc, Y[0].dt);
+    case QCUR_F64: cast_set_in<double>(c, s, Y[0].dt); break;
+    case QCUR_F32: cast_set_in<float>(c, s, Y[0].dt); break;
+    default: cast_set_in<uint16_t>(c, s, Y[0].dt);
   }
   return hipGetLastError();
 }
