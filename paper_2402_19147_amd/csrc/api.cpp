@@ -349,7 +349,6 @@ qcur_status pinv_fast_group(const Ctx& c, int nb, const QView* X, double rtol, i
   }
   HIPCHK(launch_cast_set(c, nb, X, Zr, cmode));
   HIPCHK(launch_sumsq_batch(c, nb, Zr, w.part, w.norms + 0, 4));
-  const BatchSpec bz = same_stride(nb, zslab);
   BatchSpec bzg;  // Gram matrices: lower triangle only (all the Cholesky reads)
   bzg.count = nb;
   bzg.sA = zslab;
@@ -1074,7 +1073,7 @@ Slots slots_of(Bump& b, int count, int64_t rows, int64_t cols, int dt) {
 
 QView slot_view(const Slots& s, int64_t rows, int64_t cols) { return QView{s.p, rows, cols, s.ld, s.ps, s.dt}; }
 
-Slots sl(double* p, int64_t rows, int64_t cols, int64_t ld) {
+Slots sl(double* p, int64_t rows, int64_t /*cols*/, int64_t ld) {
   return Slots{p, ld, rows * ld, 4 * rows * ld, QCUR_F64};
 }
 
@@ -1715,7 +1714,7 @@ size_t qcur_gemm_workspace(int64_t M, int64_t N, int64_t K, int compute) {
 
 size_t qcur_approx_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int core, int compute) {
   if (m < 0 || n < 0 || c < 0 || r < 0 || !valid_compute(compute)) return 0;
-  Ctx dummy{0, nullptr, nullptr};
+  Ctx dummy{};
   ApproxArgs a = sizing_args(m, n, c, r, core, compute);
   Bump b(nullptr);
   // operands may arrive in any dtype: size for the worst case (all converted)
@@ -1727,7 +1726,7 @@ size_t qcur_approx_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int cor
 
 size_t qcur_residual_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int compute) {
   if (m < 0 || n < 0 || c < 0 || r < 0 || !valid_compute(compute)) return 0;
-  Ctx dummy{0, nullptr, nullptr};
+  Ctx dummy{};
   const int other = compute == QCUR_F64 ? QCUR_F32 : QCUR_F64;
   QView A{nullptr, m, n, n, m * n, other}, C{nullptr, m, c, c, m * c, other};
   QView U{nullptr, c, r, r, c * r, other}, R{nullptr, r, n, n, r * n, other};
@@ -1738,7 +1737,7 @@ size_t qcur_residual_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int c
 
 size_t qcur_backward_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int compute) {
   if (m < 0 || n < 0 || c < 0 || r < 0 || (compute != QCUR_F64 && compute != QCUR_F32)) return 0;
-  Ctx dummy{0, nullptr, nullptr};
+  Ctx dummy{};
   BwdArgs a{};
   a.A = QView{nullptr, m, n, n, m * n, compute};
   a.r = r;
@@ -1965,7 +1964,7 @@ qcur_status qcur_approx(qcur_handle h, const qcur_qmat* A, const qcur_qmat* C, c
   a.rank_out = rank_out;
   {
     Bump sz(nullptr);
-    Ctx dummy{0, nullptr, nullptr};
+    Ctx dummy{};
     approx_run(dummy, a, m, n, cc, r, sz, true);
     const size_t need = sz.used + 256;
     if (!ws || ws_bytes < need) return fail(QCUR_ERR_WORKSPACE, "approx needs %zu workspace bytes", need);
@@ -1999,7 +1998,7 @@ qcur_status qcur_residual(qcur_handle h, const qcur_qmat* A, const qcur_qmat* C,
   QView Av = view_of(*A), Cv = view_of(*C), Uv = view_of(*U), Rv = view_of(*R);
   {
     Bump sz(nullptr);
-    Ctx dummy{0, nullptr, nullptr};
+    Ctx dummy{};
     residual_run(dummy, Av, Cv, Uv, Rv, mask, mask_ld, compute, nullptr, 1, nullptr, 0.0, sz, true);
     const size_t need = sz.used + 256;
     if (!ws || ws_bytes < need) return fail(QCUR_ERR_WORKSPACE, "residual needs %zu workspace bytes", need);
@@ -2083,7 +2082,7 @@ size_t qcur_solve_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int core
   s.compute = compute;
   s.refine = 1;
   s.U = QView{nullptr, c, r, r, c * r, acc_dt(compute)};
-  Ctx dummy{0, nullptr, nullptr};
+  Ctx dummy{};
   size_t worst = 0;
   for (int dt : {QCUR_F64, QCUR_F32, QCUR_BF16}) {
     s.A.dt = dt;
@@ -2137,7 +2136,7 @@ qcur_status qcur_solve(qcur_handle h, const qcur_qmat* A, int64_t c, int64_t r, 
   if (W) { Wv = view_of(*W); s.W = &Wv; }
   {
     Bump sz(nullptr);
-    Ctx dummy{0, nullptr, nullptr};
+    Ctx dummy{};
     solve_run(dummy, s, sz, true);
     const size_t need = sz.used + 256;
     if (!ws || ws_bytes < need) return fail(QCUR_ERR_WORKSPACE, "solve needs %zu workspace bytes", need);
@@ -2303,7 +2302,7 @@ size_t qcur_complete_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int c
   a.cc = c;
   a.compute = compute;
   Bump b(nullptr);
-  Ctx dummy{0, nullptr, nullptr};
+  Ctx dummy{};
   complete_run(dummy, a, b, true);
   return b.used + 256;
 }
@@ -2319,7 +2318,7 @@ size_t qcur_complete_resampled_workspace(int64_t m, int64_t n, int64_t c, int64_
   a.resample = true;
   a.sampling = sampling;
   Bump b(nullptr);
-  Ctx dummy{0, nullptr, nullptr};
+  Ctx dummy{};
   complete_run(dummy, a, b, true);
   return b.used + 256;
 }
@@ -2387,7 +2386,7 @@ qcur_status complete_entry(qcur_handle h, const qcur_qmat* Y, const uint8_t* mas
   a.seed = seed;
   {
     Bump sz(nullptr);
-    Ctx dummy{0, nullptr, nullptr};
+    Ctx dummy{};
     complete_run(dummy, a, sz, true);
     if (!ws || ws_bytes < sz.used + 256) return fail(QCUR_ERR_WORKSPACE, "completion needs %zu workspace bytes", sz.used + 256);
   }

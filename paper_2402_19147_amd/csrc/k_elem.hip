@@ -276,7 +276,7 @@ static void gather_set_in(const Ctx& c, QView A, const GatherSet& g, int odt) {
   }
 }
 
-hipError_t launch_gather(const Ctx& c, QView A, const int64_t* I, int64_t r, const int64_t* J, int64_t cc,
+hipError_t launch_gather(const Ctx& c, QView A, const int64_t* I, int64_t /*r*/, const int64_t* J, int64_t /*cc*/,
                          const QView* C, const QView* R, const QView* W) {
   const QView* outs[3] = {C, R, W};
   const int64_t* ri[3] = {nullptr, I, I};
