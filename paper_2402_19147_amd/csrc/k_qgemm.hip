@@ -864,6 +864,10 @@ hipError_t launch_gemm_batched(const Ctx& c, int opA, int opB, double alpha, QVi
   if (g.K == 0) {  // D = beta * D
     return launch_axpby(c, 0.0, D, beta, D);
   }
+  // tall FP64 products Z P^H with a short K: the run-streaming kernel
+  if (bs.tile == 0 && bs.splits == 0 &&
+      tall_nh_applies(compute, opA, opB, A, B, g.M, g.N, g.K, g.tri, bs.M || bs.N || bs.K, bs.sA, bs.sB))
+    return launch_tall_nh(c, alpha, A, B, beta, D, g.K, g.batch, bs.sA, bs.sB, bs.sD, (g.tri & TRI_B_UPPER) != 0);
   // thin FP64 / FP32 products with a long K (Gram matrices, cores): the
   // fragment-streaming kernel
   if (bs.tile == 0 && bs.splits == 0 && thin_hn_applies(compute, opA, opB, g.M, g.N, g.K, g.tri, bs.M || bs.N || bs.K))

@@ -230,6 +230,126 @@ __global__ __launch_bounds__(256) void k_thin_reduce(const E* __restrict__ Pall,
   }
 }
 
+// Tall products D = alpha A B^H + beta D in FP64 with both operands
+// contiguous in k (A: M x K, B: N x K, row-major) and a short K: the
+// orthonormal factors Q = Z P^H of CholeskyQR (P lower triangular, so
+// op(B) = P^H is upper triangular and the K range of column block j stops
+// at its last column).  One wave owns a 16 x 16 block of D over the whole
+// K range; a workgroup holds four row blocks of one column block.  The MFMA
+// contraction index is permuted the same way in both operands: in each
+// chunk of 16 k, lane group g (lanes 16g .. 16g + 15) takes k = 4g + s at
+// MFMA step s, so a lane's fragments for the four steps are four
+// consecutive elements of one row of A and of B: one 32-byte run each.
+// Two register chunks alternate, the loads of one fenced ahead of the
+// MFMAs of the other.
+//
+// A conj(b) in the Hamilton product (Section 2.2), with n = -a:
+//   plane 0: a0 p0 + a1 p1 + a2 p2 + a3 p3
+//   plane 1: a1 p0 + n0 p1 + a3 p2 + n2 p3
+//   plane 2: a2 p0 + n3 p1 + n0 p2 + a1 p3
+//   plane 3: a3 p0 + a2 p1 + n1 p2 + n0 p3
+struct TallArgs {
+  const double* A;
+  int64_t lda, psa, sA;
+  const double* B;
+  int64_t ldb, psb, sB;
+  double* D;
+  int64_t ldd, psd, sD;
+  int64_t M, N, K;
+  double alpha, beta;
+  int b_upper;  // op(B) upper triangular: column j meets k <= j only
+};
+
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+__global__ __launch_bounds__(256) void k_tall_nh(TallArgs g, int nbi, int nbj) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int t = blockIdx.x;  // (problem, column block, group of four row blocks)
+  const int ngi = (nbi + 3) / 4;
+  const int b = t / (nbj * ngi), rem = t % (nbj * ngi);
+  const int bj = rem / ngi, bi = (rem % ngi) * 4 + wave;
+  if (bi >= nbi) return;  // no barrier follows: the wave may leave
+  const int64_t M = g.M, N = g.N, K = g.K;
+  const int64_t i0 = (int64_t)bi * 16, j0 = (int64_t)bj * 16;
+  const int64_t kend = g.b_upper ? std::min(K, j0 + 16) : K;
+  const int64_t nch = (kend + 15) / 16;
+  const int r = lane & 15, kg = 4 * (lane >> 4);
+  const double* __restrict__ pa = g.A + (int64_t)b * g.sA + std::min(i0 + r, M - 1) * g.lda;
+  const double* __restrict__ pb = g.B + (int64_t)b * g.sB + std::min(j0 + r, N - 1) * g.ldb;
+  // K is a multiple of 4, so a run starting below K lies inside the row;
+  // runs starting at or past K (or past kend) read the row's last run and
+  // are zeroed in A
+  double ra[2][4][4], rb[2][4][4];
+  auto load_chunk = [&](int buf, int64_t ch) {
+    const int64_t k = std::min(16 * ch + kg, K - 4);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const f64x2 a01 = *(const f64x2*)(pa + q * g.psa + k), a23 = *(const f64x2*)(pa + q * g.psa + k + 2);
+      const f64x2 b01 = *(const f64x2*)(pb + q * g.psb + k), b23 = *(const f64x2*)(pb + q * g.psb + k + 2);
+      ra[buf][q][0] = a01[0];
+      ra[buf][q][1] = a01[1];
+      ra[buf][q][2] = a23[0];
+      ra[buf][q][3] = a23[1];
+      rb[buf][q][0] = b01[0];
+      rb[buf][q][1] = b01[1];
+      rb[buf][q][2] = b23[0];
+      rb[buf][q][3] = b23[1];
+    }
+    asm volatile("" ::: "memory");
+  };
+  f64x4 acc[4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) acc[p] = (f64x4){0, 0, 0, 0};
+  auto compute_chunk = [&](int buf, int64_t ch) {
+    const bool ok = ch < nch && 16 * ch + kg < kend;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const double a0 = ok ? ra[buf][0][s] : 0.0, a1 = ok ? ra[buf][1][s] : 0.0;
+      const double a2 = ok ? ra[buf][2][s] : 0.0, a3 = ok ? ra[buf][3][s] : 0.0;
+      const double n0 = -a0, n1 = -a1, n2 = -a2, n3 = -a3;
+      const double p0 = rb[buf][0][s], p1 = rb[buf][1][s], p2 = rb[buf][2][s], p3 = rb[buf][3][s];
+      acc[0] = TT<double>::mfma(a0, p0, acc[0]);
+      acc[1] = TT<double>::mfma(a1, p0, acc[1]);
+      acc[2] = TT<double>::mfma(a2, p0, acc[2]);
+      acc[3] = TT<double>::mfma(a3, p0, acc[3]);
+      acc[0] = TT<double>::mfma(a1, p1, acc[0]);
+      acc[1] = TT<double>::mfma(n0, p1, acc[1]);
+      acc[2] = TT<double>::mfma(n3, p1, acc[2]);
+      acc[3] = TT<double>::mfma(a2, p1, acc[3]);
+      acc[0] = TT<double>::mfma(a2, p2, acc[0]);
+      acc[1] = TT<double>::mfma(a3, p2, acc[1]);
+      acc[2] = TT<double>::mfma(n0, p2, acc[2]);
+      acc[3] = TT<double>::mfma(n1, p2, acc[3]);
+      acc[0] = TT<double>::mfma(a3, p3, acc[0]);
+      acc[1] = TT<double>::mfma(n2, p3, acc[1]);
+      acc[2] = TT<double>::mfma(a1, p3, acc[2]);
+      acc[3] = TT<double>::mfma(n0, p3, acc[3]);
+    }
+  };
+  load_chunk(0, 0);
+  for (int64_t ch = 0; ch < nch; ch += 2) {
+    load_chunk(1, ch + 1);
+    compute_chunk(0, ch);
+    load_chunk(0, ch + 2);
+    compute_chunk(1, ch + 1);
+  }
+  const int64_t j = j0 + r;
+  double* D = g.D + (int64_t)b * g.sD;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t i = i0 + TT<double>::out_row(lane, q);
+    if (i < M && j < N) {
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const int64_t o = i * g.ldd + j + p * g.psd;
+        double v = g.alpha * acc[p][q];
+        if (g.beta != 0.0) v += g.beta * D[o];
+        D[o] = v;
+      }
+    }
+  }
+}
+
 }  // namespace
 
 bool thin_hn_applies(int compute, int opA, int opB, int64_t M, int64_t N, int64_t K, int tri, bool per_problem_dims) {
@@ -285,6 +405,43 @@ hipError_t launch_thin_hn(const Ctx& c, int compute, double alpha, QView A, QVie
   if (compute == QCUR_F32)
     return launch_thin_dt<float>(c, alpha, A, B, beta, D, K, batch, sA, sB, sD, lower_only, ws, ws_bytes);
   return launch_thin_dt<double>(c, alpha, A, B, beta, D, K, batch, sA, sB, sD, lower_only, ws, ws_bytes);
+}
+
+bool tall_nh_applies(int compute, int opA, int opB, QView A, QView B, int64_t M, int64_t N, int64_t K, int tri,
+                     bool per_problem_dims, int64_t sA, int64_t sB) {
+  auto even = [](int64_t x) { return (x & 1) == 0; };
+  return compute == QCUR_F64 && opA == QCUR_OP_N && opB == QCUR_OP_H && !per_problem_dims &&
+         (tri & ~TRI_B_UPPER) == 0 && M >= 512 && N <= 256 && K >= 4 && K <= 256 && K % 4 == 0 &&
+         ((uintptr_t)A.p % 16) == 0 && ((uintptr_t)B.p % 16) == 0 && even(A.ld) && even(A.ps) && even(B.ld) &&
+         even(B.ps) && even(sA) && even(sB);
+}
+
+hipError_t launch_tall_nh(const Ctx& c, double alpha, QView A, QView B, double beta, QView D, int64_t K, int batch,
+                          int64_t sA, int64_t sB, int64_t sD, bool b_upper) {
+  const int64_t M = D.rows, N = D.cols;
+  const int nbi = (int)((M + 15) / 16), nbj = (int)((N + 15) / 16);
+  TallArgs g;
+  g.A = (const double*)A.p;
+  g.lda = A.ld;
+  g.psa = A.ps;
+  g.sA = sA;
+  g.B = (const double*)B.p;
+  g.ldb = B.ld;
+  g.psb = B.ps;
+  g.sB = sB;
+  g.D = (double*)D.p;
+  g.ldd = D.ld;
+  g.psd = D.ps;
+  g.sD = sD;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.alpha = alpha;
+  g.beta = beta;
+  g.b_upper = b_upper ? 1 : 0;
+  const int64_t wgs = (int64_t)batch * nbj * ((nbi + 3) / 4);
+  hipLaunchKernelGGL(k_tall_nh, dim3((unsigned)wgs), dim3(256), 0, c.stream, g, nbi, nbj);
+  return hipGetLastError();
 }
 
 }  // namespace qcur

@@ -119,6 +119,14 @@ bool thin_hn_applies(int compute, int opA, int opB, int64_t M, int64_t N, int64_
 hipError_t launch_thin_hn(const Ctx& c, int compute, double alpha, QView A, QView B, double beta, QView D,
                           int64_t K, int batch, int64_t sA, int64_t sB, int64_t sD, bool lower_only, void* ws,
                           size_t ws_bytes);
+// Tall FP64 products D = alpha A B^H + beta D with both operands contiguous
+// in k (M >= 512, N <= 256, K <= 256 a multiple of 4, 16-byte aligned rows;
+// equal sizes over a batch; op(B) may be upper triangular): one wave per
+// 16 x 16 block of D over the whole K range, no workspace.
+bool tall_nh_applies(int compute, int opA, int opB, QView A, QView B, int64_t M, int64_t N, int64_t K, int tri,
+                     bool per_problem_dims, int64_t sA, int64_t sB);
+hipError_t launch_tall_nh(const Ctx& c, double alpha, QView A, QView B, double beta, QView D, int64_t K, int batch,
+                          int64_t sA, int64_t sB, int64_t sD, bool b_upper);
 // Workspace for any plan with at most max_splits K slices.
 size_t gemm_workspace_splits(int64_t M, int64_t N, int compute, int batch, int max_splits);
 hipError_t launch_gemm(const Ctx& c, int opA, int opB, double alpha, QView A, QView B, double beta,

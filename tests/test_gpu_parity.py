@@ -112,6 +112,23 @@ def test_gemm_thin_hn(M, K, Nn, compute, tol):
     assert np.array_equal(N(Q.gemm(T(Ai, dt), T(Bi, dt), opA=1, opB=0, compute=compute)), qmul(qH(Ai), Bi))
 
 
+@pytest.mark.parametrize("M,K,Nn", [(1024, 200, 200), (1000, 64, 37), (777, 256, 250), (512, 4, 16), (600, 70, 40)])
+def test_gemm_f64_tall_nh(M, K, Nn):
+    # FP64 A B^H with a tall output and a short K: the run-streaming kernel
+    # (ragged 16-blocks, K at its limit; K = 70 is not a multiple of 4 and
+    # takes the tiled kernel)
+    rng = np.random.default_rng(M + 3 * K + Nn)
+    A = rng.standard_normal((4, M, K))
+    B = rng.standard_normal((4, Nn, K))
+    D0 = rng.standard_normal((4, M, Nn))
+    Dt = T(D0)
+    Q.gemm(T(A), T(B), opA=0, opB=1, alpha=-0.5, beta=0.25, D=Dt, compute=Q.F64)
+    assert rel(N(Dt), -0.5 * qmul(A, qH(B)) + 0.25 * D0) < 1e-13
+    Ai = workloads.small_int_quat(M, K, rng, 3)
+    Bi = workloads.small_int_quat(Nn, K, rng, 3)
+    assert np.array_equal(N(Q.gemm(T(Ai), T(Bi), opA=0, opB=1, compute=Q.F64)), qmul(Ai, qH(Bi)))
+
+
 @pytest.mark.parametrize("compute,tol", [(Q.F64, 1e-13), (Q.F32, 1e-5), (Q.BF16, 2e-2), (Q.BF16X3, 1e-4)])
 def test_gemm_gaussian_alpha_beta(compute, tol):
     rng = np.random.default_rng(7)
