@@ -261,3 +261,12 @@ def test_split_bf16_compute_validation(L):
     assert L.qcur_approx_workspace(1024, 1024, 200, 200, Q.CORE_CAR, Q.BF16X3) > 0
     d, dp = _dims([(64, 80, 16, 12)])
     assert L.qcur_batch_workspace(1, dp, Q.F32, Q.LENGTH, Q.BF16X3, 0, 0) == 0
+
+
+def test_every_source_is_built():
+    # each HIP / C++ source under csrc/ is compiled into one of the two
+    # libraries, so no kernel file can drop out of the build unnoticed
+    from paper_2402_19147_amd import build as B
+    on_disk = {f for f in os.listdir(B.CSRC) if f.endswith((".hip", ".cpp"))}
+    assert on_disk == set(B.SOURCES) | set(B.PROBE_SOURCES)
+    assert not set(B.SOURCES) & set(B.PROBE_SOURCES)
