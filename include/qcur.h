@@ -147,8 +147,13 @@ qcur_status qcur_gather(qcur_handle handle, const qcur_qmat* A, const int64_t* I
  * (Section 2.1).  Singular values <= rtol * sigma_max count as zero
  * (rtol < 0 selects max(p, q) * 2^-52); max_rank > 0 keeps at most that many.
  * rank_out (device int64[1], may be NULL) receives the kept rank.
- * Computed by one-sided (Hestenes) Jacobi on quaternion columns.
- * Synchronises the stream once per Jacobi sweep to test convergence.
+ * Route: with Z = X (p >= q) or X^H, FP64 CholeskyQR2 (Z = Q T, X^+ from
+ * Q and T^{-1}) when its full-rank certificate holds (Cholesky succeeds,
+ * kappa_F(Z) below 1e7 and kappa_F * rtol below 1e-2) and no rank cap
+ * applies; otherwise, and for matrices small enough for one workgroup,
+ * one-sided (Hestenes) Jacobi on quaternion columns.  Synchronises the
+ * stream once to read the certificate, and on the Jacobi route once per
+ * sweep to test convergence.
  * ws: qcur_pinv_workspace(p, q) bytes.  Non-finite input raises
  * QCUR_ERR_NUMERIC in the status word. */
 qcur_status qcur_pinv(qcur_handle handle, const qcur_qmat* X, double rtol, int64_t max_rank,
@@ -231,7 +236,8 @@ qcur_status qcur_residual(qcur_handle handle, const qcur_qmat* A, const qcur_qma
  * gB != NULL: dA = d<gB, CUR(A)>/dA (vector-Jacobian product).
  * gB == NULL: masked loss L = ||P_Omega(A - CUR(A))||_F^2 (mask as in
  * qcur_residual); dA = dL/dA and loss (device double[1], may be NULL)
- * receives L.  I and J must hold distinct in-range indices (else
+ * receives L.  In this mode dA may be NULL when loss is given: then only L
+ * is computed.  I and J must hold distinct in-range indices (else
  * QCUR_ERR_ARG in the status word).  compute QCUR_F64 or QCUR_F32 (A, gB
  * and dA in that dtype).  ws: qcur_backward_workspace(m, n, c, r, compute). */
 qcur_status qcur_backward(qcur_handle handle, const qcur_qmat* A, const int64_t* I, int64_t r,
@@ -248,8 +254,9 @@ qcur_status qcur_backward(qcur_handle handle, const qcur_qmat* A, const int64_t*
  * max_rank) and residual (device double[1]) = ||A - C U R||_F as in
  * qcur_residual.  Outputs: I (int64[r]), J (int64[c]) sorted, U (c x r, FP64
  * for QCUR_F64 else FP32), rank_out (device int64[2] or NULL).  Optional
- * outputs (NULL = internal): p_col[n], q_row[m] and C, R, W in A's dtype.
- * Same limits as qcur_draw for m and n.  Synchronises once per group of
+ * outputs (NULL = internal): p_col[n], q_row[m] and C, R, W in A's dtype;
+ * B (m x n, FP64 for QCUR_F64 else FP32, NULL = not formed) receives C U R
+ * as in qcur_approx.  Same limits as qcur_draw for m and n.  Synchronises once per group of
  * pseudoinverses (the full-rank certificate), after the products that follow
  * it when they are cheap (as in qcur_approx).
  * ws: qcur_solve_workspace(m, n, c, r, core, compute) bytes. */
@@ -257,7 +264,7 @@ qcur_status qcur_solve(qcur_handle handle, const qcur_qmat* A, int64_t c, int64_
                        int compute, uint64_t seed, int with_replacement, int refine_steps, double rtol,
                        int64_t max_rank, int64_t* I, int64_t* J, qcur_qmat* U, double* residual,
                        int64_t* rank_out, double* p_col, double* q_row, qcur_qmat* C, qcur_qmat* R,
-                       qcur_qmat* W, void* ws, size_t ws_bytes);
+                       qcur_qmat* W, qcur_qmat* B, void* ws, size_t ws_bytes);
 size_t qcur_solve_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int core, int compute);
 
 /* ---- many independent solves of uneven sizes --------------------------- */

@@ -3,8 +3,10 @@
 CURLoss(A, I, J, mask)  ->  ||P_Omega(A - C W^+ R)||_F^2  with C = A(:,J),
     R = A(I,:), W = A(I,J) for fixed index sets: the data-fit term of the
     completion problem (Example 4.4) restricted to the observed set.  Its
-    backward calls qcur_backward in masked-loss mode, which recomputes W^+
-    instead of storing it.
+    forward is one qcur_backward call in masked-loss mode, which returns the
+    loss and, when A needs a gradient, dL/dA (kept for the backward pass,
+    which only scales it); W^+ is computed inside that call and never
+    stored.
 CUR(A, I, J)  ->  B = C W^+ R (materialised).  Its backward is the
     vector-Jacobian product of qcur_backward for the incoming gradient of B.
 
@@ -30,18 +32,15 @@ def _compute(A):
 class CURLossFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, A, I, J, mask, rtol, max_rank):
-        compute = _compute(A)
-        C, R, W = Q.gather(A, I, J)
-        U, _, _ = Q.approx(None, C, R, W, core=Q.CORE_WPINV, compute=compute, rtol=rtol, max_rank=max_rank)
-        fro, _ = Q.residual(A, C, U, R, mask=mask, compute=compute)
-        ctx.save_for_backward(A, I, J, mask)   # W^+ is recomputed in backward
-        ctx.rtol, ctx.max_rank = rtol, max_rank
-        return (fro[0] * fro[0]).to(A.dtype)
+        _compute(A)
+        need = ctx.needs_input_grad[0]
+        dA, loss = Q.backward(A.detach(), I, J, mask=mask, rtol=rtol, max_rank=max_rank, want_dA=need)
+        ctx.save_for_backward(dA if need else None)
+        return loss[0].to(A.dtype)
 
     @staticmethod
     def backward(ctx, g):
-        A, I, J, mask = ctx.saved_tensors
-        dA, _ = Q.backward(A, I, J, mask=mask, rtol=ctx.rtol, max_rank=ctx.max_rank)
+        (dA,) = ctx.saved_tensors
         return g.to(dA.dtype) * dA, None, None, None, None, None
 
 

@@ -865,7 +865,7 @@ qcur_status residual_run(const Ctx& c, QView A, QView C, QView U, QView R, const
 // ---- backward ---------------------------------------------------------------
 struct BwdArgs {
   QView A, gB, dA;
-  bool hasgB;
+  bool hasgB, hasdA;
   const int64_t* I;
   const int64_t* J;
   int64_t r, cc;
@@ -927,7 +927,8 @@ qcur_status backward_run(const Ctx& c, const BwdArgs& a, Bump& b, bool count_onl
     Bump t = shared;
     t.take(8);
     double* lossp = a.loss ? a.loss : lossbuf;
-    CHK(residual_run(c, a.A, C, Ux, R, a.mask, a.mask_ld, dt, lossp, 0, &G, 2.0, t, false));
+    CHK(residual_run(c, a.A, C, Ux, R, a.mask, a.mask_ld, dt, lossp, 0, a.hasdA ? &G : nullptr, 2.0, t, false));
+    if (!a.hasdA) return QCUR_OK;  // the loss alone
     Gb = G;
     sgn = -1.0;
   }
@@ -971,6 +972,7 @@ struct SolveArgs {
   int64_t* rank_out;
   double *p, *q;
   const QView *C, *R, *W;  // optional caller buffers for the gathers
+  const QView* B;           // optional output C U R
 };
 
 // Algorithm 1 end to end: probabilities, the two draws in one launch, the
@@ -994,7 +996,8 @@ qcur_status solve_run(const Ctx& c, const SolveArgs& s, Bump& b, bool count_only
   a.R = R;
   a.W = W;
   a.U = s.U;
-  a.hasB = false;
+  a.hasB = s.B != nullptr;
+  if (s.B) a.B = *s.B;
   a.core = s.core;
   a.compute = s.compute;
   a.refine = s.core == QCUR_CORE_CAR ? s.refine : 0;
@@ -2015,11 +2018,13 @@ qcur_status qcur_backward(qcur_handle h, const qcur_qmat* A, const int64_t* I, i
                           const qcur_qmat* gB, const uint8_t* mask, int64_t mask_ld, double rtol, int64_t max_rank,
                           int compute, qcur_qmat* dA, double* loss, void* ws, size_t ws_bytes) {
   CHK(check_qmat(A, "A"));
-  CHK(check_qmat(dA, "dA"));
+  if (!dA && (gB || !loss)) return fail(QCUR_ERR_ARG, "dA may be NULL only for the loss alone (gB NULL, loss given)");
+  if (dA) CHK(check_qmat(dA, "dA"));
   if (compute != QCUR_F64 && compute != QCUR_F32) return fail(QCUR_ERR_DTYPE, "backward computes in FP64 or FP32");
-  if (A->dtype != compute || dA->dtype != compute) return fail(QCUR_ERR_DTYPE, "A and dA must be in the compute dtype");
+  if (A->dtype != compute || (dA && dA->dtype != compute))
+    return fail(QCUR_ERR_DTYPE, "A and dA must be in the compute dtype");
   const int64_t m = A->rows, n = A->cols;
-  CHK(check_dims(dA, "dA", m, n));
+  if (dA) CHK(check_dims(dA, "dA", m, n));
   if (r < 1 || c < 1 || r > m || c > n) return fail(QCUR_ERR_ARG, "index counts out of range");
   if (!I || !J) return fail(QCUR_ERR_ARG, "I and J must not be NULL");
   if (gB) {
@@ -2035,7 +2040,8 @@ qcur_status qcur_backward(qcur_handle h, const qcur_qmat* A, const int64_t* I, i
   CHK(check_handle(h));
   BwdArgs a{};
   a.A = view_of(*A);
-  a.dA = view_of(*dA);
+  if (dA) a.dA = view_of(*dA);
+  a.hasdA = dA != nullptr;
   a.hasgB = gB != nullptr;
   if (gB) a.gB = view_of(*gB);
   a.I = I;
@@ -2082,6 +2088,8 @@ size_t qcur_solve_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int core
   s.compute = compute;
   s.refine = 1;
   s.U = QView{nullptr, c, r, r, c * r, acc_dt(compute)};
+  const QView Bs{nullptr, m, n, n, m * n, acc_dt(compute)};
+  s.B = &Bs;
   Ctx dummy{};
   size_t worst = 0;
   for (int dt : {QCUR_F64, QCUR_F32, QCUR_BF16}) {
@@ -2096,7 +2104,8 @@ size_t qcur_solve_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int core
 qcur_status qcur_solve(qcur_handle h, const qcur_qmat* A, int64_t c, int64_t r, int sampling, int core, int compute,
                        uint64_t seed, int with_replacement, int refine_steps, double rtol, int64_t max_rank,
                        int64_t* I, int64_t* J, qcur_qmat* U, double* residual, int64_t* rank_out, double* p_col,
-                       double* q_row, qcur_qmat* C, qcur_qmat* R, qcur_qmat* W, void* ws, size_t ws_bytes) {
+                       double* q_row, qcur_qmat* C, qcur_qmat* R, qcur_qmat* W, qcur_qmat* B, void* ws,
+                       size_t ws_bytes) {
   CHK(check_solve(A, c, r, sampling, core, compute, with_replacement, refine_steps, rtol, max_rank));
   if (!I || !J || !residual) return fail(QCUR_ERR_ARG, "I, J and residual must not be NULL");
   CHK(check_qmat(U, "U"));
@@ -2134,6 +2143,14 @@ qcur_status qcur_solve(qcur_handle h, const qcur_qmat* A, int64_t c, int64_t r, 
   if (C) { Cv = view_of(*C); s.C = &Cv; }
   if (R) { Rv = view_of(*R); s.R = &Rv; }
   if (W) { Wv = view_of(*W); s.W = &Wv; }
+  QView Bv;
+  if (B) {
+    CHK(check_qmat(B, "B"));
+    CHK(check_dims(B, "B", A->rows, A->cols));
+    if (B->dtype != acc_dt(compute)) return fail(QCUR_ERR_DTYPE, "B must be FP64 (F64 compute) or FP32");
+    Bv = view_of(*B);
+    s.B = &Bv;
+  }
   {
     Bump sz(nullptr);
     Ctx dummy{};
@@ -2365,6 +2382,8 @@ qcur_status complete_entry(qcur_handle h, const qcur_qmat* Y, const uint8_t* mas
   if (max_iter < 0) return fail(QCUR_ERR_ARG, "max_iter must be >= 0");
   if (!std::isfinite(rtol) || !(tol >= 0.0)) return fail(QCUR_ERR_ARG, "rtol must be finite and tol >= 0");
   if (max_rank < 0) return fail(QCUR_ERR_ARG, "max_rank must be >= 0");
+  if (resample && (Y->rows > 16384 || Y->cols > 16384))
+    return fail(QCUR_ERR_UNSUPPORTED, "matrix side exceeds the sampler's LDS limit");
   CompleteArgs a{};
   a.Y = view_of(*Y);
   a.X = view_of(*X);

@@ -83,6 +83,12 @@ __device__ void draw_body(const double* __restrict__ probs, int64_t n, int64_t c
   const int64_t npad = (n + 63) / 64 * 64;
   const int64_t nb = npad / 64;
   const int64_t nsb = (nb + 63) / 64;
+  constexpr int NB1 = (int)(DRAW_MAX_N_NOREPL / 64 / 64);  // superblocks the draw loop keeps in registers
+  if (nsb > NB1) {  // beyond the sampler's size limit: refuse rather than index past the registers
+    for (int64_t t = threadIdx.x; t < count; t += DRAW_THREADS) idx[t] = -1;
+    if (threadIdx.x == 0) atomicOr(status, ST_SAMPLE);
+    return;
+  }
   uint64_t* wl = lds;              // npad weights, then in-block inclusive prefix sums
   uint64_t* L1 = wl + npad;        // nb block sums
   uint64_t* L2 = L1 + nb;          // nsb superblock sums
@@ -162,7 +168,6 @@ __device__ void draw_body(const double* __restrict__ probs, int64_t n, int64_t c
   // wave complete in order; the memory clobber makes every lane reload the
   // weights of the next draw's block.
   if (wave == 0) {
-    constexpr int NB1 = (int)(DRAW_MAX_N_NOREPL / 64 / 64);  // block registers per lane
     uint64_t l2p = wave_incl_scan_u64(lane < nsb ? L2[lane] : 0ull);
     uint64_t l1p[NB1];
 #pragma unroll

@@ -77,7 +77,7 @@ def _declare(L):
                                   QP, c_p, c_p, c_sz]),
         "qcur_cast": (c_int, [c_p, QP, QP]),
         "qcur_solve": (c_int, [c_p, QP, c_i64, c_i64, c_int, c_int, c_int, c_u64, c_int, c_int, c_d, c_i64, c_p,
-                               c_p, QP, c_p, c_p, c_p, c_p, QP, QP, QP, c_p, c_sz]),
+                               c_p, QP, c_p, c_p, c_p, c_p, QP, QP, QP, QP, c_p, c_sz]),
         "qcur_solve_workspace": (c_sz, [c_i64, c_i64, c_i64, c_i64, c_int, c_int]),
         "qcur_batch_workspace": (c_sz, [ctypes.c_int32, c_p, c_int, c_int, c_int, c_int, c_int]),
         "qcur_batch_prepare": (c_int, [c_p, ctypes.c_int32, c_p, c_int, c_int, c_int, c_int, c_int, c_p, c_sz]),
@@ -282,12 +282,17 @@ def residual(A, C, U, R, mask=None, compute=F64, want_E=False, e_scale=1.0):
     return fro, E
 
 
-def backward(A, I, J, gB=None, mask=None, rtol=-1.0, max_rank=0):
-    """dA for the VJP of CUR(A) (gB given) or for the masked loss (gB None)."""
+def backward(A, I, J, gB=None, mask=None, rtol=-1.0, max_rank=0, want_dA=True):
+    """(dA, loss): dA for the VJP of CUR(A) (gB given) or for the masked loss
+    (gB None, which also returns the loss as a device double[1]); with
+    want_dA False (masked-loss mode only) dA is None and only the loss is
+    computed."""
     compute = _QCUR_DT[A.dtype]
     _, m, n = A.shape
     r, c = I.numel(), J.numel()
-    dA = torch.empty_like(A)
+    if not want_dA and gB is not None:
+        raise ValueError("want_dA=False needs the masked-loss mode (gB None)")
+    dA = torch.empty_like(A) if want_dA else None
     loss = torch.zeros(1, dtype=torch.float64, device=A.device)
     ws = _ws(lib().qcur_backward_workspace(m, n, c, r, compute), A.device)
     mld = mask.stride(0) if mask is not None else 0
@@ -320,14 +325,15 @@ class Solver:
         self.ws = _ws(lib().qcur_solve_workspace(m, n, c, r, core, compute), dev)
 
     def __call__(self, A: torch.Tensor, sampling: int = LENGTH, seed: int = 0, refine_steps: int = 0,
-                 rtol: float = -1.0, max_rank: int = 0, with_replacement: bool = False):
+                 rtol: float = -1.0, max_rank: int = 0, with_replacement: bool = False, B: torch.Tensor = None):
+        """One solve; B (optional, (4, m, n) in U's dtype) receives C U R."""
         m, n, c, r = self.shape
         if tuple(A.shape) != (4, m, n):
             raise ValueError("A does not match the solver's shape")
         _check(lib().qcur_solve(_h(A), _qp(A), c, r, sampling, self.core, self.compute, seed & (2 ** 64 - 1),
                                 int(with_replacement), refine_steps, rtol, max_rank, _ptr(self.I), _ptr(self.J),
                                 _qp(self.U), _ptr(self.residual), _ptr(self.ranks), None, None, None, None, None,
-                                _ptr(self.ws), self.ws.numel()))
+                                _qp(B), _ptr(self.ws), self.ws.numel()))
         return self
 
 

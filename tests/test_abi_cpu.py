@@ -232,6 +232,15 @@ def test_complete_resampled_workspace_and_validation(L):
     assert call(r=51) == 1 and "exceed" in L.qcur_last_error().decode()
     assert call(nbytes=16) == 4
     assert call(X=qm(50, 40, Q.F64)) == 3
+    # a side beyond the sampler's limit of 16384 is refused on the host when
+    # index sets are drawn per step (the fixed-set completion has no draw)
+    Yw, Xw = qm(8, 16385, Q.F32), qm(8, 16385, Q.F32)
+    st = L.qcur_complete_resampled(None, Yw, FAKE, 16385, 4, 4, Q.LENGTH, 7, Q.F32, -1.0, 0, 10, 1e-4, Xw,
+                                   FAKE, FAKE, None, None, FAKE, 1 << 40)
+    assert st == 8 and "sampler" in L.qcur_last_error().decode()
+    st = L.qcur_complete(None, Yw, FAKE, 16385, FAKE, 4, FAKE, 4, Q.F32, -1.0, 0, 10, 1e-4, Xw, None, None,
+                         FAKE, 1 << 40)
+    assert st == 1  # valid: only the NULL handle is rejected
 
 
 def test_svd_workspace_and_validation(L):

@@ -40,10 +40,12 @@ def kappa(X):
 
 def tol_for(compute, C, R):
     """Relative tolerance (w.r.t. ||A||_F) of CUR products and residuals:
-    the dtype's bar, widened by the conditioning of the sampled C and R."""
-    k = kappa(C) + kappa(R)
-    return {Q.F64: max(1e-12, 10 * 2.0 ** -52 * k), Q.F32: max(1e-5, 4 * U32 * k),
-            Q.BF16: max(2e-2, 4 * 2.0 ** -9 * k)}[compute]
+    FP64 1e-12, widened by the conditioning of the sampled C and R (which
+    limits how well the FP64 projectors are determined); FP32 products 1e-5;
+    BF16 operands 2e-2."""
+    if compute == Q.F64:
+        return max(1e-12, 10 * 2.0 ** -52 * (kappa(C) + kappa(R)))
+    return {Q.F32: 1e-5, Q.BF16: 2e-2}[compute]
 
 
 def make_batch(count, seed, mn=(20, 150), k=(2, 8), noise=1e-3):
@@ -238,8 +240,8 @@ def test_batch_512_workload(compute):
         assert np.all(np.diff(J) > 0) and J[0] >= 0 and J[-1] < n
         assert np.all(np.diff(I) > 0) and I[0] >= 0 and I[-1] < m
     assert np.all(N(bs.ranks)[:, 0] == np.array([d[2] for d in dims]))
-    # a sample of problems against the checker, element by element
-    for b in (0, 1, 97, 255, 256, 511):
+    # every problem against the checker, element by element
+    for b in range(len(dims)):
         check_problem(bs, A, b, dims, 40, compute)
 
 
