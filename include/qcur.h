@@ -286,6 +286,9 @@ size_t qcur_solve_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int core
  * in its first r_b entries); J: int64[count][cx].  residual: device
  * double[count].  rank_out: device int64[count][2] (ranks of C_b, R_b) or
  * NULL.  p_col: device double[count][nx], q_row: double[count][mx] or NULL.
+ * B (may be NULL): B_b = C_b U_b R_b in the top-left m_b x n_b corner of
+ * slot b (rows >= mx, cols >= nx, slots b_bstride elements apart; FP64 for
+ * QCUR_F64 else FP32), written by the residual's own product tiles.
  * Problem b draws with the seed seed + b (J_b set 0, I_b set 1), so it
  * repeats qcur_solve of A_b with that seed; its probabilities are folded in
  * another order, equal to qcur_solve's up to rounding.
@@ -326,7 +329,7 @@ qcur_status qcur_solve_batched(qcur_handle handle, int32_t count, const int32_t*
                                uint64_t seed, int with_replacement, int refine_steps, double rtol,
                                int64_t max_rank, int64_t* I, int64_t* J, qcur_qmat* U, int64_t u_bstride,
                                double* residual, int64_t* rank_out, double* p_col, double* q_row,
-                               void* ws, size_t ws_bytes);
+                               qcur_qmat* B, int64_t b_bstride, void* ws, size_t ws_bytes);
 
 /* ---- completion from partially observed entries (Algorithm 2) ---------- */
 

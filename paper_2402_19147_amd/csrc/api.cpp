@@ -708,8 +708,12 @@ qcur_status approx_run(const Ctx& c, const ApproxArgs& a, int64_t m, int64_t n, 
     int64_t* ro[2] = {a.rank_out, a.rank_out ? a.rank_out + 1 : nullptr};
     // FP64 products: CholeskyQR2; FP32/BF16 products: a second pass only
     // when the first leaves Q^H Q - I above a small fraction of their
-    // rounding unit
-    const double orth_tol = a.compute == QCUR_F64 ? 0.0 : a.compute == QCUR_BF16 ? 0x1p-12 : 0x1p-26;
+    // rounding unit.  With a refinement step the bound is 2^-12: a defect
+    // delta of the factors (Q^H Q = I + Delta) leaves M0 = Q_C^H A Q_R off
+    // the least-squares core by O(delta) but the refined M1 only by
+    // O(delta^2), below the rounding of the FP32 products.
+    const double orth_tol =
+        a.compute == QCUR_F64 ? 0.0 : (a.compute == QCUR_BF16 || a.refine > 0) ? 0x1p-12 : 0x1p-26;
     // operands in the product dtype (Q_C, Q_R are cast into fixed buffers,
     // so that a recomputation reuses them)
     QView Ax = as_dtype(c, a.A, idt, b, count_only, &err);
@@ -770,11 +774,13 @@ qcur_status approx_run(const Ctx& c, const ApproxArgs& a, int64_t m, int64_t n, 
       }
       if (a.fro || a.hasB) CHK(left_factor());
       if (a.fro) {
-        // ||A - C U R||_F = ||A - Q_C M Q_R^H||_F
-        HIPCHK(launch_residual_gemm(c, a.A, B1x, Qr, nullptr, 0, a.compute, part, nullptr, 0.0, QCUR_OP_H));
+        // ||A - C U R||_F = ||A - Q_C M Q_R^H||_F (and C U R itself when asked, from the same tiles)
+        HIPCHK(launch_residual_gemm(c, a.A, B1x, Qr, nullptr, 0, a.compute, part, nullptr, 0.0, QCUR_OP_H,
+                                    a.hasB ? &a.B : nullptr));
         HIPCHK(launch_sum_partials(c, part, (int64_t)residual_tiles(m, n, a.compute), a.fro, 1));
+      } else if (a.hasB) {
+        HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_H, 1.0, B1x, Qr, 0.0, a.B, a.compute, gws, gw));
       }
-      if (a.hasB) HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_H, 1.0, B1x, Qr, 0.0, a.B, a.compute, gws, gw));
       // U = P_C^H (M P_R) in FP64
       if (M64.p != M.p) HIPCHK(launch_cast(c, M, M64, CAST_COPY));
       HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, M64, Pv[1], 0.0, W1, QCUR_F64, gws, gw));
@@ -1234,6 +1240,7 @@ struct BatchArgs {
   double* residual;
   int64_t* rank_out;
   double *p, *q;
+  Slots B;  // optional C_b U_b R_b (B.p == nullptr: not formed)
 };
 
 BatchSpec bspec(int count, const Slots& A, const Slots& B, const Slots& D, const int* M, const int* N,
@@ -1309,10 +1316,10 @@ qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, Bat
     HIPCHK(launch_gemm_batched(c, opA, opB, alpha, A, B, beta, D, compute, w.gws, w.gws_bytes, bs));
     return QCUR_OK;
   };
-  auto resid = [&](const Slots* E) -> qcur_status {
+  auto resid = [&](const Slots* E, const Slots* Bout) -> qcur_status {
     auto run = [&](int tile) {
       return launch_residual_gemm_batched(c, s.count, a.A, w.B1x, resid_R, QCUR_OP_H, s.mx, s.nx, s.rx, w.dm, w.dn,
-                                          w.dr, s.compute, w.part, E, 1.0, tile);
+                                          w.dr, s.compute, w.part, E, 1.0, tile, Bout);
     };
     if (tu && tu->measure && tu->plan[BS_RESID].tile == 0) {
       float t64 = 0.f, t32 = 0.f;
@@ -1440,7 +1447,7 @@ qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, Bat
     // E = A - Q_C M Q_R^H;  M += Q_C^H (E Q_R)
     CHK(left_factor());
     resid_R = Qr;
-    CHK(resid(&w.E));
+    CHK(resid(&w.E, nullptr));
     if (w.Ex.p != w.E.p) HIPCHK(launch_cast_batch(c, n, w.E, w.Ex, w.dm, w.dn, mx, nx, CAST_COPY));
     CHK(stage(BS_T, QCUR_OP_N, QCUR_OP_N, 1.0, slot_view(w.Ex, mx, nx), slot_view(Qr, nx, rx), 0.0,
                                slot_view(w.T, mx, rx), s.compute, bspec(n, w.Ex, Qr, w.T, w.dm, w.dr, w.dn)));
@@ -1448,10 +1455,11 @@ qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, Bat
     CHK(stage(BS_M, QCUR_OP_H, QCUR_OP_N, 1.0, slot_view(Qc, mx, cx), slot_view(w.Tx, mx, rx), 1.0,
                                slot_view(w.M, cx, rx), s.compute, bspec(n, Qc, w.Tx, w.M, w.dc, w.dr, w.dm)));
   }
-  // residual_b = ||A_b - Q_C M Q_R^H||_F = ||A_b - C_b U_b R_b||_F
+  // residual_b = ||A_b - Q_C M Q_R^H||_F = ||A_b - C_b U_b R_b||_F (and
+  // B_b = C_b U_b R_b from the same tiles when asked)
   CHK(left_factor());
   resid_R = Qr;
-  CHK(resid(nullptr));
+  CHK(resid(nullptr, a.B.p ? &a.B : nullptr));
   HIPCHK(launch_resid_sum_batch(c, n, w.part, resid_tiles, a.residual));
   // U = P_C^H M P_R in FP64
   if (w.M64.p != w.M.p) HIPCHK(launch_cast_batch(c, n, w.M, w.M64, w.dc, w.dr, cx, rx, CAST_COPY));
@@ -2249,7 +2257,7 @@ qcur_status qcur_solve_batched(qcur_handle h, int32_t count, const int32_t* dims
                                int64_t a_bstride, int sampling, int compute, uint64_t seed, int with_replacement,
                                int refine_steps, double rtol, int64_t max_rank, int64_t* I, int64_t* J,
                                qcur_qmat* U, int64_t u_bstride, double* residual, int64_t* rank_out, double* p_col,
-                               double* q_row, void* ws, size_t ws_bytes) {
+                               double* q_row, qcur_qmat* B, int64_t b_bstride, void* ws, size_t ws_bytes) {
   if (with_replacement != 0 && with_replacement != 1) return fail(QCUR_ERR_ARG, "with_replacement must be 0 or 1");
   if (!A) return fail(QCUR_ERR_ARG, "A is NULL");
   BatchShape s{};
@@ -2257,6 +2265,10 @@ qcur_status qcur_solve_batched(qcur_handle h, int32_t count, const int32_t* dims
   CHK(check_slotted(A, "A", s.mx, s.nx, a_bstride));
   CHK(check_slotted(U, "U", s.cx, s.rx, u_bstride));
   if (U->dtype != acc_dt(compute)) return fail(QCUR_ERR_DTYPE, "U must be FP64 (F64 compute) or FP32");
+  if (B) {
+    CHK(check_slotted(B, "B", s.mx, s.nx, b_bstride));
+    if (B->dtype != acc_dt(compute)) return fail(QCUR_ERR_DTYPE, "B must be FP64 (F64 compute) or FP32");
+  }
   if (!I || !J || !residual) return fail(QCUR_ERR_ARG, "I, J and residual must not be NULL");
   if (!std::isfinite(rtol)) return fail(QCUR_ERR_ARG, "rtol must be finite");
   if (max_rank < 0) return fail(QCUR_ERR_ARG, "max_rank must be >= 0");
@@ -2294,6 +2306,7 @@ qcur_status qcur_solve_batched(qcur_handle h, int32_t count, const int32_t* dims
   a.rank_out = rank_out;
   a.p = p_col;
   a.q = q_row;
+  if (B) a.B = Slots{B->p, B->ld, B->pstride, b_bstride, (int)B->dtype};
   BatchTuning* tu = nullptr;
   if (rec->autotune) {
     tu = &rec->tun;

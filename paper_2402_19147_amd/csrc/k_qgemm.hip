@@ -129,6 +129,10 @@ struct GemmArgs {
   int edt;
   int64_t eld, eps;
   double e_scale;
+  // optional copy of the product tile itself (C U R) next to E
+  void* Bo;
+  int bodt;
+  int64_t bold, bops, sBo;
   // BF16: operands are 16-byte aligned with row, plane and batch strides that
   // are multiples of 8, so eight consecutive elements load as one vector
   int vec;
@@ -629,6 +633,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
               if (!keep) d = 0.0;
               sq += d * d;
               if (g.E) store_from_double(g.E, g.edt, b * g.sE + i * g.eld + j + p * g.eps, g.e_scale * d);
+              if (g.Bo)
+                store_from_double(g.Bo, g.bodt, b * g.sBo + i * g.bold + j + p * g.bops, (double)acc[p][x][y][r]);
             }
           }
         }
@@ -926,7 +932,7 @@ static void launch_fused(const Ctx& c, GemmArgs& g, int compute, int t) {
 }
 
 hipError_t launch_residual_gemm(const Ctx& c, QView A, QView B1, QView R, const uint8_t* mask, int64_t mask_ld,
-                                int compute, double* partials, QView* E, double e_scale, int opR) {
+                                int compute, double* partials, QView* E, double e_scale, int opR, const QView* Bout) {
   GemmArgs g = {};
   g.A = B1.p; g.lda = B1.ld; g.psa = B1.ps;
   g.B = R.p; g.ldb = R.ld; g.psb = R.ps;
@@ -940,6 +946,7 @@ hipError_t launch_residual_gemm(const Ctx& c, QView A, QView B1, QView R, const 
   g.splits = 1;
   g.vec = compute == QCUR_BF16 && vec_ok(B1, 0) && vec_ok(R, 0);
   if (E) { g.E = E->p; g.edt = E->dt; g.eld = E->ld; g.eps = E->ps; g.e_scale = e_scale; }
+  if (Bout) { g.Bo = Bout->p; g.bodt = Bout->dt; g.bold = Bout->ld; g.bops = Bout->ps; }
   if (g.M == 0 || g.N == 0) return hipSuccess;
   g.splits = 1;
   launch_fused<EPI_RESID>(c, g, compute, resid_tile(g.M, g.N, compute));
@@ -951,7 +958,8 @@ hipError_t launch_residual_gemm(const Ctx& c, QView A, QView B1, QView R, const 
 // when E is given.
 hipError_t launch_residual_gemm_batched(const Ctx& c, int count, Slots A, Slots B1, Slots R, int opR, int64_t mx,
                                         int64_t nx, int64_t kx, const int* bM, const int* bN, const int* bK,
-                                        int compute, double* partials, const Slots* E, double e_scale, int tile) {
+                                        int compute, double* partials, const Slots* E, double e_scale, int tile,
+                                        const Slots* Bout) {
   if (count <= 0 || mx <= 0 || nx <= 0) return hipSuccess;
   GemmArgs g = {};
   g.A = B1.p; g.lda = B1.ld; g.psa = B1.ps; g.sA = B1.slab;
@@ -967,6 +975,7 @@ hipError_t launch_residual_gemm_batched(const Ctx& c, int count, Slots A, Slots 
   g.vec = compute == QCUR_BF16 && vec_ok(QView{B1.p, 1, 1, B1.ld, B1.ps, B1.dt}, B1.slab) &&
           vec_ok(QView{R.p, 1, 1, R.ld, R.ps, R.dt}, R.slab);
   if (E) { g.E = E->p; g.edt = E->dt; g.eld = E->ld; g.eps = E->ps; g.sE = E->slab; g.e_scale = e_scale; }
+  if (Bout) { g.Bo = Bout->p; g.bodt = Bout->dt; g.bold = Bout->ld; g.bops = Bout->ps; g.sBo = Bout->slab; }
   if (compute == QCUR_BF16X3) return hipErrorInvalidValue;  // not offered for batches
   const int t = tile == 32 ? 32 : 64;
   const dim3 grid((unsigned)((nx + t - 1) / t), (unsigned)((mx + t - 1) / t), (unsigned)count);

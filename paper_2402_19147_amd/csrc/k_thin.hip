@@ -354,7 +354,7 @@ __global__ __launch_bounds__(256) void k_tall_nh(TallArgs g, int nbi, int nbj) {
 
 bool thin_hn_applies(int compute, int opA, int opB, int64_t M, int64_t N, int64_t K, int tri, bool per_problem_dims) {
   return (compute == QCUR_F64 || compute == QCUR_F32) && opA == QCUR_OP_H && opB == QCUR_OP_N && !per_problem_dims &&
-         (tri & ~TRI_LOWER_OUT) == 0 && (!(tri & TRI_LOWER_OUT) || M == N) && M <= 256 && N <= 256 &&
+         (tri & ~TRI_LOWER_OUT) == 0 && (!(tri & TRI_LOWER_OUT) || M == N) && M <= 512 && N <= 512 &&
          K >= 4 * std::max(M, N);
 }
 
@@ -411,7 +411,7 @@ bool tall_nh_applies(int compute, int opA, int opB, QView A, QView B, int64_t M,
                      bool per_problem_dims, int64_t sA, int64_t sB) {
   auto even = [](int64_t x) { return (x & 1) == 0; };
   return compute == QCUR_F64 && opA == QCUR_OP_N && opB == QCUR_OP_H && !per_problem_dims &&
-         (tri & ~TRI_B_UPPER) == 0 && M >= 512 && N <= 256 && K >= 4 && K <= 256 && K % 4 == 0 &&
+         (tri & ~TRI_B_UPPER) == 0 && M >= 512 && N <= 512 && K >= 4 && K <= 512 && K % 4 == 0 &&
          ((uintptr_t)A.p % 16) == 0 && ((uintptr_t)B.p % 16) == 0 && even(A.ld) && even(A.ps) && even(B.ld) &&
          even(B.ps) && even(sA) && even(sB);
 }

@@ -134,11 +134,12 @@ hipError_t launch_gemm(const Ctx& c, int opA, int opB, double alpha, QView A, QV
 hipError_t launch_gemm_batched(const Ctx& c, int opA, int opB, double alpha, QView A, QView B, double beta,
                                QView D, int compute, void* ws, size_t ws_bytes, const BatchSpec& bs);
 // Residual: partial sums of squares of e_scale-free P_Omega(A - B1 R) per tile,
-// then a fixed-order final sum into fro (sqrt).  Optional E output.
+// then a fixed-order final sum into fro (sqrt).  Optional E output and
+// optional Bout = B1 op(R) itself (the product tile before the subtraction).
 size_t residual_tiles(int64_t m, int64_t n, int compute);
 hipError_t launch_residual_gemm(const Ctx& c, QView A, QView B1, QView R, const uint8_t* mask,
                                 int64_t mask_ld, int compute, double* partials, QView* E,
-                                double e_scale, int opR = QCUR_OP_N);
+                                double e_scale, int opR = QCUR_OP_N, const QView* Bout = nullptr);
 hipError_t launch_sum_partials(const Ctx& c, const double* partials, int64_t count, double* out,
                                int take_sqrt);
 // Completion step (Algorithm 2): X1 = P_Omega(Y) + P_Omega^c(B1 op(R)) with
@@ -264,6 +265,6 @@ hipError_t launch_resid_sum_batch(const Ctx& c, int count, const double* part, i
 hipError_t launch_residual_gemm_batched(const Ctx& c, int count, Slots A, Slots B1, Slots R, int opR, int64_t mx,
                                         int64_t nx, int64_t kx, const int* bM, const int* bN, const int* bK,
                                         int compute, double* partials, const Slots* E, double e_scale,
-                                        int tile = 64);
+                                        int tile = 64, const Slots* Bout = nullptr);
 
 }  // namespace qcur

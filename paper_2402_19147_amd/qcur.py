@@ -92,7 +92,7 @@ def _declare(L):
         "qcur_svd": (c_int, [c_p, QP, c_p, QP, QP, c_p, c_sz]),
         "qcur_svd_workspace": (c_sz, [c_i64, c_i64]),
         "qcur_solve_batched": (c_int, [c_p, ctypes.c_int32, c_p, QP, c_i64, c_int, c_int, c_u64, c_int, c_int, c_d,
-                                       c_i64, c_p, c_p, QP, c_i64, c_p, c_p, c_p, c_p, c_p, c_sz]),
+                                       c_i64, c_p, c_p, QP, c_i64, c_p, c_p, c_p, c_p, QP, c_i64, c_p, c_sz]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -372,13 +372,14 @@ class BatchSolver:
     least the largest m_b, n_b); see pack_batch.  Outputs after a call:
     I (count, rx), J (count, cx), U (count, 4, cx, rx), residual (count,),
     ranks (count, 2), p (count, nx), q (count, mx), each problem in the
-    leading part of its row/slot.  The call enqueues kernels only, so it may
-    be captured in a torch.cuda.CUDAGraph after one eager call.  With
+    leading part of its row/slot, and with want_B=True also B (count, 4, mx,
+    nx) = C_b U_b R_b.  The call enqueues kernels only, so it may be
+    captured in a torch.cuda.CUDAGraph after one eager call.  With
     autotune=True the first eager call times the candidate launch plans of
     every GEMM stage and keeps the fastest (see plans())."""
 
     def __init__(self, dims, compute: int = F32, sampling: int = LENGTH, refine_steps: int = 0,
-                 a_dtype=torch.float32, device=None, autotune: bool = False):
+                 a_dtype=torch.float32, device=None, autotune: bool = False, want_B: bool = False):
         import numpy as np
         dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         d = np.ascontiguousarray(np.asarray(dims, dtype=np.int32).reshape(-1, 4))
@@ -396,6 +397,7 @@ class BatchSolver:
         self.ranks = torch.zeros((n, 2), dtype=torch.int64, device=dev)
         self.p = torch.zeros((n, self.nx), dtype=torch.float64, device=dev)
         self.q = torch.zeros((n, self.mx), dtype=torch.float64, device=dev)
+        self.B = torch.zeros((n, 4, self.mx, self.nx), dtype=odt, device=dev) if want_B else None
         dptr = ctypes.c_void_p(d.ctypes.data)
         self.autotune = int(bool(autotune))
         nbytes = lib().qcur_batch_workspace(n, dptr, _QCUR_DT[a_dtype], sampling, compute, refine_steps,
@@ -429,11 +431,13 @@ class BatchSolver:
             raise ValueError("A has the wrong number of slots")
         qa, sa = _slots(A)
         qu, su = _slots(self.U)
+        qb, sb = _slots(self.B) if self.B is not None else (None, 0)
         _check(lib().qcur_solve_batched(_h(A), self.count, ctypes.c_void_p(self.dims.ctypes.data), ctypes.byref(qa),
                                         sa, self.sampling, self.compute, seed & (2 ** 64 - 1), int(with_replacement),
                                         self.refine_steps, rtol, max_rank, _ptr(self.I), _ptr(self.J),
                                         ctypes.byref(qu), su, _ptr(self.residual), _ptr(self.ranks), _ptr(self.p),
-                                        _ptr(self.q), _ptr(self.ws), self.ws.numel()))
+                                        _ptr(self.q), ctypes.byref(qb) if qb is not None else None, sb,
+                                        _ptr(self.ws), self.ws.numel()))
         return self
 
 

@@ -193,9 +193,10 @@ def test_batch_workspace_and_validation(L):
     U = qm(20, 30, Q.F32)
     sa, su = 4 * 100 * 80, 4 * 20 * 30
 
-    def solve(count=2, dims=dp, A=A, sa=sa, U=U, su=su, I=FAKE, ws=FAKE, nbytes=ws, compute=Q.F32, repl=0):
+    def solve(count=2, dims=dp, A=A, sa=sa, U=U, su=su, I=FAKE, ws=FAKE, nbytes=ws, compute=Q.F32, repl=0,
+              B=None, sb=0):
         return L.qcur_solve_batched(None, count, dims, A, sa, Q.LENGTH, compute, 1, repl, 0, -1.0, 0, I, FAKE, U,
-                                    su, FAKE, None, None, None, ws, nbytes)
+                                    su, FAKE, None, None, None, B, sb, ws, nbytes)
 
     assert solve() == 1  # valid: only the NULL handle is rejected
     assert "handle" in L.qcur_last_error().decode()
@@ -204,6 +205,9 @@ def test_batch_workspace_and_validation(L):
     assert solve(A=qm(99, 80, Q.F32)) == 2       # slot smaller than the largest problem
     assert solve(U=qm(20, 30, Q.F64)) == 3       # U must be FP32 for FP32 products
     assert solve(I=None) == 1
+    assert solve(B=qm(100, 80, Q.F32), sb=sa) == 1            # the optional C U R output, valid
+    assert solve(B=qm(100, 80, Q.F64), sb=sa) == 3            # B in U's dtype
+    assert solve(B=qm(100, 79, Q.F32), sb=sa) == 2            # B slots hold the largest problem
     over, op = _dims([(64, 80, 100, 12)])        # c > n without replacement
     assert solve(count=1, dims=op) == 2
     assert solve(count=0) == 1

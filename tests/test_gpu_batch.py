@@ -87,9 +87,20 @@ def check_problem(bs, A, b, dims, seed, compute, sampling="length", max_rank=0):
     tol = tol_for(compute, ref["C"], ref["R"])
     res = float(N(bs.residual)[b])
     assert abs(res - ref["residual"]) <= tol * nA, (b, res, ref["residual"])
-    B = cur_product(ref["C"], N(bs.U[b, :, :c, :r]), ref["R"])
     Bref = cur_product(ref["C"], ref["U"], ref["R"])
+    if bs.B is not None:
+        # the batch's own C U R, element by element
+        B = N(bs.B[b, :, :m, :n])
+    else:
+        # C U R from the returned U (FP64 U only: an FP32 U carries its own
+        # rounding, amplified by the conditioning of C and R)
+        assert compute == Q.F64
+        B = cur_product(ref["C"], N(bs.U[b, :, :c, :r]), ref["R"])
     assert np.sqrt(fro2(B - Bref)) <= tol * nA, b
+    if compute == Q.F64:
+        # and the core itself through C U R in FP64
+        Bu = cur_product(ref["C"], N(bs.U[b, :, :c, :r]), ref["R"])
+        assert np.sqrt(fro2(Bu - Bref)) <= tol * nA, b
     return ref
 
 
@@ -97,7 +108,8 @@ def check_problem(bs, A, b, dims, seed, compute, sampling="length", max_rank=0):
 def test_batch_matches_checker(compute):
     probs, dims = make_batch(10, seed=21)
     dt = tdt(compute)
-    bs = Q.BatchSolver(dims, compute=compute, refine_steps=1 if compute == Q.BF16 else 0, a_dtype=dt)
+    bs = Q.BatchSolver(dims, compute=compute, refine_steps=1 if compute == Q.BF16 else 0, a_dtype=dt,
+                       want_B=True)
     A = Q.pack_batch([P["A"] for P in probs], dtype=dt, device=DEV)
     bs(A, seed=5)
     Q.sync_status()
@@ -120,22 +132,21 @@ def test_batch_uniform_sampling():
 def test_batch_equals_single_solve(compute):
     probs, dims = make_batch(6, seed=22, mn=(64, 200), k=(4, 12))
     dt = tdt(compute)
-    bs = Q.BatchSolver(dims, compute=compute, a_dtype=dt)
+    bs = Q.BatchSolver(dims, compute=compute, a_dtype=dt, want_B=True)
     A = Q.pack_batch([P["A"] for P in probs], dtype=dt, device=DEV)
     bs(A, seed=9)
     for b, (m, n, c, r) in enumerate(dims):
         Ab = A[b, :, :m, :n].contiguous()
         S = Q.Solver(m, n, c, r, core=Q.CORE_CAR, compute=compute)
-        S(Ab, seed=9 + b)
+        Bs = torch.empty((4, m, n), dtype=bs.B.dtype, device=DEV)
+        S(Ab, seed=9 + b, B=Bs)
         Q.sync_status()
         assert torch.equal(S.I, bs.I[b, :r]) and torch.equal(S.J, bs.J[b, :c])
         C, R, _ = oracle.gather(N(Ab), N(S.I), N(S.J))
         tol = tol_for(compute, C, R)
         nA = np.sqrt(fro2(N(Ab)))
         assert abs(float(N(S.residual)[0]) - float(N(bs.residual)[b])) <= tol * nA
-        B1 = cur_product(C, N(S.U), R)
-        B2 = cur_product(C, N(bs.U[b, :, :c, :r]), R)
-        assert np.sqrt(fro2(B1 - B2)) <= tol * nA
+        assert np.sqrt(fro2(N(Bs) - N(bs.B[b, :, :m, :n]))) <= tol * nA
 
 
 @pytest.mark.parametrize("compute", [Q.F64, Q.F32])
@@ -227,7 +238,7 @@ def test_batch_512_workload(compute):
     # 512 problems, m, n ~ U{64..512}, k ~ U{8..32}, c = r = 2k
     probs = workloads.batch_problems(512, 4)
     dims = [(P["m"], P["n"], 2 * P["k"], 2 * P["k"]) for P in probs]
-    bs = Q.BatchSolver(dims, compute=compute, refine_steps=1, a_dtype=torch.float32)
+    bs = Q.BatchSolver(dims, compute=compute, refine_steps=1, a_dtype=torch.float32, want_B=True)
     A = Q.pack_batch([P["A"] for P in probs], dtype=torch.float32, device=DEV)
     bs(A, seed=40)
     Q.sync_status()
@@ -249,7 +260,7 @@ def test_batch_512_workload(compute):
 def test_batch_autotuned_plans(compute):
     probs, dims = make_batch(12, seed=28, mn=(40, 260), k=(3, 12))
     A = Q.pack_batch([P["A"] for P in probs], dtype=torch.float32, device=DEV)
-    bs = Q.BatchSolver(dims, compute=compute, refine_steps=1, a_dtype=torch.float32, autotune=True)
+    bs = Q.BatchSolver(dims, compute=compute, refine_steps=1, a_dtype=torch.float32, autotune=True, want_B=True)
     assert bs.plans() is None
     bs(A, seed=6)  # measures the candidate plans
     Q.sync_status()

@@ -93,7 +93,7 @@ def test_gemm_bf16_64_tiles_bit_exact(M, K, Nn, opA, opB):
 
 
 @pytest.mark.parametrize("M,K,Nn", [(200, 1024, 200), (37, 301, 45), (256, 1024, 256), (1, 64, 1), (16, 4099, 16),
-                                    (200, 800, 13)])
+                                    (200, 800, 13), (400, 4096, 400), (512, 2051, 300)])
 @pytest.mark.parametrize("compute,tol", [(Q.F64, 1e-13), (Q.F32, 1e-5)])
 def test_gemm_thin_hn(M, K, Nn, compute, tol):
     # A^H B with a long K and a small output: the fragment-streaming kernel
@@ -112,7 +112,8 @@ def test_gemm_thin_hn(M, K, Nn, compute, tol):
     assert np.array_equal(N(Q.gemm(T(Ai, dt), T(Bi, dt), opA=1, opB=0, compute=compute)), qmul(qH(Ai), Bi))
 
 
-@pytest.mark.parametrize("M,K,Nn", [(1024, 200, 200), (1000, 64, 37), (777, 256, 250), (512, 4, 16), (600, 70, 40)])
+@pytest.mark.parametrize("M,K,Nn", [(1024, 200, 200), (1000, 64, 37), (777, 256, 250), (512, 4, 16), (600, 70, 40),
+                                    (4096, 400, 400), (900, 512, 512), (700, 300, 333)])
 def test_gemm_f64_tall_nh(M, K, Nn):
     # FP64 A B^H with a tall output and a short K: the run-streaming kernel
     # (ragged 16-blocks, K at its limit; K = 70 is not a multiple of 4 and

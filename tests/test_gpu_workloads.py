@@ -52,22 +52,26 @@ def color():
 @pytest.mark.parametrize("compute,refine", [(Q.F64, 0), (Q.F32, 0), (Q.F32, 1), (Q.BF16, 1), (Q.BF16X3, 0)])
 def test_color_workload(color, compute, refine):
     cfg, A, ref = color
+    m, n = cfg["m"], cfg["n"]
     dt = torch.float64 if compute == Q.F64 else torch.float32
     Ad = N(T(A, dt))
-    out = q.solve(T(A, dt), cfg["c"], cfg["r"], sampling=Q.LENGTH, core=Q.CORE_CAR, compute=compute,
-                  seed=cfg["seed"], refine_steps=refine, want_B=True)
+    # the native solve (qcur_solve) with its C U R output
+    S = Q.Solver(m, n, cfg["c"], cfg["r"], core=Q.CORE_CAR, compute=compute)
+    B = torch.empty((4, m, n), dtype=dt, device=DEV)
+    S(T(A, dt), sampling=Q.LENGTH, seed=cfg["seed"], refine_steps=refine, B=B)
     q.sync_status()
     if compute == Q.F64:
         refd = ref
     else:  # the checker on the same (rounded) input
         refd = oracle.solve(Ad, cfg["c"], cfg["r"], "length", "car", seed=cfg["seed"])
-    assert N(out["J"]).astype(np.int64).tolist() == refd["J"].tolist()
-    assert N(out["I"]).astype(np.int64).tolist() == refd["I"].tolist()
+    assert N(S.J).astype(np.int64).tolist() == refd["J"].tolist()
+    assert N(S.I).astype(np.int64).tolist() == refd["I"].tolist()
     Bref = oracle.cur_product(refd["C"], refd["U"], refd["R"])
-    err = np.sqrt(fro2(N(out["B"]) - Bref) / fro2(Bref))
-    assert err < tolerance(compute, refd["C"], refd["R"]), err
-    res = float(N(out["residual"])[0])
-    assert abs(res - refd["residual"]) <= tolerance(compute, refd["C"], refd["R"]) * np.sqrt(fro2(Ad))
+    err = np.sqrt(fro2(N(B) - Bref) / fro2(Bref))
+    tol = tolerance(compute, refd["C"], refd["R"])
+    assert err < tol, err
+    res = float(N(S.residual)[0])
+    assert abs(res - refd["residual"]) <= tol * np.sqrt(fro2(Ad))
 
 
 @pytest.mark.slow
