@@ -468,18 +468,19 @@ qcur_status pinv_fast_group(const Ctx& c, int nb, const QView* X, double rtol, i
 qcur_status jacobi_sweeps(const Ctx& c, const PinvWs& w, int64_t pp, int64_t qq, double tol, double rtol) {
   double* cmax = (double*)((char*)w.flag + 64);
   unsigned* bad = (unsigned*)((char*)w.flag + 128);
-  HIPCHK(launch_zero(c, cmax, 1));
+  HIPCHK(launch_zero(c, cmax, 2));  // the two alternating slots of the running maximum
   const int64_t qpad = (qq + 1) / 2 * 2;
   // negligible pairs: first the per-column bound rtol sigma_max / 2, checked
   // on the result; if the skipped columns add up to more, sweeps go on with
   // the bound divided by sqrt(q)
   double drop2 = rtol > 0.0 ? rtol * rtol / 4.0 : 0.0;
+  int launches = 0;  // round launches so far: selects the slot each one reads
   for (int attempt = 0; attempt < 2; ++attempt) {
     unsigned host_flag = 1;
     for (int sweep = 0; sweep < MAX_SWEEPS && host_flag; ++sweep) {
       HIPCHK(launch_zero_i32(c, (int*)w.flag, 1));
       for (int round = 0; round < qpad - 1; ++round)
-        HIPCHK(launch_jacobi_round(c, w.Y, pp, qq, w.V, qpad, round, tol, w.flag, drop2, cmax));
+        HIPCHK(launch_jacobi_round(c, w.Y, pp, qq, w.V, qpad, round, tol, w.flag, drop2, cmax, launches++));
       HIPCHK(hipMemcpyAsync(&host_flag, w.flag, sizeof(unsigned), hipMemcpyDeviceToHost, c.stream));
       HIPCHK(hipStreamSynchronize(c.stream));
     }

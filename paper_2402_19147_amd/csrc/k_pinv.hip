@@ -120,10 +120,9 @@ __device__ inline double wsum(double v) {
 }
 
 // Pairs of negligible columns.  Any column of Y = Z V has norm at most
-// sigma_max(Z), so the largest squared column norm seen so far (*cmax, kept
-// by atomicMax on its bit pattern: positive doubles order like their bits)
-// bounds sigma_max^2 from below.  A pair whose squared norms are both at
-// most drop2 * (*cmax) is not rotated.  When the sweeps stop, those columns
+// sigma_max(Z), so the largest squared column norm seen so far bounds
+// sigma_max^2 from below.  A pair whose squared norms are both at most
+// drop2 * that bound is not rotated.  When the sweeps stop, those columns
 // D hold a block Y_D orthogonal to all other columns; if ||Y_D||_F <=
 // rtol sigma_max / 2 its singular values fall below the truncation
 // threshold rtol sigma_max and the kept singular triplets are those of the
@@ -131,12 +130,22 @@ __device__ inline double wsum(double v) {
 // afterwards (k_deflation_check), else sweeps again with drop2 =
 // rtol^2 / (4 q), for which the bound holds whatever D is.  Such pairs only
 // slow convergence (columns of rounding noise of a rank-deficient Z).
-// Records max(alpha, beta) in *cmax (an atomic only when it is larger than
-// the value read) and tells whether the pair is negligible.
-__device__ inline bool negligible_pair(double alpha, double beta, double drop2, double* cmax) {
-  const double seen = *(volatile const double*)cmax;
+//
+// The bound is a running maximum kept in two slots that alternate by
+// round: round t reads slot t % 2, which no workgroup of that launch
+// writes, so every decision of the round uses the same value whatever the
+// order in which its workgroups run (run-to-run identical results), and
+// raises slot (t + 1) % 2 to the largest norm it sees (t counts the round
+// launches of the whole factorisation, across sweeps) (atomicMax on the bit
+// pattern: positive doubles order like their bits), workgroup 0 also
+// carrying the value it read, so that slot holds the running maximum for
+// round t + 1.
+__device__ inline bool negligible_pair(double alpha, double beta, double drop2, const double* cmax_rd,
+                                       double* cmax_wr, bool carry) {
+  const double seen = *cmax_rd;
   const double m = alpha > beta ? alpha : beta;
-  if (m > seen) atomicMax((unsigned long long*)cmax, (unsigned long long)__double_as_longlong(m));
+  const double up = carry && seen > m ? seen : m;
+  atomicMax((unsigned long long*)cmax_wr, (unsigned long long)__double_as_longlong(up));
   const double t = drop2 * (m > seen ? m : seen);
   return alpha <= t && beta <= t;
 }
@@ -144,7 +153,7 @@ __device__ inline bool negligible_pair(double alpha, double beta, double drop2, 
 // One round of the circle schedule: workgroup k rotates pair k.
 __global__ __launch_bounds__(256) void k_jacobi_round(double* __restrict__ Y, int64_t p, int64_t q,
                                                       double* __restrict__ V, int qpad, int round, double tol,
-                                                      unsigned* rotated, double drop2, double* cmax) {
+                                                      unsigned* rotated, double drop2, double* cmax, int slot) {
   __shared__ double red[4][6];
   __shared__ Rot rot;
   int a, b;
@@ -165,7 +174,8 @@ __global__ __launch_bounds__(256) void k_jacobi_round(double* __restrict__ Y, in
     double s[6];
     for (int x = 0; x < 6; ++x) s[x] = ((red[0][x] + red[1][x]) + red[2][x]) + red[3][x];
     rot = make_rot(s[0], s[1], s[2], s[3], s[4], s[5], tol);
-    if (negligible_pair(s[0], s[1], drop2, cmax)) rot.rotate = false;
+    if (negligible_pair(s[0], s[1], drop2, cmax + slot, cmax + (slot ^ 1), blockIdx.x == 0))
+      rot.rotate = false;
     if (rot.rotate) atomicOr(rotated, 1u);
   }
   __syncthreads();
@@ -217,9 +227,9 @@ hipError_t launch_deflation_check(const Ctx& c, const double* Y, int64_t p, int6
 }
 
 hipError_t launch_jacobi_round(const Ctx& c, double* Y, int64_t p, int64_t q, double* V, int64_t qpad, int round,
-                               double tol, unsigned* rotated, double drop2, double* cmax) {
+                               double tol, unsigned* rotated, double drop2, double* cmax, int slot) {
   hipLaunchKernelGGL(k_jacobi_round, dim3((unsigned)(qpad / 2)), dim3(256), 0, c.stream, Y, p, q, V, (int)qpad,
-                     round, tol, rotated, drop2, cmax);
+                     round, tol, rotated, drop2, cmax, slot & 1);
   return hipGetLastError();
 }
 

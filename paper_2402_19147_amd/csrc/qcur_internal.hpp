@@ -152,7 +152,7 @@ hipError_t launch_mask_init(const Ctx& c, QView Y, const uint8_t* mask, int64_t 
 
 // Jacobi pseudoinverse pieces.
 hipError_t launch_jacobi_round(const Ctx& c, double* Y, int64_t p, int64_t q, double* V, int64_t qpad, int round,
-                               double tol, unsigned* rotated, double drop2, double* cmax);
+                               double tol, unsigned* rotated, double drop2, double* cmax, int slot);
 hipError_t launch_deflation_check(const Ctx& c, const double* Y, int64_t p, int64_t q, double drop2, double rtol2q,
                                   unsigned* bad);
 hipError_t launch_jacobi_small(const Ctx& c, double* Y, int64_t p, int64_t q, double* V,

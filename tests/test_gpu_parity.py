@@ -356,6 +356,27 @@ def test_pinv_rank_deficient_deflated_jacobi(p, q, k, mr):
     assert rel(qmul(qmul(X, N(Xp)), X), X) < 1e-11
 
 
+@pytest.mark.parametrize("shape,k,mr", [((256, 256), 64, 64), ((300, 230), 45, 0), ((1024, 200), 0, 0),
+                                        ((300, 70), 0, 20)])
+def test_pinv_and_svd_run_twice_bitwise(shape, k, mr):
+    # the same input twice gives the same bits: the CholeskyQR path (fixed-order
+    # reductions), the multi-launch Jacobi sweeps of a rank-deficient matrix
+    # (every workgroup of a round reads the same negligible-pair bound) and
+    # the rank-capped route; the thin SVD likewise
+    p, q = shape
+    rng = np.random.default_rng(p + 7 * q + k)
+    X = (qmul(rng.standard_normal((4, p, k)), rng.standard_normal((4, k, q))) if k
+         else rng.standard_normal((4, p, q)))
+    Xt = T(X)
+    runs = [Q.pinv(Xt, max_rank=mr) for _ in range(2)]
+    Q.sync_status()
+    assert torch.equal(runs[0][0], runs[1][0]) and torch.equal(runs[0][1], runs[1][1])
+    svds = [Q.svd(Xt) for _ in range(2)]
+    Q.sync_status()
+    for a, b in zip(svds[0], svds[1]):
+        assert torch.equal(a, b)
+
+
 # ---------------------------------------------------------------- thin QSVD
 def _qH(X):
     Y = np.swapaxes(X, 1, 2).copy()
