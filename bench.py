@@ -35,9 +35,9 @@ sys.path.insert(0, ROOT)
 WORKLOAD = "dense_4096"
 HEAD = "f32_refine1"
 # HBM bytes per launch of the roofline kernel (FETCH_SIZE + WRITE_SIZE of the
-# FP32 T = A Q_R product at 4096 x 4096 x 400, scaled by a copy of known
-# size), from profiles/qgemm_f32_T_AQr_dense_4096.md; None until measured
-T_AQR_F32_HBM_BYTES = None
+# FP32 T = A Q_R product at 4096 x 4096 x 400 and its split-K reduction,
+# scaled by a copy of known size), from profiles/qgemm_f32_T_AQr_dense_4096.md
+T_AQR_F32_HBM_BYTES = 952.8e6
 
 
 def parse():
@@ -242,8 +242,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "dense_4096: 4096x4096 quaternion, rank-100 N(0,1) factors + N(0,1e-3^2), length "
-                               "sampling c=r=400, U=C^+AR^+ with FP32 products, one refinement step (its "
-                               "correction product on BF16 operands), FP64 pinv of C and R",
+                               "sampling c=r=400, U=C^+AR^+ with FP32 products, one refinement step, FP64 pinv "
+                               "of C and R",
                    "variant": HEAD},
         "roofline": roofline,
         "cpu_baseline": cpu,
