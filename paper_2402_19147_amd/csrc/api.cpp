@@ -251,6 +251,11 @@ qcur_status chol_inv(const Ctx& c, GroupWs& w, double* P) {
   bs_up.tri = TRI_B_UPPER;     // op(B) = P_kk^H
   bs_low.tri = TRI_LOWER_OUT;  // the trailing Gram block: lower triangle only
   double *G = w.G, *L = w.L;
+  if (n > nb) {
+    // larger than one diagonal block: the tile-task graph in one launch
+    HIPCHK(launch_chol_dag(c, G, L, P, n, slab, w.nb, (int*)w.S, w.fail));
+    return QCUR_OK;
+  }
   HIPCHK(launch_zero(c, P, w.nb * slab));
   for (int64_t kb = 0; kb < n; kb += nb) {
     const int64_t wd = std::min(nb, n - kb);

@@ -266,6 +266,358 @@ hipError_t launch_chol_block(const Ctx& c, const double* G, double* P, int w, in
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Factorisation G = L L^H and inverse P = L^{-1} of nb Hermitian positive
+// definite n x n quaternion matrices in one launch, as a graph of 32 x 32
+// tile tasks whose dependencies are met through ready flags in global memory
+// (the blocked right-looking schedule above needs a launch per block step and
+// waits for every tile of a step before the next one starts; here a tile
+// starts as soon as the tiles it reads are ready).  Tasks, one per
+// workgroup:
+//   factor (i, j), j <= i:  S = G_ij - sum_{k<j} L_ik L_jk^H (k in order);
+//       i == j: P_jj = (the factor of S)^{-1} by the elementary steps of
+//       chol_diag;  i > j: L_ij = S P_jj^H;
+//   inverse (i, j), i > j:  P_ij = -P_ii sum_{l=j}^{i-1} L_il P_lj (l in order).
+// Only P and the off-diagonal L tiles are stored.  Every workgroup takes its
+// task from a ticket counter, in an order in which each task depends only on
+// tasks with smaller tickets, and a ticket is only held by a workgroup that
+// is running, so every wait is on a task that is running or done, whatever
+// the number of workgroups the device holds at once.  Waits are bounded:
+// past the spin limit the task goes on, marks its matrix as failed (the
+// caller then takes the Jacobi path) and raises ST_NUMERIC.  Sums run in a
+// fixed order, so results do not depend on scheduling.
+constexpr int DTS = 32;  // tile edge
+constexpr int DAG_THREADS = 256;
+constexpr long DAG_SPIN_LIMIT = 1L << 22;
+typedef double DTile[4][DTS][DTS + 1];
+
+struct DagArgs {
+  const double* G;  // lower triangles; matrix b at G + b * slab, row stride n, plane stride n * n
+  double* L;        // off-diagonal tiles of L
+  double* P;        // L^{-1}, lower (upper part zeroed)
+  int64_t n, slab;
+  int nb, nt;
+  int64_t nfact;    // factor tasks: nb * nt (nt + 1) / 2
+  int* flags;       // [nb][2][nt][nt]: 0 = L tile (and P_jj for a diagonal tile), 1 = P tile
+  int* ticket;
+  int* fail;        // [nb]
+  unsigned* status;
+};
+
+__device__ inline int* dag_flag(const DagArgs& g, int b, int kind, int i, int j) {
+  return g.flags + (((int64_t)b * 2 + kind) * g.nt + i) * g.nt + j;
+}
+
+// Thread 0 waits for a flag (bounded); then every thread fences (acquire).
+__device__ inline void dag_wait(const DagArgs& g, const int* f, int b, int* timed_out) {
+  if (threadIdx.x == 0 && !*timed_out) {
+    long it = 0;
+    while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++it > DAG_SPIN_LIMIT) {
+        *timed_out = 1;
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Every thread's stores are made visible, then thread 0 sets the flag.
+__device__ inline void dag_publish(int* f) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(f, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// tile (ti, tj) of one matrix (row stride n, plane stride n * n) into LDS;
+// entries past n read as zero
+__device__ inline void dag_load(DTile& t, const double* __restrict__ M, int64_t n, int ti, int tj) {
+  const int64_t ps = n * n;
+  for (int e = threadIdx.x; e < DTS * DTS; e += DAG_THREADS) {
+    const int r = e / DTS, c = e % DTS;
+    const int64_t gi = (int64_t)ti * DTS + r, gj = (int64_t)tj * DTS + c;
+    const bool ok = gi < n && gj < n;
+    const int64_t o = gi * n + gj;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) t[q][r][c] = ok ? M[o + q * ps] : 0.0;
+  }
+}
+
+// the four elements of a 32 x 32 tile owned by a thread in the tile
+// products: row tid / 8, columns tid % 8 + 8 s
+__device__ inline void dag_store(double* __restrict__ M, int64_t n, int ti, int tj, const Qd (&v)[4]) {
+  const int64_t ps = n * n;
+  const int r = threadIdx.x >> 3;
+  const int64_t gi = (int64_t)ti * DTS + r;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int c = (threadIdx.x & 7) + 8 * s;
+    const int64_t gj = (int64_t)tj * DTS + c;
+    if (gi < n && gj < n) {
+      const int64_t o = gi * n + gj;
+      M[o] = v[s].w;
+      M[o + ps] = v[s].x;
+      M[o + 2 * ps] = v[s].y;
+      M[o + 3 * ps] = v[s].z;
+    }
+  }
+}
+
+__device__ inline Qd dldq(const DTile& t, int r, int c) { return Qd{t[0][r][c], t[1][r][c], t[2][r][c], t[3][r][c]}; }
+__device__ inline void dstq(DTile& t, int r, int c, Qd v) {
+  t[0][r][c] = v.w;
+  t[1][r][c] = v.x;
+  t[2][r][c] = v.y;
+  t[3][r][c] = v.z;
+}
+
+// acc[s] += sgn * sum_k X[r][k] conj(Y[c][k])  (k < kmax)
+__device__ inline void dag_mul_h(Qd (&acc)[4], const DTile& X, const DTile& Y, double sgn, int kmax = DTS) {
+  const int r = threadIdx.x >> 3, c0 = threadIdx.x & 7;
+  for (int k = 0; k < kmax; ++k) {
+    const Qd a = dldq(X, r, k);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const Qd u = qmul_conj(a, dldq(Y, c0 + 8 * s, k));
+      acc[s].w += sgn * u.w;
+      acc[s].x += sgn * u.x;
+      acc[s].y += sgn * u.y;
+      acc[s].z += sgn * u.z;
+    }
+  }
+}
+
+// acc[s] += sgn * sum_k X[r][k] Y[k][c]  (k < kmax)
+__device__ inline void dag_mul_n(Qd (&acc)[4], const DTile& X, const DTile& Y, double sgn, int kmax = DTS) {
+  const int r = threadIdx.x >> 3, c0 = threadIdx.x & 7;
+  for (int k = 0; k < kmax; ++k) {
+    const Qd a = dldq(X, r, k);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const Qd u = qmul(a, dldq(Y, k, c0 + 8 * s));
+      acc[s].w += sgn * u.w;
+      acc[s].x += sgn * u.x;
+      acc[s].y += sgn * u.y;
+      acc[s].z += sgn * u.z;
+    }
+  }
+}
+
+// Factor and invert the 32 x 32 diagonal tile held in T (lower triangle;
+// entries past the matrix edge, rows >= w, are treated as the identity):
+// the elementary steps of chol_diag over 32 pivots, the lower triangle in
+// registers (elements tid + 256 s of the square), column j and row j of each
+// pivot published through LDS with one barrier per pivot.  On return T holds
+// P = L^{-1} (lower, upper part zero).  A pivot that is not finite and
+// positive sets *bad.
+struct DagDiag {
+  double col[2][DTS][4];
+  double row[2][DTS][4];
+  double piv[2][4];
+  double rs[DTS];
+};
+__device__ void dag_potri(DTile& T, DagDiag& db, int w, int* bad) {
+  const int tid = threadIdx.x;
+  Qd x[4];
+  bool in[4];
+  int ei[4], ec[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int e = tid + DAG_THREADS * s;
+    ei[s] = e / DTS;
+    ec[s] = e % DTS;
+    in[s] = ec[s] <= ei[s];
+    Qd v = in[s] ? dldq(T, ei[s], ec[s]) : Qd{0, 0, 0, 0};
+    if (ei[s] >= w) v = ei[s] == ec[s] ? Qd{1, 0, 0, 0} : Qd{0, 0, 0, 0};  // identity past the edge
+    if (ec[s] >= w && ei[s] != ec[s]) v = Qd{0, 0, 0, 0};
+    x[s] = v;
+  }
+  for (int j = 0; j < DTS; ++j) {
+    const int par = j & 1;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      if (!in[s]) continue;
+      if (ec[s] == j) {
+        if (ei[s] == j) {
+          const bool ok = x[s].w > 0.0 && x[s].w < INFINITY;
+          const double r = rsqrt_nr(ok ? x[s].w : 1.0);
+          db.piv[par][0] = x[s].w;
+          db.piv[par][1] = r;
+          db.piv[par][2] = r * r;
+          db.piv[par][3] = ok ? 0.0 : 1.0;
+          db.rs[j] = r;
+        } else {
+          stq4(db.col[par][ei[s]], x[s]);
+        }
+      }
+      if (ei[s] == j && ec[s] < j) stq4(db.row[par][ec[s]], x[s]);
+    }
+    __syncthreads();
+    const double rd = db.piv[par][2];
+    if (tid == 0 && db.piv[par][3] != 0.0) *bad = 1;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int i = ei[s], c = ec[s];
+      if (!in[s] || i <= j) continue;
+      const Qd ar = ldq4(db.col[par][i]);
+      const Qd u{ar.w * rd, ar.x * rd, ar.y * rd, ar.z * rd};
+      if (c == j) {
+        x[s] = Qd{-u.w, -u.x, -u.y, -u.z};
+      } else {
+        // c > j: A_ic -= u conj(A_cj);  c < j: X_ic -= u X_jc
+        const Qd vr = c > j ? ldq4(db.col[par][c]) : ldq4(db.row[par][c]);
+        const double sg = c > j ? -1.0 : 1.0;
+        const Qd q = qmul(u, Qd{vr.w, sg * vr.x, sg * vr.y, sg * vr.z});
+        x[s] = Qd{x[s].w - q.w, x[s].x - q.x, x[s].y - q.y, x[s].z - q.z};
+      }
+    }
+  }
+  __syncthreads();
+  // P = diag(d^{-1/2}) (X + I)
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int i = ei[s], c = ec[s];
+    const double r = db.rs[i];
+    Qd v{0, 0, 0, 0};
+    if (c < i) v = Qd{x[s].w * r, x[s].x * r, x[s].y * r, x[s].z * r};
+    else if (c == i) v = Qd{r, 0, 0, 0};
+    dstq(T, i, c, v);
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(DAG_THREADS) void k_chol_dag(DagArgs g) {
+  __shared__ DTile ta, tb;
+  __shared__ __align__(16) DagDiag db;
+  __shared__ int task_s, bad, timed_out;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    task_s = atomicAdd(g.ticket, 1);
+    bad = 0;
+    timed_out = 0;
+  }
+  __syncthreads();
+  const int64_t t = task_s;
+  const int nt = g.nt;
+  const bool fact = t < g.nfact;
+  const int64_t u0 = fact ? t : t - g.nfact;
+  const int b = (int)(u0 % g.nb);
+  int64_t u = u0 / g.nb;
+  // column-major position of the tile among the lower (factor) or strictly
+  // lower (inverse) tiles
+  int j = 0;
+  while (u >= (fact ? nt - j : nt - 1 - j)) {
+    u -= fact ? nt - j : nt - 1 - j;
+    ++j;
+  }
+  const int i = j + (int)u + (fact ? 0 : 1);
+  const double* G = g.G + (int64_t)b * g.slab;
+  double* L = g.L + (int64_t)b * g.slab;
+  double* P = g.P + (int64_t)b * g.slab;
+  const int64_t n = g.n;
+  Qd acc[4];
+  const int r = tid >> 3, c0 = tid & 7;
+  if (fact) {
+    // S = G_ij - sum_k L_ik L_jk^H, in k order
+    dag_load(ta, G, n, i, j);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc[s] = dldq(ta, r, c0 + 8 * s);
+    __syncthreads();
+    for (int k = 0; k < j; ++k) {
+      dag_wait(g, dag_flag(g, b, 0, i, k), b, &timed_out);
+      if (i != j) dag_wait(g, dag_flag(g, b, 0, j, k), b, &timed_out);
+      dag_load(ta, L, n, i, k);
+      if (i != j) dag_load(tb, L, n, j, k);
+      __syncthreads();
+      dag_mul_h(acc, ta, i != j ? tb : ta, -1.0);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) dstq(ta, r, c0 + 8 * s, acc[s]);
+    __syncthreads();
+    if (i == j) {
+      const int w = (int)std::min<int64_t>(DTS, n - (int64_t)j * DTS);
+      dag_potri(ta, db, w, &bad);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc[s] = dldq(ta, r, c0 + 8 * s);
+      dag_store(P, n, j, j, acc);
+      // the tiles of P right of the diagonal are zero
+      const Qd z[4] = {Qd{0, 0, 0, 0}, Qd{0, 0, 0, 0}, Qd{0, 0, 0, 0}, Qd{0, 0, 0, 0}};
+      for (int tj = j + 1; tj < nt; ++tj) dag_store(P, n, j, tj, z);
+    } else {
+      // L_ij = S P_jj^H (P_jj lower triangular)
+      dag_wait(g, dag_flag(g, b, 0, j, j), b, &timed_out);
+      dag_load(tb, P, n, j, j);
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc[s] = Qd{0, 0, 0, 0};
+      dag_mul_h(acc, ta, tb, 1.0);
+      dag_store(L, n, i, j, acc);
+    }
+    if (tid == 0 && (bad || timed_out)) atomicOr(g.fail + b, 1);
+    if (tid == 0 && timed_out) atomicOr(g.status, ST_NUMERIC);
+    dag_publish(dag_flag(g, b, 0, i, j));
+  } else {
+    // P_ij = -P_ii sum_{l=j}^{i-1} L_il P_lj, in l order
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc[s] = Qd{0, 0, 0, 0};
+    for (int l = j; l < i; ++l) {
+      dag_wait(g, dag_flag(g, b, 0, i, l), b, &timed_out);
+      dag_wait(g, l == j ? dag_flag(g, b, 0, j, j) : dag_flag(g, b, 1, l, j), b, &timed_out);
+      dag_load(ta, L, n, i, l);
+      dag_load(tb, P, n, l, j);
+      __syncthreads();
+      dag_mul_n(acc, ta, tb, 1.0);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) dstq(tb, r, c0 + 8 * s, acc[s]);
+    dag_wait(g, dag_flag(g, b, 0, i, i), b, &timed_out);
+    dag_load(ta, P, n, i, i);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc[s] = Qd{0, 0, 0, 0};
+    dag_mul_n(acc, ta, tb, -1.0);
+    dag_store(P, n, i, j, acc);
+    if (tid == 0 && timed_out) {
+      atomicOr(g.fail + b, 1);
+      atomicOr(g.status, ST_NUMERIC);
+    }
+    dag_publish(dag_flag(g, b, 1, i, j));
+  }
+}
+
+size_t chol_dag_flag_ints(int nb, int64_t n) {
+  const int64_t nt = (n + DTS - 1) / DTS;
+  return (size_t)nb * 2 * nt * nt + 1;
+}
+
+hipError_t launch_chol_dag(const Ctx& c, const double* G, double* L, double* P, int64_t n, int64_t slab, int nb,
+                           int* flags, int* fail) {
+  const int nt = (int)((n + DTS - 1) / DTS);
+  DagArgs g;
+  g.G = G;
+  g.L = L;
+  g.P = P;
+  g.n = n;
+  g.slab = slab;
+  g.nb = nb;
+  g.nt = nt;
+  g.nfact = (int64_t)nb * nt * (nt + 1) / 2;
+  g.flags = flags;
+  g.ticket = flags + (chol_dag_flag_ints(nb, n) - 1);
+  g.fail = fail;
+  g.status = c.status;
+  hipError_t e = launch_zero_i32(c, flags, (int64_t)chol_dag_flag_ints(nb, n));
+  if (e != hipSuccess) return e;
+  const int64_t tasks = (int64_t)nb * nt * nt;
+  hipLaunchKernelGGL(k_chol_dag, dim3((unsigned)tasks), dim3(DAG_THREADS), 0, c.stream, g);
+  return hipGetLastError();
+}
+
 // Sum of squares of a quaternion view, one FP64 partial per workgroup.
 __global__ __launch_bounds__(256) void k_sumsq(const void* X, int dt, int64_t rows, int64_t cols, int64_t ld,
                                                int64_t ps, double* partials) {

@@ -176,6 +176,14 @@ constexpr int CHOL_BLOCK = 64;
 constexpr int MAXB = 4;
 hipError_t launch_chol_block(const Ctx& c, const double* G, double* P, int w, int64_t ld, int64_t ps, int* fail,
                              int batch, int64_t sbatch);
+// Factorisation and inverse of nb Hermitian positive definite n x n Gram
+// matrices (matrix b at G + b * slab, lower triangle read) in one graph of
+// 32 x 32 tile tasks: P = L^{-1} (lower; the upper part zeroed), the
+// off-diagonal tiles of L in L.  flags: chol_dag_flag_ints(nb, n) ints of
+// workspace (zeroed by the call).  A failed pivot sets fail[b].
+size_t chol_dag_flag_ints(int nb, int64_t n);
+hipError_t launch_chol_dag(const Ctx& c, const double* G, double* L, double* P, int64_t n, int64_t slab, int nb,
+                           int* flags, int* fail);
 hipError_t launch_sumsq(const Ctx& c, QView X, double* partials, double* out);
 hipError_t launch_sumsq_batch(const Ctx& c, int nb, const QView* X, double* partials, double* out, int ostride);
 hipError_t launch_pad_identity(const Ctx& c, double* G, int64_t n, int64_t sbatch, int nb, const int64_t* q);
