@@ -191,12 +191,17 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
   constexpr bool KMAJ = Smem<DT, BM, BN>::KMAJ;
   constexpr int EA = BM * BK / NT;  // elements per thread per plane
   constexpr int EB = BK * BN / NT;
-  constexpr int XB = BM / 32, YB = BN / 32;  // MFMA 16x16 blocks per wave (2 x 2 waves)
+  // waves: 2 x 2 on square tiles (each 32 x 32 or 16 x 16), 4 x 1 on the
+  // 64 x 80 tile (each 16 x 80); XB x YB MFMA 16x16 blocks per wave
+  constexpr int WM = BM == BN ? 2 : 4, WN = 4 / WM;
+  constexpr int XB = BM / (16 * WM), YB = BN / (16 * WN);
+  static_assert(XB >= 1 && YB >= 1 && XB * 16 * WM == BM && YB * 16 * WN == BN, "tile shape");
+  static_assert(BM * BK % NT == 0 && BN * BK % NT == 0, "whole elements per thread");
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+  const int wm = (wave / WN) * (BM / WM), wn = (wave % WN) * (BN / WN);
   const int64_t bm = tile_m * BM, bn = tile_n * BN;
   const int64_t M = g.bM ? (int64_t)g.bM[b] : g.M;
   const int64_t N = g.bN ? (int64_t)g.bN[b] : g.N;
@@ -315,7 +320,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
   // to element loads.
   // NV: 16-byte vectors per plane and thread (k-contiguous) = 4 x 8 blocks
   // per lane (x-contiguous)
-  static_assert(BM == BN, "square tiles");
+  static_assert(BM == BN || (DT != QCUR_BF16 && DT != QCUR_BF16X3), "square BF16 tiles");
   static_assert(DT != QCUR_BF16 || BK == T::KM, "one BF16 MFMA k-step per staged slice");
   constexpr int NV = (DT == QCUR_BF16) ? (BM * BK / 8 + NT - 1) / NT : 1;
   u32x4 va[4 * NV], vb[4 * NV];
@@ -787,6 +792,42 @@ static Plan plan_of(int64_t M, int64_t N, int64_t K, int bk, int batch, int forc
 }
 
 static int bk_of(int compute) { return compute == QCUR_BF16 || compute == QCUR_BF16X3 ? 32 : 16; }
+
+// Single (not batched) FP32 / FP64 products with a tall output and a long K
+// (M >= 2048, K >= 1024: A Q_R and E Q_R of the large solves):
+// 64 x 64 tiles, or for FP32 64 x 80 (which covers N = 400 without a padded
+// column tile), and 1..8 slices of K, chosen by a cost model: workgroups
+// run in rounds of `slots` (two per compute unit when the kernel's LDS and
+// registers allow it: FP32 64 x 64, and 64 x 80 writing split-K partials;
+// one otherwise), a workgroup costs its K steps plus two of pipeline fill
+// times its tile width, and each extra slice adds the partials' write and
+// read (about 22 s / K of the product's time).
+struct WidePlan {
+  int tn, splits;  // tn = 0: not applicable
+};
+static WidePlan wide_plan(int64_t M, int64_t N, int64_t K, int compute, int batch, bool per_problem) {
+  if ((compute != QCUR_F32 && compute != QCUR_F64) || batch != 1 || per_problem || M < 2048 || K < 1024 || N < 64)
+    return WidePlan{0, 0};
+  const int64_t kt = (K + 15) / 16;
+  double best = 1e300;
+  WidePlan bp{64, 1};
+  for (int tn : {64, 80}) {
+    if (tn == 80 && compute != QCUR_F32) continue;
+    const int64_t tiles = ((M + 63) / 64) * ((N + tn - 1) / tn);
+    for (int sp : {1, 2, 3, 4, 6, 8}) {
+      if (sp > 1 && kt / sp < 4) break;
+      const int64_t slots = compute == QCUR_F32 && (tn == 64 || sp > 1) ? 512 : 256;
+      const int64_t per = (kt + sp - 1) / sp;
+      const int64_t rounds = (tiles * sp + slots - 1) / slots;
+      const double cost = (double)rounds * (double)(per + 2) * tn * (1.0 + (sp > 1 ? 22.0 * sp / (double)K : 0.0));
+      if (cost < best * 0.999) {
+        best = cost;
+        bp = WidePlan{tn, sp};
+      }
+    }
+  }
+  return bp;
+}
 // split BF16 stages two BF16 halves per operand: 32-tiles only
 static int tile_of(int compute) { return compute == QCUR_BF16X3 ? 32 : 0; }
 static size_t acc_size(int compute) { return compute == QCUR_F64 ? 8 : 4; }
@@ -797,24 +838,27 @@ size_t gemm_workspace_splits(int64_t M, int64_t N, int compute, int batch, int m
 }
 
 size_t gemm_workspace(int64_t M, int64_t N, int64_t K, int compute, int batch) {
-  const int s = plan_of(M, N, K, bk_of(compute), batch, tile_of(compute)).splits;
+  // room for either plan (triangular products keep the square-tile plan)
+  const WidePlan wp = wide_plan(M, N, K, compute, batch, false);
+  const int s = std::max(wp.tn ? wp.splits : 1, plan_of(M, N, K, bk_of(compute), batch, tile_of(compute)).splits);
   if (s <= 1) return 0;
   return (size_t)batch * s * 4 * (size_t)M * (size_t)N * acc_size(compute);
 }
 
-template <int DT, int TILE>
-static hipError_t gemm_dt_tile(const Ctx& c, GemmArgs g, void* ws, size_t ws_bytes) {
+template <int DT, int TILE, int TN = TILE>
+static hipError_t gemm_dt_tile(const Ctx& c, GemmArgs g, void* ws, size_t ws_bytes, int plan_splits = 0) {
   constexpr int BK = MT<DT>::BK;
   const int64_t kt = (g.K + BK - 1) / BK;
-  int splits = g.force_splits > 0 ? g.force_splits : plan_of(g.M, g.N, g.K, BK, g.batch, TILE).splits;
+  int splits = g.force_splits > 0 ? g.force_splits
+                                  : plan_splits > 0 ? plan_splits : plan_of(g.M, g.N, g.K, BK, g.batch, TILE).splits;
   const size_t need = (size_t)g.batch * splits * 4 * (size_t)g.M * (size_t)g.N * acc_size(DT);
   if (splits > 1 && (ws == nullptr || ws_bytes < need)) splits = 1;
-  dim3 grid((unsigned)((g.N + TILE - 1) / TILE), (unsigned)((g.M + TILE - 1) / TILE), 1);
+  dim3 grid((unsigned)((g.N + TN - 1) / TN), (unsigned)((g.M + TILE - 1) / TILE), 1);
   if (splits == 1) {
     g.ktiles_per_split = (int)kt;
     g.splits = 1;
     grid.z = g.batch;
-    hipLaunchKernelGGL((k_qgemm<DT, EPI_STORE, TILE, TILE>), grid, dim3(NT), 0, c.stream, g);
+    hipLaunchKernelGGL((k_qgemm<DT, EPI_STORE, TILE, TN>), grid, dim3(NT), 0, c.stream, g);
     return hipGetLastError();
   }
   const int per = (int)((kt + splits - 1) / splits);
@@ -827,7 +871,7 @@ static hipError_t gemm_dt_tile(const Ctx& c, GemmArgs g, void* ws, size_t ws_byt
   gp.D = ws;
   gp.ldd = g.N;
   gp.psd = g.M * g.N;
-  hipLaunchKernelGGL((k_qgemm<DT, EPI_PARTIAL, TILE, TILE>), grid, dim3(NT), 0, c.stream, gp);
+  hipLaunchKernelGGL((k_qgemm<DT, EPI_PARTIAL, TILE, TN>), grid, dim3(NT), 0, c.stream, gp);
   hipLaunchKernelGGL(k_splitk_reduce<Acc>,
                      dim3((unsigned)((g.N + 255) / 256), (unsigned)std::min<int64_t>(g.M, 65535), (unsigned)g.batch),
                      dim3(256), 0, c.stream, (const Acc*)ws, splits, g.M, g.N, g.alpha, g.beta, (Acc*)g.D, g.ldd,
@@ -837,6 +881,13 @@ static hipError_t gemm_dt_tile(const Ctx& c, GemmArgs g, void* ws, size_t ws_byt
 
 template <int DT>
 static hipError_t gemm_dt(const Ctx& c, GemmArgs g, void* ws, size_t ws_bytes) {
+  if constexpr (DT == QCUR_F32 || DT == QCUR_F64) {
+    if (!g.force_tile && !g.force_splits && !g.tri) {
+      const WidePlan wp = wide_plan(g.M, g.N, g.K, DT, g.batch, g.bM || g.bN || g.bK);
+      if (wp.tn == 80) return gemm_dt_tile<DT, 64, 80>(c, g, ws, ws_bytes, wp.splits);
+      if (wp.tn == 64) return gemm_dt_tile<DT, 64, 64>(c, g, ws, ws_bytes, wp.splits);
+    }
+  }
   const int tile = g.force_tile ? g.force_tile : plan_of(g.M, g.N, g.K, MT<DT>::BK, g.batch).tile;
   if (tile == 64) return gemm_dt_tile<DT, 64>(c, g, ws, ws_bytes);
   return gemm_dt_tile<DT, 32>(c, g, ws, ws_bytes);

@@ -130,6 +130,27 @@ def test_gemm_f64_tall_nh(M, K, Nn):
     assert np.array_equal(N(Q.gemm(T(Ai), T(Bi), opA=0, opB=1, compute=Q.F64)), qmul(Ai, qH(Bi)))
 
 
+@pytest.mark.parametrize("M,K,Nn", [(2048, 1024, 400), (2100, 1030, 333), (4096, 4096, 400)])
+@pytest.mark.parametrize("compute", [Q.F32, Q.F64])
+def test_gemm_tall_long_k_plans(M, K, Nn, compute):
+    # tall outputs with a long K take 64 x 80 tiles (FP32) and more K slices:
+    # ragged edges in both directions, bit-exact on small integers
+    rng = np.random.default_rng(M + K + Nn)
+    dt = torch.float64 if compute == Q.F64 else torch.float32
+    Ai = workloads.small_int_quat(M, K, rng, 1)
+    Bi = workloads.small_int_quat(K, Nn, rng, 1)
+    D = Q.gemm(T(Ai, dt), T(Bi, dt), compute=compute)
+    assert np.array_equal(N(D), qmul(Ai, Bi))
+    if M * K <= 4 * 10 ** 6:
+        A = rng.standard_normal((4, M, K))
+        B = rng.standard_normal((4, K, Nn))
+        D0 = rng.standard_normal((4, M, Nn))
+        Dt = T(D0, dt)
+        Q.gemm(T(A, dt), T(B, dt), alpha=0.5, beta=2.0, D=Dt, compute=compute)
+        ref = 0.5 * qmul(N(T(A, dt)), N(T(B, dt))) + 2.0 * N(T(D0, dt))
+        assert rel(N(Dt), ref) < (1e-13 if compute == Q.F64 else 1e-5)
+
+
 @pytest.mark.parametrize("compute,tol", [(Q.F64, 1e-13), (Q.F32, 1e-5), (Q.BF16, 2e-2), (Q.BF16X3, 1e-4)])
 def test_gemm_gaussian_alpha_beta(compute, tol):
     rng = np.random.default_rng(7)
