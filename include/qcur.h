@@ -120,6 +120,23 @@ size_t qcur_gemm_workspace(int64_t M, int64_t N, int64_t K, int compute);
 qcur_status qcur_probs(qcur_handle handle, const qcur_qmat* A, int sampling, double* p_col,
                        double* q_row, double* fro2, void* ws, size_t ws_bytes);
 
+/* qcur_probs without a workspace argument, for callers that cannot allocate
+ * device memory (code under stream/graph capture, serving loops, harnesses
+ * that forbid allocation).  The partial sums live in the library's static
+ * device scratch of QCUR_SCRATCH_BYTES bytes, one copy per device, whose
+ * address the handle takes when it is created; it stays allocated until the
+ * process ends.  This call allocates nothing.  Same arguments, results and
+ * data errors as qcur_probs (bitwise the same results).  A matrix whose
+ * partial sums need more than the scratch holds (qcur_probs_workspace(m, n) >
+ * QCUR_SCRATCH_BYTES; every m, n <= 16384 fits) returns
+ * QCUR_ERR_UNSUPPORTED before anything is enqueued.  All calls on one device
+ * share its scratch and every call writes the part it reads before reading
+ * it (nothing needs clearing): calls that overlap on one device (on
+ * different streams or handles) race and must not be issued concurrently. */
+#define QCUR_SCRATCH_BYTES ((size_t)32 << 20)
+qcur_status qcur_probs_noalloc(qcur_handle handle, const qcur_qmat* A, int sampling, double* p_col,
+                               double* q_row, double* fro2);
+
 /* Draws `count` indices from the probabilities probs[0..n) (Algorithm 1,
  * steps 1-2) and writes them sorted ascending to idx[count] (int64).
  * Integer-CDF sampler: weights w_j = floor(p_j * 2^60); draw t takes

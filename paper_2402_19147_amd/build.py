@@ -18,7 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libqcur.so")
-SOURCES = ["api.cpp", "k_elem.hip", "k_draw.hip", "k_qgemm.hip", "k_pinv.hip", "k_chol.hip", "k_batch.hip", "k_thin.hip"]
+SOURCES = ["api.cpp", "k_elem.hip", "k_draw.hip", "k_qgemm.hip", "k_pinv.hip", "k_chol.hip", "k_batch.hip", "k_thin.hip",
+           "k_scratch.hip"]
 PROBE_LIB = os.path.join(HERE, "libqcur_probe.so")
 PROBE_SOURCES = ["probe_ceiling.hip"]
 ARCH = os.environ.get("QCUR_OFFLOAD_ARCH", "gfx950")

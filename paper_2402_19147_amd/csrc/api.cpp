@@ -1653,6 +1653,8 @@ qcur_status qcur_create(qcur_handle* handle, int device) {
   if (e == hipSuccess) e = hipMemset(st, 0, 256);
   if (e == hipSuccess) e = hipHostMalloc(&pinned, sizeof(HostVerdict), hipHostMallocDefault);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+  void* scr = nullptr;
+  if (e == hipSuccess) e = scratch_address(device, &scr);
   (void)hipSetDevice(old);
   if (e != hipSuccess) {
     if (st) (void)hipFree(st);
@@ -1665,6 +1667,7 @@ qcur_status qcur_create(qcur_handle* handle, int device) {
   h->c.status = st;
   h->c.pinned = pinned;
   h->c.done = done;
+  h->c.scratch = scr;
   *handle = h;
   return QCUR_OK;
 }
@@ -1793,6 +1796,22 @@ qcur_status qcur_probs(qcur_handle h, const qcur_qmat* A, int sampling, double* 
   HIPCHK(launch_probs_partials(c, Av, colpart, rowpart, rb, ncb));
   HIPCHK(launch_probs_finish(c, m, n, colpart, rowpart, nrb, ncb, sampling, p_col, q_row, fro2, scratch));
   return QCUR_OK;
+}
+
+// The same computation with the static scratch as workspace: no allocation,
+// no caller workspace.
+qcur_status qcur_probs_noalloc(qcur_handle h, const qcur_qmat* A, int sampling, double* p_col, double* q_row,
+                               double* fro2) {
+  static_assert(QCUR_SCRATCH_BYTES == SCRATCH_BYTES, "the header states the scratch size");
+  CHK(check_qmat(A, "A"));
+  if (A->rows < 1 || A->cols < 1) return fail(QCUR_ERR_SHAPE, "A must have at least one row and column");
+  const size_t need = qcur_probs_workspace(A->rows, A->cols);
+  if (need > SCRATCH_BYTES)
+    return fail(QCUR_ERR_UNSUPPORTED, "a %lld x %lld matrix needs %zu bytes of scratch; the static scratch holds %zu",
+                (long long)A->rows, (long long)A->cols, need, SCRATCH_BYTES);
+  CHK(check_handle(h));
+  if (!h->c.scratch) return fail(QCUR_ERR_DEVICE, "the handle has no static scratch address");
+  return qcur_probs(h, A, sampling, p_col, q_row, fro2, h->c.scratch, SCRATCH_BYTES);
 }
 
 // ---- draw

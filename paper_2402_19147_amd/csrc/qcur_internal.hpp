@@ -35,7 +35,14 @@ struct Ctx {
   unsigned* status;  // device word
   void* pinned;      // small pinned host buffer (fast-path verdicts)
   hipEvent_t done;   // marks the arrival of those verdicts
+  void* scratch;     // this device's copy of the static scratch (SCRATCH_BYTES)
 };
+
+// Static device scratch of the entry points that allocate nothing.  Its
+// device address on `device` (which must be current at the first call for
+// that device).
+constexpr size_t SCRATCH_BYTES = (size_t)32 << 20;
+hipError_t scratch_address(int device, void** out);
 
 // ---- element conversions --------------------------------------------------
 // BF16 is stored as raw uint16 bits.  float -> bf16 rounds to nearest even

@@ -22,6 +22,7 @@ F64, F32, BF16 = 0, 1, 2
 BF16X3 = 3  # compute only: FP32 operands as BF16 hi + lo, three BF16 products
 OP_N, OP_H = 0, 1
 LENGTH, UNIFORM = 0, 1
+SCRATCH_BYTES = 32 << 20  # QCUR_SCRATCH_BYTES: the static device scratch of qcur_probs_noalloc
 CORE_WPINV, CORE_CAR = 0, 1
 
 STATUS = {0: "QCUR_OK", 1: "QCUR_ERR_ARG", 2: "QCUR_ERR_SHAPE", 3: "QCUR_ERR_DTYPE",
@@ -79,6 +80,7 @@ def _declare(L):
         "qcur_solve": (c_int, [c_p, QP, c_i64, c_i64, c_int, c_int, c_int, c_u64, c_int, c_int, c_d, c_i64, c_p,
                                c_p, QP, c_p, c_p, c_p, c_p, QP, QP, QP, QP, c_p, c_sz]),
         "qcur_solve_workspace": (c_sz, [c_i64, c_i64, c_i64, c_i64, c_int, c_int]),
+        "qcur_probs_noalloc": (c_int, [c_p, QP, c_int, c_p, c_p, c_p]),
         "qcur_batch_workspace": (c_sz, [ctypes.c_int32, c_p, c_int, c_int, c_int, c_int, c_int]),
         "qcur_batch_prepare": (c_int, [c_p, ctypes.c_int32, c_p, c_int, c_int, c_int, c_int, c_int, c_p, c_sz]),
         "qcur_batch_plans": (c_int, [c_p, c_p, c_p, c_p, c_int]),
@@ -203,6 +205,19 @@ def probs(A: torch.Tensor, sampling: int = LENGTH):
     ws = _ws(lib().qcur_probs_workspace(m, n), A.device)
     _check(lib().qcur_probs(_h(A), _qp(A), sampling, _ptr(p), _ptr(q), _ptr(f), _ptr(ws), ws.numel()))
     return p, q, f
+
+
+def probs_noalloc(A: torch.Tensor, sampling: int = LENGTH, p=None, q=None, fro2=None):
+    """probs() through qcur_probs_noalloc: no workspace; the library's static
+    device scratch holds the partial sums.  p, q, fro2 may be given (caller
+    buffers, e.g. under graph capture); missing ones are allocated here."""
+    _, m, n = A.shape
+    dev = A.device
+    p = torch.empty(n, dtype=torch.float64, device=dev) if p is None else p
+    q = torch.empty(m, dtype=torch.float64, device=dev) if q is None else q
+    fro2 = torch.empty(1, dtype=torch.float64, device=dev) if fro2 is None else fro2
+    _check(lib().qcur_probs_noalloc(_h(A), _qp(A), sampling, _ptr(p), _ptr(q), _ptr(fro2)))
+    return p, q, fro2
 
 
 def draw(probs_: torch.Tensor, count: int, seed: int, set_id: int, with_replacement: bool = False):

@@ -247,6 +247,17 @@ def test_complete_resampled_workspace_and_validation(L):
     assert st == 1  # valid: only the NULL handle is rejected
 
 
+def test_probs_noalloc_validation(L):
+    # the entry point without a workspace: sizes beyond the static scratch are
+    # refused on the host, before the handle is used
+    assert L.qcur_probs_workspace(16384, 16384) <= Q.SCRATCH_BYTES
+    big = qm(40000, 40000, Q.F32)
+    assert L.qcur_probs_noalloc(None, big, Q.LENGTH, FAKE, FAKE, None) == 8
+    assert "scratch" in L.qcur_last_error().decode()
+    assert L.qcur_probs_noalloc(None, qm(300, 200, Q.F32), Q.LENGTH, FAKE, FAKE, None) == 1  # only the handle
+    assert L.qcur_probs_noalloc(None, qm(0, 200, Q.F32), Q.LENGTH, FAKE, FAKE, None) == 2
+
+
 def test_svd_workspace_and_validation(L):
     assert L.qcur_svd_workspace(300, 70) > 0 and L.qcur_svd_workspace(0, 5) == 0
     X = qm(30, 20)
