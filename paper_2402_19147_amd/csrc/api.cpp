@@ -1063,8 +1063,8 @@ constexpr int TUNE_MAX_SPLITS = 4;
 struct BatchWs {
   int *dm, *dn, *dc, *dr, *zp, *zq;  // header (uploaded by qcur_batch_prepare)
   double *colpart, *rowpart, *p, *q;
-  Slots Ax, C64, R64, Cx, Rx;
-  double *G, *L, *P1, *P2, *P, *Sch, *Q1, *Q, *norms;
+  Slots Ax;
+  double *Z, *G, *L, *P1, *P2, *P, *Sch, *Q1, *Q, *norms;
   int *fail, *ok;
   double *Y, *V;
   Slots Qcx, Qrx, T, Tx, M, Mx, B1, B1x, E, Ex, M64, W1, U64;
@@ -1109,13 +1109,12 @@ BatchWs batch_carve(Bump& b, const BatchShape& s) {
   w.p = (double*)b.take((size_t)n * s.nx * 8);
   w.q = (double*)b.take((size_t)n * s.mx * 8);
   w.Ax = s.a_dt != idt ? slots_of(b, n, s.mx, s.nx, idt) : Slots{};
-  w.C64 = slots_of(b, n, s.mx, s.cx, QCUR_F64);
-  w.R64 = slots_of(b, n, s.rx, s.nx, QCUR_F64);
-  w.Cx = idt != QCUR_F64 ? slots_of(b, n, s.mx, s.cx, idt) : w.C64;
-  w.Rx = idt != QCUR_F64 ? slots_of(b, n, s.rx, s.nx, idt) : w.R64;
+  // FP64 factor slots: Z_t = C_b (t = b) or R_b^H (t = count + b), px x qx
+  // with qx a multiple of 4 (rows of whole runs for the tall products)
   w.px = std::max(s.mx, s.nx);
-  w.qx = std::max(s.cx, s.rx);
+  w.qx = (std::max(s.cx, s.rx) + 3) / 4 * 4;
   const size_t gsl = (size_t)n2 * 4 * w.qx * w.qx * 8, zsl = (size_t)n2 * 4 * w.px * w.qx * 8;
+  w.Z = (double*)b.take(zsl);
   w.G = (double*)b.take(gsl);
   w.L = (double*)b.take(gsl);
   w.P1 = (double*)b.take(gsl);
@@ -1350,17 +1349,38 @@ qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, Bat
   d.p = p; d.q = q; d.I = a.I; d.J = a.J;
   d.seed = a.seed; d.sampling = s.sampling; d.repl = a.repl;
   HIPCHK(launch_draw_batch(c, n, d));
-  // gathers: C_b = A_b(:, J_b), R_b = A_b(I_b, :)
-  HIPCHK(launch_gather_batch(c, n, a.A, w.dm, w.dn, nullptr, 0, a.J, cx, w.dm, w.dc, mx, cx, w.C64,
-                             idt != QCUR_F64 ? &w.Cx : nullptr));
-  HIPCHK(launch_gather_batch(c, n, a.A, w.dm, w.dn, a.I, rx, nullptr, 0, w.dr, w.dn, rx, nx, w.R64,
-                             idt != QCUR_F64 ? &w.Rx : nullptr));
   // factors of C_b and R_b^H in FP64
   const Slots G = sl(w.G, qx, qx, qx), P1 = sl(w.P1, qx, qx, qx), Q = sl(w.Q, px, qx, qx);
+  const Slots Zs = sl(w.Z, px, qx, qx);
   auto half = [&](const Slots& x) {  // the R_b half of a 2*count array
     Slots y = x;
     y.p = (char*)x.p + (size_t)n * x.slab * dtype_size(x.dt);
     return y;
+  };
+  // gathers straight into the factor slots: Z_b = C_b = A_b(:, J_b) and
+  // Z_{count+b} = R_b^H with R_b = A_b(I_b, :)
+  HIPCHK(launch_gather_batch(c, n, a.A, w.dm, w.dn, nullptr, 0, a.J, cx, w.dm, w.dc, mx, cx, Zs, nullptr, 0));
+  HIPCHK(launch_gather_batch(c, n, a.A, w.dm, w.dn, a.I, rx, nullptr, 0, w.dr, w.dn, rx, nx, half(Zs), nullptr, 1));
+  // Gram matrices and Z P^H products of all 2 count factors run in the
+  // fragment-streaming kernels with per-problem sizes (launch plans fixed:
+  // reported as 16-blocks, not tuned)
+  const QView Zv{w.Z, px, qx, qx, px * qx, QCUR_F64}, Q1v{w.Q1, px, qx, qx, px * qx, QCUR_F64};
+  const QView Qv{w.Q, px, qx, qx, px * qx, QCUR_F64}, Gv{w.G, qx, qx, qx, qx * qx, QCUR_F64};
+  const QView P1v{w.P1, qx, qx, qx, qx * qx, QCUR_F64}, P2v{w.P2, qx, qx, qx, qx * qx, QCUR_F64};
+  const int64_t zslab = 4 * px * qx, gslab = 4 * qx * qx;
+  auto fixed_stage = [&](int id) {
+    if (tu && tu->measure && tu->plan[id].tile == 0) tu->plan[id] = StagePlan{16, 1};
+  };
+  auto gram = [&](const QView& X, int id) -> qcur_status {  // G_t = X_t^H X_t, lower
+    fixed_stage(id);
+    HIPCHK(launch_thin_hn(c, QCUR_F64, 1.0, X, X, 0.0, Gv, px, n2, zslab, zslab, gslab, true, nullptr, 0, w.zq,
+                          w.zq, w.zp));
+    return QCUR_OK;
+  };
+  auto zph = [&](const QView& X, const QView& Pv, const QView& D, int id) -> qcur_status {  // D_t = X_t P_t^H
+    fixed_stage(id);
+    HIPCHK(launch_tall_nh(c, 1.0, X, Pv, 0.0, D, qx, n2, zslab, gslab, zslab, true, w.zp, w.zq, w.zq));
+    return QCUR_OK;
   };
   GroupWs gw{};
   gw.nb = n2;
@@ -1372,37 +1392,30 @@ qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, Bat
   gw.gws = w.gws;
   gw.gws_bytes = w.gws_bytes;
   HIPCHK(launch_zero_i32(c, w.fail, n2));
-  // G = Z^H Z:  C_b^H C_b  and  R_b R_b^H
-  CHK(stage(BS_GRAM_C, QCUR_OP_H, QCUR_OP_N, 1.0, slot_view(w.C64, mx, cx), slot_view(w.C64, mx, cx), 0.0,
-                             slot_view(G, cx, cx), QCUR_F64, bspec(n, w.C64, w.C64, G, w.dc, w.dc, w.dm, TRI_LOWER_OUT)));
-  CHK(stage(BS_GRAM_R, QCUR_OP_N, QCUR_OP_H, 1.0, slot_view(w.R64, rx, nx), slot_view(w.R64, rx, nx), 0.0,
-                             slot_view(half(G), rx, rx), QCUR_F64, bspec(n, w.R64, w.R64, G, w.dr, w.dr, w.dn, TRI_LOWER_OUT)));
+  // G = Z^H Z:  C_b^H C_b  and  R_b R_b^H, one launch
+  CHK(gram(Zv, BS_GRAM_C));
+  fixed_stage(BS_GRAM_R);
   HIPCHK(launch_pad_gram_batch(c, n2, w.G, qx, G.slab, w.zq));
   CHK(chol_inv(c, gw, w.P1));
-  HIPCHK(launch_sumsq_ragged(c, n, w.C64, w.dm, w.dc, w.norms, 4));
-  HIPCHK(launch_sumsq_ragged(c, n, w.R64, w.dr, w.dn, w.norms + 4 * n, 4));
+  HIPCHK(launch_sumsq_ragged(c, n2, Zs, w.zp, w.zq, w.norms, 4));
   HIPCHK(launch_sumsq_ragged(c, n2, P1, w.zq, w.zq, w.norms + 1, 4));
-  // Q1 = Z P1^H:  C_b P1^H  and  R_b^H P1^H.  The second pass (CholeskyQR2)
-  // runs for every product dtype: one pass leaves Q1^H Q1 - I near
-  // eps kappa^2, which the orthonormal form would carry into C U R.
+  // Q1 = Z P1^H:  C_b P1^H  and  R_b^H P1^H, one launch.  The second pass
+  // (CholeskyQR2) runs for every product dtype: one pass leaves Q1^H Q1 - I
+  // near eps kappa^2, which the orthonormal form would carry into C U R.
   const bool two = true;
   const Slots Q1 = two ? sl(w.Q1, px, qx, qx) : Q;
-  CHK(stage(BS_Q1_C, QCUR_OP_N, QCUR_OP_H, 1.0, slot_view(w.C64, mx, cx), slot_view(P1, cx, cx), 0.0,
-                             slot_view(Q1, mx, cx), QCUR_F64, bspec(n, w.C64, P1, Q1, w.dm, w.dc, w.dc, TRI_B_UPPER)));
-  CHK(stage(BS_Q1_R, QCUR_OP_H, QCUR_OP_H, 1.0, slot_view(w.R64, rx, nx), slot_view(half(P1), rx, rx),
-                             0.0, slot_view(half(Q1), nx, rx), QCUR_F64, bspec(n, w.R64, P1, Q1, w.dn, w.dr, w.dr, TRI_B_UPPER)));
+  CHK(zph(Zv, P1v, two ? Q1v : Qv, BS_Q1_C));
+  fixed_stage(BS_Q1_R);
   Slots Pf = P1;
   if (two) {
     // CholeskyQR2: Q1^H Q1 = L2 L2^H, P = P2 P1, Q = Q1 P2^H
     const Slots P2 = sl(w.P2, qx, qx, qx), P = sl(w.P, qx, qx, qx);
-    CHK(stage(BS_G2, QCUR_OP_H, QCUR_OP_N, 1.0, slot_view(Q1, px, qx), slot_view(Q1, px, qx), 0.0,
-                               slot_view(G, qx, qx), QCUR_F64, bspec(n2, Q1, Q1, G, w.zq, w.zq, w.zp, TRI_LOWER_OUT)));
+    CHK(gram(Q1v, BS_G2));
     HIPCHK(launch_pad_gram_batch(c, n2, w.G, qx, G.slab, w.zq));
     CHK(chol_inv(c, gw, w.P2));
     CHK(stage(BS_P, QCUR_OP_N, QCUR_OP_N, 1.0, slot_view(P2, qx, qx), slot_view(P1, qx, qx), 0.0,
                                slot_view(P, qx, qx), QCUR_F64, bspec(n2, P2, P1, P, w.zq, w.zq, w.zq, TRI_A_LOWER | TRI_B_LOWER)));
-    CHK(stage(BS_Q, QCUR_OP_N, QCUR_OP_H, 1.0, slot_view(Q1, px, qx), slot_view(P2, qx, qx), 0.0,
-                               slot_view(Q, px, qx), QCUR_F64, bspec(n2, Q1, P2, Q, w.zp, w.zq, w.zq, TRI_B_UPPER)));
+    CHK(zph(Q1v, P2v, Qv, BS_Q));
     Pf = P;
   }
   HIPCHK(launch_sumsq_ragged(c, n2, Pf, w.zq, w.zq, w.norms + 2, 4));
@@ -1412,8 +1425,8 @@ qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, Bat
     // problems whose certificate failed: Jacobi SVD, same (Q, P) form
     JacobiBatch jb{};
     jb.ok = w.ok;
-    jb.Cz = (const double*)w.C64.p; jb.cld = w.C64.ld; jb.cps = w.C64.ps; jb.cslab = w.C64.slab;
-    jb.Rz = (const double*)w.R64.p; jb.rld = w.R64.ld; jb.rps = w.R64.ps; jb.rslab = w.R64.slab;
+    jb.Cz = w.Z; jb.cld = qx; jb.cps = px * qx; jb.cslab = zslab;
+    jb.Rz = nullptr;  // both halves are tall slots of Z
     jb.dm = w.dm; jb.dn = w.dn; jb.dc = w.dc; jb.dr = w.dr;
     jb.Y = w.Y; jb.V = w.V;
     jb.yslab = 4 * px * qx;

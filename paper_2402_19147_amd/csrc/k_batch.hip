@@ -130,7 +130,7 @@ __global__ __launch_bounds__(256) void kb_gather(const TI* __restrict__ A, int64
                                                  const int* __restrict__ orows, const int* __restrict__ ocols,
                                                  double* __restrict__ O, int64_t ldo, int64_t pso, int64_t so,
                                                  TX* __restrict__ Ox, int64_t ldx, int64_t psx, int64_t sx,
-                                                 unsigned* status) {
+                                                 int tconj, unsigned* status) {
   const int b = blockIdx.z;
   const int64_t rows = orows[b], cols = ocols[b];
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -143,13 +143,14 @@ __global__ __launch_bounds__(256) void kb_gather(const TI* __restrict__ A, int64
     const bool ok = i >= 0 && i < m && j >= 0 && j < n;
     if (!ok) atomicOr(status, ST_ARG);
     const int64_t src = i * lda + j;
-    const int64_t dst = s * ldo + t, dx = s * ldx + t;
+    // tconj: O receives the conjugate transpose (element (t, s), planes 1..3 negated)
+    const int64_t dst = tconj ? t * ldo + s : s * ldo + t, dx = s * ldx + t;
     bool finite = true;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const double v = ok ? ld_d(Ab, src + k * psa) : 0.0;
       finite &= isfinite(v);
-      O[(int64_t)b * so + dst + k * pso] = v;
+      O[(int64_t)b * so + dst + k * pso] = (tconj && k > 0) ? -v : v;
       if (Ox) st_d(Ox + (int64_t)b * sx, dx + k * psx, v);
     }
     if (!finite) atomicOr(status, ST_NUMERIC);
@@ -159,7 +160,7 @@ __global__ __launch_bounds__(256) void kb_gather(const TI* __restrict__ A, int64
 hipError_t launch_gather_batch(const Ctx& c, int count, Slots A, const int* dm, const int* dn,
                                const int64_t* ridx, int64_t ris, const int64_t* cidx, int64_t cis,
                                const int* orows, const int* ocols, int64_t rowsx, int64_t colsx, Slots O,
-                               const Slots* Ox) {
+                               const Slots* Ox, int tconj) {
   if (count <= 0 || rowsx <= 0 || colsx <= 0) return hipSuccess;
   const dim3 grid((unsigned)((colsx + 255) / 256), (unsigned)std::min<int64_t>(rowsx, 1024), (unsigned)count);
   return by_dtype(A.dt, [&](auto* ti) {
@@ -170,7 +171,7 @@ hipError_t launch_gather_batch(const Ctx& c, int count, Slots A, const int* dm, 
       hipLaunchKernelGGL((kb_gather<TI, TX>), grid, dim3(256), 0, c.stream, (const TI*)A.p, A.ld, A.ps, A.slab,
                          dm, dn, ridx, ris, cidx, cis, orows, ocols, (double*)O.p, O.ld, O.ps, O.slab,
                          Ox ? (TX*)Ox->p : (TX*)nullptr, Ox ? Ox->ld : 0, Ox ? Ox->ps : 0, Ox ? Ox->slab : 0,
-                         c.status);
+                         tconj, c.status);
     });
   });
 }

@@ -481,7 +481,8 @@ namespace qcur {
 // singular values and 0 otherwise, Q[:, k] = Y_k s_k (orthonormal or zero
 // columns) and P[k][a] = conj(V_{a,k}) s_k, so that P^H Q^H = V D Y^H.
 // Problem t < count is C_b (m_b x c_b, Z = C_b); t >= count is R_b
-// (r_b x n_b), handled as Z = R_b^H.
+// (r_b x n_b), handled as Z = R_b^H.  With jb.Rz NULL both halves are read
+// from the tall slots jb.Cz (slot t holds Z_t itself, R_b^H for t >= count).
 __global__ __launch_bounds__(1024) void kb_jacobi_pinv(JacobiBatch jb) {
   const int t = blockIdx.x;
   if (jb.ok[t]) return;  // uniform over the workgroup
@@ -501,8 +502,8 @@ __global__ __launch_bounds__(1024) void kb_jacobi_pinv(JacobiBatch jb) {
   // Y[a][i] = Z[i][a]
   for (int64_t e = tid; e < q * p; e += 1024) {
     const int64_t a = e / p, i = e % p;
-    if (isC) {
-      const double* src = jb.Cz + (int64_t)b * jb.cslab + i * jb.cld + a;
+    if (isC || !jb.Rz) {
+      const double* src = jb.Cz + (int64_t)(jb.Rz ? b : t) * jb.cslab + i * jb.cld + a;
 #pragma unroll
       for (int k = 0; k < 4; ++k) Y[e + k * psy] = src[k * jb.cps];
     } else {

@@ -45,9 +45,11 @@ struct ThinArgs {
   int64_t ldb, psb, sB;
   void* D;  // D itself, or the partial slabs when splits > 1
   int64_t ldd, psd, sD;
-  int64_t M, N, K;
+  int64_t M, N, K;  // grid extents (the largest problem of a batch)
   double alpha, beta;
   int splits;
+  // batches of uneven problems: problem b's own M, N, K (NULL: the extents)
+  const int *bM, *bN, *bK;
 };
 
 // per dtype: element, accumulator vector, MFMA 16x16x4 and the row of
@@ -94,8 +96,12 @@ __global__ __launch_bounds__(256) void k_thin_hn(ThinArgs g, int nblocks, int ba
     bi = t / nbj;
     bj = t % nbj;
   }
-  const int64_t M = g.M, N = g.N, K = g.K;
+  const int64_t M = g.bM ? (int64_t)g.bM[b] : g.M, N = g.bN ? (int64_t)g.bN[b] : g.N;
+  const int64_t K = g.bK ? (int64_t)g.bK[b] : g.K;
   const int64_t i0 = (int64_t)bi * 16, j0 = (int64_t)bj * 16;
+  // a block outside its problem (uniform over the workgroup; only with
+  // per-problem sizes, where the K split is not used) stores nothing
+  if (i0 >= M || j0 >= N) return;
   // this wave's k-steps (four rows of K each): a quarter of the split's share
   const int64_t ksteps = (K + 3) / 4;
   const int64_t per_split = (ksteps + splits - 1) / splits;
@@ -258,6 +264,9 @@ struct TallArgs {
   int64_t M, N, K;
   double alpha, beta;
   int b_upper;  // op(B) upper triangular: column j meets k <= j only
+  // batches of uneven problems: problem b's own M, N, K (NULL: the extents);
+  // then K need not be a multiple of 4 (elements at k >= K are zeroed)
+  const int *bM, *bN, *bK;
 };
 
 typedef double f64x2 __attribute__((ext_vector_type(2)));
@@ -269,8 +278,10 @@ __global__ __launch_bounds__(256) void k_tall_nh(TallArgs g, int nbi, int nbj) {
   const int b = t / (nbj * ngi), rem = t % (nbj * ngi);
   const int bj = rem / ngi, bi = (rem % ngi) * 4 + wave;
   if (bi >= nbi) return;  // no barrier follows: the wave may leave
-  const int64_t M = g.M, N = g.N, K = g.K;
+  const int64_t M = g.bM ? (int64_t)g.bM[b] : g.M, N = g.bN ? (int64_t)g.bN[b] : g.N;
+  const int64_t K = g.bK ? (int64_t)g.bK[b] : g.K;
   const int64_t i0 = (int64_t)bi * 16, j0 = (int64_t)bj * 16;
+  if (i0 >= M || j0 >= N || K <= 0) return;  // outside its problem
   const int64_t kend = g.b_upper ? std::min(K, j0 + 16) : K;
   const int64_t nch = (kend + 15) / 16;
   const int r = lane & 15, kg = 4 * (lane >> 4);
@@ -280,8 +291,13 @@ __global__ __launch_bounds__(256) void k_tall_nh(TallArgs g, int nbi, int nbj) {
   // runs starting at or past K (or past kend) read the row's last run and
   // are zeroed in A
   double ra[2][4][4], rb[2][4][4];
+  // runs of four k are read from in-range addresses: the last run of a row
+  // of the extents' width (a multiple of 4), so with per-problem K the
+  // elements at k >= K of a straddling run are read from the slot's padding
+  // and zeroed below
+  const int64_t Kx = g.K;
   auto load_chunk = [&](int buf, int64_t ch) {
-    const int64_t k = std::min(16 * ch + kg, K - 4);
+    const int64_t k = std::min(16 * ch + kg, Kx - 4);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const f64x2 a01 = *(const f64x2*)(pa + q * g.psa + k), a23 = *(const f64x2*)(pa + q * g.psa + k + 2);
@@ -301,9 +317,9 @@ __global__ __launch_bounds__(256) void k_tall_nh(TallArgs g, int nbi, int nbj) {
 #pragma unroll
   for (int p = 0; p < 4; ++p) acc[p] = (f64x4){0, 0, 0, 0};
   auto compute_chunk = [&](int buf, int64_t ch) {
-    const bool ok = ch < nch && 16 * ch + kg < kend;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
+      const bool ok = ch < nch && 16 * ch + kg + s < kend;
       const double a0 = ok ? ra[buf][0][s] : 0.0, a1 = ok ? ra[buf][1][s] : 0.0;
       const double a2 = ok ? ra[buf][2][s] : 0.0, a3 = ok ? ra[buf][3][s] : 0.0;
       const double n0 = -a0, n1 = -a1, n2 = -a2, n3 = -a3;
@@ -361,7 +377,7 @@ bool thin_hn_applies(int compute, int opA, int opB, int64_t M, int64_t N, int64_
 template <typename E>
 static hipError_t launch_thin_dt(const Ctx& c, double alpha, QView A, QView B, double beta, QView D, int64_t K,
                                  int batch, int64_t sA, int64_t sB, int64_t sD, bool lower_only, void* ws,
-                                 size_t ws_bytes) {
+                                 size_t ws_bytes, const int* bM, const int* bN, const int* bK) {
   const int64_t M = D.rows, N = D.cols;
   const int nbi = (int)((M + 15) / 16), nbj = (int)((N + 15) / 16);
   const int64_t blocks = lower_only ? (int64_t)nbi * (nbi + 1) / 2 : (int64_t)nbi * nbj;
@@ -372,7 +388,11 @@ static hipError_t launch_thin_dt(const Ctx& c, double alpha, QView A, QView B, d
   splits = std::min<int64_t>(splits, 32);
   const size_t need = (size_t)batch * splits * 4 * (size_t)M * (size_t)N * sizeof(E);
   if (splits > 1 && (ws == nullptr || ws_bytes < need)) splits = 1;
+  if (bM || bN || bK) splits = 1;  // per-problem sizes: no K split
   ThinArgs g;
+  g.bM = bM;
+  g.bN = bN;
+  g.bK = bK;
   g.A = A.p;
   g.lda = A.ld;
   g.psa = A.ps;
@@ -401,10 +421,11 @@ static hipError_t launch_thin_dt(const Ctx& c, double alpha, QView A, QView B, d
 }
 
 hipError_t launch_thin_hn(const Ctx& c, int compute, double alpha, QView A, QView B, double beta, QView D, int64_t K,
-                          int batch, int64_t sA, int64_t sB, int64_t sD, bool lower_only, void* ws, size_t ws_bytes) {
+                          int batch, int64_t sA, int64_t sB, int64_t sD, bool lower_only, void* ws, size_t ws_bytes,
+                          const int* bM, const int* bN, const int* bK) {
   if (compute == QCUR_F32)
-    return launch_thin_dt<float>(c, alpha, A, B, beta, D, K, batch, sA, sB, sD, lower_only, ws, ws_bytes);
-  return launch_thin_dt<double>(c, alpha, A, B, beta, D, K, batch, sA, sB, sD, lower_only, ws, ws_bytes);
+    return launch_thin_dt<float>(c, alpha, A, B, beta, D, K, batch, sA, sB, sD, lower_only, ws, ws_bytes, bM, bN, bK);
+  return launch_thin_dt<double>(c, alpha, A, B, beta, D, K, batch, sA, sB, sD, lower_only, ws, ws_bytes, bM, bN, bK);
 }
 
 bool tall_nh_applies(int compute, int opA, int opB, QView A, QView B, int64_t M, int64_t N, int64_t K, int tri,
@@ -417,10 +438,14 @@ bool tall_nh_applies(int compute, int opA, int opB, QView A, QView B, int64_t M,
 }
 
 hipError_t launch_tall_nh(const Ctx& c, double alpha, QView A, QView B, double beta, QView D, int64_t K, int batch,
-                          int64_t sA, int64_t sB, int64_t sD, bool b_upper) {
+                          int64_t sA, int64_t sB, int64_t sD, bool b_upper, const int* bM, const int* bN,
+                          const int* bK) {
   const int64_t M = D.rows, N = D.cols;
   const int nbi = (int)((M + 15) / 16), nbj = (int)((N + 15) / 16);
   TallArgs g;
+  g.bM = bM;
+  g.bN = bN;
+  g.bK = bK;
   g.A = (const double*)A.p;
   g.lda = A.ld;
   g.psa = A.ps;

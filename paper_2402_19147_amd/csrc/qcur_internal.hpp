@@ -123,17 +123,23 @@ size_t gemm_workspace(int64_t M, int64_t N, int64_t K, int compute, int batch = 
 // memory.  Needs no more workspace than gemm_workspace gives the tiled plan
 // (fewer K splits); lower_only computes the blocks on and below the diagonal.
 bool thin_hn_applies(int compute, int opA, int opB, int64_t M, int64_t N, int64_t K, int tri, bool per_problem_dims);
+// With bM / bN / bK (device int[batch], may be NULL) problem b has its own
+// M, N, K within the extents (D.rows, D.cols, K); no K split then.
 hipError_t launch_thin_hn(const Ctx& c, int compute, double alpha, QView A, QView B, double beta, QView D,
                           int64_t K, int batch, int64_t sA, int64_t sB, int64_t sD, bool lower_only, void* ws,
-                          size_t ws_bytes);
+                          size_t ws_bytes, const int* bM = nullptr, const int* bN = nullptr,
+                          const int* bK = nullptr);
 // Tall FP64 products D = alpha A B^H + beta D with both operands contiguous
 // in k (M >= 512, N <= 256, K <= 256 a multiple of 4, 16-byte aligned rows;
 // equal sizes over a batch; op(B) may be upper triangular): one wave per
 // 16 x 16 block of D over the whole K range, no workspace.
 bool tall_nh_applies(int compute, int opA, int opB, QView A, QView B, int64_t M, int64_t N, int64_t K, int tri,
                      bool per_problem_dims, int64_t sA, int64_t sB);
+// With bM / bN / bK as for launch_thin_hn; the extent K must be a multiple
+// of 4 and the operands' rows hold at least that many elements.
 hipError_t launch_tall_nh(const Ctx& c, double alpha, QView A, QView B, double beta, QView D, int64_t K, int batch,
-                          int64_t sA, int64_t sB, int64_t sD, bool b_upper);
+                          int64_t sA, int64_t sB, int64_t sD, bool b_upper, const int* bM = nullptr,
+                          const int* bN = nullptr, const int* bK = nullptr);
 // Workspace for any plan with at most max_splits K slices.
 size_t gemm_workspace_splits(int64_t M, int64_t N, int compute, int batch, int max_splits);
 hipError_t launch_gemm(const Ctx& c, int opA, int opB, double alpha, QView A, QView B, double beta,
@@ -265,7 +271,7 @@ hipError_t launch_draw_batch(const Ctx& c, int count, const DrawBatch& d);
 hipError_t launch_gather_batch(const Ctx& c, int count, Slots A, const int* dm, const int* dn,
                                const int64_t* ridx, int64_t ris, const int64_t* cidx, int64_t cis,
                                const int* orows, const int* ocols, int64_t rowsx, int64_t colsx, Slots O,
-                               const Slots* Ox);
+                               const Slots* Ox, int tconj = 0);
 hipError_t launch_cast_batch(const Ctx& c, int count, Slots X, Slots Y, const int* rows, const int* cols,
                              int64_t rowsx, int64_t colsx, int mode);
 hipError_t launch_pad_gram_batch(const Ctx& c, int count, double* G, int64_t n, int64_t slab, const int* zq);
