@@ -315,7 +315,16 @@ struct PinvSpec {
   int nb = 0;
   bool adaptive = false;
   double orth_tol = 0.0;
+  void* dev_dst = nullptr;  // when set: the verdict is copied there (device), not to the pinned buffer
 };
+
+// Whether a verdict confirms the fast path (as pinv_spec_resolve decides).
+bool verdict_valid(const PinvSpec& spec, const int* ok, const double* nrm) {
+  bool valid = true;
+  for (int b = 0; b < spec.nb; ++b)
+    valid = valid && ok[b] && (!spec.adaptive || nrm[4 * b + 3] <= spec.orth_tol * spec.orth_tol);
+  return valid;
+}
 
 // Did the pending verdict confirm the fast path?  Waits for it.
 qcur_status pinv_spec_resolve(const Ctx& c, const PinvSpec& spec, bool* valid) {
@@ -323,10 +332,10 @@ qcur_status pinv_spec_resolve(const Ctx& c, const PinvSpec& spec, bool* valid) {
   if (!spec.pending) return QCUR_OK;
   HIPCHK(hipEventSynchronize(c.done));
   const HostVerdict* hv = (const HostVerdict*)c.pinned;
-  for (int b = 0; b < spec.nb; ++b)
-    *valid = *valid && hv->ok[b] && (!spec.adaptive || hv->nrm[4 * b + 3] <= spec.orth_tol * spec.orth_tol);
+  *valid = verdict_valid(spec, hv->ok, hv->nrm);
   return QCUR_OK;
 }
+
 
 qcur_status pinv_fast_group(const Ctx& c, int nb, const QView* X, double rtol, int64_t max_rank, const QView* Xp,
                             int64_t* const* rank_out, GroupWs& w, int passes, bool* done, double orth_tol = 0.0,
@@ -398,8 +407,12 @@ qcur_status pinv_fast_group(const Ctx& c, int nb, const QView* X, double rtol, i
   // to pinned memory and return the fast path's factors without waiting
   auto decide_async = [&](bool adaptive, int fp) -> qcur_status {
     HIPCHK(launch_pinv_decide(c, w.norms, w.fail, rtol, max_rank, nb, qb, rank_out, w.ok));
-    HIPCHK(hipMemcpyAsync(c.pinned, w.verdict, sizeof(DevVerdict), hipMemcpyDeviceToHost, c.stream));
-    HIPCHK(hipEventRecord(c.done, c.stream));
+    if (spec->dev_dst) {
+      HIPCHK(hipMemcpyAsync(spec->dev_dst, w.verdict, sizeof(DevVerdict), hipMemcpyDeviceToDevice, c.stream));
+    } else {
+      HIPCHK(hipMemcpyAsync(c.pinned, w.verdict, sizeof(DevVerdict), hipMemcpyDeviceToHost, c.stream));
+      HIPCHK(hipEventRecord(c.done, c.stream));
+    }
     spec->pending = true;
     spec->nb = nb;
     spec->adaptive = adaptive;
@@ -1518,8 +1531,10 @@ struct CompleteArgs {
 // index sets I, J, least-squares core in orthonormal form) and
 // X^{t+1} = P_Omega(Y) + P_Omega^c(M^{t+1}) in one fused product, until
 // ||X^{t+1} - X^t||_F / ||X^t||_F <= tol or max_iter steps.  The iterates
-// alternate between the output X and one workspace copy; the last one is
-// left in X.
+// alternate between the output X and one workspace copy (with fixed index
+// sets and cheap steps they rotate through a ring of workspace copies, so
+// that several steps run between host round trips); the last one is left
+// in X.
 qcur_status complete_run(const Ctx& c, const CompleteArgs& a, Bump& b, bool count_only) {
   const int64_t m = a.Y.rows, n = a.Y.cols, r = a.r, cc = a.cc;
   const int xdt = a.X.dt, idt = in_dt(a.compute), adt = acc_dt(a.compute);
@@ -1551,14 +1566,131 @@ qcur_status complete_run(const Ctx& c, const CompleteArgs& a, Bump& b, bool coun
   double* colpart = pass ? (double*)b.take((size_t)nrb * n * 8) : nullptr;
   double* rowpart = pass ? (double*)b.take((size_t)ncb * m * 8) : nullptr;
   double* f2 = a.resample ? (double*)b.take(8) : nullptr;
+  const bool speculate = 32.0 * (double)m * (double)n * (double)r <= 4e10;
+  // Fixed index sets and cheap steps: up to CHUNK steps are enqueued between
+  // host round trips.  Each step leaves its certificate verdict, stopping
+  // sums and a copy of the status word in a device record; the iterates go to
+  // a ring of chunk + 1 buffers (X itself, Xw and more), so that the host,
+  // reading the chunk's records at once, can take the iterate of the first
+  // step that meets the stopping rule, or go back to the step before a
+  // rejected certificate and redo it without speculation.  Steps enqueued
+  // past the one that stands are discarded, and so are the status bits they
+  // raised.  The ring is held to about 512 MiB.
+  constexpr int CHUNK = 8;
+  struct StepRec {
+    DevVerdict v;
+    double sums[2];
+    unsigned st;
+  };
+  const bool chunked = speculate && !a.resample;
+  const size_t xbytes = (size_t)4 * m * n * dtype_size(xdt);
+  const int chunk = chunked ? (int)std::clamp<size_t>(((size_t)512 << 20) / std::max<size_t>(xbytes, 1), 2, CHUNK) : 0;
+  QView ring[CHUNK + 1];
+  StepRec* recs = nullptr;
+  if (chunked) {
+    ring[0] = a.X;
+    ring[1] = Xw;
+    for (int k = 2; k <= chunk; ++k) ring[k] = b.mat(m, n, xdt);
+    recs = (StepRec*)b.take(sizeof(StepRec) * (CHUNK + 1));
+  }
   if (count_only) return QCUR_OK;
   HIPCHK(launch_mask_init(c, a.Y, a.mask, a.mask_ld, a.X));
   // the iterate of step t lives in cur; the next goes to nxt
   QView cur = a.X, nxt = Xw;
   const double orth_tol = a.compute == QCUR_F64 ? 0.0 : a.compute == QCUR_BF16 ? 0x1p-12 : 0x1p-26;
-  const bool speculate = 32.0 * (double)m * (double)n * (double)r <= 4e10;
   int t = 0;
   double rel = INFINITY;
+  // one step X^t (cur) -> X^{t+1} (nxt); with spec, the certificate's verdict
+  // is left pending (in the device record spec->dev_dst when that is set)
+  auto step = [&](QView from, QView to, double* sums_to, PinvSpec* spec) -> qcur_status {
+    HIPCHK(launch_gather(c, from, a.I, r, a.J, cc, &C, &R, nullptr));
+    QView Qv[2], Pv[2];
+    QView xs[2] = {C, R};
+    int64_t* ro[2] = {ranks, ranks + 1};
+    CHK(pinv_group_qp(c, 2, xs, a.rtol, a.max_rank, ro, gw, jw, Qv, Pv, orth_tol, spec));
+    const QView cs[3] = {Qv[0], Qv[1], from}, cd[3] = {Qc, Qr, Xx};
+    const int cm[3] = {CAST_COPY, CAST_COPY, CAST_COPY};
+    HIPCHK(launch_cast_set(c, Xx.p ? 3 : 2, cs, cd, cm));
+    const QView Xin = Xx.p ? Xx : from;
+    HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Xin, Qr, 0.0, T, a.compute, gws, gwb));
+    if (Tx.p != T.p) HIPCHK(launch_cast(c, T, Tx, CAST_COPY));
+    HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, Qc, Tx, 0.0, M, a.compute, gws, gwb));
+    if (Mx.p != M.p) HIPCHK(launch_cast(c, M, Mx, CAST_COPY));
+    HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Qc, Mx, 0.0, B1, a.compute, gws, gwb));
+    if (B1x.p != B1.p) HIPCHK(launch_cast(c, B1, B1x, CAST_COPY));
+    HIPCHK(launch_merge_gemm(c, a.Y, a.mask, a.mask_ld, from, B1x, Qr, QCUR_OP_H, a.compute, to, pd, po));
+    HIPCHK(launch_sum_partials(c, pd, tiles, sums_to, 0));
+    HIPCHK(launch_sum_partials(c, po, tiles, sums_to + 1, 0));
+    return QCUR_OK;
+  };
+  auto rel_of = [](const double* h2) {
+    return h2[1] > 0.0 ? std::sqrt(h2[0] / h2[1]) : (h2[0] > 0.0 ? INFINITY : 0.0);
+  };
+  if (chunked) {
+    const int ring_n = chunk + 1;
+    StepRec* const base = recs + CHUNK;  // status word before the chunk
+    int slot = 0;                         // ring slot of X^t
+    int hold = 0;   // steps still to run one at a time after a rejection
+    int fails = 0;  // chunks rejected in a row
+    bool stop = false;
+    while (t < a.max_iter && !stop) {
+      if (hold > 0) {
+        // one step with the host waiting for the certificate's verdict
+        // (Jacobi when it fails): after a rejection the next ones are
+        // likely rejected too, and a rejected chunk costs up to a chunk of
+        // steps; the hold doubles with every chunk rejected in a row
+        StepRec h1;
+        CHK(step(ring[slot], ring[(slot + 1) % ring_n], recs[0].sums, nullptr));
+        HIPCHK(hipMemcpyAsync(h1.sums, recs[0].sums, sizeof(h1.sums), hipMemcpyDeviceToHost, c.stream));
+        HIPCHK(hipStreamSynchronize(c.stream));
+        rel = rel_of(h1.sums);
+        ++t;
+        --hold;
+        slot = (slot + 1) % ring_n;
+        stop = rel <= a.tol;
+        continue;
+      }
+      const int kc = std::min(chunk, a.max_iter - t);
+      bool pending[CHUNK];
+      PinvSpec specs[CHUNK];
+      HIPCHK(hipMemcpyAsync(&base->st, c.status, sizeof(unsigned), hipMemcpyDeviceToDevice, c.stream));
+      for (int s = 0; s < kc; ++s) {
+        specs[s].dev_dst = &recs[s].v;
+        CHK(step(ring[(slot + s) % ring_n], ring[(slot + s + 1) % ring_n], recs[s].sums, &specs[s]));
+        HIPCHK(hipMemcpyAsync(&recs[s].st, c.status, sizeof(unsigned), hipMemcpyDeviceToDevice, c.stream));
+        pending[s] = specs[s].pending;
+      }
+      StepRec host[CHUNK];
+      HIPCHK(hipMemcpyAsync(host, recs, sizeof(StepRec) * kc, hipMemcpyDeviceToHost, c.stream));
+      HIPCHK(hipStreamSynchronize(c.stream));
+      int done = kc;  // steps of the chunk that stand
+      for (int s = 0; s < kc; ++s) {
+        if (pending[s] && !verdict_valid(specs[s], host[s].v.ok, host[s].v.nrm)) {
+          done = s;
+          hold = chunk << std::min(fails++, 5);
+          break;
+        }
+        rel = rel_of(host[s].sums);
+        if (rel <= a.tol) {
+          done = s + 1;
+          stop = true;
+          break;
+        }
+      }
+      if (hold == 0) fails = 0;
+      // the status word as the last standing step left it
+      if (done < kc) {
+        const unsigned* keep = done == 0 ? &base->st : &recs[done - 1].st;
+        HIPCHK(hipMemcpyAsync(c.status, keep, sizeof(unsigned), hipMemcpyDeviceToDevice, c.stream));
+      }
+      t += done;
+      slot = (slot + done) % ring_n;
+    }
+    if (slot != 0) HIPCHK(launch_cast(c, ring[slot], a.X, CAST_COPY));
+    if (a.iters) *a.iters = t;
+    if (a.rel) *a.rel = rel;
+    return QCUR_OK;
+  }
   while (t < a.max_iter) {
     if (a.resample) {
       // step t draws J (set 0) and I (set 1) from the probabilities of X^t

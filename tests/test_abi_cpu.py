@@ -223,7 +223,9 @@ def test_sample_size_matches_checker(L):
 
 def test_complete_resampled_workspace_and_validation(L):
     ws = L.qcur_complete_resampled_workspace(512, 768, 60, 60, Q.LENGTH, Q.F32)
-    assert ws > L.qcur_complete_workspace(512, 768, 60, 60, Q.F32) > 0
+    assert ws > 0
+    # fixed index sets: the iterates of several steps in flight at once
+    assert L.qcur_complete_workspace(512, 768, 60, 60, Q.F32) > 8 * 4 * 512 * 768 * 4
     assert L.qcur_complete_resampled_workspace(0, 768, 60, 60, Q.LENGTH, Q.F32) == 0
     Y, X = qm(50, 40, Q.F32), qm(50, 40, Q.F32)
 

@@ -63,6 +63,24 @@ def test_fixed_steps_match_checker(compute, tol):
     assert np.array_equal(Xg[keep], Yc[keep])
 
 
+def test_stop_between_host_round_trips_matches_checker():
+    # Several steps run between host round trips; the stopping rule must
+    # still take the first step that meets it (here step 11, inside the
+    # second group of steps) and leave that step's iterate in X.
+    A, Y, mask, I, J = problem(150, 130, 4, 0.5, 12, seed=34, noise=1e-3)
+    rels = [ref_complete(Y, mask, I, J, max_iter=t, tol=0.0)["rel"] for t in range(1, 12)]
+    assert rels[10] < 0.99 * min(rels[:10])
+    tol = float(np.sqrt(rels[10] * min(rels[:10])))
+    ref = ref_complete(Y, mask, I, J, max_iter=100, tol=tol)
+    assert ref["iters"] == 11
+    X, iters, rel = Q.complete(T(Y), T(mask, torch.uint8), T(I, torch.int64), T(J, torch.int64), compute=Q.F64,
+                               max_iter=100, tol=tol)
+    Q.sync_status()
+    assert iters == 11
+    assert abs(rel - ref["rel"]) <= 1e-9 * ref["rel"]
+    assert np.sqrt(fro2(N(X) - ref["X"]) / fro2(ref["X"])) < 1e-9
+
+
 def test_exact_recovery_with_observed_cross():
     A, Y, mask, I, J = problem(130, 110, 3, 0.25, 8, seed=32, full_cross=True)
     X, iters, rel = Q.complete(T(Y), T(mask, torch.uint8), T(I, torch.int64), T(J, torch.int64), compute=Q.F64,
