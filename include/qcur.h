@@ -363,9 +363,15 @@ qcur_status qcur_solve_batched(qcur_handle handle, int32_t count, const int32_t*
  * FP32) receives the last iterate.  rtol and max_rank (the predefined rank
  * k) apply to the pseudoinverses.  iters (host int, may be NULL): steps
  * taken; rel (host double, may be NULL): the last relative change.
- * Synchronises with the host once per step (the stopping test) and once for
- * the pseudoinverses' certificate (after the step's products when they are
- * cheap, as in qcur_approx).  ws: qcur_complete_workspace(m, n, c, r, compute). */
+ * When a step is cheap (32 m n r <= 4e10 flops), up to eight steps are
+ * enqueued per host round trip: each leaves its certificate verdict and
+ * stopping sums on the device, the host reads them together and keeps the
+ * first step that meets the stopping rule (later ones are discarded, status
+ * bits included), or redoes a step whose certificate was rejected while
+ * waiting for the verdict (Jacobi fallback), then runs the following steps
+ * one at a time for a while.  The workspace then holds up to eight more
+ * m x n iterates (at most about 512 MiB).  Larger steps synchronise once
+ * per step.  ws: qcur_complete_workspace(m, n, c, r, compute). */
 qcur_status qcur_complete(qcur_handle handle, const qcur_qmat* Y, const uint8_t* mask, int64_t mask_ld,
                           const int64_t* I, int64_t r, const int64_t* J, int64_t c, int compute, double rtol,
                           int64_t max_rank, int max_iter, double tol, qcur_qmat* X, int* iters, double* rel,
