@@ -187,6 +187,10 @@ struct GroupWs {
   void* verdict;  // DevVerdict holding ok and norms
   void* gws;
   size_t gws_bytes;
+  // per-matrix orders (device int[nb], may be NULL) for Gram matrices that
+  // fit one diagonal block: matrix b is factored over its leading dims[b]
+  // rows and columns only (0: skipped, P left as it is)
+  const int* dims = nullptr;
 };
 
 GroupWs group_carve(Bump& b, int nb, int64_t pp, int64_t qq) {
@@ -254,6 +258,10 @@ qcur_status chol_inv(const Ctx& c, GroupWs& w, double* P) {
   if (n > nb) {
     // larger than one diagonal block: the tile-task graph in one launch
     HIPCHK(launch_chol_dag(c, G, L, P, n, slab, w.nb, (int*)w.S, w.fail));
+    return QCUR_OK;
+  }
+  if (w.dims) {
+    HIPCHK(launch_chol_block(c, G, P, (int)n, n, n * n, w.fail, w.nb, slab, w.dims));
     return QCUR_OK;
   }
   HIPCHK(launch_zero(c, P, w.nb * slab));
@@ -1078,7 +1086,7 @@ struct BatchWs {
   double *colpart, *rowpart, *p, *q;
   Slots Ax;
   double *Z, *G, *L, *P1, *P2, *P, *Sch, *Q1, *Q, *norms;
-  int *fail, *ok;
+  int *fail, *ok, *zq2, *skip;
   double *Y, *V;
   Slots Qcx, Qrx, T, Tx, M, Mx, B1, B1x, E, Ex, M64, W1, U64;
   double* part;
@@ -1139,6 +1147,8 @@ BatchWs batch_carve(Bump& b, const BatchShape& s) {
   w.norms = (double*)b.take((size_t)n2 * 4 * 8);
   w.fail = (int*)b.take((size_t)n2 * 4);
   w.ok = (int*)b.take((size_t)n2 * 4);
+  w.zq2 = (int*)b.take((size_t)n2 * 4);
+  w.skip = (int*)b.take((size_t)n2 * 4);
   w.Y = (double*)b.take(zsl);
   w.V = (double*)b.take(gsl);
   if (idt != QCUR_F64) {
@@ -1390,9 +1400,27 @@ qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, Bat
                           w.zq, w.zp));
     return QCUR_OK;
   };
-  auto zph = [&](const QView& X, const QView& Pv, const QView& D, int id) -> qcur_status {  // D_t = X_t P_t^H
+  // D_t = X_t P_t^H over the leading q_t columns (qd: per-factor orders),
+  // and/or its copy in the product dtype into the C and R factor slots
+  auto zph = [&](const QView& X, const QView& Pv, const QView* D, const int* qd, bool to_product,
+                 int id) -> qcur_status {
     fixed_stage(id);
-    HIPCHK(launch_tall_nh(c, 1.0, X, Pv, 0.0, D, qx, n2, zslab, gslab, zslab, true, w.zp, w.zq, w.zq));
+    TallCopy cp{};
+    if (to_product) {
+      cp.p[0] = w.Qcx.p;
+      cp.p[1] = w.Qrx.p;
+      cp.ld[0] = w.Qcx.ld;
+      cp.ld[1] = w.Qrx.ld;
+      cp.ps[0] = w.Qcx.ps;
+      cp.ps[1] = w.Qrx.ps;
+      cp.slab[0] = w.Qcx.slab;
+      cp.slab[1] = w.Qrx.slab;
+      cp.dt = idt;
+      cp.split = n;
+    }
+    const QView Dv = D ? *D : QView{nullptr, px, qx, qx, px * qx, QCUR_F64};
+    HIPCHK(launch_tall_nh(c, 1.0, X, Pv, 0.0, Dv, qx, n2, zslab, gslab, zslab, true, w.zp, qd, qd,
+                          to_product ? &cp : nullptr));
     return QCUR_OK;
   };
   GroupWs gw{};
@@ -1404,33 +1432,45 @@ qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, Bat
   gw.fail = w.fail;
   gw.gws = w.gws;
   gw.gws_bytes = w.gws_bytes;
+  // Gram matrices that fit one diagonal block are factored over each
+  // factor's own order; larger ones get an identity block outside it
+  const bool padded = qx > CHOL_BLOCK;
   HIPCHK(launch_zero_i32(c, w.fail, n2));
   // G = Z^H Z:  C_b^H C_b  and  R_b R_b^H, one launch
   CHK(gram(Zv, BS_GRAM_C));
   fixed_stage(BS_GRAM_R);
-  HIPCHK(launch_pad_gram_batch(c, n2, w.G, qx, G.slab, w.zq));
+  if (padded) HIPCHK(launch_pad_gram_batch(c, n2, w.G, qx, G.slab, w.zq));
+  gw.dims = w.zq;
   CHK(chol_inv(c, gw, w.P1));
   HIPCHK(launch_sumsq_ragged(c, n2, Zs, w.zp, w.zq, w.norms, 4));
   HIPCHK(launch_sumsq_ragged(c, n2, P1, w.zq, w.zq, w.norms + 1, 4));
-  // Q1 = Z P1^H:  C_b P1^H  and  R_b^H P1^H, one launch.  The second pass
-  // (CholeskyQR2) runs for every product dtype: one pass leaves Q1^H Q1 - I
-  // near eps kappa^2, which the orthonormal form would carry into C U R.
-  const bool two = true;
-  const Slots Q1 = two ? sl(w.Q1, px, qx, qx) : Q;
-  CHK(zph(Zv, P1v, two ? Q1v : Qv, BS_Q1_C));
+  // Q1 = Z P1^H:  C_b P1^H  and  R_b^H P1^H, one launch (with its copy in the
+  // product dtype: the orthonormal factors of the factors that keep one pass)
+  const bool f64 = idt == QCUR_F64;
+  CHK(zph(Zv, P1v, &Q1v, w.zq, !f64, BS_Q1_C));
   fixed_stage(BS_Q1_R);
-  Slots Pf = P1;
-  if (two) {
-    // CholeskyQR2: Q1^H Q1 = L2 L2^H, P = P2 P1, Q = Q1 P2^H
-    const Slots P2 = sl(w.P2, qx, qx, qx), P = sl(w.P, qx, qx, qx);
-    CHK(gram(Q1v, BS_G2));
-    HIPCHK(launch_pad_gram_batch(c, n2, w.G, qx, G.slab, w.zq));
-    CHK(chol_inv(c, gw, w.P2));
-    CHK(stage(BS_P, QCUR_OP_N, QCUR_OP_N, 1.0, slot_view(P2, qx, qx), slot_view(P1, qx, qx), 0.0,
-                               slot_view(P, qx, qx), QCUR_F64, bspec(n2, P2, P1, P, w.zq, w.zq, w.zq, TRI_A_LOWER | TRI_B_LOWER)));
-    CHK(zph(Q1v, P2v, Qv, BS_Q));
-    Pf = P;
+  // CholeskyQR2: Q1^H Q1 = L2 L2^H, P = P2 P1, Q = Q1 P2^H.  FP64 products
+  // always take the second pass; FP32 and BF16 products only for the
+  // factors whose first-pass defect ||Q1^H Q1 - I||_F exceeds the bound of
+  // the single solve (q2 = 0 and P = P1 for the others, which then skip
+  // the second pass's factorisation and products)
+  const Slots P2 = sl(w.P2, qx, qx, qx), P = sl(w.P, qx, qx, qx);
+  CHK(gram(Q1v, BS_G2));
+  const int* q2 = w.zq;
+  if (!f64) {
+    const double tol = (s.compute == QCUR_BF16 || s.refine > 0) ? 0x1p-12 : 0x1p-26;
+    HIPCHK(launch_defect_plan_batch(c, n2, w.G, qx, G.slab, w.zq, w.fail, tol * tol, w.P1, w.P, w.zq2, w.skip));
+    q2 = w.zq2;
   }
+  if (padded) HIPCHK(launch_pad_gram_batch(c, n2, w.G, qx, G.slab, w.zq));
+  gw.dims = q2;
+  CHK(chol_inv(c, gw, w.P2));
+  CHK(stage(BS_P, QCUR_OP_N, QCUR_OP_N, 1.0, slot_view(P2, qx, qx), slot_view(P1, qx, qx), 0.0,
+            slot_view(P, qx, qx), QCUR_F64, bspec(n2, P2, P1, P, q2, q2, q2, TRI_A_LOWER | TRI_B_LOWER)));
+  // FP64 products read Q; the others read the product-dtype copy (Q itself
+  // is then only written by the Jacobi fallback below)
+  CHK(zph(Q1v, P2v, f64 ? &Qv : nullptr, q2, !f64, BS_Q));
+  const Slots Pf = P;
   HIPCHK(launch_sumsq_ragged(c, n2, Pf, w.zq, w.zq, w.norms + 2, 4));
   int64_t* ranks = a.rank_out ? a.rank_out : w.ranks;
   HIPCHK(launch_decide_batch(c, n2, n, w.norms, w.fail, a.rtol, a.max_rank, w.zp, w.zq, ranks, w.ok));
@@ -1453,11 +1493,12 @@ qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, Bat
     jb.max_sweeps = MAX_SWEEPS;
     HIPCHK(launch_jacobi_pinv_batch(c, jb, n2));
   }
-  // orthonormal factors in the product dtype
+  // orthonormal factors in the product dtype: those of the Jacobi fallback
+  // still to be cast (the others were written by the products above)
   Slots Qc = Q, Qr = half(Q);
-  if (idt != QCUR_F64) {
-    HIPCHK(launch_cast_batch(c, n, Q, w.Qcx, w.dm, w.dc, mx, cx, CAST_COPY));
-    HIPCHK(launch_cast_batch(c, n, half(Q), w.Qrx, w.dn, w.dr, nx, rx, CAST_COPY));
+  if (!f64) {
+    HIPCHK(launch_cast_batch(c, n, Q, w.Qcx, w.dm, w.dc, mx, cx, CAST_COPY, w.ok));
+    HIPCHK(launch_cast_batch(c, n, half(Q), w.Qrx, w.dn, w.dr, nx, rx, CAST_COPY, w.ok + n));
     Qc = w.Qcx;
     Qr = w.Qrx;
   }

@@ -183,8 +183,9 @@ template <typename TI, typename TO>
 __global__ __launch_bounds__(256) void kb_cast(const TI* __restrict__ X, int64_t ldx, int64_t psx, int64_t sx,
                                                TO* __restrict__ Y, int64_t ldy, int64_t psy, int64_t sy,
                                                const int* __restrict__ rows, const int* __restrict__ cols,
-                                               int mode) {
+                                               int mode, const int* __restrict__ skip_if) {
   const int b = blockIdx.z;
+  if (skip_if && skip_if[b]) return;
   const int64_t R = rows[b], C = cols[b];
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (j >= C) return;
@@ -203,7 +204,7 @@ __global__ __launch_bounds__(256) void kb_cast(const TI* __restrict__ X, int64_t
 }
 
 hipError_t launch_cast_batch(const Ctx& c, int count, Slots X, Slots Y, const int* rows, const int* cols,
-                             int64_t rowsx, int64_t colsx, int mode) {
+                             int64_t rowsx, int64_t colsx, int mode, const int* skip_if) {
   if (count <= 0 || rowsx <= 0 || colsx <= 0) return hipSuccess;
   const dim3 grid((unsigned)((colsx + 255) / 256), (unsigned)std::min<int64_t>(rowsx, 1024), (unsigned)count);
   return by_dtype(X.dt, [&](auto* ti) {
@@ -211,7 +212,7 @@ hipError_t launch_cast_batch(const Ctx& c, int count, Slots X, Slots Y, const in
     by_dtype(Y.dt, [&](auto* to) {
       typedef std::remove_pointer_t<decltype(to)> TO;
       hipLaunchKernelGGL((kb_cast<TI, TO>), grid, dim3(256), 0, c.stream, (const TI*)X.p, X.ld, X.ps, X.slab,
-                         (TO*)Y.p, Y.ld, Y.ps, Y.slab, rows, cols, mode);
+                         (TO*)Y.p, Y.ld, Y.ps, Y.slab, rows, cols, mode, skip_if);
     });
   });
 }
@@ -295,6 +296,53 @@ hipError_t launch_decide_batch(const Ctx& c, int count2, int count, const double
   if (count2 <= 0) return hipSuccess;
   hipLaunchKernelGGL(kb_decide, dim3((unsigned)((count2 + 255) / 256)), dim3(256), 0, c.stream, norms, fail, rtol,
                      max_rank, zp, zq, count2, count, rank_out, ok);
+  return hipGetLastError();
+}
+
+// One workgroup per factor t: the defect sum over the leading q x q block in
+// a fixed order (each thread a fixed set of entries, then the fixed-order
+// workgroup sum), the plan, and the copy of P1 for a factor that keeps its
+// first pass.
+__global__ __launch_bounds__(256) void kb_defect_plan(const double* __restrict__ G, int64_t n, int64_t slab,
+                                                      const int* __restrict__ zq, const int* __restrict__ fail,
+                                                      double tol2, const double* __restrict__ P1,
+                                                      double* __restrict__ P, int* q2, int* skip) {
+  __shared__ double red[256];
+  __shared__ int keep;
+  const int t = blockIdx.x, tid = threadIdx.x;
+  const int64_t q = zq[t], nn = n * n;
+  const double* Gt = G + (int64_t)t * slab;
+  double s = 0.0;
+  for (int64_t e = tid; e < q * q; e += 256) {
+    const int64_t i = e / q, j = e % q;
+    if (j > i) continue;
+    const double w = i == j ? 1.0 : 2.0;  // the strict lower part stands for both triangles
+    const double d0 = Gt[i * n + j] - (i == j ? 1.0 : 0.0);
+    const double d1 = Gt[i * n + j + nn], d2 = Gt[i * n + j + 2 * nn], d3 = Gt[i * n + j + 3 * nn];
+    s += w * (d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3);
+  }
+  s = block_sum_256(s, red);
+  if (tid == 0) {
+    keep = (fail[t] == 0 && s <= tol2) ? 1 : 0;
+    q2[t] = keep ? 0 : (int)q;
+    skip[t] = keep;
+  }
+  __syncthreads();
+  if (!keep) return;
+  const double* src = P1 + (int64_t)t * slab;
+  double* dst = P + (int64_t)t * slab;
+  for (int64_t e = tid; e < q * q; e += 256) {
+    const int64_t o = (e / q) * n + e % q;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) dst[o + c * nn] = src[o + c * nn];
+  }
+}
+
+hipError_t launch_defect_plan_batch(const Ctx& c, int count, const double* G, int64_t n, int64_t slab, const int* zq,
+                                    const int* fail, double tol2, const double* P1, double* P, int* q2, int* skip) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kb_defect_plan, dim3((unsigned)count), dim3(256), 0, c.stream, G, n, slab, zq, fail, tol2, P1, P,
+                     q2, skip);
   return hipGetLastError();
 }
 

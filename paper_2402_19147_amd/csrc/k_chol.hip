@@ -147,8 +147,12 @@ __device__ void chol_diag(Tile& a, double* rdg, DiagBuf& db, int kb, int kw, int
 }
 
 __global__ __launch_bounds__(CHOL_THREADS) void k_chol_block(const double* __restrict__ G0, double* __restrict__ P0,
-                                                             int w, int64_t ld, int64_t ps, int64_t sbatch,
-                                                             int* fail0) {
+                                                             int wx, int64_t ld, int64_t ps, int64_t sbatch,
+                                                             int* fail0, const int* __restrict__ dims) {
+  // matrix b's own order (dims: per-matrix orders; 0 = nothing to do, P
+  // left as it is; outside the leading w x w block nothing is written)
+  const int w = dims ? min(dims[blockIdx.x], wx) : wx;
+  if (w <= 0) return;
   const double* __restrict__ G = G0 + (int64_t)blockIdx.x * sbatch;
   double* __restrict__ Pg = P0 + (int64_t)blockIdx.x * sbatch;
   int* fail = fail0 + blockIdx.x;
@@ -261,8 +265,9 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_block(const double* __res
 }
 
 hipError_t launch_chol_block(const Ctx& c, const double* G, double* P, int w, int64_t ld, int64_t ps, int* fail,
-                             int batch, int64_t sbatch) {
-  hipLaunchKernelGGL(k_chol_block, dim3(batch), dim3(CHOL_THREADS), 0, c.stream, G, P, w, ld, ps, sbatch, fail);
+                             int batch, int64_t sbatch, const int* dims) {
+  hipLaunchKernelGGL(k_chol_block, dim3(batch), dim3(CHOL_THREADS), 0, c.stream, G, P, w, ld, ps, sbatch, fail,
+                     dims);
   return hipGetLastError();
 }
 

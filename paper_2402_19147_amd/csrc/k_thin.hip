@@ -267,6 +267,7 @@ struct TallArgs {
   // batches of uneven problems: problem b's own M, N, K (NULL: the extents);
   // then K need not be a multiple of 4 (elements at k >= K are zeroed)
   const int *bM, *bN, *bK;
+  TallCopy copy;  // optional copy of D in a product dtype (copy.p[0] NULL: none)
 };
 
 typedef double f64x2 __attribute__((ext_vector_type(2)));
@@ -319,11 +320,14 @@ __global__ __launch_bounds__(256) void k_tall_nh(TallArgs g, int nbi, int nbj) {
   auto compute_chunk = [&](int buf, int64_t ch) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
+      // both operands are zeroed past kend: with per-problem K the elements
+      // of a row past its problem's K are not part of the operand
       const bool ok = ch < nch && 16 * ch + kg + s < kend;
       const double a0 = ok ? ra[buf][0][s] : 0.0, a1 = ok ? ra[buf][1][s] : 0.0;
       const double a2 = ok ? ra[buf][2][s] : 0.0, a3 = ok ? ra[buf][3][s] : 0.0;
       const double n0 = -a0, n1 = -a1, n2 = -a2, n3 = -a3;
-      const double p0 = rb[buf][0][s], p1 = rb[buf][1][s], p2 = rb[buf][2][s], p3 = rb[buf][3][s];
+      const double p0 = ok ? rb[buf][0][s] : 0.0, p1 = ok ? rb[buf][1][s] : 0.0;
+      const double p2 = ok ? rb[buf][2][s] : 0.0, p3 = ok ? rb[buf][3][s] : 0.0;
       acc[0] = TT<double>::mfma(a0, p0, acc[0]);
       acc[1] = TT<double>::mfma(a1, p0, acc[1]);
       acc[2] = TT<double>::mfma(a2, p0, acc[2]);
@@ -350,7 +354,11 @@ __global__ __launch_bounds__(256) void k_tall_nh(TallArgs g, int nbi, int nbj) {
     compute_chunk(1, ch + 1);
   }
   const int64_t j = j0 + r;
-  double* D = g.D + (int64_t)b * g.sD;
+  double* D = g.D ? g.D + (int64_t)b * g.sD : nullptr;
+  const int h = b < g.copy.split ? 0 : 1;
+  void* D2 = g.copy.p[0] ? (char*)g.copy.p[h] +
+                               (size_t)(b - h * g.copy.split) * g.copy.slab[h] * dtype_size(g.copy.dt)
+                         : nullptr;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int64_t i = i0 + TT<double>::out_row(lane, q);
@@ -360,7 +368,8 @@ __global__ __launch_bounds__(256) void k_tall_nh(TallArgs g, int nbi, int nbj) {
         const int64_t o = i * g.ldd + j + p * g.psd;
         double v = g.alpha * acc[p][q];
         if (g.beta != 0.0) v += g.beta * D[o];
-        D[o] = v;
+        if (D) D[o] = v;
+        if (D2) store_from_double(D2, g.copy.dt, i * g.copy.ld[h] + j + p * g.copy.ps[h], v);
       }
     }
   }
@@ -439,7 +448,8 @@ bool tall_nh_applies(int compute, int opA, int opB, QView A, QView B, int64_t M,
 
 hipError_t launch_tall_nh(const Ctx& c, double alpha, QView A, QView B, double beta, QView D, int64_t K, int batch,
                           int64_t sA, int64_t sB, int64_t sD, bool b_upper, const int* bM, const int* bN,
-                          const int* bK) {
+                          const int* bK, const TallCopy* copy) {
+  if (!D.p && beta != 0.0) return hipErrorInvalidValue;
   const int64_t M = D.rows, N = D.cols;
   const int nbi = (int)((M + 15) / 16), nbj = (int)((N + 15) / 16);
   TallArgs g;
@@ -464,6 +474,7 @@ hipError_t launch_tall_nh(const Ctx& c, double alpha, QView A, QView B, double b
   g.alpha = alpha;
   g.beta = beta;
   g.b_upper = b_upper ? 1 : 0;
+  g.copy = copy ? *copy : TallCopy{};
   const int64_t wgs = (int64_t)batch * nbj * ((nbi + 3) / 4);
   hipLaunchKernelGGL(k_tall_nh, dim3((unsigned)wgs), dim3(256), 0, c.stream, g, nbi, nbj);
   return hipGetLastError();

@@ -27,7 +27,7 @@ inline QView view_of(const qcur_qmat& m) {
   return QView{m.p, m.rows, m.cols, m.ld, m.pstride, (int)m.dtype};
 }
 
-inline size_t dtype_size(int dt) { return dt == QCUR_F64 ? 8 : dt == QCUR_F32 ? 4 : 2; }
+__host__ __device__ inline size_t dtype_size(int dt) { return dt == QCUR_F64 ? 8 : dt == QCUR_F32 ? 4 : 2; }
 
 struct Ctx {
   int device;
@@ -118,7 +118,7 @@ struct BatchSpec {
 enum { TRI_LOWER_OUT = 1, TRI_A_LOWER = 2, TRI_A_UPPER = 4, TRI_B_LOWER = 8, TRI_B_UPPER = 16 };
 size_t gemm_workspace(int64_t M, int64_t N, int64_t K, int compute, int batch = 1);
 // Thin FP64 / FP32 products D = alpha A^H B + beta D (A: K x M, B: K x N,
-// both K-major; M, N <= 256, K >= 4 max(M, N), equal sizes over a batch):
+// both K-major; M, N <= 512, K >= 4 max(M, N), equal sizes over a batch):
 // one wave per 16 x 16 block of D streaming its fragments from global
 // memory.  Needs no more workspace than gemm_workspace gives the tiled plan
 // (fewer K splits); lower_only computes the blocks on and below the diagonal.
@@ -130,16 +130,25 @@ hipError_t launch_thin_hn(const Ctx& c, int compute, double alpha, QView A, QVie
                           size_t ws_bytes, const int* bM = nullptr, const int* bN = nullptr,
                           const int* bK = nullptr);
 // Tall FP64 products D = alpha A B^H + beta D with both operands contiguous
-// in k (M >= 512, N <= 256, K <= 256 a multiple of 4, 16-byte aligned rows;
+// in k (M >= 512, N <= 512, K <= 512 a multiple of 4, 16-byte aligned rows;
 // equal sizes over a batch; op(B) may be upper triangular): one wave per
 // 16 x 16 block of D over the whole K range, no workspace.
 bool tall_nh_applies(int compute, int opA, int opB, QView A, QView B, int64_t M, int64_t N, int64_t K, int tri,
                      bool per_problem_dims, int64_t sA, int64_t sB);
 // With bM / bN / bK as for launch_thin_hn; the extent K must be a multiple
-// of 4 and the operands' rows hold at least that many elements.
+// of 4 and the operands' rows hold at least that many elements.  copy: D
+// also stored (or only stored, when D.p is NULL and beta is 0) in dtype
+// copy->dt, problems b < copy->split in slot b of p[0], the others in slot
+// b - split of p[1] (row stride ld, plane stride ps, slot stride slab, in
+// elements).
+struct TallCopy {
+  void* p[2];
+  int64_t ld[2], ps[2], slab[2];
+  int dt, split;
+};
 hipError_t launch_tall_nh(const Ctx& c, double alpha, QView A, QView B, double beta, QView D, int64_t K, int batch,
                           int64_t sA, int64_t sB, int64_t sD, bool b_upper, const int* bM = nullptr,
-                          const int* bN = nullptr, const int* bK = nullptr);
+                          const int* bN = nullptr, const int* bK = nullptr, const TallCopy* copy = nullptr);
 // Workspace for any plan with at most max_splits K slices.
 size_t gemm_workspace_splits(int64_t M, int64_t N, int compute, int batch, int max_splits);
 hipError_t launch_gemm(const Ctx& c, int opA, int opB, double alpha, QView A, QView B, double beta,
@@ -188,7 +197,7 @@ hipError_t launch_pinv_qp(const Ctx& c, const double* Y, int64_t p, int64_t q, c
 constexpr int CHOL_BLOCK = 64;
 constexpr int MAXB = 4;
 hipError_t launch_chol_block(const Ctx& c, const double* G, double* P, int w, int64_t ld, int64_t ps, int* fail,
-                             int batch, int64_t sbatch);
+                             int batch, int64_t sbatch, const int* dims = nullptr);
 // Factorisation and inverse of nb Hermitian positive definite n x n Gram
 // matrices (matrix b at G + b * slab, lower triangle read) in one graph of
 // 32 x 32 tile tasks: P = L^{-1} (lower; the upper part zeroed), the
@@ -272,8 +281,17 @@ hipError_t launch_gather_batch(const Ctx& c, int count, Slots A, const int* dm, 
                                const int64_t* ridx, int64_t ris, const int64_t* cidx, int64_t cis,
                                const int* orows, const int* ocols, int64_t rowsx, int64_t colsx, Slots O,
                                const Slots* Ox, int tconj = 0);
+// skip_if (device int[count], may be NULL): problems b with skip_if[b] != 0
+// are left alone
 hipError_t launch_cast_batch(const Ctx& c, int count, Slots X, Slots Y, const int* rows, const int* cols,
-                             int64_t rowsx, int64_t colsx, int mode);
+                             int64_t rowsx, int64_t colsx, int mode, const int* skip_if = nullptr);
+// Second-pass plan of a batch of CholeskyQR factors from G = Q1^H Q1 (n x n
+// slots, leading q_t x q_t block of factor t, lower triangle): factor t
+// keeps its first pass when that pass did not fail and
+// ||Q1^H Q1 - I||_F^2 <= tol2; then q2[t] = 0, skip[t] = 1 and P1 is copied
+// to P; otherwise q2[t] = q_t and skip[t] = 0.
+hipError_t launch_defect_plan_batch(const Ctx& c, int count, const double* G, int64_t n, int64_t slab, const int* zq,
+                                    const int* fail, double tol2, const double* P1, double* P, int* q2, int* skip);
 hipError_t launch_pad_gram_batch(const Ctx& c, int count, double* G, int64_t n, int64_t slab, const int* zq);
 hipError_t launch_sumsq_ragged(const Ctx& c, int count, Slots X, const int* rows, const int* cols, double* out,
                                int ostride);
