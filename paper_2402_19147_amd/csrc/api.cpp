@@ -318,6 +318,20 @@ static_assert(offsetof(HostVerdict, ok) == offsetof(DevVerdict, ok) &&
 // also requires the orthogonality defect to be small) are in place, so the
 // caller can enqueue the work that follows before it waits; if the verdict
 // rejects the fast path, the caller recomputes without speculation.
+// Largest orthogonality defect ||Q1^H Q1 - I||_F of a first CholeskyQR
+// pass that the products of a solve accept in place of a second pass.  A
+// defect delta (Q^H Q = I + Delta) moves the orthogonal projectors Q Q^H by
+// O(delta), and so C U R.  FP64 products: 0 (always two passes).  FP32
+// products: 2^-22, a fraction of the relative error the FP32 products
+// themselves leave in C U R (sqrt(K) rounding units, about 1e-6 on the
+// benchmark shapes).  BF16 operands, or a refinement step after the first
+// core: 2^-12, since the refined core M1 is off the least-squares core by
+// O(delta^2) only (and BF16 rounding is 2^-8).
+double orth_bound(int compute, int refine) {
+  if (compute == QCUR_F64) return 0.0;
+  return (compute == QCUR_BF16 || refine > 0) ? 0x1p-12 : 0x1p-22;
+}
+
 struct PinvSpec {
   bool pending = false;
   int nb = 0;
@@ -734,13 +748,8 @@ qcur_status approx_run(const Ctx& c, const ApproxArgs& a, int64_t m, int64_t n, 
     QView xs[2] = {a.C, a.R};
     int64_t* ro[2] = {a.rank_out, a.rank_out ? a.rank_out + 1 : nullptr};
     // FP64 products: CholeskyQR2; FP32/BF16 products: a second pass only
-    // when the first leaves Q^H Q - I above a small fraction of their
-    // rounding unit.  With a refinement step the bound is 2^-12: a defect
-    // delta of the factors (Q^H Q = I + Delta) leaves M0 = Q_C^H A Q_R off
-    // the least-squares core by O(delta) but the refined M1 only by
-    // O(delta^2), below the rounding of the FP32 products.
-    const double orth_tol =
-        a.compute == QCUR_F64 ? 0.0 : (a.compute == QCUR_BF16 || a.refine > 0) ? 0x1p-12 : 0x1p-26;
+    // when the first leaves Q^H Q - I above the bound orth_bound gives
+    const double orth_tol = orth_bound(a.compute, a.refine);
     // operands in the product dtype (Q_C, Q_R are cast into fixed buffers,
     // so that a recomputation reuses them)
     QView Ax = as_dtype(c, a.A, idt, b, count_only, &err);
@@ -1458,7 +1467,7 @@ qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, Bat
   CHK(gram(Q1v, BS_G2));
   const int* q2 = w.zq;
   if (!f64) {
-    const double tol = (s.compute == QCUR_BF16 || s.refine > 0) ? 0x1p-12 : 0x1p-26;
+    const double tol = orth_bound(s.compute, s.refine);
     HIPCHK(launch_defect_plan_batch(c, n2, w.G, qx, G.slab, w.zq, w.fail, tol * tol, w.P1, w.P, w.zq2, w.skip));
     q2 = w.zq2;
   }
@@ -1638,7 +1647,7 @@ qcur_status complete_run(const Ctx& c, const CompleteArgs& a, Bump& b, bool coun
   HIPCHK(launch_mask_init(c, a.Y, a.mask, a.mask_ld, a.X));
   // the iterate of step t lives in cur; the next goes to nxt
   QView cur = a.X, nxt = Xw;
-  const double orth_tol = a.compute == QCUR_F64 ? 0.0 : a.compute == QCUR_BF16 ? 0x1p-12 : 0x1p-26;
+  const double orth_tol = orth_bound(a.compute, 0);
   int t = 0;
   double rel = INFINITY;
   // one step X^t (cur) -> X^{t+1} (nxt); with spec, the certificate's verdict

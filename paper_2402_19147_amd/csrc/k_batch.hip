@@ -206,7 +206,9 @@ __global__ __launch_bounds__(256) void kb_cast(const TI* __restrict__ X, int64_t
 hipError_t launch_cast_batch(const Ctx& c, int count, Slots X, Slots Y, const int* rows, const int* cols,
                              int64_t rowsx, int64_t colsx, int mode, const int* skip_if) {
   if (count <= 0 || rowsx <= 0 || colsx <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((colsx + 255) / 256), (unsigned)std::min<int64_t>(rowsx, 1024), (unsigned)count);
+  // rows strided over at most 64 workgroups per column stripe: problems
+  // skipped, or smaller than the extents, then cost few idle workgroups
+  const dim3 grid((unsigned)((colsx + 255) / 256), (unsigned)std::min<int64_t>(rowsx, 64), (unsigned)count);
   return by_dtype(X.dt, [&](auto* ti) {
     typedef std::remove_pointer_t<decltype(ti)> TI;
     by_dtype(Y.dt, [&](auto* to) {
