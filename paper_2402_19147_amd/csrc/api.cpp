@@ -1091,7 +1091,7 @@ struct BatchShape {
 constexpr int TUNE_MAX_SPLITS = 4;
 
 struct BatchWs {
-  int *dm, *dn, *dc, *dr, *zp, *zq;  // header (uploaded by qcur_batch_prepare)
+  int *dm, *dn, *dc, *dr, *zp, *zq, *order;  // header (uploaded by qcur_batch_prepare)
   double *colpart, *rowpart, *p, *q;
   Slots Ax;
   double *Z, *G, *L, *P1, *P2, *P, *Sch, *Q1, *Q, *norms;
@@ -1133,6 +1133,7 @@ BatchWs batch_carve(Bump& b, const BatchShape& s) {
   w.dr = (int*)b.take((size_t)n * 4);
   w.zp = (int*)b.take((size_t)n2 * 4);
   w.zq = (int*)b.take((size_t)n2 * 4);
+  w.order = (int*)b.take((size_t)n * 4);
   const int64_t nrbx = (s.mx + BATCH_RB - 1) / BATCH_RB, ncbx = (s.nx + 255) / 256;
   w.colpart = (double*)b.take((size_t)n * nrbx * s.nx * 8);
   w.rowpart = (double*)b.take((size_t)n * ncbx * s.mx * 8);
@@ -1311,6 +1312,7 @@ qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, Bat
   const bool cast_A = s.a_dt != idt;
   Slots resid_R{};
   int64_t resid_tiles = w.tiles;
+  int resid_tile_of = 64;
 
   // One GEMM stage: with the autotuner measuring, every candidate plan (tile
   // 32 or 64, 1..TUNE_MAX_SPLITS slices of K) is timed on the real operands
@@ -1350,13 +1352,14 @@ qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, Bat
       bs.tile = tu->plan[id].tile;
       bs.splits = tu->plan[id].splits;
     }
+    if (bs.count == n) bs.order = w.order;  // (an order of the problems, not of the 2 count factors)
     HIPCHK(launch_gemm_batched(c, opA, opB, alpha, A, B, beta, D, compute, w.gws, w.gws_bytes, bs));
     return QCUR_OK;
   };
   auto resid = [&](const Slots* E, const Slots* Bout) -> qcur_status {
     auto run = [&](int tile) {
       return launch_residual_gemm_batched(c, s.count, a.A, w.B1x, resid_R, QCUR_OP_H, s.mx, s.nx, s.rx, w.dm, w.dn,
-                                          w.dr, s.compute, w.part, E, 1.0, tile, Bout);
+                                          w.dr, s.compute, w.part, E, 1.0, tile, Bout, w.order);
     };
     if (tu && tu->measure && tu->plan[BS_RESID].tile == 0) {
       float t64 = 0.f, t32 = 0.f;
@@ -1367,6 +1370,7 @@ qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, Bat
     const int tile = (s.autotune && tu && tu->plan[BS_RESID].tile) ? tu->plan[BS_RESID].tile : 64;
     HIPCHK(run(tile));
     resid_tiles = tile == 32 ? w.tiles32 : w.tiles;
+    resid_tile_of = tile;
     return QCUR_OK;
   };
   // probabilities and draws
@@ -1542,7 +1546,8 @@ qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, Bat
   CHK(left_factor());
   resid_R = Qr;
   CHK(resid(nullptr, a.B.p ? &a.B : nullptr));
-  HIPCHK(launch_resid_sum_batch(c, n, w.part, resid_tiles, a.residual));
+  HIPCHK(launch_resid_sum_batch(c, n, w.part, resid_tiles, (s.nx + resid_tile_of - 1) / resid_tile_of, resid_tile_of,
+                                w.dm, w.dn, a.residual));
   // U = P_C^H M P_R in FP64
   if (w.M64.p != w.M.p) HIPCHK(launch_cast_batch(c, n, w.M, w.M64, w.dc, w.dr, cx, rx, CAST_COPY));
   CHK(stage(BS_W1, QCUR_OP_N, QCUR_OP_N, 1.0, slot_view(w.M64, cx, rx), slot_view(half(Pf), rx, rx), 0.0,
@@ -2430,11 +2435,17 @@ qcur_status qcur_batch_prepare(qcur_handle h, int32_t count, const int32_t* dims
     hp[count + i] = hn[i];
     hq[count + i] = hr[i];
   }
-  const int* srcs[6] = {hm, hn, hc, hr, hp, hq};
-  int* dsts[6] = {w.dm, w.dn, w.dc, w.dr, w.zp, w.zq};
-  const size_t lens[6] = {(size_t)count, (size_t)count, (size_t)count, (size_t)count, (size_t)2 * count,
-                          (size_t)2 * count};
-  for (int k = 0; k < 6; ++k)
+  // the order in which persistent launches hand out the problems' tiles:
+  // largest m n (c + r) first (the products' work), ties by index
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  auto work = [&](int i) { return (double)hm[i] * (double)hn[i] * (double)(hc[i] + hr[i]); };
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
+  const int* srcs[7] = {hm, hn, hc, hr, hp, hq, order.data()};
+  int* dsts[7] = {w.dm, w.dn, w.dc, w.dr, w.zp, w.zq, w.order};
+  const size_t lens[7] = {(size_t)count, (size_t)count, (size_t)count, (size_t)count, (size_t)2 * count,
+                          (size_t)2 * count, (size_t)count};
+  for (int k = 0; k < 7; ++k)
     HIPCHK(hipMemcpyAsync(dsts[k], srcs[k], lens[k] * sizeof(int), hipMemcpyHostToDevice, h->c.stream));
   HIPCHK(hipStreamSynchronize(h->c.stream));
   int slot = -1;

@@ -348,19 +348,26 @@ hipError_t launch_defect_plan_batch(const Ctx& c, int count, const double* G, in
   return hipGetLastError();
 }
 
-// residual_b = sqrt(sum of problem b's tile partials), in tile order.
-__global__ __launch_bounds__(256) void kb_resid_sum(const double* __restrict__ part, int64_t tiles, double* out) {
+// residual_b = sqrt(sum of problem b's tile partials), in tile order over
+// the problem's own tiles (the others are never written).
+__global__ __launch_bounds__(256) void kb_resid_sum(const double* __restrict__ part, int64_t tiles, int64_t gx,
+                                                   int tile, const int* __restrict__ dm,
+                                                   const int* __restrict__ dn, double* out) {
   __shared__ double red[256];
   const int b = blockIdx.x;
+  const int64_t ty = (dm[b] + tile - 1) / tile, tx = (dn[b] + tile - 1) / tile;
   double s = 0.0;
-  for (int64_t k = threadIdx.x; k < tiles; k += 256) s += part[(int64_t)b * tiles + k];
+  for (int64_t k = threadIdx.x; k < tiles; k += 256)
+    if (k / gx < ty && k % gx < tx) s += part[(int64_t)b * tiles + k];
   s = block_sum_256(s, red);
   if (threadIdx.x == 0) out[b] = sqrt(s);
 }
 
-hipError_t launch_resid_sum_batch(const Ctx& c, int count, const double* part, int64_t tiles, double* out) {
+hipError_t launch_resid_sum_batch(const Ctx& c, int count, const double* part, int64_t tiles, int64_t gx, int tile,
+                                  const int* dm, const int* dn, double* out) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(kb_resid_sum, dim3((unsigned)count), dim3(256), 0, c.stream, part, tiles, out);
+  hipLaunchKernelGGL(kb_resid_sum, dim3((unsigned)count), dim3(256), 0, c.stream, part, tiles, gx, tile, dm, dn,
+                     out);
   return hipGetLastError();
 }
 

@@ -140,6 +140,9 @@ struct GemmArgs {
   int force_tile, force_splits;
   // triangular structure of op(A), op(B) and of the wanted output (TRI_*)
   int tri;
+  // batches with per-problem sizes: the problems in the order their tiles
+  // are handed out (largest first; NULL: the grid mapping)
+  const int* order;
   // merge epilogue (completion step): X0 = current iterate, partials2
   const void* X0;
   int x0dt;
@@ -748,6 +751,100 @@ __global__ __launch_bounds__(NT) void k_qgemm(GemmArgs g) {
   gemm_tile<DT, EPI, BM, BN>(g, b, ty, tx, split, (int64_t)b * tiles + ty * gx + tx, sm);
 }
 
+// Persistent form for batches of uneven problems: a grid of about one
+// resident wave of workgroups takes the tiles of all problems as one list,
+// problem after problem in the given order (largest first: a longest-
+// processing-time order, so that the last tiles to start are short), the
+// tiles of one problem in (K slice, row, column) order.  Every workgroup
+// builds the prefix sums of the per-problem tile counts in LDS, then takes
+// list entries x, x + grid, ... with x its XCD-remapped id, so that each
+// XCD works through contiguous runs of the list (the tiles that share rows
+// of A and the same B behind one L2).  No tile outside a problem is
+// visited.
+constexpr int LIST_MAX = 2048;  // problems a list launch takes
+template <int DT, int EPI, int BM, int BN>
+__global__ __launch_bounds__(NT) void k_qgemm_list(GemmArgs g) {
+  __shared__ Smem<DT, BM, BN> sm;
+  __shared__ int off[LIST_MAX + 1];
+  __shared__ int wsum[NT / 64];
+  const int tid = threadIdx.x, count = g.batch;
+  const int64_t gx = (g.N + BN - 1) / BN, gy = (g.M + BM - 1) / BM;
+  // tiles of the problem at list position k
+  auto tiles_of = [&](int k) -> int {
+    const int b = g.order[k];
+    const int64_t M = g.bM ? (int64_t)g.bM[b] : g.M, N = g.bN ? (int64_t)g.bN[b] : g.N;
+    return (int)(((M + BM - 1) / BM) * ((N + BN - 1) / BN) * g.splits);
+  };
+  // exclusive prefix sums: thread tid sums its contiguous run of positions,
+  // the runs are scanned across the workgroup, then the run is written out
+  const int per = (count + NT - 1) / NT, k0 = tid * per, k1 = min(count, k0 + per);
+  int run = 0;
+  for (int k = k0; k < k1; ++k) run += tiles_of(k);
+  int incl = run;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(incl, o, 64);
+    if ((tid & 63) >= o) incl += v;
+  }
+  if ((tid & 63) == 63) wsum[tid >> 6] = incl;
+  __syncthreads();
+  int base = incl - run;
+  for (int w = 0; w < (tid >> 6); ++w) base += wsum[w];
+  for (int k = k0; k < k1; ++k) {
+    off[k] = base;
+    base += tiles_of(k);
+  }
+  if (tid == NT - 1) off[count] = base;
+  __syncthreads();
+  const int total = off[count];
+  for (int64_t t = xcd_tile(blockIdx.x, gridDim.x); t < total; t += gridDim.x) {
+    // the list position holding entry t: the last k with off[k] <= t
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (off[mid] <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const int b = g.order[lo];
+    const int64_t M = g.bM ? (int64_t)g.bM[b] : g.M, N = g.bN ? (int64_t)g.bN[b] : g.N;
+    const int64_t tn = (N + BN - 1) / BN, tm = (M + BM - 1) / BM;
+    const int64_t local = t - off[lo];
+    const int split = (int)(local / (tm * tn));
+    const int64_t rem = local % (tm * tn), ty = rem / tn, tx = rem % tn;
+    gemm_tile<DT, EPI, BM, BN>(g, b, ty, tx, split, (int64_t)b * gx * gy + ty * gx + tx, sm);
+  }
+}
+
+// Launch of the tile kernel: the persistent list form for batches with
+// per-problem sizes and an order, else one workgroup per tile of the grid.
+int list_workers(const void* kernel, int device) {
+  static int cus[64] = {0};
+  const int d = device < 0 || device >= 64 ? 0 : device;
+  if (cus[d] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, d) != hipSuccess || n <= 0) n = 256;
+    cus[d] = n;
+  }
+  int per = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, NT, 0) != hipSuccess || per <= 0) per = 1;
+  return per * cus[d];
+}
+
+template <int DT, int EPI, int BM, int BN>
+static void launch_tiles(const Ctx& c, const GemmArgs& g, dim3 grid) {
+  if constexpr (BM == BN) {  // batches take square tiles only
+    if (g.order && g.batch > 1 && g.batch <= LIST_MAX && (g.bM || g.bN)) {
+      static int workers = 0;  // per instantiation (the same on every MI355X)
+      if (workers == 0) workers = list_workers((const void*)k_qgemm_list<DT, EPI, BM, BN>, c.device);
+      const int64_t upper = (int64_t)grid.x * grid.y * grid.z;
+      hipLaunchKernelGGL((k_qgemm_list<DT, EPI, BM, BN>), dim3((unsigned)std::min<int64_t>(upper, workers)),
+                         dim3(NT), 0, c.stream, g);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_qgemm<DT, EPI, BM, BN>), grid, dim3(NT), 0, c.stream, g);
+}
+
 // Split-K reduction: D = alpha * sum_z P[z] + beta * D, z in fixed order.
 template <typename Acc>
 __global__ void k_splitk_reduce(const Acc* __restrict__ Pall, int splits, int64_t Mx, int64_t Nx, double alpha,
@@ -858,7 +955,7 @@ static hipError_t gemm_dt_tile(const Ctx& c, GemmArgs g, void* ws, size_t ws_byt
     g.ktiles_per_split = (int)kt;
     g.splits = 1;
     grid.z = g.batch;
-    hipLaunchKernelGGL((k_qgemm<DT, EPI_STORE, TILE, TN>), grid, dim3(NT), 0, c.stream, g);
+    launch_tiles<DT, EPI_STORE, TILE, TN>(c, g, grid);
     return hipGetLastError();
   }
   const int per = (int)((kt + splits - 1) / splits);
@@ -871,7 +968,7 @@ static hipError_t gemm_dt_tile(const Ctx& c, GemmArgs g, void* ws, size_t ws_byt
   gp.D = ws;
   gp.ldd = g.N;
   gp.psd = g.M * g.N;
-  hipLaunchKernelGGL((k_qgemm<DT, EPI_PARTIAL, TILE, TN>), grid, dim3(NT), 0, c.stream, gp);
+  launch_tiles<DT, EPI_PARTIAL, TILE, TN>(c, gp, grid);
   hipLaunchKernelGGL(k_splitk_reduce<Acc>,
                      dim3((unsigned)((g.N + 255) / 256), (unsigned)std::min<int64_t>(g.M, 65535), (unsigned)g.batch),
                      dim3(256), 0, c.stream, (const Acc*)ws, splits, g.M, g.N, g.alpha, g.beta, (Acc*)g.D, g.ldd,
@@ -910,6 +1007,7 @@ hipError_t launch_gemm_batched(const Ctx& c, int opA, int opB, double alpha, QVi
   g.force_tile = bs.tile;
   g.tri = bs.tri;
   g.force_splits = bs.splits;
+  g.order = bs.order;
   g.A = A.p; g.lda = A.ld; g.psa = A.ps;
   g.B = B.p; g.ldb = B.ld; g.psb = B.ps;
   g.D = D.p; g.ldd = D.ld; g.psd = D.ps;
@@ -1010,9 +1108,10 @@ hipError_t launch_residual_gemm(const Ctx& c, QView A, QView B1, QView R, const 
 hipError_t launch_residual_gemm_batched(const Ctx& c, int count, Slots A, Slots B1, Slots R, int opR, int64_t mx,
                                         int64_t nx, int64_t kx, const int* bM, const int* bN, const int* bK,
                                         int compute, double* partials, const Slots* E, double e_scale, int tile,
-                                        const Slots* Bout) {
+                                        const Slots* Bout, const int* order) {
   if (count <= 0 || mx <= 0 || nx <= 0) return hipSuccess;
   GemmArgs g = {};
+  g.order = order;
   g.A = B1.p; g.lda = B1.ld; g.psa = B1.ps; g.sA = B1.slab;
   g.B = R.p; g.ldb = R.ld; g.psb = R.ps; g.sB = R.slab;
   g.M = mx; g.N = nx; g.K = kx;
@@ -1033,18 +1132,18 @@ hipError_t launch_residual_gemm_batched(const Ctx& c, int count, Slots A, Slots 
   switch (compute) {
     case QCUR_F64:
       g.ktiles_per_split = (int)((kx + 15) / 16);
-      if (t == 64) hipLaunchKernelGGL((k_qgemm<QCUR_F64, EPI_RESID, 64, 64>), grid, dim3(NT), 0, c.stream, g);
-      else hipLaunchKernelGGL((k_qgemm<QCUR_F64, EPI_RESID, 32, 32>), grid, dim3(NT), 0, c.stream, g);
+      if (t == 64) launch_tiles<QCUR_F64, EPI_RESID, 64, 64>(c, g, grid);
+      else launch_tiles<QCUR_F64, EPI_RESID, 32, 32>(c, g, grid);
       break;
     case QCUR_F32:
       g.ktiles_per_split = (int)((kx + 15) / 16);
-      if (t == 64) hipLaunchKernelGGL((k_qgemm<QCUR_F32, EPI_RESID, 64, 64>), grid, dim3(NT), 0, c.stream, g);
-      else hipLaunchKernelGGL((k_qgemm<QCUR_F32, EPI_RESID, 32, 32>), grid, dim3(NT), 0, c.stream, g);
+      if (t == 64) launch_tiles<QCUR_F32, EPI_RESID, 64, 64>(c, g, grid);
+      else launch_tiles<QCUR_F32, EPI_RESID, 32, 32>(c, g, grid);
       break;
     default:
       g.ktiles_per_split = (int)((kx + 31) / 32);
-      if (t == 64) hipLaunchKernelGGL((k_qgemm<QCUR_BF16, EPI_RESID, 64, 64>), grid, dim3(NT), 0, c.stream, g);
-      else hipLaunchKernelGGL((k_qgemm<QCUR_BF16, EPI_RESID, 32, 32>), grid, dim3(NT), 0, c.stream, g);
+      if (t == 64) launch_tiles<QCUR_BF16, EPI_RESID, 64, 64>(c, g, grid);
+      else launch_tiles<QCUR_BF16, EPI_RESID, 32, 32>(c, g, grid);
   }
   return hipGetLastError();
 }

@@ -111,6 +111,10 @@ struct BatchSpec {
   int tile = 0;    // launch plan override: tile edge 32 or 64 (0: automatic)
   int splits = 0;  // K slices (0: automatic; reduced to 1 without enough workspace)
   int tri = 0;     // TRI_* flags: zero triangles of op(A), op(B), lower output only
+  // with M or N given: the problems in the order a persistent launch hands
+  // out their tiles (device int[count], largest first; NULL: one workgroup
+  // per tile of the padded grid)
+  const int* order = nullptr;
 };
 // op(A) / op(B) lower or upper triangular (exact zeros elsewhere): K steps
 // that meet only zeros are skipped.  TRI_LOWER_OUT: only the lower triangle
@@ -298,12 +302,17 @@ hipError_t launch_sumsq_ragged(const Ctx& c, int count, Slots X, const int* rows
 hipError_t launch_decide_batch(const Ctx& c, int count2, int count, const double* norms, const int* fail,
                                double rtol, int64_t max_rank, const int* zp, const int* zq, int64_t* rank_out,
                                int* ok);
-hipError_t launch_resid_sum_batch(const Ctx& c, int count, const double* part, int64_t tiles, double* out);
+// residual_b = sqrt(sum of problem b's tile partials) over its own tiles:
+// rows ceil(m_b / tile) and columns ceil(n_b / tile) of the gx-wide tile
+// grid (tiles = partials per problem)
+hipError_t launch_resid_sum_batch(const Ctx& c, int count, const double* part, int64_t tiles, int64_t gx, int tile,
+                                  const int* dm, const int* dn, double* out);
 // Batched residual A_b - B1_b op(R_b) (op = QCUR_OP_N or QCUR_OP_H).
-// tile: 64 or 32 (partials per problem: ceil(mx/tile) * ceil(nx/tile)).
+// tile: 64 or 32 (partials per problem: ceil(mx/tile) * ceil(nx/tile); only
+// those of the problem's own tiles are written).  order: as BatchSpec::order.
 hipError_t launch_residual_gemm_batched(const Ctx& c, int count, Slots A, Slots B1, Slots R, int opR, int64_t mx,
                                         int64_t nx, int64_t kx, const int* bM, const int* bN, const int* bK,
                                         int compute, double* partials, const Slots* E, double e_scale,
-                                        int tile = 64, const Slots* Bout = nullptr);
+                                        int tile = 64, const Slots* Bout = nullptr, const int* order = nullptr);
 
 }  // namespace qcur
