@@ -420,7 +420,7 @@ __device__ inline void dag_mul_n(Qd (&acc)[4], const DTile& X, const DTile& Y, d
 struct DagDiag {
   double col[2][DTS][4];
   double row[2][DTS][4];
-  double piv[2][4];
+  double piv[2][4];  // [0]: 1 / d_j
   double rs[DTS];
 };
 __device__ void dag_potri(DTile& T, DagDiag& db, int w, int* bad) {
@@ -441,42 +441,41 @@ __device__ void dag_potri(DTile& T, DagDiag& db, int w, int* bad) {
   }
   for (int j = 0; j < DTS; ++j) {
     const int par = j & 1;
+    // publish column j below the pivot, row j left of it, and 1/sqrt(d_j)
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      if (!in[s]) continue;
-      if (ec[s] == j) {
-        if (ei[s] == j) {
-          const bool ok = x[s].w > 0.0 && x[s].w < INFINITY;
-          const double r = rsqrt_nr(ok ? x[s].w : 1.0);
-          db.piv[par][0] = x[s].w;
-          db.piv[par][1] = r;
-          db.piv[par][2] = r * r;
-          db.piv[par][3] = ok ? 0.0 : 1.0;
-          db.rs[j] = r;
-        } else {
-          stq4(db.col[par][ei[s]], x[s]);
-        }
+      const bool cj = in[s] && ec[s] == j;
+      if (cj && ei[s] == j) {
+        const bool ok = x[s].w > 0.0 && x[s].w < INFINITY;
+        const double r = rsqrt_nr(ok ? x[s].w : 1.0);
+        db.piv[par][0] = r * r;
+        db.rs[j] = r;
+        if (!ok) *bad = 1;
       }
-      if (ei[s] == j && ec[s] < j) stq4(db.row[par][ec[s]], x[s]);
+      if (cj && ei[s] > j) stq4(db.col[par][ei[s]], x[s]);
+      if (in[s] && ei[s] == j && ec[s] < j) stq4(db.row[par][ec[s]], x[s]);
     }
     __syncthreads();
-    const double rd = db.piv[par][2];
-    if (tid == 0 && db.piv[par][3] != 0.0) *bad = 1;
+    // reads from in-range slots, with no branch around them (stale ones are
+    // never used: the updates select, so they cannot reach the arithmetic)
+    const double rd = db.piv[par][0];
+    Qd ar[4], vv[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      ar[s] = ldq4(db.col[par][ei[s]]);
+      vv[s] = ldq4(ec[s] > j ? db.col[par][ec[s]] : db.row[par][ec[s]]);
+    }
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int i = ei[s], c = ec[s];
-      if (!in[s] || i <= j) continue;
-      const Qd ar = ldq4(db.col[par][i]);
-      const Qd u{ar.w * rd, ar.x * rd, ar.y * rd, ar.z * rd};
-      if (c == j) {
-        x[s] = Qd{-u.w, -u.x, -u.y, -u.z};
-      } else {
-        // c > j: A_ic -= u conj(A_cj);  c < j: X_ic -= u X_jc
-        const Qd vr = c > j ? ldq4(db.col[par][c]) : ldq4(db.row[par][c]);
-        const double sg = c > j ? -1.0 : 1.0;
-        const Qd q = qmul(u, Qd{vr.w, sg * vr.x, sg * vr.y, sg * vr.z});
-        x[s] = Qd{x[s].w - q.w, x[s].x - q.x, x[s].y - q.y, x[s].z - q.z};
-      }
+      const bool act = in[s] && i > j;
+      const Qd u{ar[s].w * rd, ar[s].x * rd, ar[s].y * rd, ar[s].z * rd};
+      // c > j: A_ic -= u conj(A_cj);  c < j: X_ic -= u X_jc;  c == j: X_ij = -u
+      const Qd v = c > j ? Qd{vv[s].w, -vv[s].x, -vv[s].y, -vv[s].z} : vv[s];
+      const Qd q = qmul(u, v);
+      Qd nx{x[s].w - q.w, x[s].x - q.x, x[s].y - q.y, x[s].z - q.z};
+      if (c == j) nx = Qd{-u.w, -u.x, -u.y, -u.z};
+      if (act) x[s] = nx;
     }
   }
   __syncthreads();

@@ -890,8 +890,8 @@ static Plan plan_of(int64_t M, int64_t N, int64_t K, int bk, int batch, int forc
 
 static int bk_of(int compute) { return compute == QCUR_BF16 || compute == QCUR_BF16X3 ? 32 : 16; }
 
-// Single (not batched) FP32 / FP64 products with a tall output and a long K
-// (M >= 2048, K >= 1024: A Q_R and E Q_R of the large solves):
+// Single (not batched) FP32 / FP64 products with a tall output (M >= 2048,
+// K >= 256: A Q_R, E Q_R and Q_C M of the large solves):
 // 64 x 64 tiles, or for FP32 64 x 80 (which covers N = 400 without a padded
 // column tile), and 1..8 slices of K, chosen by a cost model: workgroups
 // run in rounds of `slots` (two per compute unit when the kernel's LDS and
@@ -903,7 +903,7 @@ struct WidePlan {
   int tn, splits;  // tn = 0: not applicable
 };
 static WidePlan wide_plan(int64_t M, int64_t N, int64_t K, int compute, int batch, bool per_problem) {
-  if ((compute != QCUR_F32 && compute != QCUR_F64) || batch != 1 || per_problem || M < 2048 || K < 1024 || N < 64)
+  if ((compute != QCUR_F32 && compute != QCUR_F64) || batch != 1 || per_problem || M < 2048 || K < 256 || N < 64)
     return WidePlan{0, 0};
   const int64_t kt = (K + 15) / 16;
   double best = 1e300;
