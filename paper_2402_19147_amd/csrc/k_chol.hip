@@ -283,7 +283,8 @@ hipError_t launch_chol_block(const Ctx& c, const double* G, double* P, int w, in
 //       i == j: P_jj = (the factor of S)^{-1} by the elementary steps of
 //       chol_diag;  i > j: L_ij = S P_jj^H;
 //   inverse (i, j), i > j:  P_ij = -P_ii sum_{l=j}^{i-1} L_il P_lj (l in order).
-// Only P and the off-diagonal L tiles are stored.  Every workgroup takes its
+// The 32 x 32 tile products run on the FP64 matrix cores (dag_mfma).  Only P
+// and the off-diagonal L tiles are stored.  Every workgroup takes its
 // task from a ticket counter, in an order in which each task depends only on
 // tasks with smaller tickets, and a ticket is only held by a workgroup that
 // is running, so every wait is on a task that is running or done, whatever
@@ -350,22 +351,29 @@ __device__ inline void dag_load(DTile& t, const double* __restrict__ M, int64_t 
   }
 }
 
-// the four elements of a 32 x 32 tile owned by a thread in the tile
-// products: row tid / 8, columns tid % 8 + 8 s
-__device__ inline void dag_store(double* __restrict__ M, int64_t n, int ti, int tj, const Qd (&v)[4]) {
+// a tile from LDS to the matrix (row stride n, plane stride n * n); entries
+// past n are not stored
+__device__ inline void dag_store_tile(double* __restrict__ M, int64_t n, int ti, int tj, const DTile& t) {
   const int64_t ps = n * n;
-  const int r = threadIdx.x >> 3;
-  const int64_t gi = (int64_t)ti * DTS + r;
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int c = (threadIdx.x & 7) + 8 * s;
-    const int64_t gj = (int64_t)tj * DTS + c;
+  for (int e = threadIdx.x; e < DTS * DTS; e += DAG_THREADS) {
+    const int r = e / DTS, c = e % DTS;
+    const int64_t gi = (int64_t)ti * DTS + r, gj = (int64_t)tj * DTS + c;
     if (gi < n && gj < n) {
       const int64_t o = gi * n + gj;
-      M[o] = v[s].w;
-      M[o + ps] = v[s].x;
-      M[o + 2 * ps] = v[s].y;
-      M[o + 3 * ps] = v[s].z;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) M[o + q * ps] = t[q][r][c];
+    }
+  }
+}
+__device__ inline void dag_store_zero(double* __restrict__ M, int64_t n, int ti, int tj) {
+  const int64_t ps = n * n;
+  for (int e = threadIdx.x; e < DTS * DTS; e += DAG_THREADS) {
+    const int r = e / DTS, c = e % DTS;
+    const int64_t gi = (int64_t)ti * DTS + r, gj = (int64_t)tj * DTS + c;
+    if (gi < n && gj < n) {
+      const int64_t o = gi * n + gj;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) M[o + q * ps] = 0.0;
     }
   }
 }
@@ -378,35 +386,70 @@ __device__ inline void dstq(DTile& t, int r, int c, Qd v) {
   t[3][r][c] = v.z;
 }
 
-// acc[s] += sgn * sum_k X[r][k] conj(Y[c][k])  (k < kmax)
-__device__ inline void dag_mul_h(Qd (&acc)[4], const DTile& X, const DTile& Y, double sgn, int kmax = DTS) {
-  const int r = threadIdx.x >> 3, c0 = threadIdx.x & 7;
-  for (int k = 0; k < kmax; ++k) {
-    const Qd a = dldq(X, r, k);
+// Tile products on the FP64 matrix cores.  Wave w owns the 16 x 16 quadrant
+// (16 (w / 2), 16 (w % 2)) of a 32 x 32 product; its accumulators hold, per
+// plane, the MFMA 16x16x4 output layout: lane l has column l % 16 and rows
+// l / 16 + 4 r.  Each step of four k loads one fragment per plane of each
+// operand and issues the sixteen real products of the Hamilton product.
+typedef double f64x4d __attribute__((ext_vector_type(4)));
+struct DAcc {
+  f64x4d p[4];
+};
+__device__ inline int dq_row(int r) { return 16 * ((threadIdx.x >> 6) >> 1) + ((threadIdx.x & 63) >> 4) + 4 * r; }
+__device__ inline int dq_col() { return 16 * ((threadIdx.x >> 6) & 1) + (threadIdx.x & 15); }
+__device__ inline void acc_zero(DAcc& a) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const Qd u = qmul_conj(a, dldq(Y, c0 + 8 * s, k));
-      acc[s].w += sgn * u.w;
-      acc[s].x += sgn * u.x;
-      acc[s].y += sgn * u.y;
-      acc[s].z += sgn * u.z;
-    }
-  }
+  for (int q = 0; q < 4; ++q) a.p[q] = (f64x4d){0, 0, 0, 0};
 }
-
-// acc[s] += sgn * sum_k X[r][k] Y[k][c]  (k < kmax)
-__device__ inline void dag_mul_n(Qd (&acc)[4], const DTile& X, const DTile& Y, double sgn, int kmax = DTS) {
-  const int r = threadIdx.x >> 3, c0 = threadIdx.x & 7;
-  for (int k = 0; k < kmax; ++k) {
-    const Qd a = dldq(X, r, k);
+__device__ inline void acc_from_tile(DAcc& a, const DTile& t) {
+  const int c = dq_col();
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const Qd u = qmul(a, dldq(Y, k, c0 + 8 * s));
-      acc[s].w += sgn * u.w;
-      acc[s].x += sgn * u.x;
-      acc[s].y += sgn * u.y;
-      acc[s].z += sgn * u.z;
-    }
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a.p[q][r] = t[q][dq_row(r)][c];
+}
+__device__ inline void acc_to_tile(DTile& t, const DAcc& a) {
+  const int c = dq_col();
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) t[q][dq_row(r)][c] = a.p[q][r];
+}
+// acc += sgn * X op(Y), op(Y) = Y^H when herm (entries conj(Y[c][k])), else Y
+__device__ inline void dag_mfma(DAcc& acc, const DTile& X, const DTile& Y, bool herm, double sgn) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ar = 16 * (wave >> 1) + (lane & 15), bc = 16 * (wave & 1) + (lane & 15), kl = lane >> 4;
+  const double hs = herm ? -1.0 : 1.0;
+#pragma unroll 2
+  for (int k0 = 0; k0 < DTS; k0 += 4) {
+    const int k = k0 + kl;
+    // A fragments carry sgn; B fragments the conjugation's signs
+    const double a0 = sgn * X[0][ar][k], a1 = sgn * X[1][ar][k], a2 = sgn * X[2][ar][k], a3 = sgn * X[3][ar][k];
+    const double b0 = herm ? Y[0][bc][k] : Y[0][k][bc];
+    const double b1 = hs * (herm ? Y[1][bc][k] : Y[1][k][bc]);
+    const double b2 = hs * (herm ? Y[2][bc][k] : Y[2][k][bc]);
+    const double b3 = hs * (herm ? Y[3][bc][k] : Y[3][k][bc]);
+    const double n1 = -a1, n2 = -a2, n3 = -a3;
+    // plane 0: a0 b0 - a1 b1 - a2 b2 - a3 b3
+    acc.p[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc.p[0], 0, 0, 0);
+    acc.p[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(n1, b1, acc.p[0], 0, 0, 0);
+    acc.p[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(n2, b2, acc.p[0], 0, 0, 0);
+    acc.p[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(n3, b3, acc.p[0], 0, 0, 0);
+    // plane 1: a1 b0 + a0 b1 - a3 b2 + a2 b3
+    acc.p[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc.p[1], 0, 0, 0);
+    acc.p[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc.p[1], 0, 0, 0);
+    acc.p[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(n3, b2, acc.p[1], 0, 0, 0);
+    acc.p[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b3, acc.p[1], 0, 0, 0);
+    // plane 2: a2 b0 + a3 b1 + a0 b2 - a1 b3
+    acc.p[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b0, acc.p[2], 0, 0, 0);
+    acc.p[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, b1, acc.p[2], 0, 0, 0);
+    acc.p[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b2, acc.p[2], 0, 0, 0);
+    acc.p[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(n1, b3, acc.p[2], 0, 0, 0);
+    // plane 3: a3 b0 - a2 b1 + a1 b2 + a0 b3
+    acc.p[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, b0, acc.p[3], 0, 0, 0);
+    acc.p[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(n2, b1, acc.p[3], 0, 0, 0);
+    acc.p[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b2, acc.p[3], 0, 0, 0);
+    acc.p[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b3, acc.p[3], 0, 0, 0);
   }
 }
 
@@ -521,14 +564,12 @@ __global__ __launch_bounds__(DAG_THREADS) void k_chol_dag(DagArgs g) {
   double* L = g.L + (int64_t)b * g.slab;
   double* P = g.P + (int64_t)b * g.slab;
   const int64_t n = g.n;
-  Qd acc[4];
-  const int r = tid >> 3, c0 = tid & 7;
+  DAcc acc;
   if (fact) {
     // S = G_ij - sum_k L_ik L_jk^H, in k order
     dag_load(ta, G, n, i, j);
     __syncthreads();
-#pragma unroll
-    for (int s = 0; s < 4; ++s) acc[s] = dldq(ta, r, c0 + 8 * s);
+    acc_from_tile(acc, ta);
     __syncthreads();
     for (int k = 0; k < j; ++k) {
       dag_wait(g, dag_flag(g, b, 0, i, k), b, &timed_out);
@@ -536,56 +577,54 @@ __global__ __launch_bounds__(DAG_THREADS) void k_chol_dag(DagArgs g) {
       dag_load(ta, L, n, i, k);
       if (i != j) dag_load(tb, L, n, j, k);
       __syncthreads();
-      dag_mul_h(acc, ta, i != j ? tb : ta, -1.0);
+      dag_mfma(acc, ta, i != j ? tb : ta, true, -1.0);
       __syncthreads();
     }
-#pragma unroll
-    for (int s = 0; s < 4; ++s) dstq(ta, r, c0 + 8 * s, acc[s]);
+    acc_to_tile(ta, acc);
     __syncthreads();
     if (i == j) {
       const int w = (int)std::min<int64_t>(DTS, n - (int64_t)j * DTS);
       dag_potri(ta, db, w, &bad);
-#pragma unroll
-      for (int s = 0; s < 4; ++s) acc[s] = dldq(ta, r, c0 + 8 * s);
-      dag_store(P, n, j, j, acc);
+      dag_store_tile(P, n, j, j, ta);
       // the tiles of P right of the diagonal are zero
-      const Qd z[4] = {Qd{0, 0, 0, 0}, Qd{0, 0, 0, 0}, Qd{0, 0, 0, 0}, Qd{0, 0, 0, 0}};
-      for (int tj = j + 1; tj < nt; ++tj) dag_store(P, n, j, tj, z);
+      for (int tj = j + 1; tj < nt; ++tj) dag_store_zero(P, n, j, tj);
     } else {
       // L_ij = S P_jj^H (P_jj lower triangular)
       dag_wait(g, dag_flag(g, b, 0, j, j), b, &timed_out);
       dag_load(tb, P, n, j, j);
       __syncthreads();
-#pragma unroll
-      for (int s = 0; s < 4; ++s) acc[s] = Qd{0, 0, 0, 0};
-      dag_mul_h(acc, ta, tb, 1.0);
-      dag_store(L, n, i, j, acc);
+      acc_zero(acc);
+      dag_mfma(acc, ta, tb, true, 1.0);
+      __syncthreads();
+      acc_to_tile(ta, acc);
+      __syncthreads();
+      dag_store_tile(L, n, i, j, ta);
     }
     if (tid == 0 && (bad || timed_out)) atomicOr(g.fail + b, 1);
     if (tid == 0 && timed_out) atomicOr(g.status, ST_NUMERIC);
     dag_publish(dag_flag(g, b, 0, i, j));
   } else {
     // P_ij = -P_ii sum_{l=j}^{i-1} L_il P_lj, in l order
-#pragma unroll
-    for (int s = 0; s < 4; ++s) acc[s] = Qd{0, 0, 0, 0};
+    acc_zero(acc);
     for (int l = j; l < i; ++l) {
       dag_wait(g, dag_flag(g, b, 0, i, l), b, &timed_out);
       dag_wait(g, l == j ? dag_flag(g, b, 0, j, j) : dag_flag(g, b, 1, l, j), b, &timed_out);
       dag_load(ta, L, n, i, l);
       dag_load(tb, P, n, l, j);
       __syncthreads();
-      dag_mul_n(acc, ta, tb, 1.0);
+      dag_mfma(acc, ta, tb, false, 1.0);
       __syncthreads();
     }
-#pragma unroll
-    for (int s = 0; s < 4; ++s) dstq(tb, r, c0 + 8 * s, acc[s]);
+    acc_to_tile(tb, acc);
     dag_wait(g, dag_flag(g, b, 0, i, i), b, &timed_out);
     dag_load(ta, P, n, i, i);
     __syncthreads();
-#pragma unroll
-    for (int s = 0; s < 4; ++s) acc[s] = Qd{0, 0, 0, 0};
-    dag_mul_n(acc, ta, tb, -1.0);
-    dag_store(P, n, i, j, acc);
+    acc_zero(acc);
+    dag_mfma(acc, ta, tb, false, -1.0);
+    __syncthreads();
+    acc_to_tile(ta, acc);
+    __syncthreads();
+    dag_store_tile(P, n, i, j, ta);
     if (tid == 0 && timed_out) {
       atomicOr(g.fail + b, 1);
       atomicOr(g.status, ST_NUMERIC);
