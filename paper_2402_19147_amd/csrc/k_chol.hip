@@ -304,14 +304,15 @@ struct DagArgs {
   int64_t n, slab;
   int nb, nt;
   int64_t nfact;    // factor tasks: nb * nt (nt + 1) / 2
-  int* flags;       // [nb][2][nt][nt]: 0 = L tile (and P_jj for a diagonal tile), 1 = P tile
+  int* flags;       // [nb][3][nt][nt]: 0 = L tile (and P_jj for a diagonal tile), 1 = P tile,
+                    // 2 = S_{j+1,j} (the factor task's tile before its multiply by P_jj^H)
   int* ticket;
   int* fail;        // [nb]
   unsigned* status;
 };
 
 __device__ inline int* dag_flag(const DagArgs& g, int b, int kind, int i, int j) {
-  return g.flags + (((int64_t)b * 2 + kind) * g.nt + i) * g.nt + j;
+  return g.flags + (((int64_t)b * 3 + kind) * g.nt + i) * g.nt + j;
 }
 
 // Thread 0 waits for a flag (bounded); then every thread fences (acquire).
@@ -375,6 +376,34 @@ __device__ inline void dag_store_zero(double* __restrict__ M, int64_t n, int ti,
 #pragma unroll
       for (int q = 0; q < 4; ++q) M[o + q * ps] = 0.0;
     }
+  }
+}
+
+// The tile S_{i,j} (j < i) kept in the unused upper slot (j, i) of L,
+// transposed (its element (r, c) at row 32 j + c, column 32 i + r), so that
+// the rows of S past n, the ones a partial last tile row i pads with, are the
+// ones not stored
+__device__ inline void dag_store_tile_t(double* __restrict__ M, int64_t n, int tj, int ti, const DTile& t) {
+  const int64_t ps = n * n;
+  for (int e = threadIdx.x; e < DTS * DTS; e += DAG_THREADS) {
+    const int c = e / DTS, r = e % DTS;
+    const int64_t gi = (int64_t)tj * DTS + c, gj = (int64_t)ti * DTS + r;
+    if (gi < n && gj < n) {
+      const int64_t o = gi * n + gj;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) M[o + q * ps] = t[q][r][c];
+    }
+  }
+}
+__device__ inline void dag_load_t(DTile& t, const double* __restrict__ M, int64_t n, int tj, int ti) {
+  const int64_t ps = n * n;
+  for (int e = threadIdx.x; e < DTS * DTS; e += DAG_THREADS) {
+    const int c = e / DTS, r = e % DTS;
+    const int64_t gi = (int64_t)tj * DTS + c, gj = (int64_t)ti * DTS + r;
+    const bool ok = gi < n && gj < n;
+    const int64_t o = gi * n + gj;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) t[q][r][c] = ok ? M[o + q * ps] : 0.0;
   }
 }
 
@@ -572,6 +601,26 @@ __global__ __launch_bounds__(DAG_THREADS) void k_chol_dag(DagArgs g) {
     acc_from_tile(acc, ta);
     __syncthreads();
     for (int k = 0; k < j; ++k) {
+      if (i == j && k == j - 1) {
+        // the last tile of the row, L_{j,j-1} = S_{j,j-1} P_{j-1,j-1}^H, is
+        // formed here from the factor task's S (the same operands and the
+        // same products, so bit for bit its tile) instead of waiting for
+        // that task to publish it: one dependency hop less per diagonal step
+        dag_wait(g, dag_flag(g, b, 2, j, k), b, &timed_out);
+        dag_wait(g, dag_flag(g, b, 0, k, k), b, &timed_out);
+        dag_load_t(tb, L, n, k, j);
+        dag_load(ta, P, n, k, k);
+        __syncthreads();
+        DAcc lt;
+        acc_zero(lt);
+        dag_mfma(lt, tb, ta, true, 1.0);
+        __syncthreads();
+        acc_to_tile(ta, lt);
+        __syncthreads();
+        dag_mfma(acc, ta, ta, true, -1.0);
+        __syncthreads();
+        continue;
+      }
       dag_wait(g, dag_flag(g, b, 0, i, k), b, &timed_out);
       if (i != j) dag_wait(g, dag_flag(g, b, 0, j, k), b, &timed_out);
       dag_load(ta, L, n, i, k);
@@ -582,6 +631,11 @@ __global__ __launch_bounds__(DAG_THREADS) void k_chol_dag(DagArgs g) {
     }
     acc_to_tile(ta, acc);
     __syncthreads();
+    if (i == j + 1) {
+      // S_{j+1,j} for the next diagonal task
+      dag_store_tile_t(L, n, j, i, ta);
+      dag_publish(dag_flag(g, b, 2, i, j));
+    }
     if (i == j) {
       const int w = (int)std::min<int64_t>(DTS, n - (int64_t)j * DTS);
       dag_potri(ta, db, w, &bad);
@@ -635,7 +689,7 @@ __global__ __launch_bounds__(DAG_THREADS) void k_chol_dag(DagArgs g) {
 
 size_t chol_dag_flag_ints(int nb, int64_t n) {
   const int64_t nt = (n + DTS - 1) / DTS;
-  return (size_t)nb * 2 * nt * nt + 1;
+  return (size_t)nb * 3 * nt * nt + 1;
 }
 
 hipError_t launch_chol_dag(const Ctx& c, const double* G, double* L, double* P, int64_t n, int64_t slab, int nb,
