@@ -59,6 +59,16 @@ __device__ inline void stq(Tile& a, int i, int j, Qd v) {
   a[2][i][j] = v.y;
   a[3][i][j] = v.z;
 }
+// tiles of the tile-task factorisation below (32 x 32 quaternions)
+constexpr int DTS = 32;  // tile edge
+typedef double DTile[4][DTS][DTS + 1];
+__device__ inline Qd ldq(const DTile& a, int i, int j) { return Qd{a[0][i][j], a[1][i][j], a[2][i][j], a[3][i][j]}; }
+__device__ inline void stq(DTile& a, int i, int j, Qd v) {
+  a[0][i][j] = v.w;
+  a[1][i][j] = v.x;
+  a[2][i][j] = v.y;
+  a[3][i][j] = v.z;
+}
 __device__ inline void qacc(Qd& s, Qd u) {
   s.w += u.w;
   s.x += u.x;
@@ -67,7 +77,8 @@ __device__ inline void qacc(Qd& s, Qd u) {
 }
 // Element (r, c) (r >= c) of the inverse of diagonal block at kb: 1/L on the
 // diagonal, else kept transposed in the block's upper triangle.
-__device__ inline Qd pdiag(const Tile& a, const double* rdg, int kb, int r, int c) {
+template <typename TileT>
+__device__ inline Qd pdiag(const TileT& a, const double* rdg, int kb, int r, int c) {
   return r == c ? Qd{rdg[kb + r], 0.0, 0.0, 0.0} : ldq(a, kb + c, kb + r);
 }
 
@@ -102,7 +113,8 @@ __device__ inline void stq4(double* p, Qd v) {
 // of X (c <= j), so the thread keeps one value; column j and row j travel
 // through LDS with one barrier per pivot, and every thread issues all of its
 // reads right after the barrier.
-__device__ void chol_diag(Tile& a, double* rdg, DiagBuf& db, int kb, int kw, int tid, int* bad) {
+template <typename TileT>
+__device__ void chol_diag(TileT& a, double* rdg, DiagBuf& db, int kb, int kw, int tid, int* bad) {
   const int i = tid >> 4, c = tid & 15;
   const bool in = tid < SB * SB && i < kw && c <= i;
   Qd x = in ? ldq(a, kb + i, kb + c) : Qd{0, 0, 0, 0};
@@ -292,10 +304,8 @@ hipError_t launch_chol_block(const Ctx& c, const double* G, double* P, int w, in
 // past the spin limit the task goes on, marks its matrix as failed (the
 // caller then takes the Jacobi path) and raises ST_NUMERIC.  Sums run in a
 // fixed order, so results do not depend on scheduling.
-constexpr int DTS = 32;  // tile edge
 constexpr int DAG_THREADS = 256;
 constexpr long DAG_SPIN_LIMIT = 1L << 22;
-typedef double DTile[4][DTS][DTS + 1];
 
 struct DagArgs {
   const double* G;  // lower triangles; matrix b at G + b * slab, row stride n, plane stride n * n
@@ -483,83 +493,73 @@ __device__ inline void dag_mfma(DAcc& acc, const DTile& X, const DTile& Y, bool 
 }
 
 // Factor and invert the 32 x 32 diagonal tile held in T (lower triangle;
-// entries past the matrix edge, rows >= w, are treated as the identity):
-// the elementary steps of chol_diag over 32 pivots, the lower triangle in
-// registers (elements tid + 256 s of the square), column j and row j of each
-// pivot published through LDS with one barrier per pivot.  On return T holds
-// P = L^{-1} (lower, upper part zero).  A pivot that is not finite and
-// positive sets *bad.
+// entries past the matrix edge, rows >= w, are made the identity), blocked
+// by 16: T = [A 0; B D] = L L^H with
+//   A = L_A L_A^H (chol_diag: P_A = L_A^{-1}),  L_B = B P_A^H,
+//   D - L_B L_B^H = L_D L_D^H (chol_diag: P_D),
+//   P = L^{-1} = [P_A 0; -P_D L_B P_A  P_D],
+// the 16 x 16 products one element per thread.  On return T holds P (lower,
+// upper part zero).  A pivot that is not finite and positive sets *bad.
 struct DagDiag {
-  double col[2][DTS][4];
-  double row[2][DTS][4];
-  double piv[2][4];  // [0]: 1 / d_j
-  double rs[DTS];
+  DiagBuf d;
+  double rdg[DTS];
 };
 __device__ void dag_potri(DTile& T, DagDiag& db, int w, int* bad) {
   const int tid = threadIdx.x;
-  Qd x[4];
-  bool in[4];
-  int ei[4], ec[4];
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int e = tid + DAG_THREADS * s;
-    ei[s] = e / DTS;
-    ec[s] = e % DTS;
-    in[s] = ec[s] <= ei[s];
-    Qd v = in[s] ? dldq(T, ei[s], ec[s]) : Qd{0, 0, 0, 0};
-    if (ei[s] >= w) v = ei[s] == ec[s] ? Qd{1, 0, 0, 0} : Qd{0, 0, 0, 0};  // identity past the edge
-    if (ec[s] >= w && ei[s] != ec[s]) v = Qd{0, 0, 0, 0};
-    x[s] = v;
-  }
-  for (int j = 0; j < DTS; ++j) {
-    const int par = j & 1;
-    // publish column j below the pivot, row j left of it, and 1/sqrt(d_j)
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const bool cj = in[s] && ec[s] == j;
-      if (cj && ei[s] == j) {
-        const bool ok = x[s].w > 0.0 && x[s].w < INFINITY;
-        const double r = rsqrt_nr(ok ? x[s].w : 1.0);
-        db.piv[par][0] = r * r;
-        db.rs[j] = r;
-        if (!ok) *bad = 1;
+  if (tid >= w && tid < DTS) T[0][tid][tid] = 1.0;  // identity past the edge (the rest there is zero)
+  __syncthreads();
+  chol_diag(T, db.rdg, db.d, 0, SB, tid, bad);
+  __syncthreads();
+  const int bi = SB + (tid >> 4), bc = tid & 15;  // this thread's element of the lower-left block
+  // L_B[i][c] = sum_{t <= c} B[i][t] conj(P_A[c][t])
+  Qd s{0, 0, 0, 0};
+  for (int t = 0; t <= bc; ++t) qacc(s, qmul_conj(ldq(T, bi, t), pdiag(T, db.rdg, 0, bc, t)));
+  __syncthreads();
+  stq(T, bi, bc, s);
+  __syncthreads();
+  // D[i][c] -= sum_t L_B[i][t] conj(L_B[c][t]) on the lower triangle of D
+  {
+    const int di = SB + (tid >> 4), dc = SB + (tid & 15);
+    if (dc <= di) {
+      Qd u = ldq(T, di, dc);
+      for (int t = 0; t < SB; ++t) {
+        const Qd v = qmul_conj(ldq(T, di, t), ldq(T, dc, t));
+        u = Qd{u.w - v.w, u.x - v.x, u.y - v.y, u.z - v.z};
       }
-      if (cj && ei[s] > j) stq4(db.col[par][ei[s]], x[s]);
-      if (in[s] && ei[s] == j && ec[s] < j) stq4(db.row[par][ec[s]], x[s]);
-    }
-    __syncthreads();
-    // reads from in-range slots, with no branch around them (stale ones are
-    // never used: the updates select, so they cannot reach the arithmetic)
-    const double rd = db.piv[par][0];
-    Qd ar[4], vv[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      ar[s] = ldq4(db.col[par][ei[s]]);
-      vv[s] = ldq4(ec[s] > j ? db.col[par][ec[s]] : db.row[par][ec[s]]);
-    }
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int i = ei[s], c = ec[s];
-      const bool act = in[s] && i > j;
-      const Qd u{ar[s].w * rd, ar[s].x * rd, ar[s].y * rd, ar[s].z * rd};
-      // c > j: A_ic -= u conj(A_cj);  c < j: X_ic -= u X_jc;  c == j: X_ij = -u
-      const Qd v = c > j ? Qd{vv[s].w, -vv[s].x, -vv[s].y, -vv[s].z} : vv[s];
-      const Qd q = qmul(u, v);
-      Qd nx{x[s].w - q.w, x[s].x - q.x, x[s].y - q.y, x[s].z - q.z};
-      if (c == j) nx = Qd{-u.w, -u.x, -u.y, -u.z};
-      if (act) x[s] = nx;
+      stq(T, di, dc, u);
     }
   }
   __syncthreads();
-  // P = diag(d^{-1/2}) (X + I)
+  chol_diag(T, db.rdg, db.d, SB, SB, tid, bad);
+  __syncthreads();
+  // W = L_B P_A (P_A lower: t >= c), then Y = -P_D W (P_D lower: t <= i)
+  s = Qd{0, 0, 0, 0};
+  for (int t = bc; t < SB; ++t) qacc(s, qmul(ldq(T, bi, t), pdiag(T, db.rdg, 0, t, bc)));
+  __syncthreads();
+  stq(T, bi, bc, s);
+  __syncthreads();
+  s = Qd{0, 0, 0, 0};
+  for (int t = SB; t <= bi; ++t) qacc(s, qmul(pdiag(T, db.rdg, SB, bi - SB, t - SB), ldq(T, t, bc)));
+  __syncthreads();
+  stq(T, bi, bc, Qd{-s.w, -s.x, -s.y, -s.z});
+  __syncthreads();
+  // P into the lower triangle, zeros above
+  Qd v[4];
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int i = ei[s], c = ec[s];
-    const double r = db.rs[i];
-    Qd v{0, 0, 0, 0};
-    if (c < i) v = Qd{x[s].w * r, x[s].x * r, x[s].y * r, x[s].z * r};
-    else if (c == i) v = Qd{r, 0, 0, 0};
-    dstq(T, i, c, v);
+  for (int k = 0; k < 4; ++k) {
+    const int e = tid + DAG_THREADS * k, r = e / DTS, c = e % DTS;
+    v[k] = Qd{0, 0, 0, 0};
+    if (c <= r) {
+      if (r < SB) v[k] = pdiag(T, db.rdg, 0, r, c);
+      else if (c >= SB) v[k] = pdiag(T, db.rdg, SB, r - SB, c - SB);
+      else v[k] = ldq(T, r, c);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int e = tid + DAG_THREADS * k;
+    stq(T, e / DTS, e % DTS, v[k]);
   }
   __syncthreads();
 }
