@@ -588,6 +588,16 @@ qcur_status pinv_jacobi_qp(const Ctx& c, QView X, double rtol, int64_t max_rank,
 // (pp_b x qq_b, orthonormal or zero columns) and P_b (qq_b x qq_b) left in
 // the views Qv[b], Pv[b] inside the group workspace.  CholeskyQR2 where its
 // certificate holds, else the Jacobi SVD.
+// Matrices that skip the CholeskyQR attempt and go straight to the Jacobi
+// SVD: those that fit one workgroup's LDS and whose rank is capped below
+// their order (the certificate would reject the fast path anyway).  Small
+// matrices without a cap take the fast path first: the one-workgroup Jacobi
+// costs about a millisecond at 300 x 16, the CholeskyQR group tens of
+// microseconds.
+bool jacobi_direct(const PinvPlan& pl, int64_t max_rank) {
+  return jacobi_small_fits(pl.pp, pl.qq) && max_rank > 0 && max_rank < pl.qq;
+}
+
 qcur_status pinv_group_qp(const Ctx& c, int nb, const QView* X, double rtol, int64_t max_rank,
                           int64_t* const* rank_out, GroupWs& gw, PinvWs jw, QView* Qv, QView* Pv,
                           double orth_tol, PinvSpec* spec = nullptr) {
@@ -607,7 +617,7 @@ qcur_status pinv_group_qp(const Ctx& c, int nb, const QView* X, double rtol, int
       Pv[b] = QView{gw.P, 0, 0, 1, 1, QCUR_F64};
       continue;
     }
-    if (jacobi_small_fits(pl.pp, pl.qq)) {
+    if (jacobi_direct(pl, max_rank)) {
       HIPCHK(launch_check_finite(c, X[b]));  // the CholeskyQR group checks in its cast
       small[ns++] = b;
       continue;
@@ -665,7 +675,7 @@ qcur_status pinv_group(const Ctx& c, int nb, const QView* X, double rtol, int64_
       if (rank_out[b]) HIPCHK(launch_zero(c, (double*)rank_out[b], 1));
       continue;
     }
-    if (jacobi_small_fits(pl.pp, pl.qq)) {
+    if (jacobi_direct(pl, max_rank)) {
       HIPCHK(launch_check_finite(c, X[b]));  // the CholeskyQR group checks in its cast
       CHK(pinv_jacobi(c, X[b], rt[b], max_rank, Xp[b], rank_out[b], jw));
       continue;
