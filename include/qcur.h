@@ -167,10 +167,17 @@ qcur_status qcur_gather(qcur_handle handle, const qcur_qmat* A, const int64_t* I
  * Route: with Z = X (p >= q) or X^H, FP64 CholeskyQR2 (Z = Q T, X^+ from
  * Q and T^{-1}) when its full-rank certificate holds (Cholesky succeeds,
  * kappa_F(Z) below 1e7 and kappa_F * rtol below 1e-2) and no rank cap
- * applies; otherwise, and for matrices small enough for one workgroup,
- * one-sided (Hestenes) Jacobi on quaternion columns.  Synchronises the
- * stream once to read the certificate, and on the Jacobi route once per
- * sweep to test convergence.
+ * applies.  A cap k with 2k <= min(p, q) (Algorithm 1's predefined rank)
+ * on a matrix too large for one workgroup: subspace iteration (a fixed
+ * pseudo-random sketch, CholeskyQR2 of the p x k and q x k iterates), kept
+ * when an a posteriori bound (Davis-Kahan on the Rayleigh-Ritz residual,
+ * then Wedin's pseudoinverse perturbation bound) puts the result within
+ * 2^-30 relative of the k-truncated pseudoinverse, at most three
+ * iterations.  Otherwise, and for matrices small enough for one
+ * workgroup, one-sided (Hestenes) Jacobi on quaternion columns.
+ * Synchronises the stream once to read the certificate (three to four
+ * times per iteration on the capped route), and on the Jacobi route once
+ * per sweep to test convergence.
  * ws: qcur_pinv_workspace(p, q) bytes.  Non-finite input raises
  * QCUR_ERR_NUMERIC in the status word. */
 qcur_status qcur_pinv(qcur_handle handle, const qcur_qmat* X, double rtol, int64_t max_rank,

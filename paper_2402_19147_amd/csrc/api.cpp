@@ -598,6 +598,125 @@ bool jacobi_direct(const PinvPlan& pl, int64_t max_rank) {
   return jacobi_small_fits(pl.pp, pl.qq) && max_rank > 0 && max_rank < pl.qq;
 }
 
+// Rank-capped pseudoinverse (cap k, 2k <= min(p, q), FP64) by subspace
+// iteration in place of the Jacobi SVD of the whole matrix (Algorithm 1's
+// predefined rank k; the truncated pseudoinverse X_k^+ of Section 2.1):
+//   Q = orth(X S)   (S a fixed pseudo-random q x k sketch, one CholeskyQR pass)
+//   repeat:  V = orth(X^H Q) (CholeskyQR2),  Y = X V = Q T (CholeskyQR2), P = T^{-H}
+// and X^+ ~ V Y^+ = V (Q P)^H, the pseudoinverse of X V V^H.  Each iteration
+// ends in an a posteriori bound on the relative distance of that result from
+// X_k^+: with G = X^H X, the Rayleigh-Ritz residual R = G V - V (Y^H Y) and
+// the separation delta = 1/||P||_F^2 - (||X||_F^2 - ||Y||_F^2) (a lower
+// bound on the smallest eigenvalue of Y^H Y minus an upper bound on the
+// (k+1)-th of G), the Davis-Kahan theorem gives ||sin Theta(V, V_k)||_F <=
+// ||R||_F / delta; then ||X V V^H - X_k||_F <= 2 sigma_1 ||sin Theta||_F, and
+// pseudoinverses of equal-rank matrices move by at most sqrt(2) ||A^+||_2
+// ||B^+||_2 ||A - B||_F (Wedin), so the relative distance is at most
+//   2 sqrt(2) ||X||_F ||P||_F ||R||_F / delta.
+// Accepted below 2^-30 (CholeskyQR's own certificates holding too); up to
+// three iterations while the bound at least halves, else the Jacobi SVD.  A
+// rank below k, a small gap sigma_k / sigma_{k+1} or a cap that cuts
+// through a cluster of singular values all end there.
+constexpr double LOWRANK_TOL = 0x1p-30;
+constexpr int LOWRANK_ITERS = 3;
+constexpr uint64_t LOWRANK_SEED = 0x2402191470ull;
+
+struct LowrankWs {
+  GroupWs g;  // CholeskyQR of the p x k and q x k matrices
+  double *A1, *A2, *A3, *A4, *sums;
+};
+
+bool lowrank_route(const PinvPlan& pl, int64_t max_rank, int dt) {
+  return dt == QCUR_F64 && max_rank > 0 && 2 * max_rank <= pl.qq;
+}
+
+// The route's buffers lie over the Jacobi buffers Y and V and over the
+// CholeskyQR group of the whole matrix, neither of which is in use while it
+// runs.  False when they do not fit.
+bool lowrank_carve(const PinvPlan& pl, int64_t k, const PinvWs& jw, const GroupWs& gw, LowrankWs* w) {
+  Bump cg(nullptr), cl(nullptr);
+  group_carve(cg, 1, pl.pp, pl.qq);
+  group_carve(cl, 1, pl.pp, k);
+  if (cl.used > cg.used) return false;
+  Bump gb(gw.Z);
+  w->g = group_carve(gb, 1, pl.pp, k);
+  const size_t avail = (size_t)((char*)jw.V - (char*)jw.Y) + (size_t)4 * pl.qq * pl.qq * 8;
+  Bump ab(jw.Y);
+  w->A1 = (double*)ab.take((size_t)4 * pl.pp * k * 8);
+  w->A2 = (double*)ab.take((size_t)4 * pl.q * k * 8);
+  w->A3 = (double*)ab.take((size_t)4 * pl.p * k * 8);
+  w->A4 = (double*)ab.take((size_t)4 * k * k * 8);
+  w->sums = (double*)ab.take(4 * 8);
+  return ab.used <= avail;
+}
+
+qcur_status pinv_lowrank(const Ctx& c, QView X, double rtol, int64_t k, QView Xp, int64_t* rank_out,
+                         const PinvWs& jw, const GroupWs& gw, bool* accepted) {
+  *accepted = false;
+  const PinvPlan pl = pinv_plan(X.rows, X.cols);
+  LowrankWs w;
+  if (!lowrank_carve(pl, k, jw, gw, &w)) return QCUR_OK;
+  const int64_t p = X.rows, q = X.cols, slot = pl.pp * k;
+  auto mat = [](double* base, int64_t rows, int64_t cols) {
+    return QView{base, rows, cols, cols, rows * cols, QCUR_F64};
+  };
+  const QView S = mat(w.A1, q, k), R = mat(w.A1, q, k), T1 = mat(w.A1, p, k);
+  const QView V = mat(w.A2, q, k), Y = mat(w.A3, p, k), Hm = mat(w.A4, k, k);
+  void* gws = jw.gws;
+  const size_t gwb = jw.gws_bytes;
+  int64_t* none[1] = {nullptr};
+  int64_t* ro[1] = {rank_out};
+  bool done = false;
+  HIPCHK(launch_check_finite(c, X));
+  HIPCHK(launch_sumsq_batch(c, 1, &X, w.g.part, w.sums + 0, 1));
+  HIPCHK(launch_sketch(c, S, LOWRANK_SEED));
+  HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, X, S, 0.0, Y, QCUR_F64, gws, gwb));
+  CHK(pinv_fast_group(c, 1, &Y, rtol, 0, nullptr, none, w.g, 1, &done));
+  if (!done) return QCUR_OK;
+  QView Qc{w.g.Q1, p, k, k, slot, QCUR_F64};
+  double last = INFINITY;
+  for (int it = 0; it < LOWRANK_ITERS; ++it) {
+    // V = orth(X^H Q), moved out of the group, which Y's factorisation reuses
+    HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, X, Qc, 0.0, V, QCUR_F64, gws, gwb));
+    CHK(pinv_fast_group(c, 1, &V, rtol, 0, nullptr, none, w.g, 2, &done));
+    if (!done) return QCUR_OK;
+    HIPCHK(launch_cast(c, QView{w.g.Q, q, k, k, slot, QCUR_F64}, V, CAST_COPY));
+    // Y = X V, H = Y^H Y, R = X^H Y - V H and their norms
+    HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, X, V, 0.0, Y, QCUR_F64, gws, gwb));
+    HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, Y, Y, 0.0, Hm, QCUR_F64, gws, gwb));
+    HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, X, Y, 0.0, R, QCUR_F64, gws, gwb));
+    HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, -1.0, V, Hm, 1.0, R, QCUR_F64, gws, gwb));
+    HIPCHK(launch_sumsq_batch(c, 1, &R, w.g.part, w.sums + 1, 1));
+    HIPCHK(launch_sumsq_batch(c, 1, &Y, w.g.part, w.sums + 2, 1));
+    // Y = Q T with its certificate (this waits for the stream)
+    CHK(pinv_fast_group(c, 1, &Y, rtol, 0, nullptr, ro, w.g, 2, &done));
+    if (!done) return QCUR_OK;
+    double h[3], nrm[4];
+    HIPCHK(hipMemcpyAsync(h, w.sums, sizeof(h), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipMemcpyAsync(nrm, w.g.norms, sizeof(nrm), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    const double nx2 = h[0], rho2 = h[1], ny2 = h[2], pf2 = nrm[2];
+    // the tail ||X||_F^2 - ||Y||_F^2 with room for the rounding of both sums
+    const double eta2 = std::max(0.0, nx2 - ny2) + 0x1p-46 * (double)(p + q) * nx2;
+    const double delta = 1.0 / pf2 - eta2;
+    const double bound = delta > 0.0 ? 2.0 * std::sqrt(2.0) * std::sqrt(nx2 * pf2 * rho2) / delta : INFINITY;
+    if (bound <= LOWRANK_TOL) {
+      // X^+ = V (Q P)^H
+      BatchSpec lo;
+      lo.tri = TRI_B_LOWER;
+      HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_N, 1.0, QView{w.g.Q, p, k, k, slot, QCUR_F64},
+                                 QView{w.g.P, k, k, k, k * k, QCUR_F64}, 0.0, T1, QCUR_F64, gws, gwb, lo));
+      HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_H, 1.0, V, T1, 0.0, Xp, QCUR_F64, gws, gwb));
+      *accepted = true;
+      return QCUR_OK;
+    }
+    if (!(bound < 0.5 * last)) return QCUR_OK;
+    last = bound;
+    Qc = QView{w.g.Q, p, k, k, slot, QCUR_F64};
+  }
+  return QCUR_OK;
+}
+
 qcur_status pinv_group_qp(const Ctx& c, int nb, const QView* X, double rtol, int64_t max_rank,
                           int64_t* const* rank_out, GroupWs& gw, PinvWs jw, QView* Qv, QView* Pv,
                           double orth_tol, PinvSpec* spec = nullptr) {
@@ -678,6 +797,14 @@ qcur_status pinv_group(const Ctx& c, int nb, const QView* X, double rtol, int64_
     if (jacobi_direct(pl, max_rank)) {
       HIPCHK(launch_check_finite(c, X[b]));  // the CholeskyQR group checks in its cast
       CHK(pinv_jacobi(c, X[b], rt[b], max_rank, Xp[b], rank_out[b], jw));
+      continue;
+    }
+    if (lowrank_route(pl, max_rank, X[b].dt) && nb == 1) {
+      // a rank cap: subspace iteration, else the Jacobi SVD (the CholeskyQR
+      // certificate of the whole matrix would reject it)
+      bool ok = false;
+      CHK(pinv_lowrank(c, X[b], rt[b], max_rank, Xp[b], rank_out[b], jw, gw, &ok));
+      if (!ok) CHK(pinv_jacobi(c, X[b], rt[b], max_rank, Xp[b], rank_out[b], jw));
       continue;
     }
     fx[nf] = X[b];

@@ -489,6 +489,27 @@ hipError_t launch_fill_identity(const Ctx& c, double* V, int64_t q) {
   return hipGetLastError();
 }
 
+// Entry t of the flat four-plane array: the SplitMix64 output function of
+// seed + (t + 1) * 0x9E3779B97F4A7C15, its top 53 bits scaled to [-1, 1).
+__global__ void k_sketch(double* S, int64_t total, uint64_t seed) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= total) return;
+  uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(t + 1);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  S[t] = (double)(z >> 11) * 0x1p-52 - 1.0;
+}
+
+hipError_t launch_sketch(const Ctx& c, QView S, uint64_t seed) {
+  if (S.dt != QCUR_F64 || S.ld != S.cols || S.ps != S.rows * S.cols) return hipErrorInvalidValue;
+  const int64_t total = 4 * S.rows * S.cols;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sketch, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c.stream, (double*)S.p, total,
+                     seed);
+  return hipGetLastError();
+}
+
 // Y = alpha X + beta Y, elementwise over four planes (any dtypes).
 __global__ void k_axpby(double alpha, const void* X, int xdt, int64_t xld, int64_t xps, double beta, void* Y,
                         int ydt, int64_t yld, int64_t yps, int64_t rows, int64_t cols) {

@@ -191,6 +191,10 @@ hipError_t launch_pinv_scale(const Ctx& c, double* Y, int64_t p, int64_t q, doub
                              int64_t max_rank, int64_t* rank_out, double* sig);
 hipError_t launch_check_finite(const Ctx& c, QView X);
 hipError_t launch_fill_identity(const Ctx& c, double* V, int64_t q);
+// Fixed pseudo-random sketch: every entry of the four planes of S (FP64,
+// contiguous rows, plane stride rows * cols) uniform in [-1, 1), a function
+// of the seed and the entry's flat index only.
+hipError_t launch_sketch(const Ctx& c, QView S, uint64_t seed);
 hipError_t launch_pinv_apply(const Ctx& c, double* Y, int64_t p, int64_t q, double* V, const double* dsc);
 // Orthonormal-form output of the Jacobi pseudoinverse: Z^+ = P^H Q^H with
 // Q (p x q, orthonormal or zero columns) and P (q x q), both FP64.

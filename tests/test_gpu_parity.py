@@ -358,13 +358,13 @@ def test_pinv_ill_conditioned_falls_back():
     ref, k = oracle.qpinv(X)
     assert int(N(rank)[0]) == k == 70
     assert rel(N(Xp), ref) < 64 * 2.0 ** -52 * 1e9
-    Xp2, rank2 = Q.pinv(T(X), max_rank=20)      # a rank cap also disables the fast path
+    Xp2, rank2 = Q.pinv(T(X), max_rank=20)      # no gap at the cap: subspace iteration gives way to Jacobi
     ref2, k2 = oracle.qpinv(X, max_rank=20)
     assert int(N(rank2)[0]) == k2 == 20
     assert rel(N(Xp2), ref2) < 1e-9
 
 
-@pytest.mark.parametrize("p,q,k,mr", [(256, 256, 64, 64), (256, 256, 64, 0), (300, 230, 45, 0)])
+@pytest.mark.parametrize("p,q,k,mr", [(256, 256, 64, 0), (300, 230, 45, 0)])
 def test_pinv_rank_deficient_deflated_jacobi(p, q, k, mr):
     # exact-rank products of Gaussian factors (the differentiation workload's
     # W = A(I, J)): multi-launch Jacobi sweeps with the pairs of rounding-noise
@@ -376,6 +376,35 @@ def test_pinv_rank_deficient_deflated_jacobi(p, q, k, mr):
     assert int(N(rank)[0]) == kr == k
     assert rel(N(Xp), ref) < 1e-10
     assert rel(qmul(qmul(X, N(Xp)), X), X) < 1e-11
+
+
+@pytest.mark.parametrize("p,q,k,mr,noise", [
+    (256, 256, 64, 64, 0.0),      # the differentiation workload's W = A(I, J): exact rank 64
+    (256, 256, 64, 64, "f32"),    # the same with FP32-rounded entries (a tail near 1e-7 of sigma_1)
+    (400, 300, 40, 40, 1e-9),     # tall, rank 40 plus a small full-rank tail
+    (200, 520, 30, 30, 0.0),      # wide
+    (256, 256, 64, 20, 0.0),      # a cap below the rank cuts into the spectrum
+    (256, 256, 40, 64, 0.0),      # rank below the cap: the sketch is rank-deficient, Jacobi takes over
+])
+def test_pinv_rank_capped_subspace_route(p, q, k, mr, noise):
+    # a rank cap k with 2k <= min(p, q): subspace iteration with its a posteriori
+    # bound, else the Jacobi SVD; either way the truncated pseudoinverse
+    rng = np.random.default_rng(p + 3 * q + k + mr)
+    X = qmul(rng.standard_normal((4, p, k)), rng.standard_normal((4, k, q)))
+    if noise == "f32":
+        X = X.astype(np.float32).astype(np.float64)
+    elif noise:
+        X = X + noise * rng.standard_normal(X.shape)
+    Xp, rank = Q.pinv(T(X), max_rank=mr)
+    ref, kr = oracle.qpinv(X, max_rank=mr)
+    assert int(N(rank)[0]) == kr == min(k, mr)
+    from oracle.pinv import singular_values
+    sv = singular_values(X)
+    # the kept pairs carry ~eps * sigma_1 / sigma_k; a cut inside the spectrum
+    # also moves the subspace by ~eps * sigma_1 / (sigma_k - sigma_{k+1})
+    gap = sv[kr - 1] - sv[kr] if kr < len(sv) else sv[kr - 1]
+    tol = max(1e-10, 64 * 2.0 ** -52 * sv[0] ** 2 / (sv[kr - 1] * gap))
+    assert rel(N(Xp), ref) < tol
 
 
 @pytest.mark.parametrize("shape,k,mr", [((256, 256), 64, 64), ((300, 230), 45, 0), ((1024, 200), 0, 0),
