@@ -118,7 +118,14 @@ __device__ void chol_diag(TileT& a, double* rdg, DiagBuf& db, int kb, int kw, in
   const int i = tid >> 4, c = tid & 15;
   const bool in = tid < SB * SB && i < kw && c <= i;
   Qd x = in ? ldq(a, kb + i, kb + c) : Qd{0, 0, 0, 0};
+  // the exchange slots start at zero, so that every read below returns a
+  // value of the matrix (finite for a finite matrix) and the factors that
+  // switch a term off can be plain multiplications by zero
+  for (int e = tid; e < (int)(sizeof(DiagBuf) / sizeof(double)); e += 256)
+    if (tid < 256) reinterpret_cast<double*>(&db)[e] = 0.0;
+  __syncthreads();
   double rsi = 1.0;
+  bool failed = false;
   for (int j = 0; j < kw; ++j) {
     const int par = j & 1;
     if (in && c == j) {
@@ -132,24 +139,26 @@ __device__ void chol_diag(TileT& a, double* rdg, DiagBuf& db, int kb, int kw, in
     }
     if (in && i == j && c < j) stq4(db.row[par][c], x);
     __syncthreads();
+    // all three reads are unconditional and issued together
     const Qd piv = ldq4(db.col[par][j]);
     const Qd ar = ldq4(db.col[par][i & (SB - 1)]);
     const Qd vr = ldq4(c > j ? db.col[par][c] : db.row[par][c]);
     const double rs = piv.x, rd = piv.y;
     const bool act = in && i > j, ret = c == j;
-    // inactive rows take u = 0 and the retiring column v = 0 (selects, so
-    // that stale LDS contents never reach the arithmetic); then one fused
+    // inactive rows take u = 0 and the retiring column v = 0; then one fused
     // form covers the three cases with the roundings of the plain formulas
-    const Qd u = act ? Qd{ar.w * rd, ar.x * rd, ar.y * rd, ar.z * rd} : Qd{0, 0, 0, 0};
-    const double sg = c > j ? -1.0 : 1.0;
-    const Qd v = ret ? Qd{0, 0, 0, 0} : Qd{vr.w, sg * vr.x, sg * vr.y, sg * vr.z};
+    const double fu = act ? rd : 0.0;
+    const Qd u = Qd{ar.w * fu, ar.x * fu, ar.y * fu, ar.z * fu};
+    const double f0 = ret ? 0.0 : 1.0, f1 = ret ? 0.0 : (c > j ? -1.0 : 1.0);
+    const Qd v = Qd{vr.w * f0, vr.x * f1, vr.y * f1, vr.z * f1};
     const Qd q = qmul(u, v);
     const double m = ret && act ? -rd : 1.0;
     x = Qd{__builtin_fma(x.w, m, -q.w), __builtin_fma(x.x, m, -q.x), __builtin_fma(x.y, m, -q.y),
            __builtin_fma(x.z, m, -q.z)};
     rsi = i == j ? rs : rsi;
-    if (tid == 0 && piv.z != 0.0) *bad = 1;
+    failed |= piv.z != 0.0;
   }
+  if (tid == 0 && failed) *bad = 1;
   if (in) {
     if (c < i)
       stq(a, kb + c, kb + i, Qd{x.w * rsi, x.x * rsi, x.y * rsi, x.z * rsi});
