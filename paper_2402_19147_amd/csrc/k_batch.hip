@@ -121,7 +121,11 @@ hipError_t launch_norms_batch(const Ctx& c, int count, Slots A, const int* dm, c
 // O_b[s][t] = A_b[rows(s)][cols(t)] for s < orows[b], t < ocols[b], where the
 // index lists (slots of stride ris/cis) or the identity give rows and
 // columns.  An index outside A_b writes zeros and raises ST_ARG; a
-// non-finite gathered value raises ST_NUMERIC.
+// non-finite gathered value raises ST_NUMERIC.  One workgroup per 32 x 32
+// tile of O_b (grid x: tiles of the largest extents, z: problems); the
+// reads run along t and so do the writes, the conjugate transpose's through
+// an LDS tile so that it writes along s.
+constexpr int GT = 32;
 template <typename TI, typename TX>
 __global__ __launch_bounds__(256) void kb_gather(const TI* __restrict__ A, int64_t lda, int64_t psa, int64_t sa,
                                                  const int* __restrict__ dm, const int* __restrict__ dn,
@@ -130,30 +134,52 @@ __global__ __launch_bounds__(256) void kb_gather(const TI* __restrict__ A, int64
                                                  const int* __restrict__ orows, const int* __restrict__ ocols,
                                                  double* __restrict__ O, int64_t ldo, int64_t pso, int64_t so,
                                                  TX* __restrict__ Ox, int64_t ldx, int64_t psx, int64_t sx,
-                                                 int tconj, unsigned* status) {
+                                                 int tconj, int tiles_t, unsigned* status) {
+  __shared__ double tile[4][GT][GT + 1];
   const int b = blockIdx.z;
   const int64_t rows = orows[b], cols = ocols[b];
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= cols) return;  // no barriers below
+  const int64_t s0 = (int64_t)(blockIdx.x / tiles_t) * GT, t0 = (int64_t)(blockIdx.x % tiles_t) * GT;
+  if (s0 >= rows || t0 >= cols) return;  // uniform over the workgroup
   const int64_t m = dm[b], n = dn[b];
   const TI* Ab = A + (int64_t)b * sa;
-  const int64_t j = cidx ? cidx[(int64_t)b * cis + t] : t;
-  for (int64_t s = blockIdx.y; s < rows; s += gridDim.y) {
-    const int64_t i = ridx ? ridx[(int64_t)b * ris + s] : s;
-    const bool ok = i >= 0 && i < m && j >= 0 && j < n;
-    if (!ok) atomicOr(status, ST_ARG);
-    const int64_t src = i * lda + j;
-    // tconj: O receives the conjugate transpose (element (t, s), planes 1..3 negated)
-    const int64_t dst = tconj ? t * ldo + s : s * ldo + t, dx = s * ldx + t;
-    bool finite = true;
+  const int tx = threadIdx.x % GT, ty = threadIdx.x / GT;  // 8 rows of 32 per pass
+  const int64_t t = t0 + tx;
+  const int64_t j = t < cols ? (cidx ? cidx[(int64_t)b * cis + t] : t) : 0;
+  bool bad = false, finite = true;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const double v = ok ? ld_d(Ab, src + k * psa) : 0.0;
-      finite &= isfinite(v);
-      O[(int64_t)b * so + dst + k * pso] = (tconj && k > 0) ? -v : v;
-      if (Ox) st_d(Ox + (int64_t)b * sx, dx + k * psx, v);
+  for (int r = 0; r < GT / 8; ++r) {
+    const int64_t s = s0 + ty + 8 * r;
+    if (s < rows && t < cols) {
+      const int64_t i = ridx ? ridx[(int64_t)b * ris + s] : s;
+      const bool ok = i >= 0 && i < m && j >= 0 && j < n;
+      bad |= !ok;
+      const int64_t src = i * lda + j;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double v = ok ? ld_d(Ab, src + k * psa) : 0.0;
+        finite &= isfinite(v);
+        if (tconj) tile[k][ty + 8 * r][tx] = v;
+        else O[(int64_t)b * so + s * ldo + t + k * pso] = v;
+        if (Ox) st_d(Ox + (int64_t)b * sx, s * ldx + t + k * psx, v);
+      }
     }
-    if (!finite) atomicOr(status, ST_NUMERIC);
+  }
+  if (bad) atomicOr(status, ST_ARG);
+  if (!finite) atomicOr(status, ST_NUMERIC);
+  if (!tconj) return;
+  double* Ob = O + (int64_t)b * so;
+  // conjugate transpose: O receives element (t, s), planes 1..3 negated;
+  // thread (ty, tx) now writes row t0 + ty + 8r, column s0 + tx
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < GT / 8; ++r) {
+    const int64_t tt = t0 + ty + 8 * r, ss = s0 + tx;
+    if (tt < cols && ss < rows)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double v = tile[k][tx][ty + 8 * r];
+        Ob[tt * ldo + ss + k * pso] = k > 0 ? -v : v;
+      }
   }
 }
 
@@ -162,7 +188,9 @@ hipError_t launch_gather_batch(const Ctx& c, int count, Slots A, const int* dm, 
                                const int* orows, const int* ocols, int64_t rowsx, int64_t colsx, Slots O,
                                const Slots* Ox, int tconj) {
   if (count <= 0 || rowsx <= 0 || colsx <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((colsx + 255) / 256), (unsigned)std::min<int64_t>(rowsx, 1024), (unsigned)count);
+  const int64_t ts = (rowsx + GT - 1) / GT, tt = (colsx + GT - 1) / GT;
+  if (ts * tt > 0x7fffffff) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(ts * tt), 1, (unsigned)count);
   return by_dtype(A.dt, [&](auto* ti) {
     typedef std::remove_pointer_t<decltype(ti)> TI;
     const int xdt = Ox ? Ox->dt : QCUR_F32;
@@ -171,7 +199,7 @@ hipError_t launch_gather_batch(const Ctx& c, int count, Slots A, const int* dm, 
       hipLaunchKernelGGL((kb_gather<TI, TX>), grid, dim3(256), 0, c.stream, (const TI*)A.p, A.ld, A.ps, A.slab,
                          dm, dn, ridx, ris, cidx, cis, orows, ocols, (double*)O.p, O.ld, O.ps, O.slab,
                          Ox ? (TX*)Ox->p : (TX*)nullptr, Ox ? Ox->ld : 0, Ox ? Ox->ps : 0, Ox ? Ox->slab : 0,
-                         tconj, c.status);
+                         tconj, (int)tt, c.status);
     });
   });
 }

@@ -611,6 +611,37 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
     __syncthreads();
     }
   };
+  // Small tiles of the fused epilogues (one 16 x 16 block per wave) with FP32
+  // operands fetch the tile of the matrix they subtract from (and the merge's
+  // previous iterate) before the K loop, so that the reads are in flight
+  // during the MFMAs instead of starting after them: a short K loop (the
+  // batch's residual has K = r <= 64) left them exposed.  Addresses are
+  // clamped into the matrix so that every load is unconditional.
+  constexpr bool PREF = (EPI == EPI_RESID || EPI == EPI_MERGE) && XB == 1 && YB == 1;
+  const bool pref_r0 = PREF && g.r0dt == QCUR_F32;
+  const bool pref_x0 = PREF && EPI == EPI_MERGE && g.x0dt == QCUR_F32;
+  float r0f[PREF ? 16 : 1], x0f[PREF ? 16 : 1];
+  if constexpr (PREF) {
+    const int64_t jc = min(bn + wn + (lane & 15), N - 1);
+    if (pref_r0) {
+      const float* R0 = (const float*)g.R0 + (EPI == EPI_RESID ? b * g.sR0 : 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t ic = min(bm + wm + T::out_row(lane, r), M - 1);
+#pragma unroll
+        for (int p = 0; p < 4; ++p) r0f[4 * r + p] = R0[ic * g.r0ld + jc + p * g.r0ps];
+      }
+    }
+    if (pref_x0) {
+      const float* X0 = (const float*)g.X0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t ic = min(bm + wm + T::out_row(lane, r), M - 1);
+#pragma unroll
+        for (int p = 0; p < 4; ++p) x0f[4 * r + p] = X0[ic * g.x0ld + jc + p * g.x0ps];
+      }
+    }
+  }
   if constexpr (DT == QCUR_BF16) {
     const bool kvec_op = g.opA == QCUR_OP_N || g.opB == QCUR_OP_H;
     const bool fast = aligned && bm + BM <= M && bn + BN <= N && (!kvec_op || (K & 7) == 0);
@@ -636,8 +667,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
             const bool keep = g.mask ? (g.mask[b * g.sMask + i * g.mask_ld + j] != 0) : true;
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
-              double d = load_as_double(g.R0, g.r0dt, b * g.sR0 + i * g.r0ld + j + p * g.r0ps) -
-                         (double)acc[p][x][y][r];
+              const double a0 = pref_r0 ? (double)r0f[PREF ? 4 * r + p : 0]
+                                        : load_as_double(g.R0, g.r0dt, b * g.sR0 + i * g.r0ld + j + p * g.r0ps);
+              double d = a0 - (double)acc[p][x][y][r];
               if (!keep) d = 0.0;
               sq += d * d;
               if (g.E) store_from_double(g.E, g.edt, b * g.sE + i * g.eld + j + p * g.eps, g.e_scale * d);
@@ -668,9 +700,11 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int b, int64_t tile
             const bool obs = g.mask[i * g.mask_ld + j] != 0;
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
-              const double xo = load_as_double(g.X0, g.x0dt, i * g.x0ld + j + p * g.x0ps);
-              const double xn = obs ? load_as_double(g.R0, g.r0dt, i * g.r0ld + j + p * g.r0ps)
-                                    : (double)acc[p][x][y][r];
+              const double xo = pref_x0 ? (double)x0f[PREF ? 4 * r + p : 0]
+                                        : load_as_double(g.X0, g.x0dt, i * g.x0ld + j + p * g.x0ps);
+              const double yo = pref_r0 ? (double)r0f[PREF ? 4 * r + p : 0]
+                                        : load_as_double(g.R0, g.r0dt, i * g.r0ld + j + p * g.r0ps);
+              const double xn = obs ? yo : (double)acc[p][x][y][r];
               store_from_double(g.E, g.edt, i * g.eld + j + p * g.eps, xn);
               const double xs = load_as_double(g.E, g.edt, i * g.eld + j + p * g.eps);  // as stored
               sd += (xs - xo) * (xs - xo);
