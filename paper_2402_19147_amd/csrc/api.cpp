@@ -1228,7 +1228,7 @@ struct BatchShape {
 constexpr int TUNE_MAX_SPLITS = 4;
 
 struct BatchWs {
-  int *dm, *dn, *dc, *dr, *zp, *zq, *order;  // header (uploaded by qcur_batch_prepare)
+  int *dm, *dn, *dc, *dr, *zp, *zq, *order, *forder;  // header (uploaded by qcur_batch_prepare)
   double *colpart, *rowpart, *p, *q;
   Slots Ax;
   double *Z, *G, *L, *P1, *P2, *P, *Sch, *Q1, *Q, *norms;
@@ -1271,6 +1271,7 @@ BatchWs batch_carve(Bump& b, const BatchShape& s) {
   w.zp = (int*)b.take((size_t)n2 * 4);
   w.zq = (int*)b.take((size_t)n2 * 4);
   w.order = (int*)b.take((size_t)n * 4);
+  w.forder = (int*)b.take((size_t)n2 * 4);
   const int64_t nrbx = (s.mx + BATCH_RB - 1) / BATCH_RB, ncbx = (s.nx + 255) / 256;
   w.colpart = (double*)b.take((size_t)n * nrbx * s.nx * 8);
   w.rowpart = (double*)b.take((size_t)n * ncbx * s.mx * 8);
@@ -1552,22 +1553,24 @@ qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, Bat
   };
   // D_t = X_t P_t^H over the leading q_t columns (qd: per-factor orders),
   // and/or its copy in the product dtype into the C and R factor slots
+  auto product_copy = [&]() {  // the C and R factor slots in the product dtype
+    TallCopy cp{};
+    cp.p[0] = w.Qcx.p;
+    cp.p[1] = w.Qrx.p;
+    cp.ld[0] = w.Qcx.ld;
+    cp.ld[1] = w.Qrx.ld;
+    cp.ps[0] = w.Qcx.ps;
+    cp.ps[1] = w.Qrx.ps;
+    cp.slab[0] = w.Qcx.slab;
+    cp.slab[1] = w.Qrx.slab;
+    cp.dt = idt;
+    cp.split = n;
+    return cp;
+  };
   auto zph = [&](const QView& X, const QView& Pv, const QView* D, const int* qd, bool to_product,
                  int id) -> qcur_status {
     fixed_stage(id);
-    TallCopy cp{};
-    if (to_product) {
-      cp.p[0] = w.Qcx.p;
-      cp.p[1] = w.Qrx.p;
-      cp.ld[0] = w.Qcx.ld;
-      cp.ld[1] = w.Qrx.ld;
-      cp.ps[0] = w.Qcx.ps;
-      cp.ps[1] = w.Qrx.ps;
-      cp.slab[0] = w.Qcx.slab;
-      cp.slab[1] = w.Qrx.slab;
-      cp.dt = idt;
-      cp.split = n;
-    }
+    const TallCopy cp = to_product ? product_copy() : TallCopy{};
     const QView Dv = D ? *D : QView{nullptr, px, qx, qx, px * qx, QCUR_F64};
     HIPCHK(launch_tall_nh(c, 1.0, X, Pv, 0.0, Dv, qx, n2, zslab, gslab, zslab, true, w.zp, qd, qd,
                           to_product ? &cp : nullptr));
@@ -1586,31 +1589,42 @@ qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, Bat
   // factor's own order; larger ones get an identity block outside it
   const bool padded = qx > CHOL_BLOCK;
   HIPCHK(launch_zero_i32(c, w.fail, n2));
-  // G = Z^H Z:  C_b^H C_b  and  R_b R_b^H, one launch
-  CHK(gram(Zv, BS_GRAM_C));
-  fixed_stage(BS_GRAM_R);
-  if (padded) HIPCHK(launch_pad_gram_batch(c, n2, w.G, qx, G.slab, w.zq));
-  gw.dims = w.zq;
-  CHK(chol_inv(c, gw, w.P1));
-  HIPCHK(launch_sumsq_ragged(c, n2, Zs, w.zp, w.zq, w.norms, 4));
-  HIPCHK(launch_sumsq_ragged(c, n2, P1, w.zq, w.zq, w.norms + 1, 4));
-  // Q1 = Z P1^H:  C_b P1^H  and  R_b^H P1^H, one launch (with its copy in the
-  // product dtype: the orthonormal factors of the factors that keep one pass)
-  const bool f64 = idt == QCUR_F64;
-  CHK(zph(Zv, P1v, &Q1v, w.zq, !f64, BS_Q1_C));
-  fixed_stage(BS_Q1_R);
   // CholeskyQR2: Q1^H Q1 = L2 L2^H, P = P2 P1, Q = Q1 P2^H.  FP64 products
   // always take the second pass; FP32 and BF16 products only for the
   // factors whose first-pass defect ||Q1^H Q1 - I||_F exceeds the bound of
   // the single solve (q2 = 0 and P = P1 for the others, which then skip
   // the second pass's factorisation and products)
+  const bool f64 = idt == QCUR_F64;
+  const double otol = orth_bound(s.compute, s.refine);
   const Slots P2 = sl(w.P2, qx, qx, qx), P = sl(w.P, qx, qx, qx);
-  CHK(gram(Q1v, BS_G2));
   const int* q2 = w.zq;
-  if (!f64) {
-    const double tol = orth_bound(s.compute, s.refine);
-    HIPCHK(launch_defect_plan_batch(c, n2, w.G, qx, G.slab, w.zq, w.fail, tol * tol, w.P1, w.P, w.zq2, w.skip));
+  if (!padded) {
+    // the whole first pass of every factor (Gram matrix, factor and inverse,
+    // Q1 with its product-dtype copy, the defect and the plan): one launch,
+    // one workgroup per factor
+    for (int id : {BS_GRAM_C, BS_GRAM_R, BS_Q1_C, BS_Q1_R, BS_G2}) fixed_stage(id);
+    const TallCopy cp = product_copy();
+    HIPCHK(launch_cholqr_batch(c, n2, w.Z, w.Q1, qx, px * qx, zslab, w.P1, w.P, w.G, qx, qx * qx, gslab, w.zp, w.zq,
+                               w.fail, w.norms, w.zq2, w.skip, otol * otol, f64 ? 0 : 1, f64 ? nullptr : &cp, w.forder));
     q2 = w.zq2;
+  } else {
+    // G = Z^H Z:  C_b^H C_b  and  R_b R_b^H, one launch
+    CHK(gram(Zv, BS_GRAM_C));
+    fixed_stage(BS_GRAM_R);
+    HIPCHK(launch_pad_gram_batch(c, n2, w.G, qx, G.slab, w.zq));
+    gw.dims = w.zq;
+    CHK(chol_inv(c, gw, w.P1));
+    HIPCHK(launch_sumsq_ragged(c, n2, Zs, w.zp, w.zq, w.norms, 4));
+    HIPCHK(launch_sumsq_ragged(c, n2, P1, w.zq, w.zq, w.norms + 1, 4));
+    // Q1 = Z P1^H:  C_b P1^H  and  R_b^H P1^H, one launch (with its copy in the
+    // product dtype: the orthonormal factors of the factors that keep one pass)
+    CHK(zph(Zv, P1v, &Q1v, w.zq, !f64, BS_Q1_C));
+    fixed_stage(BS_Q1_R);
+    CHK(gram(Q1v, BS_G2));
+    if (!f64) {
+      HIPCHK(launch_defect_plan_batch(c, n2, w.G, qx, G.slab, w.zq, w.fail, otol * otol, w.P1, w.P, w.zq2, w.skip));
+      q2 = w.zq2;
+    }
   }
   if (padded) HIPCHK(launch_pad_gram_batch(c, n2, w.G, qx, G.slab, w.zq));
   gw.dims = q2;
@@ -2578,11 +2592,16 @@ qcur_status qcur_batch_prepare(qcur_handle h, int32_t count, const int32_t* dims
   for (int i = 0; i < count; ++i) order[i] = i;
   auto work = [&](int i) { return (double)hm[i] * (double)hn[i] * (double)(hc[i] + hr[i]); };
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
-  const int* srcs[7] = {hm, hn, hc, hr, hp, hq, order.data()};
-  int* dsts[7] = {w.dm, w.dn, w.dc, w.dr, w.zp, w.zq, w.order};
-  const size_t lens[7] = {(size_t)count, (size_t)count, (size_t)count, (size_t)count, (size_t)2 * count,
-                          (size_t)2 * count, (size_t)count};
-  for (int k = 0; k < 7; ++k)
+  // the order of the factors' CholeskyQR workgroups: largest p q^2 first
+  std::vector<int> forder(2 * count);
+  for (int i = 0; i < 2 * count; ++i) forder[i] = i;
+  auto fwork = [&](int t) { return (double)hp[t] * (double)hq[t] * (double)hq[t]; };
+  std::stable_sort(forder.begin(), forder.end(), [&](int x, int y) { return fwork(x) > fwork(y); });
+  const int* srcs[8] = {hm, hn, hc, hr, hp, hq, order.data(), forder.data()};
+  int* dsts[8] = {w.dm, w.dn, w.dc, w.dr, w.zp, w.zq, w.order, w.forder};
+  const size_t lens[8] = {(size_t)count, (size_t)count, (size_t)count, (size_t)count, (size_t)2 * count,
+                          (size_t)2 * count, (size_t)count, (size_t)2 * count};
+  for (int k = 0; k < 8; ++k)
     HIPCHK(hipMemcpyAsync(dsts[k], srcs[k], lens[k] * sizeof(int), hipMemcpyHostToDevice, h->c.stream));
   HIPCHK(hipStreamSynchronize(h->c.stream));
   int slot = -1;

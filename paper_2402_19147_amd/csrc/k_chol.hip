@@ -13,6 +13,7 @@
 namespace qcur {
 
 constexpr int CB = 64;  // diagonal block size
+typedef double f64x4d __attribute__((ext_vector_type(4)));
 
 struct Qd {
   double w, x, y, z;
@@ -167,35 +168,16 @@ __device__ void chol_diag(TileT& a, double* rdg, DiagBuf& db, int kb, int kw, in
   }
 }
 
-__global__ __launch_bounds__(CHOL_THREADS) void k_chol_block(const double* __restrict__ G0, double* __restrict__ P0,
-                                                             int wx, int64_t ld, int64_t ps, int64_t sbatch,
-                                                             int* fail0, const int* __restrict__ dims) {
-  // matrix b's own order (dims: per-matrix orders; 0 = nothing to do, P
-  // left as it is; outside the leading w x w block nothing is written)
-  const int w = dims ? min(dims[blockIdx.x], wx) : wx;
-  if (w <= 0) return;
-  const double* __restrict__ G = G0 + (int64_t)blockIdx.x * sbatch;
-  double* __restrict__ Pg = P0 + (int64_t)blockIdx.x * sbatch;
-  int* fail = fail0 + blockIdx.x;
-  __shared__ Tile a;
-  __shared__ double sbuf[3][4][SB][SB + 1];  // block-row sums of the inverse phase
-  __shared__ double rdg[CB];                 // 1 / L[j][j]
-  __shared__ __align__(16) DiagBuf db;
-  __shared__ int bad;
+// Factorisation and inverse of the leading w x w block (w <= 64) of the
+// lower triangle held in a: on return a holds P = L^{-1} in the layout of
+// chol_diag (diagonal sub-blocks' strict lower parts transposed into their
+// upper triangles, 1 / L[j][j] in rdg; read back through pdiag), the rest of
+// P's lower triangle in place.  All CHOL_THREADS threads take part.
+__device__ void chol_block_lds(Tile& a, double (*sbuf)[4][SB][SB + 1], double* rdg, DiagBuf& db, int* bad, int w) {
   const int tid = threadIdx.x;
-  if (tid == 0) bad = 0;
-  for (int e = tid; e < w * w; e += CHOL_THREADS) {
-    const int i = e / w, j = e % w;
-    if (j <= i) {
-      const int64_t o = (int64_t)i * ld + j;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) a[c][i][j] = G[o + c * ps];
-    }
-  }
-  __syncthreads();
   for (int kb = 0; kb < w; kb += SB) {
     const int kw = min(SB, w - kb);
-    chol_diag(a, rdg, db, kb, kw, tid, &bad);
+    chol_diag(a, rdg, db, kb, kw, tid, bad);
     __syncthreads();
     const int r0 = kb + kw, rows = w - r0;
     if (rows <= 0) break;
@@ -272,6 +254,35 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_block(const double* __res
     }
     __syncthreads();
   }
+}
+
+__global__ __launch_bounds__(CHOL_THREADS) void k_chol_block(const double* __restrict__ G0, double* __restrict__ P0,
+                                                             int wx, int64_t ld, int64_t ps, int64_t sbatch,
+                                                             int* fail0, const int* __restrict__ dims) {
+  // matrix b's own order (dims: per-matrix orders; 0 = nothing to do, P
+  // left as it is; outside the leading w x w block nothing is written)
+  const int w = dims ? min(dims[blockIdx.x], wx) : wx;
+  if (w <= 0) return;
+  const double* __restrict__ G = G0 + (int64_t)blockIdx.x * sbatch;
+  double* __restrict__ Pg = P0 + (int64_t)blockIdx.x * sbatch;
+  int* fail = fail0 + blockIdx.x;
+  __shared__ Tile a;
+  __shared__ double sbuf[3][4][SB][SB + 1];  // block-row sums of the inverse phase
+  __shared__ double rdg[CB];                 // 1 / L[j][j]
+  __shared__ __align__(16) DiagBuf db;
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  for (int e = tid; e < w * w; e += CHOL_THREADS) {
+    const int i = e / w, j = e % w;
+    if (j <= i) {
+      const int64_t o = (int64_t)i * ld + j;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) a[c][i][j] = G[o + c * ps];
+    }
+  }
+  __syncthreads();
+  chol_block_lds(a, sbuf, rdg, db, &bad, w);
   for (int e = tid; e < w * w; e += CHOL_THREADS) {
     const int i = e / w, j = e % w;
     const int64_t o = (int64_t)i * ld + j;
@@ -289,6 +300,359 @@ hipError_t launch_chol_block(const Ctx& c, const double* G, double* P, int w, in
                              int batch, int64_t sbatch, const int* dims) {
   hipLaunchKernelGGL(k_chol_block, dim3(batch), dim3(CHOL_THREADS), 0, c.stream, G, P, w, ld, ps, sbatch, fail,
                      dims);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// The first CholeskyQR pass of every factor of a batch in one launch, one
+// workgroup per factor Z_t (p_t x q_t, q_t <= 64, FP64 slots):
+//   1. G = Z^H Z (lower 16 x 16 blocks, FP64 matrix cores) into LDS, and
+//      ||Z||_F^2 from the same loads;
+//   2. G = L L^H and P1 = L^{-1} in LDS (chol_block_lds), P1 and ||P1||_F^2
+//      written out;
+//   3. Q1 = Z P1^H (FP64 and the product-dtype copy);
+//   4. G2 = Q1^H Q1 from the Q1 just written, its defect ||G2 - I||_F^2 and
+//      the plan of the second pass: with `adaptive` the factor keeps its
+//      first pass (q2 = 0, P = P1) when its Cholesky succeeded and the defect
+//      is at most tol2, else q2 = q_t and G2 (lower) goes to the G slot for
+//      the second pass.
+// The separate launches this replaces spread each factor over many
+// workgroups; here every compute unit works through whole factors and Z is
+// read from HBM once per pass.  Every sum runs in a fixed order.
+struct CholqrBatch {
+  const double* Z;
+  double* Q1;
+  int64_t zld, zps, zslab;  // Z and Q1 slots: row stride, plane stride, slot stride
+  double *P1, *P, *G;
+  int64_t gld, gps, gslab;  // q x q slots
+  const int *zp, *zq;
+  int* fail;
+  double* norms;  // [4 t]: ||Z_t||_F^2, [4 t + 1]: ||P1_t||_F^2
+  int *q2, *skip;
+  double tol2;
+  int adaptive;
+  TallCopy copy;
+  // workgroup k takes factor order[k] (NULL: k): largest first
+  const int* order;
+};
+
+// Hermitian Gram blocks of X (rows < p, columns < q) into the lower 16 x 16
+// blocks of a: tasks (block, row slice) spread over the eight waves, the
+// slices' partial blocks added into a in slice order.  *sq gains the sum of
+// squares of the entries the diagonal-block tasks load (each entry once).
+__device__ void cholqr_gram(const double* __restrict__ X, int64_t ld, int64_t ps, int p, int q, Tile& a,
+                            double* sq) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g4 = lane >> 4, cl = lane & 15;
+  // (at most two tasks per wave, whose accumulators stay in registers: the
+  // task loops are unrolled so that every index is a constant)
+  const int nb = (q + 15) >> 4, nblk = nb * (nb + 1) / 2;
+  const int H = max(1, min(8, 16 / nblk));
+  const int rows = (((p + H - 1) / H) + 15) & ~15;
+  const int ntask = nblk * H;
+  f64x4d acc[2][4];
+  int tb[2], th[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int task = wave + 8 * u;
+    tb[u] = -1;
+    th[u] = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[u][c] = (f64x4d){0, 0, 0, 0};
+    if (task >= ntask) continue;  // wave-uniform
+    const int blk = task / H, h = task % H;
+    int bi = 0;
+    while ((bi + 1) * (bi + 2) / 2 <= blk) ++bi;
+    const int bj = blk - bi * (bi + 1) / 2;
+    tb[u] = blk;
+    th[u] = h;
+    const int r0 = h * rows, r1 = min(p, r0 + rows);
+    const int ca = 16 * bi + cl, cb = 16 * bj + cl;
+    const bool oka = ca < q, okb = cb < q, diag = bi == bj;
+    const double* pa = X + min(ca, q - 1);
+    const double* pb = X + min(cb, q - 1);
+    // chunks of 16 rows; MFMA step s takes row k0 + 4 s + g4 (the same in
+    // both operands); rows are clamped into the matrix, so every load is
+    // unconditional, and rows past the slice are zeroed
+    double va[1][4][4], vb[1][4][4];
+    auto load = [&](int buf, int k0) __attribute__((always_inline)) {
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int64_t kc = min(k0 + 4 * st + g4, p - 1);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          va[buf][st][c] = pa[kc * ld + c * ps];
+          vb[buf][st][c] = pb[kc * ld + c * ps];
+        }
+      }
+    };
+    auto comp = [&](int buf, int k0) __attribute__((always_inline)) {
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const bool okr = k0 + 4 * st + g4 < r1;
+        const double a0 = okr && oka ? va[buf][st][0] : 0.0, a1 = okr && oka ? va[buf][st][1] : 0.0;
+        const double a2 = okr && oka ? va[buf][st][2] : 0.0, a3 = okr && oka ? va[buf][st][3] : 0.0;
+        const double b0 = okr && okb ? vb[buf][st][0] : 0.0, b1 = okr && okb ? vb[buf][st][1] : 0.0;
+        const double b2 = okr && okb ? vb[buf][st][2] : 0.0, b3 = okr && okb ? vb[buf][st][3] : 0.0;
+        if (diag) *sq += a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3;
+        const double n1 = -a1, n2 = -a2, n3 = -a3;
+        // conj(a) b:  w = a0 b0 + a1 b1 + a2 b2 + a3 b3,  x = a0 b1 - a1 b0 - a2 b3 + a3 b2,
+        //             y = a0 b2 + a1 b3 - a2 b0 - a3 b1,  z = a0 b3 - a1 b2 + a2 b1 - a3 b0
+        acc[u][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[u][0], 0, 0, 0);
+        acc[u][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[u][1], 0, 0, 0);
+        acc[u][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b2, acc[u][2], 0, 0, 0);
+        acc[u][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b3, acc[u][3], 0, 0, 0);
+        acc[u][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[u][0], 0, 0, 0);
+        acc[u][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(n1, b0, acc[u][1], 0, 0, 0);
+        acc[u][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b3, acc[u][2], 0, 0, 0);
+        acc[u][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(n1, b2, acc[u][3], 0, 0, 0);
+        acc[u][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b2, acc[u][0], 0, 0, 0);
+        acc[u][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(n2, b3, acc[u][1], 0, 0, 0);
+        acc[u][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(n2, b0, acc[u][2], 0, 0, 0);
+        acc[u][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b1, acc[u][3], 0, 0, 0);
+        acc[u][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, b3, acc[u][0], 0, 0, 0);
+        acc[u][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, b2, acc[u][1], 0, 0, 0);
+        acc[u][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(n3, b1, acc[u][2], 0, 0, 0);
+        acc[u][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(n3, b0, acc[u][3], 0, 0, 0);
+      }
+    };
+    for (int k0 = r0; k0 < r1; k0 += 16) {
+      load(0, k0);
+      comp(0, k0);
+    }
+  }
+  // slice h's partial blocks go into a after those of slices < h
+  for (int h = 0; h < H; ++h) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      if (tb[u] < 0 || th[u] != h) continue;
+      int bi = 0;
+      while ((bi + 1) * (bi + 2) / 2 <= tb[u]) ++bi;
+      const int bj = tb[u] - bi * (bi + 1) / 2;
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * bi + g4 + 4 * r, j = 16 * bj + cl;
+          a[c][i][j] = h == 0 ? acc[u][c][r] : a[c][i][j] + acc[u][c][r];
+        }
+    }
+  }
+  __syncthreads();
+}
+
+// fixed-order sum over the workgroup (CHOL_THREADS threads); every thread
+// gets the total
+__device__ double cholqr_sum(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < CHOL_THREADS / 64; ++w) s += red[w];
+  return s;
+}
+
+__global__ __launch_bounds__(CHOL_THREADS) void kb_cholqr(CholqrBatch g) {
+  __shared__ Tile a;
+  __shared__ double sbuf[3][4][SB][SB + 1];
+  __shared__ double rdg[CB];
+  __shared__ __align__(16) DiagBuf db;
+  __shared__ double red[CHOL_THREADS / 64];
+  __shared__ int bad;
+  const int t = g.order ? g.order[blockIdx.x] : blockIdx.x, tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6, g4 = lane >> 4, cl = lane & 15;
+  const int p = g.zp[t], q = g.zq[t];
+  if (p <= 0 || q <= 0) {
+    if (tid == 0) {
+      g.norms[4 * t] = 0.0;
+      g.norms[4 * t + 1] = 0.0;
+      g.q2[t] = 0;
+      g.skip[t] = 1;
+    }
+    return;
+  }
+  const double* __restrict__ Z = g.Z + (int64_t)t * g.zslab;
+  double* __restrict__ Q1 = g.Q1 + (int64_t)t * g.zslab;
+  double* __restrict__ P1 = g.P1 + (int64_t)t * g.gslab;
+  if (tid == 0) bad = 0;
+  // 1. G = Z^H Z
+  double sq = 0.0;
+  cholqr_gram(Z, g.zld, g.zps, p, q, a, &sq);
+  sq = cholqr_sum(sq, red);
+  if (tid == 0) g.norms[4 * t] = sq;
+  // 2. P1 = L^{-1}; written out, then put back into a as a plain lower
+  //    triangle for the product
+  chol_block_lds(a, sbuf, rdg, db, &bad, q);
+  constexpr int PE = CB * CB / CHOL_THREADS;
+  Qd pv[PE];
+  double ps2 = 0.0;
+#pragma unroll
+  for (int m = 0; m < PE; ++m) {
+    const int e = tid + CHOL_THREADS * m;
+    const int i = e / q, j = e % q;
+    Qd v{0, 0, 0, 0};
+    if (e < q * q && j <= i) v = (i / SB == j / SB) ? pdiag(a, rdg, (i / SB) * SB, i % SB, j % SB) : ldq(a, i, j);
+    pv[m] = v;
+    if (e < q * q) {
+      const int64_t o = (int64_t)i * g.gld + j;
+      P1[o] = v.w;
+      P1[o + g.gps] = v.x;
+      P1[o + 2 * g.gps] = v.y;
+      P1[o + 3 * g.gps] = v.z;
+      ps2 += v.w * v.w + v.x * v.x + v.y * v.y + v.z * v.z;
+    }
+  }
+  ps2 = cholqr_sum(ps2, red);  // (its barriers also end the reads of a above)
+  if (tid == 0) g.norms[4 * t + 1] = ps2;
+#pragma unroll
+  for (int m = 0; m < PE; ++m) {
+    const int e = tid + CHOL_THREADS * m;
+    if (e < q * q) stq(a, e / q, e % q, pv[m]);
+  }
+  __syncthreads();
+  // 3. Q1 = Z P1^H: tasks (16-row block, 16-column block); lane group g4
+  //    takes k = k0 + 4 g4 + s at MFMA step s, a run of four consecutive k
+  //    in both operands.  A conj(b) with n = -a:
+  //      w: a0 p0 + a1 p1 + a2 p2 + a3 p3    x: a1 p0 + n0 p1 + a3 p2 + n2 p3
+  //      y: a2 p0 + n3 p1 + n0 p2 + a1 p3    z: a3 p0 + a2 p1 + n1 p2 + n0 p3
+  {
+    const int nbj = (q + 15) >> 4, nbi = (p + 15) >> 4;
+    const int h = t < g.copy.split ? 0 : 1;
+    void* D2 = g.copy.p[0] ? (char*)g.copy.p[h] +
+                                 (size_t)(t - h * g.copy.split) * g.copy.slab[h] * dtype_size(g.copy.dt)
+                           : nullptr;
+    for (int task = wave; task < nbi * nbj; task += CHOL_THREADS / 64) {
+      const int bi = task / nbj, bj = task % nbj;
+      const int ir = 16 * bi + cl, jc = 16 * bj + cl;
+      const double* pa = Z + (int64_t)min(ir, p - 1) * g.zld;
+      const int kend = min(q, 16 * bj + 16);
+      f64x4d acc[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = (f64x4d){0, 0, 0, 0};
+      double va[1][4][4];
+      auto load = [&](int buf, int k0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const int k = min(k0 + 4 * g4 + st, q - 1);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) va[buf][st][c] = pa[k + c * g.zps];
+        }
+      };
+      auto comp = [&](int buf, int k0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const int k = k0 + 4 * g4 + st;
+          const bool ok = ir < p && k < kend;
+          const bool okp = jc < q && k <= jc && k < q;
+          const int kc = min(k, CB - 1);
+          const double a0 = ok ? va[buf][st][0] : 0.0, a1 = ok ? va[buf][st][1] : 0.0;
+          const double a2 = ok ? va[buf][st][2] : 0.0, a3 = ok ? va[buf][st][3] : 0.0;
+          const double p0 = okp ? a[0][jc][kc] : 0.0, p1 = okp ? a[1][jc][kc] : 0.0;
+          const double p2 = okp ? a[2][jc][kc] : 0.0, p3 = okp ? a[3][jc][kc] : 0.0;
+          const double n0 = -a0, n1 = -a1, n2 = -a2, n3 = -a3;
+          acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, p0, acc[0], 0, 0, 0);
+          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, p0, acc[1], 0, 0, 0);
+          acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, p0, acc[2], 0, 0, 0);
+          acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, p0, acc[3], 0, 0, 0);
+          acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, p1, acc[0], 0, 0, 0);
+          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(n0, p1, acc[1], 0, 0, 0);
+          acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(n3, p1, acc[2], 0, 0, 0);
+          acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, p1, acc[3], 0, 0, 0);
+          acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, p2, acc[0], 0, 0, 0);
+          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, p2, acc[1], 0, 0, 0);
+          acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(n0, p2, acc[2], 0, 0, 0);
+          acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(n1, p2, acc[3], 0, 0, 0);
+          acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, p3, acc[0], 0, 0, 0);
+          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(n2, p3, acc[1], 0, 0, 0);
+          acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, p3, acc[2], 0, 0, 0);
+          acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(n0, p3, acc[3], 0, 0, 0);
+        }
+      };
+      for (int k0 = 0; k0 < kend; k0 += 16) {
+        load(0, k0);
+        comp(0, k0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * bi + g4 + 4 * r;
+        if (i < p && jc < q) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const int64_t o = (int64_t)i * g.zld + jc + c * g.zps;
+            Q1[o] = acc[c][r];
+            if (D2) store_from_double(D2, g.copy.dt, (int64_t)i * g.copy.ld[h] + jc + c * g.copy.ps[h], acc[c][r]);
+          }
+        }
+      }
+    }
+  }
+  // 4. G2 = Q1^H Q1 from the Q1 this workgroup wrote
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  double unused = 0.0;
+  cholqr_gram(Q1, g.zld, g.zps, p, q, a, &unused);
+  double d2 = 0.0;
+  for (int e = tid; e < q * q; e += CHOL_THREADS) {
+    const int i = e / q, j = e % q;
+    if (j > i) continue;
+    const double wgt = i == j ? 1.0 : 2.0;  // the strict lower part stands for both triangles
+    const double d0 = a[0][i][j] - (i == j ? 1.0 : 0.0);
+    d2 += wgt * (d0 * d0 + a[1][i][j] * a[1][i][j] + a[2][i][j] * a[2][i][j] + a[3][i][j] * a[3][i][j]);
+  }
+  d2 = cholqr_sum(d2, red);
+  const bool keep = g.adaptive && bad == 0 && d2 <= g.tol2;
+  if (tid == 0) {
+    if (bad) g.fail[t] = 1;
+    g.q2[t] = keep ? 0 : q;
+    g.skip[t] = keep ? 1 : 0;
+  }
+  double* __restrict__ Gt = g.G + (int64_t)t * g.gslab;
+  double* __restrict__ Pt = g.P + (int64_t)t * g.gslab;
+  for (int e = tid; e < q * q; e += CHOL_THREADS) {
+    const int i = e / q, j = e % q;
+    const int64_t o = (int64_t)i * g.gld + j;
+    if (keep) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) Pt[o + c * g.gps] = P1[o + c * g.gps];
+    } else if (j <= i) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) Gt[o + c * g.gps] = a[c][i][j];
+    }
+  }
+}
+
+hipError_t launch_cholqr_batch(const Ctx& c, int count, const double* Z, double* Q1, int64_t zld, int64_t zps,
+                               int64_t zslab, double* P1, double* P, double* G, int64_t gld, int64_t gps,
+                               int64_t gslab, const int* zp, const int* zq, int* fail, double* norms, int* q2,
+                               int* skip, double tol2, int adaptive, const TallCopy* copy, const int* order) {
+  if (count <= 0) return hipSuccess;
+  CholqrBatch g;
+  g.Z = Z;
+  g.Q1 = Q1;
+  g.zld = zld;
+  g.zps = zps;
+  g.zslab = zslab;
+  g.P1 = P1;
+  g.P = P;
+  g.G = G;
+  g.gld = gld;
+  g.gps = gps;
+  g.gslab = gslab;
+  g.zp = zp;
+  g.zq = zq;
+  g.fail = fail;
+  g.norms = norms;
+  g.q2 = q2;
+  g.skip = skip;
+  g.tol2 = tol2;
+  g.adaptive = adaptive;
+  g.copy = copy ? *copy : TallCopy{};
+  g.order = order;
+  hipLaunchKernelGGL(kb_cholqr, dim3((unsigned)count), dim3(CHOL_THREADS), 0, c.stream, g);
   return hipGetLastError();
 }
 
@@ -439,7 +803,6 @@ __device__ inline void dstq(DTile& t, int r, int c, Qd v) {
 // plane, the MFMA 16x16x4 output layout: lane l has column l % 16 and rows
 // l / 16 + 4 r.  Each step of four k loads one fragment per plane of each
 // operand and issues the sixteen real products of the Hamilton product.
-typedef double f64x4d __attribute__((ext_vector_type(4)));
 struct DAcc {
   f64x4d p[4];
 };
