@@ -1599,14 +1599,14 @@ qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, Bat
   const Slots P2 = sl(w.P2, qx, qx, qx), P = sl(w.P, qx, qx, qx);
   const int* q2 = w.zq;
   if (!padded) {
-    // the whole first pass of every factor (Gram matrix, factor and inverse,
-    // Q1 with its product-dtype copy, the defect and the plan): one launch,
-    // one workgroup per factor
-    for (int id : {BS_GRAM_C, BS_GRAM_R, BS_Q1_C, BS_Q1_R, BS_G2}) fixed_stage(id);
+    // CholeskyQR2 of every factor (Gram matrices, factors and inverses, Q1
+    // with its product-dtype copy, the defect and, where it is needed, the
+    // second pass): one launch, one workgroup per factor
+    for (int id : {BS_GRAM_C, BS_GRAM_R, BS_Q1_C, BS_Q1_R, BS_G2, BS_P, BS_Q}) fixed_stage(id);
     const TallCopy cp = product_copy();
-    HIPCHK(launch_cholqr_batch(c, n2, w.Z, w.Q1, qx, px * qx, zslab, w.P1, w.P, w.G, qx, qx * qx, gslab, w.zp, w.zq,
-                               w.fail, w.norms, w.zq2, w.skip, otol * otol, f64 ? 0 : 1, f64 ? nullptr : &cp, w.forder));
-    q2 = w.zq2;
+    HIPCHK(launch_cholqr_batch(c, n2, w.Z, w.Q1, f64 ? w.Q : nullptr, qx, px * qx, zslab, w.P1, w.P, qx, qx * qx,
+                               gslab, w.zp, w.zq, w.fail, w.norms, w.zq2, w.skip, otol * otol, f64 ? 0 : 1,
+                               f64 ? nullptr : &cp, w.forder));
   } else {
     // G = Z^H Z:  C_b^H C_b  and  R_b R_b^H, one launch
     CHK(gram(Zv, BS_GRAM_C));
@@ -1625,15 +1625,15 @@ qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, Bat
       HIPCHK(launch_defect_plan_batch(c, n2, w.G, qx, G.slab, w.zq, w.fail, otol * otol, w.P1, w.P, w.zq2, w.skip));
       q2 = w.zq2;
     }
+    HIPCHK(launch_pad_gram_batch(c, n2, w.G, qx, G.slab, w.zq));
+    gw.dims = q2;
+    CHK(chol_inv(c, gw, w.P2));
+    CHK(stage(BS_P, QCUR_OP_N, QCUR_OP_N, 1.0, slot_view(P2, qx, qx), slot_view(P1, qx, qx), 0.0,
+              slot_view(P, qx, qx), QCUR_F64, bspec(n2, P2, P1, P, q2, q2, q2, TRI_A_LOWER | TRI_B_LOWER)));
+    // FP64 products read Q; the others read the product-dtype copy (Q itself
+    // is then only written by the Jacobi fallback below)
+    CHK(zph(Q1v, P2v, f64 ? &Qv : nullptr, q2, !f64, BS_Q));
   }
-  if (padded) HIPCHK(launch_pad_gram_batch(c, n2, w.G, qx, G.slab, w.zq));
-  gw.dims = q2;
-  CHK(chol_inv(c, gw, w.P2));
-  CHK(stage(BS_P, QCUR_OP_N, QCUR_OP_N, 1.0, slot_view(P2, qx, qx), slot_view(P1, qx, qx), 0.0,
-            slot_view(P, qx, qx), QCUR_F64, bspec(n2, P2, P1, P, q2, q2, q2, TRI_A_LOWER | TRI_B_LOWER)));
-  // FP64 products read Q; the others read the product-dtype copy (Q itself
-  // is then only written by the Jacobi fallback below)
-  CHK(zph(Q1v, P2v, f64 ? &Qv : nullptr, q2, !f64, BS_Q));
   const Slots Pf = P;
   HIPCHK(launch_sumsq_ragged(c, n2, Pf, w.zq, w.zq, w.norms + 2, 4));
   int64_t* ranks = a.rank_out ? a.rank_out : w.ranks;

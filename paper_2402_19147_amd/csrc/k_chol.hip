@@ -311,19 +311,20 @@ hipError_t launch_chol_block(const Ctx& c, const double* G, double* P, int w, in
 //   2. G = L L^H and P1 = L^{-1} in LDS (chol_block_lds), P1 and ||P1||_F^2
 //      written out;
 //   3. Q1 = Z P1^H (FP64 and the product-dtype copy);
-//   4. G2 = Q1^H Q1 from the Q1 just written, its defect ||G2 - I||_F^2 and
-//      the plan of the second pass: with `adaptive` the factor keeps its
-//      first pass (q2 = 0, P = P1) when its Cholesky succeeded and the defect
-//      is at most tol2, else q2 = q_t and G2 (lower) goes to the G slot for
-//      the second pass.
+//   4. G2 = Q1^H Q1 from the Q1 just written and its defect ||G2 - I||_F^2:
+//      with `adaptive` the factor keeps its first pass (q2 = 0, P = P1) when
+//      its Cholesky succeeded and the defect is at most tol2;
+//   5. otherwise (always without `adaptive`) the second pass in place:
+//      G2 = L2 L2^H, P2 = L2^{-1}, Q = Q1 P2^H (FP64 and/or the product-dtype
+//      copy), P = P2 P1, q2 = q_t.
 // The separate launches this replaces spread each factor over many
 // workgroups; here every compute unit works through whole factors and Z is
 // read from HBM once per pass.  Every sum runs in a fixed order.
 struct CholqrBatch {
   const double* Z;
-  double* Q1;
-  int64_t zld, zps, zslab;  // Z and Q1 slots: row stride, plane stride, slot stride
-  double *P1, *P, *G;
+  double *Q1, *Q;             // Q: the second pass's FP64 factor (NULL: only the product-dtype copy)
+  int64_t zld, zps, zslab;  // Z, Q1 and Q slots: row stride, plane stride, slot stride
+  double *P1, *P;
   int64_t gld, gps, gslab;  // q x q slots
   const int *zp, *zq;
   int* fail;
@@ -455,6 +456,123 @@ __device__ double cholqr_sum(double v, double* red) {
   return s;
 }
 
+// D = X P^H over rows < p and columns < q with P (lower triangular, plain
+// layout) in a: tasks (16-row block, 16-column block) over the waves; lane
+// group g4 takes k = k0 + 4 g4 + s at MFMA step s, a run of four consecutive
+// k in both operands.  A conj(b) with n = -a:
+//   w: a0 p0 + a1 p1 + a2 p2 + a3 p3    x: a1 p0 + n0 p1 + a3 p2 + n2 p3
+//   y: a2 p0 + n3 p1 + n0 p2 + a1 p3    z: a3 p0 + a2 p1 + n1 p2 + n0 p3
+// D (FP64, may be NULL) and D2 (dtype d2dt, may be NULL) receive the result.
+__device__ void cholqr_zph(const double* __restrict__ X, int64_t ld, int64_t ps, int p, int q, const Tile& a,
+                           double* __restrict__ D, void* D2, int d2dt, int64_t d2ld, int64_t d2ps) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g4 = lane >> 4, cl = lane & 15;
+  const int nbj = (q + 15) >> 4, nbi = (p + 15) >> 4;
+  // row blocks fastest, so that every wave gets a share of each column
+  // block (column block bj costs bj + 1 chunks of 16 k)
+  for (int task = wave; task < nbi * nbj; task += CHOL_THREADS / 64) {
+    const int bi = task % nbi, bj = task / nbi;
+    const int ir = 16 * bi + cl, jc = 16 * bj + cl;
+    const double* pa = X + (int64_t)min(ir, p - 1) * ld;
+    const int kend = min(q, 16 * bj + 16);
+    f64x4d acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = (f64x4d){0, 0, 0, 0};
+    for (int k0 = 0; k0 < kend; k0 += 16) {
+      double va[4][4];
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int k = min(k0 + 4 * g4 + st, q - 1);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) va[st][c] = pa[k + c * ps];
+      }
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int k = k0 + 4 * g4 + st;
+        const bool ok = ir < p && k < kend;
+        const bool okp = jc < q && k <= jc && k < q;
+        const int kc = min(k, CB - 1);
+        const double a0 = ok ? va[st][0] : 0.0, a1 = ok ? va[st][1] : 0.0;
+        const double a2 = ok ? va[st][2] : 0.0, a3 = ok ? va[st][3] : 0.0;
+        const double p0 = okp ? a[0][jc][kc] : 0.0, p1 = okp ? a[1][jc][kc] : 0.0;
+        const double p2 = okp ? a[2][jc][kc] : 0.0, p3 = okp ? a[3][jc][kc] : 0.0;
+        const double n0 = -a0, n1 = -a1, n2 = -a2, n3 = -a3;
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, p0, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, p0, acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, p0, acc[2], 0, 0, 0);
+        acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, p0, acc[3], 0, 0, 0);
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, p1, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(n0, p1, acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(n3, p1, acc[2], 0, 0, 0);
+        acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, p1, acc[3], 0, 0, 0);
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, p2, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, p2, acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(n0, p2, acc[2], 0, 0, 0);
+        acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(n1, p2, acc[3], 0, 0, 0);
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, p3, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(n2, p3, acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, p3, acc[2], 0, 0, 0);
+        acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(n0, p3, acc[3], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * bi + g4 + 4 * r;
+      if (i < p && jc < q) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          if (D) D[(int64_t)i * ld + jc + c * ps] = acc[c][r];
+          if (D2) store_from_double(D2, d2dt, (int64_t)i * d2ld + jc + c * d2ps, acc[c][r]);
+        }
+      }
+    }
+  }
+}
+
+// After chol_block_lds on the leading q x q block of a: P = L^{-1} written
+// to Pg (q x q, upper part zero; NULL: not written) and put back into a as
+// a plain lower triangle (upper part zero) for cholqr_zph; returns
+// ||P||_F^2 (every thread).
+__device__ double cholqr_restage(Tile& a, const double* rdg, int q, double* __restrict__ Pg, int64_t gld,
+                                 int64_t gps, double* red) {
+  const int tid = threadIdx.x;
+  constexpr int PE = CB * CB / CHOL_THREADS;
+  Qd pv[PE];
+  double ps2 = 0.0;
+#pragma unroll
+  for (int m = 0; m < PE; ++m) {
+    const int e = tid + CHOL_THREADS * m;
+    const int i = e / q, j = e % q;
+    Qd v{0, 0, 0, 0};
+    if (e < q * q && j <= i) v = (i / SB == j / SB) ? pdiag(a, rdg, (i / SB) * SB, i % SB, j % SB) : ldq(a, i, j);
+    pv[m] = v;
+    if (e < q * q) {
+      if (Pg) {
+        const int64_t o = (int64_t)i * gld + j;
+        Pg[o] = v.w;
+        Pg[o + gps] = v.x;
+        Pg[o + 2 * gps] = v.y;
+        Pg[o + 3 * gps] = v.z;
+      }
+      ps2 += v.w * v.w + v.x * v.x + v.y * v.y + v.z * v.z;
+    }
+  }
+  ps2 = cholqr_sum(ps2, red);  // (its barriers also end the reads of a above)
+#pragma unroll
+  for (int m = 0; m < PE; ++m) {
+    const int e = tid + CHOL_THREADS * m;
+    if (e < q * q) stq(a, e / q, e % q, pv[m]);
+  }
+  __syncthreads();
+  return ps2;
+}
+
+// release the workgroup's global writes to its other waves
+__device__ inline void cholqr_sync_global() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 __global__ __launch_bounds__(CHOL_THREADS) void kb_cholqr(CholqrBatch g) {
   __shared__ Tile a;
   __shared__ double sbuf[3][4][SB][SB + 1];
@@ -463,7 +581,6 @@ __global__ __launch_bounds__(CHOL_THREADS) void kb_cholqr(CholqrBatch g) {
   __shared__ double red[CHOL_THREADS / 64];
   __shared__ int bad;
   const int t = g.order ? g.order[blockIdx.x] : blockIdx.x, tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6, g4 = lane >> 4, cl = lane & 15;
   const int p = g.zp[t], q = g.zq[t];
   if (p <= 0 || q <= 0) {
     if (tid == 0) {
@@ -477,122 +594,24 @@ __global__ __launch_bounds__(CHOL_THREADS) void kb_cholqr(CholqrBatch g) {
   const double* __restrict__ Z = g.Z + (int64_t)t * g.zslab;
   double* __restrict__ Q1 = g.Q1 + (int64_t)t * g.zslab;
   double* __restrict__ P1 = g.P1 + (int64_t)t * g.gslab;
+  double* __restrict__ Pt = g.P + (int64_t)t * g.gslab;
+  const int h = t < g.copy.split ? 0 : 1;
+  void* D2 = g.copy.p[0] ? (char*)g.copy.p[h] + (size_t)(t - h * g.copy.split) * g.copy.slab[h] * dtype_size(g.copy.dt)
+                         : nullptr;
   if (tid == 0) bad = 0;
   // 1. G = Z^H Z
   double sq = 0.0;
   cholqr_gram(Z, g.zld, g.zps, p, q, a, &sq);
   sq = cholqr_sum(sq, red);
   if (tid == 0) g.norms[4 * t] = sq;
-  // 2. P1 = L^{-1}; written out, then put back into a as a plain lower
-  //    triangle for the product
+  // 2. P1 = L^{-1}, written out and put back into a
   chol_block_lds(a, sbuf, rdg, db, &bad, q);
-  constexpr int PE = CB * CB / CHOL_THREADS;
-  Qd pv[PE];
-  double ps2 = 0.0;
-#pragma unroll
-  for (int m = 0; m < PE; ++m) {
-    const int e = tid + CHOL_THREADS * m;
-    const int i = e / q, j = e % q;
-    Qd v{0, 0, 0, 0};
-    if (e < q * q && j <= i) v = (i / SB == j / SB) ? pdiag(a, rdg, (i / SB) * SB, i % SB, j % SB) : ldq(a, i, j);
-    pv[m] = v;
-    if (e < q * q) {
-      const int64_t o = (int64_t)i * g.gld + j;
-      P1[o] = v.w;
-      P1[o + g.gps] = v.x;
-      P1[o + 2 * g.gps] = v.y;
-      P1[o + 3 * g.gps] = v.z;
-      ps2 += v.w * v.w + v.x * v.x + v.y * v.y + v.z * v.z;
-    }
-  }
-  ps2 = cholqr_sum(ps2, red);  // (its barriers also end the reads of a above)
-  if (tid == 0) g.norms[4 * t + 1] = ps2;
-#pragma unroll
-  for (int m = 0; m < PE; ++m) {
-    const int e = tid + CHOL_THREADS * m;
-    if (e < q * q) stq(a, e / q, e % q, pv[m]);
-  }
-  __syncthreads();
-  // 3. Q1 = Z P1^H: tasks (16-row block, 16-column block); lane group g4
-  //    takes k = k0 + 4 g4 + s at MFMA step s, a run of four consecutive k
-  //    in both operands.  A conj(b) with n = -a:
-  //      w: a0 p0 + a1 p1 + a2 p2 + a3 p3    x: a1 p0 + n0 p1 + a3 p2 + n2 p3
-  //      y: a2 p0 + n3 p1 + n0 p2 + a1 p3    z: a3 p0 + a2 p1 + n1 p2 + n0 p3
-  {
-    const int nbj = (q + 15) >> 4, nbi = (p + 15) >> 4;
-    const int h = t < g.copy.split ? 0 : 1;
-    void* D2 = g.copy.p[0] ? (char*)g.copy.p[h] +
-                                 (size_t)(t - h * g.copy.split) * g.copy.slab[h] * dtype_size(g.copy.dt)
-                           : nullptr;
-    for (int task = wave; task < nbi * nbj; task += CHOL_THREADS / 64) {
-      const int bi = task / nbj, bj = task % nbj;
-      const int ir = 16 * bi + cl, jc = 16 * bj + cl;
-      const double* pa = Z + (int64_t)min(ir, p - 1) * g.zld;
-      const int kend = min(q, 16 * bj + 16);
-      f64x4d acc[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[c] = (f64x4d){0, 0, 0, 0};
-      double va[1][4][4];
-      auto load = [&](int buf, int k0) __attribute__((always_inline)) {
-#pragma unroll
-        for (int st = 0; st < 4; ++st) {
-          const int k = min(k0 + 4 * g4 + st, q - 1);
-#pragma unroll
-          for (int c = 0; c < 4; ++c) va[buf][st][c] = pa[k + c * g.zps];
-        }
-      };
-      auto comp = [&](int buf, int k0) __attribute__((always_inline)) {
-#pragma unroll
-        for (int st = 0; st < 4; ++st) {
-          const int k = k0 + 4 * g4 + st;
-          const bool ok = ir < p && k < kend;
-          const bool okp = jc < q && k <= jc && k < q;
-          const int kc = min(k, CB - 1);
-          const double a0 = ok ? va[buf][st][0] : 0.0, a1 = ok ? va[buf][st][1] : 0.0;
-          const double a2 = ok ? va[buf][st][2] : 0.0, a3 = ok ? va[buf][st][3] : 0.0;
-          const double p0 = okp ? a[0][jc][kc] : 0.0, p1 = okp ? a[1][jc][kc] : 0.0;
-          const double p2 = okp ? a[2][jc][kc] : 0.0, p3 = okp ? a[3][jc][kc] : 0.0;
-          const double n0 = -a0, n1 = -a1, n2 = -a2, n3 = -a3;
-          acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, p0, acc[0], 0, 0, 0);
-          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, p0, acc[1], 0, 0, 0);
-          acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, p0, acc[2], 0, 0, 0);
-          acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, p0, acc[3], 0, 0, 0);
-          acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, p1, acc[0], 0, 0, 0);
-          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(n0, p1, acc[1], 0, 0, 0);
-          acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(n3, p1, acc[2], 0, 0, 0);
-          acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, p1, acc[3], 0, 0, 0);
-          acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, p2, acc[0], 0, 0, 0);
-          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, p2, acc[1], 0, 0, 0);
-          acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(n0, p2, acc[2], 0, 0, 0);
-          acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(n1, p2, acc[3], 0, 0, 0);
-          acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, p3, acc[0], 0, 0, 0);
-          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(n2, p3, acc[1], 0, 0, 0);
-          acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, p3, acc[2], 0, 0, 0);
-          acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(n0, p3, acc[3], 0, 0, 0);
-        }
-      };
-      for (int k0 = 0; k0 < kend; k0 += 16) {
-        load(0, k0);
-        comp(0, k0);
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = 16 * bi + g4 + 4 * r;
-        if (i < p && jc < q) {
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            const int64_t o = (int64_t)i * g.zld + jc + c * g.zps;
-            Q1[o] = acc[c][r];
-            if (D2) store_from_double(D2, g.copy.dt, (int64_t)i * g.copy.ld[h] + jc + c * g.copy.ps[h], acc[c][r]);
-          }
-        }
-      }
-    }
-  }
-  // 4. G2 = Q1^H Q1 from the Q1 this workgroup wrote
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  const double p1n = cholqr_restage(a, rdg, q, P1, g.gld, g.gps, red);
+  if (tid == 0) g.norms[4 * t + 1] = p1n;
+  // 3. Q1 = Z P1^H (and its product-dtype copy)
+  cholqr_zph(Z, g.zld, g.zps, p, q, a, Q1, D2, g.copy.dt, g.copy.ld[h], g.copy.ps[h]);
+  // 4. G2 = Q1^H Q1 from the Q1 this workgroup wrote, its defect, the plan
+  cholqr_sync_global();
   double unused = 0.0;
   cholqr_gram(Q1, g.zld, g.zps, p, q, a, &unused);
   double d2 = 0.0;
@@ -606,39 +625,54 @@ __global__ __launch_bounds__(CHOL_THREADS) void kb_cholqr(CholqrBatch g) {
   d2 = cholqr_sum(d2, red);
   const bool keep = g.adaptive && bad == 0 && d2 <= g.tol2;
   if (tid == 0) {
-    if (bad) g.fail[t] = 1;
     g.q2[t] = keep ? 0 : q;
     g.skip[t] = keep ? 1 : 0;
   }
-  double* __restrict__ Gt = g.G + (int64_t)t * g.gslab;
-  double* __restrict__ Pt = g.P + (int64_t)t * g.gslab;
-  for (int e = tid; e < q * q; e += CHOL_THREADS) {
-    const int i = e / q, j = e % q;
-    const int64_t o = (int64_t)i * g.gld + j;
-    if (keep) {
+  if (keep) {
+    for (int e = tid; e < q * q; e += CHOL_THREADS) {
+      const int64_t o = (int64_t)(e / q) * g.gld + e % q;
 #pragma unroll
       for (int c = 0; c < 4; ++c) Pt[o + c * g.gps] = P1[o + c * g.gps];
-    } else if (j <= i) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) Gt[o + c * g.gps] = a[c][i][j];
     }
+    if (tid == 0 && bad) g.fail[t] = 1;
+    return;
   }
+  // 5. second pass: G2 = L2 L2^H, P2 = L2^{-1} (into a), Q = Q1 P2^H (FP64
+  //    to the Q slot when given, and the product-dtype copy), P = P2 P1
+  chol_block_lds(a, sbuf, rdg, db, &bad, q);
+  cholqr_restage(a, rdg, q, nullptr, 0, 0, red);
+  double* __restrict__ Q = g.Q ? g.Q + (int64_t)t * g.zslab : nullptr;
+  cholqr_zph(Q1, g.zld, g.zps, p, q, a, Q, D2, g.copy.dt, g.copy.ld[h], g.copy.ps[h]);
+  // P[i][j] = sum_{j <= k <= i} P2[i][k] P1[k][j], in order of k
+  for (int e = tid; e < q * q; e += CHOL_THREADS) {
+    const int i = e / q, j = e % q;
+    Qd s{0, 0, 0, 0};
+    for (int k = j; k <= i; ++k) {
+      const int64_t o = (int64_t)k * g.gld + j;
+      qacc(s, qmul(ldq(a, i, k), Qd{P1[o], P1[o + g.gps], P1[o + 2 * g.gps], P1[o + 3 * g.gps]}));
+    }
+    const int64_t o = (int64_t)i * g.gld + j;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Pt[o + c * g.gps] = c == 0 ? s.w : c == 1 ? s.x : c == 2 ? s.y : s.z;
+  }
+  __syncthreads();
+  if (tid == 0 && bad) g.fail[t] = 1;
 }
 
-hipError_t launch_cholqr_batch(const Ctx& c, int count, const double* Z, double* Q1, int64_t zld, int64_t zps,
-                               int64_t zslab, double* P1, double* P, double* G, int64_t gld, int64_t gps,
+hipError_t launch_cholqr_batch(const Ctx& c, int count, const double* Z, double* Q1, double* Q, int64_t zld, int64_t zps,
+                               int64_t zslab, double* P1, double* P, int64_t gld, int64_t gps,
                                int64_t gslab, const int* zp, const int* zq, int* fail, double* norms, int* q2,
                                int* skip, double tol2, int adaptive, const TallCopy* copy, const int* order) {
   if (count <= 0) return hipSuccess;
   CholqrBatch g;
   g.Z = Z;
   g.Q1 = Q1;
+  g.Q = Q;
   g.zld = zld;
   g.zps = zps;
   g.zslab = zslab;
   g.P1 = P1;
   g.P = P;
-  g.G = G;
   g.gld = gld;
   g.gps = gps;
   g.gslab = gslab;

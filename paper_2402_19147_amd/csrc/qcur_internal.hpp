@@ -204,15 +204,16 @@ hipError_t launch_pinv_qp(const Ctx& c, const double* Y, int64_t p, int64_t q, c
 // Fast pseudoinverse pieces (CholeskyQR2), batched over up to MAXB matrices.
 constexpr int CHOL_BLOCK = 64;
 constexpr int MAXB = 4;
-// The first CholeskyQR pass of a batch's factors in one launch (one
-// workgroup per factor, orders q_t <= 64): Gram matrix, Cholesky factor and
-// inverse P1, Q1 = Z P1^H (and its product-dtype copy), ||Z||_F^2 and
-// ||P1||_F^2 into norms[4t], norms[4t+1], and the second pass's plan from
-// the defect of Q1 (adaptive: q2 = 0 and P = P1 when the defect is at most
-// tol2; otherwise q2 = q_t and Q1^H Q1 in the G slot).  order (may be NULL):
-// the factors in the order their workgroups start (largest first).
-hipError_t launch_cholqr_batch(const Ctx& c, int count, const double* Z, double* Q1, int64_t zld, int64_t zps,
-                               int64_t zslab, double* P1, double* P, double* G, int64_t gld, int64_t gps,
+// CholeskyQR2 of a batch's factors in one launch (one workgroup per factor,
+// orders q_t <= 64): Gram matrix, Cholesky factor and inverse P1,
+// Q1 = Z P1^H (and its product-dtype copy), ||Z||_F^2 and ||P1||_F^2 into
+// norms[4t], norms[4t+1]; with `adaptive` a factor whose first pass
+// succeeded with ||Q1^H Q1 - I||_F^2 <= tol2 keeps it (q2 = 0, P = P1),
+// every other one takes the second pass in place (q2 = q_t, P = P2 P1,
+// Q = Q1 P2^H into Q (FP64, may be NULL) and the copy).  order (may be
+// NULL): the factors in the order their workgroups start (largest first).
+hipError_t launch_cholqr_batch(const Ctx& c, int count, const double* Z, double* Q1, double* Q, int64_t zld,
+                               int64_t zps, int64_t zslab, double* P1, double* P, int64_t gld, int64_t gps,
                                int64_t gslab, const int* zp, const int* zq, int* fail, double* norms, int* q2,
                                int* skip, double tol2, int adaptive, const TallCopy* copy, const int* order);
 hipError_t launch_chol_block(const Ctx& c, const double* G, double* P, int w, int64_t ld, int64_t ps, int* fail,

@@ -266,9 +266,9 @@ def test_batch_autotuned_plans(compute):
     Q.sync_status()
     plans = bs.plans()
     assert plans is not None and len(plans) == 13
-    # the FP64 factor stages run on the fragment-streaming kernels (16-blocks,
-    # fixed); the others on tuned 32- or 64-tiles
-    fixed = ("gram_C", "gram_R", "q1_C", "q1_R", "gram2", "q1p2")
+    # the FP64 factor stages run in the one-workgroup-per-factor CholeskyQR2
+    # kernel (reported as 16-blocks, fixed); the others on tuned 32- or 64-tiles
+    fixed = ("gram_C", "gram_R", "q1_C", "q1_R", "gram2", "p2p1", "q1p2")
     assert all(plans[k] == (16, 1) for k in fixed)
     assert all(t in (32, 64) for name, (t, s) in plans.items() if name not in fixed)
     assert all(1 <= s <= 4 for name, (t, s) in plans.items() if name != "residual")
