@@ -173,7 +173,7 @@ __device__ void chol_diag(TileT& a, double* rdg, DiagBuf& db, int kb, int kw, in
 // chol_diag (diagonal sub-blocks' strict lower parts transposed into their
 // upper triangles, 1 / L[j][j] in rdg; read back through pdiag), the rest of
 // P's lower triangle in place.  All CHOL_THREADS threads take part.
-__device__ void chol_block_lds(Tile& a, double (*sbuf)[4][SB][SB + 1], double* rdg, DiagBuf& db, int* bad, int w) {
+__device__ __attribute__((always_inline)) void chol_block_lds(Tile& a, double (*sbuf)[4][SB][SB + 1], double* rdg, DiagBuf& db, int* bad, int w) {
   const int tid = threadIdx.x;
   for (int kb = 0; kb < w; kb += SB) {
     const int kw = min(SB, w - kb);
@@ -341,7 +341,7 @@ struct CholqrBatch {
 // blocks of a: tasks (block, row slice) spread over the eight waves, the
 // slices' partial blocks added into a in slice order.  *sq gains the sum of
 // squares of the entries the diagonal-block tasks load (each entry once).
-__device__ void cholqr_gram(const double* __restrict__ X, int64_t ld, int64_t ps, int p, int q, Tile& a,
+__device__ __attribute__((always_inline)) void cholqr_gram(const double* __restrict__ X, int64_t ld, int64_t ps, int p, int q, Tile& a,
                             double* sq) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g4 = lane >> 4, cl = lane & 15;
   // (at most two tasks per wave, whose accumulators stay in registers: the
@@ -463,7 +463,7 @@ __device__ double cholqr_sum(double v, double* red) {
 //   w: a0 p0 + a1 p1 + a2 p2 + a3 p3    x: a1 p0 + n0 p1 + a3 p2 + n2 p3
 //   y: a2 p0 + n3 p1 + n0 p2 + a1 p3    z: a3 p0 + a2 p1 + n1 p2 + n0 p3
 // D (FP64, may be NULL) and D2 (dtype d2dt, may be NULL) receive the result.
-__device__ void cholqr_zph(const double* __restrict__ X, int64_t ld, int64_t ps, int p, int q, const Tile& a,
+__device__ __attribute__((always_inline)) void cholqr_zph(const double* __restrict__ X, int64_t ld, int64_t ps, int p, int q, const Tile& a,
                            double* __restrict__ D, void* D2, int d2dt, int64_t d2ld, int64_t d2ps) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g4 = lane >> 4, cl = lane & 15;
   const int nbj = (q + 15) >> 4, nbi = (p + 15) >> 4;
@@ -532,7 +532,7 @@ __device__ void cholqr_zph(const double* __restrict__ X, int64_t ld, int64_t ps,
 // to Pg (q x q, upper part zero; NULL: not written) and put back into a as
 // a plain lower triangle (upper part zero) for cholqr_zph; returns
 // ||P||_F^2 (every thread).
-__device__ double cholqr_restage(Tile& a, const double* rdg, int q, double* __restrict__ Pg, int64_t gld,
+__device__ __attribute__((always_inline)) double cholqr_restage(Tile& a, const double* rdg, int q, double* __restrict__ Pg, int64_t gld,
                                  int64_t gps, double* red) {
   const int tid = threadIdx.x;
   constexpr int PE = CB * CB / CHOL_THREADS;
