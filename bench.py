@@ -312,6 +312,7 @@ def bench_color(q, torch, workloads, dev, args, use_oracle):
             out[name]["cur_rel_err_vs_oracle"] = rel_err(B, Bref) if same else None
         log("color vs oracle: " + ", ".join(f"{k} {out[k]['cur_rel_err_vs_oracle']:.2e}" for k in variants
                                             if out[k].get("cur_rel_err_vs_oracle") is not None))
+        settle()
     return out
 
 
@@ -396,6 +397,7 @@ def bench_batch(q, torch, workloads, dev, args, use_oracle):
                                                    problems=int(len(e)), draws_differ=int(np.isnan(e).sum()))
         log("batch vs oracle (max over problems): " +
             ", ".join(f"{k} {out[k]['cur_rel_err_vs_oracle']['max']:.2e}" for k in errs))
+        settle()
     return out
 
 
@@ -450,7 +452,7 @@ def bench_adjoint(q, torch, workloads, dev, args, use_oracle):
         q.sync_status()
         nA = float(torch.linalg.vector_norm(A.to(torch.float64)))
         out[name] = dict(ms_per_step=dt_s * 1e3, steps_per_s=1.0 / dt_s,
-                         loss_over_normA2=float(loss) / nA ** 2,
+                         loss_over_normA2=float(loss.detach()) / nA ** 2,
                          grad_norm_over_normA=float(torch.linalg.vector_norm(g.to(torch.float64))) / nA)
         dA, _ = q.backward(A, I, J, gB=torch.tensor(gB_host, dtype=dt, device=dev), max_rank=cfg["max_rank"])
         q.sync_status()
@@ -489,6 +491,7 @@ def bench_complete(q, torch, workloads, dev, use_oracle):
     def N64(t):
         return t.to(torch.float64).cpu().numpy()
 
+    checks = []  # the checker runs after all timed runs (its host threads would compete with the launches)
     for name, comp, dt in (("f64", q.F64, torch.float64), ("f32", q.F32, torch.float32)):
         Y = torch.tensor(A, dtype=dt, device=dev)
         Mk = torch.tensor(mask, device=dev)
@@ -505,13 +508,7 @@ def bench_complete(q, torch, workloads, dev, use_oracle):
         err = float(np.sqrt(((Xh - truth)[:, miss] ** 2).sum() / ((truth[:, miss]) ** 2).sum()))
         out[name] = dict(iterations=iters, last_rel_change=rel, ms_per_iter=dt_s * 1e3 / max(iters, 1),
                          total_ms=dt_s * 1e3, rel_err_missing_vs_noiseless=err)
-        if use_oracle:
-            # the checker's Algorithm 2 on the same input for the same number of steps
-            import oracle
-            t1 = time.perf_counter()
-            ref = oracle.complete.complete(N64(Y), mask, I, J, max_iter=iters, tol=0.0)
-            out[name]["oracle_seconds"] = time.perf_counter() - t1
-            out[name]["iterate_rel_err_vs_oracle"] = rel_err(Xh, ref["X"])
+        checks.append((name, N64(Y), iters, Xh))
         log(f"complete {name}: {iters} steps, {dt_s * 1e3 / max(iters, 1):.3f} ms/step")
     # the same problem with I, J drawn again from every iterate (length
     # probabilities), c = r = ceil(k ln k)
@@ -532,7 +529,22 @@ def bench_complete(q, torch, workloads, dev, use_oracle):
                                        ms_per_iter=dt_s * 1e3 / max(iters, 1), total_ms=dt_s * 1e3,
                                        rel_err_missing_vs_noiseless=err)
     log(f"complete f32 resampled: {iters} steps, {dt_s * 1e3 / max(iters, 1):.3f} ms/step, err {err:.4f}")
+    if use_oracle:
+        # the checker's Algorithm 2 on the same inputs for the same numbers of steps
+        import oracle
+        for name, Yh, iters, Xh in checks:
+            t1 = time.perf_counter()
+            ref = oracle.complete.complete(Yh, mask, I, J, max_iter=iters, tol=0.0)
+            out[name]["oracle_seconds"] = time.perf_counter() - t1
+            out[name]["iterate_rel_err_vs_oracle"] = rel_err(Xh, ref["X"])
+        settle()
     return out
+
+
+def settle():
+    """A pause after a checker run, so that its host threads have gone idle
+    before the next timed GPU run (they would compete with its launches)."""
+    time.sleep(1.0)
 
 
 def bench_qsvd(q, torch, workloads, dev, use_oracle):
