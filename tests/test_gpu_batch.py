@@ -118,6 +118,22 @@ def test_batch_matches_checker(compute):
         assert N(bs.ranks[b]).astype(int).tolist() == [dims[b][2], dims[b][3]]
 
 
+@pytest.mark.parametrize("compute", [Q.F64, Q.F32])
+def test_batch_factors_wider_than_one_block(compute):
+    # c = r = 2k > 64: the factors' Gram matrices exceed one 64 x 64 block, so
+    # the batch takes the multi-launch CholeskyQR route (tile-task Cholesky
+    # with identity padding) instead of the one-workgroup-per-factor kernel
+    probs, dims = make_batch(4, seed=29, mn=(150, 260), k=(33, 40))
+    assert max(max(d[2], d[3]) for d in dims) > 64
+    dt = tdt(compute)
+    bs = Q.BatchSolver(dims, compute=compute, a_dtype=dt, want_B=True)
+    A = Q.pack_batch([P["A"] for P in probs], dtype=dt, device=DEV)
+    bs(A, seed=8)
+    Q.sync_status()
+    for b in range(len(dims)):
+        check_problem(bs, A, b, dims, 8, compute)
+
+
 def test_batch_uniform_sampling():
     probs, dims = make_batch(7, seed=24)
     bs = Q.BatchSolver(dims, compute=Q.F64, sampling=Q.UNIFORM, a_dtype=torch.float64)
