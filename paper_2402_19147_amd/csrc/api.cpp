@@ -2592,10 +2592,17 @@ qcur_status qcur_batch_prepare(qcur_handle h, int32_t count, const int32_t* dims
   for (int i = 0; i < count; ++i) order[i] = i;
   auto work = [&](int i) { return (double)hm[i] * (double)hn[i] * (double)(hc[i] + hr[i]); };
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
-  // the order of the factors' CholeskyQR workgroups: largest p q^2 first
+  // the order of the factors' CholeskyQR workgroups, longest first: the
+  // passes over Z and Q_1 cost p per 16 x 16 block of the lower triangle
+  // (three of them, five when the second pass runs, which on measured
+  // workloads it mostly does for more than 48 columns), the factorisations
+  // a pivot chain per 16 columns
   std::vector<int> forder(2 * count);
   for (int i = 0; i < 2 * count; ++i) forder[i] = i;
-  auto fwork = [&](int t) { return (double)hp[t] * (double)hq[t] * (double)hq[t]; };
+  auto fwork = [&](int t) {
+    const double nb = (double)((hq[t] + 15) / 16), blk = nb * (nb + 1) / 2;
+    return (double)hp[t] * blk * (hq[t] > 48 ? 5.0 : 3.0) + 2500.0 * nb;
+  };
   std::stable_sort(forder.begin(), forder.end(), [&](int x, int y) { return fwork(x) > fwork(y); });
   const int* srcs[8] = {hm, hn, hc, hr, hp, hq, order.data(), forder.data()};
   int* dsts[8] = {w.dm, w.dn, w.dc, w.dr, w.zp, w.zq, w.order, w.forder};
