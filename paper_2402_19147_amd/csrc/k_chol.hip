@@ -345,11 +345,15 @@ __device__ __attribute__((always_inline)) void cholqr_gram(const double* __restr
                             double* sq) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g4 = lane >> 4, cl = lane & 15;
   // (at most two tasks per wave, whose accumulators stay in registers: the
-  // task loops are unrolled so that every index is a constant)
+  // task loops are unrolled so that every index is a constant).  Up to eight
+  // blocks: every block in H equal row slices.  Ten blocks (49-64 columns):
+  // the first six in two halves, the last four whole, listed whole blocks
+  // first, so that waves w and w + 4 (one SIMD) always get five halves
   const int nb = (q + 15) >> 4, nblk = nb * (nb + 1) / 2;
-  const int H = max(1, min(8, 16 / nblk));
-  const int rows = (((p + H - 1) / H) + 15) & ~15;
-  const int ntask = nblk * H;
+  const bool mixed = nblk > 8;
+  const int nsplit = mixed ? 16 - nblk : 0, whole = nblk - nsplit;
+  const int H = mixed ? 2 : max(1, min(8, 16 / nblk));
+  const int ntask = mixed ? 16 : nblk * H;
   f64x4d acc[2][4];
   int tb[2], th[2];
 #pragma unroll
@@ -360,7 +364,21 @@ __device__ __attribute__((always_inline)) void cholqr_gram(const double* __restr
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[u][c] = (f64x4d){0, 0, 0, 0};
     if (task >= ntask) continue;  // wave-uniform
-    const int blk = task / H, h = task % H;
+    int blk, h, nsl;
+    if (!mixed) {
+      blk = task / H;
+      h = task % H;
+      nsl = H;
+    } else if (task < whole) {
+      blk = nsplit + task;
+      h = 0;
+      nsl = 1;
+    } else {
+      blk = (task - whole) >> 1;
+      h = (task - whole) & 1;
+      nsl = 2;
+    }
+    const int rows = (((p + nsl - 1) / nsl) + 15) & ~15;
     int bi = 0;
     while ((bi + 1) * (bi + 2) / 2 <= blk) ++bi;
     const int bj = blk - bi * (bi + 1) / 2;
