@@ -391,8 +391,11 @@ static hipError_t launch_thin_dt(const Ctx& c, double alpha, QView A, QView B, d
   const int nbi = (int)((M + 15) / 16), nbj = (int)((N + 15) / 16);
   const int64_t blocks = lower_only ? (int64_t)nbi * (nbi + 1) / 2 : (int64_t)nbi * nbj;
   const int64_t ksteps = (K + 3) / 4;
-  // about three waves per SIMD over the chip, at least 32 k-steps per split
+  // about three waves per SIMD over the chip, at most 256 k-steps (1024
+  // rows) per split (long K streams better with more waves in flight), at
+  // least 32 k-steps per split
   int64_t splits = std::max<int64_t>(1, 3072 / (4 * blocks * std::max(batch, 1)));
+  splits = std::max<int64_t>(splits, ksteps / 256);
   splits = std::min<int64_t>(splits, std::max<int64_t>(1, ksteps / 32));
   splits = std::min<int64_t>(splits, 32);
   const size_t need = (size_t)batch * splits * 4 * (size_t)M * (size_t)N * sizeof(E);
