@@ -905,6 +905,12 @@ qcur_status approx_run(const Ctx& c, const ApproxArgs& a, int64_t m, int64_t n, 
     const bool need_E = a.refine > 0;
     QView E = need_E ? b.mat(m, n, adt) : QView{};
     QView Ex = need_E ? ((idt == adt) ? E : b.mat(m, n, idt)) : QView{};
+    // the last refinement step's correction, its sums of squares and the
+    // flag that tells the residual product it is not needed
+    const bool ident = need_E && a.fro && !a.hasB && (adt == QCUR_F32 || adt == QCUR_F64);
+    QView Dm = ident ? b.mat(cc, r, adt) : QView{};
+    double* dpart = ident ? (double*)b.take(CORE_PARTS * 8) : nullptr;
+    int* rskip = ident ? (int*)b.take(8) : nullptr;
     double* part = (double*)b.take(std::max<size_t>(residual_tiles(m, n, a.compute), 1) * 8);
     size_t gw_bytes = std::max({gemm_workspace(m, r, n, a.compute), gemm_workspace(cc, r, m, a.compute),
                                 gemm_workspace(m, r, cc, a.compute), gemm_workspace(m, n, r, a.compute),
@@ -930,27 +936,41 @@ qcur_status approx_run(const Ctx& c, const ApproxArgs& a, int64_t m, int64_t n, 
       HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Ax, Qr, 0.0, T, a.compute, gws, gw));
       if (Tx.p != T.p) HIPCHK(launch_cast(c, T, Tx, CAST_COPY));
       HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, Qc, Tx, 0.0, M, a.compute, gws, gw));
-      auto left_factor = [&]() -> qcur_status {  // B1 = Q_C M in the product dtype
+      // B1 = Q_C M in the product dtype (not written when *skip is set)
+      auto left_factor = [&](const int* skip) -> qcur_status {
         if (Mx.p != M.p) HIPCHK(launch_cast(c, M, Mx, CAST_COPY));
-        HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Qc, Mx, 0.0, B1, a.compute, gws, gw));
+        BatchSpec one;
+        one.skip = skip;
+        HIPCHK(launch_gemm_batched(c, QCUR_OP_N, QCUR_OP_N, 1.0, Qc, Mx, 0.0, B1, a.compute, gws, gw, one));
         if (B1x.p != B1.p) HIPCHK(launch_cast(c, B1, B1x, CAST_COPY));
         return QCUR_OK;
       };
+      const int* skip_final = nullptr;
       for (int st = 0; st < a.refine; ++st) {
         // E = A - Q_C M Q_R^H (A in the precision it was given);  M += Q_C^H (E Q_R)
-        CHK(left_factor());
+        CHK(left_factor(nullptr));
         HIPCHK(launch_residual_gemm(c, a.A, B1x, Qr, nullptr, 0, a.compute, part, &E, 1.0, QCUR_OP_H));
         if (Ex.p != E.p) HIPCHK(launch_cast(c, E, Ex, CAST_COPY));
         HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_N, 1.0, Ex, Qr, 0.0, T, a.compute, gws, gw));
         if (Tx.p != T.p) HIPCHK(launch_cast(c, T, Tx, CAST_COPY));
-        HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, Qc, Tx, 1.0, M, a.compute, gws, gw));
+        if (ident && st == a.refine - 1) {
+          // the last step keeps its correction D apart: with ||E||^2 from the
+          // residual's partials, ||A - Q_C (M + D) Q_R^H|| follows without
+          // another m x n product when D is small next to E
+          HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, Qc, Tx, 0.0, Dm, a.compute, gws, gw));
+          HIPCHK(launch_core_correct(c, M, Dm, dpart));
+          HIPCHK(launch_resid_identity(c, part, (int64_t)residual_tiles(m, n, a.compute), dpart, a.fro, rskip));
+          skip_final = rskip;
+        } else {
+          HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, Qc, Tx, 1.0, M, a.compute, gws, gw));
+        }
       }
-      if (a.fro || a.hasB) CHK(left_factor());
+      if (a.fro || a.hasB) CHK(left_factor(skip_final));
       if (a.fro) {
         // ||A - C U R||_F = ||A - Q_C M Q_R^H||_F (and C U R itself when asked, from the same tiles)
         HIPCHK(launch_residual_gemm(c, a.A, B1x, Qr, nullptr, 0, a.compute, part, nullptr, 0.0, QCUR_OP_H,
-                                    a.hasB ? &a.B : nullptr));
-        HIPCHK(launch_sum_partials(c, part, (int64_t)residual_tiles(m, n, a.compute), a.fro, 1));
+                                    a.hasB ? &a.B : nullptr, skip_final));
+        HIPCHK(launch_sum_partials(c, part, (int64_t)residual_tiles(m, n, a.compute), a.fro, 1, skip_final));
       } else if (a.hasB) {
         HIPCHK(launch_gemm(c, QCUR_OP_N, QCUR_OP_H, 1.0, B1x, Qr, 0.0, a.B, a.compute, gws, gw));
       }

@@ -554,8 +554,9 @@ hipError_t launch_identity_minus(const Ctx& c, QView X) {
 
 // Fixed-order sum of `count` doubles by one workgroup.
 __global__ __launch_bounds__(1024) void k_sum_partials(const double* __restrict__ part, int64_t count,
-                                                       double* out, int take_sqrt) {
+                                                       double* out, int take_sqrt, const int* skip) {
   __shared__ double red[1024];
+  if (skip && *skip) return;  // the result is already in out
   const int t = threadIdx.x;
   double s = 0.0;
   for (int64_t i = t; i < count; i += 1024) s += part[i];
@@ -568,8 +569,78 @@ __global__ __launch_bounds__(1024) void k_sum_partials(const double* __restrict_
   if (t == 0) out[0] = take_sqrt ? sqrt(red[0]) : red[0];
 }
 
-hipError_t launch_sum_partials(const Ctx& c, const double* partials, int64_t count, double* out, int take_sqrt) {
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, c.stream, partials, count, out, take_sqrt);
+hipError_t launch_sum_partials(const Ctx& c, const double* partials, int64_t count, double* out, int take_sqrt,
+                               const int* skip) {
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, c.stream, partials, count, out, take_sqrt, skip);
+  return hipGetLastError();
+}
+
+// M += D elementwise over the four planes; workgroup w writes the FP64 sum of
+// squares of the D elements it visited (fixed element order) to dpart[w].
+template <typename T>
+__global__ __launch_bounds__(256) void k_core_correct(T* M, int64_t ldm, int64_t psm, const T* D, int64_t ldd,
+                                                      int64_t psd, int64_t rows, int64_t cols, double* dpart) {
+  __shared__ double red[256];
+  const int64_t n = rows * cols;
+  double s = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+    const int64_t i = e / cols, j = e % cols;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const T d = D[i * ldd + j + p * psd];
+      M[i * ldm + j + p * psm] += d;
+      s += (double)d * (double)d;
+    }
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) dpart[blockIdx.x] = red[0];
+}
+
+hipError_t launch_core_correct(const Ctx& c, QView M, QView D, double* dpart) {
+  if (M.dt != D.dt || M.rows != D.rows || M.cols != D.cols) return hipErrorInvalidValue;
+  if (M.dt == QCUR_F64)
+    hipLaunchKernelGGL(k_core_correct<double>, dim3(CORE_PARTS), dim3(256), 0, c.stream, (double*)M.p, M.ld, M.ps,
+                       (const double*)D.p, D.ld, D.ps, M.rows, M.cols, dpart);
+  else if (M.dt == QCUR_F32)
+    hipLaunchKernelGGL(k_core_correct<float>, dim3(CORE_PARTS), dim3(256), 0, c.stream, (float*)M.p, M.ld, M.ps,
+                       (const float*)D.p, D.ld, D.ps, M.rows, M.cols, dpart);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_resid_identity(const double* epart, int64_t ecount, const double* dpart,
+                                                        double* out, int* skip) {
+  __shared__ double red[2][256];
+  double se = 0.0, sd = 0.0;
+  for (int64_t i = threadIdx.x; i < ecount; i += 256) se += epart[i];
+  for (int i = threadIdx.x; i < CORE_PARTS; i += 256) sd += dpart[i];
+  red[0][threadIdx.x] = se;
+  red[1][threadIdx.x] = sd;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double e2 = red[0][0], d2 = red[1][0];
+    const bool take = isfinite(e2) && isfinite(d2) && d2 <= 0x1p-8 * e2;
+    if (take) out[0] = sqrt(fmax(e2 - d2, 0.0));
+    skip[0] = take ? 1 : 0;
+  }
+}
+
+hipError_t launch_resid_identity(const Ctx& c, const double* epart, int64_t ecount, const double* dpart, double* out,
+                                 int* skip) {
+  hipLaunchKernelGGL(k_resid_identity, dim3(1), dim3(256), 0, c.stream, epart, ecount, dpart, out, skip);
   return hipGetLastError();
 }
 

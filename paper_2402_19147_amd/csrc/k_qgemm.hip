@@ -138,6 +138,9 @@ struct GemmArgs {
   int vec;
   // launch plan overrides (0: automatic)
   int force_tile, force_splits;
+  // when set and *skip != 0 on the device, the launch writes nothing (its
+  // result was not needed after all)
+  const int* skip;
   // triangular structure of op(A), op(B) and of the wanted output (TRI_*)
   int tri;
   // batches with per-problem sizes: the problems in the order their tiles
@@ -775,6 +778,7 @@ __device__ inline int64_t xcd_tile(int64_t id, int64_t total) {
 template <int DT, int EPI, int BM, int BN>
 __global__ __launch_bounds__(NT) void k_qgemm(GemmArgs g) {
   __shared__ Smem<DT, BM, BN> sm;
+  if (g.skip && *g.skip) return;  // uniform over the grid
   const int64_t gx = gridDim.x, gy = gridDim.y;
   const int64_t total = gx * gy * gridDim.z;
   const int64_t id = blockIdx.x + gx * (blockIdx.y + gy * (int64_t)blockIdx.z);
@@ -798,6 +802,7 @@ __global__ __launch_bounds__(NT) void k_qgemm(GemmArgs g) {
 constexpr int LIST_MAX = 2048;  // problems a list launch takes
 template <int DT, int EPI, int BM, int BN>
 __global__ __launch_bounds__(NT) void k_qgemm_list(GemmArgs g) {
+  if (g.skip && *g.skip) return;  // uniform over the grid
   __shared__ Smem<DT, BM, BN> sm;
   __shared__ int off[LIST_MAX + 1];
   __shared__ int wsum[NT / 64];
@@ -883,7 +888,8 @@ static void launch_tiles(const Ctx& c, const GemmArgs& g, dim3 grid) {
 template <typename Acc>
 __global__ void k_splitk_reduce(const Acc* __restrict__ Pall, int splits, int64_t Mx, int64_t Nx, double alpha,
                                 double beta, Acc* Dall, int64_t ldd, int64_t psd, int64_t sD, const int* bM,
-                                const int* bN) {
+                                const int* bN, const int* skip) {
+  if (skip && *skip) return;
   const int b = blockIdx.z;
   const int64_t M = bM ? bM[b] : Mx, N = bN ? bN[b] : Nx;
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -1006,7 +1012,7 @@ static hipError_t gemm_dt_tile(const Ctx& c, GemmArgs g, void* ws, size_t ws_byt
   hipLaunchKernelGGL(k_splitk_reduce<Acc>,
                      dim3((unsigned)((g.N + 255) / 256), (unsigned)std::min<int64_t>(g.M, 65535), (unsigned)g.batch),
                      dim3(256), 0, c.stream, (const Acc*)ws, splits, g.M, g.N, g.alpha, g.beta, (Acc*)g.D, g.ldd,
-                     g.psd, g.sD, g.bM, g.bN);
+                     g.psd, g.sD, g.bM, g.bN, g.skip);
   return hipGetLastError();
 }
 
@@ -1042,6 +1048,7 @@ hipError_t launch_gemm_batched(const Ctx& c, int opA, int opB, double alpha, QVi
   g.tri = bs.tri;
   g.force_splits = bs.splits;
   g.order = bs.order;
+  g.skip = bs.skip;
   g.A = A.p; g.lda = A.ld; g.psa = A.ps;
   g.B = B.p; g.ldb = B.ld; g.psb = B.ps;
   g.D = D.p; g.ldd = D.ld; g.psd = D.ps;
@@ -1115,8 +1122,10 @@ static void launch_fused(const Ctx& c, GemmArgs& g, int compute, int t) {
 }
 
 hipError_t launch_residual_gemm(const Ctx& c, QView A, QView B1, QView R, const uint8_t* mask, int64_t mask_ld,
-                                int compute, double* partials, QView* E, double e_scale, int opR, const QView* Bout) {
+                                int compute, double* partials, QView* E, double e_scale, int opR, const QView* Bout,
+                                const int* skip) {
   GemmArgs g = {};
+  g.skip = skip;
   g.A = B1.p; g.lda = B1.ld; g.psa = B1.ps;
   g.B = R.p; g.ldb = R.ld; g.psb = R.ps;
   g.M = A.rows; g.N = A.cols; g.K = B1.cols;

@@ -115,6 +115,9 @@ struct BatchSpec {
   // out their tiles (device int[count], largest first; NULL: one workgroup
   // per tile of the padded grid)
   const int* order = nullptr;
+  // device flag: when *skip != 0 the product is not written (the k_qgemm
+  // and split-K routes; the thin and tall routes compute it regardless)
+  const int* skip = nullptr;
 };
 // op(A) / op(B) lower or upper triangular (exact zeros elsewhere): K steps
 // that meet only zeros are skipped.  TRI_LOWER_OUT: only the lower triangle
@@ -165,9 +168,24 @@ hipError_t launch_gemm_batched(const Ctx& c, int opA, int opB, double alpha, QVi
 size_t residual_tiles(int64_t m, int64_t n, int compute);
 hipError_t launch_residual_gemm(const Ctx& c, QView A, QView B1, QView R, const uint8_t* mask,
                                 int64_t mask_ld, int compute, double* partials, QView* E,
-                                double e_scale, int opR = QCUR_OP_N, const QView* Bout = nullptr);
+                                double e_scale, int opR = QCUR_OP_N, const QView* Bout = nullptr,
+                                const int* skip = nullptr);
 hipError_t launch_sum_partials(const Ctx& c, const double* partials, int64_t count, double* out,
-                               int take_sqrt);
+                               int take_sqrt, const int* skip = nullptr);
+// Refinement's core update M += D (same shape and dtype, F32 or F64), with
+// FP64 sums of squares of D per workgroup into dpart[CORE_PARTS].
+constexpr int CORE_PARTS = 64;
+hipError_t launch_core_correct(const Ctx& c, QView M, QView D, double* dpart);
+// Residual of a refined core from the refinement's own residual E and
+// correction D = Q_C^H E Q_R: ||E - Q_C D Q_R^H||^2 = ||E||^2 - 2 ||D||^2 +
+// ||Q_C D Q_R^H||^2, the last term ||D||^2 (1 + e) with |e| <= 3 delta for
+// factors whose orthogonality defect delta meets the refinement's bound
+// 2^-12.  Taken when ||D||^2 <= 2^-8 ||E||^2 (no cancellation, and the
+// defect term below 2^-21 of the result, under the rounding of an FP32
+// residual product): out = sqrt(||E||^2 - ||D||^2) and *skip = 1; otherwise
+// *skip = 0 and out is left for the explicit residual product.
+hipError_t launch_resid_identity(const Ctx& c, const double* epart, int64_t ecount, const double* dpart, double* out,
+                                 int* skip);
 // Completion step (Algorithm 2): X1 = P_Omega(Y) + P_Omega^c(B1 op(R)) with
 // per-tile sums of |X1 - X0|^2 (partials) and |X0|^2 (partials2), 64 x 64
 // tiles (residual_tiles(m, n) of each).

@@ -634,6 +634,41 @@ def test_backward_repeated_index_flags_arg():
 
 
 # ---------------------------------------------------------------- the native solve
+@pytest.mark.parametrize("compute", [Q.F64, Q.F32, Q.BF16, Q.BF16X3])
+@pytest.mark.parametrize("exact", [False, True])
+def test_refined_residual_without_the_product(compute, exact):
+    # with one refinement step and no C U R requested, the residual comes
+    # from the step's own residual E and correction D (exact identity, taken
+    # when ||D|| is small next to ||E||: the noisy case); exact-rank inputs
+    # leave E and D both at rounding level and take the explicit product.
+    # Either way it matches the residual of C U R formed explicitly and the
+    # checker's.
+    if exact:
+        L, Rt, _ = workloads.lowrank_gaussian_factors(300, 260, 6, 17)
+        A = qmul(L, Rt)
+    else:
+        A = workloads.color_like(300, 260, 12, seed=9, noise=0.01)
+    c, r = 48, 40
+    dt = torch.float64 if compute == Q.F64 else torch.float32
+    S = Q.Solver(A.shape[1], A.shape[2], c, r, core=Q.CORE_CAR, compute=compute)
+    At = T(A, dt)
+    B = torch.empty((4, A.shape[1], A.shape[2]), dtype=dt, device=DEV)
+    S(At, sampling=Q.LENGTH, seed=21, refine_steps=1, B=B)
+    res_explicit = float(N(S.residual)[0])
+    S(At, sampling=Q.LENGTH, seed=21, refine_steps=1)
+    res = float(N(S.residual)[0])
+    Q.sync_status()
+    Ad = np.asarray(N(At))
+    nA = np.sqrt(fro2(Ad))
+    ref = oracle.solve(Ad, c, r, "length", "car", seed=21)
+    tol = {Q.F64: cur_tol(ref["C"], ref["R"]), Q.F32: 1e-5, Q.BF16: 2e-2, Q.BF16X3: 1e-4}[compute]
+    assert abs(res - ref["residual"]) <= tol * nA
+    assert abs(res - res_explicit) <= tol * nA
+    if not exact:
+        # the noise floor: the residual is of the noise's size, not rounding
+        assert res > 1e-3 * nA
+
+
 @pytest.mark.parametrize("sampling,core,compute", [(Q.UNIFORM, Q.CORE_WPINV, Q.F64), (Q.LENGTH, Q.CORE_CAR, Q.F64),
                                                    (Q.LENGTH, Q.CORE_CAR, Q.F32), (Q.LENGTH, Q.CORE_CAR, Q.BF16),
                                                    (Q.LENGTH, Q.CORE_CAR, Q.BF16X3)])
