@@ -320,8 +320,10 @@ def bench_batch(q, torch, workloads, dev, args, use_oracle):
     """512 uneven problems (m, n ~ U{64..512}, k ~ U{8..32}, c = r = 2k):
     the batched solve (GEMM launch plans chosen by the autotuner on the first
     call, and with fixed plans for comparison) replayed from a captured
-    graph, against plain FP64 solves of the same problems one at a time;
-    every problem's C U R against the checker's."""
+    graph, against plain FP64 solves of the same problems one at a time.
+    As with the single solves, the timed replays return U, I, J and the
+    residuals without forming C U R; one more solve per variant (untimed)
+    forms it, and every problem's C U R is held against the checker's."""
     import numpy as np
     cfg = workloads.WORKLOADS["batch_512"]
     probs = workloads.batch_problems(cfg["count"], cfg["seed"], cfg["mn_range"], cfg["k_range"], cfg["noise"])
@@ -333,8 +335,7 @@ def bench_batch(q, torch, workloads, dev, args, use_oracle):
     Bs = {}
     for name, comp, refine, tune in (("f32", q.F32, 0, True), ("f32_fixed_plans", q.F32, 0, False),
                                      ("f32_refine1", q.F32, 1, True), ("bf16_refine1", q.BF16, 1, True)):
-        bs = q.BatchSolver(dims, compute=comp, refine_steps=refine, a_dtype=torch.float32, autotune=tune,
-                           want_B=True)
+        bs = q.BatchSolver(dims, compute=comp, refine_steps=refine, a_dtype=torch.float32, autotune=tune)
         bs(A32, seed=seed)  # with autotune: times the candidate plans of every GEMM stage
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
@@ -358,9 +359,18 @@ def bench_batch(q, torch, workloads, dev, args, use_oracle):
         out[name] = dict(ms_per_batch=dt * 1e3, solves_per_s=len(dims) / dt)
         if tune:
             out[name]["plans"] = {k: list(v) for k, v in bs.plans().items()}
-        if name != "f32_fixed_plans":
-            Bs[name] = (bs.B.cpu().numpy(), bs.I.cpu().numpy(), bs.J.cpu().numpy())
         log(f"batch {name}: {dt * 1e3:.3f} ms per {len(dims)} solves")
+        if name != "f32_fixed_plans":
+            # C U R from one more solve of the same variant (untimed)
+            bsB = q.BatchSolver(dims, compute=comp, refine_steps=refine, a_dtype=torch.float32, autotune=tune,
+                                want_B=True)
+            bsB(A32, seed=seed)
+            q.sync_status()
+            nA = torch.linalg.vector_norm(A32.double(), dim=(1, 2, 3))
+            out[name]["residual_max_rel_diff_vs_B_run"] = float(
+                ((bs.residual.double() - bsB.residual.double()).abs() / nA).max())
+            Bs[name] = (bsB.B.cpu().numpy(), bsB.I.cpu().numpy(), bsB.J.cpu().numpy())
+            del bsB
         del bs, g
     # plain FP64: one qcur_solve per problem, no graph
     A64 = A32.to(torch.float64)

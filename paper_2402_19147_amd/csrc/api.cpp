@@ -1255,6 +1255,11 @@ struct BatchWs {
   int *fail, *ok, *zq2, *skip;
   double *Y, *V;
   Slots Qcx, Qrx, T, Tx, M, Mx, B1, B1x, E, Ex, M64, W1, U64;
+  // the last refinement step's corrections D_b, their sums of squares and
+  // the per-problem flags that skip the final residual products
+  Slots Dm;
+  double* dpart;
+  int* rskip;
   double* part;
   int64_t tiles, tiles32;
   int64_t* ranks;
@@ -1332,6 +1337,11 @@ BatchWs batch_carve(Bump& b, const BatchShape& s) {
   if (s.refine > 0) {
     w.E = slots_of(b, n, s.mx, s.nx, adt);
     w.Ex = idt != adt ? slots_of(b, n, s.mx, s.nx, idt) : w.E;
+    if (adt == QCUR_F32 || adt == QCUR_F64) {
+      w.Dm = slots_of(b, n, s.cx, s.rx, adt);
+      w.dpart = (double*)b.take((size_t)n * CORE_PARTS * 8);
+      w.rskip = (int*)b.take((size_t)n * 4);
+    }
   }
   w.M64 = adt != QCUR_F64 ? slots_of(b, n, s.cx, s.rx, QCUR_F64) : w.M;
   w.W1 = slots_of(b, n, s.cx, s.rx, QCUR_F64);
@@ -1514,10 +1524,10 @@ qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, Bat
     HIPCHK(launch_gemm_batched(c, opA, opB, alpha, A, B, beta, D, compute, w.gws, w.gws_bytes, bs));
     return QCUR_OK;
   };
-  auto resid = [&](const Slots* E, const Slots* Bout) -> qcur_status {
+  auto resid = [&](const Slots* E, const Slots* Bout, const int* skip) -> qcur_status {
     auto run = [&](int tile) {
       return launch_residual_gemm_batched(c, s.count, a.A, w.B1x, resid_R, QCUR_OP_H, s.mx, s.nx, s.rx, w.dm, w.dn,
-                                          w.dr, s.compute, w.part, E, 1.0, tile, Bout, w.order);
+                                          w.dr, s.compute, w.part, E, 1.0, tile, Bout, w.order, skip);
     };
     if (tu && tu->measure && tu->plan[BS_RESID].tile == 0) {
       float t64 = 0.f, t32 = 0.f;
@@ -1693,32 +1703,49 @@ qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, Bat
   if (w.Tx.p != w.T.p) HIPCHK(launch_cast_batch(c, n, w.T, w.Tx, w.dm, w.dr, mx, rx, CAST_COPY));
   CHK(stage(BS_M, QCUR_OP_H, QCUR_OP_N, 1.0, slot_view(Qc, mx, cx), slot_view(w.Tx, mx, rx), 0.0,
                              slot_view(w.M, cx, rx), s.compute, bspec(n, Qc, w.Tx, w.M, w.dc, w.dr, w.dm)));
-  auto left_factor = [&]() -> qcur_status {  // B1 = Q_C M in the product dtype
+  // B1 = Q_C M in the product dtype (problem b not written when skip[b] is set)
+  auto left_factor = [&](const int* skip) -> qcur_status {
     if (w.Mx.p != w.M.p) HIPCHK(launch_cast_batch(c, n, w.M, w.Mx, w.dc, w.dr, cx, rx, CAST_COPY));
+    BatchSpec bs = bspec(n, Qc, w.Mx, w.B1, w.dm, w.dr, w.dc);
+    bs.skip = skip;
     CHK(stage(BS_B1, QCUR_OP_N, QCUR_OP_N, 1.0, slot_view(Qc, mx, cx), slot_view(w.Mx, cx, rx), 0.0,
-                               slot_view(w.B1, mx, rx), s.compute, bspec(n, Qc, w.Mx, w.B1, w.dm, w.dr, w.dc)));
+                               slot_view(w.B1, mx, rx), s.compute, bs));
     if (w.B1x.p != w.B1.p) HIPCHK(launch_cast_batch(c, n, w.B1, w.B1x, w.dm, w.dr, mx, rx, CAST_COPY));
     return QCUR_OK;
   };
+  // with no C U R asked for, the last step's correction D_b stays apart and
+  // the residual of the refined core follows from ||E_b||^2 - ||D_b||^2 where
+  // D_b is small next to E_b (as in the single solve)
+  const bool ident = s.refine > 0 && !a.B.p && w.Dm.p != nullptr;
+  const int* skip_final = nullptr;
   for (int st = 0; st < s.refine; ++st) {
     // E = A - Q_C M Q_R^H;  M += Q_C^H (E Q_R)
-    CHK(left_factor());
+    CHK(left_factor(nullptr));
     resid_R = Qr;
-    CHK(resid(&w.E, nullptr));
+    CHK(resid(&w.E, nullptr, nullptr));
     if (w.Ex.p != w.E.p) HIPCHK(launch_cast_batch(c, n, w.E, w.Ex, w.dm, w.dn, mx, nx, CAST_COPY));
     CHK(stage(BS_T, QCUR_OP_N, QCUR_OP_N, 1.0, slot_view(w.Ex, mx, nx), slot_view(Qr, nx, rx), 0.0,
                                slot_view(w.T, mx, rx), s.compute, bspec(n, w.Ex, Qr, w.T, w.dm, w.dr, w.dn)));
     if (w.Tx.p != w.T.p) HIPCHK(launch_cast_batch(c, n, w.T, w.Tx, w.dm, w.dr, mx, rx, CAST_COPY));
-    CHK(stage(BS_M, QCUR_OP_H, QCUR_OP_N, 1.0, slot_view(Qc, mx, cx), slot_view(w.Tx, mx, rx), 1.0,
-                               slot_view(w.M, cx, rx), s.compute, bspec(n, Qc, w.Tx, w.M, w.dc, w.dr, w.dm)));
+    if (ident && st == s.refine - 1) {
+      CHK(stage(BS_M, QCUR_OP_H, QCUR_OP_N, 1.0, slot_view(Qc, mx, cx), slot_view(w.Tx, mx, rx), 0.0,
+                                 slot_view(w.Dm, cx, rx), s.compute, bspec(n, Qc, w.Tx, w.Dm, w.dc, w.dr, w.dm)));
+      HIPCHK(launch_core_correct_batch(c, n, w.M, w.Dm, w.dc, w.dr, w.dpart));
+      HIPCHK(launch_resid_identity_batch(c, n, w.part, resid_tiles, (s.nx + resid_tile_of - 1) / resid_tile_of,
+                                         resid_tile_of, w.dm, w.dn, w.dpart, a.residual, w.rskip));
+      skip_final = w.rskip;
+    } else {
+      CHK(stage(BS_M, QCUR_OP_H, QCUR_OP_N, 1.0, slot_view(Qc, mx, cx), slot_view(w.Tx, mx, rx), 1.0,
+                                 slot_view(w.M, cx, rx), s.compute, bspec(n, Qc, w.Tx, w.M, w.dc, w.dr, w.dm)));
+    }
   }
   // residual_b = ||A_b - Q_C M Q_R^H||_F = ||A_b - C_b U_b R_b||_F (and
   // B_b = C_b U_b R_b from the same tiles when asked)
-  CHK(left_factor());
+  CHK(left_factor(skip_final));
   resid_R = Qr;
-  CHK(resid(nullptr, a.B.p ? &a.B : nullptr));
+  CHK(resid(nullptr, a.B.p ? &a.B : nullptr, skip_final));
   HIPCHK(launch_resid_sum_batch(c, n, w.part, resid_tiles, (s.nx + resid_tile_of - 1) / resid_tile_of, resid_tile_of,
-                                w.dm, w.dn, a.residual));
+                                w.dm, w.dn, a.residual, skip_final));
   // U = P_C^H M P_R in FP64
   if (w.M64.p != w.M.p) HIPCHK(launch_cast_batch(c, n, w.M, w.M64, w.dc, w.dr, cx, rx, CAST_COPY));
   CHK(stage(BS_W1, QCUR_OP_N, QCUR_OP_N, 1.0, slot_view(w.M64, cx, rx), slot_view(half(Pf), rx, rx), 0.0,

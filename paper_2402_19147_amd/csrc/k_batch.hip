@@ -380,9 +380,10 @@ hipError_t launch_defect_plan_batch(const Ctx& c, int count, const double* G, in
 // the problem's own tiles (the others are never written).
 __global__ __launch_bounds__(256) void kb_resid_sum(const double* __restrict__ part, int64_t tiles, int64_t gx,
                                                    int tile, const int* __restrict__ dm,
-                                                   const int* __restrict__ dn, double* out) {
+                                                   const int* __restrict__ dn, double* out, const int* skip) {
   __shared__ double red[256];
   const int b = blockIdx.x;
+  if (skip && skip[b]) return;  // out[b] already holds the residual
   const int64_t ty = (dm[b] + tile - 1) / tile, tx = (dn[b] + tile - 1) / tile;
   double s = 0.0;
   for (int64_t k = threadIdx.x; k < tiles; k += 256)
@@ -392,10 +393,84 @@ __global__ __launch_bounds__(256) void kb_resid_sum(const double* __restrict__ p
 }
 
 hipError_t launch_resid_sum_batch(const Ctx& c, int count, const double* part, int64_t tiles, int64_t gx, int tile,
-                                  const int* dm, const int* dn, double* out) {
+                                  const int* dm, const int* dn, double* out, const int* skip) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(kb_resid_sum, dim3((unsigned)count), dim3(256), 0, c.stream, part, tiles, gx, tile, dm, dn,
-                     out);
+                     out, skip);
+  return hipGetLastError();
+}
+
+// M_b += D_b over problem b's rows x cols (blockIdx.y = b), FP64 sums of
+// squares of D_b per workgroup into dpart[b * CORE_PARTS + blockIdx.x].
+template <typename T>
+__global__ __launch_bounds__(256) void kb_core_correct(T* M, int64_t ldm, int64_t psm, int64_t sm, const T* D,
+                                                       int64_t ldd, int64_t psd, int64_t sd,
+                                                       const int* __restrict__ rows, const int* __restrict__ cols,
+                                                       double* dpart) {
+  __shared__ double red[256];
+  const int b = blockIdx.y;
+  const int64_t nc = cols[b], n = (int64_t)rows[b] * nc;
+  T* Mb = M + (int64_t)b * sm;
+  const T* Db = D + (int64_t)b * sd;
+  double s = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+    const int64_t i = e / nc, j = e % nc;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const T d = Db[i * ldd + j + p * psd];
+      Mb[i * ldm + j + p * psm] += d;
+      s += (double)d * (double)d;
+    }
+  }
+  s = block_sum_256(s, red);
+  if (threadIdx.x == 0) dpart[(int64_t)b * CORE_PARTS + blockIdx.x] = s;
+}
+
+hipError_t launch_core_correct_batch(const Ctx& c, int count, Slots M, Slots D, const int* rows, const int* cols,
+                                     double* dpart) {
+  if (count <= 0) return hipSuccess;
+  if (M.dt != D.dt) return hipErrorInvalidValue;
+  const dim3 grid(CORE_PARTS, (unsigned)count);
+  if (M.dt == QCUR_F64)
+    hipLaunchKernelGGL(kb_core_correct<double>, grid, dim3(256), 0, c.stream, (double*)M.p, M.ld, M.ps, M.slab,
+                       (const double*)D.p, D.ld, D.ps, D.slab, rows, cols, dpart);
+  else if (M.dt == QCUR_F32)
+    hipLaunchKernelGGL(kb_core_correct<float>, grid, dim3(256), 0, c.stream, (float*)M.p, M.ld, M.ps, M.slab,
+                       (const float*)D.p, D.ld, D.ps, D.slab, rows, cols, dpart);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// Per problem (blockIdx.x = b): ||E_b||^2 from its own residual tile
+// partials (as kb_resid_sum reads them) and ||D_b||^2 from dpart; the same
+// decision as the single solve's.
+__global__ __launch_bounds__(256) void kb_resid_identity(const double* __restrict__ part, int64_t tiles, int64_t gx,
+                                                         int tile, const int* __restrict__ dm,
+                                                         const int* __restrict__ dn, const double* dpart,
+                                                         double* out, int* skip) {
+  __shared__ double red[2][256];  // one array per sum: red[0][0] is read after the first one returns
+  const int b = blockIdx.x;
+  const int64_t ty = (dm[b] + tile - 1) / tile, tx = (dn[b] + tile - 1) / tile;
+  double se = 0.0;
+  for (int64_t k = threadIdx.x; k < tiles; k += 256)
+    if (k / gx < ty && k % gx < tx) se += part[(int64_t)b * tiles + k];
+  se = block_sum_256(se, red[0]);
+  double sd = (int)threadIdx.x < CORE_PARTS ? dpart[(int64_t)b * CORE_PARTS + threadIdx.x] : 0.0;
+  sd = block_sum_256(sd, red[1]);
+  if (threadIdx.x == 0) {
+    const bool take = isfinite(se) && isfinite(sd) && sd <= 0x1p-8 * se;
+    if (take) out[b] = sqrt(fmax(se - sd, 0.0));
+    skip[b] = take ? 1 : 0;
+  }
+}
+
+hipError_t launch_resid_identity_batch(const Ctx& c, int count, const double* part, int64_t tiles, int64_t gx,
+                                       int tile, const int* dm, const int* dn, const double* dpart, double* out,
+                                       int* skip) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kb_resid_identity, dim3((unsigned)count), dim3(256), 0, c.stream, part, tiles, gx, tile, dm, dn,
+                     dpart, out, skip);
   return hipGetLastError();
 }
 

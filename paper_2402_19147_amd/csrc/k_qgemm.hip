@@ -138,8 +138,9 @@ struct GemmArgs {
   int vec;
   // launch plan overrides (0: automatic)
   int force_tile, force_splits;
-  // when set and *skip != 0 on the device, the launch writes nothing (its
-  // result was not needed after all)
+  // per-problem device flags: problem b is not computed when skip[b] != 0
+  // (its result was not needed after all; tiles and partials of it are left
+  // unwritten)
   const int* skip;
   // triangular structure of op(A), op(B) and of the wanted output (TRI_*)
   int tri;
@@ -778,13 +779,13 @@ __device__ inline int64_t xcd_tile(int64_t id, int64_t total) {
 template <int DT, int EPI, int BM, int BN>
 __global__ __launch_bounds__(NT) void k_qgemm(GemmArgs g) {
   __shared__ Smem<DT, BM, BN> sm;
-  if (g.skip && *g.skip) return;  // uniform over the grid
   const int64_t gx = gridDim.x, gy = gridDim.y;
   const int64_t total = gx * gy * gridDim.z;
   const int64_t id = blockIdx.x + gx * (blockIdx.y + gy * (int64_t)blockIdx.z);
   const int64_t L = xcd_tile(id, total);
   const int64_t tx = L % gx, ty = (L / gx) % gy, tz = L / (gx * gy);
   const int b = (int)(tz / g.splits), split = (int)(tz % g.splits);
+  if (g.skip && g.skip[b]) return;  // uniform over the workgroup
   const int64_t tiles = gx * gy;
   gemm_tile<DT, EPI, BM, BN>(g, b, ty, tx, split, (int64_t)b * tiles + ty * gx + tx, sm);
 }
@@ -802,7 +803,6 @@ __global__ __launch_bounds__(NT) void k_qgemm(GemmArgs g) {
 constexpr int LIST_MAX = 2048;  // problems a list launch takes
 template <int DT, int EPI, int BM, int BN>
 __global__ __launch_bounds__(NT) void k_qgemm_list(GemmArgs g) {
-  if (g.skip && *g.skip) return;  // uniform over the grid
   __shared__ Smem<DT, BM, BN> sm;
   __shared__ int off[LIST_MAX + 1];
   __shared__ int wsum[NT / 64];
@@ -811,6 +811,7 @@ __global__ __launch_bounds__(NT) void k_qgemm_list(GemmArgs g) {
   // tiles of the problem at list position k
   auto tiles_of = [&](int k) -> int {
     const int b = g.order[k];
+    if (g.skip && g.skip[b]) return 0;  // a skipped problem has no tiles
     const int64_t M = g.bM ? (int64_t)g.bM[b] : g.M, N = g.bN ? (int64_t)g.bN[b] : g.N;
     return (int)(((M + BM - 1) / BM) * ((N + BN - 1) / BN) * g.splits);
   };
@@ -889,8 +890,8 @@ template <typename Acc>
 __global__ void k_splitk_reduce(const Acc* __restrict__ Pall, int splits, int64_t Mx, int64_t Nx, double alpha,
                                 double beta, Acc* Dall, int64_t ldd, int64_t psd, int64_t sD, const int* bM,
                                 const int* bN, const int* skip) {
-  if (skip && *skip) return;
   const int b = blockIdx.z;
+  if (skip && skip[b]) return;
   const int64_t M = bM ? bM[b] : Mx, N = bN ? bN[b] : Nx;
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (j >= N) return;
@@ -1151,10 +1152,11 @@ hipError_t launch_residual_gemm(const Ctx& c, QView A, QView B1, QView R, const 
 hipError_t launch_residual_gemm_batched(const Ctx& c, int count, Slots A, Slots B1, Slots R, int opR, int64_t mx,
                                         int64_t nx, int64_t kx, const int* bM, const int* bN, const int* bK,
                                         int compute, double* partials, const Slots* E, double e_scale, int tile,
-                                        const Slots* Bout, const int* order) {
+                                        const Slots* Bout, const int* order, const int* skip) {
   if (count <= 0 || mx <= 0 || nx <= 0) return hipSuccess;
   GemmArgs g = {};
   g.order = order;
+  g.skip = skip;
   g.A = B1.p; g.lda = B1.ld; g.psa = B1.ps; g.sA = B1.slab;
   g.B = R.p; g.ldb = R.ld; g.psb = R.ps; g.sB = R.slab;
   g.M = mx; g.N = nx; g.K = kx;

@@ -115,8 +115,9 @@ struct BatchSpec {
   // out their tiles (device int[count], largest first; NULL: one workgroup
   // per tile of the padded grid)
   const int* order = nullptr;
-  // device flag: when *skip != 0 the product is not written (the k_qgemm
-  // and split-K routes; the thin and tall routes compute it regardless)
+  // per-problem device flags: problem b's product is not written when
+  // skip[b] != 0 (the k_qgemm and split-K routes; the thin and tall routes
+  // compute it regardless)
   const int* skip = nullptr;
 };
 // op(A) / op(B) lower or upper triangular (exact zeros elsewhere): K steps
@@ -340,13 +341,22 @@ hipError_t launch_decide_batch(const Ctx& c, int count2, int count, const double
 // rows ceil(m_b / tile) and columns ceil(n_b / tile) of the gx-wide tile
 // grid (tiles = partials per problem)
 hipError_t launch_resid_sum_batch(const Ctx& c, int count, const double* part, int64_t tiles, int64_t gx, int tile,
-                                  const int* dm, const int* dn, double* out);
+                                  const int* dm, const int* dn, double* out, const int* skip = nullptr);
+// The refinement's core update and the residual identity of
+// launch_core_correct / launch_resid_identity, per problem of a batch
+// (dpart: CORE_PARTS per problem; out and skip: one per problem).
+hipError_t launch_core_correct_batch(const Ctx& c, int count, Slots M, Slots D, const int* rows, const int* cols,
+                                     double* dpart);
+hipError_t launch_resid_identity_batch(const Ctx& c, int count, const double* part, int64_t tiles, int64_t gx,
+                                       int tile, const int* dm, const int* dn, const double* dpart, double* out,
+                                       int* skip);
 // Batched residual A_b - B1_b op(R_b) (op = QCUR_OP_N or QCUR_OP_H).
 // tile: 64 or 32 (partials per problem: ceil(mx/tile) * ceil(nx/tile); only
 // those of the problem's own tiles are written).  order: as BatchSpec::order.
 hipError_t launch_residual_gemm_batched(const Ctx& c, int count, Slots A, Slots B1, Slots R, int opR, int64_t mx,
                                         int64_t nx, int64_t kx, const int* bM, const int* bN, const int* bK,
                                         int compute, double* partials, const Slots* E, double e_scale,
-                                        int tile = 64, const Slots* Bout = nullptr, const int* order = nullptr);
+                                        int tile = 64, const Slots* Bout = nullptr, const int* order = nullptr,
+                                        const int* skip = nullptr);
 
 }  // namespace qcur

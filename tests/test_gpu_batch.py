@@ -209,6 +209,35 @@ def test_batch_max_rank():
         assert np.sqrt(fro2(B - cur_product(ref["C"], ref["U"], ref["R"]))) <= 1e-9 * nA
 
 
+@pytest.mark.parametrize("compute", [Q.F64, Q.F32, Q.BF16])
+@pytest.mark.parametrize("noise", [1e-2, 0.0])
+def test_batch_refined_residual_without_the_product(compute, noise):
+    # one refinement step and no C U R asked for: each problem's residual
+    # comes from its step's ||E_b||^2 - ||D_b||^2 when D_b is small next to
+    # E_b (the noisy batch) and from the explicit product otherwise (exact
+    # rank: E_b and D_b both rounding); either way it matches the residual
+    # of the run that forms C U R, and the checker's
+    probs, dims = make_batch(10, seed=41, mn=(40, 200), k=(3, 9), noise=noise)
+    dt = tdt(compute)
+    A = Q.pack_batch([P["A"] for P in probs], dtype=dt, device=DEV)
+    with_B = Q.BatchSolver(dims, compute=compute, refine_steps=1, a_dtype=dt, want_B=True)
+    with_B(A, seed=7)
+    plain = Q.BatchSolver(dims, compute=compute, refine_steps=1, a_dtype=dt)
+    plain(A, seed=7)
+    Q.sync_status()
+    tol = {Q.F64: 1e-9, Q.F32: 1e-5, Q.BF16: 2e-2}[compute]
+    for b in range(len(dims)):
+        m, n, c, r = dims[b]
+        Ab = N(A[b, :, :m, :n])
+        nA = np.sqrt(fro2(Ab))
+        res, res_B = float(N(plain.residual)[b]), float(N(with_B.residual)[b])
+        assert abs(res - res_B) <= tol * nA, b
+        ref = oracle.solve(Ab, c, r, "length", "car", seed=7 + b)
+        assert abs(res - ref["residual"]) <= tol * nA, b
+        if noise > 0:
+            assert res > 1e-3 * nA, b
+
+
 def test_batch_graph_replay():
     probs, dims = make_batch(9, seed=26, mn=(40, 160), k=(3, 9))
     bs = Q.BatchSolver(dims, compute=Q.F32, refine_steps=1, a_dtype=torch.float32)
