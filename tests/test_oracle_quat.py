@@ -103,3 +103,39 @@ def test_spectral_norm_is_unitarily_invariant_and_bounded():
     assert s2 <= np.sqrt(fro2(A)) + 1e-12
     x = rng.standard_normal((4, 4, 1))
     assert np.sqrt(fro2(qmul(A, x))) <= s2 * np.sqrt(fro2(x)) + 1e-12
+
+
+def test_residual_identity_of_a_refined_core():
+    # The algebra the library's refined solve relies on for its residual:
+    # with D = Q_C^H E Q_R and G = Q^H Q, for any Q_C, Q_R (not only
+    # orthonormal ones),
+    #   ||E - Q_C D Q_R^H||_F^2 = ||E||^2 - 2 ||D||^2 + Re Tr(D^H G_C D G_R),
+    # because the real part of a quaternion trace is cyclic.  Near-orthonormal
+    # factors (defect delta) make the last term ||D||^2 (1 + O(delta)).
+    rng = np.random.default_rng(31)
+    m, n, c, r = 30, 26, 7, 6
+    E = rng.standard_normal((4, m, n))
+    Qc = rng.standard_normal((4, m, c))
+    Qr = rng.standard_normal((4, n, r))
+    D = qmul(qmul(qH(Qc), E), Qr)
+    lhs = fro2(E - qmul(qmul(Qc, D), qH(Qr)))
+    Gc, Gr = qmul(qH(Qc), Qc), qmul(qH(Qr), Qr)
+    rhs = fro2(E) - 2 * fro2(D) + qmul(qmul(qmul(qH(D), Gc), D), Gr)[0].trace()
+    assert lhs == pytest.approx(rhs, rel=1e-11)
+    # cyclic real trace, the step the identity takes
+    X, Y = rng.standard_normal((4, 5, 3)), rng.standard_normal((4, 3, 5))
+    assert qmul(X, Y)[0].trace() == pytest.approx(qmul(Y, X)[0].trace(), rel=1e-12)
+    # with orthonormal factors (polar factors of the random ones) the last
+    # term is ||D||^2 and the residual is ||E||^2 - ||D||^2
+    def orth(Z):
+        U, _, Vh = np.linalg.svd(chi(Z), full_matrices=False)
+        return unchi(U @ Vh, Z.shape[1], Z.shape[2])
+    Qc, Qr = orth(Qc), orth(Qr)
+    D = qmul(qmul(qH(Qc), E), Qr)
+    assert fro2(E - qmul(qmul(Qc, D), qH(Qr))) == pytest.approx(fro2(E) - fro2(D), rel=1e-11)
+    # and a defect delta moves it by at most about 3 delta ||D||^2
+    Qc2 = Qc * (1 + 1e-4)  # Q^H Q = (1 + 1e-4)^2 I: defect about 2e-4 per column
+    D2 = qmul(qmul(qH(Qc2), E), Qr)
+    exact = fro2(E - qmul(qmul(Qc2, D2), qH(Qr)))
+    approx = fro2(E) - fro2(D2)
+    assert abs(exact - approx) <= 3 * 2.0001e-4 * fro2(D2)
