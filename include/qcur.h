@@ -276,7 +276,12 @@ qcur_status qcur_backward(qcur_handle handle, const qcur_qmat* A, const int64_t*
  * I (r row indices, set 1) drawn as in qcur_draw (both in one launch), the
  * gathers, the core as in qcur_approx (core, compute, refine_steps, rtol,
  * max_rank) and residual (device double[1]) = ||A - C U R||_F as in
- * qcur_residual.  Outputs: I (int64[r]), J (int64[c]) sorted, U (c x r, FP64
+ * qcur_residual.  With refine_steps > 0 and B not requested, the residual
+ * of the refined core is taken from the last step's residual E and
+ * correction D = Q_C^H E Q_R as sqrt(||E||^2 - ||D||^2) (exact up to the
+ * factors' orthogonality defect, which the refinement holds below 2^-12)
+ * when ||D||^2 <= 2^-8 ||E||^2; otherwise, and always when B is requested,
+ * by the explicit product.  Outputs: I (int64[r]), J (int64[c]) sorted, U (c x r, FP64
  * for QCUR_F64 else FP32), rank_out (device int64[2] or NULL).  Optional
  * outputs (NULL = internal): p_col[n], q_row[m] and C, R, W in A's dtype;
  * B (m x n, FP64 for QCUR_F64 else FP32, NULL = not formed) receives C U R
@@ -308,7 +313,9 @@ size_t qcur_solve_workspace(int64_t m, int64_t n, int64_t c, int64_t r, int core
  * U_b (c_b x r_b, FP64 for QCUR_F64 else FP32) is the corner of slot b of U
  * (u_bstride apart).  I: device int64[count][rx] (row b holds I_b, sorted,
  * in its first r_b entries); J: int64[count][cx].  residual: device
- * double[count].  rank_out: device int64[count][2] (ranks of C_b, R_b) or
+ * double[count] (with refine_steps > 0 and B NULL, per problem from the last
+ * step's E_b and D_b as in qcur_solve when ||D_b||^2 <= 2^-8 ||E_b||^2, else
+ * by the explicit product).  rank_out: device int64[count][2] (ranks of C_b, R_b) or
  * NULL.  p_col: device double[count][nx], q_row: double[count][mx] or NULL.
  * B (may be NULL): B_b = C_b U_b R_b in the top-left m_b x n_b corner of
  * slot b (rows >= mx, cols >= nx, slots b_bstride elements apart; FP64 for
