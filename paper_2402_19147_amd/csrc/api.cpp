@@ -959,7 +959,8 @@ qcur_status approx_run(const Ctx& c, const ApproxArgs& a, int64_t m, int64_t n, 
           // another m x n product when D is small next to E
           HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, Qc, Tx, 0.0, Dm, a.compute, gws, gw));
           HIPCHK(launch_core_correct(c, M, Dm, dpart));
-          HIPCHK(launch_resid_identity(c, part, (int64_t)residual_tiles(m, n, a.compute), dpart, a.fro, rskip));
+          HIPCHK(launch_resid_identity(c, part, (int64_t)residual_tiles(m, n, a.compute), dpart,
+                                       resid_identity_gate(a.compute), a.fro, rskip));
           skip_final = rskip;
         } else {
           HIPCHK(launch_gemm(c, QCUR_OP_H, QCUR_OP_N, 1.0, Qc, Tx, 1.0, M, a.compute, gws, gw));
@@ -1732,7 +1733,8 @@ qcur_status batch_run(const Ctx& c, const BatchShape& s, const BatchArgs& a, Bat
                                  slot_view(w.Dm, cx, rx), s.compute, bspec(n, Qc, w.Tx, w.Dm, w.dc, w.dr, w.dm)));
       HIPCHK(launch_core_correct_batch(c, n, w.M, w.Dm, w.dc, w.dr, w.dpart));
       HIPCHK(launch_resid_identity_batch(c, n, w.part, resid_tiles, (s.nx + resid_tile_of - 1) / resid_tile_of,
-                                         resid_tile_of, w.dm, w.dn, w.dpart, a.residual, w.rskip));
+                                         resid_tile_of, w.dm, w.dn, w.dpart, resid_identity_gate(s.compute),
+                                         a.residual, w.rskip));
       skip_final = w.rskip;
     } else {
       CHK(stage(BS_M, QCUR_OP_H, QCUR_OP_N, 1.0, slot_view(Qc, mx, cx), slot_view(w.Tx, mx, rx), 1.0,

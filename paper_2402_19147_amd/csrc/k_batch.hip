@@ -448,7 +448,7 @@ hipError_t launch_core_correct_batch(const Ctx& c, int count, Slots M, Slots D, 
 __global__ __launch_bounds__(256) void kb_resid_identity(const double* __restrict__ part, int64_t tiles, int64_t gx,
                                                          int tile, const int* __restrict__ dm,
                                                          const int* __restrict__ dn, const double* dpart,
-                                                         double* out, int* skip) {
+                                                         double gate, double* out, int* skip) {
   __shared__ double red[2][256];  // one array per sum: red[0][0] is read after the first one returns
   const int b = blockIdx.x;
   const int64_t ty = (dm[b] + tile - 1) / tile, tx = (dn[b] + tile - 1) / tile;
@@ -459,18 +459,18 @@ __global__ __launch_bounds__(256) void kb_resid_identity(const double* __restric
   double sd = (int)threadIdx.x < CORE_PARTS ? dpart[(int64_t)b * CORE_PARTS + threadIdx.x] : 0.0;
   sd = block_sum_256(sd, red[1]);
   if (threadIdx.x == 0) {
-    const bool take = isfinite(se) && isfinite(sd) && sd <= 0x1p-8 * se;
+    const bool take = isfinite(se) && isfinite(sd) && sd <= gate * se;
     if (take) out[b] = sqrt(fmax(se - sd, 0.0));
     skip[b] = take ? 1 : 0;
   }
 }
 
 hipError_t launch_resid_identity_batch(const Ctx& c, int count, const double* part, int64_t tiles, int64_t gx,
-                                       int tile, const int* dm, const int* dn, const double* dpart, double* out,
-                                       int* skip) {
+                                       int tile, const int* dm, const int* dn, const double* dpart, double gate,
+                                       double* out, int* skip) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(kb_resid_identity, dim3((unsigned)count), dim3(256), 0, c.stream, part, tiles, gx, tile, dm, dn,
-                     dpart, out, skip);
+                     dpart, gate, out, skip);
   return hipGetLastError();
 }
 

@@ -615,7 +615,7 @@ hipError_t launch_core_correct(const Ctx& c, QView M, QView D, double* dpart) {
 }
 
 __global__ __launch_bounds__(256) void k_resid_identity(const double* epart, int64_t ecount, const double* dpart,
-                                                        double* out, int* skip) {
+                                                        double gate, double* out, int* skip) {
   __shared__ double red[2][256];
   double se = 0.0, sd = 0.0;
   for (int64_t i = threadIdx.x; i < ecount; i += 256) se += epart[i];
@@ -632,15 +632,15 @@ __global__ __launch_bounds__(256) void k_resid_identity(const double* epart, int
   }
   if (threadIdx.x == 0) {
     const double e2 = red[0][0], d2 = red[1][0];
-    const bool take = isfinite(e2) && isfinite(d2) && d2 <= 0x1p-8 * e2;
+    const bool take = isfinite(e2) && isfinite(d2) && d2 <= gate * e2;
     if (take) out[0] = sqrt(fmax(e2 - d2, 0.0));
     skip[0] = take ? 1 : 0;
   }
 }
 
-hipError_t launch_resid_identity(const Ctx& c, const double* epart, int64_t ecount, const double* dpart, double* out,
-                                 int* skip) {
-  hipLaunchKernelGGL(k_resid_identity, dim3(1), dim3(256), 0, c.stream, epart, ecount, dpart, out, skip);
+hipError_t launch_resid_identity(const Ctx& c, const double* epart, int64_t ecount, const double* dpart, double gate,
+                                 double* out, int* skip) {
+  hipLaunchKernelGGL(k_resid_identity, dim3(1), dim3(256), 0, c.stream, epart, ecount, dpart, gate, out, skip);
   return hipGetLastError();
 }
 

@@ -181,12 +181,19 @@ hipError_t launch_core_correct(const Ctx& c, QView M, QView D, double* dpart);
 // correction D = Q_C^H E Q_R: ||E - Q_C D Q_R^H||^2 = ||E||^2 - 2 ||D||^2 +
 // ||Q_C D Q_R^H||^2, the last term ||D||^2 (1 + e) with |e| <= 3 delta for
 // factors whose orthogonality defect delta meets the refinement's bound
-// 2^-12.  Taken when ||D||^2 <= 2^-8 ||E||^2 (no cancellation, and the
-// defect term below 2^-21 of the result, under the rounding of an FP32
-// residual product): out = sqrt(||E||^2 - ||D||^2) and *skip = 1; otherwise
-// *skip = 0 and out is left for the explicit residual product.
-hipError_t launch_resid_identity(const Ctx& c, const double* epart, int64_t ecount, const double* dpart, double* out,
-                                 int* skip);
+// 2^-12.  Taken when ||D||^2 <= gate ||E||^2: out = sqrt(||E||^2 - ||D||^2)
+// and *skip = 1; otherwise *skip = 0 and out is left for the explicit
+// residual product.  resid_identity_gate gives the gate per product dtype.
+hipError_t launch_resid_identity(const Ctx& c, const double* epart, int64_t ecount, const double* dpart, double gate,
+                                 double* out, int* skip);
+// 2^-8 for FP32 and FP64 products (no cancellation, the defect term below
+// 2^-21 of the result, under the rounding of an FP32 residual product);
+// 1/2 for BF16 operands, whose own rounding (a relative 2^-8 per product,
+// so D carries about 4e-3 of E) would fail the tighter gate: the result's
+// square is then at least half of ||E||^2 and the defect term at most
+// 3 * 2^-12 of it (a relative 4e-4 on the residual), against a BF16
+// residual product's error of about 1e-3 of ||A||.
+inline double resid_identity_gate(int compute) { return compute == QCUR_BF16 ? 0.5 : 0x1p-8; }
 // Completion step (Algorithm 2): X1 = P_Omega(Y) + P_Omega^c(B1 op(R)) with
 // per-tile sums of |X1 - X0|^2 (partials) and |X0|^2 (partials2), 64 x 64
 // tiles (residual_tiles(m, n) of each).
@@ -348,8 +355,8 @@ hipError_t launch_resid_sum_batch(const Ctx& c, int count, const double* part, i
 hipError_t launch_core_correct_batch(const Ctx& c, int count, Slots M, Slots D, const int* rows, const int* cols,
                                      double* dpart);
 hipError_t launch_resid_identity_batch(const Ctx& c, int count, const double* part, int64_t tiles, int64_t gx,
-                                       int tile, const int* dm, const int* dn, const double* dpart, double* out,
-                                       int* skip);
+                                       int tile, const int* dm, const int* dn, const double* dpart, double gate,
+                                       double* out, int* skip);
 // Batched residual A_b - B1_b op(R_b) (op = QCUR_OP_N or QCUR_OP_H).
 // tile: 64 or 32 (partials per problem: ceil(mx/tile) * ceil(nx/tile); only
 // those of the problem's own tiles are written).  order: as BatchSpec::order.
