@@ -5,6 +5,7 @@
 // once.  Every reduction runs in a fixed order, so results do not depend on
 // scheduling.
 #include <algorithm>
+#include <type_traits>
 
 #include "qcur_internal.hpp"
 
@@ -135,7 +136,10 @@ __global__ __launch_bounds__(256) void kb_gather(const TI* __restrict__ A, int64
                                                  double* __restrict__ O, int64_t ldo, int64_t pso, int64_t so,
                                                  TX* __restrict__ Ox, int64_t ldx, int64_t psx, int64_t sx,
                                                  int tconj, int tiles_t, unsigned* status) {
-  __shared__ double tile[4][GT][GT + 1];
+  // the transpose tile holds the input's values exactly: FP32 for FP32 and
+  // BF16 inputs (half the LDS of FP64, twice the resident workgroups)
+  typedef typename std::conditional<sizeof(TI) <= 4, float, double>::type TL;
+  __shared__ TL tile[4][GT][GT + 1];
   const int b = blockIdx.z;
   const int64_t rows = orows[b], cols = ocols[b];
   const int64_t s0 = (int64_t)(blockIdx.x / tiles_t) * GT, t0 = (int64_t)(blockIdx.x % tiles_t) * GT;
@@ -158,7 +162,7 @@ __global__ __launch_bounds__(256) void kb_gather(const TI* __restrict__ A, int64
       for (int k = 0; k < 4; ++k) {
         const double v = ok ? ld_d(Ab, src + k * psa) : 0.0;
         finite &= isfinite(v);
-        if (tconj) tile[k][ty + 8 * r][tx] = v;
+        if (tconj) tile[k][ty + 8 * r][tx] = (TL)v;
         else O[(int64_t)b * so + s * ldo + t + k * pso] = v;
         if (Ox) st_d(Ox + (int64_t)b * sx, s * ldx + t + k * psx, v);
       }
@@ -177,7 +181,7 @@ __global__ __launch_bounds__(256) void kb_gather(const TI* __restrict__ A, int64
     if (tt < cols && ss < rows)
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const double v = tile[k][tx][ty + 8 * r];
+        const double v = (double)tile[k][tx][ty + 8 * r];
         Ob[tt * ldo + ss + k * pso] = k > 0 ? -v : v;
       }
   }
