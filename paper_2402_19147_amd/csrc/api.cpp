@@ -1298,7 +1298,7 @@ BatchWs batch_carve(Bump& b, const BatchShape& s) {
   w.zq = (int*)b.take((size_t)n2 * 4);
   w.order = (int*)b.take((size_t)n * 4);
   w.forder = (int*)b.take((size_t)n2 * 4);
-  const int64_t nrbx = (s.mx + BATCH_RB - 1) / BATCH_RB, ncbx = (s.nx + 255) / 256;
+  const int64_t nrbx = (s.mx + BATCH_RB - 1) / BATCH_RB, ncbx = (s.nx + BATCH_CB - 1) / BATCH_CB;
   w.colpart = (double*)b.take((size_t)n * nrbx * s.nx * 8);
   w.rowpart = (double*)b.take((size_t)n * ncbx * s.mx * 8);
   w.p = (double*)b.take((size_t)n * s.nx * 8);

@@ -68,44 +68,56 @@ __global__ __launch_bounds__(256) void kb_norms(const TI* __restrict__ A, int64_
                                                 int64_t mx, int64_t nx, double* __restrict__ colpart,
                                                 double* __restrict__ rowpart, TX* __restrict__ Ax, int64_t ldx,
                                                 int64_t psx, int64_t sx) {
-  __shared__ double ws[4][BATCH_RB];
-  const int b = blockIdx.z, t = threadIdx.x;
+  // BATCH_RB rows x BATCH_CB (one wave) columns per workgroup: wave w takes
+  // rows i0 + 8w .. i0 + 8w + 7, all of whose loads are issued before any
+  // sum (addresses clamped into the problem, values past it zeroed)
+  static_assert(BATCH_RB == 32 && BATCH_CB == 64, "four waves of eight rows, one column per lane");
+  __shared__ double ws[BATCH_RB];
+  __shared__ double cs[4][BATCH_CB];
+  const int b = blockIdx.z, t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int64_t m = dm[b], n = dn[b];
-  const int64_t i0 = (int64_t)blockIdx.y * BATCH_RB, j0 = (int64_t)blockIdx.x * 256;
+  const int64_t i0 = (int64_t)blockIdx.y * BATCH_RB, j0 = (int64_t)blockIdx.x * BATCH_CB;
   if (i0 >= m || j0 >= n) return;  // uniform over the workgroup
-  const int64_t nrbx = (mx + BATCH_RB - 1) / BATCH_RB, ncbx = (nx + 255) / 256;
-  const int64_t j = j0 + t;
-  const int64_t i1 = min(m, i0 + BATCH_RB);
+  const int64_t nrbx = (mx + BATCH_RB - 1) / BATCH_RB, ncbx = (nx + BATCH_CB - 1) / BATCH_CB;
+  const int64_t j = j0 + lane, i1 = min(m, i0 + BATCH_RB);
+  const bool jok = j < n;
+  const int64_t jc = jok ? j : n - 1;
   const TI* Ab = A + (int64_t)b * sa;
-  double cacc = 0.0;
-  for (int64_t i = i0; i < i1; ++i) {
-    double s = 0.0;
-    if (j < n) {
-      const int64_t o = i * lda + j;
-      const double a0 = ld_d(Ab, o), a1 = ld_d(Ab, o + psa), a2 = ld_d(Ab, o + 2 * psa), a3 = ld_d(Ab, o + 3 * psa);
-      s = a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3;
-      if (Ax) {
-        TX* X = Ax + (int64_t)b * sx + i * ldx + j;
-        st_d(X, 0, a0);
-        st_d(X, psx, a1);
-        st_d(X, 2 * psx, a2);
-        st_d(X, 3 * psx, a3);
-      }
-    }
-    cacc += s;
-    const double w = wave_sum_d(s);
-    if ((t & 63) == 0) ws[t >> 6][i - i0] = w;
+  double v[8][4];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int64_t ic = min(i0 + 8 * wv + r, m - 1);
+    const int64_t o = ic * lda + jc;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[r][q] = ld_d(Ab, o + q * psa);
   }
+  double cacc = 0.0;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int64_t i = i0 + 8 * wv + r;
+    const bool ok = jok && i < i1;
+    const double sq = ok ? v[r][0] * v[r][0] + v[r][1] * v[r][1] + v[r][2] * v[r][2] + v[r][3] * v[r][3] : 0.0;
+    if (ok && Ax) {
+      TX* X = Ax + (int64_t)b * sx + i * ldx + j;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) st_d(X, q * psx, v[r][q]);
+    }
+    cacc += sq;
+    const double w = wave_sum_d(sq);
+    if (lane == 0) ws[8 * wv + r] = w;
+  }
+  cs[wv][lane] = cacc;
   __syncthreads();
-  for (int64_t k = t; k < i1 - i0; k += 256)
-    rowpart[((int64_t)b * ncbx + blockIdx.x) * mx + i0 + k] = ((ws[0][k] + ws[1][k]) + ws[2][k]) + ws[3][k];
-  if (j < n) colpart[((int64_t)b * nrbx + blockIdx.y) * nx + j] = cacc;
+  for (int64_t k = t; k < i1 - i0; k += 256) rowpart[((int64_t)b * ncbx + blockIdx.x) * mx + i0 + k] = ws[k];
+  if (t < BATCH_CB && jok)
+    colpart[((int64_t)b * nrbx + blockIdx.y) * nx + j] = ((cs[0][t] + cs[1][t]) + cs[2][t]) + cs[3][t];
 }
 
 hipError_t launch_norms_batch(const Ctx& c, int count, Slots A, const int* dm, const int* dn, int64_t mx,
                               int64_t nx, double* colpart, double* rowpart, const Slots* Ax) {
   if (count <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((nx + 255) / 256), (unsigned)((mx + BATCH_RB - 1) / BATCH_RB), (unsigned)count);
+  const dim3 grid((unsigned)((nx + BATCH_CB - 1) / BATCH_CB), (unsigned)((mx + BATCH_RB - 1) / BATCH_RB),
+                  (unsigned)count);
   return by_dtype(A.dt, [&](auto* ti) {
     typedef std::remove_pointer_t<decltype(ti)> TI;
     const int xdt = Ax ? Ax->dt : QCUR_F32;

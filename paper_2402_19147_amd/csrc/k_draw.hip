@@ -293,8 +293,8 @@ __global__ __launch_bounds__(DRAW_THREADS) void kb_draw(DrawBatch d, unsigned* s
     const double u = 1.0 / (double)len;
     for (int64_t j = tid; j < len; j += DRAW_THREADS) pr[j] = u;
   } else {
-    const int64_t nrbx = (d.mx + BATCH_RB - 1) / BATCH_RB, ncbx = (d.nx + 255) / 256;
-    const int64_t nrb = (m + BATCH_RB - 1) / BATCH_RB, ncb = (n + 255) / 256;
+    const int64_t nrbx = (d.mx + BATCH_RB - 1) / BATCH_RB, ncbx = (d.nx + BATCH_CB - 1) / BATCH_CB;
+    const int64_t nrb = (m + BATCH_RB - 1) / BATCH_RB, ncb = (n + BATCH_CB - 1) / BATCH_CB;
     const double* cp = d.colpart + (int64_t)b * nrbx * d.nx;
     double s = 0.0;
     for (int64_t j = tid; j < n; j += DRAW_THREADS) {

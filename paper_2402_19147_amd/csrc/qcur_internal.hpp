@@ -305,6 +305,7 @@ struct Slots {
   int dt;
 };
 constexpr int BATCH_RB = 32;  // rows per tile of the batched norm pass
+constexpr int BATCH_CB = 64;  // columns per tile of the batched norm pass
 hipError_t launch_norms_batch(const Ctx& c, int count, Slots A, const int* dm, const int* dn, int64_t mx,
                               int64_t nx, double* colpart, double* rowpart, const Slots* Ax);
 struct DrawBatch {
