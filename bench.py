@@ -65,8 +65,8 @@ def rel_err(x, ref):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(how the path would shard is described in DESIGN.md).", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: the workloads run on "
+              "a single GPU, and no multi-GPU path is built.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
